@@ -1,0 +1,174 @@
+/*
+ * ipeps.h -- C ABI of the MI355X (gfx950) library for one preconditioned
+ * gradient step of an iPEPS (arXiv:2511.09546):
+ *
+ *   ctm_init          double-layer tensor and trace-boundary environment
+ *   ctm_converge      CTMRG to a fixed point (the environment of Sec. III A,
+ *                     "gray circles" of Eq. (7))
+ *   ipeps_energy_grad energy per site E(A) (Eqs. (6)-(7)) and its gradient
+ *                     dE/dA (Sec. III A; K-step unrolled backward pass,
+ *                     Sec. IV A)
+ *   precond_apply     preconditioned gradient x = (N_local + delta I)^-1 g
+ *                     (Eq. (4); local metric Eq. (11); regularisation
+ *                     Sec. III B; implicit solve Sec. III C) by conjugate
+ *                     gradients
+ *
+ * Every call returns an int status (ipeps_status) and never aborts or throws.
+ * Negative values are errors (outputs untouched), positive values warnings
+ * (outputs valid).  Plain C types only; host arrays are row-major C order.
+ *
+ * Ownership: the caller owns every host array; inputs are copied during the
+ * call and never retained or modified.  The context owns all device memory
+ * it allocates until ctm_free.  One host thread may use a context at a time;
+ * distinct contexts may be used concurrently on distinct streams.
+ *
+ * Tensor layouts:
+ *   site tensors   A[Ly][Lx][d][D][D][D][D], legs (physical, left, up,
+ *                  right, down); "up" points to row y-1; site index y*Lx+x;
+ *                  real FP64.
+ *   gradient, directions: same layout as A.
+ *   Hamiltonian terms: ipeps_term below.
+ */
+#ifndef IPEPS_H
+#define IPEPS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ipeps_ctx ipeps_ctx;
+
+typedef enum {
+  IPEPS_OK = 0,
+  IPEPS_NOT_CONVERGED = 1,  /* warning: Delta >= tol after max_iter; the
+                               environment of the last iteration is kept */
+  IPEPS_EINVAL = -1,        /* bad argument (null pointer, sizes, non-finite
+                               values, chi < D^2, delta <= 0, ...) */
+  IPEPS_ENOMEM = -2,        /* device allocation failed */
+  IPEPS_EHIP = -3,          /* a HIP runtime call failed */
+  IPEPS_ECG_BREAKDOWN = -4, /* CG met p^T (N + delta) p <= 0; x holds the
+                               last iterate (written in this case) */
+  IPEPS_ESTATE = -5,        /* call out of order (e.g. energy before any
+                               ctm_converge) */
+  IPEPS_ENOTIMPL = -6       /* option not implemented */
+} ipeps_status;
+
+/* Arithmetic of the dense contractions.  Projector SVD, normalisation,
+ * convergence measure, energy traces and CG inner products are FP64 in every
+ * mode. */
+typedef enum {
+  IPEPS_FP64 = 0,
+  IPEPS_FP32 = 1,
+  IPEPS_BF16 = 2
+} ipeps_prec;
+
+/* One Hamiltonian term (Eq. (12), Eq. (13)).
+ *   kind 0: on-site d x d matrix acting on unit-cell site `site`;
+ *   kind 1: two-site d^2 x d^2 matrix on (site, site + (dx, dy)), periodic in
+ *           the unit cell, (dx, dy) in {(1,0), (0,1), (1,1), (1,-1)}.
+ * mat is row-major [(s1 s2)][(s1' s2')] (site 1 first); it is read during the
+ * call only.  The term contributes coef * Tr(h rho) / Tr(rho), where rho is
+ * the reduced density matrix of its sites; the energy per site is the sum
+ * over terms divided by Lx*Ly. */
+typedef struct {
+  int kind;
+  int site;
+  int dx, dy;
+  double coef;
+  const double* mat;
+} ipeps_term;
+
+typedef struct {
+  int prec;           /* ipeps_prec of the contractions */
+  double svd_cutoff;  /* keep singular values > svd_cutoff * s_1 (1e-12) */
+  int grad_K;         /* unrolled CTMRG iterations in the gradient (20) */
+  int svd_oversample; /* extra subspace columns beyond chi (0 = automatic) */
+  int svd_max_iter;   /* max subspace iterations per projector (50) */
+  double svd_tol;     /* subspace residual tolerance, relative to s_1
+                         (1e-13) */
+} ipeps_opts;
+
+/* Fill *opts with the defaults listed above. */
+void ipeps_default_opts(ipeps_opts* opts);
+
+/* Create a context, upload A, build the double layer and the trace-boundary
+ * environment (bond dimension D^2, zero padded to chi).
+ *   ctx       out: new context (on success)
+ *   Lx, Ly    unit cell (>= 1), d physical dimension, D bond dimension,
+ *   chi       environment dimension, chi >= D^2
+ *   A         host, A[Ly][Lx][d][D][D][D][D]
+ *   opts      NULL for the defaults
+ *   hip_stream a hipStream_t to run on, or NULL for a context-owned stream
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int ctm_init(ipeps_ctx** ctx, int Lx, int Ly, int d, int D, int chi,
+             const double* A, const ipeps_opts* opts, void* hip_stream);
+
+/* Replace the site tensors of an existing context (same shapes), keeping its
+ * environment as a warm start. Errors: EINVAL, EHIP. */
+int ctm_set_state(ipeps_ctx* ctx, const double* A);
+
+/* CTMRG iterations (one iteration = the simultaneous move of all four
+ * corners of every unit-cell plaquette with SVD-truncated half-system
+ * projectors) until Delta < tol or max_iter iterations.  Delta is the largest
+ * 2-norm change of the sum-normalised singular values of any corner.
+ * tol <= 0 runs exactly max_iter iterations.
+ *   n_iter, delta  out (may be NULL)
+ * Returns OK, NOT_CONVERGED (warning), or an error. */
+int ctm_converge(ipeps_ctx* ctx, double tol, int max_iter, int* n_iter,
+                 double* delta);
+
+/* Energy per site and (if grad != NULL) its gradient with respect to every
+ * real entry of A: the derivative of A -> e(A, F^K(A, env*)) where env* is
+ * the environment of the last ctm_converge (held fixed) and F one CTMRG
+ * iteration, K = opts.grad_K.  e_per_site: host scalar out; grad: host,
+ * layout of A.  Errors: EINVAL, ESTATE, EHIP, ENOMEM. */
+int ipeps_energy_grad(ipeps_ctx* ctx, int n_terms, const ipeps_term* terms,
+                      double* e_per_site, double* grad);
+
+/* Preconditioned direction x = (N_local + delta I)^-1 g, one independent CG
+ * solve per unit-cell site, from x0 = 0, on the environment of the last
+ * ctm_converge.  N_local acts on site tensor x as
+ * (N x)[t,l',u',r',d'] = sum E[(lurd),(l'u'r'd')] x[t,lurd] / Z with E the
+ * ring of the eight environment tensors of the site and Z = <A, E A>.
+ * CG stops when ||r|| <= cg_tol ||g|| or after cg_maxiter iterations.
+ *   g        host, layout of A;  delta > 0
+ *   x        host out, layout of A
+ *   n_iter   out: largest iteration count over sites (may be NULL)
+ *   rel_resid out: largest ||r||/||g|| over sites (may be NULL)
+ * Errors: EINVAL, ESTATE, EHIP, ENOMEM, ECG_BREAKDOWN (x written). */
+int precond_apply(ipeps_ctx* ctx, const double* g, double delta,
+                  double cg_tol, int cg_maxiter, double* x, int* n_iter,
+                  double* rel_resid);
+
+/* Sum-normalised singular values of every corner, out[4][Lx*Ly][chi] (host),
+ * zero padded. Errors: EINVAL, EHIP. */
+int ipeps_corner_spectra(ipeps_ctx* ctx, double* out);
+
+/* Copy the environment to / from the host: C[4][Lx*Ly][chi][chi] then
+ * T[4][Lx*Ly][chi][D*D][chi].  Index c = 0..3 runs over the upper-left,
+ * upper-right, lower-right and lower-left corners and over the top, right,
+ * bottom and left edges of a site.  Legs are in clockwise order around the
+ * site: C_c[counter-clockwise leg][clockwise leg], T_c[counter-clockwise
+ * leg][leg into the site (ket k, bra k' fused as k*D+k')][clockwise leg].
+ * Size in doubles: 4*n*chi*chi + 4*n*chi*D*D*chi (ipeps_env_size). */
+int ipeps_get_env(ipeps_ctx* ctx, double* out);
+int ipeps_set_env(ipeps_ctx* ctx, const double* in);
+
+/* Size in doubles of the environment buffer of ipeps_get_env. */
+size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
+
+/* Release the context and all its device memory (NULL is a no-op). */
+void ctm_free(ipeps_ctx* ctx);
+
+/* Static description of a status code. */
+const char* ipeps_strerror(int status);
+
+/* Library version string. */
+const char* ipeps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPEPS_H */

@@ -1,0 +1,35 @@
+/*
+ * ipeps_debug.h -- test hooks of the iPEPS library.  They run single kernels
+ * of the library on host data (device memory is allocated and released
+ * inside the call, on the null stream) so that tests can check them in
+ * isolation.  Not part of the hot path.
+ */
+#ifndef IPEPS_DEBUG_H
+#define IPEPS_DEBUG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C = alpha op(A) op(B) + beta C with the library's FP64 matrix-core GEMM;
+ * row-major host arrays: op(A) M x K (A is M x K, or K x M when tA),
+ * op(B) K x N (B is K x N, or N x K when tB), C M x N.  Returns a status. */
+int ipeps_debug_gemm(int tA, int tB, int M, int N, int K, double alpha,
+                     const double* A, const double* B, double beta,
+                     double* C);
+
+/* Symmetric eigendecomposition of `batch` b x b row-major matrices G (b even,
+ * b <= 128) by the library's Jacobi kernel: V (columns = eigenvectors) and
+ * lam, sorted by descending eigenvalue. */
+int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
+                        double* lam);
+
+/* Tall-skinny SVD W J = U diag(s) of `batch` n x b row-major matrices by
+ * the library's two-pass Gram/Jacobi routine (b even, b <= 128). */
+int ipeps_debug_svd_ts(int n, int b, int batch, const double* W, double* U,
+                       double* s, double* J);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPEPS_DEBUG_H */

@@ -14,7 +14,8 @@ the contractor.  This oracle fixes one scheme, written out step by step:
   the four enlarged corners Q_c = T_{c-1} C_c T_c a, and for each of its four
   cuts the half-system matrix M = Q_a Q_b (the two corners that meet at the
   cut, contracted over it) with its truncated SVD M ~ U S V^T (LAPACK full
-  SVD, keep k = min(chi, #{s_i > eps * s_1})) and the projectors
+  SVD, keep k = min(chi, #{s_i > eps * s_1}), sign fixed as in cut_svd)
+  and the projectors
   P = Q_b V S^-1/2 (into Q_a's columns) and Pt = S^-1/2 U^T Q_a (into Q_b's
   rows), so that Q_a P Pt Q_b is the best rank-k approximation of M;
 * renormalised corner C_c' = Pt Q_c P, renormalised edge
@@ -155,12 +156,16 @@ def enlarged_corner(C, Tprev, Tc, ac) -> torch.Tensor:
 
 
 def cut_svd(M: torch.Tensor):
-    """Full SVD by LAPACK with a deterministic sign: the largest-magnitude
-    entry of every left singular vector is made positive (the right vector
-    takes the same sign).  Returns U, S, V (M = U diag(S) V^T)."""
+    """Full SVD by LAPACK with a deterministic sign: in every left singular
+    vector u the entry r maximising |u_r| (1 + r/(2n)) is made positive (the
+    right vector takes the same sign).  The weight breaks the exact ties
+    between the (k,k') and (k',k) entries that the ket-bra exchange symmetry
+    of the double layer creates.  Returns U, S, V (M = U diag(S) V^T)."""
     U, S, Vh = torch.linalg.svd(M)
     V = Vh.transpose(0, 1)
-    piv = torch.argmax(U.abs(), dim=0)
+    n = U.shape[0]
+    w = 1.0 + torch.arange(n, dtype=U.dtype) / (2.0 * n)
+    piv = torch.argmax(U.abs() * w[:, None], dim=0)
     sgn = torch.sign(U[piv, torch.arange(U.shape[1])])
     sgn = torch.where(sgn == 0, torch.ones_like(sgn), sgn)
     return U * sgn, S, V * sgn

@@ -1,0 +1,269 @@
+"""ctypes binding of libipeps.so (argument marshalling only).
+
+Mirrors include/ipeps.h: the same entry points, host numpy arrays in C order,
+status codes turned into exceptions (``IpepsError``), warnings returned.
+Every computation runs in the library; when the library is missing this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libipeps.so")
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ENOMEM, EHIP, ECG_BREAKDOWN, ESTATE, ENOTIMPL = -1, -2, -3, -4, -5, -6
+FP64, FP32, BF16 = 0, 1, 2
+
+# every function declared in include/ipeps.h (checked by the CPU tests)
+API_FUNCTIONS = [
+    "ipeps_default_opts", "ctm_init", "ctm_set_state", "ctm_converge",
+    "ipeps_energy_grad", "precond_apply", "ipeps_corner_spectra",
+    "ipeps_get_env", "ipeps_set_env", "ipeps_env_size", "ctm_free",
+    "ipeps_strerror", "ipeps_version",
+]
+DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
+                   "ipeps_debug_svd_ts"]
+
+
+class IpepsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+class Term(ctypes.Structure):
+    _fields_ = [("kind", c_int), ("site", c_int), ("dx", c_int),
+                ("dy", c_int), ("coef", c_double), ("mat", POINTER(c_double))]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", c_int), ("svd_cutoff", c_double), ("grad_K", c_int),
+                ("svd_oversample", c_int), ("svd_max_iter", c_int),
+                ("svd_tol", c_double)]
+
+
+_lib = None
+_DP = POINTER(c_double)
+_IP = POINTER(c_int)
+
+
+def load():
+    """Load libipeps.so (once).  Raises ImportError if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run __graft_entry__.build() "
+            "(or python -m paper_2511_09546_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.ipeps_default_opts.argtypes = [POINTER(Opts)]
+    lib.ipeps_default_opts.restype = None
+    lib.ctm_init.argtypes = [POINTER(c_void_p), c_int, c_int, c_int, c_int,
+                             c_int, _DP, POINTER(Opts), c_void_p]
+    lib.ctm_set_state.argtypes = [c_void_p, _DP]
+    lib.ctm_converge.argtypes = [c_void_p, c_double, c_int, _IP, _DP]
+    lib.ipeps_energy_grad.argtypes = [c_void_p, c_int, POINTER(Term), _DP,
+                                      _DP]
+    lib.precond_apply.argtypes = [c_void_p, _DP, c_double, c_double, c_int,
+                                  _DP, _IP, _DP]
+    lib.ipeps_corner_spectra.argtypes = [c_void_p, _DP]
+    lib.ipeps_get_env.argtypes = [c_void_p, _DP]
+    lib.ipeps_set_env.argtypes = [c_void_p, _DP]
+    lib.ipeps_env_size.argtypes = [c_int, c_int, c_int, c_int]
+    lib.ipeps_env_size.restype = c_size_t
+    lib.ctm_free.argtypes = [c_void_p]
+    lib.ctm_free.restype = None
+    lib.ipeps_strerror.argtypes = [c_int]
+    lib.ipeps_strerror.restype = ctypes.c_char_p
+    lib.ipeps_version.restype = ctypes.c_char_p
+    lib.ipeps_debug_gemm.argtypes = [c_int, c_int, c_int, c_int, c_int,
+                                     c_double, _DP, _DP, c_double, _DP]
+    lib.ipeps_debug_sym_eig.argtypes = [c_int, c_int, _DP, _DP, _DP]
+    lib.ipeps_debug_svd_ts.argtypes = [c_int, c_int, c_int, _DP, _DP, _DP,
+                                       _DP]
+    for name in ("ctm_init", "ctm_set_state", "ctm_converge",
+                 "ipeps_energy_grad", "precond_apply", "ipeps_corner_spectra",
+                 "ipeps_get_env", "ipeps_set_env", "ipeps_debug_gemm",
+                 "ipeps_debug_sym_eig", "ipeps_debug_svd_ts"):
+        getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().ipeps_strerror(status).decode()
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_opts() -> Opts:
+    o = Opts()
+    load().ipeps_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_terms(terms):
+    """(kind, site, dx, dy, coef, mat) tuples -> (ctypes array, keepalive)."""
+    mats = [_f64(t[5]) for t in terms]
+    arr = (Term * max(1, len(terms)))()
+    for i, (t, m) in enumerate(zip(terms, mats)):
+        arr[i] = Term(int(t[0]), int(t[1]), int(t[2]), int(t[3]),
+                      float(t[4]), _dp(m))
+    return arr, mats
+
+
+class Context:
+    """One iPEPS state with its environment on the device."""
+
+    def __init__(self, A, chi: int, opts: Opts | None = None, stream=None):
+        lib = load()
+        A = _f64(A)
+        if A.ndim != 7:
+            raise ValueError("A must be [Ly, Lx, d, D, D, D, D]")
+        self.Ly, self.Lx, self.d, self.D = A.shape[:4]
+        self.chi = chi
+        self.shape = A.shape
+        h = c_void_p()
+        st = lib.ctm_init(ctypes.byref(h), self.Lx, self.Ly, self.d, self.D,
+                          chi, _dp(A), ctypes.byref(opts) if opts else None,
+                          c_void_p(stream) if stream else None)
+        if st != OK:
+            raise IpepsError(st, "ctm_init")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ctm_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_state(self, A):
+        A = _f64(A)
+        if A.shape != self.shape:
+            raise ValueError("shape mismatch")
+        st = load().ctm_set_state(self._h, _dp(A))
+        if st != OK:
+            raise IpepsError(st, "ctm_set_state")
+
+    def converge(self, tol: float, max_iter: int):
+        """Returns (n_iter, delta, converged)."""
+        n = c_int(0)
+        dl = c_double(0.0)
+        st = load().ctm_converge(self._h, tol, max_iter, ctypes.byref(n),
+                                 ctypes.byref(dl))
+        if st < 0:
+            raise IpepsError(st, "ctm_converge")
+        return n.value, dl.value, st == OK
+
+    def energy_grad(self, terms, grad: bool = True):
+        arr, keep = make_terms(terms)
+        e = c_double(0.0)
+        g = np.zeros(self.shape) if grad else None
+        st = load().ipeps_energy_grad(self._h, len(terms), arr,
+                                      ctypes.byref(e),
+                                      _dp(g) if grad else None)
+        del keep
+        if st != OK:
+            raise IpepsError(st, "ipeps_energy_grad")
+        return e.value, g
+
+    def precond(self, g, delta: float, cg_tol: float, cg_maxiter: int):
+        """Returns (x, n_iter, rel_resid, breakdown)."""
+        g = _f64(g)
+        x = np.zeros(self.shape)
+        n = c_int(0)
+        rr = c_double(0.0)
+        st = load().precond_apply(self._h, _dp(g), delta, cg_tol, cg_maxiter,
+                                  _dp(x), ctypes.byref(n), ctypes.byref(rr))
+        if st < 0 and st != ECG_BREAKDOWN:
+            raise IpepsError(st, "precond_apply")
+        return x, n.value, rr.value, st == ECG_BREAKDOWN
+
+    def spectra(self) -> np.ndarray:
+        out = np.zeros((4, self.Lx * self.Ly, self.chi))
+        st = load().ipeps_corner_spectra(self._h, _dp(out))
+        if st != OK:
+            raise IpepsError(st, "ipeps_corner_spectra")
+        return out
+
+    def env_size(self) -> int:
+        return int(load().ipeps_env_size(self.Lx, self.Ly, self.D, self.chi))
+
+    def get_env(self):
+        """(C[4][n][chi][chi], T[4][n][chi][D^2][chi])"""
+        buf = np.zeros(self.env_size())
+        st = load().ipeps_get_env(self._h, _dp(buf))
+        if st != OK:
+            raise IpepsError(st, "ipeps_get_env")
+        n, chi, D2 = self.Lx * self.Ly, self.chi, self.D * self.D
+        nc = 4 * n * chi * chi
+        return (buf[:nc].reshape(4, n, chi, chi),
+                buf[nc:].reshape(4, n, chi, D2, chi))
+
+    def set_env(self, C, T):
+        buf = np.concatenate([_f64(C).ravel(), _f64(T).ravel()])
+        if buf.size != self.env_size():
+            raise ValueError("environment size mismatch")
+        st = load().ipeps_set_env(self._h, _dp(buf))
+        if st != OK:
+            raise IpepsError(st, "ipeps_set_env")
+
+
+# ------------------------------------------------------------- test hooks
+def debug_gemm(A, B, C, tA=False, tB=False, alpha=1.0, beta=0.0):
+    A, B, C = _f64(A), _f64(B), _f64(C).copy()
+    M, K = (A.shape[1], A.shape[0]) if tA else A.shape
+    N = B.shape[0] if tB else B.shape[1]
+    st = load().ipeps_debug_gemm(int(tA), int(tB), M, N, K, alpha, _dp(A),
+                                 _dp(B), beta, _dp(C))
+    if st != OK:
+        raise IpepsError(st, "ipeps_debug_gemm")
+    return C
+
+
+def debug_sym_eig(G):
+    G = _f64(G)
+    batch, b = G.shape[0], G.shape[1]
+    V = np.zeros_like(G)
+    lam = np.zeros((batch, b))
+    st = load().ipeps_debug_sym_eig(b, batch, _dp(G), _dp(V), _dp(lam))
+    if st != OK:
+        raise IpepsError(st, "ipeps_debug_sym_eig")
+    return lam, V
+
+
+def debug_svd_ts(W):
+    W = _f64(W)
+    batch, n, b = W.shape
+    U = np.zeros_like(W)
+    s = np.zeros((batch, b))
+    J = np.zeros((batch, b, b))
+    st = load().ipeps_debug_svd_ts(n, b, batch, _dp(W), _dp(U), _dp(s),
+                                   _dp(J))
+    if st != OK:
+        raise IpepsError(st, "ipeps_debug_svd_ts")
+    return U, s, J

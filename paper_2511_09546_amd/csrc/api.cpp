@@ -1,0 +1,297 @@
+// C ABI of the library (include/ipeps.h): argument checks, status codes,
+// host <-> device copies.  Every entry point catches all exceptions.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "../../include/ipeps.h"
+#include "ipeps_impl.hpp"
+
+struct ipeps_ctx {
+  ipeps::Context cx;
+};
+
+using namespace ipeps;
+
+namespace {
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const ArgError&) {
+    return IPEPS_EINVAL;
+  } catch (const NotImplError&) {
+    return IPEPS_ENOTIMPL;
+  } catch (const OomError&) {
+    return IPEPS_ENOMEM;
+  } catch (const std::bad_alloc&) {
+    return IPEPS_ENOMEM;
+  } catch (const HipError&) {
+    return IPEPS_EHIP;
+  } catch (...) {
+    return IPEPS_EHIP;
+  }
+}
+
+bool all_finite(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+size_t state_size(const Context& cx) {
+  return (size_t)cx.nsite() * cx.d * cx.D2 * cx.D2;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ipeps_default_opts(ipeps_opts* o) {
+  if (!o) return;
+  o->prec = IPEPS_FP64;
+  o->svd_cutoff = 1e-12;
+  o->grad_K = 20;
+  o->svd_oversample = 0;
+  o->svd_max_iter = 50;
+  o->svd_tol = 1e-13;
+}
+
+const char* ipeps_version(void) { return "ipeps-mi355x 0.1"; }
+
+const char* ipeps_strerror(int s) {
+  switch (s) {
+    case IPEPS_OK: return "ok";
+    case IPEPS_NOT_CONVERGED: return "not converged (warning)";
+    case IPEPS_EINVAL: return "invalid argument";
+    case IPEPS_ENOMEM: return "device out of memory";
+    case IPEPS_EHIP: return "HIP runtime error";
+    case IPEPS_ECG_BREAKDOWN: return "CG breakdown (p^T P p <= 0)";
+    case IPEPS_ESTATE: return "call out of order";
+    case IPEPS_ENOTIMPL: return "not implemented";
+    default: return "unknown status";
+  }
+}
+
+size_t ipeps_env_size(int Lx, int Ly, int D, int chi) {
+  if (Lx < 1 || Ly < 1 || D < 1 || chi < 1) return 0;
+  const size_t n = (size_t)Lx * Ly;
+  return 4 * n * chi * chi + 4 * n * chi * (size_t)D * D * chi;
+}
+
+int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
+             const double* A, const ipeps_opts* opts, void* hip_stream) {
+  if (!out || !A || Lx < 1 || Ly < 1 || d < 1 || D < 1 || chi < D * D ||
+      Lx * Ly > 64 || d > 16 || D > 16)
+    return IPEPS_EINVAL;
+  ipeps_opts o;
+  ipeps_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.prec != IPEPS_FP64) return IPEPS_ENOTIMPL;
+  if (!(o.svd_cutoff >= 0.0) || o.grad_K < 0 || o.svd_max_iter < 1 ||
+      !(o.svd_tol >= 0.0) || o.svd_oversample < 0)
+    return IPEPS_EINVAL;
+  const size_t nA = (size_t)Lx * Ly * d * D * D * D * D;
+  if (!all_finite(A, nA)) return IPEPS_EINVAL;
+  ipeps_ctx* c = nullptr;
+  int st = guarded([&]() {
+    c = new ipeps_ctx();
+    Context& cx = c->cx;
+    if (hip_stream) {
+      cx.dev.stream = (hipStream_t)hip_stream;
+    } else {
+      IPEPS_HIP(hipStreamCreate(&cx.dev.stream));
+      cx.dev.own_stream = true;
+    }
+    cx.lat.Lx = Lx;
+    cx.lat.Ly = Ly;
+    cx.d = d;
+    cx.D = D;
+    cx.D2 = D * D;
+    cx.chi = chi;
+    cx.n = (int64_t)chi * D * D;
+    cx.prec = o.prec;
+    cx.grad_K = o.grad_K;
+    cx.svd.cutoff = o.svd_cutoff;
+    cx.svd.tol = o.svd_tol;
+    cx.svd.max_iter = o.svd_max_iter;
+    cx.b = subspace_block((int)cx.n, chi, o.svd_oversample);
+    cx.A = cx.dev.empty({Lx * Ly, d, D, D, D, D});
+    cx.dev.upload(cx.A, A);
+    build_double_layer(cx);
+    init_env(cx);
+    (void)corner_spectra_change(cx, cx.env);  // reference spectra
+    cx.dev.sync();
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) {
+    if (c) {
+      if (c->cx.dev.own_stream && c->cx.dev.stream)
+        (void)hipStreamDestroy(c->cx.dev.stream);
+      delete c;
+    }
+    return st;
+  }
+  *out = c;
+  return IPEPS_OK;
+}
+
+int ctm_set_state(ipeps_ctx* c, const double* A) {
+  if (!c || !A) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!all_finite(A, state_size(cx))) return IPEPS_EINVAL;
+  return guarded([&]() {
+    cx.dev.upload(cx.A, A);
+    build_double_layer(cx);
+    cx.dev.sync();
+    return IPEPS_OK;
+  });
+}
+
+int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
+                 double* delta) {
+  if (!c || max_iter < 0 || std::isnan(tol)) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  int it = 0;
+  double dl = INFINITY;
+  int st = guarded([&]() {
+    while (it < max_iter) {
+      Env next;
+      ctm_step(cx, cx.env, next, nullptr);
+      cx.env = next;
+      ++it;
+      dl = corner_spectra_change(cx, cx.env);
+      if (tol > 0.0 && dl < tol) break;
+    }
+    cx.converged_once = true;
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  if (n_iter) *n_iter = it;
+  if (delta) *delta = dl;
+  if (tol > 0.0 && !(dl < tol)) return IPEPS_NOT_CONVERGED;
+  return IPEPS_OK;
+}
+
+static int parse_terms(const Context& cx, int n_terms, const ipeps_term* H,
+                       std::vector<TermSpec>& out) {
+  if (n_terms < 0 || (n_terms > 0 && !H)) return IPEPS_EINVAL;
+  for (int i = 0; i < n_terms; ++i) {
+    const ipeps_term& t = H[i];
+    if (!t.mat || t.site < 0 || t.site >= cx.nsite() || !std::isfinite(t.coef))
+      return IPEPS_EINVAL;
+    TermSpec s;
+    s.kind = t.kind;
+    s.site = t.site;
+    s.dx = t.dx;
+    s.dy = t.dy;
+    s.coef = t.coef;
+    size_t m;
+    if (t.kind == 0) {
+      m = (size_t)cx.d;
+    } else if (t.kind == 1) {
+      const bool ok = (t.dx == 1 && t.dy == 0) || (t.dx == 0 && t.dy == 1) ||
+                      (t.dx == 1 && t.dy == 1) || (t.dx == 1 && t.dy == -1);
+      if (!ok) return IPEPS_EINVAL;
+      m = (size_t)cx.d * cx.d;
+    } else {
+      return IPEPS_EINVAL;
+    }
+    if (!all_finite(t.mat, m * m)) return IPEPS_EINVAL;
+    s.mat.assign(t.mat, t.mat + m * m);
+    out.push_back(std::move(s));
+  }
+  return IPEPS_OK;
+}
+
+int ipeps_energy_grad(ipeps_ctx* c, int n_terms, const ipeps_term* H,
+                      double* e_per_site, double* grad) {
+  if (!c || !e_per_site) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  std::vector<TermSpec> terms;
+  int st = parse_terms(cx, n_terms, H, terms);
+  if (st != IPEPS_OK) return st;
+  if (!cx.converged_once) return IPEPS_ESTATE;
+  double e = 0.0;
+  st = guarded([&]() {
+    if (grad) {
+      e = energy_grad(cx, terms, grad);
+    } else {
+      e = energy(cx, cx.env, terms, nullptr, nullptr);
+    }
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  *e_per_site = e;
+  return IPEPS_OK;
+}
+
+int precond_apply(ipeps_ctx* c, const double* g, double delta, double cg_tol,
+                  int cg_maxiter, double* x, int* n_iter, double* rel_resid) {
+  if (!c || !g || !x || !(delta > 0.0) || !std::isfinite(delta) ||
+      !(cg_tol >= 0.0) || cg_maxiter < 0)
+    return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!all_finite(g, state_size(cx))) return IPEPS_EINVAL;
+  if (!cx.converged_once) return IPEPS_ESTATE;
+  int res = 0;
+  int st = guarded([&]() {
+    res = precondition(cx, g, delta, cg_tol, cg_maxiter, x, n_iter,
+                       rel_resid);
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  return res;
+}
+
+int ipeps_corner_spectra(ipeps_ctx* c, double* out) {
+  if (!c || !out) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    (void)corner_spectra_change(cx, cx.env);
+    cx.dev.download(cx.spec_cur, out);
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_get_env(ipeps_ctx* c, double* out) {
+  if (!c || !out) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    cx.dev.download(cx.env.C, out);
+    cx.dev.download(cx.env.T, out + cx.env.C.numel());
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_set_env(ipeps_ctx* c, const double* in) {
+  if (!c || !in) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  const size_t n = ipeps_env_size(cx.lat.Lx, cx.lat.Ly, cx.D, cx.chi);
+  if (!all_finite(in, n)) return IPEPS_EINVAL;
+  return guarded([&]() {
+    Env e;
+    e.C = cx.dev.empty({4, cx.nsite(), cx.chi, cx.chi});
+    e.T = cx.dev.empty({4, cx.nsite(), cx.chi, cx.D2, cx.chi});
+    cx.dev.upload(e.C, in);
+    cx.dev.upload(e.T, in + e.C.numel());
+    cx.env = e;
+    cx.have_warm = false;
+    cx.converged_once = true;
+    (void)corner_spectra_change(cx, cx.env);
+    cx.dev.sync();
+    return IPEPS_OK;
+  });
+}
+
+void ctm_free(ipeps_ctx* c) {
+  if (!c) return;
+  hipStream_t s = c->cx.dev.stream;
+  bool own = c->cx.dev.own_stream;
+  if (s) (void)hipStreamSynchronize(s);
+  delete c;
+  if (own && s) (void)hipStreamDestroy(s);
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Test hooks declared in include/ipeps_debug.h.
+#include "../../include/ipeps.h"
+#include "../../include/ipeps_debug.h"
+#include "ipeps_impl.hpp"
+
+using namespace ipeps;
+
+namespace {
+template <class F>
+int run(F&& f) {
+  try {
+    Device dev;
+    dev.stream = nullptr;
+    f(dev);
+    dev.sync();
+    return IPEPS_OK;
+  } catch (const ArgError&) {
+    return IPEPS_EINVAL;
+  } catch (const OomError&) {
+    return IPEPS_ENOMEM;
+  } catch (...) {
+    return IPEPS_EHIP;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int ipeps_debug_gemm(int tA, int tB, int M, int N, int K, double alpha,
+                     const double* A, const double* B, double beta,
+                     double* C) {
+  if (!A || !B || !C || M < 1 || N < 1 || K < 1) return IPEPS_EINVAL;
+  return run([&](Device& dev) {
+    Tensor a = dev.empty({(int64_t)M * K}), b = dev.empty({(int64_t)K * N}),
+           c = dev.empty({(int64_t)M * N});
+    dev.upload(a, A);
+    dev.upload(b, B);
+    dev.upload(c, C);
+    gemm(dev, tA != 0, tB != 0, M, N, K, alpha, a.ptr, tA ? M : K, 0, b.ptr,
+         tB ? K : N, 0, beta, c.ptr, N, 0, 1);
+    dev.download(c, C);
+  });
+}
+
+int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
+                        double* lam) {
+  if (!G || !V || !lam || b < 2 || b > 128 || b % 2 || batch < 1)
+    return IPEPS_EINVAL;
+  return run([&](Device& dev) {
+    Tensor g = dev.empty({batch, b, b}), v = dev.empty({batch, b, b}),
+           l = dev.empty({batch, b});
+    dev.upload(g, G);
+    sym_eig_jacobi(dev, g.ptr, v.ptr, l.ptr, b, batch);
+    dev.download(v, V);
+    dev.download(l, lam);
+  });
+}
+
+int ipeps_debug_svd_ts(int n, int b, int batch, const double* W, double* U,
+                       double* s, double* J) {
+  if (!W || !U || !s || !J || n < 1 || b < 2 || b > 128 || b % 2 ||
+      batch < 1)
+    return IPEPS_EINVAL;
+  return run([&](Device& dev) {
+    Tensor w = dev.empty({batch, n, b});
+    dev.upload(w, W);
+    Tensor u, sv, j;
+    svd_ts(dev, w, batch, n, b, u, sv, j);
+    dev.download(u, U);
+    dev.download(sv, s);
+    dev.download(j, J);
+  });
+}
+
+}  // extern "C"

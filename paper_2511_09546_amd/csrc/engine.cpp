@@ -1,0 +1,314 @@
+// Device memory pool, tensor views, and the pairwise contraction planner.
+#include <algorithm>
+#include <cstring>
+#include <limits>
+
+#include "engine.hpp"
+
+namespace ipeps {
+
+// ------------------------------------------------------------------- Pool
+static size_t round_bytes(size_t b) {
+  const size_t g = 256;
+  b = (b + g - 1) / g * g;
+  if (b > (1u << 20)) {
+    // coarser rounding for large blocks so that nearby sizes share blocks
+    const size_t g2 = 1u << 16;
+    b = (b + g2 - 1) / g2 * g2;
+  }
+  return b;
+}
+
+void* Pool::alloc(size_t bytes) {
+  bytes = round_bytes(std::max<size_t>(bytes, 8));
+  auto it = free_.find(bytes);
+  if (it != free_.end()) {
+    void* p = it->second;
+    free_.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // return cached blocks to HIP and retry once
+    for (auto& kv : free_) {
+      (void)hipFree(kv.second);
+      for (auto a = all_.begin(); a != all_.end(); ++a)
+        if (a->first == kv.second) {
+          reserved_ -= a->second;
+          all_.erase(a);
+          break;
+        }
+    }
+    free_.clear();
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw OomError("hipMalloc of " + std::to_string(bytes) + " bytes");
+    }
+  }
+  all_.emplace_back(p, bytes);
+  reserved_ += bytes;
+  return p;
+}
+
+void Pool::release(void* p, size_t bytes) {
+  free_.emplace(round_bytes(std::max<size_t>(bytes, 8)), p);
+}
+
+Pool::~Pool() {
+  for (auto& a : all_) (void)hipFree(a.first);
+}
+
+// ----------------------------------------------------------------- Tensor
+Tensor Tensor::view(std::vector<int64_t> s) const {
+  Tensor t = *this;
+  t.shape = std::move(s);
+  if (t.numel() != numel()) throw ArgError("view: numel mismatch");
+  return t;
+}
+
+Tensor Tensor::slice0(int64_t i) const {
+  Tensor t = *this;
+  t.shape.erase(t.shape.begin());
+  t.ptr = ptr + i * t.numel();
+  return t;
+}
+
+// ----------------------------------------------------------------- Device
+Tensor Device::empty(std::vector<int64_t> shape) {
+  Tensor t;
+  t.shape = std::move(shape);
+  const size_t bytes = (size_t)std::max<int64_t>(t.numel(), 1) * 8;
+  auto b = std::make_shared<Buffer>();
+  b->p = pool.alloc(bytes);
+  b->bytes = bytes;
+  b->pool = &pool;
+  t.buf = b;
+  t.ptr = (double*)b->p;
+  return t;
+}
+
+Tensor Device::zeros(std::vector<int64_t> shape) {
+  Tensor t = empty(std::move(shape));
+  fill(*this, t.ptr, t.numel(), 0.0);
+  return t;
+}
+
+Tensor Device::scalar_buffer(int n) { return empty({n}); }
+
+void Device::upload(Tensor& t, const double* host) {
+  IPEPS_HIP(hipMemcpyAsync(t.ptr, host, t.numel() * 8, hipMemcpyHostToDevice,
+                           stream));
+}
+
+void Device::download(const Tensor& t, double* host) {
+  IPEPS_HIP(hipMemcpyAsync(host, t.ptr, t.numel() * 8, hipMemcpyDeviceToHost,
+                           stream));
+  IPEPS_HIP(hipStreamSynchronize(stream));
+}
+
+void Device::sync() { IPEPS_HIP(hipStreamSynchronize(stream)); }
+
+// ---------------------------------------------------------------- einsum
+namespace {
+
+struct Spec {
+  std::string a, b, o;
+};
+
+Spec parse(const std::string& spec) {
+  Spec s;
+  auto c = spec.find(',');
+  auto ar = spec.find("->");
+  if (c == std::string::npos || ar == std::string::npos || ar < c)
+    throw ArgError("einsum: bad spec " + spec);
+  s.a = spec.substr(0, c);
+  s.b = spec.substr(c + 1, ar - c - 1);
+  s.o = spec.substr(ar + 2);
+  return s;
+}
+
+bool has(const std::string& s, char ch) {
+  return s.find(ch) != std::string::npos;
+}
+
+std::vector<int> perm_of(const std::string& from, const std::string& to) {
+  std::vector<int> p;
+  for (char ch : to) p.push_back((int)from.find(ch));
+  return p;
+}
+
+bool is_identity(const std::vector<int>& p) {
+  for (size_t i = 0; i < p.size(); ++i)
+    if (p[i] != (int)i) return false;
+  return true;
+}
+
+// A candidate layout of the two GEMM operands and the output.
+struct Plan {
+  bool swap = false;       // first operand is B
+  std::string first, second, out;  // label orders actually used
+  bool tA = false, tB = false;
+  bool perm_first = false, perm_second = false, perm_out = false;
+  int64_t cost = std::numeric_limits<int64_t>::max();
+};
+
+}  // namespace
+
+static int64_t dim_of(char ch, const std::string& la, const Tensor& A,
+                      const std::string& lb, const Tensor& B) {
+  auto i = la.find(ch);
+  if (i != std::string::npos) return A.shape[i];
+  return B.shape[lb.find(ch)];
+}
+
+void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
+                 const Tensor& B, Tensor& out, double alpha, double beta) {
+  Spec s = parse(spec);
+  if ((int)s.a.size() != A.rank() || (int)s.b.size() != B.rank() ||
+      (int)s.o.size() != out.rank())
+    throw ArgError("einsum: rank mismatch in " + spec);
+  for (size_t i = 0; i < s.a.size(); ++i)
+    if (has(s.b, s.a[i]) && B.shape[s.b.find(s.a[i])] != A.shape[i])
+      throw ArgError("einsum: dim mismatch in " + spec);
+  for (size_t i = 0; i < s.o.size(); ++i)
+    if (dim_of(s.o[i], s.a, A, s.b, B) != out.shape[i])
+      throw ArgError("einsum: output dim mismatch in " + spec);
+  for (char ch : s.a)
+    if (!has(s.b, ch) && !has(s.o, ch))
+      throw ArgError("einsum: summed free label unsupported in " + spec);
+  for (char ch : s.b)
+    if (!has(s.a, ch) && !has(s.o, ch))
+      throw ArgError("einsum: summed free label unsupported in " + spec);
+
+  // label classes
+  std::string batch, contr_a, contr_b, free_a_o, free_b_o;
+  for (char ch : s.o)
+    if (has(s.a, ch) && has(s.b, ch)) batch += ch;
+  for (char ch : s.a)
+    if (has(s.b, ch) && !has(s.o, ch)) contr_a += ch;
+  for (char ch : s.b)
+    if (has(s.a, ch) && !has(s.o, ch)) contr_b += ch;
+  for (char ch : s.o)
+    if (has(s.a, ch) && !has(s.b, ch)) free_a_o += ch;
+  for (char ch : s.o)
+    if (has(s.b, ch) && !has(s.a, ch)) free_b_o += ch;
+  auto own_order = [](const std::string& src, const std::string& sel) {
+    std::string r;
+    for (char ch : src)
+      if (has(sel, ch)) r += ch;
+    return r;
+  };
+  const std::string free_a_own = own_order(s.a, free_a_o);
+  const std::string free_b_own = own_order(s.b, free_b_o);
+
+  int64_t nA = A.numel(), nB = B.numel(), nO = out.numel();
+  Plan best;
+  for (int swap = 0; swap < 2; ++swap) {
+    const std::string& L1 = swap ? s.b : s.a;
+    const std::string& L2 = swap ? s.a : s.b;
+    const int64_t n1 = swap ? nB : nA, n2 = swap ? nA : nB;
+    const std::string& f1o = swap ? free_b_o : free_a_o;
+    const std::string& f2o = swap ? free_a_o : free_b_o;
+    const std::string& f1own = swap ? free_b_own : free_a_own;
+    const std::string& f2own = swap ? free_a_own : free_b_own;
+    for (int co = 0; co < 2; ++co) {
+      const std::string contr = co ? contr_b : contr_a;
+      for (int f1c = 0; f1c < 2; ++f1c) {
+        const std::string f1 = f1c ? f1own : f1o;
+        for (int f2c = 0; f2c < 2; ++f2c) {
+          const std::string f2 = f2c ? f2own : f2o;
+          Plan p;
+          p.swap = swap;
+          // first operand: [batch f1 contr] (tA=0) or [batch contr f1]
+          const std::string l1n = batch + f1 + contr;
+          const std::string l1t = batch + contr + f1;
+          if (L1 == l1n) {
+            p.first = l1n;
+          } else if (L1 == l1t) {
+            p.first = l1t;
+            p.tA = true;
+          } else {
+            p.first = l1n;
+            p.perm_first = true;
+          }
+          const std::string l2n = batch + contr + f2;
+          const std::string l2t = batch + f2 + contr;
+          if (L2 == l2n) {
+            p.second = l2n;
+          } else if (L2 == l2t) {
+            p.second = l2t;
+            p.tB = true;
+          } else {
+            p.second = l2n;
+            p.perm_second = true;
+          }
+          p.out = batch + f1 + f2;
+          p.perm_out = (p.out != s.o);
+          p.cost = (p.perm_first ? n1 : 0) + (p.perm_second ? n2 : 0) +
+                   (p.perm_out ? 2 * nO : 0);
+          // prefer no transposes on ties (slightly faster loads)
+          if (p.cost < best.cost ||
+              (p.cost == best.cost && (int)p.tA + (int)p.tB <
+                                          (int)best.tA + (int)best.tB))
+            best = p;
+        }
+      }
+    }
+  }
+
+  const Tensor& T1 = best.swap ? B : A;
+  const Tensor& T2 = best.swap ? A : B;
+  const std::string& L1 = best.swap ? s.b : s.a;
+  const std::string& L2 = best.swap ? s.a : s.b;
+  Tensor op1 = T1, op2 = T2;
+  if (best.perm_first) op1 = permuted(dev, T1, perm_of(L1, best.first));
+  if (best.perm_second) op2 = permuted(dev, T2, perm_of(L2, best.second));
+
+  auto prod = [&](const std::string& ls) {
+    int64_t p = 1;
+    for (char ch : ls) p *= dim_of(ch, s.a, A, s.b, B);
+    return p;
+  };
+  const std::string f1 =
+      best.out.substr(batch.size(), best.out.size() - batch.size());
+  int64_t nbatch = prod(batch);
+  // free labels of the first operand are those of out after batch that
+  // belong to L1
+  std::string lf1, lf2;
+  for (char ch : f1) (has(L1, ch) ? lf1 : lf2) += ch;
+  const int64_t M = prod(lf1), N = prod(lf2);
+  std::string contr;
+  for (char ch : best.first)
+    if (has(L2, ch) && !has(batch, ch)) contr += ch;
+  const int64_t K = prod(contr);
+
+  Tensor dst = out;
+  double beta_g = beta;
+  if (best.perm_out) {
+    std::vector<int64_t> sh;
+    for (char ch : best.out) sh.push_back(dim_of(ch, s.a, A, s.b, B));
+    dst = dev.empty(sh);
+    beta_g = 0.0;
+  }
+  const int64_t lda = best.tA ? M : K;
+  const int64_t ldb = best.tB ? K : N;
+  gemm(dev, best.tA, best.tB, M, N, K, best.perm_out ? 1.0 : alpha, op1.ptr,
+       lda, M * K, op2.ptr, ldb, K * N, beta_g, dst.ptr, N, M * N, nbatch);
+  if (best.perm_out) permute(dev, dst, perm_of(best.out, s.o), out, alpha,
+                             beta);
+}
+
+Tensor einsum(Device& dev, const std::string& spec, const Tensor& A,
+              const Tensor& B) {
+  Spec s = parse(spec);
+  std::vector<int64_t> sh;
+  for (char ch : s.o) sh.push_back(dim_of(ch, s.a, A, s.b, B));
+  Tensor out = dev.empty(sh);
+  einsum_into(dev, spec, A, B, out, 1.0, 0.0);
+  return out;
+}
+
+}  // namespace ipeps

@@ -1,0 +1,179 @@
+// Internal engine of the iPEPS library: device memory, dense FP64 tensors on
+// one HIP stream, and the launch wrappers of the hand-written gfx950 kernels.
+// Errors inside the engine are C++ exceptions; the C ABI (api.cpp) turns them
+// into status codes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace ipeps {
+
+struct HipError : std::runtime_error {
+  explicit HipError(const std::string& s) : std::runtime_error(s) {}
+};
+struct OomError : std::runtime_error {
+  explicit OomError(const std::string& s) : std::runtime_error(s) {}
+};
+struct ArgError : std::runtime_error {
+  explicit ArgError(const std::string& s) : std::runtime_error(s) {}
+};
+struct NotImplError : std::runtime_error {
+  explicit NotImplError(const std::string& s) : std::runtime_error(s) {}
+};
+
+#define IPEPS_HIP(call)                                                   \
+  do {                                                                    \
+    hipError_t e__ = (call);                                              \
+    if (e__ != hipSuccess)                                                \
+      throw ::ipeps::HipError(std::string(#call) + ": " +                \
+                              hipGetErrorString(e__));                    \
+  } while (0)
+
+// Caching device allocator owned by one context.  Blocks are kept by exact
+// (rounded) size and reused; everything is returned to HIP at destruction.
+class Pool {
+ public:
+  Pool() = default;
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
+  ~Pool();
+  void* alloc(size_t bytes);
+  void release(void* p, size_t bytes);
+  size_t reserved() const { return reserved_; }
+
+ private:
+  std::multimap<size_t, void*> free_;
+  std::vector<std::pair<void*, size_t>> all_;
+  size_t reserved_ = 0;
+};
+
+struct Buffer {
+  void* p = nullptr;
+  size_t bytes = 0;
+  Pool* pool = nullptr;
+  ~Buffer() {
+    if (p) pool->release(p, bytes);
+  }
+};
+
+// Dense row-major FP64 tensor in device memory (shared ownership of the
+// buffer; views share it).
+struct Tensor {
+  std::shared_ptr<Buffer> buf;
+  double* ptr = nullptr;
+  std::vector<int64_t> shape;
+
+  int64_t numel() const {
+    int64_t n = 1;
+    for (auto s : shape) n *= s;
+    return n;
+  }
+  int rank() const { return (int)shape.size(); }
+  Tensor view(std::vector<int64_t> s) const;   // same data, new shape
+  Tensor slice0(int64_t i) const;              // sub-tensor along dim 0
+};
+
+// Execution context: one stream and one pool.
+struct Device {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  Pool pool;
+
+  Tensor empty(std::vector<int64_t> shape);
+  Tensor zeros(std::vector<int64_t> shape);
+  Tensor scalar_buffer(int n);            // n doubles
+  void upload(Tensor& t, const double* host);
+  void download(const Tensor& t, double* host);
+  void sync();
+};
+
+// ---------------------------------------------------------------- kernels
+// C[b] = alpha op(A[b]) op(B[b]) + beta C[b], row major; op(A) is M x K
+// (A[m*lda+k], or A[k*lda+m] when tA), op(B) is K x N (B[k*ldb+n], or
+// B[n*ldb+k] when tB), batch strides sA, sB, sC in elements.
+void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
+          double alpha, const double* A, int64_t lda, int64_t sA,
+          const double* B, int64_t ldb, int64_t sB, double beta, double* C,
+          int64_t ldc, int64_t sC, int64_t batch = 1);
+
+// out = alpha * permute(in, perm) + beta * out; out.shape[i] =
+// in.shape[perm[i]].
+void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
+             Tensor& out, double alpha = 1.0, double beta = 0.0);
+Tensor permuted(Device& dev, const Tensor& in, const std::vector<int>& perm);
+
+void fill(Device& dev, double* x, int64_t n, double v);
+// y = a * x + b * y
+void axpby(Device& dev, int64_t n, double a, const double* x, double b,
+           double* y);
+// x[i] *= s[0] (device scalar), or x[i] /= s[0] when inverse
+void scale_dev(Device& dev, double* x, int64_t n, const double* s,
+               bool inverse);
+// out[0] = sum x*y (deterministic two-stage reduction), FP64
+void dot(Device& dev, const double* x, const double* y, int64_t n,
+         double* out);
+// out[0] = sqrt(sum x*x)
+void nrm2(Device& dev, const double* x, int64_t n, double* out);
+
+// Batched symmetric eigendecomposition by parallel cyclic Jacobi, one
+// workgroup per matrix: G[bt] (b x b row major, b even, b <= 128) is
+// overwritten by its diagonalised form, V[bt] (b x b row major) receives
+// the eigenvectors as columns, lam[bt] the eigenvalues; both sorted by
+// descending eigenvalue.
+void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
+                    int batch);
+
+// Column 2-norms of an n x b row-major matrix: out[j] = ||X[:, j]||.
+void col_norms(Device& dev, const double* X, int64_t n, int b, double* out,
+               int batch = 1, int64_t sX = 0, int64_t sOut = 0);
+// X[:, j] *= f(s[j]) with f = 1/s (0 if s == 0) (mode 0), s^-1/2 masked by
+// keep (mode 1), plain s (mode 2).
+void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
+               int mode, const int* keep = nullptr, int batch = 1,
+               int64_t sX = 0, int64_t sS = 0);
+
+// ------------------------------------------------------------ contractions
+// Pairwise tensor contraction with single-character labels, e.g.
+// "mgi,ij->mgj".  Labels in both inputs and the output are batch labels,
+// in both inputs only are contracted, in one input and the output are free.
+// Implemented as (at most) permutes + one batched GEMM; the plan avoids
+// permutes where the GEMM transposes allow.
+Tensor einsum(Device& dev, const std::string& spec, const Tensor& A,
+              const Tensor& B);
+// out = alpha * einsum(...) + beta * out (out has the output shape)
+void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
+                 const Tensor& B, Tensor& out, double alpha = 1.0,
+                 double beta = 0.0);
+
+}  // namespace ipeps
+
+namespace ipeps {
+void random_block(Device& dev, double* X, int64_t n, uint64_t seed);
+void eye(Device& dev, double* X, int64_t n, int b, int batch, int64_t sX);
+void sign_fix(Device& dev, double* U, double* V, int64_t n, int b, int batch,
+              int64_t sU, int64_t sV);
+void kept_rank(Device& dev, const double* S, int b, int chi, double cut,
+               int* keep, int batch, int64_t sS);
+void svd_residual(Device& dev, const double* Z, const double* V,
+                  const double* S, int64_t n, int b, int k, double* r,
+                  int batch, int64_t sZ, int64_t sS);
+void pad3(Device& dev, const double* in, double* out, int a, int b, int c,
+          int B, int C);
+void spectra_update(Device& dev, const double* S, int b, int chi, int batch,
+                    int64_t sS, double* cur, double* old, double* delta);
+}  // namespace ipeps
+
+namespace ipeps {
+void term_energy(Device& dev, const double* rho, const double* h, int m,
+                 double coef, double* acc, double* rho_bar);
+void splitk_reduce(Device& dev, const double* part, int S, int64_t M,
+                   int64_t N, double alpha, double beta, double* C,
+                   int64_t ldc);
+}  // namespace ipeps

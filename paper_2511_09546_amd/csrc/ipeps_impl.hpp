@@ -1,0 +1,138 @@
+// State of one iPEPS context and the declarations of the hot-path stages.
+#pragma once
+
+#include <array>
+#include <vector>
+
+#include "engine.hpp"
+
+namespace ipeps {
+
+// ---------------------------------------------------------------- SVD
+struct CutBatch {
+  int ncut = 0;
+  int64_t n = 0;   // cut matrix side chi * D^2
+  int b = 0;       // subspace block (even)
+  int chi = 0;
+  std::vector<const double*> Qa, Qb;  // n x n row major, per cut
+};
+
+struct SvdParams {
+  double tol = 1e-13;
+  int max_iter = 50;
+  double cutoff = 1e-12;
+};
+
+struct SvdStats {
+  long iters = 0;
+  long calls = 0;
+  double worst_residual = 0.0;
+};
+
+void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
+            Tensor& U, Tensor& S, Tensor& J);
+int subspace_block(int n, int chi, int oversample);
+void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
+                   Tensor& U, Tensor& S, Tensor& V, Tensor& keep,
+                   const SvdParams& prm, SvdStats* stats);
+
+// ------------------------------------------------------------- lattice
+// Clockwise conventions (c = 0..3: upper-left, upper-right, lower-right,
+// lower-left corner; top, right, bottom, left edge):
+//   C_c[ccw, cw], T_c[ccw, in, cw], a_c = a with legs cyclically shifted by c
+//   so that a_c[g, e, b, f] has g facing T_{c-1}, e facing T_c, b on the
+//   clockwise and f on the counter-clockwise cut of corner c.
+struct Lattice {
+  int Lx = 1, Ly = 1;
+  int n() const { return Lx * Ly; }
+  int idx(int x, int y) const {
+    x %= Lx;
+    if (x < 0) x += Lx;
+    y %= Ly;
+    if (y < 0) y += Ly;
+    return y * Lx + x;
+  }
+  int shift(int s, int dx, int dy) const {
+    return idx(s % Lx + dx, s / Lx + dy);
+  }
+};
+
+constexpr int PLAQ_OFFSET[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+constexpr int CORNER_MOVE[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+constexpr int EDGE_MOVE[4][2] = {{0, 1}, {-1, 0}, {0, -1}, {1, 0}};
+constexpr int INIT_CORNER_SITE[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+constexpr int INIT_EDGE_SITE[4][2] = {{0, -1}, {1, 0}, {0, 1}, {-1, 0}};
+
+// Environment: C[c][s] (chi x chi) and T[c][s] (chi x D2 x chi) stored in
+// two contiguous tensors [4][nsite][...].
+struct Env {
+  Tensor C, T;
+};
+
+// Everything one CTMRG iteration records for the backward pass.
+struct StepTape {
+  Env in;                       // environment entering the iteration
+  Tensor Q;                     // [4][nsite][n][n] enlarged corners
+  Tensor U, S, V, keep;         // [ncut][n][b], [ncut][b], ..., ncut ints
+  Tensor P, PtT;                // [ncut][n][chi] projectors (Pt transposed)
+  Tensor Craw, Traw;            // unnormalised new corners / edges
+  Tensor Cnorm, Tnorm;          // their norms [4*nsite]
+};
+
+struct Context {
+  Device dev;
+  Lattice lat;
+  int d = 0, D = 0, D2 = 0, chi = 0;
+  int64_t n = 0;        // chi * D2
+  int b = 0;            // subspace block
+  int prec = 0;
+  double cutoff = 1e-12;
+  int grad_K = 20;
+  SvdParams svd;
+  SvdStats stats;
+
+  Tensor A;             // [nsite][d][D][D][D][D]
+  Tensor a_rot;         // [nsite][4][D2][D2][D2][D2]
+  Tensor ao_rot;        // [nsite][4][d][d][D2]^4 (built on demand)
+  Env env;
+  bool have_env = false;
+  bool converged_once = false;
+  Tensor Xwarm;         // [ncut][n][b] right singular blocks (warm start)
+  bool have_warm = false;
+  Tensor spec_cur, spec_old;  // [4*nsite][chi]
+
+  int nsite() const { return lat.n(); }
+  int ncut() const { return 4 * lat.n(); }
+  Tensor Cv(const Env& e, int c, int s) const;
+  Tensor Tv(const Env& e, int c, int s) const;
+  Tensor av(int s, int c) const;
+};
+
+// ctmrg.cpp
+void build_double_layer(Context& cx);
+void init_env(Context& cx);
+// One simultaneous CTMRG iteration: env_out from env_in; records into tape
+// when tape != nullptr.
+void ctm_step(Context& cx, const Env& in, Env& out, StepTape* tape);
+double corner_spectra_change(Context& cx, const Env& e);
+void corner_spectra(Context& cx, const Env& e, Tensor& out);
+
+// observables.cpp
+struct TermSpec {
+  int kind, site, dx, dy;
+  double coef;
+  std::vector<double> mat;
+};
+double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms,
+              Tensor* gA, Env* gEnv);
+
+// metric.cpp
+int precondition(Context& cx, const double* g_host, double delta,
+                 double cg_tol, int cg_maxiter, double* x_host, int* n_iter,
+                 double* rel_resid);
+
+// adjoint.cpp
+double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
+                   double* grad_host);
+
+}  // namespace ipeps

@@ -1,0 +1,920 @@
+// Hand-written gfx950 kernels of the iPEPS library (FP64 path).
+//
+//  * gemm_f64: batched GEMM on the FP64 matrix cores
+//    (v_mfma_f64_16x16x4_f64), LDS-staged tiles, 4 waves of 64 lanes per
+//    workgroup, each wave owning a (BM/2) x (BN/2) block of 16x16 MFMA tiles.
+//  * permute: generic rank <= 8 transpose, coalesced writes.
+//  * deterministic two-stage FP64 reductions (dot, 2-norm).
+//  * sym_eig_jacobi: batched parallel cyclic Jacobi eigensolver, one
+//    workgroup per matrix, the matrix resident in LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "engine.hpp"
+
+namespace ipeps {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ GEMM
+// MFMA f64 16x16x4 lane layout (checked on gfx950): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; the 16x16 result holds D[l/16 + 4r][l%16]
+// in register r of lane l.
+template <int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A,
+    long lda, long sA, int tA, const double* __restrict__ B, long ldb,
+    long sB, int tB, double beta, double* __restrict__ C, long ldc,
+    long sC) {
+  constexpr int WTM = BM / 2, WTN = BN / 2;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long bz = blockIdx.z;
+  A += bz * sA;
+  B += bz * sB;
+  C += bz * sC;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  f64x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int kb = 0; kb < K; kb += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      int mm, kk;
+      if (!tA) {
+        mm = e / BK;
+        kk = e % BK;
+      } else {
+        kk = e / BM;
+        mm = e % BM;
+      }
+      const int gm = m0 + mm, gk = kb + kk;
+      double v = 0.0;
+      if (gm < M && gk < K)
+        v = tA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
+      As[kk][mm] = v;
+    }
+    for (int e = tid; e < BK * BN; e += 256) {
+      int kk, nn;
+      if (!tB) {
+        kk = e / BN;
+        nn = e % BN;
+      } else {
+        nn = e / BK;
+        kk = e % BK;
+      }
+      const int gk = kb + kk, gn = n0 + nn;
+      double v = 0.0;
+      if (gk < K && gn < N)
+        v = tB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < BK; k4 += 4) {
+      double a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        a[i] = As[k4 + (lane >> 4)][wm * WTM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        b[j] = Bs[k4 + (lane >> 4)][wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j],
+                                                           acc[i][j], 0, 0,
+                                                           0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + i * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          double v = alpha * acc[i][j][r];
+          if (beta != 0.0) v += beta * C[(long)row * ldc + col];
+          C[(long)row * ldc + col] = v;
+        }
+      }
+}
+
+void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
+          double alpha, const double* A, int64_t lda, int64_t sA,
+          const double* B, int64_t ldb, int64_t sB, double beta, double* C,
+          int64_t ldc, int64_t sC, int64_t batch) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31) ||
+      batch > 65535)
+    throw ArgError("gemm: size out of range");
+  if (K == 0) {
+    // C = beta C
+    for (int64_t b = 0; b < batch; ++b)
+      for (int64_t m = 0; m < M; ++m)
+        axpby(dev, N, 0.0, C + b * sC + m * ldc, beta, C + b * sC + m * ldc);
+    return;
+  }
+  constexpr int BM = 64, BN = 64, BK = 16;
+  const int64_t tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
+  if (tiles * batch < 128 && K >= 2048) {
+    // split K: every chunk is one batch entry of a strided GEMM into a
+    // partial buffer, then a fixed-order reduction (deterministic)
+    int S = (int)std::min<int64_t>(256 / std::max<int64_t>(tiles, 1),
+                                   K / 512);
+    S = std::max(S, 2);
+    const int64_t kc = (K + S - 1) / S;
+    S = (int)((K + kc - 1) / kc);
+    Tensor part = dev.empty({S, M, N});
+    for (int64_t bt = 0; bt < batch; ++bt) {
+      const double* Ab = A + bt * sA;
+      const double* Bb = B + bt * sB;
+      const int64_t last = K - (S - 1) * kc;
+      // full chunks
+      if (S > 1) {
+        dim3 g((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM),
+               (unsigned)(S - 1));
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), g, dim3(256), 0,
+                           dev.stream, (int)M, (int)N, (int)kc, 1.0, Ab,
+                           (long)lda, (long)(tA ? kc * lda : kc), (int)tA, Bb,
+                           (long)ldb, (long)(tB ? kc : kc * ldb), (int)tB,
+                           0.0, part.ptr, (long)N, (long)(M * N));
+      }
+      {
+        const double* Al = Ab + (tA ? (S - 1) * kc * lda : (S - 1) * kc);
+        const double* Bl = Bb + (tB ? (S - 1) * kc : (S - 1) * kc * ldb);
+        dim3 g((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM),
+               1);
+        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), g, dim3(256), 0,
+                           dev.stream, (int)M, (int)N, (int)last, 1.0, Al,
+                           (long)lda, 0L, (int)tA, Bl, (long)ldb, 0L, (int)tB,
+                           0.0, part.ptr + (S - 1) * M * N, (long)N, 0L);
+      }
+      IPEPS_HIP(hipGetLastError());
+      splitk_reduce(dev, part.ptr, S, M, N, alpha, beta, C + bt * sC, ldc);
+    }
+    return;
+  }
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM),
+            (unsigned)batch);
+  if (grid.y > 65535) throw ArgError("gemm: M too large for grid");
+  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), grid, dim3(256), 0,
+                     dev.stream, (int)M, (int)N, (int)K, alpha, A, (long)lda,
+                     (long)sA, (int)tA, B, (long)ldb, (long)sB, (int)tB, beta,
+                     C, (long)ldc, (long)sC);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------------------- permute
+struct PermArgs {
+  int rank;
+  int out_shape[8];
+  int in_stride[8];  // input stride along output dimension i
+};
+
+__global__ void permute_kernel(const double* __restrict__ in,
+                               double* __restrict__ out, int n, PermArgs p,
+                               double alpha, double beta) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += gridDim.x * blockDim.x) {
+    int rem = i, off = 0;
+    for (int d = p.rank - 1; d >= 0; --d) {
+      const int q = rem / p.out_shape[d];
+      off += (rem - q * p.out_shape[d]) * p.in_stride[d];
+      rem = q;
+    }
+    double v = alpha * in[off];
+    if (beta != 0.0) v += beta * out[i];
+    out[i] = v;
+  }
+}
+
+static int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
+             Tensor& out, double alpha, double beta) {
+  const int r = in.rank();
+  if ((int)perm.size() != r || out.rank() != r)
+    throw ArgError("permute: rank mismatch");
+  // fold: drop size-1 dims and merge output dims that are contiguous in the
+  // input
+  std::vector<int64_t> istride(r);
+  int64_t s = 1;
+  for (int d = r - 1; d >= 0; --d) {
+    istride[d] = s;
+    s *= in.shape[d];
+  }
+  std::vector<int64_t> oshape, ostr;
+  for (int i = 0; i < r; ++i) {
+    if (out.shape[i] != in.shape[perm[i]])
+      throw ArgError("permute: shape mismatch");
+    if (in.shape[perm[i]] == 1) continue;
+    const int64_t st = istride[perm[i]];
+    if (!oshape.empty() && ostr.back() == st * in.shape[perm[i]]) {
+      oshape.back() *= in.shape[perm[i]];
+      ostr.back() = st;
+    } else {
+      oshape.push_back(in.shape[perm[i]]);
+      ostr.push_back(st);
+    }
+  }
+  const int64_t n = in.numel();
+  if (n == 0) return;
+  if (n >= (1LL << 31)) throw ArgError("permute: tensor too large");
+  if (oshape.size() == 1 && ostr[0] == 1) {
+    // contiguous: plain copy/axpby
+    axpby(dev, n, alpha, in.ptr, beta, out.ptr);
+    return;
+  }
+  if (oshape.empty()) {
+    axpby(dev, n, alpha, in.ptr, beta, out.ptr);
+    return;
+  }
+  if (oshape.size() > 8) throw ArgError("permute: rank > 8");
+  PermArgs p{};
+  p.rank = (int)oshape.size();
+  for (int i = 0; i < p.rank; ++i) {
+    p.out_shape[i] = (int)oshape[i];
+    p.in_stride[i] = (int)ostr[i];
+  }
+  hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, in.ptr, out.ptr, (int)n, p, alpha, beta);
+  IPEPS_HIP(hipGetLastError());
+}
+
+Tensor permuted(Device& dev, const Tensor& in, const std::vector<int>& perm) {
+  std::vector<int64_t> sh(perm.size());
+  for (size_t i = 0; i < perm.size(); ++i) sh[i] = in.shape[perm[i]];
+  Tensor out = dev.empty(sh);
+  permute(dev, in, perm, out);
+  return out;
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void fill_kernel(double* x, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+void fill(Device& dev, double* x, int64_t n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, x, n, v);
+  IPEPS_HIP(hipGetLastError());
+}
+
+__global__ void axpby_kernel(int64_t n, double a, const double* x, double b,
+                             double* y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = a * x[i];
+    if (b != 0.0) v += b * y[i];
+    y[i] = v;
+  }
+}
+
+void axpby(Device& dev, int64_t n, double a, const double* x, double b,
+           double* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, n, a, x, b, y);
+  IPEPS_HIP(hipGetLastError());
+}
+
+__global__ void scale_dev_kernel(double* x, int64_t n, const double* s,
+                                 int inverse) {
+  const double f = inverse ? 1.0 / s[0] : s[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= f;
+}
+
+void scale_dev(Device& dev, double* x, int64_t n, const double* s,
+               bool inverse) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scale_dev_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, x, n, s, (int)inverse);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------- reductions
+// Stage 1: each of G blocks reduces a strided range; stage 2 adds the G
+// partials in a fixed order.  Bitwise deterministic for a fixed n.
+constexpr int RED_BLOCK = 256;
+constexpr int RED_GRID = 256;
+
+__device__ inline double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(RED_BLOCK) void dot_partial_kernel(
+    const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+    double* __restrict__ part) {
+  __shared__ double sh[RED_BLOCK / 64];
+  double v = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)RED_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * RED_BLOCK)
+    v += x[i] * y[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(RED_BLOCK) void final_sum_kernel(
+    const double* __restrict__ part, int np, double* out, int take_sqrt) {
+  __shared__ double sh[RED_BLOCK / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += RED_BLOCK) v += part[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) out[0] = take_sqrt ? sqrt(v) : v;
+}
+
+static void reduce_dot(Device& dev, const double* x, const double* y,
+                       int64_t n, double* out, int take_sqrt) {
+  Tensor part = dev.empty({RED_GRID});
+  const int g = (int)std::max<int64_t>(
+      1, std::min<int64_t>(RED_GRID, (n + RED_BLOCK - 1) / RED_BLOCK));
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(g), dim3(RED_BLOCK), 0,
+                     dev.stream, x, y, n, part.ptr);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(RED_BLOCK), 0,
+                     dev.stream, part.ptr, g, out, take_sqrt);
+  IPEPS_HIP(hipGetLastError());
+}
+
+void dot(Device& dev, const double* x, const double* y, int64_t n,
+         double* out) {
+  reduce_dot(dev, x, y, n, out, 0);
+}
+
+void nrm2(Device& dev, const double* x, int64_t n, double* out) {
+  reduce_dot(dev, x, x, n, out, 1);
+}
+
+// ------------------------------------------------------- column utilities
+__global__ void col_norms_kernel(const double* __restrict__ X, int64_t n,
+                                 int b, double* __restrict__ out, long sX,
+                                 long sOut) {
+  // one wave per column; rows strided over 64 lanes
+  const int bt = blockIdx.y;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= b) return;
+  const double* x = X + bt * sX;
+  double v = 0.0;
+  for (int64_t i = lane; i < n; i += 64) {
+    const double t = x[i * b + j];
+    v += t * t;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane == 0) out[bt * sOut + j] = sqrt(v);
+}
+
+void col_norms(Device& dev, const double* X, int64_t n, int b, double* out,
+               int batch, int64_t sX, int64_t sOut) {
+  dim3 grid((b + 3) / 4, batch);
+  hipLaunchKernelGGL(col_norms_kernel, grid, dim3(256), 0, dev.stream, X, n,
+                     b, out, (long)sX, (long)sOut);
+  IPEPS_HIP(hipGetLastError());
+}
+
+__global__ void col_scale_kernel(double* __restrict__ X, int64_t n, int b,
+                                 const double* __restrict__ s, int mode,
+                                 const int* __restrict__ keep, long sX,
+                                 long sS) {
+  const int bt = blockIdx.y;
+  double* x = X + bt * sX;
+  const double* ss = s + bt * sS;
+  const int64_t total = n * b;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(i % b);
+    const double v = ss[j];
+    double f;
+    if (mode == 0) {
+      f = v != 0.0 ? 1.0 / v : 0.0;
+    } else if (mode == 1) {
+      const int k = keep ? keep[bt] : b;
+      f = (j < k && v > 0.0) ? 1.0 / sqrt(v) : 0.0;
+    } else {
+      f = v;
+    }
+    x[i] *= f;
+  }
+}
+
+void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
+               int mode, const int* keep, int batch, int64_t sX,
+               int64_t sS) {
+  dim3 grid(grid_for(n * b, 256), batch);
+  hipLaunchKernelGGL(col_scale_kernel, grid, dim3(256), 0, dev.stream, X, n,
+                     b, s, mode, keep, (long)sX, (long)sS);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------- Jacobi eigensolver
+// Parallel cyclic Jacobi (round-robin pairing, b-1 rounds of b/2 disjoint
+// rotations per sweep).  The rotation of pair (p,q) annihilates G[p][q]
+// (Golub & Van Loan, symmetric Schur 2x2); a pair is skipped when
+// |G_pq| <= 1e-15 sqrt|G_pp G_qq| (relative criterion, so small eigenvalues
+// of graded matrices keep their relative accuracy).  Stops after a sweep
+// without rotations (or 40 sweeps).  G lives in LDS, V in global memory.
+constexpr int JAC_THREADS = 512;
+constexpr int JAC_MAXB = 128;
+
+__global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
+    double* __restrict__ Gall, double* __restrict__ Vall,
+    double* __restrict__ lamall, int b) {
+  extern __shared__ double lds[];
+  double* G = lds;                  // b*b
+  double* cs = G + b * b;           // b/2
+  double* sn = cs + b / 2;          // b/2
+  int* pp = (int*)(sn + b / 2);     // b/2
+  int* qq = pp + b / 2;             // b/2
+  __shared__ int rotated;
+  const int bt = blockIdx.x;
+  double* Gg = Gall + (long)bt * b * b;
+  double* V = Vall + (long)bt * b * b;
+  double* lam = lamall + (long)bt * b;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i < b * b; i += nt) {
+    G[i] = Gg[i];
+    V[i] = (i / b == i % b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int half = b / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < b - 1; ++r) {
+      // pairs of this round, rotation parameters from the current G
+      for (int i = tid; i < half; i += nt) {
+        auto P = [&](int j) { return j == 0 ? 0 : 1 + (j - 1 + r) % (b - 1); };
+        int p = P(i), q = P(b - 1 - i);
+        if (p > q) {
+          int t = p;
+          p = q;
+          q = t;
+        }
+        pp[i] = p;
+        qq[i] = q;
+        const double apq = G[p * b + q];
+        const double app = G[p * b + p], aqq = G[q * b + q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) /
+                           (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          rotated = 1;
+        }
+        cs[i] = c;
+        sn[i] = s;
+      }
+      __syncthreads();
+      // rows: G <- J^T G
+      for (int e = tid; e < half * b; e += nt) {
+        const int i = e / b, k = e % b;
+        const double c = cs[i], s = sn[i];
+        if (s == 0.0) continue;
+        const int p = pp[i], q = qq[i];
+        const double gp = G[p * b + k], gq = G[q * b + k];
+        G[p * b + k] = c * gp - s * gq;
+        G[q * b + k] = s * gp + c * gq;
+      }
+      __syncthreads();
+      // columns: G <- G J, V <- V J
+      for (int e = tid; e < half * b; e += nt) {
+        const int i = e % half, k = e / half;
+        const double c = cs[i], s = sn[i];
+        if (s == 0.0) continue;
+        const int p = pp[i], q = qq[i];
+        const double gp = G[k * b + p], gq = G[k * b + q];
+        G[k * b + p] = c * gp - s * gq;
+        G[k * b + q] = s * gp + c * gq;
+        const double vp = V[k * b + p], vq = V[k * b + q];
+        V[k * b + p] = c * vp - s * vq;
+        V[k * b + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  // sort by descending eigenvalue (stable rank of every diagonal entry);
+  // pp/qq and cs/sn are contiguous, giving b ints and b doubles of LDS
+  int* rk = pp;
+  double* ev = cs;
+  __syncthreads();
+  for (int i = tid; i < b; i += nt) {
+    const double gi = G[i * b + i];
+    int rank = 0;
+    for (int j = 0; j < b; ++j) {
+      const double gj = G[j * b + j];
+      rank += (gj > gi) || (gj == gi && j < i);
+    }
+    rk[i] = rank;
+  }
+  __syncthreads();
+  for (int i = tid; i < b; i += nt) ev[rk[i]] = G[i * b + i];
+  __syncthreads();
+  // G is no longer needed: permute the columns of V through it
+  for (int e = tid; e < b * b; e += nt) {
+    const int k = e / b, i = e % b;
+    G[k * b + rk[i]] = V[k * b + i];
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += nt) {
+    V[e] = G[e];
+    Gg[e] = (e / b == e % b) ? ev[e / b] : 0.0;
+  }
+  for (int i = tid; i < b; i += nt) lam[i] = ev[i];
+}
+
+void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
+                    int batch) {
+  if (b % 2 != 0 || b < 2 || b > JAC_MAXB)
+    throw ArgError("sym_eig_jacobi: b must be even and <= 128");
+  const size_t lds = (size_t)b * b * sizeof(double) +
+                     2 * (b / 2) * sizeof(double) + 2 * (b / 2) * sizeof(int);
+  static size_t lds_set = 0;
+  if (lds > 65536 && lds > lds_set) {
+    IPEPS_HIP(hipFuncSetAttribute((const void*)sym_eig_jacobi_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    lds_set = lds;
+  }
+  hipLaunchKernelGGL(sym_eig_jacobi_kernel, dim3(batch), dim3(JAC_THREADS),
+                     lds, dev.stream, G, V, lam, b);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps
+
+namespace ipeps {
+
+// ------------------------------------------------------- SVD helper kernels
+// Deterministic pseudo-random start block: splitmix64 of (seed, index)
+// mapped to (-1, 1).
+__global__ void random_block_kernel(double* X, int64_t n, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    X[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+void random_block(Device& dev, double* X, int64_t n, uint64_t seed) {
+  hipLaunchKernelGGL(random_block_kernel, dim3(grid_for(n, 256)), dim3(256),
+                     0, dev.stream, X, n, seed);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// X (n x b, batched) = identity in the leading min(n, b) block.
+__global__ void eye_kernel(double* X, int64_t n, int b, long sX) {
+  double* x = X + blockIdx.y * sX;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+       i < n * b; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (i / b == i % b) ? 1.0 : 0.0;
+}
+
+void eye(Device& dev, double* X, int64_t n, int b, int batch, int64_t sX) {
+  hipLaunchKernelGGL(eye_kernel, dim3(grid_for(n * b, 256), batch), dim3(256),
+                     0, dev.stream, X, n, b, (long)sX);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Sign convention: in every column u of U the entry r maximising
+// |u_r| (1 + r/(2n)) (first one on ties) is made positive; the same column of
+// V takes the same sign.  The weight separates the entries (k,k') and (k',k)
+// that the ket-bra exchange symmetry of the double layer makes equal in
+// magnitude.
+__global__ void sign_fix_kernel(double* U, double* V, int64_t n, int b,
+                                long sU, long sV) {
+  const int bt = blockIdx.y;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= b) return;
+  double* u = U + bt * sU;
+  double* v = V + bt * sV;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = lane; i < n; i += 64) {
+    const double a = fabs(u[i * b + j]) * (1.0 + (double)i / (2.0 * (double)n));
+    if (a > best) {
+      best = a;
+      bi = i;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_down(best, o, 64);
+    const int64_t oi = __shfl_down(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  bi = __shfl(bi, 0, 64);
+  const double sg = u[bi * b + j] < 0.0 ? -1.0 : 1.0;
+  if (sg < 0.0) {
+    for (int64_t i = lane; i < n; i += 64) {
+      u[i * b + j] = -u[i * b + j];
+      v[i * b + j] = -v[i * b + j];
+    }
+  }
+}
+
+void sign_fix(Device& dev, double* U, double* V, int64_t n, int b, int batch,
+              int64_t sU, int64_t sV) {
+  dim3 grid((b + 3) / 4, batch);
+  hipLaunchKernelGGL(sign_fix_kernel, grid, dim3(256), 0, dev.stream, U, V, n,
+                     b, (long)sU, (long)sV);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// keep[bt] = min(chi, #{s_i > cut * s_0})
+__global__ void kept_rank_kernel(const double* S, int b, int chi, double cut,
+                                 int* keep, long sS) {
+  const int bt = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const double* s = S + bt * sS;
+  const double thr = cut * s[0];
+  int k = 0;
+  for (int i = 0; i < b; ++i) k += (s[i] > thr) ? 1 : 0;
+  keep[bt] = k < chi ? k : chi;
+}
+
+void kept_rank(Device& dev, const double* S, int b, int chi, double cut,
+               int* keep, int batch, int64_t sS) {
+  hipLaunchKernelGGL(kept_rank_kernel, dim3(batch), dim3(64), 0, dev.stream,
+                     S, b, chi, cut, keep, (long)sS);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Residual of the top-k triplets: r[bt] = max_{i<k} ||Z_i - s_i V_i|| / s_0
+// (Z = M^T U), one workgroup per batch entry.
+__global__ void svd_residual_kernel(const double* Z, const double* V,
+                                    const double* S, int64_t n, int b, int k,
+                                    double* r, long sZ, long sS) {
+  const int bt = blockIdx.x;
+  const double* z = Z + bt * sZ;
+  const double* v = V + bt * sZ;
+  const double* s = S + bt * sS;
+  __shared__ double red[64];
+  double worst = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const double t = z[i * b + j] - s[j] * v[i * b + j];
+      acc += t * t;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+      worst = fmax(worst, sqrt(t));
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) r[bt] = s[0] > 0.0 ? worst / s[0] : 0.0;
+}
+
+void svd_residual(Device& dev, const double* Z, const double* V,
+                  const double* S, int64_t n, int b, int k, double* r,
+                  int batch, int64_t sZ, int64_t sS) {
+  hipLaunchKernelGGL(svd_residual_kernel, dim3(batch), dim3(256), 0,
+                     dev.stream, Z, V, S, n, b, k, r, (long)sZ, (long)sS);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Zero-padded 3-D copy: out[A][B][C] (pre-zeroed) <- in[a][b][c] in its
+// leading corner.
+__global__ void pad3_kernel(const double* in, double* out, int a, int b, int c,
+                            int B, int C) {
+  const int64_t n = (int64_t)a * b * c;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i % c);
+    const int j = (int)((i / c) % b);
+    const int l = (int)(i / ((int64_t)b * c));
+    out[((int64_t)l * B + j) * C + k] = in[i];
+  }
+}
+
+void pad3(Device& dev, const double* in, double* out, int a, int b, int c,
+          int B, int C) {
+  const int64_t n = (int64_t)a * b * c;
+  hipLaunchKernelGGL(pad3_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, in, out, a, b, c, B, C);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Corner-spectrum change: spec[bt] (b values, sorted) normalised to sum 1
+// into out (chi values, zero padded); delta[0] = max_bt ||out - old||_2 and
+// old <- out.  One workgroup.
+__global__ void spectra_update_kernel(const double* S, int b, int chi,
+                                      int batch, long sS, double* cur,
+                                      double* old, double* delta) {
+  __shared__ double red[64];
+  double worst = 0.0;
+  for (int bt = 0; bt < batch; ++bt) {
+    const double* s = S + bt * sS;
+    double tot = 0.0;
+    for (int i = threadIdx.x; i < b; i += blockDim.x) tot += s[i];
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_down(tot, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += red[w];
+    __syncthreads();
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < chi; i += blockDim.x) {
+      const double v = (i < b && sum > 0.0) ? s[i] / sum : 0.0;
+      const double dlt = v - old[bt * chi + i];
+      acc += dlt * dlt;
+      cur[bt * chi + i] = v;
+      old[bt * chi + i] = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    worst = fmax(worst, sqrt(t));
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) delta[0] = worst;
+}
+
+void spectra_update(Device& dev, const double* S, int b, int chi, int batch,
+                    int64_t sS, double* cur, double* old, double* delta) {
+  hipLaunchKernelGGL(spectra_update_kernel, dim3(1), dim3(256), 0, dev.stream,
+                     S, b, chi, batch, (long)sS, cur, old, delta);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps
+
+namespace ipeps {
+
+// ------------------------------------------------------------ term energy
+// value = sum_{s,t} h[t][s] rho[s][t], tr = sum_s rho[s][s];
+// acc[0] += coef * value / tr;
+// rho_bar[s][t] = coef * (h[t][s] - (value/tr) delta_st) / tr  (cotangent of
+// rho for the backward pass), if rho_bar != nullptr.  One workgroup.
+__global__ void term_energy_kernel(const double* rho, const double* h, int m,
+                                   double coef, double* acc,
+                                   double* rho_bar) {
+  __shared__ double red[2][64];
+  double v = 0.0, tr = 0.0;
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+    const int s = i / m, t = i % m;
+    v += h[t * m + s] * rho[i];
+    if (s == t) tr += rho[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    v += __shfl_down(v, o, 64);
+    tr += __shfl_down(tr, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = v;
+    red[1][threadIdx.x >> 6] = tr;
+  }
+  __syncthreads();
+  double V = 0.0, TR = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    V += red[0][w];
+    TR += red[1][w];
+  }
+  const double e = V / TR;
+  if (threadIdx.x == 0) acc[0] += coef * e;
+  if (rho_bar)
+    for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+      const int s = i / m, t = i % m;
+      rho_bar[i] = coef * (h[t * m + s] - (s == t ? e : 0.0)) / TR;
+    }
+}
+
+void term_energy(Device& dev, const double* rho, const double* h, int m,
+                 double coef, double* acc, double* rho_bar) {
+  hipLaunchKernelGGL(term_energy_kernel, dim3(1), dim3(256), 0, dev.stream,
+                     rho, h, m, coef, acc, rho_bar);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Split-K partial tiles: C = alpha * sum_s part[s] + beta * C.
+__global__ void splitk_reduce_kernel(const double* part, int S, int64_t M,
+                                     int64_t N, double alpha, double beta,
+                                     double* C, int64_t ldc) {
+  const int64_t mn = M * N;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < mn;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += part[s * mn + i];
+    const int64_t r = i / N, c = i % N;
+    double o = alpha * v;
+    if (beta != 0.0) o += beta * C[r * ldc + c];
+    C[r * ldc + c] = o;
+  }
+}
+
+void splitk_reduce(Device& dev, const double* part, int S, int64_t M,
+                   int64_t N, double alpha, double beta, double* C,
+                   int64_t ldc) {
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(M * N, 256)),
+                     dim3(256), 0, dev.stream, part, S, M, N, alpha, beta, C,
+                     ldc);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps
+
+namespace ipeps {
+
+// ------------------------------------------------------------- CG updates
+// All scalars live on the device; a step is skipped when p^T A p <= 0 so
+// that the host sees the breakdown with x still holding the last iterate.
+__global__ void cg_update_xr_kernel(int64_t n, const double* rr,
+                                    const double* pAp, const double* p,
+                                    const double* Ap, double* x, double* r) {
+  if (!(pAp[0] > 0.0)) return;
+  const double alpha = rr[0] / pAp[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    r[i] -= alpha * Ap[i];
+  }
+}
+
+void cg_update_xr(Device& dev, int64_t n, const double* rr, const double* pAp,
+                  const double* p, const double* Ap, double* x, double* r) {
+  hipLaunchKernelGGL(cg_update_xr_kernel, dim3(grid_for(n, 256)), dim3(256),
+                     0, dev.stream, n, rr, pAp, p, Ap, x, r);
+  IPEPS_HIP(hipGetLastError());
+}
+
+__global__ void cg_update_p_kernel(int64_t n, const double* rr_new,
+                                   const double* rr, const double* pAp,
+                                   const double* r, double* p) {
+  if (!(pAp[0] > 0.0)) return;
+  const double beta = rr_new[0] / rr[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = r[i] + beta * p[i];
+}
+
+void cg_update_p(Device& dev, int64_t n, const double* rr_new,
+                 const double* rr, const double* pAp, const double* r,
+                 double* p) {
+  hipLaunchKernelGGL(cg_update_p_kernel, dim3(grid_for(n, 256)), dim3(256),
+                     0, dev.stream, n, rr_new, rr, pAp, r, p);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// y = y / s[0] + delta * x
+__global__ void scale_add_dev_kernel(int64_t n, const double* s,
+                                     const double* x, double delta,
+                                     double* y) {
+  const double f = 1.0 / s[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = y[i] * f + delta * x[i];
+}
+
+void scale_add_dev(Device& dev, int64_t n, const double* s, const double* x,
+                   double delta, double* y) {
+  hipLaunchKernelGGL(scale_add_dev_kernel, dim3(grid_for(n, 256)), dim3(256),
+                     0, dev.stream, n, s, x, delta, y);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps

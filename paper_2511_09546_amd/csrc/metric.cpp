@@ -1,0 +1,138 @@
+// Local-metric preconditioner (Eq. (11)) with regularisation N + delta I
+// (Sec. III B), solved by conjugate gradients (Sec. III C), one independent
+// solve per unit-cell site (Sec. IV B).
+//
+// N is applied matrix-free from the converged environment: with the
+// half-rings LT = T4 (C1 T1 C2) (left + top) and RB = T2 (C3 T3 C4) (right +
+// bottom), the single-site ring is E[(l l'),(u u'),(r r'),(d d')] =
+// sum_{w,m} LT[w,(l l'),(u u'),m] RB[m,(r r'),(d d'),w], and
+//   (N x)[t, l'u'r'd'] = sum_{lurd} E x[t, lurd] / Z,  Z = <A, E A>.
+// Two GEMMs per application (K = D^2, then K = chi^2 D^2) with LT and RB
+// permuted once so that neither GEMM needs a permute.  CG scalars, dots and
+// residuals are FP64; alpha and beta stay on the device.
+#include <cmath>
+
+#include "ipeps_impl.hpp"
+#include "observables.hpp"
+
+namespace ipeps {
+
+namespace {
+
+struct SiteMetric {
+  Tensor LTq;  // [(l u), (l' u' w m)]   : [D^2][D^2 chi^2]
+  Tensor RBq;  // [(w m r d), (r' d')]   : [chi^2 D^2][D^2]
+  Tensor Zinv; // device scalar 1/Z
+};
+
+SiteMetric build_metric(Context& cx, const Env& e, int s) {
+  Device& dev = cx.dev;
+  const int D = cx.D, chi = cx.chi;
+  Tensor Tp1 = einsum(dev, "ij,jek->iek", cx.Cv(e, 0, s), cx.Tv(e, 0, s));
+  Tensor Tp = einsum(dev, "iek,km->iem", Tp1, cx.Cv(e, 1, s));
+  Tensor Bt1 = einsum(dev, "np,pzq->nzq", cx.Cv(e, 2, s), cx.Tv(e, 2, s));
+  Tensor Bt = einsum(dev, "nzq,qw->nzw", Bt1, cx.Cv(e, 3, s));
+  Tensor LT = einsum(dev, "wgi,iem->wgem", cx.Tv(e, 3, s), Tp);
+  Tensor RB = einsum(dev, "mbn,nzw->mbzw", cx.Tv(e, 1, s), Bt);
+  SiteMetric sm;
+  // LT[w, l, l', u, u', m] -> [l, u, l', u', w, m]
+  Tensor LT6 = LT.view({chi, D, D, D, D, chi});
+  sm.LTq = permuted(dev, LT6, {1, 3, 2, 4, 0, 5});
+  // RB[m, r, r', d, d', w] -> [w, m, r, d, r', d']
+  Tensor RB6 = RB.view({chi, D, D, D, D, chi});
+  sm.RBq = permuted(dev, RB6, {5, 0, 1, 3, 2, 4});
+  sm.Zinv = dev.empty({1});
+  return sm;
+}
+
+// y = E x (unnormalised), x and y [d][D^4]
+void apply_ring(Context& cx, const SiteMetric& sm, const double* x,
+                double* y, Tensor& W1) {
+  Device& dev = cx.dev;
+  const int64_t D2 = cx.D2, chi = cx.chi, d = cx.d;
+  const int64_t Mq = D2 * chi * chi;  // (l' u' w m)
+  if (W1.numel() != d * Mq * D2) W1 = dev.empty({d, Mq, D2});
+  // W1[t][(l' u' w m)][(r d)] = sum_{(l u)} LTq[(l u)][(l' u' w m)] x[t][(l u)][(r d)]
+  gemm(dev, true, false, Mq, D2, D2, 1.0, sm.LTq.ptr, Mq, 0, x, D2, D2 * D2,
+       0.0, W1.ptr, D2, Mq * D2, d);
+  // y[t][(l' u')][(r' d')] = sum_{(w m r d)} W1[t][(l' u')][(w m r d)] RBq
+  gemm(dev, false, false, D2, D2, chi * chi * D2, 1.0, W1.ptr,
+       chi * chi * D2, Mq * D2, sm.RBq.ptr, D2, 0, 0.0, y, D2, D2 * D2, d);
+}
+
+}  // namespace
+
+// CG kernels live in kernels.hip
+void cg_update_xr(Device& dev, int64_t n, const double* rr, const double* pAp,
+                  const double* p, const double* Ap, double* x, double* r);
+void cg_update_p(Device& dev, int64_t n, const double* rr_new,
+                 const double* rr, const double* pAp, const double* r,
+                 double* p);
+void scale_add_dev(Device& dev, int64_t n, const double* s, const double* x,
+                   double delta, double* y);
+
+int precondition(Context& cx, const double* g_host, double delta,
+                 double cg_tol, int cg_maxiter, double* x_host, int* n_iter,
+                 double* rel_resid) {
+  Device& dev = cx.dev;
+  const int ns = cx.nsite();
+  const int64_t m = (int64_t)cx.d * cx.D2 * cx.D2;  // per-site length
+  Tensor g = dev.empty({ns, m});
+  dev.upload(g, g_host);
+  Tensor x = dev.zeros({ns, m});
+  Tensor r = dev.empty({m}), p = dev.empty({m}), Ap = dev.empty({m});
+  Tensor sc = dev.zeros({8});  // 0 rr, 1 pAp, 2 rr_new, 3 gnorm^2, 4 Z
+  Tensor W1;
+  int worst_it = 0;
+  double worst_res = 0.0;
+  bool breakdown = false;
+  for (int s = 0; s < ns; ++s) {
+    SiteMetric sm = build_metric(cx, cx.env, s);
+    // Z = <A, E A>
+    apply_ring(cx, sm, cx.A.ptr + s * m, Ap.ptr, W1);
+    dot(dev, cx.A.ptr + s * m, Ap.ptr, m, sc.ptr + 4);
+    const double* gs = g.ptr + s * m;
+    double* xs = x.ptr + s * m;
+    axpby(dev, m, 1.0, gs, 0.0, r.ptr);
+    axpby(dev, m, 1.0, gs, 0.0, p.ptr);
+    dot(dev, r.ptr, r.ptr, m, sc.ptr + 0);
+    double hs[8];
+    dev.download(sc, hs);
+    const double gnorm = std::sqrt(hs[0]);
+    double rr = hs[0];
+    int it = 0;
+    if (gnorm > 0.0) {
+      while (it < cg_maxiter && std::sqrt(rr) > cg_tol * gnorm) {
+        apply_ring(cx, sm, p.ptr, Ap.ptr, W1);
+        // Ap = Ap / Z + delta p
+        scale_add_dev(dev, m, sc.ptr + 4, p.ptr, delta, Ap.ptr);
+        dot(dev, p.ptr, Ap.ptr, m, sc.ptr + 1);
+        cg_update_xr(dev, m, sc.ptr + 0, sc.ptr + 1, p.ptr, Ap.ptr, xs,
+                     r.ptr);
+        dot(dev, r.ptr, r.ptr, m, sc.ptr + 2);
+        cg_update_p(dev, m, sc.ptr + 2, sc.ptr + 0, sc.ptr + 1, r.ptr,
+                    p.ptr);
+        dev.download(sc, hs);
+        if (!(hs[1] > 0.0)) {
+          // breakdown: the update kernels skipped this step, x holds the
+          // last iterate
+          breakdown = true;
+          break;
+        }
+        rr = hs[2];
+        // rr <- rr_new (device)
+        axpby(dev, 1, 1.0, sc.ptr + 2, 0.0, sc.ptr + 0);
+        ++it;
+      }
+    }
+    worst_it = std::max(worst_it, it);
+    worst_res = std::max(worst_res, gnorm > 0.0 ? std::sqrt(rr) / gnorm : 0.0);
+    if (breakdown) break;
+  }
+  dev.download(x, x_host);
+  if (n_iter) *n_iter = worst_it;
+  if (rel_resid) *rel_resid = worst_res;
+  return breakdown ? -4 : 0;
+}
+
+}  // namespace ipeps

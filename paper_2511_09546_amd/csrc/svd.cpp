@@ -1,0 +1,130 @@
+// Truncated SVD of the half-system cut matrices M = Qa Qb (never formed).
+//
+// Block subspace iteration with Rayleigh-Ritz on M^T M, warm-started from the
+// right singular block of the previous CTMRG iteration:
+//   W = M X = Qa (Qb X)                       (two GEMMs)
+//   W J = U diag(s)   (tall-skinny SVD, below), V = X J
+//   Z = M^T U = Qb^T (Qa^T U)                 (two GEMMs)
+//   stop when max_{i<chi} ||Z_i - s_i V_i|| <= tol * s_1, else X = orth(Z).
+// When the block covers the whole space (b >= n) X is the identity and one
+// pass gives the exact SVD.
+//
+// Tall-skinny SVD of W (n x b): two passes of "Gram matrix W^T W, Jacobi
+// eigendecomposition W^T W = J diag(l) J^T, W <- W J".  The first pass makes
+// the columns nearly orthogonal; the second works on a graded, nearly
+// diagonal Gram matrix, where Jacobi is relatively accurate, and restores the
+// relative accuracy of the small singular values.  s = column norms.
+#include <algorithm>
+#include <cmath>
+
+#include "ipeps_impl.hpp"
+
+namespace ipeps {
+
+void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
+            Tensor& U, Tensor& S, Tensor& J) {
+  const int64_t sW = n * b, sG = (int64_t)b * b;
+  Tensor G = dev.empty({batch, b, b});
+  Tensor J1 = dev.empty({batch, b, b});
+  Tensor J2 = dev.empty({batch, b, b});
+  Tensor lam = dev.empty({batch, b});
+  Tensor B1 = dev.empty({batch, n, b});
+  // pass 1
+  gemm(dev, true, false, b, b, n, 1.0, W.ptr, b, sW, W.ptr, b, sW, 0.0, G.ptr,
+       b, sG, batch);
+  sym_eig_jacobi(dev, G.ptr, J1.ptr, lam.ptr, b, batch);
+  gemm(dev, false, false, n, b, b, 1.0, W.ptr, b, sW, J1.ptr, b, sG, 0.0,
+       B1.ptr, b, sW, batch);
+  // pass 2
+  gemm(dev, true, false, b, b, n, 1.0, B1.ptr, b, sW, B1.ptr, b, sW, 0.0,
+       G.ptr, b, sG, batch);
+  sym_eig_jacobi(dev, G.ptr, J2.ptr, lam.ptr, b, batch);
+  if (U.numel() != batch * n * b) U = dev.empty({batch, n, b});
+  if (S.numel() != batch * b) S = dev.empty({batch, b});
+  if (J.numel() != batch * sG) J = dev.empty({batch, b, b});
+  gemm(dev, false, false, n, b, b, 1.0, B1.ptr, b, sW, J2.ptr, b, sG, 0.0,
+       U.ptr, b, sW, batch);
+  gemm(dev, false, false, b, b, b, 1.0, J1.ptr, b, sG, J2.ptr, b, sG, 0.0,
+       J.ptr, b, sG, batch);
+  col_norms(dev, U.ptr, n, b, S.ptr, batch, sW, b);
+  col_scale(dev, U.ptr, n, b, S.ptr, 0, nullptr, batch, sW, b);
+}
+
+int subspace_block(int n, int chi, int oversample) {
+  int p = oversample > 0 ? oversample : std::max(16, chi / 3);
+  int b = chi + p;
+  if (b % 2) ++b;
+  if (b >= n) {
+    b = n + (n % 2);
+  }
+  if (b > 128) b = 128;
+  if (b < n && b <= chi) throw ArgError("chi too large for the projector SVD");
+  return b;
+}
+
+void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
+                   Tensor& U, Tensor& S, Tensor& V, Tensor& keep,
+                   const SvdParams& prm, SvdStats* stats) {
+  const int nc = cb.ncut, b = cb.b;
+  const int64_t n = cb.n;
+  const bool direct = b >= n;
+  const int64_t sX = n * b;
+  if (X.numel() != nc * sX) {
+    X = dev.empty({nc, n, b});
+    warm = false;
+  }
+  if (direct) {
+    eye(dev, X.ptr, n, b, nc, sX);
+  } else if (!warm) {
+    random_block(dev, X.ptr, nc * sX, 0x5eed1234ull);
+    Tensor Uo, So, Jo;
+    svd_ts(dev, X, nc, n, b, Uo, So, Jo);
+    X = Uo;
+  }
+  Tensor T1 = dev.empty({nc, n, b});
+  Tensor W = dev.empty({nc, n, b});
+  Tensor Z = dev.empty({nc, n, b});
+  Tensor J;
+  Tensor res = dev.empty({nc});
+  std::vector<double> hres(nc);
+  V = dev.empty({nc, n, b});
+  int it = 0;
+  double worst = 0.0;
+  for (;;) {
+    ++it;
+    for (int c = 0; c < nc; ++c) {
+      gemm(dev, false, false, n, b, n, 1.0, cb.Qb[c], n, 0, X.ptr + c * sX, b,
+           0, 0.0, T1.ptr + c * sX, b, 0);
+      gemm(dev, false, false, n, b, n, 1.0, cb.Qa[c], n, 0, T1.ptr + c * sX,
+           b, 0, 0.0, W.ptr + c * sX, b, 0);
+    }
+    svd_ts(dev, W, nc, n, b, U, S, J);
+    gemm(dev, false, false, n, b, b, 1.0, X.ptr, b, sX, J.ptr, b,
+         (int64_t)b * b, 0.0, V.ptr, b, sX, nc);
+    if (direct) break;
+    for (int c = 0; c < nc; ++c) {
+      gemm(dev, true, false, n, b, n, 1.0, cb.Qa[c], n, 0, U.ptr + c * sX, b,
+           0, 0.0, T1.ptr + c * sX, b, 0);
+      gemm(dev, true, false, n, b, n, 1.0, cb.Qb[c], n, 0, T1.ptr + c * sX,
+           b, 0, 0.0, Z.ptr + c * sX, b, 0);
+    }
+    svd_residual(dev, Z.ptr, V.ptr, S.ptr, n, b, std::min(cb.chi, b), res.ptr,
+                 nc, sX, b);
+    dev.download(res, hres.data());
+    worst = *std::max_element(hres.begin(), hres.end());
+    if (worst <= prm.tol || it >= prm.max_iter) break;
+    Tensor Jz, Sz;
+    svd_ts(dev, Z, nc, n, b, X, Sz, Jz);
+  }
+  sign_fix(dev, U.ptr, V.ptr, n, b, nc, sX, sX);
+  if (keep.numel() < nc) keep = dev.empty({nc});
+  kept_rank(dev, S.ptr, b, cb.chi, prm.cutoff, (int*)keep.ptr, nc, b);
+  X = V;  // warm start of the next call
+  if (stats) {
+    stats->iters += it;
+    stats->calls += 1;
+    stats->worst_residual = std::max(stats->worst_residual, worst);
+  }
+}
+
+}  // namespace ipeps

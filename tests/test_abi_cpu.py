@@ -1,0 +1,65 @@
+"""The C-ABI library builds, loads and exports every declared symbol; the
+host-only entry points and the argument checks work without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2511_09546_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", src)
+    keep = []
+    for nm in names:
+        if nm in ("sizeof", "defined") or nm in keep:
+            continue
+        keep.append(nm)
+    return keep
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2511_09546_amd import build
+        build.build()
+    return binding.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared("ipeps.h") + _declared("ipeps_debug.h")
+    assert set(binding.API_FUNCTIONS) <= set(declared)
+    for name in declared:
+        assert hasattr(lib, name), name
+    for name in binding.API_FUNCTIONS + binding.DEBUG_FUNCTIONS:
+        assert name in declared
+
+
+def test_host_only_entry_points(lib):
+    assert binding.strerror(binding.EINVAL) == "invalid argument"
+    assert lib.ipeps_version().decode().startswith("ipeps")
+    o = binding.default_opts()
+    assert o.prec == binding.FP64 and o.grad_K == 20
+    assert o.svd_cutoff == 1e-12 and o.svd_tol == 1e-13
+    assert lib.ipeps_env_size(2, 2, 3, 10) == 4 * 4 * 100 + 4 * 4 * 10 * 9 * 10
+
+
+def test_argument_checks_before_any_device_call(lib):
+    A = np.zeros((1, 1, 2, 3, 3, 3, 3))
+    h = ctypes.c_void_p()
+    dp = A.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    # chi < D^2, bad sizes, null pointers: rejected on the host
+    assert lib.ctm_init(ctypes.byref(h), 1, 1, 2, 3, 8, dp, None, None) == -1
+    assert lib.ctm_init(ctypes.byref(h), 0, 1, 2, 3, 9, dp, None, None) == -1
+    assert lib.ctm_init(None, 1, 1, 2, 3, 9, dp, None, None) == -1
+    A[0, 0, 0, 0, 0, 0, 0] = np.nan
+    assert lib.ctm_init(ctypes.byref(h), 1, 1, 2, 3, 9, dp, None, None) == -1
+    assert lib.ctm_converge(None, 1e-10, 10, None, None) == -1
+    assert lib.precond_apply(None, None, 1.0, 0.0, 1, None, None, None) == -1
+    lib.ctm_free(None)

@@ -1,0 +1,72 @@
+"""Unit checks of single device kernels against plain numpy FP64."""
+import numpy as np
+import pytest
+
+from paper_2511_09546_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("M,N,K,tA,tB", [
+    (16, 16, 4, False, False), (64, 64, 16, False, False),
+    (70, 33, 19, False, False), (70, 33, 19, True, False),
+    (70, 33, 19, False, True), (70, 33, 19, True, True),
+    (129, 200, 300, False, False), (5, 300, 1, False, False)])
+def test_gemm(M, N, K, tA, tB):
+    _say(f"gemm {M}x{N}x{K} tA={tA} tB={tB}")
+    rng = np.random.default_rng(M * N + K)
+    A = rng.standard_normal((K, M) if tA else (M, K))
+    B = rng.standard_normal((N, K) if tB else (K, N))
+    C0 = rng.standard_normal((M, N))
+    C = binding.debug_gemm(A, B, C0, tA, tB, alpha=0.7, beta=-0.3)
+    ref = 0.7 * ((A.T if tA else A) @ (B.T if tB else B)) - 0.3 * C0
+    assert np.abs(C - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()) * K
+
+
+def test_gemm_split_k():
+    _say("gemm split-K 36x36x5000")
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((36, 5000))
+    B = rng.standard_normal((5000, 36))
+    C = binding.debug_gemm(A, B, np.zeros((36, 36)))
+    assert np.abs(C - A @ B).max() < 1e-10
+
+
+@pytest.mark.parametrize("b,batch", [(2, 1), (8, 3), (32, 2), (96, 1),
+                                     (128, 1)])
+def test_sym_eig(b, batch):
+    _say(f"sym_eig b={b} batch={batch}")
+    rng = np.random.default_rng(b)
+    X = rng.standard_normal((batch, b, b))
+    G = X + X.transpose(0, 2, 1)
+    lam, V = binding.debug_sym_eig(G)
+    for i in range(batch):
+        ref = np.sort(np.linalg.eigvalsh(G[i]))[::-1]
+        assert np.abs(lam[i] - ref).max() < 1e-12 * np.abs(ref).max() * b
+        assert np.abs(V[i].T @ V[i] - np.eye(b)).max() < 1e-13 * b
+        assert np.abs(V[i] @ np.diag(lam[i]) @ V[i].T - G[i]).max() \
+            < 1e-12 * np.abs(G[i]).max() * b
+
+
+def test_svd_ts_graded():
+    """Singular values spanning 10 orders of magnitude: absolute accuracy
+    1e-14 s_1 for all of them, relative accuracy 1e-10 down to 1e-5 s_1 (the
+    second Gram/Jacobi pass restores what squaring lost in the first)."""
+    _say("svd_ts graded")
+    rng = np.random.default_rng(5)
+    n, b = 300, 24
+    Q1, _ = np.linalg.qr(rng.standard_normal((n, b)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((b, b)))
+    s_true = np.logspace(0, -10, b)
+    W = (Q1 * s_true) @ Q2.T
+    U, s, J = binding.debug_svd_ts(W[None])
+    assert np.abs(s[0] - s_true).max() < 1e-14
+    big = s_true >= 1e-5
+    assert np.abs(s[0][big] / s_true[big] - 1).max() < 1e-10
+    assert np.abs(U[0].T @ U[0] - np.eye(b)).max() < 1e-12
+    assert np.abs(W @ J[0] - U[0] * s[0]).max() < 1e-13
+    assert np.abs(J[0].T @ J[0] - np.eye(b)).max() < 1e-13
