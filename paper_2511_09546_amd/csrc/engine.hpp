@@ -103,7 +103,8 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
           const double* B, int64_t ldb, int64_t sB, double beta, double* C,
           int64_t ldc, int64_t sC, int64_t batch = 1);
 
-// out = alpha * permute(in, perm) + beta * out; out.shape[i] =
+// out = alpha * permute(in, perm) + beta * out (rank <= 12 after merging
+// contiguous dims); out.shape[i] =
 // in.shape[perm[i]].
 void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
              Tensor& out, double alpha = 1.0, double beta = 0.0);
@@ -176,4 +177,9 @@ void term_energy(Device& dev, const double* rho, const double* h, int m,
 void splitk_reduce(Device& dev, const double* part, int S, int64_t M,
                    int64_t N, double alpha, double beta, double* C,
                    int64_t ldc);
+}  // namespace ipeps
+
+namespace ipeps {
+void null_threshold(Device& dev, double* S, int b, double rel, int batch,
+                    int64_t sS);
 }  // namespace ipeps

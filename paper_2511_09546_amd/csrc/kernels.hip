@@ -181,8 +181,8 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
 // --------------------------------------------------------------- permute
 struct PermArgs {
   int rank;
-  int out_shape[8];
-  int in_stride[8];  // input stride along output dimension i
+  int out_shape[12];
+  int in_stride[12];  // input stride along output dimension i
 };
 
 __global__ void permute_kernel(const double* __restrict__ in,
@@ -246,7 +246,7 @@ void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
     axpby(dev, n, alpha, in.ptr, beta, out.ptr);
     return;
   }
-  if (oshape.size() > 8) throw ArgError("permute: rank > 8");
+  if (oshape.size() > 12) throw ArgError("permute: rank > 12");
   PermArgs p{};
   p.rank = (int)oshape.size();
   for (int i = 0; i < p.rank; ++i) {
@@ -914,6 +914,34 @@ void scale_add_dev(Device& dev, int64_t n, const double* s, const double* x,
                    double delta, double* y) {
   hipLaunchKernelGGL(scale_add_dev_kernel, dim3(grid_for(n, 256)), dim3(256),
                      0, dev.stream, n, s, x, delta, y);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps
+
+namespace ipeps {
+
+// s[bt][j] <- 0 where s[bt][j] <= rel * max_j s[bt][j] (numerical null
+// columns of a tall-skinny SVD are set to exactly zero instead of being
+// normalised into noise).  One workgroup per batch entry.
+__global__ void null_threshold_kernel(double* S, int b, double rel, long sS) {
+  double* s = S + blockIdx.x * sS;
+  __shared__ double red[64];
+  double m = 0.0;
+  for (int j = threadIdx.x; j < b; j += blockDim.x) m = fmax(m, s[j]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double mx = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, red[w]);
+  for (int j = threadIdx.x; j < b; j += blockDim.x)
+    if (s[j] <= rel * mx) s[j] = 0.0;
+}
+
+void null_threshold(Device& dev, double* S, int b, double rel, int batch,
+                    int64_t sS) {
+  hipLaunchKernelGGL(null_threshold_kernel, dim3(batch), dim3(128), 0,
+                     dev.stream, S, b, rel, (long)sS);
   IPEPS_HIP(hipGetLastError());
 }
 

@@ -13,7 +13,10 @@
 // eigendecomposition W^T W = J diag(l) J^T, W <- W J".  The first pass makes
 // the columns nearly orthogonal; the second works on a graded, nearly
 // diagonal Gram matrix, where Jacobi is relatively accurate, and restores the
-// relative accuracy of the small singular values.  s = column norms.
+// relative accuracy of the small singular values.  s = column norms; values
+// below 1e-13 of the largest are set to zero with a zero column (rank
+// deficient blocks, e.g. zero-padded environments, stay orthonormal where
+// they are nonzero).
 #include <algorithm>
 #include <cmath>
 
@@ -47,6 +50,9 @@ void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
   gemm(dev, false, false, b, b, b, 1.0, J1.ptr, b, sG, J2.ptr, b, sG, 0.0,
        J.ptr, b, sG, batch);
   col_norms(dev, U.ptr, n, b, S.ptr, batch, sW, b);
+  // columns at rounding level (<= 1e-13 of the largest) are exact zeros:
+  // normalising them would inject non-orthogonal noise into the subspace
+  null_threshold(dev, S.ptr, b, 1e-13, batch, b);
   col_scale(dev, U.ptr, n, b, S.ptr, 0, nullptr, batch, sW, b);
 }
 
@@ -113,8 +119,11 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
     dev.download(res, hres.data());
     worst = *std::max_element(hres.begin(), hres.end());
     if (worst <= prm.tol || it >= prm.max_iter) break;
-    Tensor Jz, Sz;
-    svd_ts(dev, Z, nc, n, b, X, Sz, Jz);
+    // fresh buffer: X may alias the previous call's V, which the backward
+    // tape keeps
+    Tensor Xn, Jz, Sz;
+    svd_ts(dev, Z, nc, n, b, Xn, Sz, Jz);
+    X = Xn;
   }
   sign_fix(dev, U.ptr, V.ptr, n, b, nc, sX, sX);
   if (keep.numel() < nc) keep = dev.empty({nc});
