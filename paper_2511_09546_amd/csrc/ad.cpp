@@ -1,0 +1,105 @@
+// Reverse-mode tape over the device contraction engine.
+#include "ad.hpp"
+
+namespace ipeps {
+
+Tensor& Tape::grad(const Var& x) {
+  if (!x->g.ptr) x->g = dev.zeros(x->v.shape);
+  return x->g;
+}
+
+static void parse3(const std::string& spec, std::string& a, std::string& b,
+                   std::string& o) {
+  const auto c = spec.find(','), ar = spec.find("->");
+  a = spec.substr(0, c);
+  b = spec.substr(c + 1, ar - c - 1);
+  o = spec.substr(ar + 2);
+}
+
+Var Tape::einsum(const std::string& spec, const Var& a, const Var& b) {
+  auto out = std::make_shared<Node>();
+  out->v = ipeps::einsum(dev, spec, a->v, b->v);
+  out->req = rec && (a->req || b->req);
+  if (out->req) {
+    std::string la, lb, lo;
+    parse3(spec, la, lb, lo);
+    push([this, a, b, out, la, lb, lo]() {
+      if (!has_grad(out)) return;
+      if (a->req)
+        einsum_into(dev, lo + "," + lb + "->" + la, out->g, b->v, grad(a),
+                    1.0, 1.0);
+      if (b->req)
+        einsum_into(dev, la + "," + lo + "->" + lb, a->v, out->g, grad(b),
+                    1.0, 1.0);
+    });
+  }
+  return out;
+}
+
+Var Tape::view(const Var& x, std::vector<int64_t> shape) {
+  auto out = std::make_shared<Node>();
+  out->v = x->v.view(std::move(shape));
+  out->req = x->req;
+  if (out->req)
+    push([this, x, out]() {
+      if (!has_grad(out)) return;
+      Tensor& gx = grad(x);
+      axpby(dev, gx.numel(), 1.0, out->g.ptr, 1.0, gx.ptr);
+    });
+  return out;
+}
+
+Var Tape::slice0(const Var& x, int64_t i) {
+  auto out = std::make_shared<Node>();
+  out->v = x->v.slice0(i);
+  out->req = x->req;
+  if (out->req) {
+    const int64_t off = out->v.ptr - x->v.ptr;
+    push([this, x, out, off]() {
+      if (!has_grad(out)) return;
+      Tensor& gx = grad(x);
+      axpby(dev, out->v.numel(), 1.0, out->g.ptr, 1.0, gx.ptr + off);
+    });
+  }
+  return out;
+}
+
+Var Tape::permute(const Var& x, const std::vector<int>& perm) {
+  auto out = std::make_shared<Node>();
+  out->v = permuted(dev, x->v, perm);
+  out->req = x->req;
+  if (out->req) {
+    std::vector<int> inv(perm.size());
+    for (size_t i = 0; i < perm.size(); ++i) inv[perm[i]] = (int)i;
+    push([this, x, out, inv]() {
+      if (!has_grad(out)) return;
+      ipeps::permute(dev, out->g, inv, grad(x), 1.0, 1.0);
+    });
+  }
+  return out;
+}
+
+Var Tape::normalize(const Var& x) {
+  auto out = std::make_shared<Node>();
+  const int64_t len = x->v.numel();
+  Tensor nrm = dev.empty({1});
+  nrm2(dev, x->v.ptr, len, nrm.ptr);
+  out->v = dev.empty(x->v.shape);
+  axpby(dev, len, 1.0, x->v.ptr, 0.0, out->v.ptr);
+  scale_dev(dev, out->v.ptr, len, nrm.ptr, true);
+  out->req = rec && x->req;
+  if (out->req)
+    push([this, x, out, nrm, len]() {
+      if (!has_grad(out)) return;
+      normalize_backward(dev, len, out->v.ptr, out->g.ptr, nrm.ptr,
+                         grad(x).ptr);
+    });
+  return out;
+}
+
+void Tape::backward() {
+  for (auto it = ops_.rbegin(); it != ops_.rend(); ++it) (*it)();
+  ops_.clear();
+}
+
+}  // namespace ipeps

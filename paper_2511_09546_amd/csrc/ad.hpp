@@ -1,0 +1,63 @@
+// Reverse-mode differentiation over the device contraction engine.
+//
+// A Var holds a device tensor and, once a cotangent flows into it, its
+// gradient buffer.  A Tape records one backward closure per differentiable
+// operation when recording is on; backward() runs them in reverse order.
+// With recording off the same forward code runs without keeping anything.
+#pragma once
+
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+
+namespace ipeps {
+
+struct Node {
+  Tensor v;
+  Tensor g;          // empty until a cotangent arrives
+  bool req = false;  // needs a gradient
+};
+using Var = std::shared_ptr<Node>;
+
+class Tape {
+ public:
+  Tape(Device& d, bool record) : dev(d), rec(record) {}
+  Device& dev;
+  bool rec;
+
+  Var leaf(const Tensor& t, bool req) {
+    auto n = std::make_shared<Node>();
+    n->v = t;
+    n->req = req && rec;
+    return n;
+  }
+  // gradient buffer of x (zero-initialised on first use)
+  Tensor& grad(const Var& x);
+  bool has_grad(const Var& x) const { return x->g.ptr != nullptr; }
+
+  Var einsum(const std::string& spec, const Var& a, const Var& b);
+  Var view(const Var& x, std::vector<int64_t> shape);
+  // i-th sub-tensor along the leading dimension (shares memory)
+  Var slice0(const Var& x, int64_t i);
+  Var permute(const Var& x, const std::vector<int>& perm);
+  // y = x / ||x||_F
+  Var normalize(const Var& x);
+
+  void push(std::function<void()> f) {
+    if (rec) ops_.push_back(std::move(f));
+  }
+  void backward();
+  size_t size() const { return ops_.size(); }
+
+ private:
+  std::vector<std::function<void()>> ops_;
+};
+
+// x_bar += (y_bar - y <y, y_bar>) / n  with n = ||x|| (device scalar)
+void normalize_backward(Device& dev, int64_t len, const double* y,
+                        const double* ybar, const double* nrm, double* xbar);
+
+}  // namespace ipeps

@@ -158,7 +158,7 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
   int st = guarded([&]() {
     while (it < max_iter) {
       Env next;
-      ctm_step(cx, cx.env, next, nullptr);
+      ctm_step(cx, cx.env, next);
       cx.env = next;
       ++it;
       dl = corner_spectra_change(cx, cx.env);
@@ -218,7 +218,7 @@ int ipeps_energy_grad(ipeps_ctx* c, int n_terms, const ipeps_term* H,
     if (grad) {
       e = energy_grad(cx, terms, grad);
     } else {
-      e = energy(cx, cx.env, terms, nullptr, nullptr);
+      e = energy(cx, cx.env, terms);
     }
     return IPEPS_OK;
   });

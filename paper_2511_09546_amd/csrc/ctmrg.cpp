@@ -1,10 +1,13 @@
 // CTMRG on the device: double layer, trace-boundary start, one simultaneous
 // four-corner iteration with half-system SVD projectors, normalisation and
 // the corner-spectrum convergence measure (Sec. III A: the environment of the
-// energy network, Eq. (7)).
+// energy network, Eq. (7)).  The iteration is written once, on the
+// differentiation tape: with recording off it is the plain forward move,
+// with recording on it is the step that the backward pass unrolls.
 #include <algorithm>
 #include <cmath>
 
+#include "ad.hpp"
 #include "ipeps_impl.hpp"
 
 namespace ipeps {
@@ -31,12 +34,8 @@ Tensor Context::av(int s, int c) const {
   return t;
 }
 
-static Tensor site_tensor(const Context& cx, const Tensor& A, int s) {
-  Tensor t = A;
-  const int64_t sz = (int64_t)cx.d * cx.D * cx.D * cx.D * cx.D;
-  t.ptr = A.ptr + s * sz;
-  t.shape = {cx.d, cx.D, cx.D, cx.D, cx.D};
-  return t;
+static std::vector<int> rot_perm(int c) {
+  return {c % 4, (c + 1) % 4, (c + 2) % 4, (c + 3) % 4};
 }
 
 // a = sum_p A[p,l,u,r,d] A[p,l',u',r',d'], legs fused (k k') -> k*D + k',
@@ -44,24 +43,71 @@ static Tensor site_tensor(const Context& cx, const Tensor& A, int s) {
 void build_double_layer(Context& cx) {
   const int ns = cx.nsite(), D2 = cx.D2, D = cx.D;
   const int64_t a4 = (int64_t)D2 * D2 * D2 * D2;
-  if (cx.a_rot.numel() != ns * 4 * a4) cx.a_rot = cx.dev.empty({ns, 4, D2, D2, D2, D2});
+  if (cx.a_rot.numel() != ns * 4 * a4)
+    cx.a_rot = cx.dev.empty({ns, 4, D2, D2, D2, D2});
   for (int s = 0; s < ns; ++s) {
-    Tensor As = site_tensor(cx, cx.A, s);
-    Tensor a8 = einsum(cx.dev, "pabce,pfghi->afbgchei", As, As);
-    Tensor a = a8.view({D2, D2, D2, D2});
-    (void)D;
+    Tensor As = cx.A;
+    As.ptr = cx.A.ptr + (int64_t)s * cx.d * D * D * D * D;
+    As.shape = {cx.d, D, D, D, D};
+    Tensor a = einsum(cx.dev, "pabce,pfghi->afbgchei", As, As)
+                   .view({D2, D2, D2, D2});
     for (int c = 0; c < 4; ++c) {
       Tensor dst = cx.av(s, c);
-      permute(cx.dev, a, {c % 4, (c + 1) % 4, (c + 2) % 4, (c + 3) % 4}, dst);
+      permute(cx.dev, a, rot_perm(c), dst);
     }
   }
 }
 
-static Tensor trace_vector(Context& cx) {
-  std::vector<double> h((size_t)cx.D2, 0.0);
-  for (int k = 0; k < cx.D; ++k) h[(size_t)k * cx.D + k] = 1.0;
-  Tensor e = cx.dev.empty({cx.D2});
-  cx.dev.upload(e, h.data());
+std::vector<Var> arot_leaves(Tape& tp, Context& cx) {
+  std::vector<Var> r(4 * cx.nsite());
+  for (int s = 0; s < cx.nsite(); ++s)
+    for (int c = 0; c < 4; ++c) r[s * 4 + c] = tp.leaf(cx.av(s, c), false);
+  return r;
+}
+
+std::vector<Var> arot_from_sites(Tape& tp, Context& cx,
+                                 const std::vector<Var>& As) {
+  const int D2 = cx.D2;
+  std::vector<Var> r(4 * cx.nsite());
+  for (int s = 0; s < cx.nsite(); ++s) {
+    Var a = tp.view(tp.einsum("pabce,pfghi->afbgchei", As[s], As[s]),
+                    {D2, D2, D2, D2});
+    r[s * 4] = a;
+    for (int c = 1; c < 4; ++c) r[s * 4 + c] = tp.permute(a, rot_perm(c));
+  }
+  return r;
+}
+
+std::vector<Var> site_leaves(Tape& tp, Context& cx, bool req) {
+  Var A = tp.leaf(cx.A, req);
+  std::vector<Var> r(cx.nsite());
+  for (int s = 0; s < cx.nsite(); ++s) r[s] = tp.slice0(A, s);
+  return r;
+}
+
+VEnv venv_leaves(Tape& tp, Context& cx, const Env& e) {
+  VEnv v;
+  const int ns = cx.nsite();
+  v.C.resize(4 * ns);
+  v.T.resize(4 * ns);
+  for (int c = 0; c < 4; ++c)
+    for (int s = 0; s < ns; ++s) {
+      v.C[c * ns + s] = tp.leaf(cx.Cv(e, c, s), false);
+      v.T[c * ns + s] = tp.leaf(cx.Tv(e, c, s), false);
+    }
+  return v;
+}
+
+Env env_pack(Context& cx, const VEnv& v) {
+  const int ns = cx.nsite(), chi = cx.chi, D2 = cx.D2;
+  Env e;
+  e.C = cx.dev.empty({4, ns, chi, chi});
+  e.T = cx.dev.empty({4, ns, chi, D2, chi});
+  const int64_t cs = (int64_t)chi * chi, ts = cs * D2;
+  for (int i = 0; i < 4 * ns; ++i) {
+    axpby(cx.dev, cs, 1.0, v.C[i]->v.ptr, 0.0, e.C.ptr + i * cs);
+    axpby(cx.dev, ts, 1.0, v.T[i]->v.ptr, 0.0, e.T.ptr + i * ts);
+  }
   return e;
 }
 
@@ -72,7 +118,10 @@ void init_env(Context& cx) {
   Env e;
   e.C = cx.dev.zeros({4, ns, chi, chi});
   e.T = cx.dev.zeros({4, ns, chi, D2, chi});
-  Tensor tv = trace_vector(cx);
+  std::vector<double> h((size_t)D2, 0.0);
+  for (int k = 0; k < cx.D; ++k) h[(size_t)k * cx.D + k] = 1.0;
+  Tensor tv = cx.dev.empty({D2});
+  cx.dev.upload(tv, h.data());
   for (int s = 0; s < ns; ++s)
     for (int c = 0; c < 4; ++c) {
       Tensor ac = cx.av(cx.lat.shift(s, INIT_CORNER_SITE[c][0],
@@ -92,120 +141,67 @@ void init_env(Context& cx) {
   cx.have_warm = false;
 }
 
-void ctm_step(Context& cx, const Env& in, Env& out, StepTape* tape) {
-  Device& dev = cx.dev;
+VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
+                 const std::vector<Var>& arot) {
   const int ns = cx.nsite(), chi = cx.chi, D2 = cx.D2, nc = cx.ncut();
-  const int64_t n = cx.n, nn = n * n;
+  const int64_t n = cx.n;
   const Lattice& L = cx.lat;
+  auto C = [&](int c, int s) { return in.C[c * ns + s]; };
+  auto T = [&](int c, int s) { return in.T[c * ns + s]; };
+  auto a = [&](int s, int c) { return arot[s * 4 + c]; };
 
   // enlarged corners Q_c(s)[(m f), (k b)]
-  Tensor Q = dev.empty({4, ns, n, n});
+  std::vector<Var> Q(4 * ns);
   for (int c = 0; c < 4; ++c)
     for (int s = 0; s < ns; ++s) {
-      Tensor X1 = einsum(dev, "mgi,ij->mgj", cx.Tv(in, (c + 3) % 4, s),
-                         cx.Cv(in, c, s));
-      Tensor X2 = einsum(dev, "mgj,jek->mgek", X1, cx.Tv(in, c, s));
-      Tensor Qcs = Q;
-      Qcs.ptr = Q.ptr + ((int64_t)c * ns + s) * nn;
-      Qcs.shape = {chi, D2, chi, D2};
-      einsum_into(dev, "mgek,gebf->mfkb", X2, cx.av(s, c), Qcs);
+      Var X1 = tp.einsum("mgi,ij->mgj", T((c + 3) % 4, s), C(c, s));
+      Var X2 = tp.einsum("mgj,jek->mgek", X1, T(c, s));
+      Q[c * ns + s] = tp.view(tp.einsum("mgek,gebf->mfkb", X2, a(s, c)),
+                              {n, n});
     }
-  auto Qp = [&](int c, int s) { return Q.ptr + ((int64_t)c * ns + s) * nn; };
-
   // projectors of every cut: cut index c*ns + p (plaquette p, cut c between
   // its corners c and c+1)
-  CutBatch cb;
-  cb.ncut = nc;
-  cb.n = n;
-  cb.b = cx.b;
-  cb.chi = chi;
-  cb.Qa.resize(nc);
-  cb.Qb.resize(nc);
+  std::vector<Var> Qa(nc), Qb(nc);
   for (int c = 0; c < 4; ++c)
     for (int p = 0; p < ns; ++p) {
       const int sa = L.shift(p, PLAQ_OFFSET[c][0], PLAQ_OFFSET[c][1]);
       const int sb = L.shift(p, PLAQ_OFFSET[(c + 1) % 4][0],
                              PLAQ_OFFSET[(c + 1) % 4][1]);
-      cb.Qa[c * ns + p] = Qp(c, sa);
-      cb.Qb[c * ns + p] = Qp((c + 1) % 4, sb);
+      Qa[c * ns + p] = Q[c * ns + sa];
+      Qb[c * ns + p] = Q[((c + 1) % 4) * ns + sb];
     }
-  Tensor U, S, V, keep;
-  projector_svd(dev, cb, cx.Xwarm, cx.have_warm, U, S, V, keep, cx.svd,
-                &cx.stats);
-  cx.have_warm = true;
-  const int b = cx.b;
-  const int64_t sUV = n * b;
-  // P = Qb V_k S_k^-1/2 and Pt^T = Qa^T U_k S_k^-1/2, zero beyond k
-  Tensor P = dev.empty({nc, n, chi});
-  Tensor PtT = dev.empty({nc, n, chi});
-  for (int i = 0; i < nc; ++i) {
-    gemm(dev, false, false, n, chi, n, 1.0, cb.Qb[i], n, 0, V.ptr + i * sUV,
-         b, 0, 0.0, P.ptr + i * n * chi, chi, 0);
-    gemm(dev, true, false, n, chi, n, 1.0, cb.Qa[i], n, 0, U.ptr + i * sUV, b,
-         0, 0.0, PtT.ptr + i * n * chi, chi, 0);
-  }
-  col_scale(dev, P.ptr, n, chi, S.ptr, 1, (const int*)keep.ptr, nc, n * chi,
-            b);
-  col_scale(dev, PtT.ptr, n, chi, S.ptr, 1, (const int*)keep.ptr, nc,
-            n * chi, b);
-  auto Pv = [&](const Tensor& T, int cut) {
-    Tensor t = T;
-    t.ptr = T.ptr + (int64_t)cut * n * chi;
-    t.shape = {n, chi};
-    return t;
-  };
+  auto proj = projector_op(tp, cx, Qa, Qb);
+  const std::vector<Var>& P = proj.first;
+  const std::vector<Var>& PtT = proj.second;
 
-  Env raw;
-  raw.C = dev.empty({4, ns, chi, chi});
-  raw.T = dev.empty({4, ns, chi, D2, chi});
+  VEnv out;
+  out.C.resize(4 * ns);
+  out.T.resize(4 * ns);
   for (int c = 0; c < 4; ++c)
     for (int s = 0; s < ns; ++s) {
       const int p = L.shift(s, -PLAQ_OFFSET[c][0], -PLAQ_OFFSET[c][1]);
       const int cutL = ((c + 3) % 4) * ns + p, cutR = c * ns + p;
-      Tensor Qcs = Q;
-      Qcs.ptr = Qp(c, s);
-      Qcs.shape = {n, n};
-      Tensor Y = einsum(dev, "rx,rq->xq", Pv(PtT, cutL), Qcs);
-      Tensor Cd = cx.Cv(raw, c, L.shift(s, CORNER_MOVE[c][0],
-                                        CORNER_MOVE[c][1]));
-      einsum_into(dev, "xq,qy->xy", Y, Pv(P, cutR), Cd);
+      Var Y = tp.einsum("rx,rq->xq", PtT[cutL], Q[c * ns + s]);
+      Var Cn = tp.einsum("xq,qy->xy", Y, P[cutR]);
+      out.C[c * ns + L.shift(s, CORNER_MOVE[c][0], CORNER_MOVE[c][1])] =
+          tp.normalize(Cn);
       const int pccw = L.shift(s, -PLAQ_OFFSET[(c + 1) % 4][0],
                                -PLAQ_OFFSET[(c + 1) % 4][1]);
-      Tensor Pt3 = Pv(PtT, c * ns + pccw).view({chi, D2, chi});
-      Tensor Y1 = einsum(dev, "jgx,jek->xgek", Pt3, cx.Tv(in, c, s));
-      Tensor Y2 = einsum(dev, "xgek,gebf->xkbf", Y1, cx.av(s, c));
-      Tensor P3 = Pv(P, cutR).view({chi, D2, chi});
-      Tensor Td = cx.Tv(raw, c, L.shift(s, EDGE_MOVE[c][0], EDGE_MOVE[c][1]));
-      einsum_into(dev, "xkbf,kby->xfy", Y2, P3, Td);
+      Var Pt3 = tp.view(PtT[c * ns + pccw], {chi, D2, chi});
+      Var Y1 = tp.einsum("jgx,jek->xgek", Pt3, T(c, s));
+      Var Y2 = tp.einsum("xgek,gebf->xkbf", Y1, a(s, c));
+      Var P3 = tp.view(P[cutR], {chi, D2, chi});
+      Var Tn = tp.einsum("xkbf,kby->xfy", Y2, P3);
+      out.T[c * ns + L.shift(s, EDGE_MOVE[c][0], EDGE_MOVE[c][1])] =
+          tp.normalize(Tn);
     }
-  // normalise every tensor by its Frobenius norm
-  Tensor norms = dev.empty({2, 4 * ns});
-  out.C = dev.empty({4, ns, chi, chi});
-  out.T = dev.empty({4, ns, chi, D2, chi});
-  const int64_t cs = (int64_t)chi * chi, ts = (int64_t)chi * D2 * chi;
-  for (int i = 0; i < 4 * ns; ++i) {
-    nrm2(dev, raw.C.ptr + i * cs, cs, norms.ptr + i);
-    nrm2(dev, raw.T.ptr + i * ts, ts, norms.ptr + 4 * ns + i);
-  }
-  axpby(dev, raw.C.numel(), 1.0, raw.C.ptr, 0.0, out.C.ptr);
-  axpby(dev, raw.T.numel(), 1.0, raw.T.ptr, 0.0, out.T.ptr);
-  for (int i = 0; i < 4 * ns; ++i) {
-    scale_dev(dev, out.C.ptr + i * cs, cs, norms.ptr + i, true);
-    scale_dev(dev, out.T.ptr + i * ts, ts, norms.ptr + 4 * ns + i, true);
-  }
-  if (tape) {
-    tape->in = in;
-    tape->Q = Q;
-    tape->U = U;
-    tape->S = S;
-    tape->V = V;
-    tape->keep = keep;
-    tape->P = P;
-    tape->PtT = PtT;
-    tape->Craw = raw.C;
-    tape->Traw = raw.T;
-    tape->Cnorm = norms;
-  }
+  return out;
+}
+
+void ctm_step(Context& cx, const Env& in, Env& out) {
+  Tape tp(cx.dev, false);
+  VEnv v = ctm_step_ad(tp, cx, venv_leaves(tp, cx, in), arot_leaves(tp, cx));
+  out = env_pack(cx, v);
 }
 
 // Singular values of every corner (two-pass tall-skinny SVD), sorted.

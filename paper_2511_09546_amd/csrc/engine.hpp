@@ -183,3 +183,20 @@ namespace ipeps {
 void null_threshold(Device& dev, double* S, int b, double rel, int batch,
                     int64_t sS);
 }  // namespace ipeps
+
+namespace ipeps {
+void coldot(Device& dev, const double* X, const double* Y, int64_t n, int m,
+            double* out);
+void proj_weights(Device& dev, const double* S, const int* keep, int chi,
+                  double* w);
+void proj_sbar(Device& dev, const double* S, const int* keep, int chi,
+               const double* wb1, const double* wb2, double* sbar);
+void svd_gkk(Device& dev, const double* Au, const double* Av, const double* S,
+             const double* sbar, const int* keep, int chi, double* G);
+void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep);
+void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
+           const double* den, double* x, double* r, double* p,
+           const double* Ap);
+void col_axpby(Device& dev, int64_t n, int m, double a, const double* s,
+               const double* x, double b, double* y);
+}  // namespace ipeps

@@ -4,6 +4,7 @@
 #include <array>
 #include <vector>
 
+#include "ad.hpp"
 #include "engine.hpp"
 
 namespace ipeps {
@@ -27,6 +28,8 @@ struct SvdStats {
   long iters = 0;
   long calls = 0;
   double worst_residual = 0.0;
+  long cg_iters = 0;    // complement solves of the backward pass
+  long cg_solves = 0;
 };
 
 void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
@@ -69,14 +72,10 @@ struct Env {
   Tensor C, T;
 };
 
-// Everything one CTMRG iteration records for the backward pass.
-struct StepTape {
-  Env in;                       // environment entering the iteration
-  Tensor Q;                     // [4][nsite][n][n] enlarged corners
-  Tensor U, S, V, keep;         // [ncut][n][b], [ncut][b], ..., ncut ints
-  Tensor P, PtT;                // [ncut][n][chi] projectors (Pt transposed)
-  Tensor Craw, Traw;            // unnormalised new corners / edges
-  Tensor Cnorm, Tnorm;          // their norms [4*nsite]
+// Environment on the differentiation tape: one Var per tensor, index
+// c * nsite + s.
+struct VEnv {
+  std::vector<Var> C, T;
 };
 
 struct Context {
@@ -111,11 +110,24 @@ struct Context {
 // ctmrg.cpp
 void build_double_layer(Context& cx);
 void init_env(Context& cx);
-// One simultaneous CTMRG iteration: env_out from env_in; records into tape
-// when tape != nullptr.
-void ctm_step(Context& cx, const Env& in, Env& out, StepTape* tape);
+std::vector<Var> arot_leaves(Tape& tp, Context& cx);
+std::vector<Var> arot_from_sites(Tape& tp, Context& cx,
+                                 const std::vector<Var>& As);
+std::vector<Var> site_leaves(Tape& tp, Context& cx, bool req);
+VEnv venv_leaves(Tape& tp, Context& cx, const Env& e);
+Env env_pack(Context& cx, const VEnv& v);
+// One simultaneous CTMRG iteration on the tape.
+VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
+                 const std::vector<Var>& arot);
+// Plain forward iteration (nothing recorded).
+void ctm_step(Context& cx, const Env& in, Env& out);
 double corner_spectra_change(Context& cx, const Env& e);
 void corner_spectra(Context& cx, const Env& e, Tensor& out);
+
+// projector.cpp: differentiable projectors of a batch of cuts
+std::pair<std::vector<Var>, std::vector<Var>> projector_op(
+    Tape& tp, Context& cx, const std::vector<Var>& Qa,
+    const std::vector<Var>& Qb);
 
 // observables.cpp
 struct TermSpec {
@@ -123,8 +135,12 @@ struct TermSpec {
   double coef;
   std::vector<double> mat;
 };
-double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms,
-              Tensor* gA, Env* gEnv);
+// Energy per site on the tape; with recording on, the cotangent of every
+// reduced density matrix is seeded (d e / d rho), ready for backward().
+double energy_ad(Tape& tp, Context& cx, const VEnv& e,
+                 const std::vector<Var>& As, const std::vector<Var>& arot,
+                 const std::vector<TermSpec>& terms);
+double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms);
 
 // metric.cpp
 int precondition(Context& cx, const double* g_host, double delta,

@@ -946,3 +946,206 @@ void null_threshold(Device& dev, double* S, int b, double rel, int batch,
 }
 
 }  // namespace ipeps
+
+#include "ad.hpp"
+
+namespace ipeps {
+
+__global__ void normalize_backward_kernel(int64_t n, const double* y,
+                                          const double* ybar,
+                                          const double* nrm, const double* d,
+                                          double* xbar) {
+  const double inv = 1.0 / nrm[0], dd = d[0];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    xbar[i] += (ybar[i] - y[i] * dd) * inv;
+}
+
+void normalize_backward(Device& dev, int64_t len, const double* y,
+                        const double* ybar, const double* nrm, double* xbar) {
+  Tensor d = dev.empty({1});
+  dot(dev, y, ybar, len, d.ptr);
+  hipLaunchKernelGGL(normalize_backward_kernel, dim3(grid_for(len, 256)),
+                     dim3(256), 0, dev.stream, len, y, ybar, nrm, d.ptr, xbar);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps
+
+namespace ipeps {
+
+// ---------------------------------------------- projector backward helpers
+// out[j] = sum_i X[i*m + j] * Y[i*m + j]  (one wave per column)
+__global__ void coldot_kernel(const double* __restrict__ X,
+                              const double* __restrict__ Y, int64_t n, int m,
+                              double* __restrict__ out) {
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= m) return;
+  double v = 0.0;
+  for (int64_t i = lane; i < n; i += 64) v += X[i * m + j] * Y[i * m + j];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if (lane == 0) out[j] = v;
+}
+
+void coldot(Device& dev, const double* X, const double* Y, int64_t n, int m,
+            double* out) {
+  hipLaunchKernelGGL(coldot_kernel, dim3((m + 3) / 4), dim3(256), 0,
+                     dev.stream, X, Y, n, m, out);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// w[j] = s_j^-1/2 for j < keep (and s_j > 0), else 0; j < chi.
+__global__ void proj_weights_kernel(const double* S, const int* keep, int chi,
+                                    double* w) {
+  const int j = threadIdx.x + blockIdx.x * blockDim.x;
+  if (j >= chi) return;
+  const double s = S[j];
+  w[j] = (j < keep[0] && s > 0.0) ? 1.0 / sqrt(s) : 0.0;
+}
+
+void proj_weights(Device& dev, const double* S, const int* keep, int chi,
+                  double* w) {
+  hipLaunchKernelGGL(proj_weights_kernel, dim3((chi + 127) / 128), dim3(128),
+                     0, dev.stream, S, keep, chi, w);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// sbar[j] = -1/2 s_j^-3/2 (wbar1[j] + wbar2[j]) for j < keep, else 0
+__global__ void proj_sbar_kernel(const double* S, const int* keep, int chi,
+                                 const double* wb1, const double* wb2,
+                                 double* sbar) {
+  const int j = threadIdx.x + blockIdx.x * blockDim.x;
+  if (j >= chi) return;
+  const double s = S[j];
+  sbar[j] = (j < keep[0] && s > 0.0)
+                ? -0.5 * (wb1[j] + wb2[j]) / (s * sqrt(s))
+                : 0.0;
+}
+
+void proj_sbar(Device& dev, const double* S, const int* keep, int chi,
+               const double* wb1, const double* wb2, double* sbar) {
+  hipLaunchKernelGGL(proj_sbar_kernel, dim3((chi + 127) / 128), dim3(128), 0,
+                     dev.stream, S, keep, chi, wb1, wb2, sbar);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Kept block of the SVD adjoint (chi x chi, zero outside i, j < keep):
+// G_ij = F_ij (Au_ij - Au_ji) s_j + s_i F_ij (Av_ij - Av_ji) + d_ij sbar_i,
+// F_ij = x/(x^2 + eta^2), x = s_j^2 - s_i^2, eta = 1e-12 s_0^2, F_ii = 0.
+__global__ void svd_gkk_kernel(const double* Au, const double* Av,
+                               const double* S, const double* sbar,
+                               const int* keep, int chi, double* G) {
+  const int k = keep[0];
+  const double eta = 1e-12 * S[0] * S[0];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < chi * chi;
+       e += gridDim.x * blockDim.x) {
+    const int i = e / chi, j = e % chi;
+    double g = 0.0;
+    if (i < k && j < k) {
+      if (i == j) {
+        g = sbar[i];
+      } else {
+        const double si = S[i], sj = S[j];
+        const double x = sj * sj - si * si;
+        const double F = x / (x * x + eta * eta);
+        g = F * (Au[i * chi + j] - Au[j * chi + i]) * sj +
+            si * F * (Av[i * chi + j] - Av[j * chi + i]);
+      }
+    }
+    G[e] = g;
+  }
+}
+
+void svd_gkk(Device& dev, const double* Au, const double* Av, const double* S,
+             const double* sbar, const int* keep, int chi, double* G) {
+  hipLaunchKernelGGL(svd_gkk_kernel, dim3(grid_for((int64_t)chi * chi, 256)),
+                     dim3(256), 0, dev.stream, Au, Av, S, sbar, keep, chi, G);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// X (n x m) columns j >= keep set to zero
+__global__ void mask_cols_kernel(double* X, int64_t n, int m,
+                                 const int* keep) {
+  const int k = keep[0];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x)
+    if ((int)(e % m) >= k) X[e] = 0.0;
+}
+
+void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep) {
+  hipLaunchKernelGGL(mask_cols_kernel, dim3(grid_for(n * m, 256)), dim3(256),
+                     0, dev.stream, X, n, m, keep);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Column-wise CG on blocks of `rows` x m (per-column scalars):
+//   mode 0: alpha_j = rr_j / pAp_j (0 when pAp_j <= 0 or rr_j == 0);
+//           x += alpha p; r -= alpha Ap
+//   mode 1: p = r + (rrn_j / rr_j) p  (beta 0 when rr_j == 0)
+__global__ void colcg_kernel(int mode, int64_t rows, int m, const double* rr,
+                             const double* den, double* x, double* r,
+                             double* p, const double* Ap) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+       e < rows * m; e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % m);
+    if (mode == 0) {
+      const double a = (den[j] > 0.0 && rr[j] > 0.0) ? rr[j] / den[j] : 0.0;
+      x[e] += a * p[e];
+      r[e] -= a * Ap[e];
+    } else {
+      const double bta = rr[j] > 0.0 ? den[j] / rr[j] : 0.0;
+      p[e] = r[e] + bta * p[e];
+    }
+  }
+}
+
+void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
+           const double* den, double* x, double* r, double* p,
+           const double* Ap) {
+  hipLaunchKernelGGL(colcg_kernel, dim3(grid_for(rows * m, 256)), dim3(256),
+                     0, dev.stream, mode, rows, m, rr, den, x, r, p, Ap);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// y[i][j] = a * s_j * x[i][j] + b * y[i][j]   (column-scaled axpby)
+__global__ void col_axpby_kernel(int64_t n, int m, double a, const double* s,
+                                 const double* x, double b, double* y) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double sj = s ? s[e % m] : 1.0;
+    double v = a * sj * x[e];
+    if (b != 0.0) v += b * y[e];
+    y[e] = v;
+  }
+}
+
+void col_axpby(Device& dev, int64_t n, int m, double a, const double* s,
+               const double* x, double b, double* y) {
+  hipLaunchKernelGGL(col_axpby_kernel, dim3(grid_for(n * m, 256)), dim3(256),
+                     0, dev.stream, n, m, a, s, x, b, y);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps
+
+namespace ipeps {
+
+// dst[r*ldd + c] = src[r*lds + c], rows x cols
+__global__ void copy2d_kernel(const double* src, int64_t lds, double* dst,
+                              int64_t ldd, int64_t rows, int64_t cols) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+       e < rows * cols; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    dst[r * ldd + c] = src[r * lds + c];
+  }
+}
+
+void copy2d(Device& dev, const double* src, int64_t lds, double* dst,
+            int64_t ldd, int64_t rows, int64_t cols) {
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(rows * cols, 256)),
+                     dim3(256), 0, dev.stream, src, lds, dst, ldd, rows, cols);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps

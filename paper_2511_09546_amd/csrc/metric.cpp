@@ -13,7 +13,6 @@
 #include <cmath>
 
 #include "ipeps_impl.hpp"
-#include "observables.hpp"
 
 namespace ipeps {
 

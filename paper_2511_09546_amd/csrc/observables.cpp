@@ -5,165 +5,140 @@
 //   (1,0), (0,1): 2x1 / 1x2 block  C1 T1 T1 C2 / T4 A A T2 / C4 T3 T3 C3
 //   (1,1), (1,-1): 2x2 plaquette of enlarged corners, diagonal sites open
 //   on-site: the 3x3 block around the site.
+// Written on the differentiation tape so that the same contractions serve
+// the energy and its backward pass.
 #include <cmath>
 
+#include "ad.hpp"
 #include "ipeps_impl.hpp"
-#include "observables.hpp"
 
 namespace ipeps {
 
-Tensor site_view(const Context& cx, const Tensor& A, int s) {
-  Tensor t = A;
-  const int64_t sz = (int64_t)cx.d * cx.D * cx.D * cx.D * cx.D;
-  t.ptr = A.ptr + s * sz;
-  t.shape = {cx.d, cx.D, cx.D, cx.D, cx.D};
-  return t;
-}
+namespace {
 
-// ao[s, t, (l l'), (u u'), (r r'), (d d')]
-Tensor open_double_layer(Context& cx, int s) {
-  const int D2 = cx.D2, d = cx.d;
-  Tensor As = site_view(cx, cx.A, s);
-  Tensor a10 = einsum(cx.dev, "sabce,tfghi->stafbgchei", As, As);
-  return a10.view({d, d, D2, D2, D2, D2});
-}
-
-Tensor rotate_open(Context& cx, const Tensor& ao, int c) {
-  if (c == 0) return ao;
-  return permuted(cx.dev, ao,
-                  {0, 1, 2 + c % 4, 2 + (c + 1) % 4, 2 + (c + 2) % 4,
-                   2 + (c + 3) % 4});
-}
-
-Tensor rdm_h(Context& cx, const Env& e, int s1, int s2, const Tensor& ao1,
-             const Tensor& ao2) {
-  Device& dev = cx.dev;
-  Tensor L1 = einsum(dev, "ij,mgi->jmg", cx.Cv(e, 0, s1), cx.Tv(e, 3, s1));
-  Tensor L2 = einsum(dev, "jmg,qm->jgq", L1, cx.Cv(e, 3, s1));
-  Tensor L3 = einsum(dev, "jgq,jek->gqek", L2, cx.Tv(e, 0, s1));
-  Tensor L4 = einsum(dev, "gqek,wzq->gekwz", L3, cx.Tv(e, 2, s1));
-  Tensor HL = einsum(dev, "gekwz,stgebz->kwstb", L4, ao1);
-  Tensor R1 = einsum(dev, "ji,ibm->jbm", cx.Cv(e, 1, s2), cx.Tv(e, 1, s2));
-  Tensor R2 = einsum(dev, "jbm,mq->jbq", R1, cx.Cv(e, 2, s2));
-  Tensor R3 = einsum(dev, "kej,jbq->kebq", cx.Tv(e, 0, s2), R2);
-  Tensor R4 = einsum(dev, "kebq,qzw->kebzw", R3, cx.Tv(e, 2, s2));
-  Tensor HR = einsum(dev, "kebzw,stvebz->kwstv", R4, ao2);
-  return einsum(dev, "kwstb,kwuvb->sutv", HL, HR);
-}
-
-Tensor rdm_v(Context& cx, const Env& e, int s1, int s2, const Tensor& ao1,
-             const Tensor& ao2) {
-  Device& dev = cx.dev;
-  Tensor V1 = einsum(dev, "ij,jek->iek", cx.Cv(e, 0, s1), cx.Tv(e, 0, s1));
-  Tensor V2 = einsum(dev, "iek,kp->iep", V1, cx.Cv(e, 1, s1));
-  Tensor V3 = einsum(dev, "iep,mgi->epmg", V2, cx.Tv(e, 3, s1));
-  Tensor V4 = einsum(dev, "epmg,pbn->emgbn", V3, cx.Tv(e, 1, s1));
-  Tensor HT = einsum(dev, "emgbn,stgebz->mnstz", V4, ao1);
-  Tensor W1 = einsum(dev, "qgm,wq->gmw", cx.Tv(e, 3, s2), cx.Cv(e, 3, s2));
-  Tensor W2 = einsum(dev, "gmw,vyw->gmvy", W1, cx.Tv(e, 2, s2));
-  Tensor W3 = einsum(dev, "gmvy,pv->gmyp", W2, cx.Cv(e, 2, s2));
-  Tensor W4 = einsum(dev, "gmyp,nbp->gmynb", W3, cx.Tv(e, 1, s2));
-  Tensor HB = einsum(dev, "gmynb,stgzby->mnstz", W4, ao2);
-  return einsum(dev, "mnstz,mnuvz->sutv", HT, HB);
-}
-
-// enlarged corner of site s, corner c, with a (plain, [D2]^4 rotated) or an
-// open rotated double layer ([d][d][D2]^4): returns [n][n] or [n][n][d][d]
-Tensor corner_of(Context& cx, const Env& e, int c, int s, const Tensor& ac) {
-  Device& dev = cx.dev;
-  Tensor X1 = einsum(dev, "mgi,ij->mgj", cx.Tv(e, (c + 3) % 4, s),
-                     cx.Cv(e, c, s));
-  Tensor X2 = einsum(dev, "mgj,jek->mgek", X1, cx.Tv(e, c, s));
-  if (ac.rank() == 4) {
-    Tensor Q = einsum(dev, "mgek,gebf->mfkb", X2, ac);
-    return Q.view({cx.n, cx.n});
+struct Net {
+  Tape& tp;
+  Context& cx;
+  const VEnv& e;
+  const std::vector<Var>& As;
+  const std::vector<Var>& arot;
+  int ns() const { return cx.nsite(); }
+  Var C(int c, int s) const { return e.C[c * ns() + s]; }
+  Var T(int c, int s) const { return e.T[c * ns() + s]; }
+  Var a(int s, int c) const { return arot[s * 4 + c]; }
+  Var E(const char* spec, const Var& x, const Var& y) {
+    return tp.einsum(spec, x, y);
   }
-  Tensor Q = einsum(dev, "mgek,stgebf->mfkbst", X2, ac);
-  return Q.view({cx.n, cx.n, cx.d, cx.d});
-}
-
-Tensor rdm_diag(Context& cx, const Env& e, int s00, int s10, int s11,
-                int s01, bool anti) {
-  Device& dev = cx.dev;
-  if (!anti) {
-    Tensor Q0 = corner_of(cx, e, 0, s00,
-                          rotate_open(cx, open_double_layer(cx, s00), 0));
-    Tensor Q1 = corner_of(cx, e, 1, s10, cx.av(s10, 1));
-    Tensor Q2 = corner_of(cx, e, 2, s11,
-                          rotate_open(cx, open_double_layer(cx, s11), 2));
-    Tensor Q3 = corner_of(cx, e, 3, s01, cx.av(s01, 3));
-    Tensor P1 = einsum(dev, "XYst,YZ->XZst", Q0, Q1);
-    Tensor P2 = einsum(dev, "ZWuv,WX->ZXuv", Q2, Q3);
-    return einsum(dev, "XZst,ZXuv->sutv", P1, P2);
+  // ao[s, t, (l l'), (u u'), (r r'), (d d')]
+  Var ao(int s, int c = 0) {
+    const int D2 = cx.D2, d = cx.d;
+    Var o = tp.view(E("sabce,tfghi->stafbgchei", As[s], As[s]),
+                    {d, d, D2, D2, D2, D2});
+    if (c == 0) return o;
+    return tp.permute(o, {0, 1, 2 + c % 4, 2 + (c + 1) % 4, 2 + (c + 2) % 4,
+                          2 + (c + 3) % 4});
   }
-  Tensor Q0 = corner_of(cx, e, 0, s00, cx.av(s00, 0));
-  Tensor Q1 = corner_of(cx, e, 1, s10,
-                        rotate_open(cx, open_double_layer(cx, s10), 1));
-  Tensor Q2 = corner_of(cx, e, 2, s11, cx.av(s11, 2));
-  Tensor Q3 = corner_of(cx, e, 3, s01,
-                        rotate_open(cx, open_double_layer(cx, s01), 3));
-  Tensor P1 = einsum(dev, "XY,YZuv->XZuv", Q0, Q1);
-  Tensor P2 = einsum(dev, "ZW,WXst->ZXst", Q2, Q3);
-  return einsum(dev, "XZuv,ZXst->sutv", P1, P2);
-}
-
-// ring of the eight environment tensors of site s: E[l, u, r, d] (fused)
-Tensor site_env(Context& cx, const Env& e, int s) {
-  Device& dev = cx.dev;
-  Tensor Tp1 = einsum(dev, "ij,jek->iek", cx.Cv(e, 0, s), cx.Tv(e, 0, s));
-  Tensor Tp = einsum(dev, "iek,km->iem", Tp1, cx.Cv(e, 1, s));
-  Tensor Bt1 = einsum(dev, "np,pzq->nzq", cx.Cv(e, 2, s), cx.Tv(e, 2, s));
-  Tensor Bt = einsum(dev, "nzq,qw->nzw", Bt1, cx.Cv(e, 3, s));
-  Tensor X = einsum(dev, "iem,mbn->iebn", Tp, cx.Tv(e, 1, s));
-  Tensor Y = einsum(dev, "iebn,nzw->iebzw", X, Bt);
-  return einsum(dev, "iebzw,wgi->gebz", Y, cx.Tv(e, 3, s));
-}
-
-Tensor rdm_site(Context& cx, const Env& e, int s) {
-  Tensor E = site_env(cx, e, s);
-  return einsum(cx.dev, "gebz,stgebz->st", E, open_double_layer(cx, s));
-}
-
-Tensor term_rdm(Context& cx, const Env& e, const TermSpec& t) {
-  const Lattice& L = cx.lat;
-  const int x = t.site % L.Lx, y = t.site / L.Lx;
-  if (t.kind == 0) return rdm_site(cx, e, t.site);
-  if (t.dx == 1 && t.dy == 0) {
-    const int s2 = L.idx(x + 1, y);
-    return rdm_h(cx, e, t.site, s2, open_double_layer(cx, t.site),
-                 open_double_layer(cx, s2));
+  Var rdm_h(int s1, int s2) {
+    Var L1 = E("ij,mgi->jmg", C(0, s1), T(3, s1));
+    Var L2 = E("jmg,qm->jgq", L1, C(3, s1));
+    Var L3 = E("jgq,jek->gqek", L2, T(0, s1));
+    Var L4 = E("gqek,wzq->gekwz", L3, T(2, s1));
+    Var HL = E("gekwz,stgebz->kwstb", L4, ao(s1));
+    Var R1 = E("ji,ibm->jbm", C(1, s2), T(1, s2));
+    Var R2 = E("jbm,mq->jbq", R1, C(2, s2));
+    Var R3 = E("kej,jbq->kebq", T(0, s2), R2);
+    Var R4 = E("kebq,qzw->kebzw", R3, T(2, s2));
+    Var HR = E("kebzw,stvebz->kwstv", R4, ao(s2));
+    return E("kwstb,kwuvb->sutv", HL, HR);
   }
-  if (t.dx == 0 && t.dy == 1) {
-    const int s2 = L.idx(x, y + 1);
-    return rdm_v(cx, e, t.site, s2, open_double_layer(cx, t.site),
-                 open_double_layer(cx, s2));
+  Var rdm_v(int s1, int s2) {
+    Var V1 = E("ij,jek->iek", C(0, s1), T(0, s1));
+    Var V2 = E("iek,kp->iep", V1, C(1, s1));
+    Var V3 = E("iep,mgi->epmg", V2, T(3, s1));
+    Var V4 = E("epmg,pbn->emgbn", V3, T(1, s1));
+    Var HT = E("emgbn,stgebz->mnstz", V4, ao(s1));
+    Var W1 = E("qgm,wq->gmw", T(3, s2), C(3, s2));
+    Var W2 = E("gmw,vyw->gmvy", W1, T(2, s2));
+    Var W3 = E("gmvy,pv->gmyp", W2, C(2, s2));
+    Var W4 = E("gmyp,nbp->gmynb", W3, T(1, s2));
+    Var HB = E("gmynb,stgzby->mnstz", W4, ao(s2));
+    return E("mnstz,mnuvz->sutv", HT, HB);
   }
-  if (t.dx == 1 && t.dy == 1)
-    return rdm_diag(cx, e, L.idx(x, y), L.idx(x + 1, y), L.idx(x + 1, y + 1),
-                    L.idx(x, y + 1), false);
-  if (t.dx == 1 && t.dy == -1)
-    return rdm_diag(cx, e, L.idx(x, y - 1), L.idx(x + 1, y - 1),
-                    L.idx(x + 1, y), L.idx(x, y), true);
-  throw ArgError("unsupported term displacement");
-}
+  // enlarged corner c of site s, plain ([n][n]) or open ([n][n][d][d])
+  Var corner(int c, int s, bool open) {
+    const int64_t n = cx.n;
+    Var X1 = E("mgi,ij->mgj", T((c + 3) % 4, s), C(c, s));
+    Var X2 = E("mgj,jek->mgek", X1, T(c, s));
+    if (!open) return tp.view(E("mgek,gebf->mfkb", X2, a(s, c)), {n, n});
+    return tp.view(E("mgek,stgebf->mfkbst", X2, ao(s, c)),
+                   {n, n, cx.d, cx.d});
+  }
+  Var rdm_diag(int s00, int s10, int s11, int s01, bool anti) {
+    if (!anti) {
+      Var Q0 = corner(0, s00, true), Q1 = corner(1, s10, false);
+      Var Q2 = corner(2, s11, true), Q3 = corner(3, s01, false);
+      Var P1 = E("XYst,YZ->XZst", Q0, Q1);
+      Var P2 = E("ZWuv,WX->ZXuv", Q2, Q3);
+      return E("XZst,ZXuv->sutv", P1, P2);
+    }
+    Var Q0 = corner(0, s00, false), Q1 = corner(1, s10, true);
+    Var Q2 = corner(2, s11, false), Q3 = corner(3, s01, true);
+    Var P1 = E("XY,YZuv->XZuv", Q0, Q1);
+    Var P2 = E("ZW,WXst->ZXst", Q2, Q3);
+    return E("XZuv,ZXst->sutv", P1, P2);
+  }
+  Var rdm_site(int s) {
+    Var Tp1 = E("ij,jek->iek", C(0, s), T(0, s));
+    Var Tp = E("iek,km->iem", Tp1, C(1, s));
+    Var Bt1 = E("np,pzq->nzq", C(2, s), T(2, s));
+    Var Bt = E("nzq,qw->nzw", Bt1, C(3, s));
+    Var X = E("iem,mbn->iebn", Tp, T(1, s));
+    Var Y = E("iebn,nzw->iebzw", X, Bt);
+    Var Env = E("iebzw,wgi->gebz", Y, T(3, s));
+    return E("gebz,stgebz->st", Env, ao(s));
+  }
+  Var term_rdm(const TermSpec& t) {
+    const Lattice& L = cx.lat;
+    const int x = t.site % L.Lx, y = t.site / L.Lx;
+    if (t.kind == 0) return rdm_site(t.site);
+    if (t.dx == 1 && t.dy == 0) return rdm_h(t.site, L.idx(x + 1, y));
+    if (t.dx == 0 && t.dy == 1) return rdm_v(t.site, L.idx(x, y + 1));
+    if (t.dx == 1 && t.dy == 1)
+      return rdm_diag(L.idx(x, y), L.idx(x + 1, y), L.idx(x + 1, y + 1),
+                      L.idx(x, y + 1), false);
+    if (t.dx == 1 && t.dy == -1)
+      return rdm_diag(L.idx(x, y - 1), L.idx(x + 1, y - 1), L.idx(x + 1, y),
+                      L.idx(x, y), true);
+    throw ArgError("unsupported term displacement");
+  }
+};
 
-double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms,
-              Tensor* gA, Env* gEnv) {
-  (void)gA;
-  (void)gEnv;
+}  // namespace
+
+double energy_ad(Tape& tp, Context& cx, const VEnv& e,
+                 const std::vector<Var>& As, const std::vector<Var>& arot,
+                 const std::vector<TermSpec>& terms) {
   Device& dev = cx.dev;
+  Net net{tp, cx, e, As, arot};
   Tensor acc = dev.zeros({1});
   for (const auto& t : terms) {
-    Tensor rho = term_rdm(cx, e, t);
+    Var rho = net.term_rdm(t);
     const int m = t.kind == 0 ? cx.d : cx.d * cx.d;
     Tensor h = dev.empty({m, m});
     dev.upload(h, t.mat.data());
-    term_energy(dev, rho.ptr, h.ptr, m, t.coef / cx.nsite(), acc.ptr,
-                nullptr);
+    double* rb = rho->req ? tp.grad(rho).ptr : nullptr;
+    term_energy(dev, rho->v.ptr, h.ptr, m, t.coef / cx.nsite(), acc.ptr, rb);
   }
   double v = 0.0;
   dev.download(acc, &v);
   return v;
+}
+
+double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms) {
+  Tape tp(cx.dev, false);
+  VEnv v = venv_leaves(tp, cx, e);
+  std::vector<Var> As = site_leaves(tp, cx, false);
+  return energy_ad(tp, cx, v, As, arot_leaves(tp, cx), terms);
 }
 
 }  // namespace ipeps

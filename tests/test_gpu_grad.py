@@ -1,0 +1,76 @@
+"""FP64 parity of the device gradient (K-step unrolled backward pass) and of
+the preconditioned direction built from it, against the CPU oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ctmrg, gradient, metric
+from paper_2511_09546_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _env_arrays(env):
+    C = np.stack([np.stack([t.numpy() for t in row]) for row in env.C])
+    T = np.stack([np.stack([t.numpy() for t in row]) for row in env.T])
+    return C, T
+
+
+@pytest.mark.parametrize("D,chi,K,J2,seed", [(2, 6, 3, 0.4, 7),
+                                             (2, 8, 5, 0.0, 8),
+                                             (3, 10, 2, 0.3, 9)])
+def test_grad_K_same_env(D, chi, K, J2, seed):
+    """Both sides differentiate A -> e(A, F^K(A, env*)) from the very same
+    env* (the oracle's, uploaded): element-by-element agreement."""
+    _say(f"grad parity D={D} chi={chi} K={K} J2={J2}")
+    A = inputs.random_state(seed, 1, 1, 2, D)
+    terms = inputs.terms_j1j2(1, 1, 1.0, J2)
+    env, _, _ = ctmrg.converge(A, chi, 1e-13, 500)
+    e_or, g_or = gradient.grad_K(A, terms, env, chi, K)
+    g_or = g_or.numpy()
+    C, T = _env_arrays(env)
+    o = binding.default_opts()
+    o.grad_K = K
+    with binding.Context(A, chi, opts=o) as ctx:
+        ctx.set_env(C, T)
+        e, g = ctx.energy_grad(terms, grad=True)
+    _say(f"  e {e!r} vs {e_or!r}; |g| {np.linalg.norm(g_or):.3e}")
+    assert abs(e - e_or) < 1e-10 * abs(e_or)
+    err = np.linalg.norm(g - g_or) / np.linalg.norm(g_or)
+    _say(f"  rel grad err {err:.2e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("name", ["d2chi8", "d4chi32"])
+def test_step_against_golden(name):
+    """Whole step on the seeded workload: converge, K=20 gradient,
+    preconditioned direction, against the oracle's stored values."""
+    _say(f"step vs golden {name}")
+    gold = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
+    w = inputs.WORKLOADS[name]
+    A = inputs.workload_state(name)
+    terms = inputs.workload_terms(name)
+    g_or = np.array(gold["g"]).reshape(A.shape)
+    x_or = np.array(gold["x"]).reshape(A.shape)
+    with binding.Context(A, w["chi"]) as ctx:
+        it, dl, ok = ctx.converge(w["tol"], w["n_iter"])
+        e, g = ctx.energy_grad(terms, grad=True)
+        x, cg_it, res, brk = ctx.precond(g, w["delta"], w["cg_tol"],
+                                         w["cg_maxiter"])
+    eg = np.linalg.norm(g - g_or) / np.linalg.norm(g_or)
+    ex = np.linalg.norm(x - x_or) / np.linalg.norm(x_or)
+    _say(f"  iters {it} vs {gold['n_iter']}, e {e!r} vs {gold['e']!r}, "
+         f"grad rel {eg:.2e}, x rel {ex:.2e}, cg {cg_it} vs {gold['cg_iter']}")
+    assert it == gold["n_iter"]
+    assert abs(e - gold["e"]) < 1e-10 * abs(gold["e"])
+    assert eg < 1e-9
+    assert cg_it == gold["cg_iter"]
+    assert ex < 1e-8
