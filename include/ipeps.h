@@ -159,6 +159,18 @@ int ipeps_set_env(ipeps_ctx* ctx, const double* in);
 /* Size in doubles of the environment buffer of ipeps_get_env. */
 size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
 
+/* Kernel timing of the context's own launches, for roofline reports: with
+ * on = 1 the context records HIP events on its stream around every launch
+ * of the timed kernel families (clearing earlier records); on = 0 stops.
+ * Families: 0 = GEMM (FP64 matrix-core GEMM, all shapes), 1 = Jacobi
+ * eigensolver, 2 = permute.  ipeps_profile_read returns, for one family,
+ * the number of launches, their summed device time in seconds and their
+ * algorithmic FLOP and byte counts (2 M N K flop; the operand and result
+ * bytes of each launch).  Errors: EINVAL, EHIP. */
+int ipeps_profile_enable(ipeps_ctx* ctx, int on);
+int ipeps_profile_read(ipeps_ctx* ctx, int family, long* launches,
+                       double* seconds, double* flop, double* bytes);
+
 /* Release the context and all its device memory (NULL is a no-op). */
 void ctm_free(ipeps_ctx* ctx);
 

@@ -29,6 +29,14 @@ int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
 int ipeps_debug_svd_ts(int n, int b, int batch, const double* W, double* U,
                        double* s, double* J);
 
+/* Iteration counters of a context since its creation: out[0] subspace
+ * iterations, out[1] projector-SVD calls, out[2] largest final subspace
+ * residual (relative to s_1), out[3] complement-CG iterations of the
+ * backward pass, out[4] complement solves, out[5] device memory held by the
+ * context's pool in bytes. */
+struct ipeps_ctx;
+int ipeps_debug_stats(struct ipeps_ctx* ctx, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,10 +25,12 @@ API_FUNCTIONS = [
     "ipeps_default_opts", "ctm_init", "ctm_set_state", "ctm_converge",
     "ipeps_energy_grad", "precond_apply", "ipeps_corner_spectra",
     "ipeps_get_env", "ipeps_set_env", "ipeps_env_size", "ctm_free",
-    "ipeps_strerror", "ipeps_version",
+    "ipeps_strerror", "ipeps_version", "ipeps_profile_enable",
+    "ipeps_profile_read",
 ]
+PROF_GEMM, PROF_JACOBI, PROF_PERMUTE = 0, 1, 2
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
-                   "ipeps_debug_svd_ts"]
+                   "ipeps_debug_svd_ts", "ipeps_debug_stats"]
 
 
 class IpepsError(RuntimeError):
@@ -83,15 +85,21 @@ def load():
     lib.ipeps_strerror.argtypes = [c_int]
     lib.ipeps_strerror.restype = ctypes.c_char_p
     lib.ipeps_version.restype = ctypes.c_char_p
+    lib.ipeps_profile_enable.argtypes = [c_void_p, c_int]
+    lib.ipeps_profile_read.argtypes = [c_void_p, c_int,
+                                       POINTER(ctypes.c_long), _DP, _DP, _DP]
     lib.ipeps_debug_gemm.argtypes = [c_int, c_int, c_int, c_int, c_int,
                                      c_double, _DP, _DP, c_double, _DP]
     lib.ipeps_debug_sym_eig.argtypes = [c_int, c_int, _DP, _DP, _DP]
+    lib.ipeps_debug_stats.argtypes = [c_void_p, _DP]
     lib.ipeps_debug_svd_ts.argtypes = [c_int, c_int, c_int, _DP, _DP, _DP,
                                        _DP]
     for name in ("ctm_init", "ctm_set_state", "ctm_converge",
                  "ipeps_energy_grad", "precond_apply", "ipeps_corner_spectra",
                  "ipeps_get_env", "ipeps_set_env", "ipeps_debug_gemm",
-                 "ipeps_debug_sym_eig", "ipeps_debug_svd_ts"):
+                 "ipeps_profile_enable", "ipeps_profile_read",
+                 "ipeps_debug_sym_eig", "ipeps_debug_svd_ts",
+                 "ipeps_debug_stats"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -223,6 +231,31 @@ class Context:
         nc = 4 * n * chi * chi
         return (buf[:nc].reshape(4, n, chi, chi),
                 buf[nc:].reshape(4, n, chi, D2, chi))
+
+    def profile(self, on: bool):
+        st = load().ipeps_profile_enable(self._h, int(on))
+        if st != OK:
+            raise IpepsError(st, "ipeps_profile_enable")
+
+    def profile_read(self, family: int):
+        """(launches, seconds, flop, bytes) of one kernel family."""
+        n = ctypes.c_long(0)
+        sec, fl, by = c_double(0), c_double(0), c_double(0)
+        st = load().ipeps_profile_read(self._h, family, ctypes.byref(n),
+                                       ctypes.byref(sec), ctypes.byref(fl),
+                                       ctypes.byref(by))
+        if st != OK:
+            raise IpepsError(st, "ipeps_profile_read")
+        return n.value, sec.value, fl.value, by.value
+
+    def stats(self) -> dict:
+        out = np.zeros(6)
+        st = load().ipeps_debug_stats(self._h, _dp(out))
+        if st != OK:
+            raise IpepsError(st, "ipeps_debug_stats")
+        return dict(svd_iters=int(out[0]), svd_calls=int(out[1]),
+                    svd_worst_residual=float(out[2]), cg_iters=int(out[3]),
+                    cg_solves=int(out[4]), pool_bytes=int(out[5]))
 
     def set_env(self, C, T):
         buf = np.concatenate([_f64(C).ravel(), _f64(T).ravel()])

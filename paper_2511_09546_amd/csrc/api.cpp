@@ -5,6 +5,7 @@
 #include <new>
 
 #include "../../include/ipeps.h"
+#include "../../include/ipeps_debug.h"
 #include "ipeps_impl.hpp"
 
 struct ipeps_ctx {
@@ -283,6 +284,41 @@ int ipeps_set_env(ipeps_ctx* c, const double* in) {
     cx.dev.sync();
     return IPEPS_OK;
   });
+}
+
+int ipeps_profile_enable(ipeps_ctx* c, int on) {
+  if (!c) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    cx.dev.sync();
+    cx.dev.prof.clear();
+    cx.dev.prof.on = on != 0;
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_profile_read(ipeps_ctx* c, int family, long* launches,
+                       double* seconds, double* flop, double* bytes) {
+  if (!c || family < 0 || family >= PROF_N || !launches || !seconds ||
+      !flop || !bytes)
+    return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    cx.dev.prof.read(family, launches, seconds, flop, bytes);
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_debug_stats(ipeps_ctx* c, double* out) {
+  if (!c || !out) return IPEPS_EINVAL;
+  const SvdStats& st = c->cx.stats;
+  out[0] = (double)st.iters;
+  out[1] = (double)st.calls;
+  out[2] = st.worst_residual;
+  out[3] = (double)st.cg_iters;
+  out[4] = (double)st.cg_solves;
+  out[5] = (double)c->cx.dev.pool.reserved();
+  return IPEPS_OK;
 }
 
 void ctm_free(ipeps_ctx* c) {

@@ -76,6 +76,59 @@ Tensor Tensor::slice0(int64_t i) const {
   return t;
 }
 
+// --------------------------------------------------------------- Profiler
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  IPEPS_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::begin(hipStream_t s, int fam, double flop, double bytes) {
+  Rec r{fam, get(), get(), flop, bytes};
+  IPEPS_HIP(hipEventRecord(r.a, s));
+  recs.push_back(r);
+}
+
+void Profiler::end(hipStream_t s) { IPEPS_HIP(hipEventRecord(recs.back().b, s)); }
+
+void Profiler::read(int fam, long* n, double* sec, double* flop,
+                    double* bytes) {
+  long cnt = 0;
+  double t = 0.0, f = 0.0, by = 0.0;
+  for (auto& r : recs) {
+    if (r.fam != fam) continue;
+    IPEPS_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    IPEPS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    ++cnt;
+    t += ms * 1e-3;
+    f += r.flop;
+    by += r.bytes;
+  }
+  *n = cnt;
+  *sec = t;
+  *flop = f;
+  *bytes = by;
+}
+
+void Profiler::clear() {
+  for (auto& r : recs) {
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+}
+
+Profiler::~Profiler() {
+  clear();
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 // ----------------------------------------------------------------- Device
 Tensor Device::empty(std::vector<int64_t> shape) {
   Tensor t;

@@ -80,11 +80,35 @@ struct Tensor {
   Tensor slice0(int64_t i) const;              // sub-tensor along dim 0
 };
 
+// Optional timing of the library's own launches: HIP events on the launch
+// stream around every launch of a kernel family, with the algorithmic FLOP
+// and byte counts of each launch.
+enum ProfFamily { PROF_GEMM = 0, PROF_JACOBI = 1, PROF_PERMUTE = 2, PROF_N = 3 };
+
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int fam;
+    hipEvent_t a, b;
+    double flop, bytes;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void begin(hipStream_t s, int fam, double flop, double bytes);
+  void end(hipStream_t s);
+  // launches, seconds, flop, bytes of one family (synchronises)
+  void read(int fam, long* n, double* sec, double* flop, double* bytes);
+  void clear();
+  ~Profiler();
+};
+
 // Execution context: one stream and one pool.
 struct Device {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   Pool pool;
+  Profiler prof;
 
   Tensor empty(std::vector<int64_t> shape);
   Tensor zeros(std::vector<int64_t> shape);

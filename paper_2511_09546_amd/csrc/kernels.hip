@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A,
     long lda, long sA, int tA, const double* __restrict__ B, long ldb,
     long sB, int tB, double beta, double* __restrict__ C, long ldc,
-    long sC) {
+    long sC, int tiles_n) {
   constexpr int WTM = BM / 2, WTN = BN / 2;
   constexpr int TM = WTM / 16, TN = WTN / 16;
   __shared__ double As[BK][BM + 1];
@@ -35,11 +35,11 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const long bz = blockIdx.z;
+  const long bz = blockIdx.y;
   A += bz * sA;
   B += bz * sB;
   C += bz * sC;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = (blockIdx.x / tiles_n) * BM, n0 = (blockIdx.x % tiles_n) * BN;
   f64x4 acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -119,7 +119,7 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
           int64_t ldc, int64_t sC, int64_t batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31) ||
-      batch > 65535)
+      batch > 65535 || (M / 64 + 1) * (N / 64 + 1) >= (1LL << 31))
     throw ArgError("gemm: size out of range");
   if (K == 0) {
     // C = beta C
@@ -139,42 +139,48 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
     const int64_t kc = (K + S - 1) / S;
     S = (int)((K + kc - 1) / kc);
     Tensor part = dev.empty({S, M, N});
+    if (dev.prof.on)
+      dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
+                     8.0 * batch * (M * K + K * N + M * N));
     for (int64_t bt = 0; bt < batch; ++bt) {
       const double* Ab = A + bt * sA;
       const double* Bb = B + bt * sB;
       const int64_t last = K - (S - 1) * kc;
       // full chunks
+      const int tn = (int)((N + BN - 1) / BN);
       if (S > 1) {
-        dim3 g((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM),
-               (unsigned)(S - 1));
+        dim3 g((unsigned)tiles, (unsigned)(S - 1));
         hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), g, dim3(256), 0,
                            dev.stream, (int)M, (int)N, (int)kc, 1.0, Ab,
                            (long)lda, (long)(tA ? kc * lda : kc), (int)tA, Bb,
                            (long)ldb, (long)(tB ? kc : kc * ldb), (int)tB,
-                           0.0, part.ptr, (long)N, (long)(M * N));
+                           0.0, part.ptr, (long)N, (long)(M * N), tn);
       }
       {
         const double* Al = Ab + (tA ? (S - 1) * kc * lda : (S - 1) * kc);
         const double* Bl = Bb + (tB ? (S - 1) * kc : (S - 1) * kc * ldb);
-        dim3 g((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM),
-               1);
+        dim3 g((unsigned)tiles, 1);
         hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), g, dim3(256), 0,
                            dev.stream, (int)M, (int)N, (int)last, 1.0, Al,
                            (long)lda, 0L, (int)tA, Bl, (long)ldb, 0L, (int)tB,
-                           0.0, part.ptr + (S - 1) * M * N, (long)N, 0L);
+                           0.0, part.ptr + (S - 1) * M * N, (long)N, 0L, tn);
       }
       IPEPS_HIP(hipGetLastError());
       splitk_reduce(dev, part.ptr, S, M, N, alpha, beta, C + bt * sC, ldc);
     }
+    if (dev.prof.on) dev.prof.end(dev.stream);
     return;
   }
-  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM),
-            (unsigned)batch);
-  if (grid.y > 65535) throw ArgError("gemm: M too large for grid");
+  const int tn = (int)((N + BN - 1) / BN);
+  dim3 grid((unsigned)tiles, (unsigned)batch);
+  if (dev.prof.on)
+    dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
+                   8.0 * batch * (M * K + K * N + (beta != 0.0 ? 2 : 1) * M * N));
   hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), grid, dim3(256), 0,
                      dev.stream, (int)M, (int)N, (int)K, alpha, A, (long)lda,
                      (long)sA, (int)tA, B, (long)ldb, (long)sB, (int)tB, beta,
-                     C, (long)ldc, (long)sC);
+                     C, (long)ldc, (long)sC, tn);
+  if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -253,8 +259,12 @@ void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
     p.out_shape[i] = (int)oshape[i];
     p.in_stride[i] = (int)ostr[i];
   }
+  if (dev.prof.on)
+    dev.prof.begin(dev.stream, PROF_PERMUTE, 0.0,
+                   8.0 * n * (beta != 0.0 ? 3 : 2));
   hipLaunchKernelGGL(permute_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
                      dev.stream, in.ptr, out.ptr, (int)n, p, alpha, beta);
+  if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -568,8 +578,10 @@ void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
                                   (int)lds));
     lds_set = lds;
   }
+  if (dev.prof.on) dev.prof.begin(dev.stream, PROF_JACOBI, 0.0, 0.0);
   hipLaunchKernelGGL(sym_eig_jacobi_kernel, dim3(batch), dim3(JAC_THREADS),
                      lds, dev.stream, G, V, lam, b);
+  if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
 }
 

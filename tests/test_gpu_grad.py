@@ -49,10 +49,12 @@ def test_grad_K_same_env(D, chi, K, J2, seed):
     assert err < 1e-10
 
 
-@pytest.mark.parametrize("name", ["d2chi8", "d4chi32"])
+@pytest.mark.parametrize("name", ["d2chi8", "d4chi32", "d6chi72"])
 def test_step_against_golden(name):
     """Whole step on the seeded workload: converge, K=20 gradient,
-    preconditioned direction, against the oracle's stored values."""
+    preconditioned direction, against the oracle's stored values (written by
+    tests/golden/make_golden.py; d6chi72 is the benchmarked D=6, chi=72
+    workload at full size)."""
     _say(f"step vs golden {name}")
     gold = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
     w = inputs.WORKLOADS[name]
