@@ -1,8 +1,6 @@
 // Hand-written gfx950 kernels of the iPEPS library (FP64 path).
 //
-//  * gemm_f64: batched GEMM on the FP64 matrix cores
-//    (v_mfma_f64_16x16x4_f64), LDS-staged tiles, 4 waves of 64 lanes per
-//    workgroup, each wave owning a (BM/2) x (BN/2) block of 16x16 MFMA tiles.
+//  (the FP64 matrix-core GEMM is in gemm.hip)
 //  * permute: generic rank <= 8 transpose, coalesced writes.
 //  * deterministic two-stage FP64 reductions (dot, 2-norm).
 //  * sym_eig_jacobi: batched parallel cyclic Jacobi eigensolver, one
@@ -17,172 +15,6 @@
 namespace ipeps {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// ------------------------------------------------------------------ GEMM
-// MFMA f64 16x16x4 lane layout (checked on gfx950): lane l supplies
-// A[l%16][l/16] and B[l/16][l%16]; the 16x16 result holds D[l/16 + 4r][l%16]
-// in register r of lane l.
-template <int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(
-    int M, int N, int K, double alpha, const double* __restrict__ A,
-    long lda, long sA, int tA, const double* __restrict__ B, long ldb,
-    long sB, int tB, double beta, double* __restrict__ C, long ldc,
-    long sC, int tiles_n) {
-  constexpr int WTM = BM / 2, WTN = BN / 2;
-  constexpr int TM = WTM / 16, TN = WTN / 16;
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const long bz = blockIdx.y;
-  A += bz * sA;
-  B += bz * sB;
-  C += bz * sC;
-  const int m0 = (blockIdx.x / tiles_n) * BM, n0 = (blockIdx.x % tiles_n) * BN;
-  f64x4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-
-  for (int kb = 0; kb < K; kb += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      int mm, kk;
-      if (!tA) {
-        mm = e / BK;
-        kk = e % BK;
-      } else {
-        kk = e / BM;
-        mm = e % BM;
-      }
-      const int gm = m0 + mm, gk = kb + kk;
-      double v = 0.0;
-      if (gm < M && gk < K)
-        v = tA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
-      As[kk][mm] = v;
-    }
-    for (int e = tid; e < BK * BN; e += 256) {
-      int kk, nn;
-      if (!tB) {
-        kk = e / BN;
-        nn = e % BN;
-      } else {
-        nn = e / BK;
-        kk = e % BK;
-      }
-      const int gk = kb + kk, gn = n0 + nn;
-      double v = 0.0;
-      if (gk < K && gn < N)
-        v = tB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k4 = 0; k4 < BK; k4 += 4) {
-      double a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-        a[i] = As[k4 + (lane >> 4)][wm * WTM + i * 16 + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-        b[j] = Bs[k4 + (lane >> 4)][wn * WTN + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j],
-                                                           acc[i][j], 0, 0,
-                                                           0);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WTM + i * 16 + (lane >> 4) + 4 * r;
-        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (row < M && col < N) {
-          double v = alpha * acc[i][j][r];
-          if (beta != 0.0) v += beta * C[(long)row * ldc + col];
-          C[(long)row * ldc + col] = v;
-        }
-      }
-}
-
-void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
-          double alpha, const double* A, int64_t lda, int64_t sA,
-          const double* B, int64_t ldb, int64_t sB, double beta, double* C,
-          int64_t ldc, int64_t sC, int64_t batch) {
-  if (M <= 0 || N <= 0 || batch <= 0) return;
-  if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31) ||
-      batch > 65535 || (M / 64 + 1) * (N / 64 + 1) >= (1LL << 31))
-    throw ArgError("gemm: size out of range");
-  if (K == 0) {
-    // C = beta C
-    for (int64_t b = 0; b < batch; ++b)
-      for (int64_t m = 0; m < M; ++m)
-        axpby(dev, N, 0.0, C + b * sC + m * ldc, beta, C + b * sC + m * ldc);
-    return;
-  }
-  constexpr int BM = 64, BN = 64, BK = 16;
-  const int64_t tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
-  if (tiles * batch < 128 && K >= 2048) {
-    // split K: every chunk is one batch entry of a strided GEMM into a
-    // partial buffer, then a fixed-order reduction (deterministic)
-    int S = (int)std::min<int64_t>(256 / std::max<int64_t>(tiles, 1),
-                                   K / 512);
-    S = std::max(S, 2);
-    const int64_t kc = (K + S - 1) / S;
-    S = (int)((K + kc - 1) / kc);
-    Tensor part = dev.empty({S, M, N});
-    if (dev.prof.on)
-      dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
-                     8.0 * batch * (M * K + K * N + M * N));
-    for (int64_t bt = 0; bt < batch; ++bt) {
-      const double* Ab = A + bt * sA;
-      const double* Bb = B + bt * sB;
-      const int64_t last = K - (S - 1) * kc;
-      // full chunks
-      const int tn = (int)((N + BN - 1) / BN);
-      if (S > 1) {
-        dim3 g((unsigned)tiles, (unsigned)(S - 1));
-        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), g, dim3(256), 0,
-                           dev.stream, (int)M, (int)N, (int)kc, 1.0, Ab,
-                           (long)lda, (long)(tA ? kc * lda : kc), (int)tA, Bb,
-                           (long)ldb, (long)(tB ? kc : kc * ldb), (int)tB,
-                           0.0, part.ptr, (long)N, (long)(M * N), tn);
-      }
-      {
-        const double* Al = Ab + (tA ? (S - 1) * kc * lda : (S - 1) * kc);
-        const double* Bl = Bb + (tB ? (S - 1) * kc : (S - 1) * kc * ldb);
-        dim3 g((unsigned)tiles, 1);
-        hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), g, dim3(256), 0,
-                           dev.stream, (int)M, (int)N, (int)last, 1.0, Al,
-                           (long)lda, 0L, (int)tA, Bl, (long)ldb, 0L, (int)tB,
-                           0.0, part.ptr + (S - 1) * M * N, (long)N, 0L, tn);
-      }
-      IPEPS_HIP(hipGetLastError());
-      splitk_reduce(dev, part.ptr, S, M, N, alpha, beta, C + bt * sC, ldc);
-    }
-    if (dev.prof.on) dev.prof.end(dev.stream);
-    return;
-  }
-  const int tn = (int)((N + BN - 1) / BN);
-  dim3 grid((unsigned)tiles, (unsigned)batch);
-  if (dev.prof.on)
-    dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
-                   8.0 * batch * (M * K + K * N + (beta != 0.0 ? 2 : 1) * M * N));
-  hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, BK>), grid, dim3(256), 0,
-                     dev.stream, (int)M, (int)N, (int)K, alpha, A, (long)lda,
-                     (long)sA, (int)tA, B, (long)ldb, (long)sB, (int)tB, beta,
-                     C, (long)ldc, (long)sC, tn);
-  if (dev.prof.on) dev.prof.end(dev.stream);
-  IPEPS_HIP(hipGetLastError());
-}
 
 // --------------------------------------------------------------- permute
 struct PermArgs {

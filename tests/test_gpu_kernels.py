@@ -15,7 +15,12 @@ def _say(msg):
     (16, 16, 4, False, False), (64, 64, 16, False, False),
     (70, 33, 19, False, False), (70, 33, 19, True, False),
     (70, 33, 19, False, True), (70, 33, 19, True, True),
-    (129, 200, 300, False, False), (5, 300, 1, False, False)])
+    (129, 200, 300, False, False), (5, 300, 1, False, False),
+    (300, 200, 700, False, False), (300, 200, 700, True, False),
+    (300, 200, 700, False, True), (300, 200, 700, True, True),
+    (2592, 96, 2592, False, False), (2592, 72, 2592, True, False),
+    (257, 65, 33, True, True), (36, 36, 20000, False, False),
+    (100, 1000, 16, False, True)])
 def test_gemm(M, N, K, tA, tB):
     _say(f"gemm {M}x{N}x{K} tA={tA} tB={tB}")
     rng = np.random.default_rng(M * N + K)
