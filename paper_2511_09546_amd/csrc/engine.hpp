@@ -127,6 +127,13 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
           const double* B, int64_t ldb, int64_t sB, double beta, double* C,
           int64_t ldc, int64_t sC, int64_t batch = 1);
 
+// Batched GEMM over arbitrary operand addresses (one launch): C[i] = alpha
+// op(A[i]) op(B[i]) + beta C[i], same shapes and leading dimensions.
+void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
+               int64_t K, double alpha, const std::vector<const double*>& A,
+               int64_t lda, const std::vector<const double*>& B, int64_t ldb,
+               double beta, const std::vector<double*>& C, int64_t ldc);
+
 // out = alpha * permute(in, perm) + beta * out (rank <= 12 after merging
 // contiguous dims); out.shape[i] =
 // in.shape[perm[i]].
@@ -209,18 +216,29 @@ void null_threshold(Device& dev, double* S, int b, double rel, int batch,
 }  // namespace ipeps
 
 namespace ipeps {
+// Column dots of `batch` n x m row-major blocks (stride sXY):
+// out[bt][j] = sum_i X[bt][i][j] Y[bt][i][j]
 void coldot(Device& dev, const double* X, const double* Y, int64_t n, int m,
-            double* out);
+            double* out, int batch = 1, int64_t sXY = 0);
 void proj_weights(Device& dev, const double* S, const int* keep, int chi,
-                  double* w);
+                  double* w, int batch = 1, int sS = 0);
 void proj_sbar(Device& dev, const double* S, const int* keep, int chi,
-               const double* wb1, const double* wb2, double* sbar);
+               const double* wb1, const double* wb2, double* sbar,
+               int batch = 1, int sS = 0);
 void svd_gkk(Device& dev, const double* Au, const double* Av, const double* S,
-             const double* sbar, const int* keep, int chi, double* G);
-void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep);
+             const double* sbar, const int* keep, int chi, double* G,
+             int batch = 1, int sS = 0);
+void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep,
+               int batch = 1);
+// rows = total rows of all batches; per-(batch, column) scalars use
+// rows_per_batch (0 = one batch)
 void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
            const double* den, double* x, double* r, double* p,
-           const double* Ap);
+           const double* Ap, int64_t rows_per_batch = 0);
 void col_axpby(Device& dev, int64_t n, int m, double a, const double* s,
-               const double* x, double b, double* y);
+               const double* x, double b, double* y,
+               int64_t rows_per_batch = 0, int64_t sS = 0);
+void copy2d(Device& dev, const double* src, int64_t lds, double* dst,
+            int64_t ldd, int64_t rows, int64_t cols, int batch = 1,
+            int64_t sSrc = 0, int64_t sDst = 0);
 }  // namespace ipeps

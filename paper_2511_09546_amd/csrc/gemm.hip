@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "engine.hpp"
 
@@ -39,7 +40,9 @@ __global__ __launch_bounds__(256, 2) void gemm64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
-    int splits, int kchunk, double* __restrict__ part) {
+    int splits, int kchunk, double* __restrict__ part,
+    const double* const* __restrict__ Ap, const double* const* __restrict__ Bp,
+    double* const* __restrict__ Cp) {
   static_assert(WM * WN == 4, "4 waves");
   constexpr int WTM = BM / WM, WTN = BN / WN;
   constexpr int TM = WTM / 16, TN = WTN / 16;
@@ -50,8 +53,8 @@ __global__ __launch_bounds__(256, 2) void gemm64_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int bz = blockIdx.y / splits, sp = blockIdx.y % splits;
-  A += (long)bz * sA;
-  B += (long)bz * sB;
+  A = Ap ? Ap[bz] : A + (long)bz * sA;
+  B = Bp ? Bp[bz] : B + (long)bz * sB;
   const int m0 = (blockIdx.x / tiles_n) * BM;
   const int n0 = (blockIdx.x % tiles_n) * BN;
   const int kbeg = sp * kchunk;
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(256, 2) void gemm64_kernel(
   double* out;
   long ldo;
   if (splits == 1) {
-    out = C + (long)bz * sC;
+    out = Cp ? Cp[bz] : C + (long)bz * sC;
     ldo = ldc;
   } else {
     out = part + ((long)sp * gridDim.y / splits + bz) * (long)M * N;
@@ -184,7 +187,8 @@ __global__ __launch_bounds__(256, 2) void gemm64_kernel(
 __global__ void splitk_sum_kernel(const double* __restrict__ part, int S,
                                   int batch, long M, long N, double alpha,
                                   double beta, double* __restrict__ C,
-                                  long ldc, long sC) {
+                                  long ldc, long sC,
+                                  double* const* __restrict__ Cp) {
   const long mn = M * N, tot = mn * batch;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
        e += (long)gridDim.x * blockDim.x) {
@@ -192,7 +196,7 @@ __global__ void splitk_sum_kernel(const double* __restrict__ part, int S,
     double v = 0.0;
     for (int s = 0; s < S; ++s) v += part[((long)s * batch + b) * mn + i];
     const long r = i / N, c = i % N;
-    double* cp = C + b * sC + r * ldc + c;
+    double* cp = (Cp ? Cp[b] : C + b * sC) + r * ldc + c;
     double o = alpha * v;
     if (beta != 0.0) o += beta * *cp;
     *cp = o;
@@ -203,7 +207,8 @@ template <int BM, int BN, int WM, int WN>
 void launch_cfg(Device& dev, bool tA, bool tB, int M, int N, int K,
                 double alpha, const double* A, long lda, long sA,
                 const double* B, long ldb, long sB, double beta, double* C,
-                long ldc, long sC, int batch) {
+                long ldc, long sC, int batch, const double* const* Ap,
+                const double* const* Bp, double* const* Cp) {
   const long tm = (M + BM - 1) / BM, tn = (N + BN - 1) / BN;
   const long tiles = tm * tn;
   // split K until the grid covers the chip (>= 320 workgroups), keeping at
@@ -226,7 +231,7 @@ void launch_cfg(Device& dev, bool tA, bool tB, int M, int N, int K,
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), 0, dev.stream, M, N, K, alpha,
                        A, lda, sA, B, ldb, sB, beta, C, ldc, sC, (int)tn, S,
-                       kchunk, part.ptr);
+                       kchunk, part.ptr, Ap, Bp, Cp);
   };
   if (!tA && !tB) go(gemm64_kernel<BM, BN, WM, WN, false, false>);
   if (tA && !tB) go(gemm64_kernel<BM, BN, WM, WN, true, false>);
@@ -239,45 +244,87 @@ void launch_cfg(Device& dev, bool tA, bool tB, int M, int N, int K,
                                                         8192));
     hipLaunchKernelGGL(splitk_sum_kernel, dim3(g), dim3(256), 0, dev.stream,
                        part.ptr, S, batch, (long)M, (long)N, alpha, beta, C,
-                       ldc, sC);
+                       ldc, sC, Cp);
     IPEPS_HIP(hipGetLastError());
   }
 }
 
 }  // namespace
 
+static void dispatch(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
+                     int64_t K, double alpha, const double* A, int64_t lda,
+                     int64_t sA, const double* B, int64_t ldb, int64_t sB,
+                     double beta, double* C, int64_t ldc, int64_t sC,
+                     int64_t batch, const double* const* Ap,
+                     const double* const* Bp, double* const* Cp) {
+  if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31) ||
+      batch > 65535)
+    throw ArgError("gemm: size out of range");
+  if (dev.prof.on)
+    dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
+                   8.0 * batch *
+                       (M * K + K * N + (beta != 0.0 ? 2 : 1) * M * N));
+  const int m = (int)M, n = (int)N, k = (int)K, bt = (int)batch;
+#define IPEPS_CFG(BM_, BN_, WM_, WN_)                                        \
+  launch_cfg<BM_, BN_, WM_, WN_>(dev, tA, tB, m, n, k, alpha, A, lda, sA, B, \
+                                 ldb, sB, beta, C, ldc, sC, bt, Ap, Bp, Cp)
+  if (M >= 128) {
+    // narrow N (chi-wide blocks of the projector SVD and the complement
+    // solves): 4 waves stacked along M, tile width rounded up to 16
+    if (N <= 48)
+      IPEPS_CFG(128, 48, 4, 1);
+    else if (N <= 64)
+      IPEPS_CFG(128, 64, 4, 1);
+    else if (N <= 80)
+      IPEPS_CFG(128, 80, 4, 1);
+    else if (N <= 96)
+      IPEPS_CFG(128, 96, 4, 1);
+    else
+      IPEPS_CFG(128, 128, 2, 2);
+  } else if (N >= 128) {
+    IPEPS_CFG(64, 128, 2, 2);
+  } else {
+    IPEPS_CFG(64, 64, 2, 2);
+  }
+#undef IPEPS_CFG
+  if (dev.prof.on) dev.prof.end(dev.stream);
+}
+
 void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
           double alpha, const double* A, int64_t lda, int64_t sA,
           const double* B, int64_t ldb, int64_t sB, double beta, double* C,
           int64_t ldc, int64_t sC, int64_t batch) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
-  if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31) ||
-      batch > 65535)
-    throw ArgError("gemm: size out of range");
   if (K == 0) {
     for (int64_t b = 0; b < batch; ++b)
       for (int64_t m = 0; m < M; ++m)
         axpby(dev, N, 0.0, C + b * sC + m * ldc, beta, C + b * sC + m * ldc);
     return;
   }
-  if (dev.prof.on)
-    dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
-                   8.0 * batch *
-                       (M * K + K * N + (beta != 0.0 ? 2 : 1) * M * N));
-  const int m = (int)M, n = (int)N, k = (int)K, bt = (int)batch;
-  if (M >= 128 && N > 64)
-    launch_cfg<128, 128, 2, 2>(dev, tA, tB, m, n, k, alpha, A, lda, sA, B,
-                               ldb, sB, beta, C, ldc, sC, bt);
-  else if (M >= 128)
-    launch_cfg<128, 64, 2, 2>(dev, tA, tB, m, n, k, alpha, A, lda, sA, B, ldb,
-                              sB, beta, C, ldc, sC, bt);
-  else if (N >= 128)
-    launch_cfg<64, 128, 2, 2>(dev, tA, tB, m, n, k, alpha, A, lda, sA, B, ldb,
-                              sB, beta, C, ldc, sC, bt);
-  else
-    launch_cfg<64, 64, 2, 2>(dev, tA, tB, m, n, k, alpha, A, lda, sA, B, ldb,
-                             sB, beta, C, ldc, sC, bt);
-  if (dev.prof.on) dev.prof.end(dev.stream);
+  dispatch(dev, tA, tB, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
+           sC, batch, nullptr, nullptr, nullptr);
+}
+
+void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
+               int64_t K, double alpha, const std::vector<const double*>& A,
+               int64_t lda, const std::vector<const double*>& B, int64_t ldb,
+               double beta, const std::vector<double*>& C, int64_t ldc) {
+  const int64_t batch = (int64_t)A.size();
+  if (M <= 0 || N <= 0 || batch <= 0 || K <= 0) return;
+  if ((int64_t)B.size() != batch || (int64_t)C.size() != batch)
+    throw ArgError("gemm_ptrs: pointer counts differ");
+  // one upload of the three pointer arrays (stream ordered, pageable copy)
+  std::vector<double> h(3 * batch);
+  std::memcpy(h.data(), A.data(), 8 * batch);
+  std::memcpy(h.data() + batch, B.data(), 8 * batch);
+  std::memcpy(h.data() + 2 * batch, C.data(), 8 * batch);
+  Tensor d = dev.empty({3 * batch});
+  dev.upload(d, h.data());
+  const double* const* Ap = (const double* const*)d.ptr;
+  const double* const* Bp = (const double* const*)(d.ptr + batch);
+  double* const* Cp = (double* const*)(d.ptr + 2 * batch);
+  dispatch(dev, tA, tB, M, N, K, alpha, A[0], lda, 0, B[0], ldb, 0, beta,
+           C[0], ldc, 0, batch, Ap, Bp, Cp);
 }
 
 }  // namespace ipeps

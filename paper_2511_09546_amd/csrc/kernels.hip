@@ -283,10 +283,13 @@ void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
 // (Golub & Van Loan, symmetric Schur 2x2); a pair is skipped when
 // |G_pq| <= 1e-15 sqrt|G_pp G_qq| (relative criterion, so small eigenvalues
 // of graded matrices keep their relative accuracy).  Stops after a sweep
-// without rotations (or 40 sweeps).  G lives in LDS, V in global memory.
+// without rotations (or 40 sweeps).  G lives in LDS; the eigenvector matrix
+// V too when b <= 96 (2 b^2 doubles fit the 160 KB of LDS), else in global
+// memory.
 constexpr int JAC_THREADS = 512;
 constexpr int JAC_MAXB = 128;
 
+template <bool VLDS>
 __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
     double* __restrict__ Gall, double* __restrict__ Vall,
     double* __restrict__ lamall, int b) {
@@ -299,7 +302,9 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
   __shared__ int rotated;
   const int bt = blockIdx.x;
   double* Gg = Gall + (long)bt * b * b;
-  double* V = Vall + (long)bt * b * b;
+  double* Vout = Vall + (long)bt * b * b;
+  // eigenvectors accumulate in LDS when they fit (b <= 96), else in global
+  double* V = VLDS ? (double*)(qq + b / 2 + (b / 2) % 2) : Vout;
   double* lam = lamall + (long)bt * b;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i < b * b; i += nt) {
@@ -391,7 +396,7 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
   }
   __syncthreads();
   for (int e = tid; e < b * b; e += nt) {
-    V[e] = G[e];
+    Vout[e] = G[e];
     Gg[e] = (e / b == e % b) ? ev[e / b] : 0.0;
   }
   for (int i = tid; i < b; i += nt) lam[i] = ev[i];
@@ -401,18 +406,26 @@ void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
                     int batch) {
   if (b % 2 != 0 || b < 2 || b > JAC_MAXB)
     throw ArgError("sym_eig_jacobi: b must be even and <= 128");
-  const size_t lds = (size_t)b * b * sizeof(double) +
-                     2 * (b / 2) * sizeof(double) + 2 * (b / 2) * sizeof(int);
-  static size_t lds_set = 0;
-  if (lds > 65536 && lds > lds_set) {
-    IPEPS_HIP(hipFuncSetAttribute((const void*)sym_eig_jacobi_kernel,
+  const bool vlds = b <= 96;
+  size_t lds = (size_t)b * b * sizeof(double) + 2 * (b / 2) * sizeof(double) +
+               2 * ((b / 2) + (b / 2) % 2) * sizeof(int);
+  if (vlds) lds += (size_t)b * b * sizeof(double);
+  static size_t lds_set[2] = {0, 0};
+  const void* fn = vlds ? (const void*)sym_eig_jacobi_kernel<true>
+                        : (const void*)sym_eig_jacobi_kernel<false>;
+  if (lds > 65536 && lds > lds_set[vlds]) {
+    IPEPS_HIP(hipFuncSetAttribute(fn,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds));
-    lds_set = lds;
+    lds_set[vlds] = lds;
   }
   if (dev.prof.on) dev.prof.begin(dev.stream, PROF_JACOBI, 0.0, 0.0);
-  hipLaunchKernelGGL(sym_eig_jacobi_kernel, dim3(batch), dim3(JAC_THREADS),
-                     lds, dev.stream, G, V, lam, b);
+  if (vlds)
+    hipLaunchKernelGGL(sym_eig_jacobi_kernel<true>, dim3(batch),
+                       dim3(JAC_THREADS), lds, dev.stream, G, V, lam, b);
+  else
+    hipLaunchKernelGGL(sym_eig_jacobi_kernel<false>, dim3(batch),
+                       dim3(JAC_THREADS), lds, dev.stream, G, V, lam, b);
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
 }
@@ -819,58 +832,88 @@ void normalize_backward(Device& dev, int64_t len, const double* y,
 namespace ipeps {
 
 // ---------------------------------------------- projector backward helpers
-// out[j] = sum_i X[i*m + j] * Y[i*m + j]  (one wave per column)
-__global__ void coldot_kernel(const double* __restrict__ X,
-                              const double* __restrict__ Y, int64_t n, int m,
-                              double* __restrict__ out) {
-  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (j >= m) return;
+// out[j] = sum_i X[i*m + j] * Y[i*m + j].  Stage 1: workgroup (cx, ry)
+// sweeps rows ry, ry + R, ... for the 64 columns of chunk cx with coalesced
+// row reads (4 rows in flight per workgroup) and writes one partial per
+// column; stage 2 adds the R partials in a fixed order.
+constexpr int CD_R = 32;
+
+__global__ __launch_bounds__(256) void coldot_partial_kernel(
+    const double* __restrict__ X, const double* __restrict__ Y, int64_t n,
+    int m, double* __restrict__ part, long sXY) {
+  __shared__ double red[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int r0 = threadIdx.x >> 6;
+  X += blockIdx.z * sXY;
+  Y += blockIdx.z * sXY;
   double v = 0.0;
-  for (int64_t i = lane; i < n; i += 64) v += X[i * m + j] * Y[i * m + j];
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  if (lane == 0) out[j] = v;
+  if (c < m)
+    for (int64_t i = blockIdx.y * 4 + r0; i < n; i += 4 * CD_R)
+      v += X[i * m + c] * Y[i * m + c];
+  red[r0][threadIdx.x & 63] = v;
+  __syncthreads();
+  if (threadIdx.x < 64 && c < m)
+    part[((long)blockIdx.z * CD_R + blockIdx.y) * m + c] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+        red[3][threadIdx.x];
+}
+
+__global__ void coldot_final_kernel(const double* __restrict__ part, int m,
+                                    double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  const double* p = part + (long)blockIdx.y * CD_R * m;
+  double v = 0.0;
+  for (int r = 0; r < CD_R; ++r) v += p[r * m + c];
+  out[(long)blockIdx.y * m + c] = v;
 }
 
 void coldot(Device& dev, const double* X, const double* Y, int64_t n, int m,
-            double* out) {
-  hipLaunchKernelGGL(coldot_kernel, dim3((m + 3) / 4), dim3(256), 0,
-                     dev.stream, X, Y, n, m, out);
+            double* out, int batch, int64_t sXY) {
+  Tensor part = dev.empty({batch, CD_R, m});
+  hipLaunchKernelGGL(coldot_partial_kernel, dim3((m + 63) / 64, CD_R, batch),
+                     dim3(256), 0, dev.stream, X, Y, n, m, part.ptr,
+                     (long)sXY);
+  hipLaunchKernelGGL(coldot_final_kernel, dim3((m + 127) / 128, batch),
+                     dim3(128), 0, dev.stream, part.ptr, m, out);
   IPEPS_HIP(hipGetLastError());
 }
 
 // w[j] = s_j^-1/2 for j < keep (and s_j > 0), else 0; j < chi.
 __global__ void proj_weights_kernel(const double* S, const int* keep, int chi,
-                                    double* w) {
-  const int j = threadIdx.x + blockIdx.x * blockDim.x;
+                                    double* w, int sS) {
+  const int j = threadIdx.x + blockIdx.x * blockDim.x, bt = blockIdx.y;
   if (j >= chi) return;
-  const double s = S[j];
-  w[j] = (j < keep[0] && s > 0.0) ? 1.0 / sqrt(s) : 0.0;
+  const double s = S[bt * sS + j];
+  w[bt * chi + j] = (j < keep[bt] && s > 0.0) ? 1.0 / sqrt(s) : 0.0;
 }
 
 void proj_weights(Device& dev, const double* S, const int* keep, int chi,
-                  double* w) {
-  hipLaunchKernelGGL(proj_weights_kernel, dim3((chi + 127) / 128), dim3(128),
-                     0, dev.stream, S, keep, chi, w);
+                  double* w, int batch, int sS) {
+  hipLaunchKernelGGL(proj_weights_kernel, dim3((chi + 127) / 128, batch),
+                     dim3(128), 0, dev.stream, S, keep, chi, w, sS);
   IPEPS_HIP(hipGetLastError());
 }
 
 // sbar[j] = -1/2 s_j^-3/2 (wbar1[j] + wbar2[j]) for j < keep, else 0
 __global__ void proj_sbar_kernel(const double* S, const int* keep, int chi,
                                  const double* wb1, const double* wb2,
-                                 double* sbar) {
-  const int j = threadIdx.x + blockIdx.x * blockDim.x;
+                                 double* sbar, int sS) {
+  const int j = threadIdx.x + blockIdx.x * blockDim.x, bt = blockIdx.y;
   if (j >= chi) return;
-  const double s = S[j];
-  sbar[j] = (j < keep[0] && s > 0.0)
-                ? -0.5 * (wb1[j] + wb2[j]) / (s * sqrt(s))
+  const double s = S[bt * sS + j];
+  const int o = bt * chi + j;
+  sbar[o] = (j < keep[bt] && s > 0.0)
+                ? -0.5 * (wb1[o] + wb2[o]) / (s * sqrt(s))
                 : 0.0;
 }
 
 void proj_sbar(Device& dev, const double* S, const int* keep, int chi,
-               const double* wb1, const double* wb2, double* sbar) {
-  hipLaunchKernelGGL(proj_sbar_kernel, dim3((chi + 127) / 128), dim3(128), 0,
-                     dev.stream, S, keep, chi, wb1, wb2, sbar);
+               const double* wb1, const double* wb2, double* sbar, int batch,
+               int sS) {
+  hipLaunchKernelGGL(proj_sbar_kernel, dim3((chi + 127) / 128, batch),
+                     dim3(128), 0, dev.stream, S, keep, chi, wb1, wb2, sbar,
+                     sS);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -879,8 +922,15 @@ void proj_sbar(Device& dev, const double* S, const int* keep, int chi,
 // F_ij = x/(x^2 + eta^2), x = s_j^2 - s_i^2, eta = 1e-12 s_0^2, F_ii = 0.
 __global__ void svd_gkk_kernel(const double* Au, const double* Av,
                                const double* S, const double* sbar,
-                               const int* keep, int chi, double* G) {
-  const int k = keep[0];
+                               const int* keep, int chi, double* G, int sS) {
+  const int bt = blockIdx.y;
+  const long off = (long)bt * chi * chi;
+  Au += off;
+  Av += off;
+  G += off;
+  S += (long)bt * sS;
+  sbar += (long)bt * chi;
+  const int k = keep[bt];
   const double eta = 1e-12 * S[0] * S[0];
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < chi * chi;
        e += gridDim.x * blockDim.x) {
@@ -902,24 +952,29 @@ __global__ void svd_gkk_kernel(const double* Au, const double* Av,
 }
 
 void svd_gkk(Device& dev, const double* Au, const double* Av, const double* S,
-             const double* sbar, const int* keep, int chi, double* G) {
-  hipLaunchKernelGGL(svd_gkk_kernel, dim3(grid_for((int64_t)chi * chi, 256)),
-                     dim3(256), 0, dev.stream, Au, Av, S, sbar, keep, chi, G);
+             const double* sbar, const int* keep, int chi, double* G,
+             int batch, int sS) {
+  hipLaunchKernelGGL(svd_gkk_kernel,
+                     dim3(grid_for((int64_t)chi * chi, 256), batch),
+                     dim3(256), 0, dev.stream, Au, Av, S, sbar, keep, chi, G,
+                     sS);
   IPEPS_HIP(hipGetLastError());
 }
 
 // X (n x m) columns j >= keep set to zero
 __global__ void mask_cols_kernel(double* X, int64_t n, int m,
                                  const int* keep) {
-  const int k = keep[0];
+  const int k = keep[blockIdx.y];
+  X += (long)blockIdx.y * n * m;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * m;
        e += (int64_t)gridDim.x * blockDim.x)
     if ((int)(e % m) >= k) X[e] = 0.0;
 }
 
-void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep) {
-  hipLaunchKernelGGL(mask_cols_kernel, dim3(grid_for(n * m, 256)), dim3(256),
-                     0, dev.stream, X, n, m, keep);
+void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep,
+               int batch) {
+  hipLaunchKernelGGL(mask_cols_kernel, dim3(grid_for(n * m, 256), batch),
+                     dim3(256), 0, dev.stream, X, n, m, keep);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -929,10 +984,10 @@ void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep) {
 //   mode 1: p = r + (rrn_j / rr_j) p  (beta 0 when rr_j == 0)
 __global__ void colcg_kernel(int mode, int64_t rows, int m, const double* rr,
                              const double* den, double* x, double* r,
-                             double* p, const double* Ap) {
+                             double* p, const double* Ap, int64_t rpb) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
        e < rows * m; e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e % m);
+    const int64_t j = (e / (rpb * m)) * m + e % m;
     if (mode == 0) {
       const double a = (den[j] > 0.0 && rr[j] > 0.0) ? rr[j] / den[j] : 0.0;
       x[e] += a * p[e];
@@ -946,18 +1001,20 @@ __global__ void colcg_kernel(int mode, int64_t rows, int m, const double* rr,
 
 void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
            const double* den, double* x, double* r, double* p,
-           const double* Ap) {
+           const double* Ap, int64_t rows_per_batch) {
   hipLaunchKernelGGL(colcg_kernel, dim3(grid_for(rows * m, 256)), dim3(256),
-                     0, dev.stream, mode, rows, m, rr, den, x, r, p, Ap);
+                     0, dev.stream, mode, rows, m, rr, den, x, r, p, Ap,
+                     rows_per_batch > 0 ? rows_per_batch : rows);
   IPEPS_HIP(hipGetLastError());
 }
 
 // y[i][j] = a * s_j * x[i][j] + b * y[i][j]   (column-scaled axpby)
 __global__ void col_axpby_kernel(int64_t n, int m, double a, const double* s,
-                                 const double* x, double b, double* y) {
+                                 const double* x, double b, double* y,
+                                 int64_t rpb, int64_t sS) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * m;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const double sj = s ? s[e % m] : 1.0;
+    const double sj = s ? s[(e / (rpb * m)) * sS + e % m] : 1.0;
     double v = a * sj * x[e];
     if (b != 0.0) v += b * y[e];
     y[e] = v;
@@ -965,9 +1022,11 @@ __global__ void col_axpby_kernel(int64_t n, int m, double a, const double* s,
 }
 
 void col_axpby(Device& dev, int64_t n, int m, double a, const double* s,
-               const double* x, double b, double* y) {
+               const double* x, double b, double* y, int64_t rows_per_batch,
+               int64_t sS) {
   hipLaunchKernelGGL(col_axpby_kernel, dim3(grid_for(n * m, 256)), dim3(256),
-                     0, dev.stream, n, m, a, s, x, b, y);
+                     0, dev.stream, n, m, a, s, x, b, y,
+                     rows_per_batch > 0 ? rows_per_batch : n, sS);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -977,7 +1036,10 @@ namespace ipeps {
 
 // dst[r*ldd + c] = src[r*lds + c], rows x cols
 __global__ void copy2d_kernel(const double* src, int64_t lds, double* dst,
-                              int64_t ldd, int64_t rows, int64_t cols) {
+                              int64_t ldd, int64_t rows, int64_t cols,
+                              int64_t sSrc, int64_t sDst) {
+  src += blockIdx.y * sSrc;
+  dst += blockIdx.y * sDst;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
        e < rows * cols; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / cols, c = e % cols;
@@ -986,9 +1048,11 @@ __global__ void copy2d_kernel(const double* src, int64_t lds, double* dst,
 }
 
 void copy2d(Device& dev, const double* src, int64_t lds, double* dst,
-            int64_t ldd, int64_t rows, int64_t cols) {
-  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(rows * cols, 256)),
-                     dim3(256), 0, dev.stream, src, lds, dst, ldd, rows, cols);
+            int64_t ldd, int64_t rows, int64_t cols, int batch, int64_t sSrc,
+            int64_t sDst) {
+  hipLaunchKernelGGL(copy2d_kernel, dim3(grid_for(rows * cols, 256), batch),
+                     dim3(256), 0, dev.stream, src, lds, dst, ldd, rows, cols,
+                     sSrc, sDst);
   IPEPS_HIP(hipGetLastError());
 }
 

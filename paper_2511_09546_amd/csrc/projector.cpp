@@ -12,9 +12,13 @@
 //   vectors (P_D = 1 - U_k U_k^T, P'_D = 1 - V_k V_k^T), which is
 //   symmetric positive definite there (eigenvalues s_j +- s_i, i discarded)
 //   and solved by column-wise CG with M applied as Qa (Qb x).  This equals
-//   the full-spectrum formula sum over discarded i of
-//   1/(s_j^2 - s_i^2) terms without forming the discarded vectors.
+//   the full-spectrum formula (sum over discarded i of 1/(s_j^2 - s_i^2)
+//   terms) without forming the discarded vectors.
 // Finally Qa_bar += M_bar Qb^T, Qb_bar += Qa^T M_bar in low-rank form.
+//
+// All cuts of one CTMRG iteration are processed together: every product of
+// a cut matrix is one batched launch over the cuts (pointer arrays), every
+// chi-wide block operation one strided batched launch.
 #include <algorithm>
 #include <cmath>
 
@@ -23,90 +27,23 @@
 
 namespace ipeps {
 
-void copy2d(Device& dev, const double* src, int64_t lds, double* dst,
-            int64_t ldd, int64_t rows, int64_t cols);
-
 namespace {
 
-// y <- y - Q (Q^T y), Q and y n x m
-void project_out(Device& dev, const double* Q, double* y, int64_t n, int m) {
-  Tensor t = dev.empty({m, m});
-  gemm(dev, true, false, m, m, n, 1.0, Q, m, 0, y, m, 0, 0.0, t.ptr, m, 0);
-  gemm(dev, false, false, n, m, m, -1.0, Q, m, 0, t.ptr, m, 0, 1.0, y, m, 0);
+// y[i] <- y[i] - Q[i] (Q[i]^T y[i]); Q, y: batch x n x m, strides sQ, sY
+void project_out(Device& dev, const double* Q, int64_t sQ, double* y,
+                 int64_t sY, int64_t n, int m, int batch) {
+  Tensor t = dev.empty({batch, m, m});
+  gemm(dev, true, false, m, m, n, 1.0, Q, m, sQ, y, m, sY, 0.0, t.ptr, m,
+       (int64_t)m * m, batch);
+  gemm(dev, false, false, n, m, m, -1.0, Q, m, sQ, t.ptr, m, (int64_t)m * m,
+       1.0, y, m, sY, batch);
 }
 
-struct CutData {
-  const double *Qa, *Qb;
-  const double *U, *V, *S;  // U, V: n x b (ld b); S: b
-  const int* keep;
-  const double* w;          // chi
-  const double *QbV, *QaU;  // n x chi unscaled
-};
-
-// Solve the complement system for all kept columns; returns [2][n][chi].
-Tensor complement_solve(Device& dev, const CutData& cd, int64_t n, int chi,
-                        int b, const Tensor& Ukm, const Tensor& Vkm,
-                        const Tensor& rhs, SvdStats* st) {
-  const int64_t rows = 2 * n;
-  Tensor X = dev.zeros({2, n, chi});
-  Tensor R = dev.empty({2, n, chi});
-  Tensor Pp = dev.empty({2, n, chi});
-  Tensor AP = dev.empty({2, n, chi});
-  Tensor t1 = dev.empty({n, chi});
-  Tensor sc = dev.empty({4, chi});  // rr, pAp, rr_new, rr0
-  Tensor Sk = dev.empty({chi});
-  // singular values as a column scale (first chi of the b values)
-  axpby(dev, chi, 1.0, cd.S, 0.0, Sk.ptr);
-  axpby(dev, rows * chi, 1.0, rhs.ptr, 0.0, R.ptr);
-  axpby(dev, rows * chi, 1.0, rhs.ptr, 0.0, Pp.ptr);
-  coldot(dev, R.ptr, R.ptr, rows, chi, sc.ptr);
-  axpby(dev, chi, 1.0, sc.ptr, 0.0, sc.ptr + 3 * chi);
-  std::vector<double> h(4 * chi);
-  const double tol2 = 1e-24;
-  int it = 0;
-  const int max_it = 600;
-  for (; it < max_it; ++it) {
-    double* pc = Pp.ptr;
-    double* pb = Pp.ptr + n * chi;
-    double* ac = AP.ptr;
-    double* ab = AP.ptr + n * chi;
-    // ac = s p_c - P_D M p_b
-    gemm(dev, false, false, n, chi, n, 1.0, cd.Qb, n, 0, pb, chi, 0, 0.0,
-         t1.ptr, chi, 0);
-    gemm(dev, false, false, n, chi, n, 1.0, cd.Qa, n, 0, t1.ptr, chi, 0, 0.0,
-         ac, chi, 0);
-    project_out(dev, Ukm.ptr, ac, n, chi);
-    col_axpby(dev, n, chi, 1.0, Sk.ptr, pc, -1.0, ac);
-    // ab = s p_b - P'_D M^T p_c
-    gemm(dev, true, false, n, chi, n, 1.0, cd.Qa, n, 0, pc, chi, 0, 0.0,
-         t1.ptr, chi, 0);
-    gemm(dev, true, false, n, chi, n, 1.0, cd.Qb, n, 0, t1.ptr, chi, 0, 0.0,
-         ab, chi, 0);
-    project_out(dev, Vkm.ptr, ab, n, chi);
-    col_axpby(dev, n, chi, 1.0, Sk.ptr, pb, -1.0, ab);
-    coldot(dev, Pp.ptr, AP.ptr, rows, chi, sc.ptr + chi);
-    colcg(dev, 0, rows, chi, sc.ptr, sc.ptr + chi, X.ptr, R.ptr, Pp.ptr,
-          AP.ptr);
-    coldot(dev, R.ptr, R.ptr, rows, chi, sc.ptr + 2 * chi);
-    colcg(dev, 1, rows, chi, sc.ptr, sc.ptr + 2 * chi, X.ptr, R.ptr, Pp.ptr,
-          AP.ptr);
-    axpby(dev, chi, 1.0, sc.ptr + 2 * chi, 0.0, sc.ptr);
-    if ((it + 1) % 4 == 0) {
-      dev.download(sc, h.data());
-      bool done = true;
-      for (int j = 0; j < chi; ++j)
-        if (h[3 * chi + j] > 0.0 && h[j] > tol2 * h[3 * chi + j]) done = false;
-      if (done) {
-        ++it;
-        break;
-      }
-    }
-  }
-  if (st) {
-    st->cg_iters += it;
-    st->cg_solves += 1;
-  }
-  return X;
+template <class T>
+std::vector<T> offsets(T base, int64_t stride, int count) {
+  std::vector<T> v(count);
+  for (int i = 0; i < count; ++i) v[i] = base + i * stride;
+  return v;
 }
 
 }  // namespace
@@ -116,7 +53,7 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const std::vector<Var>& Qb) {
   Device& dev = tp.dev;
   const int nc = (int)Qa.size(), chi = cx.chi, b = cx.b;
-  const int64_t n = cx.n, sUV = n * b;
+  const int64_t n = cx.n, sUV = n * b, sP = n * chi;
   CutBatch cb;
   cb.ncut = nc;
   cb.n = n;
@@ -130,119 +67,201 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
   projector_svd(dev, cb, cx.Xwarm, cx.have_warm, U, S, V, keep, cx.svd,
                 &cx.stats);
   cx.have_warm = true;
-  Tensor w = dev.empty({nc, chi});
-  Tensor QbV = dev.empty({nc, n, chi}), QaU = dev.empty({nc, n, chi});
-  std::vector<Var> P(nc), PtT(nc);
   const int* kp = (const int*)keep.ptr;
-  for (int i = 0; i < nc; ++i) {
-    proj_weights(dev, S.ptr + i * b, kp + i, chi, w.ptr + i * chi);
-    gemm(dev, false, false, n, chi, n, 1.0, cb.Qb[i], n, 0, V.ptr + i * sUV,
-         b, 0, 0.0, QbV.ptr + i * n * chi, chi, 0);
-    gemm(dev, true, false, n, chi, n, 1.0, cb.Qa[i], n, 0, U.ptr + i * sUV, b,
-         0, 0.0, QaU.ptr + i * n * chi, chi, 0);
-    Tensor Pi = dev.empty({n, chi}), Ti = dev.empty({n, chi});
-    col_axpby(dev, n, chi, 1.0, w.ptr + i * chi, QbV.ptr + i * n * chi, 0.0,
-              Pi.ptr);
-    col_axpby(dev, n, chi, 1.0, w.ptr + i * chi, QaU.ptr + i * n * chi, 0.0,
-              Ti.ptr);
-    P[i] = tp.leaf(Pi, false);
-    PtT[i] = tp.leaf(Ti, false);
-    P[i]->req = PtT[i]->req = tp.rec && (Qa[i]->req || Qb[i]->req);
-  }
+  Tensor w = dev.empty({nc, chi});
+  proj_weights(dev, S.ptr, kp, chi, w.ptr, nc, b);
+  Tensor QbV = dev.empty({nc, n, chi}), QaU = dev.empty({nc, n, chi});
+  gemm_ptrs(dev, false, false, n, chi, n, 1.0, cb.Qb, n,
+            offsets<const double*>(V.ptr, sUV, nc), b, 0.0,
+            offsets<double*>(QbV.ptr, sP, nc), chi);
+  gemm_ptrs(dev, true, false, n, chi, n, 1.0, cb.Qa, n,
+            offsets<const double*>(U.ptr, sUV, nc), b, 0.0,
+            offsets<double*>(QaU.ptr, sP, nc), chi);
+  Tensor Pall = dev.empty({nc, n, chi}), Tall = dev.empty({nc, n, chi});
+  col_axpby(dev, nc * n, chi, 1.0, w.ptr, QbV.ptr, 0.0, Pall.ptr, n, chi);
+  col_axpby(dev, nc * n, chi, 1.0, w.ptr, QaU.ptr, 0.0, Tall.ptr, n, chi);
+  std::vector<Var> P(nc), PtT(nc);
   bool any = false;
-  for (int i = 0; i < nc; ++i) any = any || P[i]->req;
+  for (int i = 0; i < nc; ++i) {
+    P[i] = tp.leaf(Pall.slice0(i), false);
+    PtT[i] = tp.leaf(Tall.slice0(i), false);
+    P[i]->req = PtT[i]->req = tp.rec && (Qa[i]->req || Qb[i]->req);
+    any = any || P[i]->req;
+  }
   if (!any) return {P, PtT};
   SvdStats* st = &cx.stats;
   tp.push([&tp, Qa, Qb, P, PtT, U, S, V, keep, w, QbV, QaU, n, chi, b, nc,
            st]() {
     Device& dev = tp.dev;
-    const int64_t sUV = n * b;
+    const int64_t sUV = n * b, sP = n * chi, s2 = 2 * n * chi;
+    const int64_t sG = (int64_t)chi * chi;
     const int* kp = (const int*)keep.ptr;
+    bool anyg = false;
+    for (int i = 0; i < nc; ++i)
+      anyg = anyg || tp.has_grad(P[i]) || tp.has_grad(PtT[i]);
+    if (!anyg) return;
+    std::vector<const double*> qa(nc), qb(nc), ui(nc), vi(nc);
+    std::vector<double*> gqa, gqb;
+    std::vector<int> ia, ib;
     for (int i = 0; i < nc; ++i) {
-      const bool hp = tp.has_grad(P[i]), ht = tp.has_grad(PtT[i]);
-      if (!hp && !ht) continue;
-      CutData cd;
-      cd.Qa = Qa[i]->v.ptr;
-      cd.Qb = Qb[i]->v.ptr;
-      cd.U = U.ptr + i * sUV;
-      cd.V = V.ptr + i * sUV;
-      cd.S = S.ptr + i * b;
-      cd.keep = kp + i;
-      cd.w = w.ptr + i * chi;
-      cd.QbV = QbV.ptr + i * n * chi;
-      cd.QaU = QaU.ptr + i * n * chi;
-      Tensor Pb = hp ? P[i]->g : dev.zeros({n, chi});
-      Tensor Tb = ht ? PtT[i]->g : dev.zeros({n, chi});
-      Tensor Pbw = dev.empty({n, chi}), Tbw = dev.empty({n, chi});
-      col_axpby(dev, n, chi, 1.0, cd.w, Pb.ptr, 0.0, Pbw.ptr);
-      col_axpby(dev, n, chi, 1.0, cd.w, Tb.ptr, 0.0, Tbw.ptr);
-      double* gQa = Qa[i]->req ? tp.grad(Qa[i]).ptr : nullptr;
-      double* gQb = Qb[i]->req ? tp.grad(Qb[i]).ptr : nullptr;
-      // direct terms of P = Qb V w and Pt^T = Qa^T U w
-      if (gQb)
-        gemm(dev, false, true, n, n, chi, 1.0, Pbw.ptr, chi, 0, cd.V, b, 0,
-             1.0, gQb, n, 0);
-      if (gQa)
-        gemm(dev, false, true, n, n, chi, 1.0, cd.U, b, 0, Tbw.ptr, chi, 0,
-             1.0, gQa, n, 0);
-      // s_bar through w = s^-1/2
-      Tensor wb = dev.empty({3, chi});
-      coldot(dev, cd.QbV, Pb.ptr, n, chi, wb.ptr);
-      coldot(dev, cd.QaU, Tb.ptr, n, chi, wb.ptr + chi);
-      proj_sbar(dev, cd.S, cd.keep, chi, wb.ptr, wb.ptr + chi,
-                wb.ptr + 2 * chi);
-      // U_bar, V_bar (columns >= k vanish with w)
-      Tensor Vb = dev.empty({n, chi}), Ub = dev.empty({n, chi});
-      gemm(dev, true, false, n, chi, n, 1.0, cd.Qb, n, 0, Pbw.ptr, chi, 0,
-           0.0, Vb.ptr, chi, 0);
-      gemm(dev, false, false, n, chi, n, 1.0, cd.Qa, n, 0, Tbw.ptr, chi, 0,
-           0.0, Ub.ptr, chi, 0);
-      // kept block
-      Tensor Au = dev.empty({chi, chi}), Av = dev.empty({chi, chi}),
-             Gkk = dev.empty({chi, chi});
-      gemm(dev, true, false, chi, chi, n, 1.0, cd.U, b, 0, Ub.ptr, chi, 0,
-           0.0, Au.ptr, chi, 0);
-      gemm(dev, true, false, chi, chi, n, 1.0, cd.V, b, 0, Vb.ptr, chi, 0,
-           0.0, Av.ptr, chi, 0);
-      svd_gkk(dev, Au.ptr, Av.ptr, cd.S, wb.ptr + 2 * chi, cd.keep, chi,
-              Gkk.ptr);
-      // complement right-hand side [P_D U_bar; P'_D V_bar]
-      Tensor Ukm = dev.empty({n, chi}), Vkm = dev.empty({n, chi});
-      copy2d(dev, cd.U, b, Ukm.ptr, chi, n, chi);
-      copy2d(dev, cd.V, b, Vkm.ptr, chi, n, chi);
-      mask_cols(dev, Ukm.ptr, n, chi, cd.keep);
-      mask_cols(dev, Vkm.ptr, n, chi, cd.keep);
-      Tensor rhs = dev.empty({2, n, chi});
-      axpby(dev, n * chi, 1.0, Ub.ptr, 0.0, rhs.ptr);
-      axpby(dev, n * chi, 1.0, Vb.ptr, 0.0, rhs.ptr + n * chi);
-      project_out(dev, Ukm.ptr, rhs.ptr, n, chi);
-      project_out(dev, Vkm.ptr, rhs.ptr + n * chi, n, chi);
-      Tensor cbv = complement_solve(dev, cd, n, chi, b, Ukm, Vkm, rhs, st);
-      // B = V Gkk^T + b_part, C = c_part
-      Tensor Bm = dev.empty({n, chi});
-      axpby(dev, n * chi, 1.0, cbv.ptr + n * chi, 0.0, Bm.ptr);
-      gemm(dev, false, true, n, chi, chi, 1.0, cd.V, b, 0, Gkk.ptr, chi, 0,
-           1.0, Bm.ptr, chi, 0);
-      const double* Cm = cbv.ptr;
-      Tensor t1 = dev.empty({n, chi});
-      if (gQa) {
-        // Qa_bar += U (Qb B)^T + C (Qb V)^T
-        gemm(dev, false, false, n, chi, n, 1.0, cd.Qb, n, 0, Bm.ptr, chi, 0,
-             0.0, t1.ptr, chi, 0);
-        gemm(dev, false, true, n, n, chi, 1.0, cd.U, b, 0, t1.ptr, chi, 0,
-             1.0, gQa, n, 0);
-        gemm(dev, false, true, n, n, chi, 1.0, Cm, chi, 0, cd.QbV, chi, 0,
-             1.0, gQa, n, 0);
+      qa[i] = Qa[i]->v.ptr;
+      qb[i] = Qb[i]->v.ptr;
+      ui[i] = U.ptr + i * sUV;
+      vi[i] = V.ptr + i * sUV;
+      if (Qa[i]->req) {
+        gqa.push_back(tp.grad(Qa[i]).ptr);
+        ia.push_back(i);
       }
-      if (gQb) {
-        // Qb_bar += (Qa^T U) B^T + (Qa^T C) V^T
-        gemm(dev, false, true, n, n, chi, 1.0, cd.QaU, chi, 0, Bm.ptr, chi,
-             0, 1.0, gQb, n, 0);
-        gemm(dev, true, false, n, chi, n, 1.0, cd.Qa, n, 0, Cm, chi, 0, 0.0,
-             t1.ptr, chi, 0);
-        gemm(dev, false, true, n, n, chi, 1.0, t1.ptr, chi, 0, cd.V, b, 0,
-             1.0, gQb, n, 0);
+      if (Qb[i]->req) {
+        gqb.push_back(tp.grad(Qb[i]).ptr);
+        ib.push_back(i);
       }
+    }
+    auto pick = [](const std::vector<const double*>& v,
+                   const std::vector<int>& idx) {
+      std::vector<const double*> r;
+      for (int i : idx) r.push_back(v[i]);
+      return r;
+    };
+    // gather the cotangents (zeros where none arrived)
+    Tensor Pb = dev.zeros({nc, n, chi}), Tb = dev.zeros({nc, n, chi});
+    for (int i = 0; i < nc; ++i) {
+      if (tp.has_grad(P[i]))
+        axpby(dev, sP, 1.0, P[i]->g.ptr, 0.0, Pb.ptr + i * sP);
+      if (tp.has_grad(PtT[i]))
+        axpby(dev, sP, 1.0, PtT[i]->g.ptr, 0.0, Tb.ptr + i * sP);
+    }
+    Tensor Pbw = dev.empty({nc, n, chi}), Tbw = dev.empty({nc, n, chi});
+    col_axpby(dev, nc * n, chi, 1.0, w.ptr, Pb.ptr, 0.0, Pbw.ptr, n, chi);
+    col_axpby(dev, nc * n, chi, 1.0, w.ptr, Tb.ptr, 0.0, Tbw.ptr, n, chi);
+    const auto pbw = offsets<const double*>(Pbw.ptr, sP, nc);
+    const auto tbw = offsets<const double*>(Tbw.ptr, sP, nc);
+    // direct terms of P = Qb V w and Pt^T = Qa^T U w
+    if (!gqb.empty())
+      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(pbw, ib), chi,
+                pick(vi, ib), b, 1.0, gqb, n);
+    if (!gqa.empty())
+      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(ui, ia), b,
+                pick(tbw, ia), chi, 1.0, gqa, n);
+    // s_bar through w = s^-1/2
+    Tensor wb = dev.empty({3, nc, chi});
+    coldot(dev, QbV.ptr, Pb.ptr, n, chi, wb.ptr, nc, sP);
+    coldot(dev, QaU.ptr, Tb.ptr, n, chi, wb.ptr + nc * chi, nc, sP);
+    double* sbar = wb.ptr + 2 * nc * chi;
+    proj_sbar(dev, S.ptr, kp, chi, wb.ptr, wb.ptr + nc * chi, sbar, nc, b);
+    // U_bar, V_bar (columns >= k vanish with w)
+    Tensor Vb = dev.empty({nc, n, chi}), Ub = dev.empty({nc, n, chi});
+    gemm_ptrs(dev, true, false, n, chi, n, 1.0, qb, n, pbw, chi, 0.0,
+              offsets<double*>(Vb.ptr, sP, nc), chi);
+    gemm_ptrs(dev, false, false, n, chi, n, 1.0, qa, n, tbw, chi, 0.0,
+              offsets<double*>(Ub.ptr, sP, nc), chi);
+    // kept block
+    Tensor Au = dev.empty({nc, chi, chi}), Av = dev.empty({nc, chi, chi}),
+           Gkk = dev.empty({nc, chi, chi});
+    gemm(dev, true, false, chi, chi, n, 1.0, U.ptr, b, sUV, Ub.ptr, chi, sP,
+         0.0, Au.ptr, chi, sG, nc);
+    gemm(dev, true, false, chi, chi, n, 1.0, V.ptr, b, sUV, Vb.ptr, chi, sP,
+         0.0, Av.ptr, chi, sG, nc);
+    svd_gkk(dev, Au.ptr, Av.ptr, S.ptr, sbar, kp, chi, Gkk.ptr, nc, b);
+    // kept vectors as contiguous chi-wide blocks, columns >= k zeroed
+    Tensor Ukm = dev.empty({nc, n, chi}), Vkm = dev.empty({nc, n, chi});
+    copy2d(dev, U.ptr, b, Ukm.ptr, chi, n, chi, nc, sUV, sP);
+    copy2d(dev, V.ptr, b, Vkm.ptr, chi, n, chi, nc, sUV, sP);
+    mask_cols(dev, Ukm.ptr, n, chi, kp, nc);
+    mask_cols(dev, Vkm.ptr, n, chi, kp, nc);
+    // complement right-hand side [P_D U_bar; P'_D V_bar], [nc][2][n][chi]
+    Tensor rhs = dev.empty({nc, 2, n, chi});
+    copy2d(dev, Ub.ptr, chi, rhs.ptr, chi, n, chi, nc, sP, s2);
+    copy2d(dev, Vb.ptr, chi, rhs.ptr + sP, chi, n, chi, nc, sP, s2);
+    project_out(dev, Ukm.ptr, sP, rhs.ptr, s2, n, chi, nc);
+    project_out(dev, Vkm.ptr, sP, rhs.ptr + sP, s2, n, chi, nc);
+
+    // ---- column-wise CG on [[s, -M], [-M^T, s]] over all cuts at once
+    Tensor X = dev.zeros({nc, 2, n, chi}), R = dev.empty({nc, 2, n, chi});
+    Tensor Pp = dev.empty({nc, 2, n, chi}), AP = dev.empty({nc, 2, n, chi});
+    Tensor t1 = dev.empty({nc, n, chi});
+    Tensor sc = dev.empty({4, nc, chi});  // rr, pAp, rr_new, rr0
+    double *rr = sc.ptr, *pap = sc.ptr + nc * chi, *rrn = pap + nc * chi,
+           *rr0 = rrn + nc * chi;
+    const int64_t tot = nc * s2;
+    axpby(dev, tot, 1.0, rhs.ptr, 0.0, R.ptr);
+    axpby(dev, tot, 1.0, rhs.ptr, 0.0, Pp.ptr);
+    coldot(dev, R.ptr, R.ptr, 2 * n, chi, rr, nc, s2);
+    axpby(dev, nc * chi, 1.0, rr, 0.0, rr0);
+    const auto pc = offsets<const double*>(Pp.ptr, s2, nc);
+    const auto pb = offsets<const double*>(Pp.ptr + sP, s2, nc);
+    const auto ac = offsets<double*>(AP.ptr, s2, nc);
+    const auto ab = offsets<double*>(AP.ptr + sP, s2, nc);
+    const auto t1w = offsets<double*>(t1.ptr, sP, nc);
+    const auto t1r = offsets<const double*>(t1.ptr, sP, nc);
+    std::vector<double> h(4 * nc * chi);
+    const double tol2 = 1e-24;
+    const int max_it = 600;
+    int it = 0;
+    for (; it < max_it; ++it) {
+      // ac = s p_c - P_D M p_b
+      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qb, n, pb, chi, 0.0, t1w,
+                chi);
+      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qa, n, t1r, chi, 0.0, ac,
+                chi);
+      project_out(dev, Ukm.ptr, sP, AP.ptr, s2, n, chi, nc);
+      // ab = s p_b - P'_D M^T p_c
+      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qa, n, pc, chi, 0.0, t1w,
+                chi);
+      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qb, n, t1r, chi, 0.0, ab,
+                chi);
+      project_out(dev, Vkm.ptr, sP, AP.ptr + sP, s2, n, chi, nc);
+      // AP = s P - AP (columns scaled by their singular value)
+      col_axpby(dev, nc * 2 * n, chi, 1.0, S.ptr, Pp.ptr, -1.0, AP.ptr, 2 * n,
+                b);
+      coldot(dev, Pp.ptr, AP.ptr, 2 * n, chi, pap, nc, s2);
+      colcg(dev, 0, nc * 2 * n, chi, rr, pap, X.ptr, R.ptr, Pp.ptr, AP.ptr,
+            2 * n);
+      coldot(dev, R.ptr, R.ptr, 2 * n, chi, rrn, nc, s2);
+      colcg(dev, 1, nc * 2 * n, chi, rr, rrn, X.ptr, R.ptr, Pp.ptr, AP.ptr,
+            2 * n);
+      axpby(dev, nc * chi, 1.0, rrn, 0.0, rr);
+      if ((it + 1) % 4 == 0) {
+        dev.download(sc, h.data());
+        bool done = true;
+        const double* hr = h.data();
+        const double* h0 = h.data() + 3 * nc * chi;
+        for (int j = 0; j < nc * chi; ++j)
+          if (h0[j] > 0.0 && hr[j] > tol2 * h0[j]) done = false;
+        if (done) {
+          ++it;
+          break;
+        }
+      }
+    }
+    st->cg_iters += it;
+    st->cg_solves += nc;
+    // B = V Gkk^T + b_part, C = c_part
+    Tensor Bm = dev.empty({nc, n, chi});
+    copy2d(dev, X.ptr + sP, chi, Bm.ptr, chi, n, chi, nc, s2, sP);
+    gemm(dev, false, true, n, chi, chi, 1.0, V.ptr, b, sUV, Gkk.ptr, chi, sG,
+         1.0, Bm.ptr, chi, sP, nc);
+    const auto bm = offsets<const double*>(Bm.ptr, sP, nc);
+    const auto cm = offsets<const double*>(X.ptr, s2, nc);
+    const auto qbv = offsets<const double*>(QbV.ptr, sP, nc);
+    const auto qau = offsets<const double*>(QaU.ptr, sP, nc);
+    if (!gqa.empty()) {
+      // Qa_bar += U (Qb B)^T + C (Qb V)^T
+      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qb, n, bm, chi, 0.0, t1w,
+                chi);
+      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(ui, ia), b,
+                pick(t1r, ia), chi, 1.0, gqa, n);
+      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(cm, ia), chi,
+                pick(qbv, ia), chi, 1.0, gqa, n);
+    }
+    if (!gqb.empty()) {
+      // Qb_bar += (Qa^T U) B^T + (Qa^T C) V^T
+      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(qau, ib), chi,
+                pick(bm, ib), chi, 1.0, gqb, n);
+      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qa, n, cm, chi, 0.0, t1w,
+                chi);
+      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(t1r, ib), chi,
+                pick(vi, ib), b, 1.0, gqb, n);
     }
   });
   return {P, PtT};

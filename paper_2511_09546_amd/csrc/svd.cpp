@@ -87,6 +87,17 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
     svd_ts(dev, X, nc, n, b, Uo, So, Jo);
     X = Uo;
   }
+  // per-cut block addresses of [nc][n][b] tensors
+  auto ptrs = [&](const Tensor& t) {
+    std::vector<double*> v(nc);
+    for (int c = 0; c < nc; ++c) v[c] = t.ptr + c * sX;
+    return v;
+  };
+  auto cptrs = [&](const Tensor& t) {
+    std::vector<const double*> v(nc);
+    for (int c = 0; c < nc; ++c) v[c] = t.ptr + c * sX;
+    return v;
+  };
   Tensor T1 = dev.empty({nc, n, b});
   Tensor W = dev.empty({nc, n, b});
   Tensor Z = dev.empty({nc, n, b});
@@ -98,22 +109,18 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
   double worst = 0.0;
   for (;;) {
     ++it;
-    for (int c = 0; c < nc; ++c) {
-      gemm(dev, false, false, n, b, n, 1.0, cb.Qb[c], n, 0, X.ptr + c * sX, b,
-           0, 0.0, T1.ptr + c * sX, b, 0);
-      gemm(dev, false, false, n, b, n, 1.0, cb.Qa[c], n, 0, T1.ptr + c * sX,
-           b, 0, 0.0, W.ptr + c * sX, b, 0);
-    }
+    gemm_ptrs(dev, false, false, n, b, n, 1.0, cb.Qb, n, cptrs(X), b, 0.0,
+              ptrs(T1), b);
+    gemm_ptrs(dev, false, false, n, b, n, 1.0, cb.Qa, n, cptrs(T1), b, 0.0,
+              ptrs(W), b);
     svd_ts(dev, W, nc, n, b, U, S, J);
     gemm(dev, false, false, n, b, b, 1.0, X.ptr, b, sX, J.ptr, b,
          (int64_t)b * b, 0.0, V.ptr, b, sX, nc);
     if (direct) break;
-    for (int c = 0; c < nc; ++c) {
-      gemm(dev, true, false, n, b, n, 1.0, cb.Qa[c], n, 0, U.ptr + c * sX, b,
-           0, 0.0, T1.ptr + c * sX, b, 0);
-      gemm(dev, true, false, n, b, n, 1.0, cb.Qb[c], n, 0, T1.ptr + c * sX,
-           b, 0, 0.0, Z.ptr + c * sX, b, 0);
-    }
+    gemm_ptrs(dev, true, false, n, b, n, 1.0, cb.Qa, n, cptrs(U), b, 0.0,
+              ptrs(T1), b);
+    gemm_ptrs(dev, true, false, n, b, n, 1.0, cb.Qb, n, cptrs(T1), b, 0.0,
+              ptrs(Z), b);
     svd_residual(dev, Z.ptr, V.ptr, S.ptr, n, b, std::min(cb.chi, b), res.ptr,
                  nc, sX, b);
     dev.download(res, hres.data());
