@@ -1,5 +1,6 @@
 // C ABI of the library (include/ipeps.h): argument checks, status codes,
 // host <-> device copies.  Every entry point catches all exceptions.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -156,8 +157,16 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
   Context& cx = c->cx;
   int it = 0;
   double dl = INFINITY;
+  const double svd_tol = cx.svd.tol;
   int st = guarded([&]() {
     while (it < max_iter) {
+      // when iterating to a tolerance, the projector SVD of an iteration
+      // only needs to be as accurate as the environment it produces: its
+      // tolerance follows the last spectrum change (never looser than 1e-6,
+      // never tighter than the configured one), so the final iterations and
+      // the fixed point are computed at full accuracy
+      if (tol > 0.0)
+        cx.svd.tol = std::max(svd_tol, std::min(1e-6, 1e-2 * dl));
       Env next;
       ctm_step(cx, cx.env, next);
       cx.env = next;
@@ -165,9 +174,11 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
       dl = corner_spectra_change(cx, cx.env);
       if (tol > 0.0 && dl < tol) break;
     }
+    cx.svd.tol = svd_tol;
     cx.converged_once = true;
     return IPEPS_OK;
   });
+  cx.svd.tol = svd_tol;
   if (st != IPEPS_OK) return st;
   if (n_iter) *n_iter = it;
   if (delta) *delta = dl;

@@ -280,7 +280,9 @@ void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
 // ------------------------------------------------------- Jacobi eigensolver
 // Parallel cyclic Jacobi (round-robin pairing, b-1 rounds of b/2 disjoint
 // rotations per sweep).  The rotation of pair (p,q) annihilates G[p][q]
-// (Golub & Van Loan, symmetric Schur 2x2); a pair is skipped when
+// (Golub & Van Loan, symmetric Schur 2x2): G_pq is set to zero and the two
+// diagonal entries take their closed forms G_pp - t G_pq, G_qq + t G_pq, so
+// no rounding noise re-creates the annihilated entry; a pair is skipped when
 // |G_pq| <= 1e-15 sqrt|G_pp G_qq| (relative criterion, so small eigenvalues
 // of graded matrices keep their relative accuracy).  Stops after a sweep
 // without rotations (or 40 sweeps).  G lives in LDS; the eigenvector matrix
@@ -297,7 +299,10 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
   double* G = lds;                  // b*b
   double* cs = G + b * b;           // b/2
   double* sn = cs + b / 2;          // b/2
-  int* pp = (int*)(sn + b / 2);     // b/2
+  double* dp = sn + b / 2;          // b/2: diagonal before the rotation
+  double* dq = dp + b / 2;          // b/2
+  double* tq = dq + b / 2;          // b/2: t * G_pq
+  int* pp = (int*)(tq + b / 2);     // b/2
   int* qq = pp + b / 2;             // b/2
   __shared__ int rotated;
   const int bt = blockIdx.x;
@@ -330,6 +335,8 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
         qq[i] = q;
         const double apq = G[p * b + q];
         const double app = G[p * b + p], aqq = G[q * b + q];
+        dp[i] = app;
+        dq[i] = aqq;
         double c = 1.0, s = 0.0;
         if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && apq != 0.0) {
           const double tau = (aqq - app) / (2.0 * apq);
@@ -341,6 +348,8 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
         }
         cs[i] = c;
         sn[i] = s;
+        // closed-form new diagonal; the (p,q) entry is annihilated exactly
+        tq[i] = s != 0.0 ? (s / c) * apq : 0.0;
       }
       __syncthreads();
       // rows: G <- J^T G
@@ -366,6 +375,15 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
         const double vp = V[k * b + p], vq = V[k * b + q];
         V[k * b + p] = c * vp - s * vq;
         V[k * b + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+      for (int i = tid; i < half; i += nt) {
+        if (sn[i] == 0.0) continue;
+        const int p = pp[i], q = qq[i];
+        G[p * b + q] = 0.0;
+        G[q * b + p] = 0.0;
+        G[p * b + p] = dp[i] - tq[i];
+        G[q * b + q] = dq[i] + tq[i];
       }
       __syncthreads();
     }
@@ -407,7 +425,7 @@ void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
   if (b % 2 != 0 || b < 2 || b > JAC_MAXB)
     throw ArgError("sym_eig_jacobi: b must be even and <= 128");
   const bool vlds = b <= 96;
-  size_t lds = (size_t)b * b * sizeof(double) + 2 * (b / 2) * sizeof(double) +
+  size_t lds = (size_t)b * b * sizeof(double) + 5 * (b / 2) * sizeof(double) +
                2 * ((b / 2) + (b / 2) % 2) * sizeof(int);
   if (vlds) lds += (size_t)b * b * sizeof(double);
   static size_t lds_set[2] = {0, 0};
@@ -536,40 +554,66 @@ void kept_rank(Device& dev, const double* S, int b, int chi, double cut,
 }
 
 // Residual of the top-k triplets: r[bt] = max_{i<k} ||Z_i - s_i V_i|| / s_0
-// (Z = M^T U), one workgroup per batch entry.
-__global__ void svd_residual_kernel(const double* Z, const double* V,
-                                    const double* S, int64_t n, int b, int k,
-                                    double* r, long sZ, long sS) {
-  const int bt = blockIdx.x;
+// (Z = M^T U).  Stage 1 sweeps rows with coalesced reads (64 columns per
+// workgroup, 32 row groups), stage 2 adds the partials per column in a fixed
+// order and takes the maximum.
+__global__ __launch_bounds__(256) void svd_residual_partial_kernel(
+    const double* __restrict__ Z, const double* __restrict__ V,
+    const double* __restrict__ S, int64_t n, int b, double* __restrict__ part,
+    long sZ, long sS) {
+  __shared__ double red[4][64];
+  const int bt = blockIdx.z;
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int r0 = threadIdx.x >> 6;
   const double* z = Z + bt * sZ;
   const double* v = V + bt * sZ;
-  const double* s = S + bt * sS;
-  __shared__ double red[64];
-  double worst = 0.0;
-  for (int j = 0; j < k; ++j) {
-    double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-      const double t = z[i * b + j] - s[j] * v[i * b + j];
+  double acc = 0.0;
+  if (c < b) {
+    const double sc = S[bt * sS + c];
+    for (int64_t i = blockIdx.y * 4 + r0; i < n; i += 4 * 32) {
+      const double t = z[i * b + c] - sc * v[i * b + c];
       acc += t * t;
     }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
-      worst = fmax(worst, sqrt(t));
-    }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) r[bt] = s[0] > 0.0 ? worst / s[0] : 0.0;
+  red[r0][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (threadIdx.x < 64 && c < b)
+    part[((long)bt * 32 + blockIdx.y) * b + c] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+        red[3][threadIdx.x];
+}
+
+__global__ void svd_residual_final_kernel(const double* __restrict__ part,
+                                          const double* __restrict__ S, int b,
+                                          int k, double* r, long sS) {
+  const int bt = blockIdx.x;
+  __shared__ double red[128];
+  double worst = 0.0;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double v = 0.0;
+    for (int g = 0; g < 32; ++g) v += part[((long)bt * 32 + g) * b + c];
+    worst = fmax(worst, sqrt(v));
+  }
+  red[threadIdx.x] = worst;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double w = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) w = fmax(w, red[i]);
+    const double s0 = S[bt * sS];
+    r[bt] = s0 > 0.0 ? w / s0 : 0.0;
+  }
 }
 
 void svd_residual(Device& dev, const double* Z, const double* V,
                   const double* S, int64_t n, int b, int k, double* r,
                   int batch, int64_t sZ, int64_t sS) {
-  hipLaunchKernelGGL(svd_residual_kernel, dim3(batch), dim3(256), 0,
-                     dev.stream, Z, V, S, n, b, k, r, (long)sZ, (long)sS);
+  Tensor part = dev.empty({batch, 32, b});
+  hipLaunchKernelGGL(svd_residual_partial_kernel,
+                     dim3((b + 63) / 64, 32, batch), dim3(256), 0,
+                     dev.stream, Z, V, S, n, b, part.ptr, (long)sZ,
+                     (long)sS);
+  hipLaunchKernelGGL(svd_residual_final_kernel, dim3(batch), dim3(128), 0,
+                     dev.stream, part.ptr, S, b, k, r, (long)sS);
   IPEPS_HIP(hipGetLastError());
 }
 
