@@ -142,6 +142,21 @@ int precond_apply(ipeps_ctx* ctx, const double* g, double delta,
                   double cg_tol, int cg_maxiter, double* x, int* n_iter,
                   double* rel_resid);
 
+/* Device-pointer twins of ctm_set_state, ipeps_energy_grad and
+ * precond_apply: identical semantics, but A, grad, g and x are device
+ * pointers (FP64, same layouts) that the caller keeps resident; no host
+ * copies of the site tensors.  The caller makes its device inputs ready
+ * before the call (e.g. synchronises the stream that wrote them); each call
+ * returns after its results are written (the context stream is
+ * synchronised).  Scalars (energy, iteration counts, residuals) still go to
+ * host pointers.  Non-finite device inputs are not detected. */
+int ctm_set_state_dev(ipeps_ctx* ctx, const double* d_A);
+int ipeps_energy_grad_dev(ipeps_ctx* ctx, int n_terms, const ipeps_term* terms,
+                          double* e_per_site, double* d_grad);
+int precond_apply_dev(ipeps_ctx* ctx, const double* d_g, double delta,
+                      double cg_tol, int cg_maxiter, double* d_x, int* n_iter,
+                      double* rel_resid);
+
 /* Sum-normalised singular values of every corner, out[4][Lx*Ly][chi] (host),
  * zero padded. Errors: EINVAL, EHIP. */
 int ipeps_corner_spectra(ipeps_ctx* ctx, double* out);

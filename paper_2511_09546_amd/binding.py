@@ -26,7 +26,8 @@ API_FUNCTIONS = [
     "ipeps_energy_grad", "precond_apply", "ipeps_corner_spectra",
     "ipeps_get_env", "ipeps_set_env", "ipeps_env_size", "ctm_free",
     "ipeps_strerror", "ipeps_version", "ipeps_profile_enable",
-    "ipeps_profile_read",
+    "ipeps_profile_read", "ctm_set_state_dev", "ipeps_energy_grad_dev",
+    "precond_apply_dev",
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE = 0, 1, 2
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
@@ -85,6 +86,11 @@ def load():
     lib.ipeps_strerror.argtypes = [c_int]
     lib.ipeps_strerror.restype = ctypes.c_char_p
     lib.ipeps_version.restype = ctypes.c_char_p
+    lib.ctm_set_state_dev.argtypes = [c_void_p, c_void_p]
+    lib.ipeps_energy_grad_dev.argtypes = [c_void_p, c_int, POINTER(Term),
+                                          _DP, c_void_p]
+    lib.precond_apply_dev.argtypes = [c_void_p, c_void_p, c_double,
+                                      c_double, c_int, c_void_p, _IP, _DP]
     lib.ipeps_profile_enable.argtypes = [c_void_p, c_int]
     lib.ipeps_profile_read.argtypes = [c_void_p, c_int,
                                        POINTER(ctypes.c_long), _DP, _DP, _DP]
@@ -98,6 +104,8 @@ def load():
                  "ipeps_energy_grad", "precond_apply", "ipeps_corner_spectra",
                  "ipeps_get_env", "ipeps_set_env", "ipeps_debug_gemm",
                  "ipeps_profile_enable", "ipeps_profile_read",
+                 "ctm_set_state_dev", "ipeps_energy_grad_dev",
+                 "precond_apply_dev",
                  "ipeps_debug_sym_eig", "ipeps_debug_svd_ts",
                  "ipeps_debug_stats"):
         getattr(lib, name).restype = c_int
@@ -210,6 +218,35 @@ class Context:
         if st < 0 and st != ECG_BREAKDOWN:
             raise IpepsError(st, "precond_apply")
         return x, n.value, rr.value, st == ECG_BREAKDOWN
+
+    # ---- device-pointer twins: arguments are device addresses (int) of
+    # FP64 buffers in the layout of A (e.g. torch_tensor.data_ptr())
+    def set_state_dev(self, d_A: int):
+        st = load().ctm_set_state_dev(self._h, c_void_p(d_A))
+        if st != OK:
+            raise IpepsError(st, "ctm_set_state_dev")
+
+    def energy_grad_dev(self, terms, d_grad: int) -> float:
+        arr, keep = make_terms(terms)
+        e = c_double(0.0)
+        st = load().ipeps_energy_grad_dev(self._h, len(terms), arr,
+                                          ctypes.byref(e), c_void_p(d_grad))
+        del keep
+        if st != OK:
+            raise IpepsError(st, "ipeps_energy_grad_dev")
+        return e.value
+
+    def precond_dev(self, d_g: int, d_x: int, delta: float, cg_tol: float,
+                    cg_maxiter: int):
+        """Returns (n_iter, rel_resid, breakdown)."""
+        n = c_int(0)
+        rr = c_double(0.0)
+        st = load().precond_apply_dev(self._h, c_void_p(d_g), delta, cg_tol,
+                                      cg_maxiter, c_void_p(d_x),
+                                      ctypes.byref(n), ctypes.byref(rr))
+        if st < 0 and st != ECG_BREAKDOWN:
+            raise IpepsError(st, "precond_apply_dev")
+        return n.value, rr.value, st == ECG_BREAKDOWN
 
     def spectra(self) -> np.ndarray:
         out = np.zeros((4, self.Lx * self.Ly, self.chi))

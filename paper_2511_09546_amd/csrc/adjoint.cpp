@@ -12,8 +12,22 @@
 namespace ipeps {
 
 double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
-                   double* grad_host) {
+                   double* grad_host, bool on_device) {
   Device& dev = cx.dev;
+  // the unrolled iterations must not move the projector-SVD warm start that
+  // ctm_converge left behind: repeated calls on the same state then give
+  // bitwise identical gradients
+  const Tensor warm = cx.Xwarm;
+  const bool have_warm = cx.have_warm;
+  struct Restore {
+    Context& c;
+    Tensor w;
+    bool h;
+    ~Restore() {
+      c.Xwarm = w;
+      c.have_warm = h;
+    }
+  } restore{cx, warm, have_warm};
   Tape tp(dev, true);
   Var A = tp.leaf(cx.A, true);
   std::vector<Var> As(cx.nsite());
@@ -23,10 +37,17 @@ double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
   for (int k = 0; k < cx.grad_K; ++k) env = ctm_step_ad(tp, cx, env, arot);
   const double e = energy_ad(tp, cx, env, As, arot, terms);
   tp.backward();
-  if (tp.has_grad(A)) {
+  const int64_t len = A->v.numel();
+  if (on_device) {
+    if (tp.has_grad(A))
+      axpby(dev, len, 1.0, A->g.ptr, 0.0, grad_host);
+    else
+      fill(dev, grad_host, len, 0.0);
+    dev.sync();
+  } else if (tp.has_grad(A)) {
     dev.download(A->g, grad_host);
   } else {
-    std::fill(grad_host, grad_host + A->v.numel(), 0.0);
+    std::fill(grad_host, grad_host + len, 0.0);
   }
   return e;
 }

@@ -257,6 +257,53 @@ int precond_apply(ipeps_ctx* c, const double* g, double delta, double cg_tol,
   return res;
 }
 
+int ctm_set_state_dev(ipeps_ctx* c, const double* dA) {
+  if (!c || !dA) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    axpby(cx.dev, cx.A.numel(), 1.0, dA, 0.0, cx.A.ptr);
+    build_double_layer(cx);
+    cx.dev.sync();
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_energy_grad_dev(ipeps_ctx* c, int n_terms, const ipeps_term* H,
+                          double* e_per_site, double* d_grad) {
+  if (!c || !e_per_site || !d_grad) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  std::vector<TermSpec> terms;
+  int st = parse_terms(cx, n_terms, H, terms);
+  if (st != IPEPS_OK) return st;
+  if (!cx.converged_once) return IPEPS_ESTATE;
+  double e = 0.0;
+  st = guarded([&]() {
+    e = energy_grad(cx, terms, d_grad, true);
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  *e_per_site = e;
+  return IPEPS_OK;
+}
+
+int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
+                      double cg_tol, int cg_maxiter, double* d_x, int* n_iter,
+                      double* rel_resid) {
+  if (!c || !d_g || !d_x || !(delta > 0.0) || !std::isfinite(delta) ||
+      !(cg_tol >= 0.0) || cg_maxiter < 0)
+    return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!cx.converged_once) return IPEPS_ESTATE;
+  int res = 0;
+  int st = guarded([&]() {
+    res = precondition(cx, d_g, delta, cg_tol, cg_maxiter, d_x, n_iter,
+                       rel_resid, true);
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  return res;
+}
+
 int ipeps_corner_spectra(ipeps_ctx* c, double* out) {
   if (!c || !out) return IPEPS_EINVAL;
   Context& cx = c->cx;

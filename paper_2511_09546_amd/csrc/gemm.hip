@@ -228,6 +228,12 @@ void launch_cfg(Device& dev, bool tA, bool tB, int M, int N, int K,
   if (tiles * batch * S >= (1L << 31) || (long)batch * S > 65535)
     throw ArgError("gemm: grid too large");
   dim3 grid((unsigned)tiles, (unsigned)(batch * S));
+  // the profiler brackets the matrix-core kernel alone (split-K partial
+  // sums are a kernel of their own), with the algorithmic 2 M N K flops
+  if (dev.prof.on)
+    dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
+                   8.0 * batch * ((double)M * K + (double)K * N +
+                                  (beta != 0.0 ? 2.0 : 1.0) * M * N));
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), 0, dev.stream, M, N, K, alpha,
                        A, lda, sA, B, ldb, sB, beta, C, ldc, sC, (int)tn, S,
@@ -237,6 +243,7 @@ void launch_cfg(Device& dev, bool tA, bool tB, int M, int N, int K,
   if (tA && !tB) go(gemm64_kernel<BM, BN, WM, WN, true, false>);
   if (!tA && tB) go(gemm64_kernel<BM, BN, WM, WN, false, true>);
   if (tA && tB) go(gemm64_kernel<BM, BN, WM, WN, true, true>);
+  if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
   if (S > 1) {
     const long tot = (long)batch * M * N;
@@ -260,10 +267,6 @@ static void dispatch(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
   if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31) ||
       batch > 65535)
     throw ArgError("gemm: size out of range");
-  if (dev.prof.on)
-    dev.prof.begin(dev.stream, PROF_GEMM, 2.0 * M * N * K * batch,
-                   8.0 * batch *
-                       (M * K + K * N + (beta != 0.0 ? 2 : 1) * M * N));
   const int m = (int)M, n = (int)N, k = (int)K, bt = (int)batch;
 #define IPEPS_CFG(BM_, BN_, WM_, WN_)                                        \
   launch_cfg<BM_, BN_, WM_, WN_>(dev, tA, tB, m, n, k, alpha, A, lda, sA, B, \
@@ -287,7 +290,6 @@ static void dispatch(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
     IPEPS_CFG(64, 64, 2, 2);
   }
 #undef IPEPS_CFG
-  if (dev.prof.on) dev.prof.end(dev.stream);
 }
 
 void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,

@@ -143,12 +143,14 @@ double energy_ad(Tape& tp, Context& cx, const VEnv& e,
 double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms);
 
 // metric.cpp
-int precondition(Context& cx, const double* g_host, double delta,
-                 double cg_tol, int cg_maxiter, double* x_host, int* n_iter,
-                 double* rel_resid);
+// g and x are host pointers, or device pointers when on_device
+int precondition(Context& cx, const double* g, double delta, double cg_tol,
+                 int cg_maxiter, double* x, int* n_iter, double* rel_resid,
+                 bool on_device = false);
 
 // adjoint.cpp
+// grad is a host pointer, or a device pointer when on_device
 double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
-                   double* grad_host);
+                   double* grad, bool on_device = false);
 
 }  // namespace ipeps

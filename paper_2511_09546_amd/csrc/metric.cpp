@@ -72,12 +72,15 @@ void scale_add_dev(Device& dev, int64_t n, const double* s, const double* x,
 
 int precondition(Context& cx, const double* g_host, double delta,
                  double cg_tol, int cg_maxiter, double* x_host, int* n_iter,
-                 double* rel_resid) {
+                 double* rel_resid, bool on_device) {
   Device& dev = cx.dev;
   const int ns = cx.nsite();
   const int64_t m = (int64_t)cx.d * cx.D2 * cx.D2;  // per-site length
   Tensor g = dev.empty({ns, m});
-  dev.upload(g, g_host);
+  if (on_device)
+    axpby(dev, ns * m, 1.0, g_host, 0.0, g.ptr);
+  else
+    dev.upload(g, g_host);
   Tensor x = dev.zeros({ns, m});
   Tensor r = dev.empty({m}), p = dev.empty({m}), Ap = dev.empty({m});
   Tensor sc = dev.zeros({8});  // 0 rr, 1 pAp, 2 rr_new, 3 gnorm^2, 4 Z
@@ -128,7 +131,12 @@ int precondition(Context& cx, const double* g_host, double delta,
     worst_res = std::max(worst_res, gnorm > 0.0 ? std::sqrt(rr) / gnorm : 0.0);
     if (breakdown) break;
   }
-  dev.download(x, x_host);
+  if (on_device) {
+    axpby(dev, ns * m, 1.0, x.ptr, 0.0, x_host);
+    dev.sync();
+  } else {
+    dev.download(x, x_host);
+  }
   if (n_iter) *n_iter = worst_it;
   if (rel_resid) *rel_resid = worst_res;
   return breakdown ? -4 : 0;

@@ -76,3 +76,31 @@ def test_step_against_golden(name):
     assert eg < 1e-9
     assert cg_it == gold["cg_iter"]
     assert ex < 1e-8
+
+
+def test_device_pointer_twins():
+    """ctm_set_state_dev / ipeps_energy_grad_dev / precond_apply_dev give
+    the same results as the host entry points."""
+    _say("device-pointer twins")
+    w = inputs.WORKLOADS["d2chi8"]
+    A = inputs.workload_state("d2chi8")
+    terms = inputs.workload_terms("d2chi8")
+    with binding.Context(A, w["chi"]) as ctx:
+        ctx.converge(0.0, 10)
+        e_h, g_h = ctx.energy_grad(terms, grad=True)
+        x_h, it_h, _, _ = ctx.precond(g_h, 1e-3, 0.0, 15)
+        dg = torch.zeros(A.shape, dtype=torch.float64, device="cuda:0")
+        dx = torch.zeros_like(dg)
+        e_d = ctx.energy_grad_dev(terms, dg.data_ptr())
+        it_d, _, _ = ctx.precond_dev(dg.data_ptr(), dx.data_ptr(), 1e-3, 0.0,
+                                     15)
+        assert e_d == e_h and it_d == it_h
+        assert np.array_equal(dg.cpu().numpy(), g_h)
+        assert np.array_equal(dx.cpu().numpy(), x_h)
+        A2 = A * 1.5
+        ctx.set_state(A2)
+        e2, _ = ctx.energy_grad(terms, grad=False)
+        dA = torch.tensor(A2 * 2.0, device="cuda:0")
+        ctx.set_state_dev(dA.data_ptr())
+        e3, _ = ctx.energy_grad(terms, grad=False)
+        assert abs(e3 - e2) < 1e-13 * abs(e2)   # scale invariance
