@@ -238,6 +238,12 @@ void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
 void col_axpby(Device& dev, int64_t n, int m, double a, const double* s,
                const double* x, double b, double* y,
                int64_t rows_per_batch = 0, int64_t sS = 0);
+void defl_build_k(Device& dev, const double* B1, const double* B2, int m,
+                  double* K, int batch);
+void inv_sqrt_clip(Device& dev, double* x, int64_t n, double thr);
+void defl_coef(Device& dev, int mode, const double* S, const int* keep,
+               const double* lam, int chi, int m2, int sS, const double* H,
+               double* out, int batch);
 void copy2d(Device& dev, const double* src, int64_t lds, double* dst,
             int64_t ldd, int64_t rows, int64_t cols, int batch = 1,
             int64_t sSrc = 0, int64_t sDst = 0);

@@ -1052,6 +1052,93 @@ void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
   IPEPS_HIP(hipGetLastError());
 }
 
+// Deflation of the complement solves (projector backward).  W is an
+// orthonormal basis of pairs [w_u; 0], [0; w_v] in the complement of the kept
+// singular vectors, H = [[0, P_D M], [P'_D M^T, 0]] and, for kept column j,
+// A_j = s_j I - H.  With K = W^T H W = Phi diag(lambda) Phi^T the Galerkin
+// matrix is W^T A_j W = Phi diag(s_j - lambda) Phi^T, so one eigenbasis
+// serves every column.
+//
+// K from B1 = W_u^T P_D M W_v and B2 = W_v^T P'_D M^T W_u (equal to B1^T up
+// to rounding; the mean is used): K = [[0, B], [B^T, 0]], [batch][2m][2m].
+__global__ void defl_build_k_kernel(const double* B1, const double* B2, int m,
+                                    double* K) {
+  const int bt = blockIdx.y, m2 = 2 * m;
+  B1 += (long)bt * m * m;
+  B2 += (long)bt * m * m;
+  K += (long)bt * m2 * m2;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m2 * m2;
+       e += gridDim.x * blockDim.x) {
+    const int i = e / m2, j = e % m2;
+    double v = 0.0;
+    if (i < m && j >= m)
+      v = 0.5 * (B1[i * m + (j - m)] + B2[(j - m) * m + i]);
+    else if (i >= m && j < m)
+      v = 0.5 * (B1[j * m + (i - m)] + B2[(i - m) * m + j]);
+    K[e] = v;
+  }
+}
+
+void defl_build_k(Device& dev, const double* B1, const double* B2, int m,
+                  double* K, int batch) {
+  hipLaunchKernelGGL(defl_build_k_kernel,
+                     dim3(grid_for((int64_t)4 * m * m, 256), batch), dim3(256),
+                     0, dev.stream, B1, B2, m, K);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// x <- 1/sqrt(x) where x > thr, else 0
+__global__ void inv_sqrt_clip_kernel(double* x, int64_t n, double thr) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = x[i] > thr ? 1.0 / sqrt(x[i]) : 0.0;
+}
+
+void inv_sqrt_clip(Device& dev, double* x, int64_t n, double thr) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(inv_sqrt_clip_kernel, dim3(grid_for(n, 256)), dim3(256),
+                     0, dev.stream, x, n, thr);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Coefficients in the eigenbasis of K, [batch][2m][chi], from
+// H = [(W Phi)^T r; (H W Phi)^T r] ([batch][4m][chi]):
+//   mode 0: c = h1 / (s_j - lambda)                (x0 = W Phi c)
+//   mode 1: c = (s_j h1 - h2) / (s_j - lambda)      (p -= W Phi c)
+// Zero for masked columns (j >= keep) and where s_j - lambda <= 1e-12 s_1
+// (that direction is left out of the deflation space of column j).
+__global__ void defl_coef_kernel(int mode, const double* S, const int* keep,
+                                 const double* lam, int chi, int m2, int sS,
+                                 const double* H, double* out) {
+  const int bt = blockIdx.y;
+  const double* s = S + (long)bt * sS;
+  const double* l = lam + (long)bt * m2;
+  H += (long)bt * 2 * m2 * chi;
+  out += (long)bt * m2 * chi;
+  const int k = keep[bt];
+  const double guard = 1e-12 * s[0];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m2 * chi;
+       e += gridDim.x * blockDim.x) {
+    const int i = e / chi, j = e % chi;
+    const double sj = s[j], dd = sj - l[i];
+    double v = 0.0;
+    if (j < k && dd > guard) {
+      const double h1 = H[e];
+      v = mode == 0 ? h1 / dd : (sj * h1 - H[m2 * chi + e]) / dd;
+    }
+    out[e] = v;
+  }
+}
+
+void defl_coef(Device& dev, int mode, const double* S, const int* keep,
+               const double* lam, int chi, int m2, int sS, const double* H,
+               double* out, int batch) {
+  hipLaunchKernelGGL(defl_coef_kernel,
+                     dim3(grid_for((int64_t)m2 * chi, 256), batch), dim3(256),
+                     0, dev.stream, mode, S, keep, lam, chi, m2, sS, H, out);
+  IPEPS_HIP(hipGetLastError());
+}
+
 // y[i][j] = a * s_j * x[i][j] + b * y[i][j]   (column-scaled axpby)
 __global__ void col_axpby_kernel(int64_t n, int m, double a, const double* s,
                                  const double* x, double b, double* y,

@@ -11,7 +11,8 @@
 //   [P_D u_bar_j; P'_D v_bar_j] on the complement of the kept singular
 //   vectors (P_D = 1 - U_k U_k^T, P'_D = 1 - V_k V_k^T), which is
 //   symmetric positive definite there (eigenvalues s_j +- s_i, i discarded)
-//   and solved by column-wise CG with M applied as Qa (Qb x).  This equals
+//   and solved by column-wise CG with M applied as Qa (Qb x), deflated by the
+//   subspace triplets beyond chi that the forward SVD already holds.  This equals
 //   the full-spectrum formula (sum over discarded i of 1/(s_j^2 - s_i^2)
 //   terms) without forming the discarded vectors.
 // Finally Qa_bar += M_bar Qb^T, Qb_bar += Qa^T M_bar in low-rank form.
@@ -176,50 +177,163 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     project_out(dev, Ukm.ptr, sP, rhs.ptr, s2, n, chi, nc);
     project_out(dev, Vkm.ptr, sP, rhs.ptr + sP, s2, n, chi, nc);
 
-    // ---- column-wise CG on [[s, -M], [-M^T, s]] over all cuts at once
+    // ---- column-wise deflated CG on A_j = [[s_j, -M], [-M^T, s_j]] (on the
+    // complement), all columns of all cuts at once.
+    // Deflation space: W = [[W_u, 0], [0, W_v]] with W_u, W_v orthonormal
+    // bases of the subspace singular vectors chi..chi+m-1 projected on the
+    // complement (the next triplets below the truncation, which set the
+    // smallest eigenvalues s_j - s_i of A_j).  With H W = [[0, Y], [Zt, 0]],
+    // Y = P_D M W_v, Zt = P'_D M^T W_u (formed once) and the eigenbasis Phi
+    // of K = W^T H W, the Galerkin matrix of every column is
+    // Phi diag(s_j - lambda) Phi^T.  Start x0 = W (W^T A_j W)^-1 W^T rhs, then
+    // every search direction is made A_j-orthogonal to W, so CG runs on the
+    // complement of W.  The Galerkin quantities are exact for any W, so the
+    // solution does not depend on how well the triplets beyond chi have
+    // converged; only the iteration count does.
+    int m = std::min(b - chi, 32);
+    if (m % 2) --m;
+    if (m < 2) m = 0;
+    const int m2 = 2 * m, m4 = 4 * m;
+    const int64_t sXi = 2 * n * m4, sNm = n * m;
     Tensor X = dev.zeros({nc, 2, n, chi}), R = dev.empty({nc, 2, n, chi});
     Tensor Pp = dev.empty({nc, 2, n, chi}), AP = dev.empty({nc, 2, n, chi});
     Tensor t1 = dev.empty({nc, n, chi});
-    Tensor sc = dev.empty({4, nc, chi});  // rr, pAp, rr_new, rr0
+    Tensor sc = dev.empty({5, nc, chi});  // rr, pAp, rr_new, rr0, <r, p>
     double *rr = sc.ptr, *pap = sc.ptr + nc * chi, *rrn = pap + nc * chi,
-           *rr0 = rrn + nc * chi;
+           *rr0 = rrn + nc * chi, *rp = rr0 + nc * chi;
     const int64_t tot = nc * s2;
-    axpby(dev, tot, 1.0, rhs.ptr, 0.0, R.ptr);
-    axpby(dev, tot, 1.0, rhs.ptr, 0.0, Pp.ptr);
-    coldot(dev, R.ptr, R.ptr, 2 * n, chi, rr, nc, s2);
-    axpby(dev, nc * chi, 1.0, rr, 0.0, rr0);
-    const auto pc = offsets<const double*>(Pp.ptr, s2, nc);
-    const auto pb = offsets<const double*>(Pp.ptr + sP, s2, nc);
-    const auto ac = offsets<double*>(AP.ptr, s2, nc);
-    const auto ab = offsets<double*>(AP.ptr + sP, s2, nc);
     const auto t1w = offsets<double*>(t1.ptr, sP, nc);
     const auto t1r = offsets<const double*>(t1.ptr, sP, nc);
-    std::vector<double> h(4 * nc * chi);
+    // out = A in = [s in_c - P_D Qa Qb in_b; s in_b - P'_D Qb^T Qa^T in_c]
+    auto apply = [&](const Tensor& in, Tensor& out) {
+      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qb, n,
+                offsets<const double*>(in.ptr + sP, s2, nc), chi, 0.0, t1w,
+                chi);
+      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qa, n, t1r, chi, 0.0,
+                offsets<double*>(out.ptr, s2, nc), chi);
+      project_out(dev, Ukm.ptr, sP, out.ptr, s2, n, chi, nc);
+      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qa, n,
+                offsets<const double*>(in.ptr, s2, nc), chi, 0.0, t1w, chi);
+      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qb, n, t1r, chi, 0.0,
+                offsets<double*>(out.ptr + sP, s2, nc), chi);
+      project_out(dev, Vkm.ptr, sP, out.ptr + sP, s2, n, chi, nc);
+      col_axpby(dev, nc * 2 * n, chi, 1.0, S.ptr, in.ptr, -1.0, out.ptr,
+                2 * n, b);
+    };
+    // y (n x m blocks) <- y - Qk (Qk^T y), Qk the masked kept vectors
+    auto off_kept = [&](const Tensor& Qk, double* y) {
+      Tensor tk = dev.empty({nc, chi, m});
+      gemm(dev, true, false, chi, m, n, 1.0, Qk.ptr, chi, sP, y, m, sNm, 0.0,
+           tk.ptr, m, (int64_t)chi * m, nc);
+      gemm(dev, false, false, n, m, chi, -1.0, Qk.ptr, chi, sP, tk.ptr, m,
+           (int64_t)chi * m, 1.0, y, m, sNm, nc);
+    };
+    // Xi = [[W_u Phi_u, Y Phi_v], [W_v Phi_v, Zt Phi_u]]: [nc][2n][4m]; its
+    // first 2m columns are W Phi, the last 2m are H W Phi
+    Tensor Xi, lamK, Hd, Cf;
+    if (m > 0) {
+      Tensor Wr = dev.empty({2, nc, n, m});
+      copy2d(dev, U.ptr + chi, b, Wr.ptr, m, n, m, nc, sUV, sNm);
+      copy2d(dev, V.ptr + chi, b, Wr.ptr + nc * sNm, m, n, m, nc, sUV, sNm);
+      off_kept(Ukm, Wr.ptr);
+      off_kept(Vkm, Wr.ptr + nc * sNm);
+      // orthonormalise: W <- W J diag(lambda^-1/2) from W^T W = J lambda J^T
+      // (columns that vanished, e.g. null directions, stay zero)
+      Tensor G = dev.empty({2 * nc, m, m}), J = dev.empty({2 * nc, m, m});
+      Tensor lw = dev.empty({2 * nc, m});
+      gemm(dev, true, false, m, m, n, 1.0, Wr.ptr, m, sNm, Wr.ptr, m, sNm,
+           0.0, G.ptr, m, (int64_t)m * m, 2 * nc);
+      sym_eig_jacobi(dev, G.ptr, J.ptr, lw.ptr, m, 2 * nc);
+      inv_sqrt_clip(dev, lw.ptr, 2 * nc * m, 1e-12);
+      Tensor Wn = dev.empty({2, nc, n, m});
+      gemm(dev, false, false, n, m, m, 1.0, Wr.ptr, m, sNm, J.ptr, m,
+           (int64_t)m * m, 0.0, Wn.ptr, m, sNm, 2 * nc);
+      col_axpby(dev, 2 * nc * n, m, 1.0, lw.ptr, Wn.ptr, 0.0, Wn.ptr, n, m);
+      const double* Wu = Wn.ptr;
+      const double* Wv = Wn.ptr + nc * sNm;
+      // Y = P_D Qa Qb W_v, Zt = P'_D Qb^T Qa^T W_u
+      Tensor T2 = dev.empty({nc, n, m}), YZ = dev.empty({2, nc, n, m});
+      double* Y = YZ.ptr;
+      double* Zt = YZ.ptr + nc * sNm;
+      const auto t2w = offsets<double*>(T2.ptr, sNm, nc);
+      const auto t2r = offsets<const double*>(T2.ptr, sNm, nc);
+      gemm_ptrs(dev, false, false, n, m, n, 1.0, qb, n,
+                offsets<const double*>(Wv, sNm, nc), m, 0.0, t2w, m);
+      gemm_ptrs(dev, false, false, n, m, n, 1.0, qa, n, t2r, m, 0.0,
+                offsets<double*>(Y, sNm, nc), m);
+      gemm_ptrs(dev, true, false, n, m, n, 1.0, qa, n,
+                offsets<const double*>(Wu, sNm, nc), m, 0.0, t2w, m);
+      gemm_ptrs(dev, true, false, n, m, n, 1.0, qb, n, t2r, m, 0.0,
+                offsets<double*>(Zt, sNm, nc), m);
+      off_kept(Ukm, Y);
+      off_kept(Vkm, Zt);
+      // K = W^T H W and its eigenbasis
+      Tensor Bk = dev.empty({2, nc, m, m});
+      gemm(dev, true, false, m, m, n, 1.0, Wu, m, sNm, Y, m, sNm, 0.0,
+           Bk.ptr, m, (int64_t)m * m, nc);
+      gemm(dev, true, false, m, m, n, 1.0, Wv, m, sNm, Zt, m, sNm, 0.0,
+           Bk.ptr + nc * m * m, m, (int64_t)m * m, nc);
+      Tensor K = dev.empty({nc, m2, m2}), Phi = dev.empty({nc, m2, m2});
+      lamK = dev.empty({nc, m2});
+      defl_build_k(dev, Bk.ptr, Bk.ptr + nc * m * m, m, K.ptr, nc);
+      sym_eig_jacobi(dev, K.ptr, Phi.ptr, lamK.ptr, m2, nc);
+      Xi = dev.empty({nc, 2 * n, m4});
+      const int64_t sPhi = (int64_t)m2 * m2;
+      const double* Phu = Phi.ptr;
+      const double* Phv = Phi.ptr + (int64_t)m * m2;
+      gemm(dev, false, false, n, m2, m, 1.0, Wu, m, sNm, Phu, m2, sPhi, 0.0,
+           Xi.ptr, m4, sXi, nc);
+      gemm(dev, false, false, n, m2, m, 1.0, Y, m, sNm, Phv, m2, sPhi, 0.0,
+           Xi.ptr + m2, m4, sXi, nc);
+      gemm(dev, false, false, n, m2, m, 1.0, Wv, m, sNm, Phv, m2, sPhi, 0.0,
+           Xi.ptr + n * m4, m4, sXi, nc);
+      gemm(dev, false, false, n, m2, m, 1.0, Zt, m, sNm, Phu, m2, sPhi, 0.0,
+           Xi.ptr + n * m4 + m2, m4, sXi, nc);
+      Hd = dev.empty({nc, m4, chi});
+      Cf = dev.empty({nc, m2, chi});
+    }
+    const int64_t sH = (int64_t)m4 * chi, sC = (int64_t)m2 * chi;
+    // p -= W Phi diag(s_j - lambda)^-1 ((W Phi)^T A_j r)
+    auto deflate = [&](const double* r, double* p) {
+      gemm(dev, true, false, m4, chi, 2 * n, 1.0, Xi.ptr, m4, sXi, r, chi, s2,
+           0.0, Hd.ptr, chi, sH, nc);
+      defl_coef(dev, 1, S.ptr, kp, lamK.ptr, chi, m2, b, Hd.ptr, Cf.ptr, nc);
+      gemm(dev, false, false, 2 * n, chi, m2, -1.0, Xi.ptr, m4, sXi, Cf.ptr,
+           chi, sC, 1.0, p, chi, s2, nc);
+    };
+    coldot(dev, rhs.ptr, rhs.ptr, 2 * n, chi, rr0, nc, s2);
+    axpby(dev, tot, 1.0, rhs.ptr, 0.0, R.ptr);
+    if (m > 0) {
+      // x0 = W Phi c, r0 = rhs - A_j x0 = rhs - s_j x0 + (H W Phi) c
+      gemm(dev, true, false, m4, chi, 2 * n, 1.0, Xi.ptr, m4, sXi, rhs.ptr,
+           chi, s2, 0.0, Hd.ptr, chi, sH, nc);
+      defl_coef(dev, 0, S.ptr, kp, lamK.ptr, chi, m2, b, Hd.ptr, Cf.ptr, nc);
+      gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr, m4, sXi, Cf.ptr,
+           chi, sC, 0.0, X.ptr, chi, s2, nc);
+      col_axpby(dev, nc * 2 * n, chi, -1.0, S.ptr, X.ptr, 1.0, R.ptr, 2 * n,
+                b);
+      gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr + m2, m4, sXi,
+           Cf.ptr, chi, sC, 1.0, R.ptr, chi, s2, nc);
+    }
+    axpby(dev, tot, 1.0, R.ptr, 0.0, Pp.ptr);
+    if (m > 0) deflate(R.ptr, Pp.ptr);
+    coldot(dev, R.ptr, R.ptr, 2 * n, chi, rr, nc, s2);
+    std::vector<double> h(5 * nc * chi);
     const double tol2 = 1e-24;
     const int max_it = 600;
     int it = 0;
     for (; it < max_it; ++it) {
-      // ac = s p_c - P_D M p_b
-      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qb, n, pb, chi, 0.0, t1w,
-                chi);
-      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qa, n, t1r, chi, 0.0, ac,
-                chi);
-      project_out(dev, Ukm.ptr, sP, AP.ptr, s2, n, chi, nc);
-      // ab = s p_b - P'_D M^T p_c
-      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qa, n, pc, chi, 0.0, t1w,
-                chi);
-      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qb, n, t1r, chi, 0.0, ab,
-                chi);
-      project_out(dev, Vkm.ptr, sP, AP.ptr + sP, s2, n, chi, nc);
-      // AP = s P - AP (columns scaled by their singular value)
-      col_axpby(dev, nc * 2 * n, chi, 1.0, S.ptr, Pp.ptr, -1.0, AP.ptr, 2 * n,
-                b);
+      apply(Pp, AP);
       coldot(dev, Pp.ptr, AP.ptr, 2 * n, chi, pap, nc, s2);
-      colcg(dev, 0, nc * 2 * n, chi, rr, pap, X.ptr, R.ptr, Pp.ptr, AP.ptr,
-            2 * n);
+      // x += alpha p, r -= alpha A p with alpha = <r, p> / <p, A p> (equal
+      // to <r, r> / <p, A p> when p is exactly A-orthogonal to W)
+      if (m > 0) coldot(dev, R.ptr, Pp.ptr, 2 * n, chi, rp, nc, s2);
+      colcg(dev, 0, nc * 2 * n, chi, m > 0 ? rp : rr, pap, X.ptr, R.ptr,
+            Pp.ptr, AP.ptr, 2 * n);
       coldot(dev, R.ptr, R.ptr, 2 * n, chi, rrn, nc, s2);
       colcg(dev, 1, nc * 2 * n, chi, rr, rrn, X.ptr, R.ptr, Pp.ptr, AP.ptr,
             2 * n);
+      if (m > 0) deflate(R.ptr, Pp.ptr);
       axpby(dev, nc * chi, 1.0, rrn, 0.0, rr);
       if ((it + 1) % 4 == 0) {
         dev.download(sc, h.data());
