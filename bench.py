@@ -2,7 +2,8 @@
 """Throughput of the preconditioned iPEPS step on one MI355X.
 
 One step (the whole hot path on one state):
-  ctm_converge      CTMRG to a corner-spectrum change < 1e-10
+  ctm_converge      CTMRG to a corner-spectrum change < 1e-10 (FP64) or to
+                    the rounding floor of the contraction arithmetic
   ipeps_energy_grad energy per site and dE/dA, K = 20 unrolled iterations
   precond_apply     x = (N_local + 1e-4 I)^-1 g, 20 CG iterations
   update            A <- A - 1e-3 |A| x/|x|, environment kept (warm start)
@@ -12,14 +13,21 @@ from the trace boundary (cold); timed steps are warm, as in an optimiser.
 A, g and x stay in device memory (device-pointer entry points); only
 scalars cross PCIe inside the timed region.
 
-Prints one JSON line.  The roofline object reports the library's FP64
-matrix-core GEMM (the dominant kernel): algorithmic flops (2 M N K per
-launch) over the device time of its launches, both recorded live with HIP
-events on the library's stream during the timed steps.  The cpu_baseline
-object times the CPU oracle on a bounded sample of the same workload (one
-CTMRG iteration and one K=1 gradient step) and scales it to one step.
+The headline runs the dense contractions in FP32 on the matrix cores
+(projector SVD, normalisation, traces and CG scalars stay FP64); the same
+steps are then timed with every product in FP64 ("plain FP64") and the
+energies of the two cold steps are compared.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu-baseline]
+Prints one JSON line.  The roofline object reports the library's
+matrix-core GEMM in the headline arithmetic (the dominant kernel):
+algorithmic flops (2 M N K per launch) over the device time of its
+launches, both recorded live with HIP events on the library's stream
+during the timed steps.  The cpu_baseline object times the CPU oracle on a
+bounded sample of the same workload (one CTMRG iteration and one K=1
+gradient step) and scales it to one step.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--prec fp32]
+                    [--no-fp64] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -32,7 +40,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("energy+grad+precond steps/s at D=6,χ=72 vs plain FP64; "
           "MFMA util; p50/p99 lat")
-PEAK_FP64_TFLOPS = 78.6
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 
 def cpu_baseline(name, n_conv):
@@ -61,32 +69,17 @@ def cpu_baseline(name, n_conv):
                        f"gradient steps = {t_step:.0f} s/step")}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="d6chi72")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
-              "not supported (independent states shard trivially, see the "
-              "design notes)", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def run(name, prec, steps, warmup):
+    """Warm-up and timed steps in one arithmetic; returns the measurements."""
     import torch
     from paper_2511_09546_amd import binding, inputs
-
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    binding.load()
-    name = args.workload
     w = inputs.WORKLOADS[name]
     A = inputs.workload_state(name)
     terms = inputs.workload_terms(name)
-    ctx = binding.Context(A, w["chi"])
+    o = binding.default_opts()
+    o.prec = {"fp64": binding.FP64, "fp32": binding.FP32}[prec]
+    ctx = binding.Context(A, w["chi"], opts=o)
+    fam = binding.PROF_GEMM if prec == "fp64" else binding.PROF_GEMM32
 
     # site tensor, gradient and direction stay resident in HBM: the step
     # uses the device-pointer entry points (torch provides the buffers)
@@ -107,38 +100,77 @@ def main():
         torch.cuda.synchronize()
         ctx.set_state_dev(A.data_ptr())
         return A, dict(ms=1e3 * (time.perf_counter() - t0), iters=n_it, e=e,
-                       cg=cg_it, res=res)
+                       delta=dl, cg=cg_it, res=res)
 
     A = dA
     infos = []
-    for i in range(args.warmup):
+    for i in range(warmup):
         A, info = step(A)
         infos.append(info)
-        print(f"warmup {i}: {info}", file=sys.stderr, flush=True)
+        print(f"[{prec}] warmup {i}: {info}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ctx.profile(True)
     t0 = time.perf_counter()
     timed = []
-    for i in range(args.steps):
+    for i in range(steps):
         A, info = step(A)
         timed.append(info)
-        print(f"step {i}: {info}", file=sys.stderr, flush=True)
+        print(f"[{prec}] step {i}: {info}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    n_gemm, t_gemm, fl_gemm, by_gemm = ctx.profile_read(binding.PROF_GEMM)
-    n_jac, t_jac, _, _ = ctx.profile_read(binding.PROF_JACOBI)
-    n_perm, t_perm, _, by_perm = ctx.profile_read(binding.PROF_PERMUTE)
+    prof = {f: ctx.profile_read(f) for f in
+            (fam, binding.PROF_JACOBI, binding.PROF_PERMUTE)}
     ctx.profile(False)
     stats = ctx.stats()
     ctx.close()
+    return dict(elapsed=elapsed, timed=timed, infos=infos, prof=prof,
+                fam=fam, stats=stats)
 
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="d6chi72")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the plain FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
+              "not supported (independent states shard trivially, see the "
+              "design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2511_09546_amd import binding, inputs
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    binding.load()
+    name = args.workload
+    w = inputs.WORKLOADS[name]
+
+    head = run(name, args.prec, args.steps, args.warmup)
+    base = None
+    if args.prec != "fp64" and not args.no_fp64:
+        base = run(name, "fp64", args.steps, args.warmup)
+
+    timed, elapsed = head["timed"], head["elapsed"]
+    n_g, t_g, fl_g, _ = head["prof"][head["fam"]]
+    _, t_jac, _, _ = head["prof"][binding.PROF_JACOBI]
+    _, t_perm, _, _ = head["prof"][binding.PROF_PERMUTE]
     ms = sorted(t["ms"] for t in timed)
     p = lambda q: ms[min(len(ms) - 1, int(round(q * (len(ms) - 1))))]  # noqa
-    achieved = fl_gemm / t_gemm / 1e12 if t_gemm > 0 else 0.0
+    achieved = fl_g / t_g / 1e12 if t_g > 0 else 0.0
+    peak = PEAK_TFLOPS[args.prec]
     n_conv = int(round(sum(t["iters"] for t in timed) / len(timed)))
+    value = args.steps / elapsed
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": value,
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -147,29 +179,41 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": ("f64" if args.prec == "fp64"
+                  else "f32 contractions, f64 SVD/CG"),
         "data": "synthetic",
         "config": {"workload": f"{name}: 1x1 iPEPS d={w['d']} D={w['D']} "
                                f"chi={w['chi']} J1-J2 J2={w['J2']}, warm "
-                               "steps (env kept), CTMRG tol 1e-10, "
-                               f"K={w['grad_K']}, CG 20 its, delta 1e-4",
+                               "steps (env kept), CTMRG tol 1e-10 (FP32: its "
+                               f"1e-7 floor), K={w['grad_K']}, CG 20 its, "
+                               "delta 1e-4",
                    "D": w["D"], "chi": w["chi"], "d": w["d"],
-                   "grad_K": w["grad_K"], "prec": "fp64"},
+                   "grad_K": w["grad_K"], "prec": args.prec},
         "p50_ms": p(0.5), "p99_ms": p(0.99),
         "ctm_iters_per_step": [t["iters"] for t in timed],
-        "cold_step_ms": infos[0]["ms"] if infos else None,
+        "cold_step_ms": head["infos"][0]["ms"] if head["infos"] else None,
         "energy_per_site": timed[-1]["e"],
-        "roofline": {"bound": "mfma", "achieved": achieved,
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "gemm64_kernel (FP64 MFMA, all tile shapes)",
-                     "launches": n_gemm,
-                     "avg_launch_us": 1e6 * t_gemm / max(n_gemm, 1),
-                     "gemm_share_of_step": t_gemm / elapsed},
-        "kernel_time_s": {"gemm": t_gemm, "jacobi": t_jac,
-                          "permute": t_perm},
-        "svd_stats": stats,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None,
+                     "kernel": f"gemm_kernel ({args.prec} MFMA, all tile "
+                               "shapes)",
+                     "launches": n_g,
+                     "avg_launch_us": 1e6 * t_g / max(n_g, 1),
+                     "gemm_share_of_step": t_g / elapsed},
+        "kernel_time_s": {"gemm": t_g, "jacobi": t_jac, "permute": t_perm},
+        "svd_stats": head["stats"],
     }
+    if base is not None:
+        v64 = args.steps / base["elapsed"]
+        e_h = head["infos"][0]["e"] if head["infos"] else None
+        e_b = base["infos"][0]["e"] if base["infos"] else None
+        out["plain_fp64"] = {
+            "value": v64, "ms_per_step": 1e3 * base["elapsed"] / args.steps,
+            "speedup": value / v64,
+            "ctm_iters_per_step": [t["iters"] for t in base["timed"]],
+            "cold_step_energy_abs_diff": (abs(e_h - e_b)
+                                          if e_h is not None else None)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, n_conv)
     print(json.dumps(out), flush=True)

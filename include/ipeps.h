@@ -178,7 +178,7 @@ size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
  * on = 1 the context records HIP events on its stream around every launch
  * of the timed kernel families (clearing earlier records); on = 0 stops.
  * Families: 0 = GEMM (FP64 matrix-core GEMM, all shapes), 1 = Jacobi
- * eigensolver, 2 = permute.  ipeps_profile_read returns, for one family,
+ * eigensolver, 2 = permute, 3 = FP32 GEMM.  ipeps_profile_read returns, for one family,
  * the number of launches, their summed device time in seconds and their
  * algorithmic FLOP and byte counts (2 M N K flop; the operand and result
  * bytes of each launch).  Errors: EINVAL, EHIP. */

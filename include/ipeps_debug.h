@@ -18,6 +18,18 @@ int ipeps_debug_gemm(int tA, int tB, int M, int N, int K, double alpha,
                      const double* A, const double* B, double beta,
                      double* C);
 
+/* ipeps_debug_gemm with the products in the arithmetic `prec` (ipeps_prec:
+ * IPEPS_FP64 or IPEPS_FP32; operands and result stay FP64 in memory). */
+int ipeps_debug_gemm_prec(int prec, int tA, int tB, int M, int N, int K,
+                          double alpha, const double* A, const double* B,
+                          double beta, double* C);
+
+/* Average device time in microseconds of one strided-batched GEMM call
+ * (C = op(A) op(B) on `batch` pseudo-random M x K, K x N operands, split-K
+ * reduction included), over `reps` calls after one warm-up call. */
+int ipeps_debug_gemm_time(int prec, int tA, int tB, int M, int N, int K,
+                          int batch, int reps, double* us_per_call);
+
 /* Symmetric eigendecomposition of `batch` b x b row-major matrices G (b even,
  * b <= 128) by the library's Jacobi kernel: V (columns = eigenvectors) and
  * lam, sorted by descending eigenvalue. */

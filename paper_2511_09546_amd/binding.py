@@ -29,9 +29,10 @@ API_FUNCTIONS = [
     "ipeps_profile_read", "ctm_set_state_dev", "ipeps_energy_grad_dev",
     "precond_apply_dev",
 ]
-PROF_GEMM, PROF_JACOBI, PROF_PERMUTE = 0, 1, 2
+PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32 = 0, 1, 2, 3
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
-                   "ipeps_debug_svd_ts", "ipeps_debug_stats"]
+                   "ipeps_debug_svd_ts", "ipeps_debug_stats",
+                   "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time"]
 
 
 class IpepsError(RuntimeError):
@@ -96,6 +97,11 @@ def load():
                                        POINTER(ctypes.c_long), _DP, _DP, _DP]
     lib.ipeps_debug_gemm.argtypes = [c_int, c_int, c_int, c_int, c_int,
                                      c_double, _DP, _DP, c_double, _DP]
+    lib.ipeps_debug_gemm_prec.argtypes = [c_int, c_int, c_int, c_int, c_int,
+                                          c_int, c_double, _DP, _DP,
+                                          c_double, _DP]
+    lib.ipeps_debug_gemm_time.argtypes = [c_int, c_int, c_int, c_int, c_int,
+                                          c_int, c_int, c_int, _DP]
     lib.ipeps_debug_sym_eig.argtypes = [c_int, c_int, _DP, _DP, _DP]
     lib.ipeps_debug_stats.argtypes = [c_void_p, _DP]
     lib.ipeps_debug_svd_ts.argtypes = [c_int, c_int, c_int, _DP, _DP, _DP,
@@ -107,7 +113,8 @@ def load():
                  "ctm_set_state_dev", "ipeps_energy_grad_dev",
                  "precond_apply_dev",
                  "ipeps_debug_sym_eig", "ipeps_debug_svd_ts",
-                 "ipeps_debug_stats"):
+                 "ipeps_debug_stats", "ipeps_debug_gemm_prec",
+                 "ipeps_debug_gemm_time"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -313,6 +320,28 @@ def debug_gemm(A, B, C, tA=False, tB=False, alpha=1.0, beta=0.0):
     if st != OK:
         raise IpepsError(st, "ipeps_debug_gemm")
     return C
+
+
+def debug_gemm_prec(prec, A, B, C, tA=False, tB=False, alpha=1.0,
+                    beta=0.0):
+    A, B, C = _f64(A), _f64(B), _f64(C).copy()
+    M, K = (A.shape[1], A.shape[0]) if tA else A.shape
+    N = B.shape[0] if tB else B.shape[1]
+    st = load().ipeps_debug_gemm_prec(int(prec), int(tA), int(tB), M, N, K,
+                                      alpha, _dp(A), _dp(B), beta, _dp(C))
+    if st != OK:
+        raise IpepsError(st, "ipeps_debug_gemm_prec")
+    return C
+
+
+def debug_gemm_time(prec, tA, tB, M, N, K, batch=1, reps=20):
+    """Average device microseconds of one GEMM call."""
+    us = ctypes.c_double(0.0)
+    st = load().ipeps_debug_gemm_time(int(prec), int(tA), int(tB), M, N, K,
+                                      batch, reps, ctypes.byref(us))
+    if st != OK:
+        raise IpepsError(st, "ipeps_debug_gemm_time")
+    return us.value
 
 
 def debug_sym_eig(G):

@@ -90,7 +90,9 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
   ipeps_opts o;
   ipeps_default_opts(&o);
   if (opts) o = *opts;
-  if (o.prec != IPEPS_FP64) return IPEPS_ENOTIMPL;
+  if (o.prec != IPEPS_FP64 && o.prec != IPEPS_FP32 && o.prec != IPEPS_BF16)
+    return IPEPS_EINVAL;
+  if (o.prec == IPEPS_BF16) return IPEPS_ENOTIMPL;
   if (!(o.svd_cutoff >= 0.0) || o.grad_K < 0 || o.svd_max_iter < 1 ||
       !(o.svd_tol >= 0.0) || o.svd_oversample < 0)
     return IPEPS_EINVAL;
@@ -158,7 +160,12 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
   int it = 0;
   double dl = INFINITY;
   const double svd_tol = cx.svd.tol;
+  // the spectrum change cannot fall below the rounding of the contraction
+  // arithmetic: tolerances under that floor are raised to it
+  const double floor = cx.prec == IPEPS_FP64 ? 0.0 : kSpectraFloorFp32;
+  if (tol > 0.0) tol = std::max(tol, floor);
   int st = guarded([&]() {
+    PrecScope ps(cx.dev, cx.prec);
     while (it < max_iter) {
       // when iterating to a tolerance, the projector SVD of an iteration
       // only needs to be as accurate as the environment it produces: its
@@ -227,6 +234,7 @@ int ipeps_energy_grad(ipeps_ctx* c, int n_terms, const ipeps_term* H,
   if (!cx.converged_once) return IPEPS_ESTATE;
   double e = 0.0;
   st = guarded([&]() {
+    PrecScope ps(cx.dev, cx.prec);
     if (grad) {
       e = energy_grad(cx, terms, grad);
     } else {
@@ -249,6 +257,7 @@ int precond_apply(ipeps_ctx* c, const double* g, double delta, double cg_tol,
   if (!cx.converged_once) return IPEPS_ESTATE;
   int res = 0;
   int st = guarded([&]() {
+    PrecScope ps(cx.dev, cx.prec);
     res = precondition(cx, g, delta, cg_tol, cg_maxiter, x, n_iter,
                        rel_resid);
     return IPEPS_OK;
@@ -278,6 +287,7 @@ int ipeps_energy_grad_dev(ipeps_ctx* c, int n_terms, const ipeps_term* H,
   if (!cx.converged_once) return IPEPS_ESTATE;
   double e = 0.0;
   st = guarded([&]() {
+    PrecScope ps(cx.dev, cx.prec);
     e = energy_grad(cx, terms, d_grad, true);
     return IPEPS_OK;
   });
@@ -296,6 +306,7 @@ int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
   if (!cx.converged_once) return IPEPS_ESTATE;
   int res = 0;
   int st = guarded([&]() {
+    PrecScope ps(cx.dev, cx.prec);
     res = precondition(cx, d_g, delta, cg_tol, cg_maxiter, d_x, n_iter,
                        rel_resid, true);
     return IPEPS_OK;

@@ -42,6 +42,58 @@ int ipeps_debug_gemm(int tA, int tB, int M, int N, int K, double alpha,
   });
 }
 
+int ipeps_debug_gemm_prec(int prec, int tA, int tB, int M, int N, int K,
+                          double alpha, const double* A, const double* B,
+                          double beta, double* C) {
+  if (!A || !B || !C || M < 1 || N < 1 || K < 1 ||
+      (prec != IPEPS_FP64 && prec != IPEPS_FP32))
+    return IPEPS_EINVAL;
+  return run([&](Device& dev) {
+    Tensor a = dev.empty({(int64_t)M * K}), b = dev.empty({(int64_t)K * N}),
+           c = dev.empty({(int64_t)M * N});
+    dev.upload(a, A);
+    dev.upload(b, B);
+    dev.upload(c, C);
+    PrecScope ps(dev, prec);
+    gemm(dev, tA != 0, tB != 0, M, N, K, alpha, a.ptr, tA ? M : K, 0, b.ptr,
+         tB ? K : N, 0, beta, c.ptr, N, 0, 1);
+    dev.download(c, C);
+  });
+}
+
+int ipeps_debug_gemm_time(int prec, int tA, int tB, int M, int N, int K,
+                          int batch, int reps, double* us_per_call) {
+  if (!us_per_call || M < 1 || N < 1 || K < 1 || batch < 1 || reps < 1 ||
+      (prec != IPEPS_FP64 && prec != IPEPS_FP32))
+    return IPEPS_EINVAL;
+  return run([&](Device& dev) {
+    const int64_t sA = (int64_t)M * K, sB = (int64_t)K * N,
+                  sC = (int64_t)M * N;
+    Tensor a = dev.empty({batch * sA}), b = dev.empty({batch * sB}),
+           c = dev.empty({batch * sC});
+    random_block(dev, a.ptr, batch * sA, 1);
+    random_block(dev, b.ptr, batch * sB, 2);
+    PrecScope ps(dev, prec);
+    auto call = [&]() {
+      gemm(dev, tA != 0, tB != 0, M, N, K, 1.0, a.ptr, tA ? M : K, sA,
+           b.ptr, tB ? K : N, sB, 0.0, c.ptr, N, sC, batch);
+    };
+    call();
+    hipEvent_t e0, e1;
+    IPEPS_HIP(hipEventCreate(&e0));
+    IPEPS_HIP(hipEventCreate(&e1));
+    IPEPS_HIP(hipEventRecord(e0, dev.stream));
+    for (int r = 0; r < reps; ++r) call();
+    IPEPS_HIP(hipEventRecord(e1, dev.stream));
+    IPEPS_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    IPEPS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *us_per_call = 1e3 * ms / reps;
+  });
+}
+
 int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
                         double* lam) {
   if (!G || !V || !lam || b < 2 || b > 128 || b % 2 || batch < 1)

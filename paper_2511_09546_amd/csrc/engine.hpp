@@ -83,7 +83,17 @@ struct Tensor {
 // Optional timing of the library's own launches: HIP events on the launch
 // stream around every launch of a kernel family, with the algorithmic FLOP
 // and byte counts of each launch.
-enum ProfFamily { PROF_GEMM = 0, PROF_JACOBI = 1, PROF_PERMUTE = 2, PROF_N = 3 };
+enum ProfFamily {
+  PROF_GEMM = 0,     // FP64 matrix-core GEMM
+  PROF_JACOBI = 1,
+  PROF_PERMUTE = 2,
+  PROF_GEMM32 = 3,   // FP32 matrix-core GEMM
+  PROF_N = 4
+};
+
+// Arithmetic of the GEMMs issued on a device (the contraction precision;
+// the values match ipeps_prec of the C ABI).
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
 
 struct Profiler {
   bool on = false;
@@ -109,6 +119,7 @@ struct Device {
   bool own_stream = false;
   Pool pool;
   Profiler prof;
+  int cprec = PREC_FP64;  // arithmetic of the GEMMs issued now
 
   Tensor empty(std::vector<int64_t> shape);
   Tensor zeros(std::vector<int64_t> shape);
@@ -116,6 +127,16 @@ struct Device {
   void upload(Tensor& t, const double* host);
   void download(const Tensor& t, double* host);
   void sync();
+};
+
+// Sets the GEMM arithmetic for a scope and restores the previous one.
+struct PrecScope {
+  Device& d;
+  int old;
+  PrecScope(Device& dv, int p) : d(dv), old(dv.cprec) { d.cprec = p; }
+  ~PrecScope() { d.cprec = old; }
+  PrecScope(const PrecScope&) = delete;
+  PrecScope& operator=(const PrecScope&) = delete;
 };
 
 // ---------------------------------------------------------------- kernels

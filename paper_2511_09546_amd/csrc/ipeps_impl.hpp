@@ -78,6 +78,10 @@ struct VEnv {
   std::vector<Var> C, T;
 };
 
+// Smallest corner-spectrum change that CTMRG with FP32 contractions can
+// resolve (their rounding moves the normalised spectra by about this much).
+constexpr double kSpectraFloorFp32 = 1e-7;
+
 struct Context {
   Device dev;
   Lattice lat;

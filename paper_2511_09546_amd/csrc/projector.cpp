@@ -22,6 +22,7 @@
 // chi-wide block operation one strided batched launch.
 #include <algorithm>
 #include <cmath>
+#include <utility>
 
 #include "ad.hpp"
 #include "ipeps_impl.hpp"
@@ -38,6 +39,14 @@ void project_out(Device& dev, const double* Q, int64_t sQ, double* y,
        (int64_t)m * m, batch);
   gemm(dev, false, false, n, m, m, -1.0, Q, m, sQ, t.ptr, m, (int64_t)m * m,
        1.0, y, m, sY, batch);
+}
+
+// gemm_ptrs in a given arithmetic (the products with the cut matrices are
+// contractions and follow the contraction precision)
+template <class... Args>
+void gemm_ptrs_p(Device& dev, int prec, Args&&... args) {
+  PrecScope s(dev, prec);
+  gemm_ptrs(dev, std::forward<Args>(args)...);
 }
 
 template <class T>
@@ -94,6 +103,10 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
   tp.push([&tp, Qa, Qb, P, PtT, U, S, V, keep, w, QbV, QaU, n, chi, b, nc,
            st]() {
     Device& dev = tp.dev;
+    // the products with the cut matrices keep the contraction precision of
+    // the calling scope; the SVD-adjoint algebra around them is FP64
+    const int cp = dev.cprec;
+    PrecScope f64(dev, PREC_FP64);
     const int64_t sUV = n * b, sP = n * chi, s2 = 2 * n * chi;
     const int64_t sG = (int64_t)chi * chi;
     const int* kp = (const int*)keep.ptr;
@@ -139,10 +152,10 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const auto tbw = offsets<const double*>(Tbw.ptr, sP, nc);
     // direct terms of P = Qb V w and Pt^T = Qa^T U w
     if (!gqb.empty())
-      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(pbw, ib), chi,
+      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(pbw, ib), chi,
                 pick(vi, ib), b, 1.0, gqb, n);
     if (!gqa.empty())
-      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(ui, ia), b,
+      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(ui, ia), b,
                 pick(tbw, ia), chi, 1.0, gqa, n);
     // s_bar through w = s^-1/2
     Tensor wb = dev.empty({3, nc, chi});
@@ -152,9 +165,9 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     proj_sbar(dev, S.ptr, kp, chi, wb.ptr, wb.ptr + nc * chi, sbar, nc, b);
     // U_bar, V_bar (columns >= k vanish with w)
     Tensor Vb = dev.empty({nc, n, chi}), Ub = dev.empty({nc, n, chi});
-    gemm_ptrs(dev, true, false, n, chi, n, 1.0, qb, n, pbw, chi, 0.0,
+    gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qb, n, pbw, chi, 0.0,
               offsets<double*>(Vb.ptr, sP, nc), chi);
-    gemm_ptrs(dev, false, false, n, chi, n, 1.0, qa, n, tbw, chi, 0.0,
+    gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qa, n, tbw, chi, 0.0,
               offsets<double*>(Ub.ptr, sP, nc), chi);
     // kept block
     Tensor Au = dev.empty({nc, chi, chi}), Av = dev.empty({nc, chi, chi}),
@@ -206,15 +219,15 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const auto t1r = offsets<const double*>(t1.ptr, sP, nc);
     // out = A in = [s in_c - P_D Qa Qb in_b; s in_b - P'_D Qb^T Qa^T in_c]
     auto apply = [&](const Tensor& in, Tensor& out) {
-      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qb, n,
+      gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qb, n,
                 offsets<const double*>(in.ptr + sP, s2, nc), chi, 0.0, t1w,
                 chi);
-      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qa, n, t1r, chi, 0.0,
+      gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qa, n, t1r, chi, 0.0,
                 offsets<double*>(out.ptr, s2, nc), chi);
       project_out(dev, Ukm.ptr, sP, out.ptr, s2, n, chi, nc);
-      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qa, n,
+      gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qa, n,
                 offsets<const double*>(in.ptr, s2, nc), chi, 0.0, t1w, chi);
-      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qb, n, t1r, chi, 0.0,
+      gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qb, n, t1r, chi, 0.0,
                 offsets<double*>(out.ptr + sP, s2, nc), chi);
       project_out(dev, Vkm.ptr, sP, out.ptr + sP, s2, n, chi, nc);
       col_axpby(dev, nc * 2 * n, chi, 1.0, S.ptr, in.ptr, -1.0, out.ptr,
@@ -257,13 +270,13 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       double* Zt = YZ.ptr + nc * sNm;
       const auto t2w = offsets<double*>(T2.ptr, sNm, nc);
       const auto t2r = offsets<const double*>(T2.ptr, sNm, nc);
-      gemm_ptrs(dev, false, false, n, m, n, 1.0, qb, n,
+      gemm_ptrs_p(dev, cp, false, false, n, m, n, 1.0, qb, n,
                 offsets<const double*>(Wv, sNm, nc), m, 0.0, t2w, m);
-      gemm_ptrs(dev, false, false, n, m, n, 1.0, qa, n, t2r, m, 0.0,
+      gemm_ptrs_p(dev, cp, false, false, n, m, n, 1.0, qa, n, t2r, m, 0.0,
                 offsets<double*>(Y, sNm, nc), m);
-      gemm_ptrs(dev, true, false, n, m, n, 1.0, qa, n,
+      gemm_ptrs_p(dev, cp, true, false, n, m, n, 1.0, qa, n,
                 offsets<const double*>(Wu, sNm, nc), m, 0.0, t2w, m);
-      gemm_ptrs(dev, true, false, n, m, n, 1.0, qb, n, t2r, m, 0.0,
+      gemm_ptrs_p(dev, cp, true, false, n, m, n, 1.0, qb, n, t2r, m, 0.0,
                 offsets<double*>(Zt, sNm, nc), m);
       off_kept(Ukm, Y);
       off_kept(Vkm, Zt);
@@ -319,7 +332,12 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     if (m > 0) deflate(R.ptr, Pp.ptr);
     coldot(dev, R.ptr, R.ptr, 2 * n, chi, rr, nc, s2);
     std::vector<double> h(5 * nc * chi);
-    const double tol2 = 1e-24;
+    // relative residual 1e-12 with FP64 products; with FP32 products 1e-5,
+    // and the solve also ends when four iterations no longer reduce the
+    // worst relative residual by half (rounding floor of the products)
+    const bool lowp = cp != PREC_FP64;
+    const double tol2 = lowp ? 1e-10 : 1e-24;
+    double prev_worst = INFINITY;
     const int max_it = 600;
     int it = 0;
     for (; it < max_it; ++it) {
@@ -338,10 +356,16 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       if ((it + 1) % 4 == 0) {
         dev.download(sc, h.data());
         bool done = true;
+        double worst = 0.0;
         const double* hr = h.data();
         const double* h0 = h.data() + 3 * nc * chi;
         for (int j = 0; j < nc * chi; ++j)
-          if (h0[j] > 0.0 && hr[j] > tol2 * h0[j]) done = false;
+          if (h0[j] > 0.0) {
+            worst = std::max(worst, hr[j] / h0[j]);
+            if (hr[j] > tol2 * h0[j]) done = false;
+          }
+        if (lowp && worst > 0.25 * prev_worst) done = true;
+        prev_worst = worst;
         if (done) {
           ++it;
           break;
@@ -361,20 +385,20 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const auto qau = offsets<const double*>(QaU.ptr, sP, nc);
     if (!gqa.empty()) {
       // Qa_bar += U (Qb B)^T + C (Qb V)^T
-      gemm_ptrs(dev, false, false, n, chi, n, 1.0, qb, n, bm, chi, 0.0, t1w,
+      gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qb, n, bm, chi, 0.0, t1w,
                 chi);
-      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(ui, ia), b,
+      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(ui, ia), b,
                 pick(t1r, ia), chi, 1.0, gqa, n);
-      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(cm, ia), chi,
+      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(cm, ia), chi,
                 pick(qbv, ia), chi, 1.0, gqa, n);
     }
     if (!gqb.empty()) {
       // Qb_bar += (Qa^T U) B^T + (Qa^T C) V^T
-      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(qau, ib), chi,
+      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(qau, ib), chi,
                 pick(bm, ib), chi, 1.0, gqb, n);
-      gemm_ptrs(dev, true, false, n, chi, n, 1.0, qa, n, cm, chi, 0.0, t1w,
+      gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qa, n, cm, chi, 0.0, t1w,
                 chi);
-      gemm_ptrs(dev, false, true, n, n, chi, 1.0, pick(t1r, ib), chi,
+      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(t1r, ib), chi,
                 pick(vi, ib), b, 1.0, gqb, n);
     }
   });

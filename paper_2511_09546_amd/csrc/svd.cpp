@@ -1,7 +1,8 @@
 // Truncated SVD of the half-system cut matrices M = Qa Qb (never formed).
 //
 // Block subspace iteration with Rayleigh-Ritz on M^T M, warm-started from the
-// right singular block of the previous CTMRG iteration:
+// right singular block of the previous CTMRG iteration (the products with
+// Qa, Qb in the contraction precision, everything else in FP64):
 //   W = M X = Qa (Qb X)                       (two GEMMs)
 //   W J = U diag(s)   (tall-skinny SVD, below), V = X J
 //   Z = M^T U = Qb^T (Qa^T U)                 (two GEMMs)
@@ -26,6 +27,7 @@ namespace ipeps {
 
 void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
             Tensor& U, Tensor& S, Tensor& J) {
+  PrecScope f64(dev, PREC_FP64);
   const int64_t sW = n * b, sG = (int64_t)b * b;
   Tensor G = dev.empty({batch, b, b});
   Tensor J1 = dev.empty({batch, b, b});
@@ -107,6 +109,12 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
   V = dev.empty({nc, n, b});
   int it = 0;
   double worst = 0.0;
+  // with FP32 products the residual levels off at a few 1e-6 s_1: the
+  // tolerance is raised to 1e-5 and the iteration also ends when an
+  // iteration no longer halves the residual
+  const bool lowp = dev.cprec != PREC_FP64;
+  const double tol = std::max(prm.tol, lowp ? 1e-5 : 0.0);
+  double prev = INFINITY;
   for (;;) {
     ++it;
     gemm_ptrs(dev, false, false, n, b, n, 1.0, cb.Qb, n, cptrs(X), b, 0.0,
@@ -114,8 +122,11 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
     gemm_ptrs(dev, false, false, n, b, n, 1.0, cb.Qa, n, cptrs(T1), b, 0.0,
               ptrs(W), b);
     svd_ts(dev, W, nc, n, b, U, S, J);
-    gemm(dev, false, false, n, b, b, 1.0, X.ptr, b, sX, J.ptr, b,
-         (int64_t)b * b, 0.0, V.ptr, b, sX, nc);
+    {
+      PrecScope f64(dev, PREC_FP64);
+      gemm(dev, false, false, n, b, b, 1.0, X.ptr, b, sX, J.ptr, b,
+           (int64_t)b * b, 0.0, V.ptr, b, sX, nc);
+    }
     if (direct) break;
     gemm_ptrs(dev, true, false, n, b, n, 1.0, cb.Qa, n, cptrs(U), b, 0.0,
               ptrs(T1), b);
@@ -125,7 +136,9 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
                  nc, sX, b);
     dev.download(res, hres.data());
     worst = *std::max_element(hres.begin(), hres.end());
-    if (worst <= prm.tol || it >= prm.max_iter) break;
+    if (worst <= tol || it >= prm.max_iter) break;
+    if (lowp && it >= 3 && worst > 0.5 * prev) break;
+    prev = worst;
     // fresh buffer: X may alias the previous call's V, which the backward
     // tape keeps
     Tensor Xn, Jz, Sz;
