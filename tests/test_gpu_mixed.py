@@ -57,7 +57,8 @@ def test_fp32_gemm_error_bound(tA, tB, M, N, K):
     assert np.max(err) > 0.0
 
 
-@pytest.mark.parametrize("name", ["d2chi8", "d4chi32", "d6chi72"])
+@pytest.mark.parametrize("name", ["d2chi8", "d4chi32", "d6chi72",
+                                  "kitaev2x2"])
 def test_fp32_step_against_golden(name):
     _say(f"fp32 step vs golden {name}")
     gold = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
