@@ -362,6 +362,7 @@ int ipeps_profile_enable(ipeps_ctx* c, int on) {
     cx.dev.sync();
     cx.dev.prof.clear();
     cx.dev.prof.on = on != 0;
+    if (on) cx.dev.prof.reserve(1 << 17);
     return IPEPS_OK;
   });
 }

@@ -124,6 +124,14 @@ void Profiler::clear() {
   recs.clear();
 }
 
+void Profiler::reserve(size_t n) {
+  while (pool.size() < n) {
+    hipEvent_t e;
+    IPEPS_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+}
+
 Profiler::~Profiler() {
   clear();
   for (auto e : pool) (void)hipEventDestroy(e);

@@ -110,6 +110,8 @@ struct Profiler {
   // launches, seconds, flop, bytes of one family (synchronises)
   void read(int fam, long* n, double* sec, double* flop, double* bytes);
   void clear();
+  // create events ahead so that recording adds no hipEventCreate calls
+  void reserve(size_t n);
   ~Profiler();
 };
 
@@ -234,6 +236,10 @@ void splitk_reduce(Device& dev, const double* part, int S, int64_t M,
 namespace ipeps {
 void null_threshold(Device& dev, double* S, int b, double rel, int batch,
                     int64_t sS);
+// R = L^-T from the Cholesky factor of G = L L^T (b x b, batched); dropped
+// (dependent) directions give zero rows and columns.
+void chol_orth_factor(Device& dev, const double* G, double* R, int b,
+                      int batch);
 }  // namespace ipeps
 
 namespace ipeps {

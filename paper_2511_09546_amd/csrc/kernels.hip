@@ -452,6 +452,76 @@ void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
 
 namespace ipeps {
 
+// Orthonormalising factor of a block with unit columns: from its Gram
+// matrix G = Z^T Z (b x b, diagonal 1 or 0), the Cholesky factor G = L L^T
+// and R = L^-T, so that Z R has orthonormal columns.  One workgroup per
+// matrix, G in LDS.  A pivot below 1e-12 (a column that is zero or lies in
+// the span of the earlier ones) drops that direction: its row and column of
+// R are zero and Z R has a zero column there.  The inverse is formed by
+// column-wise forward substitution into the free upper triangle of G.
+__global__ __launch_bounds__(256) void chol_orth_kernel(
+    const double* __restrict__ Gall, double* __restrict__ Rall, int b) {
+  extern __shared__ double lds[];
+  double* G = lds;       // b*b
+  double* dg = G + b * b;  // b: pivots
+  const int bt = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const double* Gg = Gall + (long)bt * b * b;
+  double* R = Rall + (long)bt * b * b;
+  for (int i = tid; i < b * b; i += nt) G[i] = Gg[i];
+  __syncthreads();
+  for (int k = 0; k < b; ++k) {
+    if (tid == 0) {
+      const double d = G[k * b + k];
+      dg[k] = d > 1e-12 ? sqrt(d) : 0.0;
+    }
+    __syncthreads();
+    const double p = dg[k];
+    for (int i = k + 1 + tid; i < b; i += nt)
+      G[i * b + k] = p > 0.0 ? G[i * b + k] / p : 0.0;
+    __syncthreads();
+    // trailing lower triangle: G[i][j] -= L[i][k] L[j][k], k < j <= i
+    const int m = b - k - 1;
+    for (int e = tid; e < m * m; e += nt) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) G[i * b + j] -= G[i * b + k] * G[j * b + k];
+    }
+    __syncthreads();
+  }
+  // Y = L^-1 by columns: thread j owns column j, stored transposed in the
+  // upper triangle (Y[i][j] at G[j][i], i >= j; the diagonal slot is free
+  // because the pivots live in dg)
+  for (int j = tid; j < b; j += nt) {
+    for (int i = j; i < b; ++i) {
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) acc -= G[i * b + k] * G[j * b + k];
+      const double y = dg[i] > 0.0 ? acc / dg[i] : 0.0;
+      G[j * b + i] = y;
+    }
+  }
+  __syncthreads();
+  // R = L^-T: R[j][i] = Y[i][j] for i >= j, else 0
+  for (int e = tid; e < b * b; e += nt) {
+    const int j = e / b, i = e % b;
+    R[e] = i >= j ? G[j * b + i] : 0.0;
+  }
+}
+
+void chol_orth_factor(Device& dev, const double* G, double* R, int b,
+                      int batch) {
+  if (b < 1 || b > 128) throw ArgError("chol_orth_factor: b must be <= 128");
+  const size_t lds = ((size_t)b * b + b) * sizeof(double);
+  static size_t lds_set = 0;
+  if (lds > 65536 && lds > lds_set) {
+    IPEPS_HIP(hipFuncSetAttribute((const void*)chol_orth_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    lds_set = lds;
+  }
+  hipLaunchKernelGGL(chol_orth_kernel, dim3(batch), dim3(256), lds,
+                     dev.stream, G, R, b);
+  IPEPS_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------- SVD helper kernels
 // Deterministic pseudo-random start block: splitmix64 of (seed, index)
 // mapped to (-1, 1).

@@ -6,7 +6,8 @@
 //   W = M X = Qa (Qb X)                       (two GEMMs)
 //   W J = U diag(s)   (tall-skinny SVD, below), V = X J
 //   Z = M^T U = Qb^T (Qa^T U)                 (two GEMMs)
-//   stop when max_{i<chi} ||Z_i - s_i V_i|| <= tol * s_1, else X = orth(Z).
+//   stop when max_{i<chi} ||Z_i - s_i V_i|| <= tol * s_1, else X = orth(Z)
+//   (Cholesky QR of the column-normalised Z).
 // When the block covers the whole space (b >= n) X is the identity and one
 // pass gives the exact SVD.
 //
@@ -56,6 +57,25 @@ void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
   // normalising them would inject non-orthogonal noise into the subspace
   null_threshold(dev, S.ptr, b, 1e-13, batch, b);
   col_scale(dev, U.ptr, n, b, S.ptr, 0, nullptr, batch, sW, b);
+}
+
+void orth_block(Device& dev, const Tensor& Z, int batch, int64_t n, int b,
+                Tensor& X) {
+  PrecScope f64(dev, PREC_FP64);
+  const int64_t sZ = n * b, sG = (int64_t)b * b;
+  Tensor cn = dev.empty({batch, b});
+  col_norms(dev, Z.ptr, n, b, cn.ptr, batch, sZ, b);
+  null_threshold(dev, cn.ptr, b, 1e-13, batch, b);
+  Tensor Zs = dev.empty({batch, n, b});
+  axpby(dev, batch * sZ, 1.0, Z.ptr, 0.0, Zs.ptr);
+  col_scale(dev, Zs.ptr, n, b, cn.ptr, 0, nullptr, batch, sZ, b);
+  Tensor G = dev.empty({batch, b, b}), R = dev.empty({batch, b, b});
+  gemm(dev, true, false, b, b, n, 1.0, Zs.ptr, b, sZ, Zs.ptr, b, sZ, 0.0,
+       G.ptr, b, sG, batch);
+  chol_orth_factor(dev, G.ptr, R.ptr, b, batch);
+  X = dev.empty({batch, n, b});
+  gemm(dev, false, false, n, b, b, 1.0, Zs.ptr, b, sZ, R.ptr, b, sG, 0.0,
+       X.ptr, b, sZ, batch);
 }
 
 int subspace_block(int n, int chi, int oversample) {
@@ -139,10 +159,13 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
     if (worst <= tol || it >= prm.max_iter) break;
     if (lowp && it >= 3 && worst > 0.5 * prev) break;
     prev = worst;
-    // fresh buffer: X may alias the previous call's V, which the backward
-    // tape keeps
-    Tensor Xn, Jz, Sz;
-    svd_ts(dev, Z, nc, n, b, Xn, Sz, Jz);
+    // next block: an orthonormal basis of span(Z) (Cholesky QR of the
+    // column-normalised Z, whose columns are nearly orthogonal since
+    // Z ~ V S); the Rayleigh-Ritz step of the next pass makes the result
+    // independent of the basis chosen.  Fresh buffer: X may alias the
+    // previous call's V, which the backward tape keeps
+    Tensor Xn;
+    orth_block(dev, Z, nc, n, b, Xn);
     X = Xn;
   }
   sign_fix(dev, U.ptr, V.ptr, n, b, nc, sX, sX);
