@@ -181,9 +181,10 @@ void nrm2(Device& dev, const double* x, int64_t n, double* out);
 // workgroup per matrix: G[bt] (b x b row major, b even, b <= 128) is
 // overwritten by its diagonalised form, V[bt] (b x b row major) receives
 // the eigenvectors as columns, lam[bt] the eigenvalues; both sorted by
-// descending eigenvalue.
+// descending eigenvalue.  Pairs with |G_pq| <= tol sqrt|G_pp G_qq| are not
+// rotated.
 void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
-                    int batch);
+                    int batch = 1, double tol = 1e-15);
 
 // Column 2-norms of an n x b row-major matrix: out[j] = ||X[:, j]||.
 void col_norms(Device& dev, const double* X, int64_t n, int b, double* out,

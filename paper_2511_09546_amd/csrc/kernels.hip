@@ -45,6 +45,56 @@ static int grid_for(int64_t n, int block) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
 }
 
+// Tiled permute for the case where the output's innermost dimension is not
+// the input's: a 32 x 32 tile over (q = the output dimension that is
+// innermost in the input, l = the innermost output dimension) goes through
+// LDS, so that reads run along q and writes along l, both coalesced.  The
+// remaining output dimensions enumerate tiles in blockIdx.y (div/mod once
+// per block).
+struct TileArgs {
+  int rank;            // remaining dimensions
+  int shape[12];
+  long in_stride[12];
+  long out_stride[12];
+  int nq, nl;          // extents of q and l
+  long sq_out;         // output stride of q (input stride of q is 1)
+  long sl_in;          // input stride of l (output stride of l is 1)
+  int tq, tl;          // tiles along q and l
+};
+
+__global__ __launch_bounds__(256) void permute_tiled_kernel(
+    const double* __restrict__ in, double* __restrict__ out, TileArgs a,
+    double alpha, double beta) {
+  __shared__ double tile[32][33];
+  long rest = blockIdx.y;
+  long oin = 0, oout = 0;
+  for (int d = a.rank - 1; d >= 0; --d) {
+    const long q = rest / a.shape[d];
+    const long i = rest - q * a.shape[d];
+    oin += i * a.in_stride[d];
+    oout += i * a.out_stride[d];
+    rest = q;
+  }
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int q0 = (blockIdx.x / a.tl) * 32, l0 = (blockIdx.x % a.tl) * 32;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int l = l0 + ty + 8 * j, q = q0 + tx;
+    if (l < a.nl && q < a.nq) tile[ty + 8 * j][tx] = in[oin + q + l * a.sl_in];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int q = q0 + ty + 8 * j, l = l0 + tx;
+    if (l < a.nl && q < a.nq) {
+      double* o = out + oout + q * a.sq_out + l;
+      double v = alpha * tile[tx][ty + 8 * j];
+      if (beta != 0.0) v += beta * *o;
+      *o = v;
+    }
+  }
+}
+
 void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
              Tensor& out, double alpha, double beta) {
   const int r = in.rank();
@@ -85,6 +135,46 @@ void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
     return;
   }
   if (oshape.size() > 12) throw ArgError("permute: rank > 12");
+  // output dimension that is innermost in the input
+  int qd = -1;
+  for (int i = 0; i < (int)oshape.size(); ++i)
+    if (ostr[i] == 1) qd = i;
+  const int ld = (int)oshape.size() - 1;
+  if (qd >= 0 && qd != ld && oshape[qd] >= 4 && oshape[ld] >= 4) {
+    TileArgs a{};
+    std::vector<int64_t> ostride(oshape.size());
+    int64_t st = 1;
+    for (int i = ld; i >= 0; --i) {
+      ostride[i] = st;
+      st *= oshape[i];
+    }
+    a.nq = (int)oshape[qd];
+    a.nl = (int)oshape[ld];
+    a.sq_out = ostride[qd];
+    a.sl_in = ostr[ld];
+    a.tq = (a.nq + 31) / 32;
+    a.tl = (a.nl + 31) / 32;
+    int64_t nrest = 1;
+    for (int i = 0; i < ld; ++i) {
+      if (i == qd) continue;
+      a.shape[a.rank] = (int)oshape[i];
+      a.in_stride[a.rank] = ostr[i];
+      a.out_stride[a.rank] = ostride[i];
+      ++a.rank;
+      nrest *= oshape[i];
+    }
+    if (nrest > 65535) goto generic;
+    if (dev.prof.on)
+      dev.prof.begin(dev.stream, PROF_PERMUTE, 0.0,
+                     8.0 * n * (beta != 0.0 ? 3 : 2));
+    hipLaunchKernelGGL(permute_tiled_kernel, dim3(a.tq * a.tl, (int)nrest),
+                       dim3(256), 0, dev.stream, in.ptr, out.ptr, a, alpha,
+                       beta);
+    if (dev.prof.on) dev.prof.end(dev.stream);
+    IPEPS_HIP(hipGetLastError());
+    return;
+  }
+generic:
   PermArgs p{};
   p.rank = (int)oshape.size();
   for (int i = 0; i < p.rank; ++i) {
@@ -283,18 +373,24 @@ void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
 // (Golub & Van Loan, symmetric Schur 2x2): G_pq is set to zero and the two
 // diagonal entries take their closed forms G_pp - t G_pq, G_qq + t G_pq, so
 // no rounding noise re-creates the annihilated entry; a pair is skipped when
-// |G_pq| <= 1e-15 sqrt|G_pp G_qq| (relative criterion, so small eigenvalues
-// of graded matrices keep their relative accuracy).  Stops after a sweep
-// without rotations (or 40 sweeps).  G lives in LDS; the eigenvector matrix
-// V too when b <= 96 (2 b^2 doubles fit the 160 KB of LDS), else in global
-// memory.
+// |G_pq| <= tol sqrt|G_pp G_qq| (relative criterion, so small eigenvalues of
+// graded matrices keep their relative accuracy).  Stops after a sweep
+// without rotations (or 40 sweeps).
+//
+// One round is a single pass over the 2x2 blocks of G: with R_i the row
+// combination of pair i, block (a, c) becomes R_a G_ac R_c^T, and the
+// diagonal blocks take the closed forms above; blocks are disjoint, so a
+// round needs one barrier after the rotation parameters and one after the
+// update (each element of G and V is read and written once per round).
+// G lives in LDS; the eigenvector matrix V too when b <= 96 (2 b^2 doubles
+// fit the 160 KB of LDS), else in global memory.
 constexpr int JAC_THREADS = 512;
 constexpr int JAC_MAXB = 128;
 
 template <bool VLDS>
 __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
     double* __restrict__ Gall, double* __restrict__ Vall,
-    double* __restrict__ lamall, int b) {
+    double* __restrict__ lamall, int b, double tol) {
   extern __shared__ double lds[];
   double* G = lds;                  // b*b
   double* cs = G + b * b;           // b/2
@@ -338,7 +434,7 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
         dp[i] = app;
         dq[i] = aqq;
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && apq != 0.0) {
+        if (fabs(apq) > tol * sqrt(fabs(app * aqq)) && apq != 0.0) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) /
                            (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -352,38 +448,42 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
         tq[i] = s != 0.0 ? (s / c) * apq : 0.0;
       }
       __syncthreads();
-      // rows: G <- J^T G
-      for (int e = tid; e < half * b; e += nt) {
-        const int i = e / b, k = e % b;
-        const double c = cs[i], s = sn[i];
-        if (s == 0.0) continue;
-        const int p = pp[i], q = qq[i];
-        const double gp = G[p * b + k], gq = G[q * b + k];
-        G[p * b + k] = c * gp - s * gq;
-        G[q * b + k] = s * gp + c * gq;
+      // G <- R G R^T block by block
+      for (int e = tid; e < half * half; e += nt) {
+        const int a = e / half, c2 = e % half;
+        const double sa = sn[a], sc = sn[c2];
+        if (sa == 0.0 && sc == 0.0) continue;
+        const int pa = pp[a], qa = qq[a];
+        if (a == c2) {
+          G[pa * b + qa] = 0.0;
+          G[qa * b + pa] = 0.0;
+          G[pa * b + pa] = dp[a] - tq[a];
+          G[qa * b + qa] = dq[a] + tq[a];
+          continue;
+        }
+        const double ca = cs[a], cc = cs[c2];
+        const int pc = pp[c2], qc = qq[c2];
+        const double g00 = G[pa * b + pc], g01 = G[pa * b + qc];
+        const double g10 = G[qa * b + pc], g11 = G[qa * b + qc];
+        // rows: (R_a G)
+        const double h00 = ca * g00 - sa * g10, h01 = ca * g01 - sa * g11;
+        const double h10 = sa * g00 + ca * g10, h11 = sa * g01 + ca * g11;
+        // columns: (R_a G) R_c^T
+        G[pa * b + pc] = cc * h00 - sc * h01;
+        G[pa * b + qc] = sc * h00 + cc * h01;
+        G[qa * b + pc] = cc * h10 - sc * h11;
+        G[qa * b + qc] = sc * h10 + cc * h11;
       }
-      __syncthreads();
-      // columns: G <- G J, V <- V J
+      // V <- V R^T (columns p, q of every row)
       for (int e = tid; e < half * b; e += nt) {
         const int i = e % half, k = e / half;
-        const double c = cs[i], s = sn[i];
+        const double s = sn[i];
         if (s == 0.0) continue;
+        const double c = cs[i];
         const int p = pp[i], q = qq[i];
-        const double gp = G[k * b + p], gq = G[k * b + q];
-        G[k * b + p] = c * gp - s * gq;
-        G[k * b + q] = s * gp + c * gq;
         const double vp = V[k * b + p], vq = V[k * b + q];
         V[k * b + p] = c * vp - s * vq;
         V[k * b + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      for (int i = tid; i < half; i += nt) {
-        if (sn[i] == 0.0) continue;
-        const int p = pp[i], q = qq[i];
-        G[p * b + q] = 0.0;
-        G[q * b + p] = 0.0;
-        G[p * b + p] = dp[i] - tq[i];
-        G[q * b + q] = dq[i] + tq[i];
       }
       __syncthreads();
     }
@@ -421,7 +521,7 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
 }
 
 void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
-                    int batch) {
+                    int batch, double tol) {
   if (b % 2 != 0 || b < 2 || b > JAC_MAXB)
     throw ArgError("sym_eig_jacobi: b must be even and <= 128");
   const bool vlds = b <= 96;
@@ -440,10 +540,10 @@ void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
   if (dev.prof.on) dev.prof.begin(dev.stream, PROF_JACOBI, 0.0, 0.0);
   if (vlds)
     hipLaunchKernelGGL(sym_eig_jacobi_kernel<true>, dim3(batch),
-                       dim3(JAC_THREADS), lds, dev.stream, G, V, lam, b);
+                       dim3(JAC_THREADS), lds, dev.stream, G, V, lam, b, tol);
   else
     hipLaunchKernelGGL(sym_eig_jacobi_kernel<false>, dim3(batch),
-                       dim3(JAC_THREADS), lds, dev.stream, G, V, lam, b);
+                       dim3(JAC_THREADS), lds, dev.stream, G, V, lam, b, tol);
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
 }
