@@ -374,8 +374,8 @@ void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
 // diagonal entries take their closed forms G_pp - t G_pq, G_qq + t G_pq, so
 // no rounding noise re-creates the annihilated entry; a pair is skipped when
 // |G_pq| <= tol sqrt|G_pp G_qq| (relative criterion, so small eigenvalues of
-// graded matrices keep their relative accuracy).  Stops after a sweep
-// without rotations (or 40 sweeps).
+// graded matrices keep their relative accuracy).  Stops when no pair meets
+// the criterion, which is tested before every sweep (or after 40 sweeps).
 //
 // One round is a single pass over the 2x2 blocks of G: with R_i the row
 // combination of pair i, block (a, c) becomes R_a G_ac R_c^T, and the
@@ -415,8 +415,22 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
   __syncthreads();
   const int half = b / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
+    // a sweep rotates some pair iff some pair exceeds the criterion now (if
+    // none does, the first round changes nothing and neither do the
+    // others): test all pairs first instead of running a sweep to find out
     if (tid == 0) rotated = 0;
     __syncthreads();
+    for (int e = tid; e < b * b; e += nt) {
+      const int p = e / b, q = e % b;
+      if (p < q) {
+        const double apq = G[e];
+        if (fabs(apq) > tol * sqrt(fabs(G[p * b + p] * G[q * b + q])) &&
+            apq != 0.0)
+          rotated = 1;
+      }
+    }
+    __syncthreads();
+    if (!rotated) break;
     for (int r = 0; r < b - 1; ++r) {
       // pairs of this round, rotation parameters from the current G
       for (int i = tid; i < half; i += nt) {
@@ -440,7 +454,6 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
                            (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
-          rotated = 1;
         }
         cs[i] = c;
         sn[i] = s;
@@ -448,47 +461,56 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
         tq[i] = s != 0.0 ? (s / c) * apq : 0.0;
       }
       __syncthreads();
-      // G <- R G R^T block by block
-      for (int e = tid; e < half * half; e += nt) {
-        const int a = e / half, c2 = e % half;
-        const double sa = sn[a], sc = sn[c2];
-        if (sa == 0.0 && sc == 0.0) continue;
-        const int pa = pp[a], qa = qq[a];
-        if (a == c2) {
-          G[pa * b + qa] = 0.0;
-          G[qa * b + pa] = 0.0;
-          G[pa * b + pa] = dp[a] - tq[a];
-          G[qa * b + qa] = dq[a] + tq[a];
-          continue;
+      // G <- R G R^T block by block: thread (ya, xc) = (tid / 32, tid % 32)
+      // takes pairs a = ya + 16 i and c = xc + 32 j, parameters in registers
+      {
+        const int ya = tid >> 5, xc = tid & 31;
+        for (int a = ya; a < half; a += 16) {
+          const double sa = sn[a], ca = cs[a];
+          const int pa = pp[a], qa = qq[a];
+          for (int c2 = xc; c2 < half; c2 += 32) {
+            const double sc = sn[c2];
+            if (sa == 0.0 && sc == 0.0) continue;
+            if (a == c2) {
+              G[pa * b + qa] = 0.0;
+              G[qa * b + pa] = 0.0;
+              G[pa * b + pa] = dp[a] - tq[a];
+              G[qa * b + qa] = dq[a] + tq[a];
+              continue;
+            }
+            const double cc = cs[c2];
+            const int pc = pp[c2], qc = qq[c2];
+            const double g00 = G[pa * b + pc], g01 = G[pa * b + qc];
+            const double g10 = G[qa * b + pc], g11 = G[qa * b + qc];
+            // rows: (R_a G)
+            const double h00 = ca * g00 - sa * g10, h01 = ca * g01 - sa * g11;
+            const double h10 = sa * g00 + ca * g10, h11 = sa * g01 + ca * g11;
+            // columns: (R_a G) R_c^T
+            G[pa * b + pc] = cc * h00 - sc * h01;
+            G[pa * b + qc] = sc * h00 + cc * h01;
+            G[qa * b + pc] = cc * h10 - sc * h11;
+            G[qa * b + qc] = sc * h10 + cc * h11;
+          }
         }
-        const double ca = cs[a], cc = cs[c2];
-        const int pc = pp[c2], qc = qq[c2];
-        const double g00 = G[pa * b + pc], g01 = G[pa * b + qc];
-        const double g10 = G[qa * b + pc], g11 = G[qa * b + qc];
-        // rows: (R_a G)
-        const double h00 = ca * g00 - sa * g10, h01 = ca * g01 - sa * g11;
-        const double h10 = sa * g00 + ca * g10, h11 = sa * g01 + ca * g11;
-        // columns: (R_a G) R_c^T
-        G[pa * b + pc] = cc * h00 - sc * h01;
-        G[pa * b + qc] = sc * h00 + cc * h01;
-        G[qa * b + pc] = cc * h10 - sc * h11;
-        G[qa * b + qc] = sc * h10 + cc * h11;
       }
-      // V <- V R^T (columns p, q of every row)
-      for (int e = tid; e < half * b; e += nt) {
-        const int i = e % half, k = e / half;
-        const double s = sn[i];
-        if (s == 0.0) continue;
-        const double c = cs[i];
-        const int p = pp[i], q = qq[i];
-        const double vp = V[k * b + p], vq = V[k * b + q];
-        V[k * b + p] = c * vp - s * vq;
-        V[k * b + q] = s * vp + c * vq;
+      // V <- V R^T (columns p, q of every row k): thread (yk, xi) =
+      // (tid / 16, tid % 16) takes rows k = yk + 32 i and pairs xi + 16 j
+      {
+        const int yk = tid >> 4, xi = tid & 15;
+        for (int i = xi; i < half; i += 16) {
+          const double s = sn[i];
+          if (s == 0.0) continue;
+          const double c = cs[i];
+          const int p = pp[i], q = qq[i];
+          for (int k = yk; k < b; k += 32) {
+            const double vp = V[k * b + p], vq = V[k * b + q];
+            V[k * b + p] = c * vp - s * vq;
+            V[k * b + q] = s * vp + c * vq;
+          }
+        }
       }
       __syncthreads();
     }
-    if (!rotated) break;
-    __syncthreads();
   }
   // sort by descending eigenvalue (stable rank of every diagonal entry);
   // pp/qq and cs/sn are contiguous, giving b ints and b doubles of LDS
