@@ -174,6 +174,15 @@ int ipeps_set_env(ipeps_ctx* ctx, const double* in);
 /* Size in doubles of the environment buffer of ipeps_get_env. */
 size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
 
+/* Device bytes a context needs at its peak (the ipeps_energy_grad call,
+ * which keeps every intermediate of the K = opts->grad_K unrolled CTMRG
+ * iterations): an upper estimate for admission decisions, 8 bytes times
+ * n_sites * chi^2 D^4 * (64 K + 64) plus the double-layer tensors
+ * (n_sites * 4 (d^2 + 1) D^8) and the environment.  opts NULL = defaults.
+ * Returns 0 for invalid sizes.  Host-only; no device call. */
+size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
+                             const ipeps_opts* opts);
+
 /* Kernel timing of the context's own launches, for roofline reports: with
  * on = 1 the context records HIP events on its stream around every launch
  * of the timed kernel families (clearing earlier records); on = 0 stops.

@@ -27,7 +27,7 @@ API_FUNCTIONS = [
     "ipeps_get_env", "ipeps_set_env", "ipeps_env_size", "ctm_free",
     "ipeps_strerror", "ipeps_version", "ipeps_profile_enable",
     "ipeps_profile_read", "ctm_set_state_dev", "ipeps_energy_grad_dev",
-    "precond_apply_dev",
+    "precond_apply_dev", "ipeps_footprint_bytes",
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32 = 0, 1, 2, 3
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
@@ -82,6 +82,9 @@ def load():
     lib.ipeps_set_env.argtypes = [c_void_p, _DP]
     lib.ipeps_env_size.argtypes = [c_int, c_int, c_int, c_int]
     lib.ipeps_env_size.restype = c_size_t
+    lib.ipeps_footprint_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int,
+                                          c_void_p]
+    lib.ipeps_footprint_bytes.restype = c_size_t
     lib.ctm_free.argtypes = [c_void_p]
     lib.ctm_free.restype = None
     lib.ipeps_strerror.argtypes = [c_int]
@@ -136,6 +139,12 @@ def default_opts() -> Opts:
     o = Opts()
     load().ipeps_default_opts(ctypes.byref(o))
     return o
+
+
+def footprint_bytes(Lx, Ly, d, D, chi, opts=None) -> int:
+    """Peak device bytes of one context (ipeps_footprint_bytes)."""
+    return int(load().ipeps_footprint_bytes(
+        Lx, Ly, d, D, chi, ctypes.byref(opts) if opts is not None else None))
 
 
 def make_terms(terms):
@@ -293,13 +302,14 @@ class Context:
         return n.value, sec.value, fl.value, by.value
 
     def stats(self) -> dict:
-        out = np.zeros(6)
+        out = np.zeros(7)
         st = load().ipeps_debug_stats(self._h, _dp(out))
         if st != OK:
             raise IpepsError(st, "ipeps_debug_stats")
         return dict(svd_iters=int(out[0]), svd_calls=int(out[1]),
                     svd_worst_residual=float(out[2]), cg_iters=int(out[3]),
-                    cg_solves=int(out[4]), pool_bytes=int(out[5]))
+                    cg_solves=int(out[4]), pool_bytes=int(out[5]),
+                    peak_live_bytes=int(out[6]))
 
     def set_env(self, C, T):
         buf = np.concatenate([_f64(C).ravel(), _f64(T).ravel()])

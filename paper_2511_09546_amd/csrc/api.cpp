@@ -82,6 +82,21 @@ size_t ipeps_env_size(int Lx, int Ly, int D, int chi) {
   return 4 * n * chi * chi + 4 * n * chi * (size_t)D * D * chi;
 }
 
+size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
+                             const ipeps_opts* opts) {
+  if (Lx < 1 || Ly < 1 || d < 1 || D < 1 || chi < 1) return 0;
+  ipeps_opts o;
+  ipeps_default_opts(&o);
+  if (opts) o = *opts;
+  const double ns = (double)Lx * Ly, D2 = (double)D * D, D4 = D2 * D2;
+  const double q = (double)chi * chi * D4;  // one enlarged corner
+  const double K = o.grad_K > 0 ? o.grad_K : 0;
+  const double dbl = ns * 4.0 * ((double)d * d + 1.0) * D4 * D4;
+  const double words = ns * q * (64.0 * K + 64.0) + dbl +
+                       (double)ipeps_env_size(Lx, Ly, D, chi);
+  return (size_t)(8.0 * words);
+}
+
 int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
              const double* A, const ipeps_opts* opts, void* hip_stream) {
   if (!out || !A || Lx < 1 || Ly < 1 || d < 1 || D < 1 || chi < D * D ||
@@ -131,9 +146,11 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
   });
   if (st != IPEPS_OK) {
     if (c) {
-      if (c->cx.dev.own_stream && c->cx.dev.stream)
-        (void)hipStreamDestroy(c->cx.dev.stream);
+      hipStream_t s = c->cx.dev.stream;
+      const bool own = c->cx.dev.own_stream;
+      if (s) (void)hipStreamSynchronize(s);  // blocks are idle before reuse
       delete c;
+      if (own && s) (void)hipStreamDestroy(s);
     }
     return st;
   }
@@ -388,6 +405,7 @@ int ipeps_debug_stats(ipeps_ctx* c, double* out) {
   out[3] = (double)st.cg_iters;
   out[4] = (double)st.cg_solves;
   out[5] = (double)c->cx.dev.pool.reserved();
+  out[6] = (double)c->cx.dev.pool.peak_live();
   return IPEPS_OK;
 }
 

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cstring>
 #include <limits>
+#include <mutex>
 
 #include "engine.hpp"
 
@@ -19,46 +20,83 @@ static size_t round_bytes(size_t b) {
   return b;
 }
 
-void* Pool::alloc(size_t bytes) {
+// Blocks of destroyed contexts, kept for later contexts of the process (a
+// context is destroyed only after its stream has drained, so its blocks are
+// idle).  Trimmed when hipMalloc runs out of memory.
+namespace {
+std::mutex g_idle_mu;
+std::multimap<size_t, void*> g_idle;
+
+bool take_idle(size_t bytes, void** p, size_t* got) {
+  std::lock_guard<std::mutex> lock(g_idle_mu);
+  auto it = g_idle.lower_bound(bytes);
+  if (it == g_idle.end() || it->first > bytes + bytes / 8) return false;
+  *p = it->second;
+  *got = it->first;
+  g_idle.erase(it);
+  return true;
+}
+
+void trim_idle() {
+  std::lock_guard<std::mutex> lock(g_idle_mu);
+  for (auto& kv : g_idle) (void)hipFree(kv.second);
+  g_idle.clear();
+}
+}  // namespace
+
+void* Pool::alloc(size_t bytes, size_t* got) {
   bytes = round_bytes(std::max<size_t>(bytes, 8));
-  auto it = free_.find(bytes);
-  if (it != free_.end()) {
+  auto it = free_.lower_bound(bytes);
+  if (it != free_.end() && it->first <= bytes + bytes / 8) {
     void* p = it->second;
+    *got = it->first;
     free_.erase(it);
+    live_ += *got;
+    peak_live_ = std::max(peak_live_, live_);
     return p;
   }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    // return cached blocks to HIP and retry once
-    for (auto& kv : free_) {
-      (void)hipFree(kv.second);
-      for (auto a = all_.begin(); a != all_.end(); ++a)
-        if (a->first == kv.second) {
-          reserved_ -= a->second;
-          all_.erase(a);
-          break;
-        }
-    }
-    free_.clear();
-    e = hipMalloc(&p, bytes);
+  size_t size = bytes;
+  if (!take_idle(bytes, &p, &size)) {
+    hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      throw OomError("hipMalloc of " + std::to_string(bytes) + " bytes");
+      // return cached blocks (this context's and the idle ones) to HIP and
+      // retry once
+      trim_idle();
+      for (auto& kv : free_) {
+        (void)hipFree(kv.second);
+        for (auto a = all_.begin(); a != all_.end(); ++a)
+          if (a->first == kv.second) {
+            reserved_ -= a->second;
+            all_.erase(a);
+            break;
+          }
+      }
+      free_.clear();
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw OomError("hipMalloc of " + std::to_string(bytes) + " bytes");
+      }
     }
   }
-  all_.emplace_back(p, bytes);
-  reserved_ += bytes;
+  all_.emplace_back(p, size);
+  reserved_ += size;
+  *got = size;
+  live_ += size;
+  peak_live_ = std::max(peak_live_, live_);
   return p;
 }
 
-void Pool::release(void* p, size_t bytes) {
-  free_.emplace(round_bytes(std::max<size_t>(bytes, 8)), p);
+void Pool::release(void* p, size_t block_bytes) {
+  live_ -= block_bytes;
+  free_.emplace(block_bytes, p);
 }
 
 Pool::~Pool() {
-  for (auto& a : all_) (void)hipFree(a.first);
+  std::lock_guard<std::mutex> lock(g_idle_mu);
+  for (auto& a : all_) g_idle.emplace(a.second, a.first);
 }
 
 // ----------------------------------------------------------------- Tensor
@@ -143,8 +181,9 @@ Tensor Device::empty(std::vector<int64_t> shape) {
   t.shape = std::move(shape);
   const size_t bytes = (size_t)std::max<int64_t>(t.numel(), 1) * 8;
   auto b = std::make_shared<Buffer>();
-  b->p = pool.alloc(bytes);
-  b->bytes = bytes;
+  size_t got = 0;
+  b->p = pool.alloc(bytes, &got);
+  b->bytes = got;
   b->pool = &pool;
   t.buf = b;
   t.ptr = (double*)b->p;

@@ -36,27 +36,33 @@ struct NotImplError : std::runtime_error {
                               hipGetErrorString(e__));                    \
   } while (0)
 
-// Caching device allocator owned by one context.  Blocks are kept by exact
-// (rounded) size and reused; everything is returned to HIP at destruction.
+// Caching device allocator owned by one context: freed blocks are kept and
+// handed out again (best fit, at most 1/8 larger than the request), so the
+// reservation stays close to the peak of live bytes.  At destruction (after
+// the context's stream has drained) the blocks go to a process-wide idle
+// list that later contexts draw from before calling hipMalloc; the idle list
+// is returned to HIP when an allocation runs out of memory.
 class Pool {
  public:
   Pool() = default;
   Pool(const Pool&) = delete;
   Pool& operator=(const Pool&) = delete;
   ~Pool();
-  void* alloc(size_t bytes);
-  void release(void* p, size_t bytes);
+  // returns a block of *got >= bytes bytes
+  void* alloc(size_t bytes, size_t* got);
+  void release(void* p, size_t block_bytes);
   size_t reserved() const { return reserved_; }
+  size_t peak_live() const { return peak_live_; }
 
  private:
   std::multimap<size_t, void*> free_;
   std::vector<std::pair<void*, size_t>> all_;
-  size_t reserved_ = 0;
+  size_t reserved_ = 0, live_ = 0, peak_live_ = 0;
 };
 
 struct Buffer {
   void* p = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;  // block size
   Pool* pool = nullptr;
   ~Buffer() {
     if (p) pool->release(p, bytes);

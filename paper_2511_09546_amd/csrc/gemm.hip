@@ -44,7 +44,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int BK = 16;
 constexpr int KPAD = 1;   // row stride BK + 1 for operands read along K
 constexpr int MPAD = 2;   // row stride BM + 2 for operands read along M/N
 constexpr int MAXP = 16;  // pointer triples per launch
@@ -56,7 +55,7 @@ struct PtrArgs {
 };
 
 template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool F32,
-          bool KM>
+          bool KM, int BK>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
@@ -243,14 +242,16 @@ struct Call {
   const PtrArgs* ptrs;  // null: strided batch
 };
 
-template <int BM, int BN, int WM, int WN, bool F32, bool KM>
+template <int BM, int BN, int WM, int WN, bool F32, bool KM, int BK = 16>
 void launch_cfg(Device& dev, const Call& c) {
   const long tm = (c.M + BM - 1) / BM, tn = (c.N + BN - 1) / BN;
   const long tiles = tm * tn;
-  // split K until the grid covers the chip (>= 320 workgroups), keeping at
-  // least 256 of K per split
+  // split K until the grid covers the chip, keeping at least 256 of K per
+  // split
   int S = 1;
-  const long want = 320;
+  // workgroup target of the split (two or three waves of workgroups over the
+  // 256 CUs; measured best for the skinny n x n x chi products)
+  const long want = F32 ? 512 : 768;
   if (tiles * c.batch < want && c.K >= 512) {
     S = (int)std::min<long>((want + tiles * c.batch - 1) / (tiles * c.batch),
                             c.K / 256);
@@ -280,10 +281,10 @@ void launch_cfg(Device& dev, const Call& c) {
                        c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.beta,
                        c.C, c.ldc, c.sC, (int)tn, S, kchunk, part.ptr, up, pa);
   };
-  if (!c.tA && !c.tB) go(gemm_kernel<BM, BN, WM, WN, false, false, F32, KM>);
-  if (c.tA && !c.tB) go(gemm_kernel<BM, BN, WM, WN, true, false, F32, KM>);
-  if (!c.tA && c.tB) go(gemm_kernel<BM, BN, WM, WN, false, true, F32, KM>);
-  if (c.tA && c.tB) go(gemm_kernel<BM, BN, WM, WN, true, true, F32, KM>);
+  if (!c.tA && !c.tB) go(gemm_kernel<BM, BN, WM, WN, false, false, F32, KM, BK>);
+  if (c.tA && !c.tB) go(gemm_kernel<BM, BN, WM, WN, true, false, F32, KM, BK>);
+  if (!c.tA && c.tB) go(gemm_kernel<BM, BN, WM, WN, false, true, F32, KM, BK>);
+  if (c.tA && c.tB) go(gemm_kernel<BM, BN, WM, WN, true, true, F32, KM, BK>);
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
   if (S > 1) {

@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "engine.hpp"
 
@@ -367,6 +369,19 @@ void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
   IPEPS_HIP(hipGetLastError());
 }
 
+// Raises a kernel's dynamic LDS limit to at least `bytes` (once per kernel
+// and size; contexts on several host threads may get here together).
+static void allow_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& have = done[fn];
+  if (bytes <= have) return;
+  IPEPS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes));
+  have = bytes;
+}
+
 // ------------------------------------------------------- Jacobi eigensolver
 // Parallel cyclic Jacobi (round-robin pairing, b-1 rounds of b/2 disjoint
 // rotations per sweep).  The rotation of pair (p,q) annihilates G[p][q]
@@ -550,15 +565,9 @@ void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
   size_t lds = (size_t)b * b * sizeof(double) + 5 * (b / 2) * sizeof(double) +
                2 * ((b / 2) + (b / 2) % 2) * sizeof(int);
   if (vlds) lds += (size_t)b * b * sizeof(double);
-  static size_t lds_set[2] = {0, 0};
   const void* fn = vlds ? (const void*)sym_eig_jacobi_kernel<true>
                         : (const void*)sym_eig_jacobi_kernel<false>;
-  if (lds > 65536 && lds > lds_set[vlds]) {
-    IPEPS_HIP(hipFuncSetAttribute(fn,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds));
-    lds_set[vlds] = lds;
-  }
+  if (lds > 65536) allow_lds(fn, lds);
   if (dev.prof.on) dev.prof.begin(dev.stream, PROF_JACOBI, 0.0, 0.0);
   if (vlds)
     hipLaunchKernelGGL(sym_eig_jacobi_kernel<true>, dim3(batch),
@@ -632,13 +641,7 @@ void chol_orth_factor(Device& dev, const double* G, double* R, int b,
                       int batch) {
   if (b < 1 || b > 128) throw ArgError("chol_orth_factor: b must be <= 128");
   const size_t lds = ((size_t)b * b + b) * sizeof(double);
-  static size_t lds_set = 0;
-  if (lds > 65536 && lds > lds_set) {
-    IPEPS_HIP(hipFuncSetAttribute((const void*)chol_orth_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds));
-    lds_set = lds;
-  }
+  if (lds > 65536) allow_lds((const void*)chol_orth_kernel, lds);
   hipLaunchKernelGGL(chol_orth_kernel, dim3(batch), dim3(256), lds,
                      dev.stream, G, R, b);
   IPEPS_HIP(hipGetLastError());

@@ -1,0 +1,264 @@
+"""Request loop: many independent preconditioned steps sharing one GPU.
+
+Each request is one step of the method on its own state (CTMRG environment,
+energy and K-step gradient, preconditioned direction; Sec. III) and runs in
+its own library context on its own HIP stream, so up to `workers` requests
+execute concurrently and small ones fill the GPU while large ones run.
+Admission follows the device-memory footprint that ipeps_footprint_bytes
+predicts for each request: a request starts only when its footprint fits
+the budget next to those already running (first come first served, later
+requests may start ahead of a waiting large one when they fit).  Contexts
+are freed when their request ends.
+
+Warm starts: a request that carries a `state_key` seen before (same cell,
+D and chi) starts CTMRG from the environment that the earlier request left
+(kept on the host), instead of the trace boundary.  The environment depends
+only on the state, not on the Hamiltonian, so e.g. a sweep of couplings on
+one state converges in a few iterations after the first request.
+
+    python -m paper_2511_09546_amd.serve [--requests 256] [--rate 20]
+        [--workers 8] [--prec fp32] [--budget-gb 230] [--seed 5]
+
+replays a seeded stream of requests (exponential inter-arrival times, D in
+3..6, chi in 2D^2..3D^2, J1-J2 with J2 in [0, 0.6], random states) in real
+time and prints one JSON line: latency percentiles (finish - arrival),
+throughput and the admission statistics.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import concurrent.futures as cf
+import json
+import sys
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import binding
+
+
+@dataclass
+class Request:
+    A: np.ndarray                 # [Ly][Lx][d][D][D][D][D]
+    chi: int
+    terms: list                   # (kind, site, dx, dy, coef, mat) tuples
+    tol: float = 1e-10
+    max_iter: int = 200
+    delta: float = 1e-4
+    cg_tol: float = 0.0
+    cg_maxiter: int = 20
+    prec: int = binding.FP32
+    grad_K: int = 20
+    state_key: Optional[str] = None
+    arrival: float = field(default_factory=time.perf_counter)
+
+
+@dataclass
+class Result:
+    e: float
+    g: np.ndarray
+    x: np.ndarray
+    ctm_iters: int
+    delta: float
+    cg_iters: int
+    warm: bool
+    arrival: float
+    start: float
+    finish: float
+
+    @property
+    def latency(self) -> float:
+        return self.finish - self.arrival
+
+
+def _shape(A):
+    """(Lx, Ly, d, D) of a state [Ly][Lx][d][D][D][D][D]."""
+    A = np.asarray(A)
+    if A.ndim != 7:
+        raise ValueError("A must be [Ly, Lx, d, D, D, D, D]")
+    return A.shape[1], A.shape[0], A.shape[2], A.shape[3]
+
+
+class Server:
+    """Footprint-admitted concurrent execution of Requests."""
+
+    def __init__(self, budget_bytes: float, workers: int = 8):
+        binding.load()
+        self.budget = float(budget_bytes)
+        self.used = 0.0
+        self.workers = workers
+        self.running = 0
+        self.queue = collections.deque()
+        self.cv = threading.Condition()
+        self.envs = {}                 # state_key -> (shape key, C, T)
+        self.pool = cf.ThreadPoolExecutor(max_workers=workers)
+        self.closed = False
+        self.peak_used = 0.0
+        self.max_running = 0
+        self.sched = threading.Thread(target=self._schedule, daemon=True)
+        self.sched.start()
+
+    def footprint(self, req: Request) -> float:
+        Lx, Ly, d, D = _shape(req.A)
+        o = binding.default_opts()
+        o.grad_K = req.grad_K
+        return float(binding.footprint_bytes(Lx, Ly, d, D, req.chi, o))
+
+    def submit(self, req: Request) -> cf.Future:
+        fut = cf.Future()
+        fp = self.footprint(req)
+        if fp > self.budget:
+            fut.set_exception(MemoryError(
+                f"request needs {fp / 1e9:.1f} GB, budget "
+                f"{self.budget / 1e9:.1f} GB"))
+            return fut
+        with self.cv:
+            self.queue.append((req, fp, fut))
+            self.cv.notify_all()
+        return fut
+
+    def _schedule(self):
+        while True:
+            with self.cv:
+                while True:
+                    if self.closed and not self.queue:
+                        return
+                    pick = None
+                    if self.running < self.workers:
+                        for i, (req, fp, fut) in enumerate(self.queue):
+                            if self.used + fp <= self.budget:
+                                pick = i
+                                break
+                    if pick is not None:
+                        break
+                    self.cv.wait()
+                req, fp, fut = self.queue[pick]
+                del self.queue[pick]
+                self.used += fp
+                self.running += 1
+                self.peak_used = max(self.peak_used, self.used)
+                self.max_running = max(self.max_running, self.running)
+            self.pool.submit(self._run, req, fp, fut)
+
+    def _run(self, req: Request, fp: float, fut: cf.Future):
+        start = time.perf_counter()
+        try:
+            res = self._step(req, start)
+            fut.set_result(res)
+        except BaseException as ex:  # delivered to the caller
+            fut.set_exception(ex)
+        finally:
+            with self.cv:
+                self.used -= fp
+                self.running -= 1
+                self.cv.notify_all()
+
+    def _step(self, req: Request, start: float) -> Result:
+        Lx, Ly, d, D = _shape(req.A)
+        o = binding.default_opts()
+        o.prec = req.prec
+        o.grad_K = req.grad_K
+        key = (Lx, Ly, d, D, req.chi)
+        warm = False
+        with binding.Context(req.A, req.chi, opts=o) as ctx:
+            if req.state_key is not None:
+                with self.cv:
+                    cached = self.envs.get(req.state_key)
+                if cached is not None and cached[0] == key:
+                    ctx.set_env(cached[1], cached[2])
+                    warm = True
+            it, dl, ok = ctx.converge(req.tol, req.max_iter)
+            if req.state_key is not None:
+                C, T = ctx.get_env()
+                with self.cv:
+                    self.envs[req.state_key] = (key, C, T)
+            e, g = ctx.energy_grad(req.terms, grad=True)
+            x, cg_it, res, brk = ctx.precond(g, req.delta, req.cg_tol,
+                                             req.cg_maxiter)
+        return Result(e=e, g=g, x=x, ctm_iters=it, delta=dl, cg_iters=cg_it,
+                      warm=warm, arrival=req.arrival, start=start,
+                      finish=time.perf_counter())
+
+    def close(self):
+        with self.cv:
+            self.closed = True
+            self.cv.notify_all()
+        self.sched.join()
+        self.pool.shutdown(wait=True)
+
+
+def request_stream(n: int, rate: float, seed: int, prec: int):
+    """(offset seconds, Request) of the seeded serving workload: exponential
+    inter-arrivals of mean 1/rate, D uniform in 3..6, chi uniform in
+    2D^2..3D^2, J1 = 1, J2 uniform in [0, 0.6], state seed 5000 + i."""
+    from . import inputs
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate)
+        D = int(rng.integers(3, 7))
+        chi = int(rng.integers(2 * D * D, 3 * D * D + 1))
+        J2 = float(rng.uniform(0.0, 0.6))
+        A = inputs.random_state(5000 + i, 1, 1, 2, D)
+        terms = inputs.terms_j1j2(1, 1, 1.0, J2)
+        out.append((t, Request(A=A, chi=chi, terms=terms, prec=prec)))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--budget-gb", type=float, default=230.0)
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args(argv)
+    prec = binding.FP32 if args.prec == "fp32" else binding.FP64
+    stream = request_stream(args.requests, args.rate, args.seed, prec)
+    srv = Server(args.budget_gb * 1e9, args.workers)
+    t0 = time.perf_counter()
+    futs = []
+    for off, req in stream:
+        now = time.perf_counter() - t0
+        if off > now:
+            time.sleep(off - now)
+        req.arrival = time.perf_counter()
+        futs.append((req, srv.submit(req)))
+    results, errors = [], 0
+    for i, (req, f) in enumerate(futs):
+        try:
+            results.append(f.result())
+        except Exception as ex:  # counted, reported
+            errors += 1
+            print(f"request {i}: {ex}", file=sys.stderr, flush=True)
+        if (i + 1) % 32 == 0:
+            print(f"{i + 1} requests done", file=sys.stderr, flush=True)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    lat = np.array([r.latency for r in results])
+    svc = np.array([r.finish - r.start for r in results])
+    out = {
+        "workload": (f"{args.requests} requests, Poisson arrivals at "
+                     f"{args.rate}/s, D 3..6, chi 2D^2..3D^2, J1-J2 random "
+                     f"states, {args.prec} contractions, cold starts"),
+        "requests": args.requests, "errors": errors,
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_service_s": float(svc.mean()),
+        "throughput_req_per_s": len(results) / makespan,
+        "makespan_s": makespan, "workers": args.workers,
+        "budget_gb": args.budget_gb,
+        "peak_admitted_gb": srv.peak_used / 1e9,
+        "max_concurrent": srv.max_running,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,62 @@
+"""The request loop on the GPU: requests that run concurrently (own
+contexts, own streams) give exactly the results of the same requests run
+alone, and a warm start from a cached environment reaches the same fixed
+point in fewer iterations."""
+import numpy as np
+import pytest
+
+from paper_2511_09546_amd import binding, inputs, serve
+
+pytestmark = pytest.mark.gpu
+
+
+def _solo(req):
+    o = binding.default_opts()
+    o.prec = req.prec
+    o.grad_K = req.grad_K
+    with binding.Context(req.A, req.chi, opts=o) as ctx:
+        it, dl, ok = ctx.converge(req.tol, req.max_iter)
+        e, g = ctx.energy_grad(req.terms, grad=True)
+        x, cg, res, brk = ctx.precond(g, req.delta, req.cg_tol,
+                                      req.cg_maxiter)
+    return e, g, x, it
+
+
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
+def test_concurrent_equals_solo(prec):
+    print(f"serve concurrent vs solo prec={prec}", flush=True)
+    specs = [(2, 8, 0.0), (3, 12, 0.3), (2, 6, 0.5), (3, 10, 0.1),
+             (2, 8, 0.2), (3, 9, 0.4)]
+    reqs = [serve.Request(A=inputs.random_state(700 + i, 1, 1, 2, D), chi=chi,
+                          terms=inputs.terms_j1j2(1, 1, 1.0, J2), prec=prec,
+                          max_iter=60, grad_K=6)
+            for i, (D, chi, J2) in enumerate(specs)]
+    srv = serve.Server(50e9, workers=4)
+    futs = [srv.submit(r) for r in reqs]
+    res = [f.result(timeout=120) for f in futs]
+    srv.close()
+    assert srv.max_running >= 2
+    for r, out in zip(reqs, res):
+        e, g, x, it = _solo(r)
+        assert out.ctm_iters == it
+        assert out.e == e
+        assert np.array_equal(out.g, g) and np.array_equal(out.x, x)
+
+
+def test_warm_start_sweep():
+    print("serve warm-start sweep", flush=True)
+    A = inputs.random_state(811, 1, 1, 2, 3)
+    srv = serve.Server(50e9, workers=1)
+    res = []
+    for J2 in (0.0, 0.25, 0.5):
+        req = serve.Request(A=A, chi=12, terms=inputs.terms_j1j2(1, 1, 1.0, J2),
+                            prec=binding.FP64, grad_K=6, state_key="s811")
+        res.append(srv.submit(req).result(timeout=120))
+    srv.close()
+    assert not res[0].warm and res[1].warm and res[2].warm
+    assert res[1].ctm_iters < res[0].ctm_iters
+    for J2, r in zip((0.0, 0.25, 0.5), res):
+        req = serve.Request(A=A, chi=12, terms=inputs.terms_j1j2(1, 1, 1.0, J2),
+                            prec=binding.FP64, grad_K=6)
+        e, g, x, it = _solo(req)
+        assert abs(r.e - e) < 1e-9 * abs(e)

@@ -1,0 +1,85 @@
+"""Host logic of the request loop: footprint-based admission, bounded
+concurrency, completion and rejection, with the device step replaced by a
+timed stand-in (no GPU needed)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2511_09546_amd import binding, inputs, serve
+
+
+def _req(D, chi, key=None):
+    A = inputs.random_state(D * 100 + chi, 1, 1, 2, D)
+    return serve.Request(A=A, chi=chi, terms=inputs.terms_j1j2(1, 1, 1.0, 0.2),
+                         state_key=key)
+
+
+def test_footprint_formula():
+    o = binding.default_opts()
+    f = binding.footprint_bytes(1, 1, 2, 6, 72, o)
+    q = 72 * 72 * 6 ** 4
+    dbl = 4 * (4 + 1) * 6 ** 8
+    env = 4 * 72 * 72 + 4 * 72 * 36 * 72
+    assert f == int(8.0 * (q * (64 * 20 + 64) + dbl + env))
+    # grows with every size and with K; zero for invalid sizes
+    assert binding.footprint_bytes(1, 1, 2, 6, 108, o) > f
+    assert binding.footprint_bytes(2, 2, 2, 6, 72, o) > 3.9 * f
+    o.grad_K = 40
+    assert binding.footprint_bytes(1, 1, 2, 6, 72, o) > 1.9 * f
+    assert binding.footprint_bytes(0, 1, 2, 6, 72, o) == 0
+
+
+def test_admission_respects_budget_and_workers(monkeypatch):
+    live = {"used": 0.0, "peak": 0.0, "n": 0, "nmax": 0}
+    lock = threading.Lock()
+
+    def fake_step(self, req, start):
+        fp = self.footprint(req)
+        with lock:
+            live["used"] += fp
+            live["n"] += 1
+            live["peak"] = max(live["peak"], live["used"])
+            live["nmax"] = max(live["nmax"], live["n"])
+        time.sleep(0.02)
+        with lock:
+            live["used"] -= fp
+            live["n"] -= 1
+        return serve.Result(e=float(req.chi), g=np.zeros(1), x=np.zeros(1),
+                            ctm_iters=0, delta=0.0, cg_iters=0, warm=False,
+                            arrival=req.arrival, start=start,
+                            finish=time.perf_counter())
+
+    monkeypatch.setattr(serve.Server, "_step", fake_step)
+    reqs = [_req(D, chi) for D, chi in
+            [(6, 72), (3, 18), (4, 32), (6, 108), (3, 27), (5, 50), (4, 48),
+             (3, 18), (5, 75), (6, 72)]]
+    big = max(serve.Server.footprint(None, r) for r in reqs)
+    budget = 1.2 * big
+    srv = serve.Server(budget, workers=3)
+    futs = [srv.submit(r) for r in reqs]
+    out = [f.result(timeout=30) for f in futs]
+    srv.close()
+    assert [r.e for r in out] == [float(r.chi) for r in reqs]
+    assert live["peak"] <= budget + 1.0
+    assert srv.peak_used <= budget + 1.0
+    assert 1 <= live["nmax"] <= 3 and srv.max_running <= 3
+
+
+def test_request_over_budget_is_rejected():
+    srv = serve.Server(1e6, workers=1)
+    f = srv.submit(_req(4, 32))
+    with pytest.raises(MemoryError):
+        f.result(timeout=5)
+    srv.close()
+
+
+def test_request_stream_is_seeded():
+    a = serve.request_stream(8, 20.0, 5, binding.FP32)
+    b = serve.request_stream(8, 20.0, 5, binding.FP32)
+    assert [t for t, _ in a] == [t for t, _ in b]
+    for (_, ra), (_, rb) in zip(a, b):
+        D = ra.A.shape[3]
+        assert 3 <= D <= 6 and 2 * D * D <= ra.chi <= 3 * D * D
+        assert ra.chi == rb.chi and np.array_equal(ra.A, rb.A)
