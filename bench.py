@@ -159,7 +159,7 @@ def main():
         base = run(name, "fp64", args.steps, args.warmup)
 
     timed, elapsed = head["timed"], head["elapsed"]
-    n_g, t_g, fl_g, _ = head["prof"][head["fam"]]
+    n_g, t_g, fl_g, by_g = head["prof"][head["fam"]]
     _, t_jac, _, _ = head["prof"][binding.PROF_JACOBI]
     _, t_perm, _, _ = head["prof"][binding.PROF_PERMUTE]
     ms = sorted(t["ms"] for t in timed)
@@ -200,6 +200,7 @@ def main():
                                "shapes)",
                      "launches": n_g,
                      "avg_launch_us": 1e6 * t_g / max(n_g, 1),
+                     "algorithmic_bytes_per_launch": by_g / max(n_g, 1),
                      "gemm_share_of_step": t_g / elapsed},
         "kernel_time_s": {"gemm": t_g, "jacobi": t_jac, "permute": t_perm},
         "svd_stats": head["stats"],

@@ -77,11 +77,21 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
-  const int bz = blockIdx.y / splits, sp = blockIdx.y % splits;
+  // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+  // Renumber them so that XCD x works on the x-th contiguous range of
+  // (tile, split, batch) indices: its concurrent workgroups share operand
+  // rows and columns in its L2 instead of every XCD fetching all of them.
+  const int gx = gridDim.x;
+  const int total = gx * gridDim.y;
+  const int lin = blockIdx.x + gx * blockIdx.y;
+  const int q8 = total / 8, r8 = total % 8, xcd = lin % 8;
+  const int vid = xcd * q8 + min(xcd, r8) + lin / 8;
+  const int bx = vid % gx, by = vid / gx;
+  const int bz = by / splits, sp = by % splits;
   A = use_ptrs ? ptrs.a[bz] : A + (long)bz * sA;
   B = use_ptrs ? ptrs.b[bz] : B + (long)bz * sB;
-  const int m0 = (blockIdx.x / tiles_n) * BM;
-  const int n0 = (blockIdx.x % tiles_n) * BN;
+  const int m0 = (bx / tiles_n) * BM;
+  const int n0 = (bx % tiles_n) * BN;
   const int kbeg = sp * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
@@ -184,7 +194,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
     out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
     ldo = ldc;
   } else {
-    out = part + ((long)sp * gridDim.y / splits + bz) * (long)M * N;
+    out = part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
     ldo = N;
   }
 #pragma unroll
