@@ -22,7 +22,9 @@ Prints one JSON line.  The roofline object reports the library's
 matrix-core GEMM in the headline arithmetic (the dominant kernel):
 algorithmic flops (2 M N K per launch) over the device time of its
 launches, both recorded live with HIP events on the library's stream
-during the timed steps.  The cpu_baseline object times the CPU oracle on a
+during the timed steps; its traffic is the HBM bytes per launch from the
+counter record under profiles/ (null when the kernel source has changed
+since the counters were taken).  The cpu_baseline object times the CPU oracle on a
 bounded sample of the same workload (one CTMRG iteration and one K=1
 gradient step) and scales it to one step.
 
@@ -67,6 +69,22 @@ def cpu_baseline(name, n_conv):
                        f"K=1 gradient step ({t_g1:.1f} s) on the host, "
                        f"scaled to {n_conv} iterations + K={w['grad_K']} "
                        f"gradient steps = {t_step:.0f} s/step")}
+
+
+def measured_traffic(prec):
+    """HBM bytes per launch of the FP32 GEMM from the committed counter
+    record (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled
+    by a plain copy), or None when the GEMM source changed since then."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "gemm_fp32_d6chi72_traffic.json")
+    src = os.path.join(ROOT, "paper_2511_09546_amd", "csrc", "gemm.hip")
+    if prec != "fp32" or not os.path.exists(rec):
+        return None
+    r = json.load(open(rec))
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != r["gemm_source_sha256"]:
+            return None
+    return r["traffic_bytes_per_launch"]
 
 
 def run(name, prec, steps, warmup):
@@ -195,7 +213,7 @@ def main():
         "energy_per_site": timed[-1]["e"],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None,
+                     "traffic": measured_traffic(args.prec),
                      "kernel": f"gemm_kernel ({args.prec} MFMA, all tile "
                                "shapes)",
                      "launches": n_g,
