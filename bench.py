@@ -15,8 +15,9 @@ scalars cross PCIe inside the timed region.
 
 The headline runs the dense contractions in FP32 on the matrix cores
 (projector SVD, normalisation, traces and CG scalars stay FP64); the same
-steps are then timed with every product in FP64 ("plain FP64") and the
-energies of the two cold steps are compared.
+steps are then timed with BF16x3 contractions (three BF16 products of a
+two-term split) and with every product in FP64 ("plain FP64"), and the
+energies of the cold steps are compared with the FP64 one.
 
 Prints one JSON line.  The roofline object reports the library's
 matrix-core GEMM in the headline arithmetic (the dominant kernel):
@@ -42,7 +43,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("energy+grad+precond steps/s at D=6,χ=72 vs plain FP64; "
           "MFMA util; p50/p99 lat")
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 
 
 def cpu_baseline(name, n_conv):
@@ -95,9 +96,11 @@ def run(name, prec, steps, warmup):
     A = inputs.workload_state(name)
     terms = inputs.workload_terms(name)
     o = binding.default_opts()
-    o.prec = {"fp64": binding.FP64, "fp32": binding.FP32}[prec]
+    o.prec = {"fp64": binding.FP64, "fp32": binding.FP32,
+              "bf16": binding.BF16}[prec]
     ctx = binding.Context(A, w["chi"], opts=o)
-    fam = binding.PROF_GEMM if prec == "fp64" else binding.PROF_GEMM32
+    fam = {"fp64": binding.PROF_GEMM, "fp32": binding.PROF_GEMM32,
+           "bf16": binding.PROF_GEMM16}[prec]
 
     # site tensor, gradient and direction stay resident in HBM: the step
     # uses the device-pointer entry points (torch provides the buffers)
@@ -151,9 +154,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="d6chi72")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16",
+                                                       "fp64"])
     ap.add_argument("--no-fp64", action="store_true",
-                    help="skip the plain FP64 comparison run")
+                    help="skip the plain FP64 and the other mixed runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -172,8 +176,10 @@ def main():
     w = inputs.WORKLOADS[name]
 
     head = run(name, args.prec, args.steps, args.warmup)
-    base = None
+    base = other = None
     if args.prec != "fp64" and not args.no_fp64:
+        oprec = "bf16" if args.prec == "fp32" else "fp32"
+        other = (oprec, run(name, oprec, args.steps, args.warmup))
         base = run(name, "fp64", args.steps, args.warmup)
 
     timed, elapsed = head["timed"], head["elapsed"]
@@ -197,8 +203,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f64" if args.prec == "fp64"
-                  else "f32 contractions, f64 SVD/CG"),
+        "dtype": {"fp64": "f64", "fp32": "f32 contractions, f64 SVD/CG",
+                  "bf16": "bf16x3 contractions, f64 SVD/CG"}[args.prec],
         "data": "synthetic",
         "config": {"workload": f"{name}: 1x1 iPEPS d={w['d']} D={w['D']} "
                                f"chi={w['chi']} J1-J2 J2={w['J2']}, warm "
@@ -225,14 +231,26 @@ def main():
     }
     if base is not None:
         v64 = args.steps / base["elapsed"]
-        e_h = head["infos"][0]["e"] if head["infos"] else None
         e_b = base["infos"][0]["e"] if base["infos"] else None
+
+        def ediff(r):
+            e = r["infos"][0]["e"] if r["infos"] else None
+            return abs(e - e_b) if e is not None and e_b is not None else None
+
         out["plain_fp64"] = {
             "value": v64, "ms_per_step": 1e3 * base["elapsed"] / args.steps,
             "speedup": value / v64,
             "ctm_iters_per_step": [t["iters"] for t in base["timed"]],
-            "cold_step_energy_abs_diff": (abs(e_h - e_b)
-                                          if e_h is not None else None)}
+            "cold_step_energy_abs_diff": ediff(head)}
+        oprec, o = other
+        vo = args.steps / o["elapsed"]
+        n_o, t_o, fl_o, _ = o["prof"][o["fam"]]
+        out[f"{oprec}_contractions"] = {
+            "value": vo, "ms_per_step": 1e3 * o["elapsed"] / args.steps,
+            "speedup_vs_fp64": vo / v64,
+            "ctm_iters_per_step": [t["iters"] for t in o["timed"]],
+            "cold_step_energy_abs_diff_vs_fp64": ediff(o),
+            "gemm_tflops": fl_o / t_o / 1e12 if t_o > 0 else 0.0}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, n_conv)
     print(json.dumps(out), flush=True)

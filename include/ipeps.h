@@ -55,9 +55,18 @@ typedef enum {
   IPEPS_ENOTIMPL = -6       /* option not implemented */
 } ipeps_status;
 
-/* Arithmetic of the dense contractions.  Projector SVD, normalisation,
+/* Arithmetic of the dense contractions (every product of the CTMRG and
+ * energy networks, of the metric, and the products with the cut matrices
+ * inside the projector SVD and its adjoint).  Projector SVD (Gram matrices,
+ * Jacobi, subspace rotations), SVD-adjoint algebra, normalisation,
  * convergence measure, energy traces and CG inner products are FP64 in every
- * mode. */
+ * mode.  Operands stay FP64 in memory in every mode.
+ *   IPEPS_FP64  FP64 matrix cores;
+ *   IPEPS_FP32  operands rounded to FP32, FP32 accumulation; ctm_converge
+ *               raises tolerances below 1e-7 to 1e-7;
+ *   IPEPS_BF16  each operand split into two BF16 terms, three BF16 products
+ *               (about 16 significant bits), FP32 accumulation;
+ *               ctm_converge raises tolerances below 3e-6 to 3e-6. */
 typedef enum {
   IPEPS_FP64 = 0,
   IPEPS_FP32 = 1,
@@ -187,7 +196,8 @@ size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
  * on = 1 the context records HIP events on its stream around every launch
  * of the timed kernel families (clearing earlier records); on = 0 stops.
  * Families: 0 = GEMM (FP64 matrix-core GEMM, all shapes), 1 = Jacobi
- * eigensolver, 2 = permute, 3 = FP32 GEMM.  ipeps_profile_read returns, for one family,
+ * eigensolver, 2 = permute, 3 = FP32 GEMM, 4 = BF16x3 GEMM.
+ * ipeps_profile_read returns, for one family,
  * the number of launches, their summed device time in seconds and their
  * algorithmic FLOP and byte counts (2 M N K flop; the operand and result
  * bytes of each launch).  Errors: EINVAL, EHIP. */

@@ -19,7 +19,8 @@ int ipeps_debug_gemm(int tA, int tB, int M, int N, int K, double alpha,
                      double* C);
 
 /* ipeps_debug_gemm with the products in the arithmetic `prec` (ipeps_prec:
- * IPEPS_FP64 or IPEPS_FP32; operands and result stay FP64 in memory). */
+ * IPEPS_FP64, IPEPS_FP32 or IPEPS_BF16, the last as three BF16 products of a
+ * two-term split; operands and result stay FP64 in memory). */
 int ipeps_debug_gemm_prec(int prec, int tA, int tB, int M, int N, int K,
                           double alpha, const double* A, const double* B,
                           double beta, double* C);

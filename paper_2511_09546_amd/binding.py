@@ -29,7 +29,7 @@ API_FUNCTIONS = [
     "ipeps_profile_read", "ctm_set_state_dev", "ipeps_energy_grad_dev",
     "precond_apply_dev", "ipeps_footprint_bytes",
 ]
-PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32 = 0, 1, 2, 3
+PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
                    "ipeps_debug_svd_ts", "ipeps_debug_stats",
                    "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time"]

@@ -107,7 +107,6 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
   if (opts) o = *opts;
   if (o.prec != IPEPS_FP64 && o.prec != IPEPS_FP32 && o.prec != IPEPS_BF16)
     return IPEPS_EINVAL;
-  if (o.prec == IPEPS_BF16) return IPEPS_ENOTIMPL;
   if (!(o.svd_cutoff >= 0.0) || o.grad_K < 0 || o.svd_max_iter < 1 ||
       !(o.svd_tol >= 0.0) || o.svd_oversample < 0)
     return IPEPS_EINVAL;
@@ -179,7 +178,10 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
   const double svd_tol = cx.svd.tol;
   // the spectrum change cannot fall below the rounding of the contraction
   // arithmetic: tolerances under that floor are raised to it
-  const double floor = cx.prec == IPEPS_FP64 ? 0.0 : kSpectraFloorFp32;
+  const double floor = cx.prec == IPEPS_FP64
+                            ? 0.0
+                            : (cx.prec == IPEPS_FP32 ? kSpectraFloorFp32
+                                                     : kSpectraFloorBf16);
   if (tol > 0.0) tol = std::max(tol, floor);
   int st = guarded([&]() {
     PrecScope ps(cx.dev, cx.prec);

@@ -94,7 +94,8 @@ enum ProfFamily {
   PROF_JACOBI = 1,
   PROF_PERMUTE = 2,
   PROF_GEMM32 = 3,   // FP32 matrix-core GEMM
-  PROF_N = 4
+  PROF_GEMM16 = 4,   // BF16x3 matrix-core GEMM
+  PROF_N = 5
 };
 
 // Arithmetic of the GEMMs issued on a device (the contraction precision;

@@ -1,10 +1,12 @@
 // Dense GEMM on the gfx950 matrix cores, FP64 in memory.
 //
 // C[b] = alpha op(A[b]) op(B[b]) + beta C[b], row major, with the products
-// computed in one of two arithmetics (Device::cprec):
+// computed in one of three arithmetics (Device::cprec):
 //   FP64  v_mfma_f64_16x16x4_f64, operands and accumulation in FP64;
 //   FP32  v_mfma_f32_16x16x4_f32, operands rounded to FP32 when they are
-//         staged into LDS, FP32 accumulation, result written in FP64.
+//         staged into LDS, FP32 accumulation, result written in FP64;
+//   BF16x3 v_mfma_f32_16x16x32_bf16 on a two-term BF16 split of each
+//         operand (three products, FP32 accumulation), gemm_bf16x3_kernel.
 //
 // Workgroup: 256 threads = 4 waves of 64 lanes arranged WM x WN; the block
 // tile BM x BN is staged through LDS in BK = 16 deep slices, double
@@ -219,6 +221,167 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
       }
 }
 
+// BF16x3 arithmetic: every FP64 operand x is split into x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi) when staged into LDS, and each product is
+// a_hi b_hi + a_hi b_lo + a_lo b_hi on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation (about 16 significant bits per product, the a_lo b_lo term
+// being below that).  K slices of 32; the tiles are kept row-major along K
+// in LDS (A as [BM][K], B as [BN][K]) so that each lane fetches its 8
+// consecutive K values with one 16-byte read.  One LDS buffer: the next
+// slice is loaded into registers while the MFMAs of the current one run.
+// Lane layout of the 16x16x32 BF16 MFMA (checked on gfx950): lane l supplies
+// A[l%16][8(l/16) + t] and B[8(l/16) + t][l%16], t = 0..7; the result holds
+// D[4(l/16) + r][l%16] in register r.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A,
+    long lda, long sA, const double* __restrict__ B, long ldb, long sB,
+    double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
+    int splits, int kchunk, double* __restrict__ part, int use_ptrs,
+    PtrArgs ptrs) {
+  static_assert(WM * WN == 4, "4 waves");
+  constexpr int BK = 32, KP = BK + 8;  // 80-byte rows, 16-byte aligned reads
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  constexpr int AE = BM * BK / 256, BE = BK * BN / 256;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[BN][KP];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int gx = gridDim.x;
+  const int total = gx * gridDim.y;
+  const int lin = blockIdx.x + gx * blockIdx.y;
+  const int q8 = total / 8, r8 = total % 8, xcd = lin % 8;
+  const int vid = xcd * q8 + min(xcd, r8) + lin / 8;
+  const int bx = vid % gx, by = vid / gx;
+  const int bz = by / splits, sp = by % splits;
+  A = use_ptrs ? ptrs.a[bz] : A + (long)bz * sA;
+  B = use_ptrs ? ptrs.b[bz] : B + (long)bz * sB;
+  const int m0 = (bx / tiles_n) * BM;
+  const int n0 = (bx % tiles_n) * BN;
+  const int kbeg = sp * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  double ra[AE], rb[BE];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int i = 0; i < AE; ++i) {
+      const int e = tid + i * 256;
+      const int mm = TA ? e % BM : e / BK, kk = TA ? e / BM : e % BK;
+      const int gm = m0 + mm, gk = kb + kk;
+      double v = 0.0;
+      if (gm < M && gk < kend)
+        v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < BE; ++i) {
+      const int e = tid + i * 256;
+      const int nn = TB ? e / BK : e % BN, kk = TB ? e % BK : e / BN;
+      const int gk = kb + kk, gn = n0 + nn;
+      double v = 0.0;
+      if (gk < kend && gn < N)
+        v = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
+      rb[i] = v;
+    }
+  };
+  auto split = [](double v, __bf16& h, __bf16& l) {
+    const float f = (float)v;
+    h = (__bf16)f;
+    l = (__bf16)(f - (float)h);
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int i = 0; i < AE; ++i) {
+      const int e = tid + i * 256;
+      const int mm = TA ? e % BM : e / BK, kk = TA ? e / BM : e % BK;
+      split(ra[i], Ah[mm][kk], Al[mm][kk]);
+    }
+#pragma unroll
+    for (int i = 0; i < BE; ++i) {
+      const int e = tid + i * 256;
+      const int nn = TB ? e / BK : e % BN, kk = TB ? e % BK : e / BN;
+      split(rb[i], Bh[nn][kk], Bl[nn][kk]);
+    }
+  };
+
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  if (kbeg < kend) {
+    load(kbeg);
+    store();
+  }
+  __syncthreads();
+  const int kq = 8 * (lane >> 4);
+  for (int kb = kbeg; kb < kend; kb += BK) {
+    const bool more = kb + BK < kend;
+    if (more) load(kb + BK);
+    bf16x8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * WTM + i * 16 + (lane & 15);
+      ah[i] = *(const bf16x8*)&Ah[r][kq];
+      al[i] = *(const bf16x8*)&Al[r][kq];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = wn * WTN + j * 16 + (lane & 15);
+      const bf16x8 bh = *(const bf16x8*)&Bh[c][kq];
+      const bf16x8 bl = *(const bf16x8*)&Bl[c][kq];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh,
+                                                            acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl,
+                                                            acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh,
+                                                            acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) store();
+    __syncthreads();
+  }
+
+  double* out;
+  long ldo;
+  if (splits == 1) {
+    out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+    ldo = ldc;
+  } else {
+    out = part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
+    ldo = N;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          const double a = (double)acc[i][j][r];
+          if (splits == 1) {
+            double v = alpha * a;
+            if (beta != 0.0) v += beta * out[(long)row * ldo + col];
+            out[(long)row * ldo + col] = v;
+          } else {
+            out[(long)row * ldo + col] = a;
+          }
+        }
+      }
+}
+
 // part layout [S][batch][M][N]; C[b] = alpha sum_s part[s][b] + beta C[b]
 __global__ void splitk_sum_kernel(const double* __restrict__ part, int S,
                                   int batch, long M, long N, double alpha,
@@ -252,8 +415,11 @@ struct Call {
   const PtrArgs* ptrs;  // null: strided batch
 };
 
-template <int BM, int BN, int WM, int WN, bool F32, bool KM, int BK = 16>
+// P: 0 = FP64, 1 = FP32, 2 = BF16x3 arithmetic
+template <int BM, int BN, int WM, int WN, int P>
 void launch_cfg(Device& dev, const Call& c) {
+  constexpr bool F32 = P == 1;
+  constexpr int BK = P == 2 ? 32 : 16;
   const long tm = (c.M + BM - 1) / BM, tn = (c.N + BN - 1) / BN;
   const long tiles = tm * tn;
   // split K until the grid covers the chip, keeping at least 256 of K per
@@ -261,7 +427,7 @@ void launch_cfg(Device& dev, const Call& c) {
   int S = 1;
   // workgroup target of the split (two or three waves of workgroups over the
   // 256 CUs; measured best for the skinny n x n x chi products)
-  const long want = F32 ? 512 : 768;
+  const long want = P == 0 ? 768 : 512;
   if (tiles * c.batch < want && c.K >= 512) {
     S = (int)std::min<long>((want + tiles * c.batch - 1) / (tiles * c.batch),
                             c.K / 256);
@@ -281,7 +447,8 @@ void launch_cfg(Device& dev, const Call& c) {
   // the profiler brackets the matrix-core kernel alone (split-K partial
   // sums are a kernel of their own), with the algorithmic 2 M N K flops
   if (dev.prof.on)
-    dev.prof.begin(dev.stream, F32 ? PROF_GEMM32 : PROF_GEMM,
+    dev.prof.begin(dev.stream,
+                   P == 0 ? PROF_GEMM : (P == 1 ? PROF_GEMM32 : PROF_GEMM16),
                    2.0 * c.M * c.N * c.K * c.batch,
                    8.0 * c.batch *
                        ((double)c.M * c.K + (double)c.K * c.N +
@@ -291,10 +458,21 @@ void launch_cfg(Device& dev, const Call& c) {
                        c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.beta,
                        c.C, c.ldc, c.sC, (int)tn, S, kchunk, part.ptr, up, pa);
   };
-  if (!c.tA && !c.tB) go(gemm_kernel<BM, BN, WM, WN, false, false, F32, KM, BK>);
-  if (c.tA && !c.tB) go(gemm_kernel<BM, BN, WM, WN, true, false, F32, KM, BK>);
-  if (!c.tA && c.tB) go(gemm_kernel<BM, BN, WM, WN, false, true, F32, KM, BK>);
-  if (c.tA && c.tB) go(gemm_kernel<BM, BN, WM, WN, true, true, F32, KM, BK>);
+  if constexpr (P == 2) {
+    if (!c.tA && !c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, false, false>);
+    if (c.tA && !c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, true, false>);
+    if (!c.tA && c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, false, true>);
+    if (c.tA && c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, true, true>);
+  } else {
+    if (!c.tA && !c.tB)
+      go(gemm_kernel<BM, BN, WM, WN, false, false, F32, false, BK>);
+    if (c.tA && !c.tB)
+      go(gemm_kernel<BM, BN, WM, WN, true, false, F32, false, BK>);
+    if (!c.tA && c.tB)
+      go(gemm_kernel<BM, BN, WM, WN, false, true, F32, false, BK>);
+    if (c.tA && c.tB)
+      go(gemm_kernel<BM, BN, WM, WN, true, true, F32, false, BK>);
+  }
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
   if (S > 1) {
@@ -308,35 +486,37 @@ void launch_cfg(Device& dev, const Call& c) {
   }
 }
 
-template <bool F32, bool KM>
+template <int P>
 void dispatch_prec(Device& dev, const Call& c) {
   if (c.M >= 128) {
     // narrow N (chi-wide blocks of the projector SVD and the complement
     // solves): 4 waves stacked along M, tile width rounded up to 16
     if (c.N <= 48)
-      launch_cfg<128, 48, 4, 1, F32, KM>(dev, c);
+      launch_cfg<128, 48, 4, 1, P>(dev, c);
     else if (c.N <= 64)
-      launch_cfg<128, 64, 4, 1, F32, KM>(dev, c);
+      launch_cfg<128, 64, 4, 1, P>(dev, c);
     else if (c.N <= 80)
-      launch_cfg<128, 80, 4, 1, F32, KM>(dev, c);
+      launch_cfg<128, 80, 4, 1, P>(dev, c);
     else if (c.N <= 96)
-      launch_cfg<128, 96, 4, 1, F32, KM>(dev, c);
+      launch_cfg<128, 96, 4, 1, P>(dev, c);
+    else if constexpr (P == 2)  // BF16x3: 128 x 128 would spill registers
+      launch_cfg<128, 96, 4, 1, P>(dev, c);
     else
-      launch_cfg<128, 128, 2, 2, F32, KM>(dev, c);
+      launch_cfg<128, 128, 2, 2, P>(dev, c);
   } else if (c.N >= 128) {
-    launch_cfg<64, 128, 2, 2, F32, KM>(dev, c);
+    launch_cfg<64, 128, 2, 2, P>(dev, c);
   } else {
-    launch_cfg<64, 64, 2, 2, F32, KM>(dev, c);
+    launch_cfg<64, 64, 2, 2, P>(dev, c);
   }
 }
 
 void dispatch(Device& dev, const Call& c) {
   if (dev.cprec == PREC_FP32)
-    dispatch_prec<true, false>(dev, c);
+    dispatch_prec<1>(dev, c);
   else if (dev.cprec == PREC_FP64)
-    dispatch_prec<false, false>(dev, c);
+    dispatch_prec<0>(dev, c);
   else
-    throw NotImplError("gemm: contraction precision not available");
+    dispatch_prec<2>(dev, c);
 }
 
 void check_sizes(int64_t M, int64_t N, int64_t K, int64_t batch) {

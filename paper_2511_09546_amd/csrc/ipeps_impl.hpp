@@ -81,6 +81,9 @@ struct VEnv {
 // Smallest corner-spectrum change that CTMRG with FP32 contractions can
 // resolve (their rounding moves the normalised spectra by about this much).
 constexpr double kSpectraFloorFp32 = 1e-7;
+// The same for the BF16x3 products (about 16 significant bits; the
+// spectrum change levels off near 1e-6).
+constexpr double kSpectraFloorBf16 = 3e-6;
 
 struct Context {
   Device dev;

@@ -332,11 +332,13 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     if (m > 0) deflate(R.ptr, Pp.ptr);
     coldot(dev, R.ptr, R.ptr, 2 * n, chi, rr, nc, s2);
     std::vector<double> h(5 * nc * chi);
-    // relative residual 1e-12 with FP64 products; with FP32 products 1e-5,
-    // and the solve also ends when four iterations no longer reduce the
-    // worst relative residual by half (rounding floor of the products)
+    // relative residual 1e-12 with FP64 products; with FP32 products 1e-5
+    // (BF16x3: 1e-3), and the solve also ends when four iterations no longer
+    // reduce the worst relative residual by half (rounding floor of the
+    // products)
     const bool lowp = cp != PREC_FP64;
-    const double tol2 = lowp ? 1e-10 : 1e-24;
+    const double tol2 = cp == PREC_FP64 ? 1e-24 : (cp == PREC_FP32 ? 1e-10
+                                                                   : 1e-6);
     double prev_worst = INFINITY;
     const int max_it = 600;
     int it = 0;

@@ -131,11 +131,14 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
   V = dev.empty({nc, n, b});
   int it = 0;
   double worst = 0.0;
-  // with FP32 products the residual levels off at a few 1e-6 s_1: the
-  // tolerance is raised to 1e-5 and the iteration also ends when an
-  // iteration no longer halves the residual
+  // with FP32 products the residual levels off at a few 1e-6 s_1 (BF16x3:
+  // a few 1e-4): the tolerance is raised to 1e-5 (1e-3) and the iteration
+  // also ends when an iteration no longer halves the residual
   const bool lowp = dev.cprec != PREC_FP64;
-  const double tol = std::max(prm.tol, lowp ? 1e-5 : 0.0);
+  const double floor = dev.cprec == PREC_FP64   ? 0.0
+                       : dev.cprec == PREC_FP32 ? 1e-5
+                                                : 1e-3;
+  const double tol = std::max(prm.tol, floor);
   double prev = INFINITY;
   for (;;) {
     ++it;
