@@ -105,11 +105,12 @@ def _step_against_golden(name, prec, rel):
                                          (0, 1, 300, 48, 1296),
                                          (0, 0, 640, 1296, 1296)])
 def test_bf16x3_gemm_error_bound(tA, tB, M, N, K):
-    """x = hi + lo + r with hi = bf16(fl32(x)), lo = bf16(fl32(x) - hi):
-    |r| <= (2^-24 + 2^-17) |x| (FP32 rounding, then the second BF16 term's
-    rounding of a remainder at most 2^-8 |x|); the dropped lo*lo term is at
-    most 2^-16 |a||b| and the three products accumulate in FP32.  Bound per
-    element: (2 (2^-24 + 2^-17) + 2^-16 + gamma_{3K}) (|A||B|)."""
+    """x = hi + lo + r with hi = bf16(fl32(x)), lo = bf16(fl32(x) - hi) and
+    BF16 unit roundoff 2^-8: |fl32(x) - hi| <= 2^-8 |x|, so
+    |r| <= (2^-24 + 2^-16) |x| (FP32 rounding, then the rounding of the
+    second term); the dropped lo*lo term is at most 2^-16 |a||b| and the three
+    exact BF16 products accumulate in FP32.  Bound per element:
+    (2 (2^-24 + 2^-16) + 2^-16 + gamma_{3K}) (|A||B|)."""
     _say(f"bf16x3 gemm {tA}{tB} {M}x{N}x{K}")
     rng = np.random.default_rng(M * N + K)
     A = rng.standard_normal((M, K))
@@ -121,7 +122,7 @@ def test_bf16x3_gemm_error_bound(tA, tB, M, N, K):
     ref = A @ B
     u = 2.0 ** -24
     g = 3 * K * u / (1 - 3 * K * u)
-    bound = (2 * (u + 2.0 ** -17) + 2.0 ** -16 + g) * (np.abs(A) @ np.abs(B))
+    bound = (2 * (u + 2.0 ** -16) + 2.0 ** -16 + g) * (np.abs(A) @ np.abs(B))
     err = np.abs(C - ref)
     _say(f"  max err/bound {np.max(err / bound):.3f}")
     assert np.all(err <= bound)
