@@ -164,6 +164,16 @@ void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                int64_t lda, const std::vector<const double*>& B, int64_t ldb,
                double beta, const std::vector<double*>& C, int64_t ldc);
 
+// gemm_ptrs with the A operands stored in FP32 (the products in the FP32
+// or BF16x3 arithmetic of the device; FP64 is refused).
+void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
+                   int64_t K, double alpha,
+                   const std::vector<const float*>& A, int64_t lda,
+                   const std::vector<const double*>& B, int64_t ldb,
+                   double beta, const std::vector<double*>& C, int64_t ldc);
+// y[i] = (float) x[i]
+void to_f32(Device& dev, const double* x, float* y, int64_t n);
+
 // out = alpha * permute(in, perm) + beta * out (rank <= 12 after merging
 // contiguous dims); out.shape[i] =
 // in.shape[perm[i]].

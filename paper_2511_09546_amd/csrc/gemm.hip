@@ -51,15 +51,15 @@ constexpr int MPAD = 2;   // row stride BM + 2 for operands read along M/N
 constexpr int MAXP = 16;  // pointer triples per launch
 
 struct PtrArgs {
-  const double* a[MAXP];
+  const void* a[MAXP];  // double, or float for FP32-stored A
   const double* b[MAXP];
   double* c[MAXP];
 };
 
-template <int BM, int BN, int WM, int WN, bool TA, bool TB, bool F32,
-          bool KM, int BK>
+template <typename TI, int BM, int BN, int WM, int WN, bool TA, bool TB,
+          bool F32, bool KM, int BK>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(
-    int M, int N, int K, double alpha, const double* __restrict__ A,
+    int M, int N, int K, double alpha, const void* __restrict__ Av,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
     int splits, int kchunk, double* __restrict__ part, int use_ptrs,
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
   const int vid = xcd * q8 + min(xcd, r8) + lin / 8;
   const int bx = vid % gx, by = vid / gx;
   const int bz = by / splits, sp = by % splits;
-  A = use_ptrs ? ptrs.a[bz] : A + (long)bz * sA;
+  const TI* A = use_ptrs ? (const TI*)ptrs.a[bz] : (const TI*)Av + (long)bz * sA;
   B = use_ptrs ? ptrs.b[bz] : B + (long)bz * sB;
   const int m0 = (bx / tiles_n) * BM;
   const int n0 = (bx % tiles_n) * BN;
@@ -99,14 +99,15 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
 
   // raw FP64 values stay in registers until the LDS store, so the global
   // loads remain in flight across the MFMAs of the current slice
-  double ra[AE], rb[BE];
+  TI ra[AE];
+  double rb[BE];
   auto load = [&](int kb) {
 #pragma unroll
     for (int i = 0; i < AE; ++i) {
       const int e = tid + i * 256;
       const int mm = TA ? e % BM : e / BK, kk = TA ? e / BM : e % BK;
       const int gm = m0 + mm, gk = kb + kk;
-      double v = 0.0;
+      TI v = 0;
       if (gm < M && gk < kend)
         v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
       ra[i] = v;
@@ -234,9 +235,9 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
 // D[4(l/16) + r][l%16] in register r.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int BM, int BN, int WM, int WN, bool TA, bool TB>
+template <typename TI, int BM, int BN, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
-    int M, int N, int K, double alpha, const double* __restrict__ A,
+    int M, int N, int K, double alpha, const void* __restrict__ Av,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
     int splits, int kchunk, double* __restrict__ part, int use_ptrs,
@@ -260,21 +261,22 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
   const int vid = xcd * q8 + min(xcd, r8) + lin / 8;
   const int bx = vid % gx, by = vid / gx;
   const int bz = by / splits, sp = by % splits;
-  A = use_ptrs ? ptrs.a[bz] : A + (long)bz * sA;
+  const TI* A = use_ptrs ? (const TI*)ptrs.a[bz] : (const TI*)Av + (long)bz * sA;
   B = use_ptrs ? ptrs.b[bz] : B + (long)bz * sB;
   const int m0 = (bx / tiles_n) * BM;
   const int n0 = (bx % tiles_n) * BN;
   const int kbeg = sp * kchunk;
   const int kend = min(K, kbeg + kchunk);
 
-  double ra[AE], rb[BE];
+  TI ra[AE];
+  double rb[BE];
   auto load = [&](int kb) {
 #pragma unroll
     for (int i = 0; i < AE; ++i) {
       const int e = tid + i * 256;
       const int mm = TA ? e % BM : e / BK, kk = TA ? e / BM : e % BK;
       const int gm = m0 + mm, gk = kb + kk;
-      double v = 0.0;
+      TI v = 0;
       if (gm < M && gk < kend)
         v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
       ra[i] = v;
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
       rb[i] = v;
     }
   };
-  auto split = [](double v, __bf16& h, __bf16& l) {
+  auto split = [](auto v, __bf16& h, __bf16& l) {
     const float f = (float)v;
     h = (__bf16)f;
     l = (__bf16)(f - (float)h);
@@ -406,13 +408,14 @@ struct Call {
   bool tA, tB;
   int M, N, K, batch;
   double alpha, beta;
-  const double* A;
+  const void* A;  // double, or float when a32
   long lda, sA;
   const double* B;
   long ldb, sB;
   double* C;
   long ldc, sC;
   const PtrArgs* ptrs;  // null: strided batch
+  bool a32 = false;     // A stored in FP32
 };
 
 // P: 0 = FP64, 1 = FP32, 2 = BF16x3 arithmetic
@@ -450,28 +453,43 @@ void launch_cfg(Device& dev, const Call& c) {
     dev.prof.begin(dev.stream,
                    P == 0 ? PROF_GEMM : (P == 1 ? PROF_GEMM32 : PROF_GEMM16),
                    2.0 * c.M * c.N * c.K * c.batch,
-                   8.0 * c.batch *
-                       ((double)c.M * c.K + (double)c.K * c.N +
-                        (c.beta != 0.0 ? 2.0 : 1.0) * c.M * c.N));
+                   c.batch * ((c.a32 ? 4.0 : 8.0) * c.M * c.K +
+                              8.0 * ((double)c.K * c.N +
+                                     (c.beta != 0.0 ? 2.0 : 1.0) * c.M * c.N)));
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), 0, dev.stream, c.M, c.N, c.K,
                        c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.beta,
                        c.C, c.ldc, c.sC, (int)tn, S, kchunk, part.ptr, up, pa);
   };
-  if constexpr (P == 2) {
-    if (!c.tA && !c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, false, false>);
-    if (c.tA && !c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, true, false>);
-    if (!c.tA && c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, false, true>);
-    if (c.tA && c.tB) go(gemm_bf16x3_kernel<BM, BN, WM, WN, true, true>);
+  auto pick = [&](auto ti) {
+    using TI = decltype(ti);
+    if constexpr (P == 2) {
+      if (!c.tA && !c.tB)
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, false, false>);
+      if (c.tA && !c.tB)
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, true, false>);
+      if (!c.tA && c.tB)
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, false, true>);
+      if (c.tA && c.tB)
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, true, true>);
+    } else {
+      if (!c.tA && !c.tB)
+        go(gemm_kernel<TI, BM, BN, WM, WN, false, false, F32, false, BK>);
+      if (c.tA && !c.tB)
+        go(gemm_kernel<TI, BM, BN, WM, WN, true, false, F32, false, BK>);
+      if (!c.tA && c.tB)
+        go(gemm_kernel<TI, BM, BN, WM, WN, false, true, F32, false, BK>);
+      if (c.tA && c.tB)
+        go(gemm_kernel<TI, BM, BN, WM, WN, true, true, F32, false, BK>);
+    }
+  };
+  if constexpr (P == 0) {
+    pick(double());
   } else {
-    if (!c.tA && !c.tB)
-      go(gemm_kernel<BM, BN, WM, WN, false, false, F32, false, BK>);
-    if (c.tA && !c.tB)
-      go(gemm_kernel<BM, BN, WM, WN, true, false, F32, false, BK>);
-    if (!c.tA && c.tB)
-      go(gemm_kernel<BM, BN, WM, WN, false, true, F32, false, BK>);
-    if (c.tA && c.tB)
-      go(gemm_kernel<BM, BN, WM, WN, true, true, F32, false, BK>);
+    if (c.a32)
+      pick(float());
+    else
+      pick(double());
   }
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
@@ -544,10 +562,13 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
   dispatch(dev, c);
 }
 
-void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
-               int64_t K, double alpha, const std::vector<const double*>& A,
-               int64_t lda, const std::vector<const double*>& B, int64_t ldb,
-               double beta, const std::vector<double*>& C, int64_t ldc) {
+namespace {
+template <class TA>
+void gemm_ptrs_impl(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
+                    int64_t K, double alpha, const std::vector<const TA*>& A,
+                    int64_t lda, const std::vector<const double*>& B,
+                    int64_t ldb, double beta, const std::vector<double*>& C,
+                    int64_t ldc) {
   const int64_t batch = (int64_t)A.size();
   if (M <= 0 || N <= 0 || batch <= 0 || K <= 0) return;
   if ((int64_t)B.size() != batch || (int64_t)C.size() != batch)
@@ -563,9 +584,27 @@ void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
       pa.c[i] = C[b0 + i];
     }
     Call c{tA, tB, (int)M, (int)N, (int)K, nb, alpha, beta, pa.a[0], lda, 0,
-           pa.b[0], ldb, 0, pa.c[0], ldc, 0, &pa};
+           pa.b[0], ldb, 0, pa.c[0], ldc, 0, &pa, sizeof(TA) == 4};
     dispatch(dev, c);
   }
+}
+}  // namespace
+
+void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
+               int64_t K, double alpha, const std::vector<const double*>& A,
+               int64_t lda, const std::vector<const double*>& B, int64_t ldb,
+               double beta, const std::vector<double*>& C, int64_t ldc) {
+  gemm_ptrs_impl(dev, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+}
+
+void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
+                   int64_t K, double alpha,
+                   const std::vector<const float*>& A, int64_t lda,
+                   const std::vector<const double*>& B, int64_t ldb,
+                   double beta, const std::vector<double*>& C, int64_t ldc) {
+  if (dev.cprec == PREC_FP64)
+    throw ArgError("gemm_ptrs_a32: FP32 operands need FP32 or BF16x3 products");
+  gemm_ptrs_impl(dev, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 }  // namespace ipeps

@@ -16,7 +16,17 @@ struct CutBatch {
   int b = 0;       // subspace block (even)
   int chi = 0;
   std::vector<const double*> Qa, Qb;  // n x n row major, per cut
+  // FP32 copies of the same matrices (empty in FP64 arithmetic)
+  std::vector<const float*> Qa32, Qb32;
 };
+
+// C[i] = op(Q[i]) B[i] for the cut matrices Q (n x n, leading dimension
+// ldq), in arithmetic `prec`, from the FP32 copies when there are any.
+void qmul(Device& dev, int prec, bool tA, int64_t M, int64_t N, int64_t K,
+          const std::vector<const double*>& Q,
+          const std::vector<const float*>& Q32, int64_t ldq,
+          const std::vector<const double*>& B, int64_t ldb,
+          const std::vector<double*>& C, int64_t ldc);
 
 struct SvdParams {
   double tol = 1e-13;

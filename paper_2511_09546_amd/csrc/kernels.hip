@@ -232,6 +232,19 @@ void axpby(Device& dev, int64_t n, double a, const double* x, double b,
   IPEPS_HIP(hipGetLastError());
 }
 
+__global__ void to_f32_kernel(const double* x, float* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+void to_f32(Device& dev, const double* x, float* y, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, x, y, n);
+  IPEPS_HIP(hipGetLastError());
+}
+
 __global__ void scale_dev_kernel(double* x, int64_t n, const double* s,
                                  int inverse) {
   const double f = inverse ? 1.0 / s[0] : s[0];

@@ -22,6 +22,7 @@
 // chi-wide block operation one strided batched launch.
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <utility>
 
 #include "ad.hpp"
@@ -73,6 +74,26 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     cb.Qa.push_back(Qa[i]->v.ptr);
     cb.Qb.push_back(Qb[i]->v.ptr);
   }
+  // FP32 copies of the distinct cut matrices, read by every product with
+  // them (subspace iteration, projectors, backward) when the contraction
+  // arithmetic is FP32 or BF16x3: half the bytes of these memory-bound
+  // products
+  std::vector<Tensor> q32;
+  if (dev.cprec != PREC_FP64) {
+    std::map<const double*, const float*> made;
+    auto conv = [&](const double* q) {
+      auto it = made.find(q);
+      if (it != made.end()) return it->second;
+      Tensor t = dev.empty({(n * n + 1) / 2});
+      to_f32(dev, q, (float*)t.ptr, n * n);
+      q32.push_back(t);
+      return made[q] = (const float*)t.ptr;
+    };
+    for (int i = 0; i < nc; ++i) {
+      cb.Qa32.push_back(conv(cb.Qa[i]));
+      cb.Qb32.push_back(conv(cb.Qb[i]));
+    }
+  }
   Tensor U, S, V, keep;
   projector_svd(dev, cb, cx.Xwarm, cx.have_warm, U, S, V, keep, cx.svd,
                 &cx.stats);
@@ -81,12 +102,12 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
   Tensor w = dev.empty({nc, chi});
   proj_weights(dev, S.ptr, kp, chi, w.ptr, nc, b);
   Tensor QbV = dev.empty({nc, n, chi}), QaU = dev.empty({nc, n, chi});
-  gemm_ptrs(dev, false, false, n, chi, n, 1.0, cb.Qb, n,
-            offsets<const double*>(V.ptr, sUV, nc), b, 0.0,
-            offsets<double*>(QbV.ptr, sP, nc), chi);
-  gemm_ptrs(dev, true, false, n, chi, n, 1.0, cb.Qa, n,
-            offsets<const double*>(U.ptr, sUV, nc), b, 0.0,
-            offsets<double*>(QaU.ptr, sP, nc), chi);
+  qmul(dev, dev.cprec, false, n, chi, n, cb.Qb, cb.Qb32, n,
+       offsets<const double*>(V.ptr, sUV, nc), b,
+       offsets<double*>(QbV.ptr, sP, nc), chi);
+  qmul(dev, dev.cprec, true, n, chi, n, cb.Qa, cb.Qa32, n,
+       offsets<const double*>(U.ptr, sUV, nc), b,
+       offsets<double*>(QaU.ptr, sP, nc), chi);
   Tensor Pall = dev.empty({nc, n, chi}), Tall = dev.empty({nc, n, chi});
   col_axpby(dev, nc * n, chi, 1.0, w.ptr, QbV.ptr, 0.0, Pall.ptr, n, chi);
   col_axpby(dev, nc * n, chi, 1.0, w.ptr, QaU.ptr, 0.0, Tall.ptr, n, chi);
@@ -100,8 +121,9 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
   }
   if (!any) return {P, PtT};
   SvdStats* st = &cx.stats;
+  const std::vector<const float*> qa32 = cb.Qa32, qb32 = cb.Qb32;
   tp.push([&tp, Qa, Qb, P, PtT, U, S, V, keep, w, QbV, QaU, n, chi, b, nc,
-           st]() {
+           st, q32, qa32, qb32]() {
     Device& dev = tp.dev;
     // the products with the cut matrices keep the contraction precision of
     // the calling scope; the SVD-adjoint algebra around them is FP64
@@ -165,10 +187,10 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     proj_sbar(dev, S.ptr, kp, chi, wb.ptr, wb.ptr + nc * chi, sbar, nc, b);
     // U_bar, V_bar (columns >= k vanish with w)
     Tensor Vb = dev.empty({nc, n, chi}), Ub = dev.empty({nc, n, chi});
-    gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qb, n, pbw, chi, 0.0,
-              offsets<double*>(Vb.ptr, sP, nc), chi);
-    gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qa, n, tbw, chi, 0.0,
-              offsets<double*>(Ub.ptr, sP, nc), chi);
+    qmul(dev, cp, true, n, chi, n, qb, qb32, n,
+         pbw, chi, offsets<double*>(Vb.ptr, sP, nc), chi);
+    qmul(dev, cp, false, n, chi, n, qa, qa32, n,
+         tbw, chi, offsets<double*>(Ub.ptr, sP, nc), chi);
     // kept block
     Tensor Au = dev.empty({nc, chi, chi}), Av = dev.empty({nc, chi, chi}),
            Gkk = dev.empty({nc, chi, chi});
@@ -219,16 +241,15 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const auto t1r = offsets<const double*>(t1.ptr, sP, nc);
     // out = A in = [s in_c - P_D Qa Qb in_b; s in_b - P'_D Qb^T Qa^T in_c]
     auto apply = [&](const Tensor& in, Tensor& out) {
-      gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qb, n,
-                offsets<const double*>(in.ptr + sP, s2, nc), chi, 0.0, t1w,
-                chi);
-      gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qa, n, t1r, chi, 0.0,
-                offsets<double*>(out.ptr, s2, nc), chi);
+      qmul(dev, cp, false, n, chi, n, qb, qb32, n,
+           offsets<const double*>(in.ptr + sP, s2, nc), chi, t1w, chi);
+      qmul(dev, cp, false, n, chi, n, qa, qa32, n, t1r, chi,
+           offsets<double*>(out.ptr, s2, nc), chi);
       project_out(dev, Ukm.ptr, sP, out.ptr, s2, n, chi, nc);
-      gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qa, n,
-                offsets<const double*>(in.ptr, s2, nc), chi, 0.0, t1w, chi);
-      gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qb, n, t1r, chi, 0.0,
-                offsets<double*>(out.ptr + sP, s2, nc), chi);
+      qmul(dev, cp, true, n, chi, n, qa, qa32, n,
+           offsets<const double*>(in.ptr, s2, nc), chi, t1w, chi);
+      qmul(dev, cp, true, n, chi, n, qb, qb32, n,
+           t1r, chi, offsets<double*>(out.ptr + sP, s2, nc), chi);
       project_out(dev, Vkm.ptr, sP, out.ptr + sP, s2, n, chi, nc);
       col_axpby(dev, nc * 2 * n, chi, 1.0, S.ptr, in.ptr, -1.0, out.ptr,
                 2 * n, b);
@@ -270,14 +291,14 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       double* Zt = YZ.ptr + nc * sNm;
       const auto t2w = offsets<double*>(T2.ptr, sNm, nc);
       const auto t2r = offsets<const double*>(T2.ptr, sNm, nc);
-      gemm_ptrs_p(dev, cp, false, false, n, m, n, 1.0, qb, n,
-                offsets<const double*>(Wv, sNm, nc), m, 0.0, t2w, m);
-      gemm_ptrs_p(dev, cp, false, false, n, m, n, 1.0, qa, n, t2r, m, 0.0,
-                offsets<double*>(Y, sNm, nc), m);
-      gemm_ptrs_p(dev, cp, true, false, n, m, n, 1.0, qa, n,
-                offsets<const double*>(Wu, sNm, nc), m, 0.0, t2w, m);
-      gemm_ptrs_p(dev, cp, true, false, n, m, n, 1.0, qb, n, t2r, m, 0.0,
-                offsets<double*>(Zt, sNm, nc), m);
+      qmul(dev, cp, false, n, m, n, qb, qb32, n,
+           offsets<const double*>(Wv, sNm, nc), m, t2w, m);
+      qmul(dev, cp, false, n, m, n, qa, qa32, n,
+           t2r, m, offsets<double*>(Y, sNm, nc), m);
+      qmul(dev, cp, true, n, m, n, qa, qa32, n,
+           offsets<const double*>(Wu, sNm, nc), m, t2w, m);
+      qmul(dev, cp, true, n, m, n, qb, qb32, n,
+           t2r, m, offsets<double*>(Zt, sNm, nc), m);
       off_kept(Ukm, Y);
       off_kept(Vkm, Zt);
       // K = W^T H W and its eigenbasis
@@ -387,10 +408,9 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const auto qau = offsets<const double*>(QaU.ptr, sP, nc);
     if (!gqa.empty()) {
       // Qa_bar += U (Qb B)^T + C (Qb V)^T
-      gemm_ptrs_p(dev, cp, false, false, n, chi, n, 1.0, qb, n, bm, chi, 0.0, t1w,
-                chi);
+      qmul(dev, cp, false, n, chi, n, qb, qb32, n, bm, chi, t1w, chi);
       gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(ui, ia), b,
-                pick(t1r, ia), chi, 1.0, gqa, n);
+                  pick(t1r, ia), chi, 1.0, gqa, n);
       gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(cm, ia), chi,
                 pick(qbv, ia), chi, 1.0, gqa, n);
     }
@@ -398,10 +418,9 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       // Qb_bar += (Qa^T U) B^T + (Qa^T C) V^T
       gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(qau, ib), chi,
                 pick(bm, ib), chi, 1.0, gqb, n);
-      gemm_ptrs_p(dev, cp, true, false, n, chi, n, 1.0, qa, n, cm, chi, 0.0, t1w,
-                chi);
+      qmul(dev, cp, true, n, chi, n, qa, qa32, n, cm, chi, t1w, chi);
       gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(t1r, ib), chi,
-                pick(vi, ib), b, 1.0, gqb, n);
+                  pick(vi, ib), b, 1.0, gqb, n);
     }
   });
   return {P, PtT};

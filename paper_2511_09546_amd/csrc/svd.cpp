@@ -80,6 +80,19 @@ void orth_block(Device& dev, const Tensor& Z, int batch, int64_t n, int b,
        X.ptr, b, sZ, batch);
 }
 
+void qmul(Device& dev, int prec, bool tA, int64_t M, int64_t N, int64_t K,
+          const std::vector<const double*>& Q,
+          const std::vector<const float*>& Q32, int64_t ldq,
+          const std::vector<const double*>& B, int64_t ldb,
+          const std::vector<double*>& C, int64_t ldc) {
+  PrecScope ps(dev, prec);
+  if (!Q32.empty())
+    gemm_ptrs_a32(dev, tA, false, M, N, K, 1.0, Q32, ldq, B, ldb, 0.0, C,
+                  ldc);
+  else
+    gemm_ptrs(dev, tA, false, M, N, K, 1.0, Q, ldq, B, ldb, 0.0, C, ldc);
+}
+
 int subspace_block(int n, int chi, int oversample) {
   int p = oversample > 0 ? oversample : std::max(16, chi / 3);
   int b = chi + p;
@@ -142,10 +155,10 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
   double prev = INFINITY;
   for (;;) {
     ++it;
-    gemm_ptrs(dev, false, false, n, b, n, 1.0, cb.Qb, n, cptrs(X), b, 0.0,
-              ptrs(T1), b);
-    gemm_ptrs(dev, false, false, n, b, n, 1.0, cb.Qa, n, cptrs(T1), b, 0.0,
-              ptrs(W), b);
+    qmul(dev, dev.cprec, false, n, b, n, cb.Qb, cb.Qb32, n, cptrs(X), b,
+         ptrs(T1), b);
+    qmul(dev, dev.cprec, false, n, b, n, cb.Qa, cb.Qa32, n, cptrs(T1), b,
+         ptrs(W), b);
     svd_ts(dev, W, nc, n, b, U, S, J);
     {
       PrecScope f64(dev, PREC_FP64);
@@ -153,10 +166,10 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
            (int64_t)b * b, 0.0, V.ptr, b, sX, nc);
     }
     if (direct) break;
-    gemm_ptrs(dev, true, false, n, b, n, 1.0, cb.Qa, n, cptrs(U), b, 0.0,
-              ptrs(T1), b);
-    gemm_ptrs(dev, true, false, n, b, n, 1.0, cb.Qb, n, cptrs(T1), b, 0.0,
-              ptrs(Z), b);
+    qmul(dev, dev.cprec, true, n, b, n, cb.Qa, cb.Qa32, n, cptrs(U), b,
+         ptrs(T1), b);
+    qmul(dev, dev.cprec, true, n, b, n, cb.Qb, cb.Qb32, n, cptrs(T1), b,
+         ptrs(Z), b);
     svd_residual(dev, Z.ptr, V.ptr, S.ptr, n, b, std::min(cb.chi, b), res.ptr,
                  nc, sX, b);
     dev.download(res, hres.data());
