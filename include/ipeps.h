@@ -97,7 +97,27 @@ typedef struct {
   int svd_max_iter;   /* max subspace iterations per projector (50) */
   double svd_tol;     /* subspace residual tolerance, relative to s_1
                          (1e-13) */
+  int grad_mode;      /* ipeps_grad_mode of ipeps_energy_grad (K-step) */
+  double adj_tol;     /* fixed-point mode: stop when the cotangent reaching
+                         the converged environment is below adj_tol times
+                         the one leaving the last iteration (1e-13) */
 } ipeps_opts;
+
+/* What ipeps_energy_grad differentiates (Sec. III A, Sec. IV A):
+ *   IPEPS_GRAD_FULL  A -> e(A, F^K(A, env0(A))): K iterations from the
+ *                    trace-boundary start, all of them differentiated;
+ *   IPEPS_GRAD_K     A -> e(A, F^K(A, env*)), env* the environment of the
+ *                    last ctm_converge held fixed (the unrolled "(3+20)"
+ *                    configuration with K = 20);
+ *   IPEPS_GRAD_FP    IPEPS_GRAD_K with K doubled (from grad_K, at most 32
+ *                    grad_K) until the cotangent reaching env* is below
+ *                    adj_tol times the one leaving the last iteration: the
+ *                    derivative at the fixed point. */
+typedef enum {
+  IPEPS_GRAD_FULL = 0,
+  IPEPS_GRAD_K = 1,
+  IPEPS_GRAD_FP = 2
+} ipeps_grad_mode;
 
 /* Fill *opts with the defaults listed above. */
 void ipeps_default_opts(ipeps_opts* opts);

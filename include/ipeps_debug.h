@@ -46,8 +46,8 @@ int ipeps_debug_svd_ts(int n, int b, int batch, const double* W, double* U,
  * iterations, out[1] projector-SVD calls, out[2] largest final subspace
  * residual (relative to s_1), out[3] complement-CG iterations of the
  * backward pass, out[4] complement solves, out[5] device memory held by the
- * context's pool in bytes, out[6] peak of the bytes in use (out has 7
- * entries). */
+ * context's pool in bytes, out[6] peak of the bytes in use, out[7] the
+ * number of unrolled iterations of the last gradient (out has 8 entries). */
 struct ipeps_ctx;
 int ipeps_debug_stats(struct ipeps_ctx* ctx, double* out);
 

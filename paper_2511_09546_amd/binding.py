@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libipeps.so")
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ECG_BREAKDOWN, ESTATE, ENOTIMPL = -1, -2, -3, -4, -5, -6
 FP64, FP32, BF16 = 0, 1, 2
+GRAD_FULL, GRAD_K, GRAD_FP = 0, 1, 2
 
 # every function declared in include/ipeps.h (checked by the CPU tests)
 API_FUNCTIONS = [
@@ -49,7 +50,8 @@ class Term(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("prec", c_int), ("svd_cutoff", c_double), ("grad_K", c_int),
                 ("svd_oversample", c_int), ("svd_max_iter", c_int),
-                ("svd_tol", c_double)]
+                ("svd_tol", c_double), ("grad_mode", c_int),
+                ("adj_tol", c_double)]
 
 
 _lib = None
@@ -302,14 +304,14 @@ class Context:
         return n.value, sec.value, fl.value, by.value
 
     def stats(self) -> dict:
-        out = np.zeros(7)
+        out = np.zeros(8)
         st = load().ipeps_debug_stats(self._h, _dp(out))
         if st != OK:
             raise IpepsError(st, "ipeps_debug_stats")
         return dict(svd_iters=int(out[0]), svd_calls=int(out[1]),
                     svd_worst_residual=float(out[2]), cg_iters=int(out[3]),
                     cg_solves=int(out[4]), pool_bytes=int(out[5]),
-                    peak_live_bytes=int(out[6]))
+                    peak_live_bytes=int(out[6]), grad_K_used=int(out[7]))
 
     def set_env(self, C, T):
         buf = np.concatenate([_f64(C).ravel(), _f64(T).ravel()])

@@ -64,6 +64,27 @@ Var Tape::slice0(const Var& x, int64_t i) {
   return out;
 }
 
+Var Tape::pad3(const Var& x, int a, int b, int c,
+               std::vector<int64_t> shape) {
+  auto out = std::make_shared<Node>();
+  out->v = dev.zeros(shape);
+  const int64_t tot = out->v.numel();
+  const int C = (int)shape.back();
+  const int B = (int)(shape.size() >= 2 ? shape[shape.size() - 2] : 1);
+  if ((int64_t)a * B * C > tot || b > B || c > C ||
+      x->v.numel() != (int64_t)a * b * c)
+    throw ArgError("pad3: shapes do not fit");
+  ipeps::pad3(dev, x->v.ptr, out->v.ptr, a, b, c, B, C);
+  out->req = x->req;
+  if (out->req) {
+    push([this, x, out, a, b, c, B, C]() {
+      if (!has_grad(out)) return;
+      crop3_add(dev, out->g.ptr, grad(x).ptr, a, b, c, B, C);
+    });
+  }
+  return out;
+}
+
 Var Tape::permute(const Var& x, const std::vector<int>& perm) {
   auto out = std::make_shared<Node>();
   out->v = permuted(dev, x->v, perm);

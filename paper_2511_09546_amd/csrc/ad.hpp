@@ -45,6 +45,10 @@ class Tape {
   Var permute(const Var& x, const std::vector<int>& perm);
   // y = x / ||x||_F
   Var normalize(const Var& x);
+  // x [a][b][c] placed at the start of each row block of a zero tensor of
+  // shape `shape` read as [*][B][C] (B, C its last two extents after a 3-d
+  // view): out[l][j][k] = x[l][j][k] for l < a, j < b, k < c
+  Var pad3(const Var& x, int a, int b, int c, std::vector<int64_t> shape);
 
   void push(std::function<void()> f) {
     if (rec) ops_.push_back(std::move(f));

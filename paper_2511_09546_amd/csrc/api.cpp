@@ -58,6 +58,8 @@ void ipeps_default_opts(ipeps_opts* o) {
   o->svd_oversample = 0;
   o->svd_max_iter = 50;
   o->svd_tol = 1e-13;
+  o->grad_mode = IPEPS_GRAD_K;
+  o->adj_tol = 1e-13;
 }
 
 const char* ipeps_version(void) { return "ipeps-mi355x 0.1"; }
@@ -108,7 +110,10 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
   if (o.prec != IPEPS_FP64 && o.prec != IPEPS_FP32 && o.prec != IPEPS_BF16)
     return IPEPS_EINVAL;
   if (!(o.svd_cutoff >= 0.0) || o.grad_K < 0 || o.svd_max_iter < 1 ||
-      !(o.svd_tol >= 0.0) || o.svd_oversample < 0)
+      !(o.svd_tol >= 0.0) || o.svd_oversample < 0 ||
+      (o.grad_mode != IPEPS_GRAD_FULL && o.grad_mode != IPEPS_GRAD_K &&
+       o.grad_mode != IPEPS_GRAD_FP) ||
+      !(o.adj_tol > 0.0) || (o.grad_mode == IPEPS_GRAD_FP && o.grad_K < 1))
     return IPEPS_EINVAL;
   const size_t nA = (size_t)Lx * Ly * d * D * D * D * D;
   if (!all_finite(A, nA)) return IPEPS_EINVAL;
@@ -131,6 +136,8 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
     cx.n = (int64_t)chi * D * D;
     cx.prec = o.prec;
     cx.grad_K = o.grad_K;
+    cx.grad_mode = o.grad_mode;
+    cx.adj_tol = o.adj_tol;
     cx.svd.cutoff = o.svd_cutoff;
     cx.svd.tol = o.svd_tol;
     cx.svd.max_iter = o.svd_max_iter;
@@ -408,6 +415,7 @@ int ipeps_debug_stats(ipeps_ctx* c, double* out) {
   out[4] = (double)st.cg_solves;
   out[5] = (double)c->cx.dev.pool.reserved();
   out[6] = (double)c->cx.dev.pool.peak_live();
+  out[7] = (double)c->cx.grad_K_used;
   return IPEPS_OK;
 }
 

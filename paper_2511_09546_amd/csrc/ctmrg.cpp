@@ -85,15 +85,40 @@ std::vector<Var> site_leaves(Tape& tp, Context& cx, bool req) {
   return r;
 }
 
-VEnv venv_leaves(Tape& tp, Context& cx, const Env& e) {
+VEnv venv_leaves(Tape& tp, Context& cx, const Env& e, bool req) {
   VEnv v;
   const int ns = cx.nsite();
   v.C.resize(4 * ns);
   v.T.resize(4 * ns);
   for (int c = 0; c < 4; ++c)
     for (int s = 0; s < ns; ++s) {
-      v.C[c * ns + s] = tp.leaf(cx.Cv(e, c, s), false);
-      v.T[c * ns + s] = tp.leaf(cx.Tv(e, c, s), false);
+      v.C[c * ns + s] = tp.leaf(cx.Cv(e, c, s), req);
+      v.T[c * ns + s] = tp.leaf(cx.Tv(e, c, s), req);
+    }
+  return v;
+}
+
+VEnv init_env_ad(Tape& tp, Context& cx, const std::vector<Var>& arot) {
+  const int ns = cx.nsite(), chi = cx.chi, D2 = cx.D2;
+  std::vector<double> h((size_t)D2, 0.0);
+  for (int k = 0; k < cx.D; ++k) h[(size_t)k * cx.D + k] = 1.0;
+  Tensor tv = cx.dev.empty({D2});
+  cx.dev.upload(tv, h.data());
+  Var t = tp.leaf(tv, false);
+  VEnv v;
+  v.C.resize(4 * ns);
+  v.T.resize(4 * ns);
+  for (int s = 0; s < ns; ++s)
+    for (int c = 0; c < 4; ++c) {
+      const int sc = cx.lat.shift(s, INIT_CORNER_SITE[c][0],
+                                  INIT_CORNER_SITE[c][1]);
+      Var t1 = tp.einsum("gebf,g->ebf", arot[sc * 4 + c], t);
+      Var cc = tp.einsum("ebf,e->fb", t1, t);
+      v.C[c * ns + s] = tp.pad3(cc, 1, D2, D2, {chi, chi});
+      const int se = cx.lat.shift(s, INIT_EDGE_SITE[c][0],
+                                  INIT_EDGE_SITE[c][1]);
+      Var tt = tp.einsum("gebf,e->gfb", arot[se * 4 + c], t);
+      v.T[c * ns + s] = tp.pad3(tt, D2, D2, D2, {chi, D2, chi});
     }
   return v;
 }

@@ -239,6 +239,9 @@ void svd_residual(Device& dev, const double* Z, const double* V,
                   int batch, int64_t sZ, int64_t sS);
 void pad3(Device& dev, const double* in, double* out, int a, int b, int c,
           int B, int C);
+// adjoint of pad3: gin[l][j][k] += gout[(l B + j) C + k]
+void crop3_add(Device& dev, const double* gout, double* gin, int a, int b,
+               int c, int B, int C);
 void spectra_update(Device& dev, const double* S, int b, int chi, int batch,
                     int64_t sS, double* cur, double* old, double* delta);
 }  // namespace ipeps

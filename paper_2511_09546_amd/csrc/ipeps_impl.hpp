@@ -104,6 +104,9 @@ struct Context {
   int prec = 0;
   double cutoff = 1e-12;
   int grad_K = 20;
+  int grad_mode = 1;     // ipeps_grad_mode
+  double adj_tol = 1e-13;
+  int grad_K_used = 0;   // K of the last gradient (fixed-point mode)
   SvdParams svd;
   SvdStats stats;
 
@@ -131,7 +134,10 @@ std::vector<Var> arot_leaves(Tape& tp, Context& cx);
 std::vector<Var> arot_from_sites(Tape& tp, Context& cx,
                                  const std::vector<Var>& As);
 std::vector<Var> site_leaves(Tape& tp, Context& cx, bool req);
-VEnv venv_leaves(Tape& tp, Context& cx, const Env& e);
+VEnv venv_leaves(Tape& tp, Context& cx, const Env& e, bool req = false);
+// The trace-boundary environment as a function of the double layers on the
+// tape (the start of the full-N gradient).
+VEnv init_env_ad(Tape& tp, Context& cx, const std::vector<Var>& arot);
 Env env_pack(Context& cx, const VEnv& v);
 // One simultaneous CTMRG iteration on the tape.
 VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,

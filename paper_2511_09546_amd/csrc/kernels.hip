@@ -847,6 +847,27 @@ void pad3(Device& dev, const double* in, double* out, int a, int b, int c,
   IPEPS_HIP(hipGetLastError());
 }
 
+__global__ void crop3_add_kernel(const double* gout, double* gin, int a,
+                                 int b, int c, int B, int C) {
+  const int64_t n = (int64_t)a * b * c;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i % c);
+    const int j = (int)((i / c) % b);
+    const int l = (int)(i / ((int64_t)b * c));
+    gin[i] += gout[((int64_t)l * B + j) * C + k];
+  }
+}
+
+void crop3_add(Device& dev, const double* gout, double* gin, int a, int b,
+               int c, int B, int C) {
+  const int64_t n = (int64_t)a * b * c;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(crop3_add_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, gout, gin, a, b, c, B, C);
+  IPEPS_HIP(hipGetLastError());
+}
+
 // Corner-spectrum change: spec[bt] (b values, sorted) normalised to sum 1
 // into out (chi values, zero padded); delta[0] = max_bt ||out - old||_2 and
 // old <- out.  One workgroup.

@@ -142,3 +142,52 @@ def test_adjoint_vs_finite_differences_kitaev():
             _say(f"  seed {seed}: adjoint {ad:.12e} fd {fd:.12e} "
                  f"diff/|g| {abs(fd - ad) / gn:.2e}")
             assert abs(fd - ad) < 1e-8 * gn
+
+
+def test_grad_mode_full():
+    """IPEPS_GRAD_FULL: derivative through the trace-boundary start and N
+    iterations (the D=2, chi=8 workload, N = 30), against the oracle's
+    grad_full element by element."""
+    _say("grad mode full, d2chi8, N=30")
+    w = inputs.WORKLOADS["d2chi8"]
+    A = inputs.workload_state("d2chi8")
+    terms = inputs.workload_terms("d2chi8")
+    e_or, g_or = gradient.grad_full(A, terms, w["chi"], 30)
+    g_or = g_or.numpy()
+    o = binding.default_opts()
+    o.grad_mode = binding.GRAD_FULL
+    o.grad_K = 30
+    with binding.Context(A, w["chi"], opts=o) as ctx:
+        ctx.converge(0.0, 1)
+        e, g = ctx.energy_grad(terms, grad=True)
+        assert ctx.stats()["grad_K_used"] == 30
+    err = np.linalg.norm(g - g_or) / np.linalg.norm(g_or)
+    _say(f"  e {e!r} vs {e_or!r}; rel grad err {err:.2e}")
+    assert abs(e - e_or) < 1e-11 * abs(e_or)
+    assert err < 1e-9
+
+
+def test_grad_mode_fixed_point():
+    """IPEPS_GRAD_FP: K doubled from K0 until the cotangent reaching env*
+    is below adj_tol of the one leaving the last iteration; same rule and
+    same K as the oracle's grad_fp, element-by-element gradient."""
+    _say("grad mode fixed point, D=2 chi=6")
+    A = inputs.random_state(7, 1, 1, 2, 2)
+    terms = inputs.terms_j1j2(1, 1, 1.0, 0.4)
+    chi = 6
+    env, _, _ = ctmrg.converge(A, chi, 1e-13, 500)
+    e_or, g_or, K_or = gradient.grad_fp(A, terms, env, chi, K0=4, rel=1e-10)
+    g_or = g_or.numpy()
+    C, T = _env_arrays(env)
+    o = binding.default_opts()
+    o.grad_mode = binding.GRAD_FP
+    o.grad_K = 4
+    o.adj_tol = 1e-10
+    with binding.Context(A, chi, opts=o) as ctx:
+        ctx.set_env(C, T)
+        e, g = ctx.energy_grad(terms, grad=True)
+        K = ctx.stats()["grad_K_used"]
+    err = np.linalg.norm(g - g_or) / np.linalg.norm(g_or)
+    _say(f"  K {K} vs {K_or}; rel grad err {err:.2e}")
+    assert K == K_or
+    assert err < 1e-9
