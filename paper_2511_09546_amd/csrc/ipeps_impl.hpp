@@ -42,8 +42,11 @@ struct SvdStats {
   long cg_solves = 0;
 };
 
+// tol2: Jacobi criterion of the second pass (1e-15 gives the full FP64
+// accuracy; with FP32 or BF16x3 products upstream 1e-12 is below their
+// rounding and saves a sweep)
 void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
-            Tensor& U, Tensor& S, Tensor& J);
+            Tensor& U, Tensor& S, Tensor& J, double tol2 = 1e-15);
 int subspace_block(int n, int chi, int oversample);
 void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
                    Tensor& U, Tensor& S, Tensor& V, Tensor& keep,

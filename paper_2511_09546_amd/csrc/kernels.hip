@@ -410,132 +410,172 @@ static void allow_lds(const void* fn, size_t bytes) {
 // diagonal blocks take the closed forms above; blocks are disjoint, so a
 // round needs one barrier after the rotation parameters and one after the
 // update (each element of G and V is read and written once per round).
-// G lives in LDS; the eigenvector matrix V too when b <= 96 (2 b^2 doubles
-// fit the 160 KB of LDS), else in global memory.
+//
+// Layout: G is symmetric and only its upper triangle is stored and updated
+// (row stride b + 1), so a round touches the b/2 (b/2 + 1)/2 blocks with
+// a <= c, half of the full matrix.  The eigenvector matrix is kept
+// transposed, Vt[p][k] = V[k][p]: the rotation of pair (p, q) combines rows
+// p and q of Vt, which consecutive lanes read at consecutive k (no LDS bank
+// conflicts).  Vt lives in LDS when it fits next to G (b <= 96), else in the
+// output buffer in global memory.  Every thread's blocks and (pair, k)
+// items are fixed for the whole solve and are computed once, into
+// registers.
 constexpr int JAC_THREADS = 512;
 constexpr int JAC_MAXB = 128;
+// most blocks and (pair, k) items of one thread at b = JAC_MAXB
+constexpr int JAC_GBLK = (64 * 65 / 2 + JAC_THREADS - 1) / JAC_THREADS;  // 5
+constexpr int JAC_VITEM = (64 * 128 + JAC_THREADS - 1) / JAC_THREADS;    // 16
+
+size_t jacobi_lds_bytes(int b, bool vlds) {
+  const size_t h = b / 2;
+  size_t n = (size_t)b * (b + 1) * sizeof(double)  // G, upper triangle
+             + h * 5 * sizeof(double)  // c, s, G_pp, G_qq, t G_pq
+             + h * 2 * sizeof(int);    // p, q
+  if (vlds) n += (size_t)b * b * sizeof(double);
+  return n;
+}
 
 template <bool VLDS>
 __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
     double* __restrict__ Gall, double* __restrict__ Vall,
     double* __restrict__ lamall, int b, double tol) {
   extern __shared__ double lds[];
-  double* G = lds;                  // b*b
-  double* cs = G + b * b;           // b/2
-  double* sn = cs + b / 2;          // b/2
-  double* dp = sn + b / 2;          // b/2: diagonal before the rotation
-  double* dq = dp + b / 2;          // b/2
-  double* tq = dq + b / 2;          // b/2: t * G_pq
-  int* pp = (int*)(tq + b / 2);     // b/2
-  int* qq = pp + b / 2;             // b/2
+  const int S = b + 1, h = b / 2;
+  double* G = lds;        // b x S, entries p <= q
+  double* cs = G + b * S;  // h: rotation cosines
+  double* sn = cs + h;     // h: sines
+  double* dp = sn + h;     // h: G_pp before the rotation
+  double* dq = dp + h;     // h: G_qq
+  double* tq = dq + h;     // h: t G_pq
+  int* pp = (int*)(tq + h);  // h: pair (p, q), p < q
+  int* qq = pp + h;
   __shared__ int rotated;
   const int bt = blockIdx.x;
   double* Gg = Gall + (long)bt * b * b;
   double* Vout = Vall + (long)bt * b * b;
-  // eigenvectors accumulate in LDS when they fit (b <= 96), else in global
-  double* V = VLDS ? (double*)(qq + b / 2 + (b / 2) % 2) : Vout;
+  double* Vt = VLDS ? (double*)(qq + h) : Vout;  // 2h ints: 8-aligned
   double* lam = lamall + (long)bt * b;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < b * b; i += nt) {
-    G[i] = Gg[i];
-    V[i] = (i / b == i % b) ? 1.0 : 0.0;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < b * b; e += JAC_THREADS) {
+    const int p = e / b, q = e - p * b;
+    if (p <= q) G[p * S + q] = Gg[e];
+    Vt[e] = p == q ? 1.0 : 0.0;
   }
+  // this thread's blocks (a, c), a <= c, enumerated row by row, and its
+  // (pair, k) items of the Vt update, packed as a | c << 16
+  const int nblk = h * (h + 1) / 2, nitem = h * b;
+  int blk[JAC_GBLK], item[JAC_VITEM];
+#pragma unroll
+  for (int j = 0; j < JAC_GBLK; ++j) {
+    const int t = tid + j * JAC_THREADS;
+    int a = 0;
+    if (t < nblk)
+      while (t >= (a + 1) * h - (a + 1) * a / 2) ++a;
+    const int c = a + t - (a * h - a * (a - 1) / 2);
+    blk[j] = a | c << 16;
+  }
+  const float invb = 1.0f / (float)b;
+#pragma unroll
+  for (int j = 0; j < JAC_VITEM; ++j) {
+    const int t = tid + j * JAC_THREADS;
+    // t / b exactly: (t + 1/2)/b is at least 1/(2b) away from an integer
+    const int i = (int)(((float)t + 0.5f) * invb);
+    item[j] = i | (t - i * b) << 16;
+  }
+  auto gi = [S](int x, int y) { return x < y ? x * S + y : y * S + x; };
   __syncthreads();
-  const int half = b / 2;
   for (int sweep = 0; sweep < 40; ++sweep) {
     // a sweep rotates some pair iff some pair exceeds the criterion now (if
     // none does, the first round changes nothing and neither do the
     // others): test all pairs first instead of running a sweep to find out
     if (tid == 0) rotated = 0;
     __syncthreads();
-    for (int e = tid; e < b * b; e += nt) {
-      const int p = e / b, q = e % b;
+    bool any = false;
+    for (int e = tid; e < b * b; e += JAC_THREADS) {
+      const int p = e / b, q = e - p * b;
       if (p < q) {
-        const double apq = G[e];
-        if (fabs(apq) > tol * sqrt(fabs(G[p * b + p] * G[q * b + q])) &&
-            apq != 0.0)
-          rotated = 1;
+        const double apq = G[p * S + q];
+        any |= apq != 0.0 &&
+               fabs(apq) > tol * sqrt(fabs(G[p * S + p] * G[q * S + q]));
       }
     }
+    if (any) rotated = 1;
     __syncthreads();
     if (!rotated) break;
     for (int r = 0; r < b - 1; ++r) {
       // pairs of this round, rotation parameters from the current G
-      for (int i = tid; i < half; i += nt) {
-        auto P = [&](int j) { return j == 0 ? 0 : 1 + (j - 1 + r) % (b - 1); };
-        int p = P(i), q = P(b - 1 - i);
+      if (tid < h) {
+        const int i = tid, j = b - 1 - i;
+        int p = i == 0 ? 0 : 1 + (i - 1 + r) % (b - 1);
+        int q = 1 + (j - 1 + r) % (b - 1);
         if (p > q) {
-          int t = p;
+          const int t = p;
           p = q;
           q = t;
         }
-        pp[i] = p;
-        qq[i] = q;
-        const double apq = G[p * b + q];
-        const double app = G[p * b + p], aqq = G[q * b + q];
-        dp[i] = app;
-        dq[i] = aqq;
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > tol * sqrt(fabs(app * aqq)) && apq != 0.0) {
+        const double apq = G[p * S + q];
+        const double app = G[p * S + p], aqq = G[q * S + q];
+        double c = 1.0, s = 0.0, tg = 0.0;
+        if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) /
                            (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
+          tg = t * apq;
         }
         cs[i] = c;
         sn[i] = s;
-        // closed-form new diagonal; the (p,q) entry is annihilated exactly
-        tq[i] = s != 0.0 ? (s / c) * apq : 0.0;
+        dp[i] = app;
+        dq[i] = aqq;
+        tq[i] = tg;
+        pp[i] = p;
+        qq[i] = q;
       }
       __syncthreads();
-      // G <- R G R^T block by block: thread (ya, xc) = (tid / 32, tid % 32)
-      // takes pairs a = ya + 16 i and c = xc + 32 j, parameters in registers
-      {
-        const int ya = tid >> 5, xc = tid & 31;
-        for (int a = ya; a < half; a += 16) {
-          const double sa = sn[a], ca = cs[a];
-          const int pa = pp[a], qa = qq[a];
-          for (int c2 = xc; c2 < half; c2 += 32) {
-            const double sc = sn[c2];
-            if (sa == 0.0 && sc == 0.0) continue;
-            if (a == c2) {
-              G[pa * b + qa] = 0.0;
-              G[qa * b + pa] = 0.0;
-              G[pa * b + pa] = dp[a] - tq[a];
-              G[qa * b + qa] = dq[a] + tq[a];
-              continue;
-            }
-            const double cc = cs[c2];
-            const int pc = pp[c2], qc = qq[c2];
-            const double g00 = G[pa * b + pc], g01 = G[pa * b + qc];
-            const double g10 = G[qa * b + pc], g11 = G[qa * b + qc];
-            // rows: (R_a G)
-            const double h00 = ca * g00 - sa * g10, h01 = ca * g01 - sa * g11;
-            const double h10 = sa * g00 + ca * g10, h11 = sa * g01 + ca * g11;
-            // columns: (R_a G) R_c^T
-            G[pa * b + pc] = cc * h00 - sc * h01;
-            G[pa * b + qc] = sc * h00 + cc * h01;
-            G[qa * b + pc] = cc * h10 - sc * h11;
-            G[qa * b + qc] = sc * h10 + cc * h11;
+      // G <- R G R^T on the upper triangle, block by block
+#pragma unroll
+      for (int j = 0; j < JAC_GBLK; ++j) {
+        if (tid + j * JAC_THREADS >= nblk) break;
+        const int a = blk[j] & 0xffff, c = blk[j] >> 16;
+        const double sa = sn[a];
+        const int pa = pp[a], qa = qq[a];
+        if (a == c) {
+          if (sa != 0.0) {
+            G[pa * S + qa] = 0.0;
+            G[pa * S + pa] = dp[a] - tq[a];
+            G[qa * S + qa] = dq[a] + tq[a];
           }
+          continue;
         }
+        const double sc = sn[c];
+        if (sa == 0.0 && sc == 0.0) continue;
+        const double ca = cs[a], cc = cs[c];
+        const int pc = pp[c], qc = qq[c];
+        const int i00 = gi(pa, pc), i01 = gi(pa, qc);
+        const int i10 = gi(qa, pc), i11 = gi(qa, qc);
+        const double g00 = G[i00], g01 = G[i01], g10 = G[i10], g11 = G[i11];
+        // rows: (R_a G)
+        const double h00 = ca * g00 - sa * g10, h01 = ca * g01 - sa * g11;
+        const double h10 = sa * g00 + ca * g10, h11 = sa * g01 + ca * g11;
+        // columns: (R_a G) R_c^T
+        G[i00] = cc * h00 - sc * h01;
+        G[i01] = sc * h00 + cc * h01;
+        G[i10] = cc * h10 - sc * h11;
+        G[i11] = sc * h10 + cc * h11;
       }
-      // V <- V R^T (columns p, q of every row k): thread (yk, xi) =
-      // (tid / 16, tid % 16) takes rows k = yk + 32 i and pairs xi + 16 j
-      {
-        const int yk = tid >> 4, xi = tid & 15;
-        for (int i = xi; i < half; i += 16) {
-          const double s = sn[i];
-          if (s == 0.0) continue;
-          const double c = cs[i];
-          const int p = pp[i], q = qq[i];
-          for (int k = yk; k < b; k += 32) {
-            const double vp = V[k * b + p], vq = V[k * b + q];
-            V[k * b + p] = c * vp - s * vq;
-            V[k * b + q] = s * vp + c * vq;
-          }
-        }
+      // V <- V R^T: rows p, q of Vt
+#pragma unroll
+      for (int j = 0; j < JAC_VITEM; ++j) {
+        if (tid + j * JAC_THREADS >= nitem) break;
+        const int i = item[j] & 0xffff, k = item[j] >> 16;
+        const double s = sn[i];
+        if (s == 0.0) continue;
+        const double c = cs[i];
+        const int p = pp[i], q = qq[i];
+        const double vp = Vt[p * b + k], vq = Vt[q * b + k];
+        Vt[p * b + k] = c * vp - s * vq;
+        Vt[q * b + k] = s * vp + c * vq;
       }
       __syncthreads();
     }
@@ -544,30 +584,29 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
   // pp/qq and cs/sn are contiguous, giving b ints and b doubles of LDS
   int* rk = pp;
   double* ev = cs;
-  __syncthreads();
-  for (int i = tid; i < b; i += nt) {
-    const double gi = G[i * b + i];
+  for (int i = tid; i < b; i += JAC_THREADS) {
+    const double g = G[i * S + i];
     int rank = 0;
     for (int j = 0; j < b; ++j) {
-      const double gj = G[j * b + j];
-      rank += (gj > gi) || (gj == gi && j < i);
+      const double gj = G[j * S + j];
+      rank += (gj > g) || (gj == g && j < i);
     }
     rk[i] = rank;
   }
   __syncthreads();
-  for (int i = tid; i < b; i += nt) ev[rk[i]] = G[i * b + i];
+  for (int i = tid; i < b; i += JAC_THREADS) ev[rk[i]] = G[i * S + i];
   __syncthreads();
-  // G is no longer needed: permute the columns of V through it
-  for (int e = tid; e < b * b; e += nt) {
-    const int k = e / b, i = e % b;
-    G[k * b + rk[i]] = V[k * b + i];
+  // G is no longer needed: V[k][rk[i]] = Vt[i][k] staged through it
+  for (int e = tid; e < b * b; e += JAC_THREADS) {
+    const int i = e / b, k = e - i * b;
+    G[k * b + rk[i]] = Vt[e];
   }
   __syncthreads();
-  for (int e = tid; e < b * b; e += nt) {
+  for (int e = tid; e < b * b; e += JAC_THREADS) {
     Vout[e] = G[e];
     Gg[e] = (e / b == e % b) ? ev[e / b] : 0.0;
   }
-  for (int i = tid; i < b; i += nt) lam[i] = ev[i];
+  for (int i = tid; i < b; i += JAC_THREADS) lam[i] = ev[i];
 }
 
 void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
@@ -575,9 +614,7 @@ void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
   if (b % 2 != 0 || b < 2 || b > JAC_MAXB)
     throw ArgError("sym_eig_jacobi: b must be even and <= 128");
   const bool vlds = b <= 96;
-  size_t lds = (size_t)b * b * sizeof(double) + 5 * (b / 2) * sizeof(double) +
-               2 * ((b / 2) + (b / 2) % 2) * sizeof(int);
-  if (vlds) lds += (size_t)b * b * sizeof(double);
+  const size_t lds = jacobi_lds_bytes(b, vlds);
   const void* fn = vlds ? (const void*)sym_eig_jacobi_kernel<true>
                         : (const void*)sym_eig_jacobi_kernel<false>;
   if (lds > 65536) allow_lds(fn, lds);

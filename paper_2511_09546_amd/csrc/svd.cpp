@@ -27,7 +27,7 @@
 namespace ipeps {
 
 void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
-            Tensor& U, Tensor& S, Tensor& J) {
+            Tensor& U, Tensor& S, Tensor& J, double tol2) {
   PrecScope f64(dev, PREC_FP64);
   const int64_t sW = n * b, sG = (int64_t)b * b;
   Tensor G = dev.empty({batch, b, b});
@@ -46,7 +46,7 @@ void svd_ts(Device& dev, const Tensor& W, int batch, int64_t n, int b,
   // pass 2
   gemm(dev, true, false, b, b, n, 1.0, B1.ptr, b, sW, B1.ptr, b, sW, 0.0,
        G.ptr, b, sG, batch);
-  sym_eig_jacobi(dev, G.ptr, J2.ptr, lam.ptr, b, batch);
+  sym_eig_jacobi(dev, G.ptr, J2.ptr, lam.ptr, b, batch, tol2);
   if (U.numel() != batch * n * b) U = dev.empty({batch, n, b});
   if (S.numel() != batch * b) S = dev.empty({batch, b});
   if (J.numel() != batch * sG) J = dev.empty({batch, b, b});
@@ -159,7 +159,7 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
          ptrs(T1), b);
     qmul(dev, dev.cprec, false, n, b, n, cb.Qa, cb.Qa32, n, cptrs(T1), b,
          ptrs(W), b);
-    svd_ts(dev, W, nc, n, b, U, S, J);
+    svd_ts(dev, W, nc, n, b, U, S, J, lowp ? 1e-12 : 1e-15);
     {
       PrecScope f64(dev, PREC_FP64);
       gemm(dev, false, false, n, b, b, 1.0, X.ptr, b, sX, J.ptr, b,
