@@ -100,6 +100,16 @@ double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
   } restore{cx, warm, have_warm};
   const int K = cx.grad_K;
   double n_in = 0.0, n_out = 0.0;
+  // the complement solves of one gradient start from each other's
+  // solutions, never from an earlier gradient's
+  cx.have_cg_warm = false;
+  struct DropCg {
+    Context& c;
+    ~DropCg() {
+      c.have_cg_warm = false;
+      c.cg_warm = Tensor();
+    }
+  } drop_cg{cx};
   if (cx.grad_mode == 0) {
     // the full function starts, like a cold ctm_converge, without a warm
     // start for the first projector SVD
@@ -116,6 +126,7 @@ double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
   for (int k = K;; k *= 2) {
     cx.Xwarm = warm;
     cx.have_warm = have_warm;
+    cx.have_cg_warm = false;
     const double e = run(cx, terms, k, false, true, grad_host, on_device,
                          &n_in, &n_out);
     cx.grad_K_used = k;

@@ -121,6 +121,10 @@ struct Context {
   bool converged_once = false;
   Tensor Xwarm;         // [ncut][n][b] right singular blocks (warm start)
   bool have_warm = false;
+  // solution of the last complement solve of the projector backward
+  // ([ncut][2][n][chi]), the start of the next one within one gradient
+  Tensor cg_warm;
+  bool have_cg_warm = false;
   Tensor spec_cur, spec_old;  // [4*nsite][chi]
 
   int nsite() const { return lat.n(); }

@@ -121,9 +121,10 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
   }
   if (!any) return {P, PtT};
   SvdStats* st = &cx.stats;
+  Context* cxp = &cx;
   const std::vector<const float*> qa32 = cb.Qa32, qb32 = cb.Qb32;
   tp.push([&tp, Qa, Qb, P, PtT, U, S, V, keep, w, QbV, QaU, n, chi, b, nc,
-           st, q32, qa32, qb32]() {
+           st, cxp, q32, qa32, qb32]() {
     Device& dev = tp.dev;
     // the products with the cut matrices keep the contraction precision of
     // the calling scope; the SVD-adjoint algebra around them is FP64
@@ -337,14 +338,33 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     };
     coldot(dev, rhs.ptr, rhs.ptr, 2 * n, chi, rr0, nc, s2);
     axpby(dev, tot, 1.0, rhs.ptr, 0.0, R.ptr);
+    // Start from the previous solve of this gradient when there is one (the
+    // unrolled iterations near the fixed point solve nearly the same systems
+    // with nearly parallel right-hand sides): x_g = alpha_j x_prev_j with
+    // alpha_j = <rhs_j, A_j x_prev_j> / |A_j x_prev_j|^2, the multiple of the
+    // previous solution with the smallest residual, r = rhs - alpha_j A_j
+    // x_prev_j.  The Galerkin correction below then makes r orthogonal to W.
+    // CG converges to the same solution from any start; only the iteration
+    // count changes.
+    const bool warm = cxp->have_cg_warm && cxp->cg_warm.numel() == tot;
+    if (warm) {
+      apply(cxp->cg_warm, AP);
+      coldot(dev, AP.ptr, rhs.ptr, 2 * n, chi, rp, nc, s2);
+      coldot(dev, AP.ptr, AP.ptr, 2 * n, chi, pap, nc, s2);
+      colcg(dev, 0, nc * 2 * n, chi, rp, pap, X.ptr, R.ptr,
+            cxp->cg_warm.ptr, AP.ptr, 2 * n);
+    }
     if (m > 0) {
-      // x0 = W Phi c, r0 = rhs - A_j x0 = rhs - s_j x0 + (H W Phi) c
-      gemm(dev, true, false, m4, chi, 2 * n, 1.0, Xi.ptr, m4, sXi, rhs.ptr,
+      // x0 = x_g + W Phi c with c = (W^T A_j W)^-1 W^T r in the eigenbasis,
+      // r0 = r - A_j W Phi c = r - s_j W Phi c + (H W Phi) c
+      gemm(dev, true, false, m4, chi, 2 * n, 1.0, Xi.ptr, m4, sXi, R.ptr,
            chi, s2, 0.0, Hd.ptr, chi, sH, nc);
       defl_coef(dev, 0, S.ptr, kp, lamK.ptr, chi, m2, b, Hd.ptr, Cf.ptr, nc);
+      Tensor Dx = warm ? dev.empty({nc, 2, n, chi}) : X;
       gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr, m4, sXi, Cf.ptr,
-           chi, sC, 0.0, X.ptr, chi, s2, nc);
-      col_axpby(dev, nc * 2 * n, chi, -1.0, S.ptr, X.ptr, 1.0, R.ptr, 2 * n,
+           chi, sC, 0.0, Dx.ptr, chi, s2, nc);
+      if (warm) axpby(dev, tot, 1.0, Dx.ptr, 1.0, X.ptr);
+      col_axpby(dev, nc * 2 * n, chi, -1.0, S.ptr, Dx.ptr, 1.0, R.ptr, 2 * n,
                 b);
       gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr + m2, m4, sXi,
            Cf.ptr, chi, sC, 1.0, R.ptr, chi, s2, nc);
@@ -354,16 +374,33 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     coldot(dev, R.ptr, R.ptr, 2 * n, chi, rr, nc, s2);
     std::vector<double> h(5 * nc * chi);
     // relative residual 1e-12 with FP64 products; with FP32 products 1e-5
-    // (BF16x3: 1e-3), and the solve also ends when four iterations no longer
-    // reduce the worst relative residual by half (rounding floor of the
-    // products)
+    // (BF16x3: 1e-3), and the solve also ends when two iterations no longer
+    // reduce the worst relative residual by a factor 1/sqrt(2) (rounding
+    // floor of the products).  Tested before the first iteration of a warm
+    // start and after every second iteration.
     const bool lowp = cp != PREC_FP64;
     const double tol2 = cp == PREC_FP64 ? 1e-24 : (cp == PREC_FP32 ? 1e-10
                                                                    : 1e-6);
     double prev_worst = INFINITY;
+    auto converged = [&](bool stagnation) {
+      dev.download(sc, h.data());
+      bool done = true;
+      double worst = 0.0;
+      const double* hr = h.data();
+      const double* h0 = h.data() + 3 * nc * chi;
+      for (int j = 0; j < nc * chi; ++j)
+        if (h0[j] > 0.0) {
+          worst = std::max(worst, hr[j] / h0[j]);
+          if (hr[j] > tol2 * h0[j]) done = false;
+        }
+      if (stagnation && lowp && worst > 0.5 * prev_worst) done = true;
+      prev_worst = worst;
+      return done;
+    };
     const int max_it = 600;
     int it = 0;
-    for (; it < max_it; ++it) {
+    const bool done0 = warm && converged(false);
+    for (; !done0 && it < max_it; ++it) {
       apply(Pp, AP);
       coldot(dev, Pp.ptr, AP.ptr, 2 * n, chi, pap, nc, s2);
       // x += alpha p, r -= alpha A p with alpha = <r, p> / <p, A p> (equal
@@ -376,27 +413,15 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
             2 * n);
       if (m > 0) deflate(R.ptr, Pp.ptr);
       axpby(dev, nc * chi, 1.0, rrn, 0.0, rr);
-      if ((it + 1) % 4 == 0) {
-        dev.download(sc, h.data());
-        bool done = true;
-        double worst = 0.0;
-        const double* hr = h.data();
-        const double* h0 = h.data() + 3 * nc * chi;
-        for (int j = 0; j < nc * chi; ++j)
-          if (h0[j] > 0.0) {
-            worst = std::max(worst, hr[j] / h0[j]);
-            if (hr[j] > tol2 * h0[j]) done = false;
-          }
-        if (lowp && worst > 0.25 * prev_worst) done = true;
-        prev_worst = worst;
-        if (done) {
-          ++it;
-          break;
-        }
+      if ((it + 1) % 2 == 0 && converged(true)) {
+        ++it;
+        break;
       }
     }
     st->cg_iters += it;
     st->cg_solves += nc;
+    cxp->cg_warm = X;
+    cxp->have_cg_warm = true;
     // B = V Gkk^T + b_part, C = c_part
     Tensor Bm = dev.empty({nc, n, chi});
     copy2d(dev, X.ptr + sP, chi, Bm.ptr, chi, n, chi, nc, s2, sP);
