@@ -173,6 +173,11 @@ void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                    double beta, const std::vector<double*>& C, int64_t ldc);
 // y[i] = (float) x[i]
 void to_f32(Device& dev, const double* x, float* y, int64_t n);
+// dst (cols x rows) = src^T (rows x cols), row major
+void transpose(Device& dev, const double* src, double* dst, int64_t rows,
+               int64_t cols);
+void transpose(Device& dev, const float* src, float* dst, int64_t rows,
+               int64_t cols);
 
 // out = alpha * permute(in, perm) + beta * out (rank <= 12 after merging
 // contiguous dims); out.shape[i] =

@@ -245,6 +245,48 @@ void to_f32(Device& dev, const double* x, float* y, int64_t n) {
   IPEPS_HIP(hipGetLastError());
 }
 
+// dst (cols x rows) = src^T (rows x cols), row major, 32 x 32 tiles staged
+// through LDS (row stride 33) so that reads and writes are both coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(
+    const T* __restrict__ src, T* __restrict__ dst, int64_t rows,
+    int64_t cols) {
+  __shared__ T tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // ty < 8
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    if (r < rows && c < cols) tile[i][tx] = src[r * cols + c];
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols && r < rows) dst[c * rows + r] = tile[tx][i];
+  }
+}
+
+template <typename T>
+static void transpose_t(Device& dev, const T* src, T* dst, int64_t rows,
+                        int64_t cols) {
+  if (rows <= 0 || cols <= 0) return;
+  if ((rows + 31) / 32 > 65535) throw ArgError("transpose: too many rows");
+  hipLaunchKernelGGL(transpose_kernel<T>,
+                     dim3((unsigned)((cols + 31) / 32),
+                          (unsigned)((rows + 31) / 32)),
+                     dim3(256), 0, dev.stream, src, dst, rows, cols);
+  IPEPS_HIP(hipGetLastError());
+}
+
+void transpose(Device& dev, const double* src, double* dst, int64_t rows,
+               int64_t cols) {
+  transpose_t(dev, src, dst, rows, cols);
+}
+
+void transpose(Device& dev, const float* src, float* dst, int64_t rows,
+               int64_t cols) {
+  transpose_t(dev, src, dst, rows, cols);
+}
+
 __global__ void scale_dev_kernel(double* x, int64_t n, const double* s,
                                  int inverse) {
   const double f = inverse ? 1.0 / s[0] : s[0];

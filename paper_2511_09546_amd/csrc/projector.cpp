@@ -231,27 +231,72 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     if (m < 2) m = 0;
     const int m2 = 2 * m, m4 = 4 * m;
     const int64_t sXi = 2 * n * m4, sNm = n * m;
-    Tensor X = dev.zeros({nc, 2, n, chi}), R = dev.empty({nc, 2, n, chi});
-    Tensor Pp = dev.empty({nc, 2, n, chi}), AP = dev.empty({nc, 2, n, chi});
-    Tensor t1 = dev.empty({nc, n, chi});
-    Tensor sc = dev.empty({5, nc, chi});  // rr, pAp, rr_new, rr0, <r, p>
-    double *rr = sc.ptr, *pap = sc.ptr + nc * chi, *rrn = pap + nc * chi,
-           *rr0 = rrn + nc * chi, *rp = rr0 + nc * chi;
+    Tensor X = dev.zeros({nc, 2, n, chi});
+    // R, P, A P as consecutive slices: <r, p> and <p, A p> are then one
+    // strided column-dot launch over 2 nc blocks
+    Tensor RPA = dev.empty({3, nc, 2, n, chi});
+    Tensor R = RPA.slice0(0), Pp = RPA.slice0(1), AP = RPA.slice0(2);
+    Tensor t2 = dev.empty({nc, 2, n, chi});
+    Tensor sc = dev.empty({5, nc, chi});  // <r, p>, pAp, rr, rr_new, rr0
+    double *rp = sc.ptr, *pap = rp + nc * chi, *rr = pap + nc * chi,
+           *rrn = rr + nc * chi, *rr0 = rrn + nc * chi;
     const int64_t tot = nc * s2;
-    const auto t1w = offsets<double*>(t1.ptr, sP, nc);
-    const auto t1r = offsets<const double*>(t1.ptr, sP, nc);
-    // out = A in = [s in_c - P_D Qa Qb in_b; s in_b - P'_D Qb^T Qa^T in_c]
+    // transposed copies of the distinct cut matrices (in the storage the
+    // products read: FP32 copies with FP32/BF16x3 products), so that every
+    // product of A is an untransposed product and the two halves of A go
+    // out in one launch each
+    std::vector<Tensor> qt_keep;
+    std::map<const void*, const void*> qt_made;
+    auto qt = [&](const void* q, bool f32) {
+      auto it = qt_made.find(q);
+      if (it != qt_made.end()) return it->second;
+      Tensor t = dev.empty({f32 ? (n * n + 1) / 2 : n * n});
+      if (f32)
+        transpose(dev, (const float*)q, (float*)t.ptr, n, n);
+      else
+        transpose(dev, (const double*)q, t.ptr, n, n);
+      qt_keep.push_back(t);
+      return qt_made[q] = (const void*)t.ptr;
+    };
+    const bool f32q = !qa32.empty();
+    std::vector<const double*> s1q(2 * nc), s2q(2 * nc);
+    std::vector<const float*> s1q32, s2q32;
+    for (int c = 0; c < nc; ++c) {
+      s1q[2 * c] = qb[c];
+      s2q[2 * c] = qa[c];
+      if (f32q) {
+        s1q32.push_back(qb32[c]);
+        s1q32.push_back((const float*)qt(qa32[c], true));
+        s2q32.push_back(qa32[c]);
+        s2q32.push_back((const float*)qt(qb32[c], true));
+      } else {
+        s1q[2 * c + 1] = (const double*)qt(qa[c], false);
+        s2q[2 * c + 1] = (const double*)qt(qb[c], false);
+      }
+    }
+    // kept vectors of both halves, interleaved per cut like out: [nc][2][n][chi]
+    Tensor UVk = dev.empty({nc, 2, n, chi});
+    copy2d(dev, Ukm.ptr, chi, UVk.ptr, chi, n, chi, nc, sP, s2);
+    copy2d(dev, Vkm.ptr, chi, UVk.ptr + sP, chi, n, chi, nc, sP, s2);
+    const auto t2w = offsets<double*>(t2.ptr, sP, 2 * nc);
+    const auto t2r = offsets<const double*>(t2.ptr, sP, 2 * nc);
+    const auto t1w = offsets<double*>(t2.ptr, sP, nc);  // n x chi per cut
+    const auto t1r = offsets<const double*>(t2.ptr, sP, nc);
+    // out = A in = [s in_c - P_D Qa Qb in_b; s in_b - P'_D Qb^T Qa^T in_c]:
+    // t = [Qb in_b; Qa^T in_c], then [Qa t_1; Qb^T t_2], both halves
+    // projected off the kept vectors in one batched pair of products
     auto apply = [&](const Tensor& in, Tensor& out) {
-      qmul(dev, cp, false, n, chi, n, qb, qb32, n,
-           offsets<const double*>(in.ptr + sP, s2, nc), chi, t1w, chi);
-      qmul(dev, cp, false, n, chi, n, qa, qa32, n, t1r, chi,
-           offsets<double*>(out.ptr, s2, nc), chi);
-      project_out(dev, Ukm.ptr, sP, out.ptr, s2, n, chi, nc);
-      qmul(dev, cp, true, n, chi, n, qa, qa32, n,
-           offsets<const double*>(in.ptr, s2, nc), chi, t1w, chi);
-      qmul(dev, cp, true, n, chi, n, qb, qb32, n,
-           t1r, chi, offsets<double*>(out.ptr + sP, s2, nc), chi);
-      project_out(dev, Vkm.ptr, sP, out.ptr + sP, s2, n, chi, nc);
+      std::vector<const double*> bi(2 * nc);
+      std::vector<double*> co(2 * nc);
+      for (int c = 0; c < nc; ++c) {
+        bi[2 * c] = in.ptr + c * s2 + sP;
+        bi[2 * c + 1] = in.ptr + c * s2;
+        co[2 * c] = out.ptr + c * s2;
+        co[2 * c + 1] = out.ptr + c * s2 + sP;
+      }
+      qmul(dev, cp, false, n, chi, n, s1q, s1q32, n, bi, chi, t2w, chi);
+      qmul(dev, cp, false, n, chi, n, s2q, s2q32, n, t2r, chi, co, chi);
+      project_out(dev, UVk.ptr, sP, out.ptr, sP, n, chi, 2 * nc);
       col_axpby(dev, nc * 2 * n, chi, 1.0, S.ptr, in.ptr, -1.0, out.ptr,
                 2 * n, b);
     };
@@ -386,8 +431,8 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       dev.download(sc, h.data());
       bool done = true;
       double worst = 0.0;
-      const double* hr = h.data();
-      const double* h0 = h.data() + 3 * nc * chi;
+      const double* hr = h.data() + 2 * nc * chi;  // rr
+      const double* h0 = h.data() + 4 * nc * chi;  // rr0
       for (int j = 0; j < nc * chi; ++j)
         if (h0[j] > 0.0) {
           worst = std::max(worst, hr[j] / h0[j]);
@@ -402,10 +447,12 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const bool done0 = warm && converged(false);
     for (; !done0 && it < max_it; ++it) {
       apply(Pp, AP);
-      coldot(dev, Pp.ptr, AP.ptr, 2 * n, chi, pap, nc, s2);
       // x += alpha p, r -= alpha A p with alpha = <r, p> / <p, A p> (equal
       // to <r, r> / <p, A p> when p is exactly A-orthogonal to W)
-      if (m > 0) coldot(dev, R.ptr, Pp.ptr, 2 * n, chi, rp, nc, s2);
+      if (m > 0)  // <r, p> and <p, A p> (consecutive slices of RPA)
+        coldot(dev, R.ptr, Pp.ptr, 2 * n, chi, rp, 2 * nc, s2);
+      else
+        coldot(dev, Pp.ptr, AP.ptr, 2 * n, chi, pap, nc, s2);
       colcg(dev, 0, nc * 2 * n, chi, m > 0 ? rp : rr, pap, X.ptr, R.ptr,
             Pp.ptr, AP.ptr, 2 * n);
       coldot(dev, R.ptr, R.ptr, 2 * n, chi, rrn, nc, s2);
