@@ -46,8 +46,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int KPAD = 1;   // row stride BK + 1 for operands read along K
-constexpr int MPAD = 2;   // row stride BM + 2 for operands read along M/N
+// LDS row padding.  FP64 tiles: row stride BK + 1 for operands read along
+// K, X + 2 for operands read along M/N (X = BM or BN).  FP32 tiles (4-byte
+// banks): BK + 2 puts the 16 rows x 2 K values that half a wave reads for
+// one MFMA operand on 32 distinct banks, and a K-major stride of 16 mod 32
+// puts K rows k and k+1 of 16 consecutive columns on distinct banks.
+template <bool F32>
+struct Pad {
+  static constexpr int K = F32 ? 2 : 1;
+  static constexpr int M(int x) { return F32 ? ((16 - x) % 32 + 32) % 32 : 2; }
+};
 constexpr int MAXP = 16;  // pointer triples per launch
 
 struct PtrArgs {
@@ -72,8 +80,11 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
   constexpr int AE = BM * BK / 256, BE = BK * BN / 256;
   // A: k-major [BK][BM + MPAD] when TA (or KM), else m-major [BM][BK + KPAD]
   constexpr bool AK = TA || KM, BKM = !TB || KM;
-  constexpr int A_ROWS = AK ? BK : BM, A_COLS = AK ? BM + MPAD : BK + KPAD;
-  constexpr int B_ROWS = BKM ? BK : BN, B_COLS = BKM ? BN + MPAD : BK + KPAD;
+  constexpr int KPAD = Pad<F32>::K;
+  constexpr int A_ROWS = AK ? BK : BM;
+  constexpr int A_COLS = AK ? BM + Pad<F32>::M(BM) : BK + KPAD;
+  constexpr int B_ROWS = BKM ? BK : BN;
+  constexpr int B_COLS = BKM ? BN + Pad<F32>::M(BN) : BK + KPAD;
   __shared__ T As[2][A_ROWS][A_COLS];
   __shared__ T Bs[2][B_ROWS][B_COLS];
 
