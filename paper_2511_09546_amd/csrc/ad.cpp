@@ -36,6 +36,88 @@ Var Tape::einsum(const std::string& spec, const Var& a, const Var& b) {
   return out;
 }
 
+// target[i] += einsum(spec, first[i], second[i]) for the listed items, in
+// batched launches whose targets are distinct (an item whose target already
+// occurs in the current launch goes to a later one)
+static void accumulate_n(Device& dev, const std::string& spec,
+                         std::vector<Tensor> first, std::vector<Tensor> second,
+                         std::vector<Tensor> target,
+                         std::vector<const Node*> key) {
+  while (!first.empty()) {
+    std::vector<Tensor> f, s, t, f2, s2, t2;
+    std::vector<const Node*> used, k2;
+    for (size_t i = 0; i < first.size(); ++i) {
+      bool dup = false;
+      for (const Node* u : used) dup = dup || u == key[i];
+      if (dup) {
+        f2.push_back(first[i]);
+        s2.push_back(second[i]);
+        t2.push_back(target[i]);
+        k2.push_back(key[i]);
+      } else {
+        f.push_back(first[i]);
+        s.push_back(second[i]);
+        t.push_back(target[i]);
+        used.push_back(key[i]);
+      }
+    }
+    einsum_into_n(dev, spec, f, s, t, 1.0, 1.0);
+    first.swap(f2);
+    second.swap(s2);
+    target.swap(t2);
+    key.swap(k2);
+  }
+}
+
+std::vector<Var> Tape::einsum_n(const std::string& spec,
+                                const std::vector<Var>& a,
+                                const std::vector<Var>& b) {
+  const size_t ni = a.size();
+  std::vector<Tensor> av(ni), bv(ni);
+  for (size_t i = 0; i < ni; ++i) {
+    av[i] = a[i]->v;
+    bv[i] = b[i]->v;
+  }
+  std::vector<Tensor> ov = ipeps::einsum_n(dev, spec, av, bv);
+  std::vector<Var> out(ni);
+  bool any = false;
+  for (size_t i = 0; i < ni; ++i) {
+    out[i] = std::make_shared<Node>();
+    out[i]->v = ov[i];
+    out[i]->req = rec && (a[i]->req || b[i]->req);
+    any = any || out[i]->req;
+  }
+  if (any) {
+    std::string la, lb, lo;
+    parse3(spec, la, lb, lo);
+    push([this, a, b, out, la, lb, lo]() {
+      std::vector<Tensor> f, s, t;
+      std::vector<const Node*> k;
+      for (size_t i = 0; i < out.size(); ++i)
+        if (has_grad(out[i]) && a[i]->req) {
+          f.push_back(out[i]->g);
+          s.push_back(b[i]->v);
+          t.push_back(grad(a[i]));
+          k.push_back(a[i].get());
+        }
+      accumulate_n(dev, lo + "," + lb + "->" + la, f, s, t, k);
+      f.clear();
+      s.clear();
+      t.clear();
+      k.clear();
+      for (size_t i = 0; i < out.size(); ++i)
+        if (has_grad(out[i]) && b[i]->req) {
+          f.push_back(a[i]->v);
+          s.push_back(out[i]->g);
+          t.push_back(grad(b[i]));
+          k.push_back(b[i].get());
+        }
+      accumulate_n(dev, la + "," + lo + "->" + lb, f, s, t, k);
+    });
+  }
+  return out;
+}
+
 Var Tape::view(const Var& x, std::vector<int64_t> shape) {
   auto out = std::make_shared<Node>();
   out->v = x->v.view(std::move(shape));

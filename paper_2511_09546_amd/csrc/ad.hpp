@@ -39,6 +39,10 @@ class Tape {
   bool has_grad(const Var& x) const { return x->g.ptr != nullptr; }
 
   Var einsum(const std::string& spec, const Var& a, const Var& b);
+  // the same contraction for items of one shape, batched in one GEMM launch
+  // forwards and backwards
+  std::vector<Var> einsum_n(const std::string& spec, const std::vector<Var>& a,
+                            const std::vector<Var>& b);
   Var view(const Var& x, std::vector<int64_t> shape);
   // i-th sub-tensor along the leading dimension (shares memory)
   Var slice0(const Var& x, int64_t i);

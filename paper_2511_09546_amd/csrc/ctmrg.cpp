@@ -175,15 +175,23 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
   auto T = [&](int c, int s) { return in.T[c * ns + s]; };
   auto a = [&](int s, int c) { return arot[s * 4 + c]; };
 
-  // enlarged corners Q_c(s)[(m f), (k b)]
+  // enlarged corners Q_c(s)[(m f), (k b)], all corners of all sites in one
+  // batched contraction per step
   std::vector<Var> Q(4 * ns);
-  for (int c = 0; c < 4; ++c)
-    for (int s = 0; s < ns; ++s) {
-      Var X1 = tp.einsum("mgi,ij->mgj", T((c + 3) % 4, s), C(c, s));
-      Var X2 = tp.einsum("mgj,jek->mgek", X1, T(c, s));
-      Q[c * ns + s] = tp.view(tp.einsum("mgek,gebf->mfkb", X2, a(s, c)),
-                              {n, n});
-    }
+  {
+    std::vector<Var> Tl(4 * ns), Cc(4 * ns), Tc(4 * ns), ac(4 * ns);
+    for (int c = 0; c < 4; ++c)
+      for (int s = 0; s < ns; ++s) {
+        Tl[c * ns + s] = T((c + 3) % 4, s);
+        Cc[c * ns + s] = C(c, s);
+        Tc[c * ns + s] = T(c, s);
+        ac[c * ns + s] = a(s, c);
+      }
+    std::vector<Var> X1 = tp.einsum_n("mgi,ij->mgj", Tl, Cc);
+    std::vector<Var> X2 = tp.einsum_n("mgj,jek->mgek", X1, Tc);
+    std::vector<Var> Qe = tp.einsum_n("mgek,gebf->mfkb", X2, ac);
+    for (int i = 0; i < 4 * ns; ++i) Q[i] = tp.view(Qe[i], {n, n});
+  }
   // projectors of every cut: cut index c*ns + p (plaquette p, cut c between
   // its corners c and c+1)
   std::vector<Var> Qa(nc), Qb(nc);
@@ -199,26 +207,40 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
   const std::vector<Var>& P = proj.first;
   const std::vector<Var>& PtT = proj.second;
 
+  // renormalised corners and edges, each contraction batched over all
+  // corners of all sites
   VEnv out;
   out.C.resize(4 * ns);
   out.T.resize(4 * ns);
+  const int m = 4 * ns;
+  std::vector<Var> PtL(m), Qc(m), PR(m), Pt3(m), Tc(m), ac(m), P3(m);
   for (int c = 0; c < 4; ++c)
     for (int s = 0; s < ns; ++s) {
+      const int i = c * ns + s;
       const int p = L.shift(s, -PLAQ_OFFSET[c][0], -PLAQ_OFFSET[c][1]);
       const int cutL = ((c + 3) % 4) * ns + p, cutR = c * ns + p;
-      Var Y = tp.einsum("rx,rq->xq", PtT[cutL], Q[c * ns + s]);
-      Var Cn = tp.einsum("xq,qy->xy", Y, P[cutR]);
-      out.C[c * ns + L.shift(s, CORNER_MOVE[c][0], CORNER_MOVE[c][1])] =
-          tp.normalize(Cn);
+      PtL[i] = PtT[cutL];
+      Qc[i] = Q[i];
+      PR[i] = P[cutR];
       const int pccw = L.shift(s, -PLAQ_OFFSET[(c + 1) % 4][0],
                                -PLAQ_OFFSET[(c + 1) % 4][1]);
-      Var Pt3 = tp.view(PtT[c * ns + pccw], {chi, D2, chi});
-      Var Y1 = tp.einsum("jgx,jek->xgek", Pt3, T(c, s));
-      Var Y2 = tp.einsum("xgek,gebf->xkbf", Y1, a(s, c));
-      Var P3 = tp.view(P[cutR], {chi, D2, chi});
-      Var Tn = tp.einsum("xkbf,kby->xfy", Y2, P3);
+      Pt3[i] = tp.view(PtT[c * ns + pccw], {chi, D2, chi});
+      Tc[i] = T(c, s);
+      ac[i] = a(s, c);
+      P3[i] = tp.view(P[cutR], {chi, D2, chi});
+    }
+  std::vector<Var> Y = tp.einsum_n("rx,rq->xq", PtL, Qc);
+  std::vector<Var> Cn = tp.einsum_n("xq,qy->xy", Y, PR);
+  std::vector<Var> Y1 = tp.einsum_n("jgx,jek->xgek", Pt3, Tc);
+  std::vector<Var> Y2 = tp.einsum_n("xgek,gebf->xkbf", Y1, ac);
+  std::vector<Var> Tn = tp.einsum_n("xkbf,kby->xfy", Y2, P3);
+  for (int c = 0; c < 4; ++c)
+    for (int s = 0; s < ns; ++s) {
+      const int i = c * ns + s;
+      out.C[c * ns + L.shift(s, CORNER_MOVE[c][0], CORNER_MOVE[c][1])] =
+          tp.normalize(Cn[i]);
       out.T[c * ns + L.shift(s, EDGE_MOVE[c][0], EDGE_MOVE[c][1])] =
-          tp.normalize(Tn);
+          tp.normalize(Tn[i]);
     }
   return out;
 }

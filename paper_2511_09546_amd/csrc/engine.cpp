@@ -264,8 +264,22 @@ static int64_t dim_of(char ch, const std::string& la, const Tensor& A,
   return B.shape[lb.find(ch)];
 }
 
-void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
-                 const Tensor& B, Tensor& out, double alpha, double beta) {
+void einsum_into_n(Device& dev, const std::string& spec,
+                   const std::vector<Tensor>& As,
+                   const std::vector<Tensor>& Bs,
+                   const std::vector<Tensor>& outs, double alpha,
+                   double beta) {
+  const size_t ni = As.size();
+  if (ni == 0) return;
+  if (Bs.size() != ni || outs.size() != ni)
+    throw ArgError("einsum: operand counts differ in " + spec);
+  for (size_t i = 1; i < ni; ++i)
+    if (As[i].shape != As[0].shape || Bs[i].shape != Bs[0].shape ||
+        outs[i].shape != outs[0].shape)
+      throw ArgError("einsum: batched items differ in shape in " + spec);
+  const Tensor& A = As[0];
+  const Tensor& B = Bs[0];
+  const Tensor& out = outs[0];
   Spec s = parse(spec);
   if ((int)s.a.size() != A.rank() || (int)s.b.size() != B.rank() ||
       (int)s.o.size() != out.rank())
@@ -359,13 +373,17 @@ void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
     }
   }
 
-  const Tensor& T1 = best.swap ? B : A;
-  const Tensor& T2 = best.swap ? A : B;
   const std::string& L1 = best.swap ? s.b : s.a;
   const std::string& L2 = best.swap ? s.a : s.b;
-  Tensor op1 = T1, op2 = T2;
-  if (best.perm_first) op1 = permuted(dev, T1, perm_of(L1, best.first));
-  if (best.perm_second) op2 = permuted(dev, T2, perm_of(L2, best.second));
+  std::vector<Tensor> op1(ni), op2(ni);
+  for (size_t i = 0; i < ni; ++i) {
+    const Tensor& T1 = best.swap ? Bs[i] : As[i];
+    const Tensor& T2 = best.swap ? As[i] : Bs[i];
+    op1[i] = best.perm_first ? permuted(dev, T1, perm_of(L1, best.first))
+                             : T1;
+    op2[i] = best.perm_second ? permuted(dev, T2, perm_of(L2, best.second))
+                              : T2;
+  }
 
   auto prod = [&](const std::string& ls) {
     int64_t p = 1;
@@ -385,30 +403,61 @@ void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
     if (has(L2, ch) && !has(batch, ch)) contr += ch;
   const int64_t K = prod(contr);
 
-  Tensor dst = out;
+  std::vector<Tensor> dst(outs);
   double beta_g = beta;
   if (best.perm_out) {
     std::vector<int64_t> sh;
     for (char ch : best.out) sh.push_back(dim_of(ch, s.a, A, s.b, B));
-    dst = dev.empty(sh);
+    for (size_t i = 0; i < ni; ++i) dst[i] = dev.empty(sh);
     beta_g = 0.0;
   }
   const int64_t lda = best.tA ? M : K;
   const int64_t ldb = best.tB ? K : N;
-  gemm(dev, best.tA, best.tB, M, N, K, best.perm_out ? 1.0 : alpha, op1.ptr,
-       lda, M * K, op2.ptr, ldb, K * N, beta_g, dst.ptr, N, M * N, nbatch);
-  if (best.perm_out) permute(dev, dst, perm_of(best.out, s.o), out, alpha,
-                             beta);
+  const double alpha_g = best.perm_out ? 1.0 : alpha;
+  if (ni == 1 || nbatch > 1) {
+    for (size_t i = 0; i < ni; ++i)
+      gemm(dev, best.tA, best.tB, M, N, K, alpha_g, op1[i].ptr, lda, M * K,
+           op2[i].ptr, ldb, K * N, beta_g, dst[i].ptr, N, M * N, nbatch);
+  } else {
+    // the items are independent products of one shape: one pointer batch
+    std::vector<const double*> pa(ni), pb(ni);
+    std::vector<double*> pc(ni);
+    for (size_t i = 0; i < ni; ++i) {
+      pa[i] = op1[i].ptr;
+      pb[i] = op2[i].ptr;
+      pc[i] = dst[i].ptr;
+    }
+    gemm_ptrs(dev, best.tA, best.tB, M, N, K, alpha_g, pa, lda, pb, ldb,
+              beta_g, pc, N);
+  }
+  if (best.perm_out)
+    for (size_t i = 0; i < ni; ++i) {
+      Tensor o = outs[i];
+      permute(dev, dst[i], perm_of(best.out, s.o), o, alpha, beta);
+    }
+}
+
+void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
+                 const Tensor& B, Tensor& out, double alpha, double beta) {
+  einsum_into_n(dev, spec, {A}, {B}, {out}, alpha, beta);
+}
+
+std::vector<Tensor> einsum_n(Device& dev, const std::string& spec,
+                             const std::vector<Tensor>& A,
+                             const std::vector<Tensor>& B) {
+  if (A.empty()) return {};
+  Spec s = parse(spec);
+  std::vector<int64_t> sh;
+  for (char ch : s.o) sh.push_back(dim_of(ch, s.a, A[0], s.b, B[0]));
+  std::vector<Tensor> out(A.size());
+  for (auto& o : out) o = dev.empty(sh);
+  einsum_into_n(dev, spec, A, B, out, 1.0, 0.0);
+  return out;
 }
 
 Tensor einsum(Device& dev, const std::string& spec, const Tensor& A,
               const Tensor& B) {
-  Spec s = parse(spec);
-  std::vector<int64_t> sh;
-  for (char ch : s.o) sh.push_back(dim_of(ch, s.a, A, s.b, B));
-  Tensor out = dev.empty(sh);
-  einsum_into(dev, spec, A, B, out, 1.0, 0.0);
-  return out;
+  return einsum_n(dev, spec, {A}, {B})[0];
 }
 
 }  // namespace ipeps

@@ -229,6 +229,16 @@ Tensor einsum(Device& dev, const std::string& spec, const Tensor& A,
 void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
                  const Tensor& B, Tensor& out, double alpha = 1.0,
                  double beta = 0.0);
+// The same contraction for several items of one shape (one plan, the
+// products of all items in one pointer-batched GEMM launch).  The outputs
+// must be distinct tensors.
+void einsum_into_n(Device& dev, const std::string& spec,
+                   const std::vector<Tensor>& A, const std::vector<Tensor>& B,
+                   const std::vector<Tensor>& out, double alpha = 1.0,
+                   double beta = 0.0);
+std::vector<Tensor> einsum_n(Device& dev, const std::string& spec,
+                             const std::vector<Tensor>& A,
+                             const std::vector<Tensor>& B);
 
 }  // namespace ipeps
 
