@@ -298,6 +298,17 @@ void mask_cols(Device& dev, double* X, int64_t n, int m, const int* keep,
 void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
            const double* den, double* x, double* r, double* p,
            const double* Ap, int64_t rows_per_batch = 0);
+// Fused column-wise CG (batch blocks of n x m, row major): colcg_step
+// does x += a p, r -= a A p with a = num / den per column and leaves the
+// per-column partial sums of r^2 in part ([batch][colcg_parts()][m]);
+// colcg_dir reduces them to rr_new and sets p = r + (rr_new / rr_old) p.
+void colcg_step(Device& dev, int64_t n, int m, int batch, const double* num,
+                const double* den, double* x, double* r, const double* p,
+                const double* Ap, double* part);
+void colcg_dir(Device& dev, int64_t n, int m, int batch, const double* part,
+               const double* rr_old, double* rr_new, const double* r,
+               double* p);
+int colcg_parts();
 void col_axpby(Device& dev, int64_t n, int m, double a, const double* s,
                const double* x, double b, double* y,
                int64_t rows_per_batch = 0, int64_t sS = 0);

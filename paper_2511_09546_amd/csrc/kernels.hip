@@ -1351,6 +1351,90 @@ __global__ void colcg_kernel(int mode, int64_t rows, int m, const double* rr,
   }
 }
 
+// One CG step of column-wise systems, fused with the reductions around it.
+// Blocks (64 columns) x (CD_R row groups) x batch, rows of a batch split
+// over the row groups as in coldot, so the sums keep coldot's order.
+//   step: a_j = num_j / den_j (0 unless both > 0), x += a p, r -= a A p,
+//         partial sums of r_j^2 into part[batch][CD_R][m];
+//   dir:  rr_new_j = sum of the partials, p = r + (rr_new_j / rr_old_j) p
+//         (0 unless rr_old_j > 0).
+__global__ __launch_bounds__(256) void colcg_step_kernel(
+    int64_t n, int m, const double* __restrict__ num,
+    const double* __restrict__ den, double* __restrict__ x,
+    double* __restrict__ r, const double* __restrict__ p,
+    const double* __restrict__ Ap, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane, bt = blockIdx.z;
+  const long off = (long)bt * n * m;
+  double v = 0.0;
+  if (c < m) {
+    const double nu = num[(long)bt * m + c], de = den[(long)bt * m + c];
+    const double a = (de > 0.0 && nu > 0.0) ? nu / de : 0.0;
+    for (int64_t i = blockIdx.y * 4 + r0; i < n; i += 4 * CD_R) {
+      const long e = off + i * m + c;
+      x[e] += a * p[e];
+      const double rv = r[e] - a * Ap[e];
+      r[e] = rv;
+      v += rv * rv;
+    }
+  }
+  red[r0][lane] = v;
+  __syncthreads();
+  if (threadIdx.x < 64 && c < m)
+    part[((long)bt * CD_R + blockIdx.y) * m + c] =
+        red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+__global__ __launch_bounds__(256) void colcg_dir_kernel(
+    int64_t n, int m, const double* __restrict__ part,
+    const double* __restrict__ rr_old, double* __restrict__ rr_new,
+    const double* __restrict__ r, double* __restrict__ p) {
+  __shared__ double beta[64];
+  const int lane = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane, bt = blockIdx.z;
+  if (threadIdx.x < 64) {
+    double b = 0.0;
+    if (c < m) {
+      const double* pp = part + (long)bt * CD_R * m + c;
+      double sum = 0.0;
+      for (int q = 0; q < CD_R; ++q) sum += pp[(long)q * m];
+      const double ro = rr_old[(long)bt * m + c];
+      b = ro > 0.0 ? sum / ro : 0.0;
+      if (blockIdx.y == 0) rr_new[(long)bt * m + c] = sum;
+    }
+    beta[lane] = b;
+  }
+  __syncthreads();
+  if (c >= m) return;
+  const double bb = beta[lane];
+  const long off = (long)bt * n * m;
+  for (int64_t i = blockIdx.y * 4 + r0; i < n; i += 4 * CD_R) {
+    const long e = off + i * m + c;
+    p[e] = r[e] + bb * p[e];
+  }
+}
+
+void colcg_step(Device& dev, int64_t n, int m, int batch, const double* num,
+                const double* den, double* x, double* r, const double* p,
+                const double* Ap, double* part) {
+  hipLaunchKernelGGL(colcg_step_kernel, dim3((m + 63) / 64, CD_R, batch),
+                     dim3(256), 0, dev.stream, n, m, num, den, x, r, p, Ap,
+                     part);
+  IPEPS_HIP(hipGetLastError());
+}
+
+void colcg_dir(Device& dev, int64_t n, int m, int batch, const double* part,
+               const double* rr_old, double* rr_new, const double* r,
+               double* p) {
+  hipLaunchKernelGGL(colcg_dir_kernel, dim3((m + 63) / 64, CD_R, batch),
+                     dim3(256), 0, dev.stream, n, m, part, rr_old, rr_new, r,
+                     p);
+  IPEPS_HIP(hipGetLastError());
+}
+
+int colcg_parts() { return CD_R; }
+
 void colcg(Device& dev, int mode, int64_t rows, int m, const double* rr,
            const double* den, double* x, double* r, double* p,
            const double* Ap, int64_t rows_per_batch) {

@@ -427,11 +427,16 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const double tol2 = cp == PREC_FP64 ? 1e-24 : (cp == PREC_FP32 ? 1e-10
                                                                    : 1e-6);
     double prev_worst = INFINITY;
+    // <r, r> alternates between the rr and rr_new slices of sc (the fused
+    // direction update writes the new value next to the old one)
+    double* rrb[2] = {rr, rrn};
+    int cur = 0;
+    Tensor part = dev.empty({nc, colcg_parts(), chi});
     auto converged = [&](bool stagnation) {
       dev.download(sc, h.data());
       bool done = true;
       double worst = 0.0;
-      const double* hr = h.data() + 2 * nc * chi;  // rr
+      const double* hr = h.data() + (rrb[cur] - sc.ptr);  // rr
       const double* h0 = h.data() + 4 * nc * chi;  // rr0
       for (int j = 0; j < nc * chi; ++j)
         if (h0[j] > 0.0) {
@@ -453,13 +458,12 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
         coldot(dev, R.ptr, Pp.ptr, 2 * n, chi, rp, 2 * nc, s2);
       else
         coldot(dev, Pp.ptr, AP.ptr, 2 * n, chi, pap, nc, s2);
-      colcg(dev, 0, nc * 2 * n, chi, m > 0 ? rp : rr, pap, X.ptr, R.ptr,
-            Pp.ptr, AP.ptr, 2 * n);
-      coldot(dev, R.ptr, R.ptr, 2 * n, chi, rrn, nc, s2);
-      colcg(dev, 1, nc * 2 * n, chi, rr, rrn, X.ptr, R.ptr, Pp.ptr, AP.ptr,
-            2 * n);
+      colcg_step(dev, 2 * n, chi, nc, m > 0 ? rp : rrb[cur], pap, X.ptr,
+                 R.ptr, Pp.ptr, AP.ptr, part.ptr);
+      colcg_dir(dev, 2 * n, chi, nc, part.ptr, rrb[cur], rrb[cur ^ 1], R.ptr,
+                Pp.ptr);
+      cur ^= 1;
       if (m > 0) deflate(R.ptr, Pp.ptr);
-      axpby(dev, nc * chi, 1.0, rrn, 0.0, rr);
       if ((it + 1) % 2 == 0 && converged(true)) {
         ++it;
         break;
