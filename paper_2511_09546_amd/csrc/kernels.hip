@@ -19,10 +19,17 @@ namespace ipeps {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------- permute
+// Division by the output extents through a multiply-high (Granlund and
+// Montgomery's round-up method): for an extent e >= 2, l = ceil(log2 e),
+// mul = ceil(2^(31+l) / e) < 2^32 and q = floor(x mul / 2^(31+l)) equals
+// floor(x / e) for every 0 <= x < 2^31 (the rounding of mul adds less than
+// x / 2^(31+l) < 1/e, which cannot carry past the next integer).
 struct PermArgs {
   int rank;
   int out_shape[12];
-  int in_stride[12];  // input stride along output dimension i
+  int in_stride[12];      // input stride along output dimension i
+  unsigned mul[12];       // division by out_shape[i]: see above
+  int shr[12];            // l - 1
 };
 
 __global__ void permute_kernel(const double* __restrict__ in,
@@ -32,8 +39,10 @@ __global__ void permute_kernel(const double* __restrict__ in,
        i += gridDim.x * blockDim.x) {
     int rem = i, off = 0;
     for (int d = p.rank - 1; d >= 0; --d) {
-      const int q = rem / p.out_shape[d];
-      off += (rem - q * p.out_shape[d]) * p.in_stride[d];
+      const int e = p.out_shape[d];
+      const int q =
+          e == 1 ? rem : (int)(__umulhi((unsigned)rem, p.mul[d]) >> p.shr[d]);
+      off += (rem - q * e) * p.in_stride[d];
       rem = q;
     }
     double v = alpha * in[off];
@@ -182,6 +191,13 @@ generic:
   for (int i = 0; i < p.rank; ++i) {
     p.out_shape[i] = (int)oshape[i];
     p.in_stride[i] = (int)ostr[i];
+    const uint64_t e = (uint64_t)oshape[i];
+    int l = 0;
+    while ((1ull << l) < e) ++l;  // ceil(log2 e)
+    if (e >= 2) {
+      p.mul[i] = (unsigned)(((1ull << (31 + l)) + e - 1) / e);
+      p.shr[i] = l - 1;
+    }
   }
   if (dev.prof.on)
     dev.prof.begin(dev.stream, PROF_PERMUTE, 0.0,
