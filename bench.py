@@ -88,7 +88,7 @@ def measured_traffic(prec):
     return r["traffic_bytes_per_launch"]
 
 
-def run(name, prec, steps, warmup):
+def run(name, prec, steps, warmup, ckpt=0):
     """Warm-up and timed steps in one arithmetic; returns the measurements."""
     import torch
     from paper_2511_09546_amd import binding, inputs
@@ -98,6 +98,7 @@ def run(name, prec, steps, warmup):
     o = binding.default_opts()
     o.prec = {"fp64": binding.FP64, "fp32": binding.FP32,
               "bf16": binding.BF16}[prec]
+    o.grad_checkpoint = ckpt
     ctx = binding.Context(A, w["chi"], opts=o)
     fam = {"fp64": binding.PROF_GEMM, "fp32": binding.PROF_GEMM32,
            "bf16": binding.PROF_GEMM16}[prec]
@@ -159,6 +160,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the plain FP64 and the other mixed runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--checkpoint", action="store_true",
+                    help="checkpointed gradient (recompute each unrolled "
+                         "iteration in the backward pass)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
@@ -175,12 +179,13 @@ def main():
     name = args.workload
     w = inputs.WORKLOADS[name]
 
-    head = run(name, args.prec, args.steps, args.warmup)
+    ck = 1 if args.checkpoint else 0
+    head = run(name, args.prec, args.steps, args.warmup, ck)
     base = other = None
     if args.prec != "fp64" and not args.no_fp64:
         oprec = "bf16" if args.prec == "fp32" else "fp32"
-        other = (oprec, run(name, oprec, args.steps, args.warmup))
-        base = run(name, "fp64", args.steps, args.warmup)
+        other = (oprec, run(name, oprec, args.steps, args.warmup, ck))
+        base = run(name, "fp64", args.steps, args.warmup, ck)
 
     timed, elapsed = head["timed"], head["elapsed"]
     n_g, t_g, fl_g, by_g = head["prof"][head["fam"]]
@@ -212,7 +217,8 @@ def main():
                                f"1e-7 floor), K={w['grad_K']}, CG 20 its, "
                                "delta 1e-4",
                    "D": w["D"], "chi": w["chi"], "d": w["d"],
-                   "grad_K": w["grad_K"], "prec": args.prec},
+                   "grad_K": w["grad_K"], "prec": args.prec,
+                   "grad_checkpoint": ck},
         "p50_ms": p(0.5), "p99_ms": p(0.99),
         "ctm_iters_per_step": [t["iters"] for t in timed],
         "cold_step_ms": head["infos"][0]["ms"] if head["infos"] else None,

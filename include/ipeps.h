@@ -101,6 +101,12 @@ typedef struct {
   double adj_tol;     /* fixed-point mode: stop when the cotangent reaching
                          the converged environment is below adj_tol times
                          the one leaving the last iteration (1e-13) */
+  int grad_checkpoint; /* 0 (default): ipeps_energy_grad keeps the
+                          intermediates of all unrolled iterations resident;
+                          1: it keeps only each iteration's input environment
+                          and recomputes the iteration in the backward pass
+                          (one iteration resident, about one more forward
+                          pass of work; same gradient up to rounding) */
 } ipeps_opts;
 
 /* What ipeps_energy_grad differentiates (Sec. III A, Sec. IV A):
@@ -205,8 +211,10 @@ size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
 
 /* Device bytes a context needs at its peak (the ipeps_energy_grad call,
  * which keeps every intermediate of the K = opts->grad_K unrolled CTMRG
- * iterations): an upper estimate for admission decisions, 8 bytes times
- * n_sites * chi^2 D^4 * (64 K + 64) plus the double-layer tensors
+ * iterations, or of one with opts->grad_checkpoint, next to the energy
+ * network's tape): an upper estimate for admission decisions, 8 bytes times
+ * n_sites * chi^2 D^4 * (64 K + 512) (K = 1 with checkpointing) plus the
+ * double-layer tensors
  * (n_sites * 4 (d^2 + 1) D^8) and the environment.  opts NULL = defaults.
  * Returns 0 for invalid sizes.  Host-only; no device call. */
 size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,

@@ -51,7 +51,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", c_int), ("svd_cutoff", c_double), ("grad_K", c_int),
                 ("svd_oversample", c_int), ("svd_max_iter", c_int),
                 ("svd_tol", c_double), ("grad_mode", c_int),
-                ("adj_tol", c_double)]
+                ("adj_tol", c_double), ("grad_checkpoint", c_int)]
 
 
 _lib = None

@@ -80,6 +80,141 @@ double run(Context& cx, const std::vector<TermSpec>& terms, int K, bool full,
   return e;
 }
 
+// Cotangents of a tape environment packed like an Env (zero where none
+// arrived).
+Env cot_pack(Tape& tp, Context& cx, const VEnv& v) {
+  const int ns = cx.nsite(), chi = cx.chi, D2 = cx.D2;
+  Env e;
+  e.C = cx.dev.zeros({4, ns, chi, chi});
+  e.T = cx.dev.zeros({4, ns, chi, D2, chi});
+  const int64_t cs = (int64_t)chi * chi, ts = cs * D2;
+  for (int i = 0; i < 4 * ns; ++i) {
+    if (tp.has_grad(v.C[i]))
+      axpby(cx.dev, cs, 1.0, v.C[i]->g.ptr, 0.0, e.C.ptr + i * cs);
+    if (tp.has_grad(v.T[i]))
+      axpby(cx.dev, ts, 1.0, v.T[i]->g.ptr, 0.0, e.T.ptr + i * ts);
+  }
+  return e;
+}
+
+// sqrt(|C|^2 + |T|^2) of a packed cotangent
+double env_norm(Device& dev, const Env& e) {
+  Tensor s = dev.empty({2});
+  nrm2(dev, e.C.ptr, e.C.numel(), s.ptr);
+  nrm2(dev, e.T.ptr, e.T.numel(), s.ptr + 1);
+  double h[2];
+  dev.download(s, h);
+  return std::sqrt(h[0] * h[0] + h[1] * h[1]);
+}
+
+// The same evaluation with checkpointed recomputation: the K iterations run
+// first without a tape, keeping only each iteration's input environment and
+// projector-SVD warm start; the energy is differentiated on its own tape,
+// then every iteration, last to first, is recomputed from its stored input
+// on a tape of its own and differentiated with the cotangent of its output.
+// One iteration's intermediates are resident at a time instead of K; the
+// recomputation repeats the forward kernels on the same inputs, so the
+// projectors and the values are the ones the forward pass produced.
+double run_ckpt(Context& cx, const std::vector<TermSpec>& terms, int K,
+                bool full, bool env_req, double* grad_host, bool on_device,
+                double* n_in, double* n_out) {
+  Device& dev = cx.dev;
+  const int64_t len = cx.A.numel();
+  Tensor gA = dev.zeros(cx.A.shape);
+  // forward, values only
+  Env e0;
+  if (full) {
+    Tape t(dev, false);
+    e0 = env_pack(cx, init_env_ad(t, cx, arot_leaves(t, cx)));
+  } else {
+    e0 = cx.env;
+  }
+  std::vector<Env> in(K);
+  std::vector<Tensor> warm(K);
+  std::vector<char> have(K);
+  Env e = e0;
+  for (int k = 0; k < K; ++k) {
+    in[k] = e;
+    warm[k] = cx.Xwarm;
+    have[k] = cx.have_warm;
+    Env nxt;
+    ctm_step(cx, e, nxt);
+    e = nxt;
+  }
+  // energy at the last environment
+  double energy = 0.0;
+  Env cot;
+  {
+    Tape tp(dev, true);
+    Var A = tp.leaf(cx.A, true);
+    std::vector<Var> As(cx.nsite());
+    for (int s = 0; s < cx.nsite(); ++s) As[s] = tp.slice0(A, s);
+    std::vector<Var> arot = arot_from_sites(tp, cx, As);
+    VEnv ve = venv_leaves(tp, cx, e, true);
+    energy = energy_ad(tp, cx, ve, As, arot, terms);
+    tp.backward();
+    if (tp.has_grad(A)) axpby(dev, len, 1.0, A->g.ptr, 1.0, gA.ptr);
+    cot = cot_pack(tp, cx, ve);
+  }
+  if (env_req) *n_out = env_norm(dev, cot);
+  // iterations, last to first
+  for (int k = K - 1; k >= 0; --k) {
+    Tape tp(dev, true);
+    Var A = tp.leaf(cx.A, true);
+    std::vector<Var> As(cx.nsite());
+    for (int s = 0; s < cx.nsite(); ++s) As[s] = tp.slice0(A, s);
+    std::vector<Var> arot = arot_from_sites(tp, cx, As);
+    const bool need_in = k > 0 || env_req || full;
+    VEnv vin = venv_leaves(tp, cx, in[k], need_in);
+    cx.Xwarm = warm[k];
+    cx.have_warm = have[k];
+    VEnv vout = ctm_step_ad(tp, cx, vin, arot);
+    const int ns = cx.nsite();
+    for (int c = 0; c < 4; ++c)
+      for (int s = 0; s < ns; ++s) {
+        vout.C[c * ns + s]->g = cx.Cv(cot, c, s);
+        vout.T[c * ns + s]->g = cx.Tv(cot, c, s);
+      }
+    tp.backward();
+    if (tp.has_grad(A)) axpby(dev, len, 1.0, A->g.ptr, 1.0, gA.ptr);
+    if (need_in) cot = cot_pack(tp, cx, vin);
+    in[k] = Env();
+  }
+  if (env_req) *n_in = env_norm(dev, cot);
+  if (full) {
+    // the trace-boundary start depends on A
+    Tape tp(dev, true);
+    Var A = tp.leaf(cx.A, true);
+    std::vector<Var> As(cx.nsite());
+    for (int s = 0; s < cx.nsite(); ++s) As[s] = tp.slice0(A, s);
+    VEnv v0 = init_env_ad(tp, cx, arot_from_sites(tp, cx, As));
+    const int ns = cx.nsite();
+    for (int c = 0; c < 4; ++c)
+      for (int s = 0; s < ns; ++s) {
+        v0.C[c * ns + s]->g = cx.Cv(cot, c, s);
+        v0.T[c * ns + s]->g = cx.Tv(cot, c, s);
+      }
+    tp.backward();
+    if (tp.has_grad(A)) axpby(dev, len, 1.0, A->g.ptr, 1.0, gA.ptr);
+  }
+  if (on_device) {
+    axpby(dev, len, 1.0, gA.ptr, 0.0, grad_host);
+    dev.sync();
+  } else {
+    dev.download(gA, grad_host);
+  }
+  return energy;
+}
+
+double run_any(Context& cx, const std::vector<TermSpec>& terms, int K,
+               bool full, bool env_req, double* grad_host, bool on_device,
+               double* n_in, double* n_out) {
+  return cx.grad_ckpt ? run_ckpt(cx, terms, K, full, env_req, grad_host,
+                                 on_device, n_in, n_out)
+                      : run(cx, terms, K, full, env_req, grad_host,
+                            on_device, n_in, n_out);
+}
+
 }  // namespace
 
 double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
@@ -115,19 +250,19 @@ double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
     // start for the first projector SVD
     cx.have_warm = false;
     cx.grad_K_used = K;
-    return run(cx, terms, K, true, false, grad_host, on_device, &n_in,
+    return run_any(cx, terms, K, true, false, grad_host, on_device, &n_in,
                &n_out);
   }
   if (cx.grad_mode == 1) {
     cx.grad_K_used = K;
-    return run(cx, terms, K, false, false, grad_host, on_device, &n_in,
+    return run_any(cx, terms, K, false, false, grad_host, on_device, &n_in,
                &n_out);
   }
   for (int k = K;; k *= 2) {
     cx.Xwarm = warm;
     cx.have_warm = have_warm;
     cx.have_cg_warm = false;
-    const double e = run(cx, terms, k, false, true, grad_host, on_device,
+    const double e = run_any(cx, terms, k, false, true, grad_host, on_device,
                          &n_in, &n_out);
     cx.grad_K_used = k;
     if (n_in <= cx.adj_tol * std::max(n_out, 1e-300) || k >= 32 * K)

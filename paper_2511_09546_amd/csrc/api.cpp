@@ -60,6 +60,7 @@ void ipeps_default_opts(ipeps_opts* o) {
   o->svd_tol = 1e-13;
   o->grad_mode = IPEPS_GRAD_K;
   o->adj_tol = 1e-13;
+  o->grad_checkpoint = 0;
 }
 
 const char* ipeps_version(void) { return "ipeps-mi355x 0.1"; }
@@ -92,9 +93,14 @@ size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
   if (opts) o = *opts;
   const double ns = (double)Lx * Ly, D2 = (double)D * D, D4 = D2 * D2;
   const double q = (double)chi * chi * D4;  // one enlarged corner
-  const double K = o.grad_K > 0 ? o.grad_K : 0;
+  // gradient intermediates of K unrolled iterations, or of one with
+  // checkpointing (the stored input environments are small)
+  const double K = o.grad_checkpoint ? 1.0 : (o.grad_K > 0 ? o.grad_K : 0);
   const double dbl = ns * 4.0 * ((double)d * d + 1.0) * D4 * D4;
-  const double words = ns * q * (64.0 * K + 64.0) + dbl +
+  // 64 enlarged-corner sizes per resident unrolled iteration; 512 for the
+  // energy network's tape (its next-nearest-neighbour reduced density
+  // matrices dominate: about 470 measured at D = 6, chi = 72) and the rest
+  const double words = ns * q * (64.0 * K + 512.0) + dbl +
                        (double)ipeps_env_size(Lx, Ly, D, chi);
   return (size_t)(8.0 * words);
 }
@@ -113,7 +119,8 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
       !(o.svd_tol >= 0.0) || o.svd_oversample < 0 ||
       (o.grad_mode != IPEPS_GRAD_FULL && o.grad_mode != IPEPS_GRAD_K &&
        o.grad_mode != IPEPS_GRAD_FP) ||
-      !(o.adj_tol > 0.0) || (o.grad_mode == IPEPS_GRAD_FP && o.grad_K < 1))
+      !(o.adj_tol > 0.0) || (o.grad_mode == IPEPS_GRAD_FP && o.grad_K < 1) ||
+      (o.grad_checkpoint != 0 && o.grad_checkpoint != 1))
     return IPEPS_EINVAL;
   const size_t nA = (size_t)Lx * Ly * d * D * D * D * D;
   if (!all_finite(A, nA)) return IPEPS_EINVAL;
@@ -138,6 +145,7 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
     cx.grad_K = o.grad_K;
     cx.grad_mode = o.grad_mode;
     cx.adj_tol = o.adj_tol;
+    cx.grad_ckpt = o.grad_checkpoint;
     cx.svd.cutoff = o.svd_cutoff;
     cx.svd.tol = o.svd_tol;
     cx.svd.max_iter = o.svd_max_iter;

@@ -109,6 +109,7 @@ struct Context {
   int grad_K = 20;
   int grad_mode = 1;     // ipeps_grad_mode
   double adj_tol = 1e-13;
+  int grad_ckpt = 0;     // recompute the unrolled iterations in the backward
   int grad_K_used = 0;   // K of the last gradient (fixed-point mode)
   SvdParams svd;
   SvdStats stats;

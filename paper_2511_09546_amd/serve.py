@@ -10,6 +10,12 @@ the budget next to those already running (first come first served, later
 requests may start ahead of a waiting large one when they fit).  Contexts
 are freed when their request ends.
 
+Checkpointing: a request whose gradient with every unrolled iteration
+resident would take more than its share of the budget (budget / workers)
+runs with the checkpointed gradient (ipeps_opts.grad_checkpoint: one
+iteration resident, recomputed in the backward pass), unless the request
+fixes grad_checkpoint itself; the large requests then no longer run alone.
+
 Warm starts: a request that carries a `state_key` seen before (same cell,
 D and chi) starts CTMRG from the environment that the earlier request left
 (kept on the host), instead of the trace boundary.  The environment depends
@@ -53,6 +59,7 @@ class Request:
     cg_maxiter: int = 20
     prec: int = binding.FP32
     grad_K: int = 20
+    grad_checkpoint: Optional[int] = None   # None: the server decides
     state_key: Optional[str] = None
     arrival: float = field(default_factory=time.perf_counter)
 
@@ -83,6 +90,15 @@ def _shape(A):
     return A.shape[1], A.shape[0], A.shape[2], A.shape[3]
 
 
+def request_footprint(req: Request, ckpt: int) -> float:
+    """Device bytes of one request (ipeps_footprint_bytes)."""
+    Lx, Ly, d, D = _shape(req.A)
+    o = binding.default_opts()
+    o.grad_K = req.grad_K
+    o.grad_checkpoint = ckpt
+    return float(binding.footprint_bytes(Lx, Ly, d, D, req.chi, o))
+
+
 class Server:
     """Footprint-admitted concurrent execution of Requests."""
 
@@ -102,11 +118,14 @@ class Server:
         self.sched = threading.Thread(target=self._schedule, daemon=True)
         self.sched.start()
 
+    def checkpoint(self, req: Request) -> int:
+        """Checkpointed gradient for this request (see the module doc)."""
+        if req.grad_checkpoint is not None:
+            return int(req.grad_checkpoint)
+        return int(request_footprint(req, 0) > self.budget / self.workers)
+
     def footprint(self, req: Request) -> float:
-        Lx, Ly, d, D = _shape(req.A)
-        o = binding.default_opts()
-        o.grad_K = req.grad_K
-        return float(binding.footprint_bytes(Lx, Ly, d, D, req.chi, o))
+        return request_footprint(req, self.checkpoint(req))
 
     def submit(self, req: Request) -> cf.Future:
         fut = cf.Future()
@@ -162,6 +181,7 @@ class Server:
         o = binding.default_opts()
         o.prec = req.prec
         o.grad_K = req.grad_K
+        o.grad_checkpoint = self.checkpoint(req)
         key = (Lx, Ly, d, D, req.chi)
         warm = False
         with binding.Context(req.A, req.chi, opts=o) as ctx:
@@ -222,6 +242,7 @@ def main(argv=None):
     prec = binding.FP32 if args.prec == "fp32" else binding.FP64
     stream = request_stream(args.requests, args.rate, args.seed, prec)
     srv = Server(args.budget_gb * 1e9, args.workers)
+    n_ckpt = sum(srv.checkpoint(r) for _, r in stream)
     t0 = time.perf_counter()
     futs = []
     for off, req in stream:
@@ -256,6 +277,7 @@ def main(argv=None):
         "budget_gb": args.budget_gb,
         "peak_admitted_gb": srv.peak_used / 1e9,
         "max_concurrent": srv.max_running,
+        "checkpointed_requests": n_ckpt,
     }
     print(json.dumps(out), flush=True)
 

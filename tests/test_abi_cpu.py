@@ -60,6 +60,12 @@ def test_argument_checks_before_any_device_call(lib):
     assert lib.ctm_init(None, 1, 1, 2, 3, 9, dp, None, None) == -1
     A[0, 0, 0, 0, 0, 0, 0] = np.nan
     assert lib.ctm_init(ctypes.byref(h), 1, 1, 2, 3, 9, dp, None, None) == -1
+    # an option outside its range (grad_checkpoint is 0 or 1)
+    A[0, 0, 0, 0, 0, 0, 0] = 0.0
+    o = binding.default_opts()
+    o.grad_checkpoint = 2
+    assert lib.ctm_init(ctypes.byref(h), 1, 1, 2, 3, 9, dp, ctypes.byref(o),
+                        None) == -1
     assert lib.ctm_converge(None, 1e-10, 10, None, None) == -1
     assert lib.precond_apply(None, None, 1.0, 0.0, 1, None, None, None) == -1
     lib.ctm_free(None)

@@ -24,13 +24,15 @@ def _env_arrays(env):
     return C, T
 
 
+@pytest.mark.parametrize("ckpt", [0, 1])
 @pytest.mark.parametrize("D,chi,K,J2,seed", [(2, 6, 3, 0.4, 7),
                                              (2, 8, 5, 0.0, 8),
                                              (3, 10, 2, 0.3, 9)])
-def test_grad_K_same_env(D, chi, K, J2, seed):
+def test_grad_K_same_env(D, chi, K, J2, seed, ckpt):
     """Both sides differentiate A -> e(A, F^K(A, env*)) from the very same
-    env* (the oracle's, uploaded): element-by-element agreement."""
-    _say(f"grad parity D={D} chi={chi} K={K} J2={J2}")
+    env* (the oracle's, uploaded): element-by-element agreement, with all
+    iterations kept on the tape and with checkpointed recomputation."""
+    _say(f"grad parity D={D} chi={chi} K={K} J2={J2} checkpoint={ckpt}")
     A = inputs.random_state(seed, 1, 1, 2, D)
     terms = inputs.terms_j1j2(1, 1, 1.0, J2)
     env, _, _ = ctmrg.converge(A, chi, 1e-13, 500)
@@ -39,6 +41,7 @@ def test_grad_K_same_env(D, chi, K, J2, seed):
     C, T = _env_arrays(env)
     o = binding.default_opts()
     o.grad_K = K
+    o.grad_checkpoint = ckpt
     with binding.Context(A, chi, opts=o) as ctx:
         ctx.set_env(C, T)
         e, g = ctx.energy_grad(terms, grad=True)
@@ -144,11 +147,12 @@ def test_adjoint_vs_finite_differences_kitaev():
             assert abs(fd - ad) < 1e-8 * gn
 
 
-def test_grad_mode_full():
+@pytest.mark.parametrize("ckpt", [0, 1])
+def test_grad_mode_full(ckpt):
     """IPEPS_GRAD_FULL: derivative through the trace-boundary start and N
     iterations (the D=2, chi=8 workload, N = 30), against the oracle's
     grad_full element by element."""
-    _say("grad mode full, d2chi8, N=30")
+    _say(f"grad mode full, d2chi8, N=30, checkpoint={ckpt}")
     w = inputs.WORKLOADS["d2chi8"]
     A = inputs.workload_state("d2chi8")
     terms = inputs.workload_terms("d2chi8")
@@ -157,6 +161,7 @@ def test_grad_mode_full():
     o = binding.default_opts()
     o.grad_mode = binding.GRAD_FULL
     o.grad_K = 30
+    o.grad_checkpoint = ckpt
     with binding.Context(A, w["chi"], opts=o) as ctx:
         ctx.converge(0.0, 1)
         e, g = ctx.energy_grad(terms, grad=True)
@@ -167,11 +172,12 @@ def test_grad_mode_full():
     assert err < 1e-9
 
 
-def test_grad_mode_fixed_point():
+@pytest.mark.parametrize("ckpt", [0, 1])
+def test_grad_mode_fixed_point(ckpt):
     """IPEPS_GRAD_FP: K doubled from K0 until the cotangent reaching env*
     is below adj_tol of the one leaving the last iteration; same rule and
     same K as the oracle's grad_fp, element-by-element gradient."""
-    _say("grad mode fixed point, D=2 chi=6")
+    _say(f"grad mode fixed point, D=2 chi=6, checkpoint={ckpt}")
     A = inputs.random_state(7, 1, 1, 2, 2)
     terms = inputs.terms_j1j2(1, 1, 1.0, 0.4)
     chi = 6
@@ -183,6 +189,7 @@ def test_grad_mode_fixed_point():
     o.grad_mode = binding.GRAD_FP
     o.grad_K = 4
     o.adj_tol = 1e-10
+    o.grad_checkpoint = ckpt
     with binding.Context(A, chi, opts=o) as ctx:
         ctx.set_env(C, T)
         e, g = ctx.energy_grad(terms, grad=True)
@@ -191,3 +198,30 @@ def test_grad_mode_fixed_point():
     _say(f"  K {K} vs {K_or}; rel grad err {err:.2e}")
     assert K == K_or
     assert err < 1e-9
+
+
+def test_checkpoint_matches_stored_d4chi32():
+    """Checkpointed recomputation against the all-resident tape on the D=4,
+    chi=32 workload (K = 20 from the converged environment, FP64): the
+    recomputed iterations repeat the forward kernels on the same inputs, so
+    the gradients agree to rounding (the partial gradients of A are summed
+    in a different association), and the peak of live device memory drops."""
+    _say("checkpoint vs stored tape, d4chi32")
+    w = inputs.WORKLOADS["d4chi32"]
+    A = inputs.workload_state("d4chi32")
+    terms = inputs.workload_terms("d4chi32")
+    out = {}
+    for ckpt in (0, 1):
+        o = binding.default_opts()
+        o.grad_checkpoint = ckpt
+        with binding.Context(A, w["chi"], opts=o) as ctx:
+            ctx.converge(w["tol"], w["n_iter"])
+            e, g = ctx.energy_grad(terms, grad=True)
+            out[ckpt] = (e, g, ctx.stats()["peak_live_bytes"])
+    (e0, g0, p0), (e1, g1, p1) = out[0], out[1]
+    err = np.linalg.norm(g1 - g0) / np.linalg.norm(g0)
+    _say(f"  e diff {e1 - e0:.1e}, rel grad diff {err:.2e}, peak "
+         f"{p0 / 1e9:.2f} GB -> {p1 / 1e9:.2f} GB")
+    assert abs(e1 - e0) < 1e-13 * abs(e0)
+    assert err < 1e-11
+    assert p1 < 0.5 * p0

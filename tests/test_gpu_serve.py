@@ -14,6 +14,7 @@ def _solo(req):
     o = binding.default_opts()
     o.prec = req.prec
     o.grad_K = req.grad_K
+    o.grad_checkpoint = req.grad_checkpoint or 0
     with binding.Context(req.A, req.chi, opts=o) as ctx:
         it, dl, ok = ctx.converge(req.tol, req.max_iter)
         e, g = ctx.energy_grad(req.terms, grad=True)
@@ -22,14 +23,17 @@ def _solo(req):
     return e, g, x, it
 
 
-@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
-def test_concurrent_equals_solo(prec):
-    print(f"serve concurrent vs solo prec={prec}", flush=True)
+@pytest.mark.parametrize("prec,ckpt", [(binding.FP64, None),
+                                       (binding.FP32, None),
+                                       (binding.FP64, 1)])
+def test_concurrent_equals_solo(prec, ckpt):
+    print(f"serve concurrent vs solo prec={prec} checkpoint={ckpt}",
+          flush=True)
     specs = [(2, 8, 0.0), (3, 12, 0.3), (2, 6, 0.5), (3, 10, 0.1),
              (2, 8, 0.2), (3, 9, 0.4)]
     reqs = [serve.Request(A=inputs.random_state(700 + i, 1, 1, 2, D), chi=chi,
                           terms=inputs.terms_j1j2(1, 1, 1.0, J2), prec=prec,
-                          max_iter=60, grad_K=6)
+                          max_iter=60, grad_K=6, grad_checkpoint=ckpt)
             for i, (D, chi, J2) in enumerate(specs)]
     srv = serve.Server(50e9, workers=4)
     futs = [srv.submit(r) for r in reqs]

@@ -22,13 +22,18 @@ def test_footprint_formula():
     q = 72 * 72 * 6 ** 4
     dbl = 4 * (4 + 1) * 6 ** 8
     env = 4 * 72 * 72 + 4 * 72 * 36 * 72
-    assert f == int(8.0 * (q * (64 * 20 + 64) + dbl + env))
+    assert f == int(8.0 * (q * (64 * 20 + 512) + dbl + env))
     # grows with every size and with K; zero for invalid sizes
     assert binding.footprint_bytes(1, 1, 2, 6, 108, o) > f
     assert binding.footprint_bytes(2, 2, 2, 6, 72, o) > 3.9 * f
     o.grad_K = 40
-    assert binding.footprint_bytes(1, 1, 2, 6, 72, o) > 1.9 * f
+    assert binding.footprint_bytes(1, 1, 2, 6, 72, o) > 1.6 * f
     assert binding.footprint_bytes(0, 1, 2, 6, 72, o) == 0
+    # checkpointed gradient: one iteration's intermediates instead of K
+    o.grad_K = 20
+    o.grad_checkpoint = 1
+    assert binding.footprint_bytes(1, 1, 2, 6, 72, o) == int(
+        8.0 * (q * (64 * 1 + 512) + dbl + env))
 
 
 def test_admission_respects_budget_and_workers(monkeypatch):
@@ -55,7 +60,7 @@ def test_admission_respects_budget_and_workers(monkeypatch):
     reqs = [_req(D, chi) for D, chi in
             [(6, 72), (3, 18), (4, 32), (6, 108), (3, 27), (5, 50), (4, 48),
              (3, 18), (5, 75), (6, 72)]]
-    big = max(serve.Server.footprint(None, r) for r in reqs)
+    big = max(serve.request_footprint(r, 0) for r in reqs)
     budget = 1.2 * big
     srv = serve.Server(budget, workers=3)
     futs = [srv.submit(r) for r in reqs]
@@ -83,3 +88,20 @@ def test_request_stream_is_seeded():
         D = ra.A.shape[3]
         assert 3 <= D <= 6 and 2 * D * D <= ra.chi <= 3 * D * D
         assert ra.chi == rb.chi and np.array_equal(ra.A, rb.A)
+
+
+def test_large_requests_are_checkpointed():
+    """A request whose all-resident gradient exceeds budget / workers runs
+    checkpointed (and is admitted with the smaller footprint); small ones
+    and requests that fix the option keep their setting."""
+    small, large = _req(3, 18), _req(6, 72)
+    srv = serve.Server(2.0 * serve.request_footprint(large, 0), workers=4)
+    try:
+        assert srv.checkpoint(small) == 0
+        assert srv.checkpoint(large) == 1
+        assert srv.footprint(large) == serve.request_footprint(large, 1)
+        assert srv.footprint(large) < 0.4 * serve.request_footprint(large, 0)
+        large.grad_checkpoint = 0
+        assert srv.checkpoint(large) == 0
+    finally:
+        srv.close()
