@@ -29,8 +29,13 @@ since the counters were taken).  The cpu_baseline object times the CPU oracle on
 bounded sample of the same workload (one CTMRG iteration and one K=1
 gradient step) and scales it to one step.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--prec fp32]
-                    [--no-fp64] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--prec fp32]
+                    [--no-fp64] [--no-cpu-baseline] [--checkpoint]
+
+Besides the contract fields the line reports the median and p10/p90 of the
+timed steps with the mean time of each phase (step_ms), and for every
+arithmetic the error of its cold step against the FP64 CPU oracle's stored
+values for the same workload (error_vs_oracle: |de|, |dg|/|g|, |dx|/|x|).
 """
 import argparse
 import json
@@ -109,25 +114,38 @@ def run(name, prec, steps, warmup, ckpt=0):
     dg = torch.zeros_like(dA)
     dx = torch.zeros_like(dA)
 
-    def step(A):
+    def step(A, keep=False):
+        # every library call returns with its results written (the context
+        # stream is synchronised), so host timers bracket the phases
         t0 = time.perf_counter()
         n_it, dl, ok = ctx.converge(w["tol"], w["n_iter"])
+        t1 = time.perf_counter()
         e = ctx.energy_grad_dev(terms, dg.data_ptr())
+        t2 = time.perf_counter()
         cg_it, res, brk = ctx.precond_dev(dg.data_ptr(), dx.data_ptr(),
                                           w["delta"], w["cg_tol"],
                                           w["cg_maxiter"])
+        t3 = time.perf_counter()
+        out = None
+        if keep:  # the cold step's g and x, for the error against the oracle
+            out = (dg.cpu().numpy().copy(), dx.cpu().numpy().copy())
         # optimiser stand-in of the benchmark loop (not part of the step's
         # method): a preconditioned descent move of 1e-3 |A|
         A.sub_(1e-3 * A.norm() / dx.norm() * dx)
         torch.cuda.synchronize()
         ctx.set_state_dev(A.data_ptr())
         return A, dict(ms=1e3 * (time.perf_counter() - t0), iters=n_it, e=e,
-                       delta=dl, cg=cg_it, res=res)
+                       delta=dl, cg=cg_it, res=res,
+                       phase_ms=[1e3 * (t1 - t0), 1e3 * (t2 - t1),
+                                 1e3 * (t3 - t2)]), out
 
     A = dA
     infos = []
+    cold = None
     for i in range(warmup):
-        A, info = step(A)
+        A, info, kept = step(A, keep=(i == 0))
+        if i == 0:
+            cold = (info["e"],) + kept
         infos.append(info)
         print(f"[{prec}] warmup {i}: {info}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -135,7 +153,7 @@ def run(name, prec, steps, warmup, ckpt=0):
     t0 = time.perf_counter()
     timed = []
     for i in range(steps):
-        A, info = step(A)
+        A, info, _ = step(A)
         timed.append(info)
         print(f"[{prec}] step {i}: {info}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -146,14 +164,46 @@ def run(name, prec, steps, warmup, ckpt=0):
     stats = ctx.stats()
     ctx.close()
     return dict(elapsed=elapsed, timed=timed, infos=infos, prof=prof,
-                fam=fam, stats=stats)
+                fam=fam, stats=stats, cold=cold)
+
+
+def step_summary(r):
+    """Median, p10, p90 of the timed steps and the mean time per phase."""
+    import numpy as np
+    ms = np.array([t["ms"] for t in r["timed"]])
+    ph = np.array([t["phase_ms"] for t in r["timed"]]).mean(axis=0)
+    return {"p10_ms": float(np.percentile(ms, 10)),
+            "p50_ms": float(np.percentile(ms, 50)),
+            "p90_ms": float(np.percentile(ms, 90)),
+            "phase_ms": {"ctm_converge": float(ph[0]),
+                         "energy_grad": float(ph[1]),
+                         "precond_apply": float(ph[2])}}
+
+
+def oracle_error(name, cold):
+    """Error of the cold step (trace boundary -> converge -> energy and
+    gradient -> preconditioned direction, the protocol of the stored oracle
+    values in tests/golden) against the FP64 CPU oracle's values."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    if cold is None or not os.path.exists(path):
+        return None
+    gold = json.load(open(path))
+    e, g, x = cold
+    g_or = np.array(gold["g"]).reshape(g.shape)
+    x_or = np.array(gold["x"]).reshape(x.shape)
+    return {"e_abs": abs(e - gold["e"]),
+            "e_rel": abs(e - gold["e"]) / abs(gold["e"]),
+            "g_rel": float(np.linalg.norm(g - g_or) / np.linalg.norm(g_or)),
+            "x_rel": float(np.linalg.norm(x - x_or) / np.linalg.norm(x_or)),
+            "reference": f"tests/golden/{name}.json (oracle, FP64)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="d6chi72")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16",
                                                        "fp64"])
@@ -166,8 +216,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
-              "not supported (independent states shard trivially, see the "
-              "design notes)", file=sys.stderr)
+              "not supported (independent states would shard across GPUs "
+              "with no exchange; one state is not split)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -220,6 +270,8 @@ def main():
                    "grad_K": w["grad_K"], "prec": args.prec,
                    "grad_checkpoint": ck},
         "p50_ms": p(0.5), "p99_ms": p(0.99),
+        "step_ms": step_summary(head),
+        "error_vs_oracle": oracle_error(name, head["cold"]),
         "ctm_iters_per_step": [t["iters"] for t in timed],
         "cold_step_ms": head["infos"][0]["ms"] if head["infos"] else None,
         "energy_per_site": timed[-1]["e"],
@@ -246,6 +298,8 @@ def main():
         out["plain_fp64"] = {
             "value": v64, "ms_per_step": 1e3 * base["elapsed"] / args.steps,
             "speedup": value / v64,
+            "step_ms": step_summary(base),
+            "error_vs_oracle": oracle_error(name, base["cold"]),
             "ctm_iters_per_step": [t["iters"] for t in base["timed"]],
             "cold_step_energy_abs_diff": ediff(head)}
         oprec, o = other
@@ -254,6 +308,8 @@ def main():
         out[f"{oprec}_contractions"] = {
             "value": vo, "ms_per_step": 1e3 * o["elapsed"] / args.steps,
             "speedup_vs_fp64": vo / v64,
+            "step_ms": step_summary(o),
+            "error_vs_oracle": oracle_error(name, o["cold"]),
             "ctm_iters_per_step": [t["iters"] for t in o["timed"]],
             "cold_step_energy_abs_diff_vs_fp64": ediff(o),
             "gemm_tflops": fl_o / t_o / 1e12 if t_o > 0 else 0.0}
