@@ -245,6 +245,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
 // A[l%16][8(l/16) + t] and B[8(l/16) + t][l%16], t = 0..7; the result holds
 // D[4(l/16) + r][l%16] in register r.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename TI, int BM, int BN, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
@@ -415,6 +416,222 @@ __global__ void splitk_sum_kernel(const double* __restrict__ part, int S,
   }
 }
 
+// BF16x3 operands split once per launch.  A large product reads every
+// element of A in N / BN column tiles and every element of B in M / BM row
+// tiles; converting at every read makes gemm_bf16x3_kernel VALU-bound
+// (about 16 VALU instructions per MFMA).  For those products each operand
+// is split once into hi and lo planes, rows zero-padded to the tile size
+// and K to a multiple of 32, stored as 16 x 32 blocks of 1 KB
+// ([batch][Rp/16][Kp/32][16][32], so that one wave's 64 16-byte loads of a
+// K slice read one contiguous block), and the product kernel copies the
+// planes into LDS with 16-byte moves.  The split
+// values (x -> fl32(x) -> hi = bf16, lo = bf16(fl32(x) - hi)) and the MFMA
+// sequence are those of gemm_bf16x3_kernel.
+struct SplitArgs {
+  const void* src[MAXP];  // per batch entry
+  long ld;                // source leading dimension
+  int R, K, Rp, Kp;       // operand rows x K, padded extents
+  __bf16* hi;
+  __bf16* lo;
+};
+
+// element (r, k) of the operand: src[k * ld + r] when TRANS, else
+// src[r * ld + k]; 32 x 32 tiles through LDS so that reads are coalesced
+// along the source's contiguous index and writes along K
+template <typename TI, bool TRANS>
+__global__ __launch_bounds__(256) void split_bf16_kernel(SplitArgs a) {
+  __shared__ float tile[32][33];
+  const int bz = blockIdx.z;
+  const TI* src = (const TI*)a.src[bz];
+  const int k0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int u = ty + 8 * j;
+    const int rr = TRANS ? tx : u, kk = TRANS ? u : tx;
+    const int r = r0 + rr, k = k0 + kk;
+    float v = 0.0f;
+    if (r < a.R && k < a.K)
+      v = (float)(TRANS ? src[(long)k * a.ld + r] : src[(long)r * a.ld + k]);
+    tile[rr][kk] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int rr = ty + 8 * j, r = r0 + rr, k = k0 + tx;
+    if (r < a.Rp && k < a.Kp) {
+      const float f = tile[rr][tx];
+      const __bf16 h = (__bf16)f;
+      const long o = (long)bz * a.Rp * a.Kp +
+                     ((long)(r >> 4) * (a.Kp >> 5) + (k >> 5)) * 512 +
+                     (r & 15) * 32 + (k & 31);
+      a.hi[o] = h;
+      a.lo[o] = (__bf16)(f - (float)h);
+    }
+  }
+}
+
+// C[b] = alpha A B + beta C from split planes A (Mp x Kp), B (Np x Kp)
+// (block layout above); tiles BM x BN, K slices of 32, LDS in the layout
+// of gemm_bf16x3_kernel; split K and XCD numbering as there.
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
+    int M, int N, int Kp, double alpha, const __bf16* __restrict__ Ah,
+    const __bf16* __restrict__ Al, long sA, const __bf16* __restrict__ Bh,
+    const __bf16* __restrict__ Bl, long sB, double beta,
+    double* __restrict__ C, long ldc, long sC, int tiles_n, int splits,
+    int kchunk, double* __restrict__ part, int use_ptrs, PtrArgs ptrs) {
+  static_assert(WM * WN == 4, "4 waves");
+  constexpr int BK = 32, KP = BK + 8;
+  constexpr int WTM = BM / WM, WTN = BN / WN;
+  constexpr int TM = WTM / 16, TN = WTN / 16;
+  // 16-byte chunks (8 bf16) of one slice: rows x 4 per plane
+  constexpr int AC = (BM * 4 + 255) / 256, BC = (BN * 4 + 255) / 256;
+  // one LDS buffer (36 KB at 128 x 96): four workgroups fit a CU, which
+  // hides more latency than double buffering at two
+  __shared__ __attribute__((aligned(16))) __bf16 Ahs[1][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Als[1][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bhs[1][BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bls[1][BN][KP];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int gx = gridDim.x;
+  const int total = gx * gridDim.y;
+  const int lin = blockIdx.x + gx * blockIdx.y;
+  const int q8 = total / 8, r8 = total % 8, xcd = lin % 8;
+  const int vid = xcd * q8 + min(xcd, r8) + lin / 8;
+  const int bx = vid % gx, by = vid / gx;
+  const int bz = by / splits, sp = by % splits;
+  const int m0 = (bx / tiles_n) * BM;
+  const int n0 = (bx % tiles_n) * BN;
+  const int kbeg = sp * kchunk;
+  const int kend = min(Kp, kbeg + kchunk);
+  // planes in 16 x 32 blocks: row block rb, K block kb of a plane start at
+  // (rb * Kp/32 + kb) * 512
+  Ah += (long)bz * sA + (long)(m0 >> 4) * (Kp >> 5) * 512;
+  Al += (long)bz * sA + (long)(m0 >> 4) * (Kp >> 5) * 512;
+  Bh += (long)bz * sB + (long)(n0 >> 4) * (Kp >> 5) * 512;
+  Bl += (long)bz * sB + (long)(n0 >> 4) * (Kp >> 5) * 512;
+  const long rbs = (long)(Kp >> 5) * 512;  // row-block stride
+
+  // staging registers, one array per plane (plain loops, so that they
+  // stay in registers)
+  u32x4 rah[AC], ral[AC], rbh[BC], rbl[BC];
+#define PS_LOAD(kb)                                                        \
+  {                                                                        \
+    _Pragma("unroll") for (int i = 0; i < AC; ++i) {                       \
+      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      if (c < BM * 4) {                                                    \
+        const long o = (row >> 4) * rbs + ((kb) >> 5) * 512 +              \
+                       (row & 15) * 32 + 8 * q;                            \
+        rah[i] = *(const u32x4*)(Ah + o);                                  \
+        ral[i] = *(const u32x4*)(Al + o);                                  \
+      }                                                                    \
+    }                                                                      \
+    _Pragma("unroll") for (int i = 0; i < BC; ++i) {                       \
+      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      if (c < BN * 4) {                                                    \
+        const long o = (row >> 4) * rbs + ((kb) >> 5) * 512 +              \
+                       (row & 15) * 32 + 8 * q;                            \
+        rbh[i] = *(const u32x4*)(Bh + o);                                  \
+        rbl[i] = *(const u32x4*)(Bl + o);                                  \
+      }                                                                    \
+    }                                                                      \
+  }
+#define PS_STORE()                                                         \
+  {                                                                        \
+    _Pragma("unroll") for (int i = 0; i < AC; ++i) {                       \
+      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      if (c < BM * 4) {                                                    \
+        *(u32x4*)&Ahs[0][row][8 * q] = rah[i];                             \
+        *(u32x4*)&Als[0][row][8 * q] = ral[i];                             \
+      }                                                                    \
+    }                                                                      \
+    _Pragma("unroll") for (int i = 0; i < BC; ++i) {                       \
+      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      if (c < BN * 4) {                                                    \
+        *(u32x4*)&Bhs[0][row][8 * q] = rbh[i];                             \
+        *(u32x4*)&Bls[0][row][8 * q] = rbl[i];                             \
+      }                                                                    \
+    }                                                                      \
+  }
+
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  if (kbeg < kend) {
+    PS_LOAD(kbeg);
+    PS_STORE();
+  }
+  __syncthreads();
+  const int kq = 8 * (lane >> 4);
+  constexpr int buf = 0;
+  for (int kb = kbeg; kb < kend; kb += BK) {
+    const bool more = kb + BK < kend;
+    if (more) PS_LOAD(kb + BK);
+    bf16x8 ah[TM], al[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * WTM + i * 16 + (lane & 15);
+      ah[i] = *(const bf16x8*)&Ahs[buf][r][kq];
+      al[i] = *(const bf16x8*)&Als[buf][r][kq];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = wn * WTN + j * 16 + (lane & 15);
+      const bf16x8 bh = *(const bf16x8*)&Bhs[buf][c][kq];
+      const bf16x8 bl = *(const bf16x8*)&Bls[buf][c][kq];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh,
+                                                            acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl,
+                                                            acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh,
+                                                            acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) PS_STORE();
+    __syncthreads();
+  }
+#undef PS_LOAD
+#undef PS_STORE
+
+  double* out;
+  long ldo;
+  if (splits == 1) {
+    out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+    ldo = ldc;
+  } else {
+    out = part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
+    ldo = N;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          const double a = (double)acc[i][j][r];
+          if (splits == 1) {
+            double v = alpha * a;
+            if (beta != 0.0) v += beta * out[(long)row * ldo + col];
+            out[(long)row * ldo + col] = v;
+          } else {
+            out[(long)row * ldo + col] = a;
+          }
+        }
+      }
+}
+
 struct Call {
   bool tA, tB;
   int M, N, K, batch;
@@ -429,9 +646,122 @@ struct Call {
   bool a32 = false;     // A stored in FP32
 };
 
+// BF16x3 product through split planes (see split_bf16_kernel): chosen when
+// both operands are read by at least four tiles and the batch fits one
+// pointer set
+template <int BM, int BN>
+bool presplit_pays(const Call& c) {
+  return c.M >= 4 * BM && c.N >= 4 * BN && c.K >= 128 && c.batch <= MAXP;
+}
+
+template <int BM, int BN, int WM, int WN>
+void launch_presplit(Device& dev, const Call& c) {
+  auto up = [](long x, long m) { return (x + m - 1) / m * m; };
+  const int Mp = (int)up(c.M, BM), Np = (int)up(c.N, BN);
+  const int Kp = (int)up(c.K, 32);
+  const long sA = (long)Mp * Kp, sB = (long)Np * Kp;
+  // hi and lo planes of A and B (bf16) in one buffer
+  const long nbf = 2L * c.batch * (sA + sB);
+  Tensor planes = dev.empty({(nbf + 3) / 4});
+  __bf16* Ah = (__bf16*)planes.ptr;
+  __bf16* Al = Ah + c.batch * sA;
+  __bf16* Bh = Al + c.batch * sA;
+  __bf16* Bl = Bh + c.batch * sB;
+  const long tm = Mp / BM, tn = Np / BN, tiles = tm * tn;
+  int S = 1;
+  if (tiles * c.batch < 512 && c.K >= 512) {
+    S = (int)std::min<long>((512 + tiles * c.batch - 1) / (tiles * c.batch),
+                            c.K / 256);
+    S = std::max(1, std::min(S, 64));
+  }
+  int kchunk = (Kp + S - 1) / S;
+  kchunk = (kchunk + 31) / 32 * 32;
+  S = (Kp + kchunk - 1) / kchunk;
+  Tensor part;
+  if (S > 1) part = dev.empty({(int64_t)S * c.batch * c.M * c.N});
+  if (tiles >= (1L << 31) || (long)c.batch * S > 65535 ||
+      Mp / 32 > 65535 || Np / 32 > 65535)
+    throw ArgError("gemm: grid too large");
+  if (dev.prof.on)
+    dev.prof.begin(dev.stream, PROF_GEMM16, 2.0 * c.M * c.N * c.K * c.batch,
+                   c.batch * ((c.a32 ? 4.0 : 8.0) * c.M * c.K +
+                              8.0 * ((double)c.K * c.N +
+                                     (c.beta != 0.0 ? 2.0 : 1.0) * c.M * c.N)));
+  SplitArgs a{}, b{};
+  const size_t ea = c.a32 ? 4 : 8;
+  for (int i = 0; i < c.batch; ++i) {
+    a.src[i] = c.ptrs ? c.ptrs->a[i]
+                      : (const void*)((const char*)c.A + (size_t)i * c.sA * ea);
+    b.src[i] = c.ptrs ? (const void*)c.ptrs->b[i]
+                      : (const void*)(c.B + (size_t)i * c.sB);
+  }
+  a.ld = c.lda;
+  a.R = c.M;
+  a.K = c.K;
+  a.Rp = Mp;
+  a.Kp = Kp;
+  a.hi = Ah;
+  a.lo = Al;
+  b.ld = c.ldb;
+  b.R = c.N;
+  b.K = c.K;
+  b.Rp = Np;
+  b.Kp = Kp;
+  b.hi = Bh;
+  b.lo = Bl;
+  const dim3 ga(Kp / 32, Mp / 32, c.batch), gb(Kp / 32, Np / 32, c.batch);
+  // A element (m, k): A[k lda + m] when transposed, else A[m lda + k];
+  // B element (n, k): B[n ldb + k] when transposed, else B[k ldb + n]
+  if (c.a32) {
+    if (c.tA)
+      hipLaunchKernelGGL((split_bf16_kernel<float, true>), ga, dim3(256), 0,
+                         dev.stream, a);
+    else
+      hipLaunchKernelGGL((split_bf16_kernel<float, false>), ga, dim3(256), 0,
+                         dev.stream, a);
+  } else {
+    if (c.tA)
+      hipLaunchKernelGGL((split_bf16_kernel<double, true>), ga, dim3(256), 0,
+                         dev.stream, a);
+    else
+      hipLaunchKernelGGL((split_bf16_kernel<double, false>), ga, dim3(256),
+                         0, dev.stream, a);
+  }
+  if (c.tB)
+    hipLaunchKernelGGL((split_bf16_kernel<double, false>), gb, dim3(256), 0,
+                       dev.stream, b);
+  else
+    hipLaunchKernelGGL((split_bf16_kernel<double, true>), gb, dim3(256), 0,
+                       dev.stream, b);
+  PtrArgs pa{};
+  if (c.ptrs) pa = *c.ptrs;
+  hipLaunchKernelGGL((gemm_bf16x3_ps_kernel<BM, BN, WM, WN>),
+                     dim3((unsigned)tiles, (unsigned)(c.batch * S)),
+                     dim3(256), 0, dev.stream, c.M, c.N, Kp, c.alpha, Ah, Al,
+                     sA, Bh, Bl, sB, c.beta, c.C, c.ldc, c.sC, (int)tn, S,
+                     kchunk, part.ptr, c.ptrs ? 1 : 0, pa);
+  if (dev.prof.on) dev.prof.end(dev.stream);
+  IPEPS_HIP(hipGetLastError());
+  if (S > 1) {
+    const long tot = (long)c.batch * c.M * c.N;
+    const int g = (int)std::max<long>(1, std::min<long>((tot + 255) / 256,
+                                                        8192));
+    hipLaunchKernelGGL(splitk_sum_kernel, dim3(g), dim3(256), 0, dev.stream,
+                       part.ptr, S, c.batch, (long)c.M, (long)c.N, c.alpha,
+                       c.beta, c.C, c.ldc, c.sC, c.ptrs ? 1 : 0, pa);
+    IPEPS_HIP(hipGetLastError());
+  }
+}
+
 // P: 0 = FP64, 1 = FP32, 2 = BF16x3 arithmetic
 template <int BM, int BN, int WM, int WN, int P>
 void launch_cfg(Device& dev, const Call& c) {
+  if constexpr (P == 2) {
+    if (presplit_pays<BM, BN>(c)) {
+      launch_presplit<BM, BN, WM, WN>(dev, c);
+      return;
+    }
+  }
   constexpr bool F32 = P == 1;
   constexpr int BK = P == 2 ? 32 : 16;
   const long tm = (c.M + BM - 1) / BM, tn = (c.N + BN - 1) / BN;

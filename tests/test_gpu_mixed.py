@@ -103,7 +103,14 @@ def _step_against_golden(name, prec, rel):
 @pytest.mark.parametrize("tA,tB,M,N,K", [(0, 0, 200, 130, 300),
                                          (1, 0, 129, 72, 2592),
                                          (0, 1, 300, 48, 1296),
-                                         (0, 0, 640, 1296, 1296)])
+                                         (0, 0, 640, 1296, 1296),
+                                         # operands split once into planes
+                                         # (both read by >= 4 tiles), all
+                                         # transposes, ragged M, N, K
+                                         (1, 0, 530, 400, 1000),
+                                         (0, 1, 530, 400, 1000),
+                                         (1, 1, 530, 400, 1000),
+                                         (0, 0, 517, 389, 131)])
 def test_bf16x3_gemm_error_bound(tA, tB, M, N, K):
     """x = hi + lo + r with hi = bf16(fl32(x)), lo = bf16(fl32(x) - hi) and
     BF16 unit roundoff 2^-8: |fl32(x) - hi| <= 2^-8 |x|, so
