@@ -40,7 +40,13 @@ def _say(msg):
 @pytest.mark.parametrize("tA,tB,M,N,K", [(0, 0, 200, 130, 300),
                                          (1, 0, 129, 72, 2592),
                                          (0, 1, 300, 48, 1296),
-                                         (0, 0, 2592, 72, 2592)])
+                                         (0, 0, 2592, 72, 2592),
+                                         # 128 x 128 tiles, every
+                                         # transpose, ragged M, N, K
+                                         (1, 0, 530, 600, 1000),
+                                         (0, 1, 530, 600, 1000),
+                                         (1, 1, 530, 600, 1000),
+                                         (0, 0, 517, 613, 131)])
 def test_fp32_gemm_error_bound(tA, tB, M, N, K):
     _say(f"fp32 gemm {tA}{tB} {M}x{N}x{K}")
     rng = np.random.default_rng(M + N + K)
