@@ -515,13 +515,19 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
   Bl += (long)bz * sB + (long)(n0 >> 4) * (Kp >> 5) * 512;
   const long rbs = (long)(Kp >> 5) * 512;  // row-block stride
 
+  // 16-byte chunk c of a slice: K quarter q = c % 4 of row ps_row(c); the
+  // 16 lanes of one LDS store take rows r, r+4, r+8, r+12 (80-byte rows:
+  // 20 r mod 64 covers the 64 banks in four disjoint runs of 16)
+  auto ps_row = [](int c) {
+    return (c >> 6) * 16 + ((c >> 2) & 3) * 4 + ((c >> 4) & 3);
+  };
   // staging registers, one array per plane (plain loops, so that they
   // stay in registers)
   u32x4 rah[AC], ral[AC], rbh[BC], rbl[BC];
 #define PS_LOAD(kb)                                                        \
   {                                                                        \
     _Pragma("unroll") for (int i = 0; i < AC; ++i) {                       \
-      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      const int c = tid + i * 256, row = ps_row(c), q = c & 3;                \
       if (c < BM * 4) {                                                    \
         const long o = (row >> 4) * rbs + ((kb) >> 5) * 512 +              \
                        (row & 15) * 32 + 8 * q;                            \
@@ -530,7 +536,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
       }                                                                    \
     }                                                                      \
     _Pragma("unroll") for (int i = 0; i < BC; ++i) {                       \
-      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      const int c = tid + i * 256, row = ps_row(c), q = c & 3;                \
       if (c < BN * 4) {                                                    \
         const long o = (row >> 4) * rbs + ((kb) >> 5) * 512 +              \
                        (row & 15) * 32 + 8 * q;                            \
@@ -542,14 +548,14 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
 #define PS_STORE()                                                         \
   {                                                                        \
     _Pragma("unroll") for (int i = 0; i < AC; ++i) {                       \
-      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      const int c = tid + i * 256, row = ps_row(c), q = c & 3;                \
       if (c < BM * 4) {                                                    \
         *(u32x4*)&Ahs[0][row][8 * q] = rah[i];                             \
         *(u32x4*)&Als[0][row][8 * q] = ral[i];                             \
       }                                                                    \
     }                                                                      \
     _Pragma("unroll") for (int i = 0; i < BC; ++i) {                       \
-      const int c = tid + i * 256, row = c >> 2, q = c & 3;                \
+      const int c = tid + i * 256, row = ps_row(c), q = c & 3;                \
       if (c < BN * 4) {                                                    \
         *(u32x4*)&Bhs[0][row][8 * q] = rbh[i];                             \
         *(u32x4*)&Bls[0][row][8 * q] = rbl[i];                             \
