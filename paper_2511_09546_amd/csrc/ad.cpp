@@ -1,4 +1,6 @@
 // Reverse-mode tape over the device contraction engine.
+#include <algorithm>
+
 #include "ad.hpp"
 
 namespace ipeps {
@@ -197,6 +199,53 @@ Var Tape::normalize(const Var& x) {
       normalize_backward(dev, len, out->v.ptr, out->g.ptr, nrm.ptr,
                          grad(x).ptr);
     });
+  return out;
+}
+
+std::vector<Var> Tape::normalize_n(const std::vector<Var>& xs) {
+  std::vector<Var> out(xs.size());
+  for (size_t b0 = 0; b0 < xs.size(); b0 += NB_MAX) {
+    const int cnt = (int)std::min<size_t>(NB_MAX, xs.size() - b0);
+    Tensor nrm = dev.empty({cnt});
+    NormBatch p{};
+    bool any = false;
+    std::vector<Var> xi(cnt), yi(cnt);
+    for (int k = 0; k < cnt; ++k) {
+      const Var& x = xs[b0 + k];
+      auto o = std::make_shared<Node>();
+      o->v = dev.empty(x->v.shape);
+      o->req = rec && x->req;
+      any = any || o->req;
+      p.a[k] = x->v.ptr;
+      p.out[k] = o->v.ptr;
+      p.n[k] = (long)x->v.numel();
+      xi[k] = x;
+      yi[k] = o;
+      out[b0 + k] = o;
+    }
+    normalize_batch(dev, p, cnt, nrm.ptr);
+    if (any)
+      push([this, xi, yi, nrm, cnt]() {
+        NormBatch q{};
+        int m = 0;
+        for (int k = 0; k < cnt; ++k)
+          if (has_grad(yi[k]) && xi[k]->req) {
+            q.a[m] = yi[k]->v.ptr;
+            q.b[m] = yi[k]->g.ptr;
+            q.out[m] = grad(xi[k]).ptr;
+            q.nrm[m] = nrm.ptr + k;
+            q.n[m] = (long)yi[k]->v.numel();
+            ++m;
+          }
+        // distinct inputs only in one launch (each accumulates into its
+        // own gradient)
+        for (int k = 1; k < m; ++k)
+          for (int j = 0; j < k; ++j)
+            if (q.out[j] == q.out[k])
+              throw ArgError("normalize_n: an input occurs twice");
+        normalize_backward_batch(dev, q, m);
+      });
+  }
   return out;
 }
 

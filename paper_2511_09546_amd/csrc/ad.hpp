@@ -49,6 +49,8 @@ class Tape {
   Var permute(const Var& x, const std::vector<int>& perm);
   // y = x / ||x||_F
   Var normalize(const Var& x);
+  // the same for several tensors, in batched launches forwards and backwards
+  std::vector<Var> normalize_n(const std::vector<Var>& xs);
   // x [a][b][c] placed at the start of each row block of a zero tensor of
   // shape `shape` read as [*][B][C] (B, C its last two extents after a 3-d
   // view): out[l][j][k] = x[l][j][k] for l < a, j < b, k < c

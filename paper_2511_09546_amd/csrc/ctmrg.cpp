@@ -234,13 +234,16 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
   std::vector<Var> Y1 = tp.einsum_n("jgx,jek->xgek", Pt3, Tc);
   std::vector<Var> Y2 = tp.einsum_n("xgek,gebf->xkbf", Y1, ac);
   std::vector<Var> Tn = tp.einsum_n("xkbf,kby->xfy", Y2, P3);
+  std::vector<Var> raw(Cn);
+  raw.insert(raw.end(), Tn.begin(), Tn.end());
+  std::vector<Var> nrm = tp.normalize_n(raw);
   for (int c = 0; c < 4; ++c)
     for (int s = 0; s < ns; ++s) {
       const int i = c * ns + s;
       out.C[c * ns + L.shift(s, CORNER_MOVE[c][0], CORNER_MOVE[c][1])] =
-          tp.normalize(Cn[i]);
+          nrm[i];
       out.T[c * ns + L.shift(s, EDGE_MOVE[c][0], EDGE_MOVE[c][1])] =
-          tp.normalize(Tn[i]);
+          nrm[m + i];
     }
   return out;
 }

@@ -173,6 +173,22 @@ void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                    double beta, const std::vector<double*>& C, int64_t ldc);
 // y[i] = (float) x[i]
 void to_f32(Device& dev, const double* x, float* y, int64_t n);
+// Up to NB_MAX vectors of any lengths, normalised in one pass (see
+// normalize_batch): a[i] the input (forward) or y (backward), b[i] ybar
+// (backward), out[i] y (forward) or xbar (backward, accumulated), nrm[i]
+// |x_i| (backward input).
+constexpr int NB_MAX = 16;
+struct NormBatch {
+  const double* a[NB_MAX];
+  const double* b[NB_MAX];
+  double* out[NB_MAX];
+  const double* nrm[NB_MAX];
+  long n[NB_MAX];
+};
+// out_i = a_i / |a_i|, nrm[i] = |a_i| (device array of count doubles)
+void normalize_batch(Device& dev, const NormBatch& p, int count, double* nrm);
+// out_i += (b_i - a_i <a_i, b_i>) / nrm_i[0]
+void normalize_backward_batch(Device& dev, const NormBatch& p, int count);
 // dst (cols x rows) = src^T (rows x cols), row major
 void transpose(Device& dev, const double* src, double* dst, int64_t rows,
                int64_t cols);

@@ -1186,6 +1186,102 @@ __global__ void normalize_backward_kernel(int64_t n, const double* y,
     xbar[i] += (ybar[i] - y[i] * dd) * inv;
 }
 
+// Batched normalisation of up to NB_MAX vectors of any lengths: one
+// partial-sum launch over (chunk, item), then one launch that reduces the
+// item's partials in a fixed order and applies the elementwise step
+//   forward   y_i = x_i / |x_i|,  nrm_i = |x_i|;
+//   backward  xbar_i += (ybar_i - y_i <y_i, ybar_i>) / nrm_i.
+constexpr int NB_CHUNKS = 64;
+
+__global__ __launch_bounds__(256) void batch_dot_partial_kernel(
+    NormBatch p, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int i = blockIdx.y, c = blockIdx.x;
+  const long n = p.n[i];
+  const double* a = p.a[i];
+  const double* b = p.b[i];
+  double v = 0.0;
+  for (long e = (long)c * 256 + threadIdx.x; e < n;
+       e += (long)NB_CHUNKS * 256)
+    v += a[e] * b[e];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) part[i * NB_CHUNKS + c] = v;
+}
+
+__global__ __launch_bounds__(256) void batch_normalize_kernel(
+    NormBatch p, const double* __restrict__ part, double* __restrict__ nrm) {
+  __shared__ double s;
+  const int i = blockIdx.y;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int c = 0; c < NB_CHUNKS; ++c) t += part[i * NB_CHUNKS + c];
+    s = sqrt(t);
+    if (blockIdx.x == 0) nrm[i] = s;
+  }
+  __syncthreads();
+  const double f = 1.0 / s;
+  const long n = p.n[i];
+  const double* x = p.a[i];
+  double* y = p.out[i];
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n;
+       e += (long)gridDim.x * 256)
+    y[e] = x[e] * f;
+}
+
+__global__ __launch_bounds__(256) void batch_normalize_backward_kernel(
+    NormBatch p, const double* __restrict__ part) {
+  __shared__ double d;
+  const int i = blockIdx.y;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int c = 0; c < NB_CHUNKS; ++c) t += part[i * NB_CHUNKS + c];
+    d = t;
+  }
+  __syncthreads();
+  const double inv = 1.0 / p.nrm[i][0], dd = d;
+  const long n = p.n[i];
+  const double* y = p.a[i];
+  const double* ybar = p.b[i];
+  double* xbar = p.out[i];
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < n;
+       e += (long)gridDim.x * 256)
+    xbar[e] += (ybar[e] - y[e] * dd) * inv;
+}
+
+static int batch_blocks(const NormBatch& p, int count) {
+  long m = 1;
+  for (int i = 0; i < count; ++i) m = std::max(m, (p.n[i] + 255) / 256);
+  return (int)std::min<long>(m, 1024);
+}
+
+void normalize_batch(Device& dev, const NormBatch& p, int count,
+                     double* nrm) {
+  if (count <= 0) return;
+  if (count > NB_MAX) throw ArgError("normalize_batch: too many items");
+  Tensor part = dev.empty({(int64_t)count * NB_CHUNKS});
+  NormBatch q = p;
+  for (int i = 0; i < count; ++i) q.b[i] = q.a[i];
+  hipLaunchKernelGGL(batch_dot_partial_kernel, dim3(NB_CHUNKS, count),
+                     dim3(256), 0, dev.stream, q, part.ptr);
+  hipLaunchKernelGGL(batch_normalize_kernel,
+                     dim3(batch_blocks(p, count), count), dim3(256), 0,
+                     dev.stream, q, part.ptr, nrm);
+  IPEPS_HIP(hipGetLastError());
+}
+
+void normalize_backward_batch(Device& dev, const NormBatch& p, int count) {
+  if (count <= 0) return;
+  if (count > NB_MAX)
+    throw ArgError("normalize_backward_batch: too many items");
+  Tensor part = dev.empty({(int64_t)count * NB_CHUNKS});
+  hipLaunchKernelGGL(batch_dot_partial_kernel, dim3(NB_CHUNKS, count),
+                     dim3(256), 0, dev.stream, p, part.ptr);
+  hipLaunchKernelGGL(batch_normalize_backward_kernel,
+                     dim3(batch_blocks(p, count), count), dim3(256), 0,
+                     dev.stream, p, part.ptr);
+  IPEPS_HIP(hipGetLastError());
+}
+
 void normalize_backward(Device& dev, int64_t len, const double* y,
                         const double* ybar, const double* nrm, double* xbar) {
   Tensor d = dev.empty({1});
