@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
     int M, int N, int K, double alpha, const void* __restrict__ Av,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
-    int splits, int kchunk, double* __restrict__ part, int use_ptrs,
+    int splits, int kchunk, void* __restrict__ part, int use_ptrs,
     PtrArgs ptrs) {
   static_assert(WM * WN == 4, "4 waves");
   using T = typename std::conditional<F32, float, double>::type;
@@ -201,16 +201,10 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
     buf ^= 1;
   }
 
-  // epilogue: direct (splits == 1) or partial tile (split K)
-  double* out;
-  long ldo;
-  if (splits == 1) {
-    out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
-    ldo = ldc;
-  } else {
-    out = part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
-    ldo = N;
-  }
+  // epilogue: direct (splits == 1) or partial tile (split K), the partial
+  // sums kept in the accumulator's type (exact)
+  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  T* pout = (T*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -221,13 +215,12 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
         const int row = m0 + wm * WTM + i * 16 + rr;
         const int col = n0 + wn * WTN + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          const double a = (double)acc[i][j][r];
           if (splits == 1) {
-            double v = alpha * a;
-            if (beta != 0.0) v += beta * out[(long)row * ldo + col];
-            out[(long)row * ldo + col] = v;
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
+            out[(long)row * ldc + col] = v;
           } else {
-            out[(long)row * ldo + col] = a;
+            pout[(long)row * N + col] = acc[i][j][r];
           }
         }
       }
@@ -252,7 +245,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
     int M, int N, int K, double alpha, const void* __restrict__ Av,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
-    int splits, int kchunk, double* __restrict__ part, int use_ptrs,
+    int splits, int kchunk, void* __restrict__ part, int use_ptrs,
     PtrArgs ptrs) {
   static_assert(WM * WN == 4, "4 waves");
   constexpr int BK = 32, KP = BK + 8;  // 80-byte rows, 16-byte aligned reads
@@ -366,15 +359,10 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
     __syncthreads();
   }
 
-  double* out;
-  long ldo;
-  if (splits == 1) {
-    out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
-    ldo = ldc;
-  } else {
-    out = part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
-    ldo = N;
-  }
+  // split K: FP32 partial sums (exact copies of the accumulators)
+  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  float* pout =
+      (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -384,20 +372,21 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
         const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
         const int col = n0 + wn * WTN + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          const double a = (double)acc[i][j][r];
           if (splits == 1) {
-            double v = alpha * a;
-            if (beta != 0.0) v += beta * out[(long)row * ldo + col];
-            out[(long)row * ldo + col] = v;
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
+            out[(long)row * ldc + col] = v;
           } else {
-            out[(long)row * ldo + col] = a;
+            pout[(long)row * N + col] = acc[i][j][r];
           }
         }
       }
 }
 
-// part layout [S][batch][M][N]; C[b] = alpha sum_s part[s][b] + beta C[b]
-__global__ void splitk_sum_kernel(const double* __restrict__ part, int S,
+// part layout [S][batch][M][N] (FP64, or FP32 for FP32 accumulators);
+// C[b] = alpha sum_s part[s][b] + beta C[b], summed in FP64 in the order of s
+template <typename PT>
+__global__ void splitk_sum_kernel(const PT* __restrict__ part, int S,
                                   int batch, long M, long N, double alpha,
                                   double beta, double* __restrict__ C,
                                   long ldc, long sC, int use_ptrs,
@@ -407,7 +396,9 @@ __global__ void splitk_sum_kernel(const double* __restrict__ part, int S,
        e += (long)gridDim.x * blockDim.x) {
     const long b = e / mn, i = e % mn;
     double v = 0.0;
-    for (int s = 0; s < S; ++s) v += part[((long)s * batch + b) * mn + i];
+#pragma unroll 8
+    for (int s = 0; s < S; ++s)
+      v += (double)part[((long)s * batch + b) * mn + i];
     const long r = i / N, c = i % N;
     double* cp = (use_ptrs ? ptrs.c[b] : C + b * sC) + r * ldc + c;
     double o = alpha * v;
@@ -480,7 +471,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
     const __bf16* __restrict__ Al, long sA, const __bf16* __restrict__ Bh,
     const __bf16* __restrict__ Bl, long sB, double beta,
     double* __restrict__ C, long ldc, long sC, int tiles_n, int splits,
-    int kchunk, double* __restrict__ part, int use_ptrs, PtrArgs ptrs) {
+    int kchunk, void* __restrict__ part, int use_ptrs, PtrArgs ptrs) {
   static_assert(WM * WN == 4, "4 waves");
   constexpr int BK = 32, KP = BK + 8;
   constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -608,15 +599,10 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
 #undef PS_LOAD
 #undef PS_STORE
 
-  double* out;
-  long ldo;
-  if (splits == 1) {
-    out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
-    ldo = ldc;
-  } else {
-    out = part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
-    ldo = N;
-  }
+  // split K: FP32 partial sums (exact copies of the accumulators)
+  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  float* pout =
+      (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -626,13 +612,12 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
         const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
         const int col = n0 + wn * WTN + j * 16 + (lane & 15);
         if (row < M && col < N) {
-          const double a = (double)acc[i][j][r];
           if (splits == 1) {
-            double v = alpha * a;
-            if (beta != 0.0) v += beta * out[(long)row * ldo + col];
-            out[(long)row * ldo + col] = v;
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
+            out[(long)row * ldc + col] = v;
           } else {
-            out[(long)row * ldo + col] = a;
+            pout[(long)row * N + col] = acc[i][j][r];
           }
         }
       }
@@ -683,8 +668,8 @@ void launch_presplit(Device& dev, const Call& c) {
   int kchunk = (Kp + S - 1) / S;
   kchunk = (kchunk + 31) / 32 * 32;
   S = (Kp + kchunk - 1) / kchunk;
-  Tensor part;
-  if (S > 1) part = dev.empty({(int64_t)S * c.batch * c.M * c.N});
+  Tensor part;  // FP32 partial sums
+  if (S > 1) part = dev.empty({((int64_t)S * c.batch * c.M * c.N + 1) / 2});
   if (tiles >= (1L << 31) || (long)c.batch * S > 65535 ||
       Mp / 32 > 65535 || Np / 32 > 65535)
     throw ArgError("gemm: grid too large");
@@ -752,11 +737,150 @@ void launch_presplit(Device& dev, const Call& c) {
     const long tot = (long)c.batch * c.M * c.N;
     const int g = (int)std::max<long>(1, std::min<long>((tot + 255) / 256,
                                                         8192));
-    hipLaunchKernelGGL(splitk_sum_kernel, dim3(g), dim3(256), 0, dev.stream,
-                       part.ptr, S, c.batch, (long)c.M, (long)c.N, c.alpha,
-                       c.beta, c.C, c.ldc, c.sC, c.ptrs ? 1 : 0, pa);
+    hipLaunchKernelGGL(splitk_sum_kernel<float>, dim3(g), dim3(256), 0,
+                       dev.stream, (const float*)part.ptr, S, c.batch,
+                       (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
+                       c.sC, c.ptrs ? 1 : 0, pa);
     IPEPS_HIP(hipGetLastError());
   }
+}
+
+// Products with at most 4 x 4 outputs per batch entry and a long K (overlaps
+// and norms of whole tensors, K up to 4 D^8): a matrix-core tile would be
+// almost all padding and the split-K grid too small to stream the operands,
+// so these run as FP64 FMAs on the vector units.  The K range is cut into
+// S fixed chunks, one workgroup each, reduced in a fixed order (lanes by a
+// butterfly, then the waves, then the chunks in small_sum_kernel), so the
+// result is deterministic.
+constexpr int SMALL_T = 256;
+constexpr int SMALL_MAXS = 256;
+
+template <typename TI, bool TA, bool TB>
+__global__ __launch_bounds__(SMALL_T) void gemm_small_kernel(
+    int M, int N, int K, const TI* __restrict__ A0, long lda, long sA,
+    const double* __restrict__ B0, long ldb, long sB, int kchunk,
+    double* __restrict__ part, int use_ptrs, PtrArgs ptrs) {
+  const int sp = blockIdx.x, bz = blockIdx.y;
+  const TI* A = use_ptrs ? (const TI*)ptrs.a[bz] : A0 + (long)bz * sA;
+  const double* B = use_ptrs ? ptrs.b[bz] : B0 + (long)bz * sB;
+  const int k0 = sp * kchunk, k1 = min(K, k0 + kchunk);
+  double acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[m][n] = 0.0;
+  for (int k = k0 + (int)threadIdx.x; k < k1; k += SMALL_T) {
+    double a[4], b[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      a[m] = m < M ? (double)(TA ? A[(long)k * lda + m] : A[(long)m * lda + k])
+                   : 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      b[n] = n < N ? (TB ? B[(long)n * ldb + k] : B[(long)k * ldb + n]) : 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[m][n] = fma(a[m], b[n], acc[m][n]);
+  }
+  __shared__ double red[SMALL_T / 64][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      double v = acc[m][n];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) red[w][m * 4 + n] = v;
+    }
+  __syncthreads();
+  const int mn = M * N;
+  if ((int)threadIdx.x < mn) {
+    const int m = threadIdx.x / N, n = threadIdx.x % N;
+    double v = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < SMALL_T / 64; ++ww) v += red[ww][m * 4 + n];
+    part[((long)sp * gridDim.y + bz) * mn + threadIdx.x] = v;
+  }
+}
+
+// C[b] = alpha sum_s part[s][b] + beta C[b] for at most 16 outputs per
+// batch entry, one workgroup per entry: thread t sums the chunks s = t,
+// t + 256, ... and the workgroup adds the thread sums in a fixed tree
+__global__ __launch_bounds__(SMALL_T) void small_sum_kernel(
+    const double* __restrict__ part, int S, int M, int N, double alpha,
+    double beta, double* __restrict__ C, long ldc, long sC, int use_ptrs,
+    PtrArgs ptrs) {
+  const int bz = blockIdx.x, batch = gridDim.x, mn = M * N;
+  __shared__ double red[SMALL_T];
+  double* Cb = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  for (int o = 0; o < mn; ++o) {
+    double v = 0.0;
+    for (int sp = threadIdx.x; sp < S; sp += SMALL_T)
+      v += part[((long)sp * batch + bz) * mn + o];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = SMALL_T / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double* cp = Cb + (long)(o / N) * ldc + o % N;
+      double r = alpha * red[0];
+      if (beta != 0.0) r += beta * *cp;
+      *cp = r;
+    }
+    __syncthreads();
+  }
+}
+
+bool small_pays(const Call& c) {
+  return c.M <= 4 && c.N <= 4 && c.K >= 4096;
+}
+
+void launch_small(Device& dev, const Call& c) {
+  // about 16 K values per thread and chunk, at most SMALL_MAXS chunks
+  int S = (int)std::min<long>(SMALL_MAXS, ((long)c.K + 16 * SMALL_T - 1) /
+                                              (16 * SMALL_T));
+  S = std::max(S, 1);
+  const int kchunk = (c.K + S - 1) / S;
+  S = (c.K + kchunk - 1) / kchunk;
+  if (c.batch > 65535) throw ArgError("gemm: grid too large");
+  Tensor part = dev.empty({(int64_t)S * c.batch * c.M * c.N});
+  PtrArgs pa{};
+  if (c.ptrs) pa = *c.ptrs;
+  const int up = c.ptrs ? 1 : 0;
+  const dim3 grid((unsigned)S, (unsigned)c.batch);
+  auto go = [&](auto ti) {
+    using TI = decltype(ti);
+    const TI* A = (const TI*)c.A;
+    if (!c.tA && !c.tB)
+      hipLaunchKernelGGL((gemm_small_kernel<TI, false, false>), grid,
+                         dim3(SMALL_T), 0, dev.stream, c.M, c.N, c.K, A, c.lda,
+                         c.sA, c.B, c.ldb, c.sB, kchunk, part.ptr, up, pa);
+    if (c.tA && !c.tB)
+      hipLaunchKernelGGL((gemm_small_kernel<TI, true, false>), grid,
+                         dim3(SMALL_T), 0, dev.stream, c.M, c.N, c.K, A, c.lda,
+                         c.sA, c.B, c.ldb, c.sB, kchunk, part.ptr, up, pa);
+    if (!c.tA && c.tB)
+      hipLaunchKernelGGL((gemm_small_kernel<TI, false, true>), grid,
+                         dim3(SMALL_T), 0, dev.stream, c.M, c.N, c.K, A, c.lda,
+                         c.sA, c.B, c.ldb, c.sB, kchunk, part.ptr, up, pa);
+    if (c.tA && c.tB)
+      hipLaunchKernelGGL((gemm_small_kernel<TI, true, true>), grid,
+                         dim3(SMALL_T), 0, dev.stream, c.M, c.N, c.K, A, c.lda,
+                         c.sA, c.B, c.ldb, c.sB, kchunk, part.ptr, up, pa);
+  };
+  if (c.a32)
+    go(float());
+  else
+    go(double());
+  IPEPS_HIP(hipGetLastError());
+  hipLaunchKernelGGL(small_sum_kernel, dim3(c.batch), dim3(SMALL_T), 0,
+                     dev.stream, part.ptr, S, c.M, c.N, c.alpha, c.beta, c.C,
+                     c.ldc, c.sC, up, pa);
+  IPEPS_HIP(hipGetLastError());
 }
 
 // P: 0 = FP64, 1 = FP32, 2 = BF16x3 arithmetic
@@ -781,13 +905,15 @@ void launch_cfg(Device& dev, const Call& c) {
   if (tiles * c.batch < want && c.K >= 512) {
     S = (int)std::min<long>((want + tiles * c.batch - 1) / (tiles * c.batch),
                             c.K / 256);
-    S = std::max(1, std::min(S, 64));
+    S = std::max(1, std::min(S, 256));
   }
   int kchunk = (c.K + S - 1) / S;
   kchunk = (kchunk + BK - 1) / BK * BK;
   S = (c.K + kchunk - 1) / kchunk;
+  // partial sums in the accumulators' type: FP64, or FP32 (FP32 and BF16x3)
+  const int64_t npart = (int64_t)S * c.batch * c.M * c.N;
   Tensor part;
-  if (S > 1) part = dev.empty({(int64_t)S * c.batch * c.M * c.N});
+  if (S > 1) part = dev.empty({P == 0 ? npart : (npart + 1) / 2});
   if (tiles >= (1L << 31) || (long)c.batch * S > 65535)
     throw ArgError("gemm: grid too large");
   dim3 grid((unsigned)tiles, (unsigned)(c.batch * S));
@@ -844,9 +970,16 @@ void launch_cfg(Device& dev, const Call& c) {
     const long tot = (long)c.batch * c.M * c.N;
     const int g = (int)std::max<long>(1, std::min<long>((tot + 255) / 256,
                                                         8192));
-    hipLaunchKernelGGL(splitk_sum_kernel, dim3(g), dim3(256), 0, dev.stream,
-                       part.ptr, S, c.batch, (long)c.M, (long)c.N, c.alpha,
-                       c.beta, c.C, c.ldc, c.sC, up, pa);
+    if constexpr (P == 0)
+      hipLaunchKernelGGL(splitk_sum_kernel<double>, dim3(g), dim3(256), 0,
+                         dev.stream, (const double*)part.ptr, S, c.batch,
+                         (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
+                         c.sC, up, pa);
+    else
+      hipLaunchKernelGGL(splitk_sum_kernel<float>, dim3(g), dim3(256), 0,
+                         dev.stream, (const float*)part.ptr, S, c.batch,
+                         (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
+                         c.sC, up, pa);
     IPEPS_HIP(hipGetLastError());
   }
 }
@@ -876,6 +1009,10 @@ void dispatch_prec(Device& dev, const Call& c) {
 }
 
 void dispatch(Device& dev, const Call& c) {
+  if (small_pays(c)) {
+    launch_small(dev, c);
+    return;
+  }
   if (dev.cprec == PREC_FP32)
     dispatch_prec<1>(dev, c);
   else if (dev.cprec == PREC_FP64)

@@ -20,7 +20,11 @@ def _say(msg):
     (300, 200, 700, False, True), (300, 200, 700, True, True),
     (2592, 96, 2592, False, False), (2592, 72, 2592, True, False),
     (257, 65, 33, True, True), (36, 36, 20000, False, False),
-    (100, 1000, 16, False, True)])
+    (100, 1000, 16, False, True),
+    # at most 4 x 4 outputs with a long K: vector-unit kernel, chunked K
+    (4, 4, 20000, False, False), (3, 4, 9001, True, False),
+    (4, 2, 70000, False, True), (1, 1, 4096, True, True),
+    (2, 3, 1100000, False, False)])
 def test_gemm(M, N, K, tA, tB):
     _say(f"gemm {M}x{N}x{K} tA={tA} tB={tB}")
     rng = np.random.default_rng(M * N + K)
@@ -30,6 +34,20 @@ def test_gemm(M, N, K, tA, tB):
     C = binding.debug_gemm(A, B, C0, tA, tB, alpha=0.7, beta=-0.3)
     ref = 0.7 * ((A.T if tA else A) @ (B.T if tB else B)) - 0.3 * C0
     assert np.abs(C - ref).max() < 1e-12 * max(1.0, np.abs(ref).max()) * K
+
+
+@pytest.mark.parametrize("prec", [binding.FP32, binding.BF16])
+def test_small_output_gemm_is_fp64(prec):
+    """Products with at most 4 x 4 outputs and K >= 4096 run as FP64 FMAs
+    whatever the contraction arithmetic: FP64 accuracy, not FP32's."""
+    _say(f"small-output gemm 4x3x50000, prec {prec}")
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((4, 50000))
+    B = rng.standard_normal((50000, 3))
+    C0 = rng.standard_normal((4, 3))
+    C = binding.debug_gemm_prec(prec, A, B, C0, alpha=1.5, beta=0.5)
+    ref = 1.5 * (A @ B) + 0.5 * C0
+    assert np.abs(C - ref).max() < 1e-10
 
 
 def test_gemm_split_k():
