@@ -984,6 +984,27 @@ void launch_cfg(Device& dev, const Call& c) {
   }
 }
 
+// Time model of a tile choice: the workgroups (tiles times the split of
+// launch_cfg) are dealt over the 256 CUs, whose matrix cores the resident
+// workgroups share, so a launch takes about ceil(workgroups / 256) times
+// the multiply-adds of one workgroup (BM BN kchunk, padding included).
+// The 128 x 144 FP32 tile runs at two waves per SIMD instead of three,
+// hence the 5 % handicap where it is compared.
+double tile_cost(const Call& c, int BM, int BN, int BK, long want) {
+  const long tiles = (long)((c.M + BM - 1) / BM) * ((c.N + BN - 1) / BN);
+  long S = 1;
+  if (tiles * c.batch < want && c.K >= 512) {
+    S = std::min<long>((want + tiles * c.batch - 1) / (tiles * c.batch),
+                       c.K / 256);
+    S = std::max<long>(1, std::min<long>(S, 256));
+  }
+  long kchunk = (c.K + S - 1) / S;
+  kchunk = (kchunk + BK - 1) / BK * BK;
+  S = (c.K + kchunk - 1) / kchunk;
+  const long wg = tiles * c.batch * S;
+  return (double)((wg + 255) / 256) * BM * BN * kchunk;
+}
+
 template <int P>
 void dispatch_prec(Device& dev, const Call& c) {
   if (c.M >= 128) {
@@ -999,7 +1020,15 @@ void dispatch_prec(Device& dev, const Call& c) {
       launch_cfg<128, 96, 4, 1, P>(dev, c);
     else if constexpr (P == 2)  // BF16x3: 128 x 128 would spill registers
       launch_cfg<128, 96, 4, 1, P>(dev, c);
-    else
+    else if constexpr (P == 1) {
+      // FP32: 128 x 144 tiles (4 waves of 32 x 144; D^4 = 1296 and its
+      // multiples by D^2 are multiples of 144) when the model below says
+      // they finish first
+      if (tile_cost(c, 128, 144, 16, 512) * 21 < tile_cost(c, 128, 128, 16, 512) * 20)
+        launch_cfg<128, 144, 4, 1, P>(dev, c);
+      else
+        launch_cfg<128, 128, 2, 2, P>(dev, c);
+    } else
       launch_cfg<128, 128, 2, 2, P>(dev, c);
   } else if (c.N >= 128) {
     launch_cfg<64, 128, 2, 2, P>(dev, c);
