@@ -42,6 +42,15 @@ int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
 int ipeps_debug_svd_ts(int n, int b, int batch, const double* W, double* U,
                        double* s, double* J);
 
+/* out = alpha permute(in) + beta out by the library's permute kernels:
+ * in is a row-major host tensor of rank `rank` (1..12) and shape `shape`,
+ * out has shape shape[perm[0]], ..., shape[perm[rank - 1]] (perm is a
+ * permutation of 0..rank-1); out[i_0..i_{r-1}] = in[j] with j[perm[d]] =
+ * i_d.  Fewer than 2^31 elements.  Returns a status. */
+int ipeps_debug_permute(int rank, const long* shape, const int* perm,
+                        double alpha, const double* in, double beta,
+                        double* out);
+
 /* Iteration counters of a context since its creation: out[0] subspace
  * iterations, out[1] projector-SVD calls, out[2] largest final subspace
  * residual (relative to s_1), out[3] complement-CG iterations of the

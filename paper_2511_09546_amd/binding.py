@@ -33,7 +33,8 @@ API_FUNCTIONS = [
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
                    "ipeps_debug_svd_ts", "ipeps_debug_stats",
-                   "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time"]
+                   "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time",
+                   "ipeps_debug_permute"]
 
 
 class IpepsError(RuntimeError):
@@ -108,6 +109,8 @@ def load():
     lib.ipeps_debug_gemm_time.argtypes = [c_int, c_int, c_int, c_int, c_int,
                                           c_int, c_int, c_int, _DP]
     lib.ipeps_debug_sym_eig.argtypes = [c_int, c_int, _DP, _DP, _DP]
+    lib.ipeps_debug_permute.argtypes = [c_int, POINTER(ctypes.c_long),
+                                        _IP, c_double, _DP, c_double, _DP]
     lib.ipeps_debug_stats.argtypes = [c_void_p, _DP]
     lib.ipeps_debug_svd_ts.argtypes = [c_int, c_int, c_int, _DP, _DP, _DP,
                                        _DP]
@@ -119,7 +122,7 @@ def load():
                  "precond_apply_dev",
                  "ipeps_debug_sym_eig", "ipeps_debug_svd_ts",
                  "ipeps_debug_stats", "ipeps_debug_gemm_prec",
-                 "ipeps_debug_gemm_time"):
+                 "ipeps_debug_gemm_time", "ipeps_debug_permute"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -365,6 +368,22 @@ def debug_sym_eig(G):
     if st != OK:
         raise IpepsError(st, "ipeps_debug_sym_eig")
     return lam, V
+
+
+def debug_permute(X, perm, alpha=1.0, beta=0.0, out=None):
+    """alpha X.transpose(perm) + beta out by the library's permute kernels."""
+    X = _f64(X)
+    r = X.ndim
+    perm = [int(p) for p in perm]
+    oshape = tuple(X.shape[p] for p in perm)
+    out = np.zeros(oshape) if out is None else _f64(out).copy()
+    sh = (ctypes.c_long * r)(*X.shape)
+    pm = np.ascontiguousarray(perm, dtype=np.int32)
+    st = load().ipeps_debug_permute(r, sh, pm.ctypes.data_as(_IP), alpha,
+                                    _dp(X), beta, _dp(out))
+    if st != OK:
+        raise IpepsError(st, "ipeps_debug_permute")
+    return out
 
 
 def debug_svd_ts(W):

@@ -3,6 +3,8 @@
 #include "../../include/ipeps_debug.h"
 #include "ipeps_impl.hpp"
 
+#include <vector>
+
 using namespace ipeps;
 
 namespace {
@@ -91,6 +93,33 @@ int ipeps_debug_gemm_time(int prec, int tA, int tB, int M, int N, int K,
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *us_per_call = 1e3 * ms / reps;
+  });
+}
+
+int ipeps_debug_permute(int rank, const long* shape, const int* perm,
+                        double alpha, const double* in, double beta,
+                        double* out) {
+  if (!shape || !perm || !in || !out || rank < 1 || rank > 12)
+    return IPEPS_EINVAL;
+  std::vector<int64_t> sh(rank), osh(rank);
+  std::vector<int> pm(rank), seen(rank, 0);
+  int64_t n = 1;
+  for (int d = 0; d < rank; ++d) {
+    if (shape[d] < 1 || perm[d] < 0 || perm[d] >= rank || seen[perm[d]])
+      return IPEPS_EINVAL;
+    seen[perm[d]] = 1;
+    sh[d] = shape[d];
+    pm[d] = perm[d];
+    n *= shape[d];
+    if (n >= (1LL << 31)) return IPEPS_EINVAL;
+  }
+  for (int d = 0; d < rank; ++d) osh[d] = sh[pm[d]];
+  return run([&](Device& dev) {
+    Tensor a = dev.empty(sh), b = dev.empty(osh);
+    dev.upload(a, in);
+    dev.upload(b, out);
+    permute(dev, a, pm, b, alpha, beta);
+    dev.download(b, out);
   });
 }
 

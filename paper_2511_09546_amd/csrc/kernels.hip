@@ -75,34 +75,39 @@ struct TileArgs {
 
 __global__ __launch_bounds__(256) void permute_tiled_kernel(
     const double* __restrict__ in, double* __restrict__ out, TileArgs a,
-    double alpha, double beta) {
+    int nrest, double alpha, double beta) {
   __shared__ double tile[32][33];
-  long rest = blockIdx.y;
-  long oin = 0, oout = 0;
-  for (int d = a.rank - 1; d >= 0; --d) {
-    const long q = rest / a.shape[d];
-    const long i = rest - q * a.shape[d];
-    oin += i * a.in_stride[d];
-    oout += i * a.out_stride[d];
-    rest = q;
-  }
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   const int q0 = (blockIdx.x / a.tl) * 32, l0 = (blockIdx.x % a.tl) * 32;
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int l = l0 + ty + 8 * j, q = q0 + tx;
-    if (l < a.nl && q < a.nq) tile[ty + 8 * j][tx] = in[oin + q + l * a.sl_in];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int q = q0 + ty + 8 * j, l = l0 + tx;
-    if (l < a.nl && q < a.nq) {
-      double* o = out + oout + q * a.sq_out + l;
-      double v = alpha * tile[tx][ty + 8 * j];
-      if (beta != 0.0) v += beta * *o;
-      *o = v;
+  // the remaining output dimensions, gridDim.y of them at a time
+  for (int r0 = blockIdx.y; r0 < nrest; r0 += gridDim.y) {
+    int rest = r0;  // below 2^31: the tensor has fewer elements
+    long oin = 0, oout = 0;
+    for (int d = a.rank - 1; d >= 0; --d) {
+      const int q = rest / a.shape[d];
+      const int i = rest - q * a.shape[d];
+      oin += i * a.in_stride[d];
+      oout += i * a.out_stride[d];
+      rest = q;
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int l = l0 + ty + 8 * j, q = q0 + tx;
+      if (l < a.nl && q < a.nq)
+        tile[ty + 8 * j][tx] = in[oin + q + l * a.sl_in];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = q0 + ty + 8 * j, l = l0 + tx;
+      if (l < a.nl && q < a.nq) {
+        double* o = out + oout + q * a.sq_out + l;
+        double v = alpha * tile[tx][ty + 8 * j];
+        if (beta != 0.0) v += beta * *o;
+        *o = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -174,18 +179,17 @@ void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
       ++a.rank;
       nrest *= oshape[i];
     }
-    if (nrest > 65535) goto generic;
     if (dev.prof.on)
       dev.prof.begin(dev.stream, PROF_PERMUTE, 0.0,
                      8.0 * n * (beta != 0.0 ? 3 : 2));
-    hipLaunchKernelGGL(permute_tiled_kernel, dim3(a.tq * a.tl, (int)nrest),
-                       dim3(256), 0, dev.stream, in.ptr, out.ptr, a, alpha,
-                       beta);
+    hipLaunchKernelGGL(permute_tiled_kernel,
+                       dim3(a.tq * a.tl, (int)std::min<int64_t>(nrest, 65535)),
+                       dim3(256), 0, dev.stream, in.ptr, out.ptr, a,
+                       (int)nrest, alpha, beta);
     if (dev.prof.on) dev.prof.end(dev.stream);
     IPEPS_HIP(hipGetLastError());
     return;
   }
-generic:
   PermArgs p{};
   p.rank = (int)oshape.size();
   for (int i = 0; i < p.rank; ++i) {

@@ -59,6 +59,24 @@ def test_gemm_split_k():
     assert np.abs(C - A @ B).max() < 1e-10
 
 
+@pytest.mark.parametrize("shape,perm,beta", [
+    ((7, 5, 3), (2, 0, 1), 0.0),             # generic path
+    ((40, 3, 70), (2, 1, 0), 0.0),           # tiled, ragged tiles
+    ((33, 36, 34), (0, 2, 1), -0.5),         # tiled, accumulate
+    ((2, 3, 4, 5, 6, 7), (5, 3, 1, 0, 2, 4), 0.0),
+    ((300, 4, 300, 4), (0, 3, 2, 1), 0.0),  # tiled, 90000 outer tiles
+    ((3, 4), (0, 1), 0.5)])                  # identity: plain copy
+def test_permute(shape, perm, beta):
+    _say(f"permute {shape} {perm} beta={beta}")
+    rng = np.random.default_rng(len(shape) + shape[0])
+    X = rng.standard_normal(shape)
+    out0 = rng.standard_normal(tuple(shape[p] for p in perm))
+    out = binding.debug_permute(X, perm, alpha=0.7, beta=beta, out=out0)
+    ref = 0.7 * np.transpose(X, perm) + beta * out0
+    assert np.array_equal(out, ref) if beta == 0.0 else \
+        np.abs(out - ref).max() < 1e-15
+
+
 @pytest.mark.parametrize("b,batch", [(2, 1), (8, 3), (32, 2), (96, 1),
                                      (128, 1)])
 def test_sym_eig(b, batch):
