@@ -57,11 +57,16 @@ static int grid_for(int64_t n, int block) {
 }
 
 // Tiled permute for the case where the output's innermost dimension is not
-// the input's: a 32 x 32 tile over (q = the output dimension that is
+// the input's: a TQ x TL tile over (q = the output dimension that is
 // innermost in the input, l = the innermost output dimension) goes through
-// LDS, so that reads run along q and writes along l, both coalesced.  The
-// remaining output dimensions enumerate tiles in blockIdx.y (div/mod once
-// per block).
+// LDS, so that reads run along q and writes along l, both coalesced.  TQ is
+// the extent of q itself when that is at most 96 (the bond dimensions D^2
+// and chi here: no lanes wasted on a partial tile), else 64, and
+// TL = min(2048 / TQ, 256); the 256 threads cover 256 / TQ rows of the tile
+// per pass when reading and 256 / TL when writing.  The remaining output
+// dimensions enumerate tiles in blockIdx.y (grid-stride, div/mod once per
+// tile).
+constexpr int PERM_TILE = 2048;  // elements of one tile
 struct TileArgs {
   int rank;            // remaining dimensions
   int shape[12];
@@ -70,16 +75,22 @@ struct TileArgs {
   int nq, nl;          // extents of q and l
   long sq_out;         // output stride of q (input stride of q is 1)
   long sl_in;          // input stride of l (output stride of l is 1)
+  int bq, bl;          // tile extents TQ, TL
   int tq, tl;          // tiles along q and l
 };
 
 __global__ __launch_bounds__(256) void permute_tiled_kernel(
     const double* __restrict__ in, double* __restrict__ out, TileArgs a,
     int nrest, double alpha, double beta) {
-  __shared__ double tile[32][33];
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  const int q0 = (blockIdx.x / a.tl) * 32, l0 = (blockIdx.x % a.tl) * 32;
-  // the remaining output dimensions, gridDim.y of them at a time
+  __shared__ double tile[PERM_TILE + 256];  // [TL][TQ + 1]
+  const int TQ = a.bq, TL = a.bl, SQ = TQ + 1;
+  const int q0 = (blockIdx.x / a.tl) * TQ, l0 = (blockIdx.x % a.tl) * TL;
+  const int tid = threadIdx.x;
+  // reading: this thread's q and first l row; writing: its l and first q
+  const int rq = tid % TQ, rl0 = tid / TQ, rstep = 256 / TQ;
+  const int wl = tid % TL, wq0 = tid / TL, wstep = 256 / TL;
+  const bool rin = rl0 < rstep && q0 + rq < a.nq;
+  const bool win = wq0 < wstep && l0 + wl < a.nl;
   for (int r0 = blockIdx.y; r0 < nrest; r0 += gridDim.y) {
     int rest = r0;  // below 2^31: the tensor has fewer elements
     long oin = 0, oout = 0;
@@ -90,19 +101,17 @@ __global__ __launch_bounds__(256) void permute_tiled_kernel(
       oout += i * a.out_stride[d];
       rest = q;
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int l = l0 + ty + 8 * j, q = q0 + tx;
-      if (l < a.nl && q < a.nq)
-        tile[ty + 8 * j][tx] = in[oin + q + l * a.sl_in];
+    if (rin) {
+      const double* src = in + oin + q0 + rq;
+      for (int ll = rl0; ll < TL && l0 + ll < a.nl; ll += rstep)
+        tile[ll * SQ + rq] = src[(long)(l0 + ll) * a.sl_in];
     }
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int q = q0 + ty + 8 * j, l = l0 + tx;
-      if (l < a.nl && q < a.nq) {
-        double* o = out + oout + q * a.sq_out + l;
-        double v = alpha * tile[tx][ty + 8 * j];
+    if (win) {
+      double* dst = out + oout + l0 + wl;
+      for (int qq = wq0; qq < TQ && q0 + qq < a.nq; qq += wstep) {
+        double* o = dst + (long)(q0 + qq) * a.sq_out;
+        double v = alpha * tile[wl * SQ + qq];
         if (beta != 0.0) v += beta * *o;
         *o = v;
       }
@@ -168,8 +177,10 @@ void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
     a.nl = (int)oshape[ld];
     a.sq_out = ostride[qd];
     a.sl_in = ostr[ld];
-    a.tq = (a.nq + 31) / 32;
-    a.tl = (a.nl + 31) / 32;
+    a.bq = a.nq <= 96 ? a.nq : 64;
+    a.bl = std::min(PERM_TILE / a.bq, 256);
+    a.tq = (a.nq + a.bq - 1) / a.bq;
+    a.tl = (a.nl + a.bl - 1) / a.bl;
     int64_t nrest = 1;
     for (int i = 0; i < ld; ++i) {
       if (i == qd) continue;

@@ -65,6 +65,8 @@ def test_gemm_split_k():
     ((33, 36, 34), (0, 2, 1), -0.5),         # tiled, accumulate
     ((2, 3, 4, 5, 6, 7), (5, 3, 1, 0, 2, 4), 0.0),
     ((300, 4, 300, 4), (0, 3, 2, 1), 0.0),  # tiled, 90000 outer tiles
+    ((5, 4, 3, 6), (0, 3, 2, 1), -0.5),      # tile of 4 x 256
+    ((130, 6, 70), (2, 1, 0), 0.0),          # q longer than one tile
     ((3, 4), (0, 1), 0.5)])                  # identity: plain copy
 def test_permute(shape, perm, beta):
     _say(f"permute {shape} {perm} beta={beta}")
