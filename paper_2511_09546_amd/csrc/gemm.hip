@@ -745,6 +745,34 @@ void launch_presplit(Device& dev, const Call& c) {
   }
 }
 
+// Split of K for a grid of tb tiles.  The workgroups (tb S) are dealt over
+// the 256 CUs, whose matrix cores the resident workgroups share, so a launch
+// takes about ceil(tb S / 256) times the work of one workgroup (kchunk of
+// K).  The split minimises that product, taking the larger split on ties
+// (more workgroups in flight to hide latency), with at least 256 of K per
+// split, at most 256 splits and 2048 workgroups.
+int split_k(long tb, int K, int BK, int& kchunk) {
+  auto up = [](long x, long m) { return (x + m - 1) / m * m; };
+  int best = 1;
+  long best_cost = -1;
+  kchunk = (int)up(K, BK);
+  if (K >= 512 && tb < 2048) {
+    const long smax = std::min<long>(
+        {256L, (long)K / 256, std::max<long>(1, 2048 / tb)});
+    for (long s = 1; s <= smax; ++s) {
+      const long kc = up((K + s - 1) / s, BK);
+      const long se = (K + kc - 1) / kc;
+      const long cost = (tb * se + 255) / 256 * kc;
+      if (best_cost < 0 || cost <= best_cost) {
+        best_cost = cost;
+        best = (int)se;
+        kchunk = (int)kc;
+      }
+    }
+  }
+  return best;
+}
+
 // Products with at most 4 x 4 outputs per batch entry and a long K (overlaps
 // and norms of whole tensors, K up to 4 D^8): a matrix-core tile would be
 // almost all padding and the split-K grid too small to stream the operands,
@@ -896,20 +924,8 @@ void launch_cfg(Device& dev, const Call& c) {
   constexpr int BK = P == 2 ? 32 : 16;
   const long tm = (c.M + BM - 1) / BM, tn = (c.N + BN - 1) / BN;
   const long tiles = tm * tn;
-  // split K until the grid covers the chip, keeping at least 256 of K per
-  // split
-  int S = 1;
-  // workgroup target of the split (two or three waves of workgroups over the
-  // 256 CUs; measured best for the skinny n x n x chi products)
-  const long want = P == 0 ? 768 : 512;
-  if (tiles * c.batch < want && c.K >= 512) {
-    S = (int)std::min<long>((want + tiles * c.batch - 1) / (tiles * c.batch),
-                            c.K / 256);
-    S = std::max(1, std::min(S, 256));
-  }
-  int kchunk = (c.K + S - 1) / S;
-  kchunk = (kchunk + BK - 1) / BK * BK;
-  S = (c.K + kchunk - 1) / kchunk;
+  int kchunk;
+  int S = split_k(tiles * c.batch, c.K, BK, kchunk);
   // partial sums in the accumulators' type: FP64, or FP32 (FP32 and BF16x3)
   const int64_t npart = (int64_t)S * c.batch * c.M * c.N;
   Tensor part;
@@ -990,17 +1006,10 @@ void launch_cfg(Device& dev, const Call& c) {
 // the multiply-adds of one workgroup (BM BN kchunk, padding included).
 // The 128 x 144 FP32 tile runs at two waves per SIMD instead of three,
 // hence the 5 % handicap where it is compared.
-double tile_cost(const Call& c, int BM, int BN, int BK, long want) {
+double tile_cost(const Call& c, int BM, int BN, int BK) {
   const long tiles = (long)((c.M + BM - 1) / BM) * ((c.N + BN - 1) / BN);
-  long S = 1;
-  if (tiles * c.batch < want && c.K >= 512) {
-    S = std::min<long>((want + tiles * c.batch - 1) / (tiles * c.batch),
-                       c.K / 256);
-    S = std::max<long>(1, std::min<long>(S, 256));
-  }
-  long kchunk = (c.K + S - 1) / S;
-  kchunk = (kchunk + BK - 1) / BK * BK;
-  S = (c.K + kchunk - 1) / kchunk;
+  int kchunk;
+  const long S = split_k(tiles * c.batch, c.K, BK, kchunk);
   const long wg = tiles * c.batch * S;
   return (double)((wg + 255) / 256) * BM * BN * kchunk;
 }
@@ -1024,7 +1033,7 @@ void dispatch_prec(Device& dev, const Call& c) {
       // FP32: 128 x 144 tiles (4 waves of 32 x 144; D^4 = 1296 and its
       // multiples by D^2 are multiples of 144) when the model below says
       // they finish first
-      if (tile_cost(c, 128, 144, 16, 512) * 21 < tile_cost(c, 128, 128, 16, 512) * 20)
+      if (tile_cost(c, 128, 144, 16) * 21 < tile_cost(c, 128, 128, 16) * 20)
         launch_cfg<128, 144, 4, 1, P>(dev, c);
       else
         launch_cfg<128, 128, 2, 2, P>(dev, c);
