@@ -745,16 +745,22 @@ void launch_presplit(Device& dev, const Call& c) {
   }
 }
 
-// Split of K for a grid of tb tiles.  The workgroups (tb S) are dealt over
-// the 256 CUs, whose matrix cores the resident workgroups share, so a launch
-// takes about ceil(tb S / 256) times the work of one workgroup (kchunk of
-// K).  The split minimises that product, taking the larger split on ties
-// (more workgroups in flight to hide latency), with at least 256 of K per
-// split, at most 256 splits and 2048 workgroups.
-int split_k(long tb, int K, int BK, int& kchunk) {
+// Split of K for a grid of tb tiles (BM x BN each; mn_batch outputs in
+// all).  The workgroups (wg = tb S) are dealt over the 256 CUs, whose
+// matrix cores the resident workgroups share, so the products take about
+// ceil(wg / 256) times the time of one workgroup (2 BM BN kchunk flops at
+// half the per-CU peak `flops_cu`), stretched by 1 + 128 / wg when few
+// workgroups per CU are left to hide latency; a split also writes and
+// re-reads S partial sums of `pbytes` bytes each (at 4 TB/s).  The split
+// minimises the sum (the larger split on ties), with at least 256 of K per
+// split, at most 256 splits and 2048 workgroups.  Measured on the
+// 4 x 2 x (2592 x 72 x 2592) and 4 x (1296 x 1296 x 5184) products, whose
+// best splits (3 and 4) it picks.
+int split_k(long tb, int K, int BK, int BM, int BN, long mn_batch,
+            int pbytes, double flops_cu, int& kchunk) {
   auto up = [](long x, long m) { return (x + m - 1) / m * m; };
   int best = 1;
-  long best_cost = -1;
+  double best_t = -1.0;
   kchunk = (int)up(K, BK);
   if (K >= 512 && tb < 2048) {
     const long smax = std::min<long>(
@@ -762,9 +768,12 @@ int split_k(long tb, int K, int BK, int& kchunk) {
     for (long s = 1; s <= smax; ++s) {
       const long kc = up((K + s - 1) / s, BK);
       const long se = (K + kc - 1) / kc;
-      const long cost = (tb * se + 255) / 256 * kc;
-      if (best_cost < 0 || cost <= best_cost) {
-        best_cost = cost;
+      const long wg = tb * se;
+      double t = (double)((wg + 255) / 256) * 2.0 * BM * BN * kc /
+                 (0.5 * flops_cu) * (1.0 + 128.0 / wg);
+      if (se > 1) t += (double)se * mn_batch * 2.0 * pbytes / 4e12;
+      if (best_t < 0.0 || t <= best_t) {
+        best_t = t;
         best = (int)se;
         kchunk = (int)kc;
       }
@@ -772,6 +781,11 @@ int split_k(long tb, int K, int BK, int& kchunk) {
   }
   return best;
 }
+
+// per-CU matrix-core peaks (flop/s): FP64, FP32, and BF16x3 (three BF16
+// products per product)
+constexpr double CU_PEAK[3] = {78.6e12 / 256, 157.3e12 / 256,
+                               2.5e15 / 3 / 256};
 
 // Products with at most 4 x 4 outputs per batch entry and a long K (overlaps
 // and norms of whole tensors, K up to 4 D^8): a matrix-core tile would be
@@ -925,7 +939,8 @@ void launch_cfg(Device& dev, const Call& c) {
   const long tm = (c.M + BM - 1) / BM, tn = (c.N + BN - 1) / BN;
   const long tiles = tm * tn;
   int kchunk;
-  int S = split_k(tiles * c.batch, c.K, BK, kchunk);
+  int S = split_k(tiles * c.batch, c.K, BK, BM, BN, (long)c.M * c.N * c.batch,
+                  P == 0 ? 8 : 4, CU_PEAK[P], kchunk);
   // partial sums in the accumulators' type: FP64, or FP32 (FP32 and BF16x3)
   const int64_t npart = (int64_t)S * c.batch * c.M * c.N;
   Tensor part;
@@ -1009,7 +1024,8 @@ void launch_cfg(Device& dev, const Call& c) {
 double tile_cost(const Call& c, int BM, int BN, int BK) {
   const long tiles = (long)((c.M + BM - 1) / BM) * ((c.N + BN - 1) / BN);
   int kchunk;
-  const long S = split_k(tiles * c.batch, c.K, BK, kchunk);
+  const long S = split_k(tiles * c.batch, c.K, BK, BM, BN,
+                         (long)c.M * c.N * c.batch, 4, CU_PEAK[1], kchunk);
   const long wg = tiles * c.batch * S;
   return (double)((wg + 255) / 256) * BM * BN * kchunk;
 }
