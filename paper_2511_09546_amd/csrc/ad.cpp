@@ -10,6 +10,19 @@ Tensor& Tape::grad(const Var& x) {
   return x->g;
 }
 
+// Gradient of x as the target of a product: a first contribution is
+// written (beta 0) into fresh memory instead of added to zeros, which saves
+// the fill and the read of the zeros.
+static Tensor& grad_target(Device& dev, Node* x, double& beta) {
+  if (!x->g.ptr) {
+    x->g = dev.empty(x->v.shape);
+    beta = 0.0;
+  } else {
+    beta = 1.0;
+  }
+  return x->g;
+}
+
 static void parse3(const std::string& spec, std::string& a, std::string& b,
                    std::string& o) {
   const auto c = spec.find(','), ar = spec.find("->");
@@ -27,47 +40,54 @@ Var Tape::einsum(const std::string& spec, const Var& a, const Var& b) {
     parse3(spec, la, lb, lo);
     push([this, a, b, out, la, lb, lo]() {
       if (!has_grad(out)) return;
-      if (a->req)
-        einsum_into(dev, lo + "," + lb + "->" + la, out->g, b->v, grad(a),
-                    1.0, 1.0);
-      if (b->req)
-        einsum_into(dev, la + "," + lo + "->" + lb, a->v, out->g, grad(b),
-                    1.0, 1.0);
+      double beta;
+      if (a->req) {
+        Tensor& ga = grad_target(dev, a.get(), beta);
+        einsum_into(dev, lo + "," + lb + "->" + la, out->g, b->v, ga, 1.0,
+                    beta);
+      }
+      if (b->req) {
+        Tensor& gb = grad_target(dev, b.get(), beta);
+        einsum_into(dev, la + "," + lo + "->" + lb, a->v, out->g, gb, 1.0,
+                    beta);
+      }
     });
   }
   return out;
 }
 
-// target[i] += einsum(spec, first[i], second[i]) for the listed items, in
-// batched launches whose targets are distinct (an item whose target already
-// occurs in the current launch goes to a later one)
+// grad(target[i]) += einsum(spec, first[i], second[i]) for the listed
+// items, in batched launches whose targets are distinct (an item whose
+// target already occurs in the current launch goes to a later one); targets
+// without a gradient yet are written (beta 0), the others accumulated
 static void accumulate_n(Device& dev, const std::string& spec,
                          std::vector<Tensor> first, std::vector<Tensor> second,
-                         std::vector<Tensor> target,
-                         std::vector<const Node*> key) {
+                         std::vector<Node*> target) {
   while (!first.empty()) {
-    std::vector<Tensor> f, s, t, f2, s2, t2;
-    std::vector<const Node*> used, k2;
+    std::vector<Tensor> f[2], s[2], t[2], f2, s2;
+    std::vector<Node*> used, k2;
     for (size_t i = 0; i < first.size(); ++i) {
       bool dup = false;
-      for (const Node* u : used) dup = dup || u == key[i];
+      for (const Node* u : used) dup = dup || u == target[i];
       if (dup) {
         f2.push_back(first[i]);
         s2.push_back(second[i]);
-        t2.push_back(target[i]);
-        k2.push_back(key[i]);
+        k2.push_back(target[i]);
       } else {
-        f.push_back(first[i]);
-        s.push_back(second[i]);
-        t.push_back(target[i]);
-        used.push_back(key[i]);
+        double beta;
+        Tensor& g = grad_target(dev, target[i], beta);
+        const int j = beta != 0.0;
+        f[j].push_back(first[i]);
+        s[j].push_back(second[i]);
+        t[j].push_back(g);
+        used.push_back(target[i]);
       }
     }
-    einsum_into_n(dev, spec, f, s, t, 1.0, 1.0);
+    einsum_into_n(dev, spec, f[0], s[0], t[0], 1.0, 0.0);
+    einsum_into_n(dev, spec, f[1], s[1], t[1], 1.0, 1.0);
     first.swap(f2);
     second.swap(s2);
-    target.swap(t2);
-    key.swap(k2);
+    target.swap(k2);
   }
 }
 
@@ -93,28 +113,25 @@ std::vector<Var> Tape::einsum_n(const std::string& spec,
     std::string la, lb, lo;
     parse3(spec, la, lb, lo);
     push([this, a, b, out, la, lb, lo]() {
-      std::vector<Tensor> f, s, t;
-      std::vector<const Node*> k;
+      std::vector<Tensor> f, s;
+      std::vector<Node*> k;
       for (size_t i = 0; i < out.size(); ++i)
         if (has_grad(out[i]) && a[i]->req) {
           f.push_back(out[i]->g);
           s.push_back(b[i]->v);
-          t.push_back(grad(a[i]));
           k.push_back(a[i].get());
         }
-      accumulate_n(dev, lo + "," + lb + "->" + la, f, s, t, k);
+      accumulate_n(dev, lo + "," + lb + "->" + la, f, s, k);
       f.clear();
       s.clear();
-      t.clear();
       k.clear();
       for (size_t i = 0; i < out.size(); ++i)
         if (has_grad(out[i]) && b[i]->req) {
           f.push_back(a[i]->v);
           s.push_back(out[i]->g);
-          t.push_back(grad(b[i]));
           k.push_back(b[i].get());
         }
-      accumulate_n(dev, la + "," + lo + "->" + lb, f, s, t, k);
+      accumulate_n(dev, la + "," + lo + "->" + lb, f, s, k);
     });
   }
   return out;
