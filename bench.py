@@ -169,7 +169,8 @@ def run(name, prec, steps, warmup, ckpt=0):
     torch.cuda.synchronize()
     elapsed_prof = time.perf_counter() - t1
     prof = {f: ctx.profile_read(f) for f in
-            (fam, binding.PROF_JACOBI, binding.PROF_PERMUTE)}
+            (fam, binding.PROF_JACOBI, binding.PROF_PERMUTE,
+             binding.PROF_NET)}
     ctx.profile(False)
     stats = ctx.stats()
     ctx.close()
@@ -254,6 +255,8 @@ def main():
     ms = sorted(t["ms"] for t in timed)
     p = lambda q: ms[min(len(ms) - 1, int(round(q * (len(ms) - 1))))]  # noqa
     achieved = fl_g / t_g / 1e12 if t_g > 0 else 0.0
+    n_net, t_net, fl_net, _ = head["prof"][binding.PROF_NET]
+    ach_net = fl_net / t_net / 1e12 if t_net > 0 else 0.0
     peak = PEAK_TFLOPS[args.prec]
     n_conv = int(round(sum(t["iters"] for t in timed) / len(timed)))
     value = args.steps / elapsed
@@ -295,7 +298,15 @@ def main():
                      "algorithmic_bytes_per_launch": by_g / max(n_g, 1),
                      "gemm_share_of_step": t_g / head["elapsed_prof"],
                      "measured_over": f"{args.steps} profiled steps after "
-                                      "the timed ones"},
+                                      "the timed ones",
+                     # the same GEMM restricted to the launches of the
+                     # tensor-network contractions (CTMRG moves, energy
+                     # network, their reverse passes): no SVD or
+                     # complement-solve products
+                     "network_contractions": {
+                         "achieved": ach_net, "frac": ach_net / peak,
+                         "launches": n_net,
+                         "share_of_gemm_time": t_net / max(t_g, 1e-30)}},
         "kernel_time_s": {"gemm": t_g, "jacobi": t_jac, "permute": t_perm},
         "svd_stats": head["stats"],
     }

@@ -224,7 +224,11 @@ size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
  * on = 1 the context records HIP events on its stream around every launch
  * of the timed kernel families (clearing earlier records); on = 0 stops.
  * Families: 0 = GEMM (FP64 matrix-core GEMM, all shapes), 1 = Jacobi
- * eigensolver, 2 = permute, 3 = FP32 GEMM, 4 = BF16x3 GEMM.
+ * eigensolver, 2 = permute, 3 = FP32 GEMM, 4 = BF16x3 GEMM, 5 = the GEMM
+ * launches of the tensor-network contractions (double layer, CTMRG moves,
+ * energy network and their reverse passes; any arithmetic, a subset of
+ * 0, 3 and 4: the products of the projector SVD and of the complement
+ * solves are not in it).
  * ipeps_profile_read returns, for one family,
  * the number of launches, their summed device time in seconds and their
  * algorithmic FLOP and byte counts (2 M N K flop; the operand and result

@@ -31,6 +31,7 @@ API_FUNCTIONS = [
     "precond_apply_dev", "ipeps_footprint_bytes",
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
+PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
                    "ipeps_debug_svd_ts", "ipeps_debug_stats",
                    "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time",

@@ -127,7 +127,7 @@ hipEvent_t Profiler::get() {
 }
 
 void Profiler::begin(hipStream_t s, int fam, double flop, double bytes) {
-  Rec r{fam, get(), get(), flop, bytes};
+  Rec r{fam, get(), get(), flop, bytes, net};
   IPEPS_HIP(hipEventRecord(r.a, s));
   recs.push_back(r);
 }
@@ -139,7 +139,9 @@ void Profiler::read(int fam, long* n, double* sec, double* flop,
   long cnt = 0;
   double t = 0.0, f = 0.0, by = 0.0;
   for (auto& r : recs) {
-    if (r.fam != fam) continue;
+    const bool gemm =
+        r.fam == PROF_GEMM || r.fam == PROF_GEMM32 || r.fam == PROF_GEMM16;
+    if (fam == PROF_NET ? !(r.net && gemm) : r.fam != fam) continue;
     IPEPS_HIP(hipEventSynchronize(r.b));
     float ms = 0.f;
     IPEPS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
@@ -273,6 +275,7 @@ void einsum_into_n(Device& dev, const std::string& spec,
   if (ni == 0) return;
   if (Bs.size() != ni || outs.size() != ni)
     throw ArgError("einsum: operand counts differ in " + spec);
+  NetScope net(dev.prof);
   for (size_t i = 1; i < ni; ++i)
     if (As[i].shape != As[0].shape || Bs[i].shape != Bs[0].shape ||
         outs[i].shape != outs[0].shape)

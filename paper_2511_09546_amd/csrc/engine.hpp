@@ -95,7 +95,9 @@ enum ProfFamily {
   PROF_PERMUTE = 2,
   PROF_GEMM32 = 3,   // FP32 matrix-core GEMM
   PROF_GEMM16 = 4,   // BF16x3 matrix-core GEMM
-  PROF_N = 5
+  PROF_NET = 5,      // GEMMs of the network contractions (einsum), any
+                     // arithmetic: a subset of the three GEMM families
+  PROF_N = 6
 };
 
 // Arithmetic of the GEMMs issued on a device (the contraction precision;
@@ -108,7 +110,9 @@ struct Profiler {
     int fam;
     hipEvent_t a, b;
     double flop, bytes;
+    bool net;  // issued by a network contraction
   };
+  bool net = false;  // launches now belong to a network contraction
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   hipEvent_t get();
@@ -136,6 +140,17 @@ struct Device {
   void upload(Tensor& t, const double* host);
   void download(const Tensor& t, double* host);
   void sync();
+};
+
+// Marks the launches of a scope as those of a network contraction (for the
+// PROF_NET profile family) and restores the previous mark.
+struct NetScope {
+  Profiler& p;
+  bool old;
+  explicit NetScope(Profiler& pr) : p(pr), old(pr.net) { p.net = true; }
+  ~NetScope() { p.net = old; }
+  NetScope(const NetScope&) = delete;
+  NetScope& operator=(const NetScope&) = delete;
 };
 
 // Sets the GEMM arithmetic for a scope and restores the previous one.

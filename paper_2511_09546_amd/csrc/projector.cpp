@@ -296,7 +296,13 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       }
       qmul(dev, cp, false, n, chi, n, s1q, s1q32, n, bi, chi, t2w, chi);
       qmul(dev, cp, false, n, chi, n, s2q, s2q32, n, t2r, chi, co, chi);
-      project_out(dev, UVk.ptr, sP, out.ptr, sP, n, chi, 2 * nc);
+      {
+        // the projection is part of the operator: contraction precision,
+        // like the products with the cut matrices (inner products and
+        // residuals of the solve stay FP64)
+        PrecScope ps(dev, cp);
+        project_out(dev, UVk.ptr, sP, out.ptr, sP, n, chi, 2 * nc);
+      }
       col_axpby(dev, nc * 2 * n, chi, 1.0, S.ptr, in.ptr, -1.0, out.ptr,
                 2 * n, b);
     };
@@ -374,7 +380,10 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     }
     const int64_t sH = (int64_t)m4 * chi, sC = (int64_t)m2 * chi;
     // p -= W Phi diag(s_j - lambda)^-1 ((W Phi)^T A_j r)
+    // (the two products of a CG iteration in the contraction precision, as
+    // the operator's; the Galerkin coefficients in FP64)
     auto deflate = [&](const double* r, double* p) {
+      PrecScope ps(dev, cp);
       gemm(dev, true, false, m4, chi, 2 * n, 1.0, Xi.ptr, m4, sXi, r, chi, s2,
            0.0, Hd.ptr, chi, sH, nc);
       defl_coef(dev, 1, S.ptr, kp, lamK.ptr, chi, m2, b, Hd.ptr, Cf.ptr, nc);

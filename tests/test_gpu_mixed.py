@@ -140,3 +140,27 @@ def test_bf16x3_gemm_error_bound(tA, tB, M, N, K):
     _say(f"  max err/bound {np.max(err / bound):.3f}")
     assert np.all(err <= bound)
     assert np.max(err) > 0.0
+
+
+def test_profile_network_family_is_a_subset():
+    """Family 5 (GEMMs of the network contractions) counts a proper subset of
+    the FP32 GEMM launches: the projector-SVD and complement-solve products
+    are FP32 GEMMs outside it."""
+    _say("profile families d2chi8 FP32")
+    w = inputs.WORKLOADS["d2chi8"]
+    A = inputs.workload_state("d2chi8")
+    terms = inputs.workload_terms("d2chi8")
+    o = binding.default_opts()
+    o.prec = binding.FP32
+    with binding.Context(A, w["chi"], opts=o) as ctx:
+        ctx.profile(True)
+        ctx.converge(w["tol"], w["n_iter"])
+        ctx.energy_grad(terms, grad=True)
+        n32, t32, f32, _ = ctx.profile_read(binding.PROF_GEMM32)
+        nn, tn, fn, _ = ctx.profile_read(binding.PROF_NET)
+        n64, _, _, _ = ctx.profile_read(binding.PROF_GEMM)
+        ctx.profile(False)
+    _say(f"  fp32 {n32} launches, network {nn}, fp64 {n64}")
+    assert 0 < nn < n32
+    assert 0 < fn < f32 and 0 < tn < t32
+    assert n64 > 0  # the SVD's own products stay FP64
