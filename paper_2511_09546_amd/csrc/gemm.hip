@@ -383,6 +383,190 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
       }
 }
 
+// FP32 products with direct global-to-LDS loads (`global_load_lds_dwordx4`:
+// lane l of a wave writes its 16 bytes at LDS base + 16 l, checked on
+// gfx950), for FP64 operands whose contiguous extent and leading dimension
+// are even and whose addresses are 16-byte aligned (`lds_ok`).  The tiles
+// stay FP64 in LDS and are rounded to FP32 when read into the MFMA
+// operands, so the loads need no registers and no LDS stores: the loads of
+// slice t + 1 are in flight while the MFMAs of slice t run, without the
+// register staging of gemm_kernel.  128 x 128 tiles, 2 x 2 waves, BK = 16,
+// two LDS stages of 2 x 16 KB.  The products, their order and the FP32
+// rounding are those of gemm_kernel's 128 x 128 FP32 instantiation.
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int NS, bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
+    int M, int N, int K, double alpha, const void* __restrict__ Av,
+    long lda, long sA, const double* __restrict__ B0, long ldb, long sB,
+    double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
+    int splits, int kchunk, void* __restrict__ part, int use_ptrs,
+    PtrArgs ptrs) {
+  constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2;
+  constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
+  constexpr int TE = BM * BK;  // doubles per operand tile (= BK * BN)
+  __shared__ __attribute__((aligned(16))) double As0[TE], Bs0[TE];
+  __shared__ __attribute__((aligned(16))) double As1[TE], Bs1[TE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int gx = gridDim.x;
+  const int total = gx * gridDim.y;
+  const int lin = blockIdx.x + gx * blockIdx.y;
+  const int q8 = total / 8, r8 = total % 8, xcd = lin % 8;
+  const int vid = xcd * q8 + min(xcd, r8) + lin / 8;
+  const int bx = vid % gx, by = vid / gx;
+  const int bz = by / splits, sp = by % splits;
+  const double* A = use_ptrs ? (const double*)ptrs.a[bz]
+                              : (const double*)Av + (long)bz * sA;
+  const double* B = use_ptrs ? ptrs.b[bz] : B0 + (long)bz * sB;
+  const int m0 = (bx / tiles_n) * BM;
+  const int n0 = (bx % tiles_n) * BN;
+  const int kbeg = sp * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  // Each wave moves 4 chunks of 64 x 16 bytes per operand and slice: chunk
+  // index L = 64 (4 wave + j) + lane of the operand's tile.  K-contiguous
+  // tiles (A not transposed, B transposed) hold row r's 8 pairs of K values
+  // at chunks 8 r + (c ^ (r & 7)) (the XOR spreads one K column of 16 rows
+  // over the banks); MN-contiguous tiles hold K row k at chunks 64 k + cc.
+  // Rows and K beyond the operand are clamped into it (finite values that
+  // only reach discarded outputs, or are zeroed on A's side below).
+  long aoff[4], boff[4];
+  int ak[4], bk[4];  // K offset of the chunk within the slice
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int L = 64 * (4 * wave + j) + lane;
+    if (!TA) {
+      const int r = L >> 3, c = (L & 7) ^ (r & 7);
+      aoff[j] = (long)min(m0 + r, M - 1) * lda;
+      ak[j] = 2 * c;
+    } else {
+      const int k = L >> 6, cc = L & 63;
+      aoff[j] = min(m0 + 2 * cc, M - 2);
+      ak[j] = k;
+    }
+    if (TB) {
+      const int r = L >> 3, c = (L & 7) ^ (r & 7);
+      boff[j] = (long)min(n0 + r, N - 1) * ldb;
+      bk[j] = 2 * c;
+    } else {
+      const int k = L >> 6, cc = L & 63;
+      boff[j] = min(n0 + 2 * cc, N - 2);
+      bk[j] = k;
+    }
+  }
+  auto issue = [&](double* as, double* bs, int kb) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double* ga;
+      if (!TA)
+        ga = A + aoff[j] + min(kb + ak[j], K - 2);
+      else
+        ga = A + (long)min(kb + ak[j], K - 1) * lda + aoff[j];
+      __builtin_amdgcn_global_load_lds((const void*)ga,
+                                       (lds_void*)(as + 128 * (4 * wave + j)),
+                                       16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double* gb;
+      if (TB)
+        gb = B + boff[j] + min(kb + bk[j], K - 2);
+      else
+        gb = B + (long)min(kb + bk[j], K - 1) * ldb + boff[j];
+      __builtin_amdgcn_global_load_lds((const void*)gb,
+                                       (lds_void*)(bs + 128 * (4 * wave + j)),
+                                       16, 0, 0);
+    }
+  };
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+  // all MFMA operands of one slice, read from LDS and rounded to FP32
+  float fa[BK / 4][TM], fb[BK / 4][TN];
+  auto fetch = [&](const double* as, const double* bs, int kb) {
+    const int klim = kend - kb;
+#pragma unroll
+    for (int s4 = 0; s4 < BK / 4; ++s4) {
+      const int kq = 4 * s4 + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int r = wm * WTM + i * 16 + (lane & 15);
+        const double v = !TA ? as[(r * 8 + ((kq >> 1) ^ (r & 7))) * 2 + (kq & 1)]
+                             : as[kq * BM + r];
+        fa[s4][i] = kq < klim ? (float)v : 0.0f;
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn * WTN + j * 16 + (lane & 15);
+        const double v = TB ? bs[(n * 8 + ((kq >> 1) ^ (n & 7))) * 2 + (kq & 1)]
+                            : bs[kq * BN + n];
+        fb[s4][j] = (float)v;
+      }
+    }
+  };
+  auto mma = [&]() {
+#pragma unroll
+    for (int s4 = 0; s4 < BK / 4; ++s4)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              fa[s4][i], fb[s4][j], acc[i][j], 0, 0, 0);
+  };
+  // Two stages.  Slice t: wait for its loads (each wave its own, then a
+  // barrier), read all its operands into registers, start the loads of
+  // slice t + 1 into the other stage (every wave has finished reading that
+  // stage: it passed this barrier after its reads of slice t - 1), then the
+  // MFMAs of slice t run while those loads are in flight.
+  static_assert(NS == 2, "two stages");
+  auto bar = []() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
+  constexpr int W_VM0 = 0xf70, W_LGKM0 = 0xc07f;
+  const int T = kbeg < kend ? (kend - kbeg + BK - 1) / BK : 0;
+  if (T > 0) issue(As0, Bs0, kbeg);
+  for (int t = 0; t < T; t += 2) {
+    __builtin_amdgcn_s_waitcnt(W_VM0);
+    bar();
+    fetch(As0, Bs0, kbeg + t * BK);
+    __builtin_amdgcn_s_waitcnt(W_LGKM0);
+    if (t + 1 < T) issue(As1, Bs1, kbeg + (t + 1) * BK);
+    mma();
+    if (t + 1 >= T) break;
+    __builtin_amdgcn_s_waitcnt(W_VM0);
+    bar();
+    fetch(As1, Bs1, kbeg + (t + 1) * BK);
+    __builtin_amdgcn_s_waitcnt(W_LGKM0);
+    if (t + 2 < T) issue(As0, Bs0, kbeg + (t + 2) * BK);
+    mma();
+  }
+  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  float* pout = (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          if (splits == 1) {
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
+            out[(long)row * ldc + col] = v;
+          } else {
+            pout[(long)row * N + col] = acc[i][j][r];
+          }
+        }
+      }
+}
+
 // part layout [S][batch][M][N] (FP64, or FP32 for FP32 accumulators);
 // C[b] = alpha sum_s part[s][b] + beta C[b], summed in FP64 in the order of s
 template <typename PT>
@@ -925,8 +1109,24 @@ void launch_small(Device& dev, const Call& c) {
   IPEPS_HIP(hipGetLastError());
 }
 
+// direct-load conditions: 16-byte aligned operands whose contiguous extent
+// and leading dimension are even
+bool lds_ok(const Call& c) {
+  auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  const bool ka = !c.tA, kb = c.tB;
+  if ((ka ? c.K : c.M) % 2 || (kb ? c.K : c.N) % 2) return false;
+  if (c.lda % 2 || c.ldb % 2 || c.K < 2 || c.M < 2 || c.N < 2) return false;
+  if (c.ptrs) {
+    for (int i = 0; i < c.batch; ++i)
+      if (!al(c.ptrs->a[i]) || !al(c.ptrs->b[i])) return false;
+  } else {
+    if (!al(c.A) || !al(c.B) || c.sA % 2 || c.sB % 2) return false;
+  }
+  return true;
+}
+
 // P: 0 = FP64, 1 = FP32, 2 = BF16x3 arithmetic
-template <int BM, int BN, int WM, int WN, int P>
+template <int BM, int BN, int WM, int WN, int P, bool LDSK = false>
 void launch_cfg(Device& dev, const Call& c) {
   if constexpr (P == 2) {
     if (presplit_pays<BM, BN>(c)) {
@@ -965,6 +1165,13 @@ void launch_cfg(Device& dev, const Call& c) {
                        c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.beta,
                        c.C, c.ldc, c.sC, (int)tn, S, kchunk, part.ptr, up, pa);
   };
+  if constexpr (LDSK) {
+    static_assert(P == 1 && BM == 128 && BN == 128, "LDS kernel: FP32 128x128");
+    if (!c.tA && !c.tB) go(gemm_f32_lds_kernel<2, false, false>);
+    if (c.tA && !c.tB) go(gemm_f32_lds_kernel<2, true, false>);
+    if (!c.tA && c.tB) go(gemm_f32_lds_kernel<2, false, true>);
+    if (c.tA && c.tB) go(gemm_f32_lds_kernel<2, true, true>);
+  }
   auto pick = [&](auto ti) {
     using TI = decltype(ti);
     if constexpr (P == 2) {
@@ -987,7 +1194,8 @@ void launch_cfg(Device& dev, const Call& c) {
         go(gemm_kernel<TI, BM, BN, WM, WN, true, true, F32, false, BK>);
     }
   };
-  if constexpr (P == 0) {
+  if constexpr (LDSK) {
+  } else if constexpr (P == 0) {
     pick(double());
   } else {
     if (c.a32)
@@ -1047,9 +1255,16 @@ void dispatch_prec(Device& dev, const Call& c) {
       launch_cfg<128, 96, 4, 1, P>(dev, c);
     else if constexpr (P == 1) {
       // FP32: 128 x 144 tiles (4 waves of 32 x 144; D^4 = 1296 and its
-      // multiples by D^2 are multiples of 144) when the model below says
-      // they finish first
-      if (tile_cost(c, 128, 144, 16) * 21 < tile_cost(c, 128, 128, 16) * 20)
+      // multiples by D^2 are multiples of 144) or 128 x 128 tiles, the
+      // latter with direct LDS loads where the operands allow; by the time
+      // model, with the measured handicaps of the 144-wide tile (two waves
+      // per SIMD, x 1.05) and the advantage of the direct loads (x 0.82)
+      const double c128 = tile_cost(c, 128, 128, 16);
+      const double c144 = tile_cost(c, 128, 144, 16) * 1.05;
+      const bool direct = c.K >= 256 && !c.a32 && lds_ok(c);
+      if (direct && c128 * 0.82 <= c144)
+        launch_cfg<128, 128, 2, 2, P, true>(dev, c);
+      else if (c144 < c128)
         launch_cfg<128, 144, 4, 1, P>(dev, c);
       else
         launch_cfg<128, 128, 2, 2, P>(dev, c);

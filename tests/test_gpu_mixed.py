@@ -46,7 +46,12 @@ def _say(msg):
                                          (1, 0, 530, 600, 1000),
                                          (0, 1, 530, 600, 1000),
                                          (1, 1, 530, 600, 1000),
-                                         (0, 0, 517, 613, 131)])
+                                         (0, 0, 517, 613, 131),
+                                         # direct LDS loads (even extents,
+                                         # K >= 256), split K, ragged tiles
+                                         (0, 0, 1296, 1296, 512),
+                                         (0, 0, 260, 258, 4000),
+                                         (1, 1, 130, 386, 2050)])
 def test_fp32_gemm_error_bound(tA, tB, M, N, K):
     _say(f"fp32 gemm {tA}{tB} {M}x{N}x{K}")
     rng = np.random.default_rng(M + N + K)
