@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <cstring>
 #include <type_traits>
 
@@ -395,18 +397,27 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
 // rounding are those of gemm_kernel's 128 x 128 FP32 instantiation.
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <int NS, bool TA, bool TB>
+// LDS bytes of the two stages of a 128 x BN tile
+constexpr size_t lds_stage_bytes(int BN) { return 2 * 8 * 16 * (128 + BN); }
+
+template <int BN, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
     int M, int N, int K, double alpha, const void* __restrict__ Av,
     long lda, long sA, const double* __restrict__ B0, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
     int splits, int kchunk, void* __restrict__ part, int use_ptrs,
     PtrArgs ptrs) {
-  constexpr int BM = 128, BN = 128, BK = 16, WM = 2, WN = 2;
+  static_assert(WM * WN == 4, "4 waves");
+  constexpr int BM = 128, BK = 16, NS = 2;
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
-  constexpr int TE = BM * BK;  // doubles per operand tile (= BK * BN)
-  __shared__ __attribute__((aligned(16))) double As0[TE], Bs0[TE];
-  __shared__ __attribute__((aligned(16))) double As1[TE], Bs1[TE];
+  constexpr int TEA = BM * BK, TEB = BK * BN;  // doubles per operand tile
+  constexpr int NIB = TEB / 128;               // 1 KB loads of a B tile
+  constexpr int NBW = (NIB + 3) / 4;           // per wave (some idle)
+  extern __shared__ __attribute__((aligned(16))) double lds_tiles[];
+  double* const As0 = lds_tiles;
+  double* const Bs0 = As0 + TEA;
+  double* const As1 = Bs0 + TEB;
+  double* const Bs1 = As1 + TEA;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int gx = gridDim.x;
@@ -423,15 +434,16 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
   const int n0 = (bx % tiles_n) * BN;
   const int kbeg = sp * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  // Each wave moves 4 chunks of 64 x 16 bytes per operand and slice: chunk
-  // index L = 64 (4 wave + j) + lane of the operand's tile.  K-contiguous
-  // tiles (A not transposed, B transposed) hold row r's 8 pairs of K values
-  // at chunks 8 r + (c ^ (r & 7)) (the XOR spreads one K column of 16 rows
-  // over the banks); MN-contiguous tiles hold K row k at chunks 64 k + cc.
-  // Rows and K beyond the operand are clamped into it (finite values that
-  // only reach discarded outputs, or are zeroed on A's side below).
-  long aoff[4], boff[4];
-  int ak[4], bk[4];  // K offset of the chunk within the slice
+  // A tile loads: 16 of 64 x 16 bytes, wave w issuing chunks
+  // L = 64 (4 w + j) + lane; B tile loads: BN / 8 of them, wave w issuing
+  // q = w + 4 j.  K-contiguous tiles (A not transposed, B transposed) hold
+  // row r's 8 pairs of K values at chunks 8 r + (c ^ (r & 7)) (the XOR
+  // spreads one K column of 16 rows over the banks); MN-contiguous tiles
+  // hold K row k at chunks (X / 2) k + cc (X = BM or BN).  Rows and K beyond
+  // the operand are clamped into it (finite values that only reach
+  // discarded outputs, or are zeroed on A's side in fetch).
+  long aoff[4], boff[NBW];
+  int ak[4], bk[NBW];  // K offset of the chunk within the slice
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int L = 64 * (4 * wave + j) + lane;
@@ -440,16 +452,20 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
       aoff[j] = (long)min(m0 + r, M - 1) * lda;
       ak[j] = 2 * c;
     } else {
-      const int k = L >> 6, cc = L & 63;
+      const int k = L / (BM / 2), cc = L % (BM / 2);
       aoff[j] = min(m0 + 2 * cc, M - 2);
       ak[j] = k;
     }
+  }
+#pragma unroll
+  for (int j = 0; j < NBW; ++j) {
+    const int L = 64 * min(wave + 4 * j, NIB - 1) + lane;
     if (TB) {
       const int r = L >> 3, c = (L & 7) ^ (r & 7);
       boff[j] = (long)min(n0 + r, N - 1) * ldb;
       bk[j] = 2 * c;
     } else {
-      const int k = L >> 6, cc = L & 63;
+      const int k = L / (BN / 2), cc = L % (BN / 2);
       boff[j] = min(n0 + 2 * cc, N - 2);
       bk[j] = k;
     }
@@ -467,15 +483,17 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
                                        16, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double* gb;
-      if (TB)
-        gb = B + boff[j] + min(kb + bk[j], K - 2);
-      else
-        gb = B + (long)min(kb + bk[j], K - 1) * ldb + boff[j];
-      __builtin_amdgcn_global_load_lds((const void*)gb,
-                                       (lds_void*)(bs + 128 * (4 * wave + j)),
-                                       16, 0, 0);
+    for (int j = 0; j < NBW; ++j) {
+      if (wave + 4 * j < NIB) {  // wave-uniform
+        const double* gb;
+        if (TB)
+          gb = B + boff[j] + min(kb + bk[j], K - 2);
+        else
+          gb = B + (long)min(kb + bk[j], K - 1) * ldb + boff[j];
+        __builtin_amdgcn_global_load_lds(
+            (const void*)gb, (lds_void*)(bs + 128 * (wave + 4 * j)), 16, 0,
+            0);
+      }
     }
   };
   f32x4 acc[TM][TN];
@@ -1109,6 +1127,19 @@ void launch_small(Device& dev, const Call& c) {
   IPEPS_HIP(hipGetLastError());
 }
 
+// Raises a kernel's dynamic LDS limit to `bytes` once (contexts on several
+// host threads may get here together).
+void allow_dyn_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& have = done[fn];
+  if (bytes <= have) return;
+  IPEPS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes));
+  have = bytes;
+}
+
 // direct-load conditions: 16-byte aligned operands whose contiguous extent
 // and leading dimension are even
 bool lds_ok(const Call& c) {
@@ -1166,11 +1197,19 @@ void launch_cfg(Device& dev, const Call& c) {
                        c.C, c.ldc, c.sC, (int)tn, S, kchunk, part.ptr, up, pa);
   };
   if constexpr (LDSK) {
-    static_assert(P == 1 && BM == 128 && BN == 128, "LDS kernel: FP32 128x128");
-    if (!c.tA && !c.tB) go(gemm_f32_lds_kernel<2, false, false>);
-    if (c.tA && !c.tB) go(gemm_f32_lds_kernel<2, true, false>);
-    if (!c.tA && c.tB) go(gemm_f32_lds_kernel<2, false, true>);
-    if (c.tA && c.tB) go(gemm_f32_lds_kernel<2, true, true>);
+    static_assert(P == 1 && BM == 128, "LDS kernel: FP32, 128 rows");
+    constexpr size_t lb = lds_stage_bytes(BN);
+    auto gol = [&](auto kern) {
+      allow_dyn_lds((const void*)kern, lb);
+      hipLaunchKernelGGL(kern, grid, dim3(256), lb, dev.stream, c.M, c.N,
+                         c.K, c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB,
+                         c.beta, c.C, c.ldc, c.sC, (int)tn, S, kchunk,
+                         part.ptr, up, pa);
+    };
+    if (!c.tA && !c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, false, false>);
+    if (c.tA && !c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, true, false>);
+    if (!c.tA && c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, false, true>);
+    if (c.tA && c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, true, true>);
   }
   auto pick = [&](auto ti) {
     using TI = decltype(ti);
@@ -1260,11 +1299,13 @@ void dispatch_prec(Device& dev, const Call& c) {
       // model, with the measured handicaps of the 144-wide tile (two waves
       // per SIMD, x 1.05) and the advantage of the direct loads (x 0.82)
       const double c128 = tile_cost(c, 128, 128, 16);
-      const double c144 = tile_cost(c, 128, 144, 16) * 1.05;
+      const double c144 = tile_cost(c, 128, 144, 16);
       const bool direct = c.K >= 256 && !c.a32 && lds_ok(c);
-      if (direct && c128 * 0.82 <= c144)
+      if (direct && c144 < c128)
+        launch_cfg<128, 144, 4, 1, P, true>(dev, c);
+      else if (direct)
         launch_cfg<128, 128, 2, 2, P, true>(dev, c);
-      else if (c144 < c128)
+      else if (c144 * 1.05 < c128)
         launch_cfg<128, 144, 4, 1, P>(dev, c);
       else
         launch_cfg<128, 128, 2, 2, P>(dev, c);

@@ -51,7 +51,12 @@ def _say(msg):
                                          # K >= 256), split K, ragged tiles
                                          (0, 0, 1296, 1296, 512),
                                          (0, 0, 260, 258, 4000),
-                                         (1, 1, 130, 386, 2050)])
+                                         (1, 1, 130, 386, 2050),
+                                         # the same with 128 x 144 tiles
+                                         (0, 0, 300, 288, 512),
+                                         (1, 0, 260, 432, 600),
+                                         (0, 1, 260, 432, 600),
+                                         (1, 1, 260, 432, 600)])
 def test_fp32_gemm_error_bound(tA, tB, M, N, K):
     _say(f"fp32 gemm {tA}{tB} {M}x{N}x{K}")
     rng = np.random.default_rng(M + N + K)
