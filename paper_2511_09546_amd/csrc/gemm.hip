@@ -397,10 +397,13 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
 // rounding are those of gemm_kernel's 128 x 128 FP32 instantiation.
 typedef __attribute__((address_space(3))) void lds_void;
 
-// LDS bytes of the two stages of a 128 x BN tile
-constexpr size_t lds_stage_bytes(int BN) { return 2 * 8 * 16 * (128 + BN); }
+// LDS bytes of the two stages of a 128 x BN tile with A stored in TI
+template <typename TI>
+constexpr size_t lds_stage_bytes(int BN) {
+  return 2 * 16 * (128 * sizeof(TI) + 8 * BN);
+}
 
-template <int BN, int WM, int WN, bool TA, bool TB>
+template <typename TI, int BN, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
     int M, int N, int K, double alpha, const void* __restrict__ Av,
     long lda, long sA, const double* __restrict__ B0, long ldb, long sB,
@@ -410,14 +413,19 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
   static_assert(WM * WN == 4, "4 waves");
   constexpr int BM = 128, BK = 16, NS = 2;
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
-  constexpr int TEA = BM * BK, TEB = BK * BN;  // doubles per operand tile
+  constexpr int TEA = BM * BK, TEB = BK * BN;  // elements per operand tile
+  constexpr int EA = 16 / sizeof(TI);          // A elements per 16 bytes
+  constexpr int CA = BK / EA;                  // chunks per K row of A
+  constexpr int NIA = TEA / (64 * EA);         // 1 KB loads of an A tile
+  constexpr int NAW = NIA / 4;                 // per wave
   constexpr int NIB = TEB / 128;               // 1 KB loads of a B tile
   constexpr int NBW = (NIB + 3) / 4;           // per wave (some idle)
+  static_assert(NIA % 4 == 0, "A loads per wave");
   extern __shared__ __attribute__((aligned(16))) double lds_tiles[];
-  double* const As0 = lds_tiles;
-  double* const Bs0 = As0 + TEA;
-  double* const As1 = Bs0 + TEB;
-  double* const Bs1 = As1 + TEA;
+  TI* const As0 = (TI*)lds_tiles;
+  double* const Bs0 = (double*)(As0 + TEA);
+  TI* const As1 = (TI*)(Bs0 + TEB);
+  double* const Bs1 = (double*)(As1 + TEA);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int gx = gridDim.x;
@@ -427,33 +435,33 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
   const int vid = xcd * q8 + min(xcd, r8) + lin / 8;
   const int bx = vid % gx, by = vid / gx;
   const int bz = by / splits, sp = by % splits;
-  const double* A = use_ptrs ? (const double*)ptrs.a[bz]
-                              : (const double*)Av + (long)bz * sA;
+  const TI* A = use_ptrs ? (const TI*)ptrs.a[bz] : (const TI*)Av + (long)bz * sA;
   const double* B = use_ptrs ? ptrs.b[bz] : B0 + (long)bz * sB;
   const int m0 = (bx / tiles_n) * BM;
   const int n0 = (bx % tiles_n) * BN;
   const int kbeg = sp * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  // A tile loads: 16 of 64 x 16 bytes, wave w issuing chunks
-  // L = 64 (4 w + j) + lane; B tile loads: BN / 8 of them, wave w issuing
-  // q = w + 4 j.  K-contiguous tiles (A not transposed, B transposed) hold
-  // row r's 8 pairs of K values at chunks 8 r + (c ^ (r & 7)) (the XOR
-  // spreads one K column of 16 rows over the banks); MN-contiguous tiles
-  // hold K row k at chunks (X / 2) k + cc (X = BM or BN).  Rows and K beyond
-  // the operand are clamped into it (finite values that only reach
-  // discarded outputs, or are zeroed on A's side in fetch).
-  long aoff[4], boff[NBW];
-  int ak[4], bk[NBW];  // K offset of the chunk within the slice
+  // Loads of 64 x 16 bytes: wave w issues A loads q = w + 4 j (NIA of
+  // them) and B loads q = w + 4 j (NIB), lane l taking chunk L = 64 q + l
+  // of the tile.  K-contiguous tiles (A not transposed, B transposed) hold
+  // row r's K values in C chunks (C = 16 / elements per chunk) at chunks
+  // C r + (c ^ (r mod C)) (the XOR spreads one K column of consecutive rows
+  // over the banks); MN-contiguous tiles hold K row k at chunks X k / E + cc
+  // (X = BM or BN, E elements per chunk).  Rows and K beyond the operand
+  // are clamped into it (finite values that only reach discarded outputs,
+  // or are zeroed on A's side in fetch).
+  long aoff[NAW], boff[NBW];
+  int ak[NAW], bk[NBW];  // K offset of the chunk within the slice
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int L = 64 * (4 * wave + j) + lane;
+  for (int j = 0; j < NAW; ++j) {
+    const int L = 64 * (wave + 4 * j) + lane;
     if (!TA) {
-      const int r = L >> 3, c = (L & 7) ^ (r & 7);
+      const int r = L / CA, c = (L % CA) ^ (r % CA);
       aoff[j] = (long)min(m0 + r, M - 1) * lda;
-      ak[j] = 2 * c;
+      ak[j] = EA * c;
     } else {
-      const int k = L / (BM / 2), cc = L % (BM / 2);
-      aoff[j] = min(m0 + 2 * cc, M - 2);
+      const int k = L / (BM / EA), cc = L % (BM / EA);
+      aoff[j] = min(m0 + EA * cc, M - EA);
       ak[j] = k;
     }
   }
@@ -470,17 +478,17 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
       bk[j] = k;
     }
   }
-  auto issue = [&](double* as, double* bs, int kb) {
+  auto issue = [&](TI* as, double* bs, int kb) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double* ga;
+    for (int j = 0; j < NAW; ++j) {
+      const TI* ga;
       if (!TA)
-        ga = A + aoff[j] + min(kb + ak[j], K - 2);
+        ga = A + aoff[j] + min(kb + ak[j], K - EA);
       else
         ga = A + (long)min(kb + ak[j], K - 1) * lda + aoff[j];
-      __builtin_amdgcn_global_load_lds((const void*)ga,
-                                       (lds_void*)(as + 128 * (4 * wave + j)),
-                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds(
+          (const void*)ga, (lds_void*)(as + 64 * EA * (wave + 4 * j)), 16, 0,
+          0);
     }
 #pragma unroll
     for (int j = 0; j < NBW; ++j) {
@@ -503,7 +511,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
   // all MFMA operands of one slice, read from LDS and rounded to FP32
   float fa[BK / 4][TM], fb[BK / 4][TN];
-  auto fetch = [&](const double* as, const double* bs, int kb) {
+  auto fetch = [&](const TI* as, const double* bs, int kb) {
     const int klim = kend - kb;
 #pragma unroll
     for (int s4 = 0; s4 < BK / 4; ++s4) {
@@ -511,8 +519,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int r = wm * WTM + i * 16 + (lane & 15);
-        const double v = !TA ? as[(r * 8 + ((kq >> 1) ^ (r & 7))) * 2 + (kq & 1)]
-                             : as[kq * BM + r];
+        const TI v = !TA ? as[(r * CA + ((kq / EA) ^ (r % CA))) * EA + kq % EA]
+                         : as[kq * BM + r];
         fa[s4][i] = kq < klim ? (float)v : 0.0f;
       }
 #pragma unroll
@@ -1144,14 +1152,15 @@ void allow_dyn_lds(const void* fn, size_t bytes) {
 // and leading dimension are even
 bool lds_ok(const Call& c) {
   auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-  const bool ka = !c.tA, kb = c.tB;
-  if ((ka ? c.K : c.M) % 2 || (kb ? c.K : c.N) % 2) return false;
-  if (c.lda % 2 || c.ldb % 2 || c.K < 2 || c.M < 2 || c.N < 2) return false;
+  const int ea = c.a32 ? 4 : 2;  // A elements per 16 bytes
+  const int xa = c.tA ? c.M : c.K, xb = c.tB ? c.K : c.N;
+  if (xa % ea || xb % 2 || c.lda % ea || c.ldb % 2) return false;
+  if (c.K < 4 || c.M < 4 || c.N < 2) return false;
   if (c.ptrs) {
     for (int i = 0; i < c.batch; ++i)
       if (!al(c.ptrs->a[i]) || !al(c.ptrs->b[i])) return false;
   } else {
-    if (!al(c.A) || !al(c.B) || c.sA % 2 || c.sB % 2) return false;
+    if (!al(c.A) || !al(c.B) || c.sA % ea || c.sB % 2) return false;
   }
   return true;
 }
@@ -1198,18 +1207,29 @@ void launch_cfg(Device& dev, const Call& c) {
   };
   if constexpr (LDSK) {
     static_assert(P == 1 && BM == 128, "LDS kernel: FP32, 128 rows");
-    constexpr size_t lb = lds_stage_bytes(BN);
-    auto gol = [&](auto kern) {
+    auto gol = [&](auto kern, size_t lb) {
       allow_dyn_lds((const void*)kern, lb);
       hipLaunchKernelGGL(kern, grid, dim3(256), lb, dev.stream, c.M, c.N,
                          c.K, c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB,
                          c.beta, c.C, c.ldc, c.sC, (int)tn, S, kchunk,
                          part.ptr, up, pa);
     };
-    if (!c.tA && !c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, false, false>);
-    if (c.tA && !c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, true, false>);
-    if (!c.tA && c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, false, true>);
-    if (c.tA && c.tB) gol(gemm_f32_lds_kernel<BN, WM, WN, true, true>);
+    auto pickl = [&](auto ti) {
+      using TI = decltype(ti);
+      constexpr size_t lb = lds_stage_bytes<TI>(BN);
+      if (!c.tA && !c.tB)
+        gol(gemm_f32_lds_kernel<TI, BN, WM, WN, false, false>, lb);
+      if (c.tA && !c.tB)
+        gol(gemm_f32_lds_kernel<TI, BN, WM, WN, true, false>, lb);
+      if (!c.tA && c.tB)
+        gol(gemm_f32_lds_kernel<TI, BN, WM, WN, false, true>, lb);
+      if (c.tA && c.tB)
+        gol(gemm_f32_lds_kernel<TI, BN, WM, WN, true, true>, lb);
+    };
+    if (c.a32)
+      pickl(float());
+    else
+      pickl(double());
   }
   auto pick = [&](auto ti) {
     using TI = decltype(ti);
@@ -1282,14 +1302,20 @@ void dispatch_prec(Device& dev, const Call& c) {
   if (c.M >= 128) {
     // narrow N (chi-wide blocks of the projector SVD and the complement
     // solves): 4 waves stacked along M, tile width rounded up to 16
+    // (FP32: direct LDS loads where the operands allow)
+    const bool direct = P == 1 && c.K >= 256 && lds_ok(c);
     if (c.N <= 48)
-      launch_cfg<128, 48, 4, 1, P>(dev, c);
+      direct ? launch_cfg<128, 48, 4, 1, P, P == 1>(dev, c)
+             : launch_cfg<128, 48, 4, 1, P>(dev, c);
     else if (c.N <= 64)
-      launch_cfg<128, 64, 4, 1, P>(dev, c);
+      direct ? launch_cfg<128, 64, 4, 1, P, P == 1>(dev, c)
+             : launch_cfg<128, 64, 4, 1, P>(dev, c);
     else if (c.N <= 80)
-      launch_cfg<128, 80, 4, 1, P>(dev, c);
+      direct ? launch_cfg<128, 80, 4, 1, P, P == 1>(dev, c)
+             : launch_cfg<128, 80, 4, 1, P>(dev, c);
     else if (c.N <= 96)
-      launch_cfg<128, 96, 4, 1, P>(dev, c);
+      direct ? launch_cfg<128, 96, 4, 1, P, P == 1>(dev, c)
+             : launch_cfg<128, 96, 4, 1, P>(dev, c);
     else if constexpr (P == 2)  // BF16x3: 128 x 128 would spill registers
       launch_cfg<128, 96, 4, 1, P>(dev, c);
     else if constexpr (P == 1) {
@@ -1300,7 +1326,7 @@ void dispatch_prec(Device& dev, const Call& c) {
       // per SIMD, x 1.05) and the advantage of the direct loads (x 0.82)
       const double c128 = tile_cost(c, 128, 128, 16);
       const double c144 = tile_cost(c, 128, 144, 16);
-      const bool direct = c.K >= 256 && !c.a32 && lds_ok(c);
+      const bool direct = c.K >= 256 && lds_ok(c);
       if (direct && c144 < c128)
         launch_cfg<128, 144, 4, 1, P, true>(dev, c);
       else if (direct)

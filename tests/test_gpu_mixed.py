@@ -56,7 +56,11 @@ def _say(msg):
                                          (0, 0, 300, 288, 512),
                                          (1, 0, 260, 432, 600),
                                          (0, 1, 260, 432, 600),
-                                         (1, 1, 260, 432, 600)])
+                                         (1, 1, 260, 432, 600),
+                                         # narrow direct-load tiles
+                                         (0, 0, 300, 72, 2592),
+                                         (1, 0, 300, 96, 1000),
+                                         (0, 1, 260, 40, 600)])
 def test_fp32_gemm_error_bound(tA, tB, M, N, K):
     _say(f"fp32 gemm {tA}{tB} {M}x{N}x{K}")
     rng = np.random.default_rng(M + N + K)
