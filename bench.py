@@ -291,8 +291,8 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": measured_traffic(args.prec),
-                     "kernel": f"gemm_kernel ({args.prec} MFMA, all tile "
-                               "shapes)",
+                     "kernel": f"{args.prec} matrix-core GEMM (gemm_kernel "
+                               "and gemm_f32_lds_kernel, all tile shapes)",
                      "launches": n_g,
                      "avg_launch_us": 1e6 * t_g / max(n_g, 1),
                      "algorithmic_bytes_per_launch": by_g / max(n_g, 1),
