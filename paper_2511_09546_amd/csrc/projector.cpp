@@ -173,13 +173,8 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     col_axpby(dev, nc * n, chi, 1.0, w.ptr, Tb.ptr, 0.0, Tbw.ptr, n, chi);
     const auto pbw = offsets<const double*>(Pbw.ptr, sP, nc);
     const auto tbw = offsets<const double*>(Tbw.ptr, sP, nc);
-    // direct terms of P = Qb V w and Pt^T = Qa^T U w
-    if (!gqb.empty())
-      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(pbw, ib), chi,
-                pick(vi, ib), b, 1.0, gqb, n);
-    if (!gqa.empty())
-      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(ui, ia), b,
-                pick(tbw, ia), chi, 1.0, gqa, n);
+    // (the direct terms of P = Qb V w and Pt^T = Qa^T U w join the
+    // complement terms at the end)
     // s_bar through w = s^-1/2
     Tensor wb = dev.empty({3, nc, chi});
     coldot(dev, QbV.ptr, Pb.ptr, n, chi, wb.ptr, nc, sP);
@@ -281,7 +276,6 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const auto t2w = offsets<double*>(t2.ptr, sP, 2 * nc);
     const auto t2r = offsets<const double*>(t2.ptr, sP, 2 * nc);
     const auto t1w = offsets<double*>(t2.ptr, sP, nc);  // n x chi per cut
-    const auto t1r = offsets<const double*>(t2.ptr, sP, nc);
     // out = A in = [s in_c - P_D Qa Qb in_b; s in_b - P'_D Qb^T Qa^T in_c]:
     // t = [Qb in_b; Qa^T in_c], then [Qa t_1; Qb^T t_2], both halves
     // projected off the kept vectors in one batched pair of products
@@ -489,23 +483,35 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
          1.0, Bm.ptr, chi, sP, nc);
     const auto bm = offsets<const double*>(Bm.ptr, sP, nc);
     const auto cm = offsets<const double*>(X.ptr, s2, nc);
-    const auto qbv = offsets<const double*>(QbV.ptr, sP, nc);
-    const auto qau = offsets<const double*>(QaU.ptr, sP, nc);
+    // Gradients of the cut matrices, each as one product of inner size
+    // 2 chi (every n x n gradient is read and written once):
+    //   Qa_bar += U (Qb B + T_w)^T + C (Qb V)^T
+    //   Qb_bar += (Qa^T C + P_w) V^T + (Qa^T U) B^T
+    // with the direct terms U T_w^T and P_w V^T of P = Qb V w and
+    // Pt^T = Qa^T U w; the factors are packed side by side, n x 2 chi.
+    const int64_t s2c = n * 2 * chi;
+    Tensor Lp = dev.empty({nc, n, 2 * chi}), Rp = dev.empty({nc, n, 2 * chi});
+    const auto lpr = offsets<const double*>(Lp.ptr, s2c, nc);
+    const auto rpr = offsets<const double*>(Rp.ptr, s2c, nc);
     if (!gqa.empty()) {
-      // Qa_bar += U (Qb B)^T + C (Qb V)^T
       qmul(dev, cp, false, n, chi, n, qb, qb32, n, bm, chi, t1w, chi);
-      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(ui, ia), b,
-                  pick(t1r, ia), chi, 1.0, gqa, n);
-      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(cm, ia), chi,
-                pick(qbv, ia), chi, 1.0, gqa, n);
+      axpby(dev, nc * sP, 1.0, Tbw.ptr, 1.0, t2.ptr);
+      copy2d(dev, U.ptr, b, Lp.ptr, 2 * chi, n, chi, nc, sUV, s2c);
+      copy2d(dev, X.ptr, chi, Lp.ptr + chi, 2 * chi, n, chi, nc, s2, s2c);
+      copy2d(dev, t2.ptr, chi, Rp.ptr, 2 * chi, n, chi, nc, sP, s2c);
+      copy2d(dev, QbV.ptr, chi, Rp.ptr + chi, 2 * chi, n, chi, nc, sP, s2c);
+      gemm_ptrs_p(dev, cp, false, true, n, n, 2 * chi, 1.0, pick(lpr, ia),
+                  2 * chi, pick(rpr, ia), 2 * chi, 1.0, gqa, n);
     }
     if (!gqb.empty()) {
-      // Qb_bar += (Qa^T U) B^T + (Qa^T C) V^T
-      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(qau, ib), chi,
-                pick(bm, ib), chi, 1.0, gqb, n);
       qmul(dev, cp, true, n, chi, n, qa, qa32, n, cm, chi, t1w, chi);
-      gemm_ptrs_p(dev, cp, false, true, n, n, chi, 1.0, pick(t1r, ib), chi,
-                  pick(vi, ib), b, 1.0, gqb, n);
+      axpby(dev, nc * sP, 1.0, Pbw.ptr, 1.0, t2.ptr);
+      copy2d(dev, t2.ptr, chi, Lp.ptr, 2 * chi, n, chi, nc, sP, s2c);
+      copy2d(dev, QaU.ptr, chi, Lp.ptr + chi, 2 * chi, n, chi, nc, sP, s2c);
+      copy2d(dev, V.ptr, b, Rp.ptr, 2 * chi, n, chi, nc, sUV, s2c);
+      copy2d(dev, Bm.ptr, chi, Rp.ptr + chi, 2 * chi, n, chi, nc, sP, s2c);
+      gemm_ptrs_p(dev, cp, false, true, n, n, 2 * chi, 1.0, pick(lpr, ib),
+                  2 * chi, pick(rpr, ib), 2 * chi, 1.0, gqb, n);
     }
   });
   return {P, PtT};
