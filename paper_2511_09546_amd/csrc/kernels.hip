@@ -1312,29 +1312,44 @@ namespace ipeps {
 
 // ---------------------------------------------- projector backward helpers
 // out[j] = sum_i X[i*m + j] * Y[i*m + j].  Stage 1: workgroup (cx, ry)
-// sweeps rows ry, ry + R, ... for the 64 columns of chunk cx with coalesced
-// row reads (4 rows in flight per workgroup) and writes one partial per
-// column; stage 2 adds the R partials in a fixed order.
-constexpr int CD_R = 32;
+// covers the CB = ceil(m / ceil(m / 64)) columns of chunk cx (36 of 72 for
+// chi = 72: no lanes idle on a partial chunk of 64) with G = 256 / CB row
+// groups, sweeps rows ry G + g, ry G + g + G CD_R, ... with coalesced row
+// reads, and writes one partial per column; stage 2 adds the CD_R partials
+// in a fixed order.  The same layout serves the fused CG updates below.
+constexpr int CD_R = 64;
+
+struct ColMap {
+  int cb, groups, c, g;  // chunk width, row groups, this column, its group
+  __device__ ColMap(int m) {
+    const int chunks = (m + 63) / 64;
+    cb = (m + chunks - 1) / chunks;
+    groups = 256 / cb;
+    c = blockIdx.x * cb + (int)threadIdx.x % cb;
+    g = (int)threadIdx.x / cb;
+  }
+  __device__ bool active(int m) const { return g < groups && c < m; }
+};
 
 __global__ __launch_bounds__(256) void coldot_partial_kernel(
     const double* __restrict__ X, const double* __restrict__ Y, int64_t n,
     int m, double* __restrict__ part, long sXY) {
-  __shared__ double red[4][64];
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int r0 = threadIdx.x >> 6;
+  __shared__ double red[256];
+  const ColMap cm(m);
   X += blockIdx.z * sXY;
   Y += blockIdx.z * sXY;
   double v = 0.0;
-  if (c < m)
-    for (int64_t i = blockIdx.y * 4 + r0; i < n; i += 4 * CD_R)
-      v += X[i * m + c] * Y[i * m + c];
-  red[r0][threadIdx.x & 63] = v;
+  if (cm.active(m))
+    for (int64_t i = blockIdx.y * cm.groups + cm.g; i < n;
+         i += (int64_t)cm.groups * CD_R)
+      v += X[i * m + cm.c] * Y[i * m + cm.c];
+  red[threadIdx.x] = v;
   __syncthreads();
-  if (threadIdx.x < 64 && c < m)
-    part[((long)blockIdx.z * CD_R + blockIdx.y) * m + c] =
-        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-        red[3][threadIdx.x];
+  if ((int)threadIdx.x < cm.cb && cm.c < m) {
+    double t = 0.0;
+    for (int q = 0; q < cm.groups; ++q) t += red[q * cm.cb + threadIdx.x];
+    part[((long)blockIdx.z * CD_R + blockIdx.y) * m + cm.c] = t;
+  }
 }
 
 __global__ void coldot_final_kernel(const double* __restrict__ part, int m,
@@ -1347,10 +1362,13 @@ __global__ void coldot_final_kernel(const double* __restrict__ part, int m,
   out[(long)blockIdx.y * m + c] = v;
 }
 
+// workgroup columns of the chunked layout
+static int col_chunks(int m) { return (m + 63) / 64; }
+
 void coldot(Device& dev, const double* X, const double* Y, int64_t n, int m,
             double* out, int batch, int64_t sXY) {
   Tensor part = dev.empty({batch, CD_R, m});
-  hipLaunchKernelGGL(coldot_partial_kernel, dim3((m + 63) / 64, CD_R, batch),
+  hipLaunchKernelGGL(coldot_partial_kernel, dim3(col_chunks(m), CD_R, batch),
                      dim3(256), 0, dev.stream, X, Y, n, m, part.ptr,
                      (long)sXY);
   hipLaunchKernelGGL(coldot_final_kernel, dim3((m + 127) / 128, batch),
@@ -1479,8 +1497,8 @@ __global__ void colcg_kernel(int mode, int64_t rows, int m, const double* rr,
 }
 
 // One CG step of column-wise systems, fused with the reductions around it.
-// Blocks (64 columns) x (CD_R row groups) x batch, rows of a batch split
-// over the row groups as in coldot, so the sums keep coldot's order.
+// Workgroups (column chunks) x (CD_R row groups) x batch in coldot's
+// layout, so the sums keep coldot's order.
 //   step: a_j = num_j / den_j (0 unless both > 0), x += a p, r -= a A p,
 //         partial sums of r_j^2 into part[batch][CD_R][m];
 //   dir:  rr_new_j = sum of the partials, p = r + (rr_new_j / rr_old_j) p
@@ -1490,15 +1508,16 @@ __global__ __launch_bounds__(256) void colcg_step_kernel(
     const double* __restrict__ den, double* __restrict__ x,
     double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ Ap, double* __restrict__ part) {
-  __shared__ double red[4][64];
-  const int lane = threadIdx.x & 63, r0 = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + lane, bt = blockIdx.z;
+  __shared__ double red[256];
+  const ColMap cm(m);
+  const int c = cm.c, bt = blockIdx.z;
   const long off = (long)bt * n * m;
   double v = 0.0;
-  if (c < m) {
+  if (cm.active(m)) {
     const double nu = num[(long)bt * m + c], de = den[(long)bt * m + c];
     const double a = (de > 0.0 && nu > 0.0) ? nu / de : 0.0;
-    for (int64_t i = blockIdx.y * 4 + r0; i < n; i += 4 * CD_R) {
+    for (int64_t i = blockIdx.y * cm.groups + cm.g; i < n;
+         i += (int64_t)cm.groups * CD_R) {
       const long e = off + i * m + c;
       x[e] += a * p[e];
       const double rv = r[e] - a * Ap[e];
@@ -1506,21 +1525,23 @@ __global__ __launch_bounds__(256) void colcg_step_kernel(
       v += rv * rv;
     }
   }
-  red[r0][lane] = v;
+  red[threadIdx.x] = v;
   __syncthreads();
-  if (threadIdx.x < 64 && c < m)
-    part[((long)bt * CD_R + blockIdx.y) * m + c] =
-        red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  if ((int)threadIdx.x < cm.cb && c < m) {
+    double t = 0.0;
+    for (int q = 0; q < cm.groups; ++q) t += red[q * cm.cb + threadIdx.x];
+    part[((long)bt * CD_R + blockIdx.y) * m + c] = t;
+  }
 }
 
 __global__ __launch_bounds__(256) void colcg_dir_kernel(
     int64_t n, int m, const double* __restrict__ part,
     const double* __restrict__ rr_old, double* __restrict__ rr_new,
     const double* __restrict__ r, double* __restrict__ p) {
-  __shared__ double beta[64];
-  const int lane = threadIdx.x & 63, r0 = threadIdx.x >> 6;
-  const int c = blockIdx.x * 64 + lane, bt = blockIdx.z;
-  if (threadIdx.x < 64) {
+  __shared__ double beta[256];
+  const ColMap cm(m);
+  const int c = cm.c, bt = blockIdx.z;
+  if ((int)threadIdx.x < cm.cb) {
     double b = 0.0;
     if (c < m) {
       const double* pp = part + (long)bt * CD_R * m + c;
@@ -1530,13 +1551,14 @@ __global__ __launch_bounds__(256) void colcg_dir_kernel(
       b = ro > 0.0 ? sum / ro : 0.0;
       if (blockIdx.y == 0) rr_new[(long)bt * m + c] = sum;
     }
-    beta[lane] = b;
+    beta[threadIdx.x] = b;
   }
   __syncthreads();
-  if (c >= m) return;
-  const double bb = beta[lane];
+  if (!cm.active(m)) return;
+  const double bb = beta[(int)threadIdx.x % cm.cb];
   const long off = (long)bt * n * m;
-  for (int64_t i = blockIdx.y * 4 + r0; i < n; i += 4 * CD_R) {
+  for (int64_t i = blockIdx.y * cm.groups + cm.g; i < n;
+       i += (int64_t)cm.groups * CD_R) {
     const long e = off + i * m + c;
     p[e] = r[e] + bb * p[e];
   }
@@ -1545,7 +1567,7 @@ __global__ __launch_bounds__(256) void colcg_dir_kernel(
 void colcg_step(Device& dev, int64_t n, int m, int batch, const double* num,
                 const double* den, double* x, double* r, const double* p,
                 const double* Ap, double* part) {
-  hipLaunchKernelGGL(colcg_step_kernel, dim3((m + 63) / 64, CD_R, batch),
+  hipLaunchKernelGGL(colcg_step_kernel, dim3(col_chunks(m), CD_R, batch),
                      dim3(256), 0, dev.stream, n, m, num, den, x, r, p, Ap,
                      part);
   IPEPS_HIP(hipGetLastError());
@@ -1554,7 +1576,7 @@ void colcg_step(Device& dev, int64_t n, int m, int batch, const double* num,
 void colcg_dir(Device& dev, int64_t n, int m, int batch, const double* part,
                const double* rr_old, double* rr_new, const double* r,
                double* p) {
-  hipLaunchKernelGGL(colcg_dir_kernel, dim3((m + 63) / 64, CD_R, batch),
+  hipLaunchKernelGGL(colcg_dir_kernel, dim3(col_chunks(m), CD_R, batch),
                      dim3(256), 0, dev.stream, n, m, part, rr_old, rr_new, r,
                      p);
   IPEPS_HIP(hipGetLastError());
