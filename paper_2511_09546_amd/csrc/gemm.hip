@@ -962,10 +962,13 @@ void launch_presplit(Device& dev, const Call& c) {
 // half the per-CU peak `flops_cu`), stretched by 1 + 128 / wg when few
 // workgroups per CU are left to hide latency; a split also writes and
 // re-reads S partial sums of `pbytes` bytes each (at 4 TB/s).  The split
-// minimises the sum (the larger split on ties), with at least 256 of K per
-// split, at most 256 splits and 2048 workgroups.  Measured on the
-// 4 x 2 x (2592 x 72 x 2592) and 4 x (1296 x 1296 x 5184) products, whose
-// best splits (3 and 4) it picks.
+// minimises the sum (the larger split on ties), with at least 64 of K per
+// split, at most 256 splits and 2048 workgroups.  Against measured sweeps
+// of the split: on the 8 x (2592 x 72 x 2592) products splits 3 to 8 lie
+// within 8 % of each other (it picks 6); on the small 8 x (72 x 72 x 2592)
+// products, which wait on memory latency slice by slice, 8 splits of 64-row
+// tiles took 27 us and 27 splits of one 96-row tile take 16 us (it picks
+// 27, hence the floor of 64 of K per split).
 int split_k(long tb, int K, int BK, int BM, int BN, long mn_batch,
             int pbytes, double flops_cu, int& kchunk) {
   auto up = [](long x, long m) { return (x + m - 1) / m * m; };
@@ -974,7 +977,7 @@ int split_k(long tb, int K, int BK, int BM, int BN, long mn_batch,
   kchunk = (int)up(K, BK);
   if (K >= 512 && tb < 2048) {
     const long smax = std::min<long>(
-        {256L, (long)K / 256, std::max<long>(1, 2048 / tb)});
+        {256L, (long)K / 64, std::max<long>(1, 2048 / tb)});
     for (long s = 1; s <= smax; ++s) {
       const long kc = up((K + s - 1) / s, BK);
       const long se = (K + kc - 1) / kc;
@@ -1337,6 +1340,14 @@ void dispatch_prec(Device& dev, const Call& c) {
         launch_cfg<128, 128, 2, 2, P>(dev, c);
     } else
       launch_cfg<128, 128, 2, 2, P>(dev, c);
+  } else if (c.M > 64 && c.M <= 96) {
+    // 65..96 rows (chi = 72 and D^2 + 60 wide blocks of the complement
+    // solves and the projector SVD): one 96-row tile instead of a 64-row
+    // tile and a mostly empty second one
+    if (c.N > 96)
+      launch_cfg<96, 128, 2, 2, P>(dev, c);
+    else
+      launch_cfg<96, 96, 2, 2, P>(dev, c);
   } else if (c.N >= 128) {
     launch_cfg<64, 128, 2, 2, P>(dev, c);
   } else {

@@ -21,6 +21,9 @@ def _say(msg):
     (2592, 96, 2592, False, False), (2592, 72, 2592, True, False),
     (257, 65, 33, True, True), (36, 36, 20000, False, False),
     (100, 1000, 16, False, True),
+    # 65 to 96 rows: 96-row tiles, split K
+    (72, 72, 2592, True, False), (96, 130, 5000, True, False),
+    (80, 24, 3000, False, True),
     # at most 4 x 4 outputs with a long K: vector-unit kernel, chunked K
     (4, 4, 20000, False, False), (3, 4, 9001, True, False),
     (4, 2, 70000, False, True), (1, 1, 4096, True, True),

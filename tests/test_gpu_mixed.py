@@ -60,7 +60,12 @@ def _say(msg):
                                          # narrow direct-load tiles
                                          (0, 0, 300, 72, 2592),
                                          (1, 0, 300, 96, 1000),
-                                         (0, 1, 260, 40, 600)])
+                                         (0, 1, 260, 40, 600),
+                                         # 96-row tiles, split K
+                                         (1, 0, 72, 72, 2592),
+                                         (1, 0, 96, 72, 5184),
+                                         (0, 0, 72, 2592, 2592),
+                                         (1, 1, 90, 200, 700)])
 def test_fp32_gemm_error_bound(tA, tB, M, N, K):
     _say(f"fp32 gemm {tA}{tB} {M}x{N}x{K}")
     rng = np.random.default_rng(M + N + K)
@@ -130,7 +135,10 @@ def _step_against_golden(name, prec, rel):
                                          (1, 0, 530, 400, 1000),
                                          (0, 1, 530, 400, 1000),
                                          (1, 1, 530, 400, 1000),
-                                         (0, 0, 517, 389, 131)])
+                                         (0, 0, 517, 389, 131),
+                                         # 96-row tiles, split K
+                                         (1, 0, 72, 72, 2592),
+                                         (0, 0, 80, 300, 1000)])
 def test_bf16x3_gemm_error_bound(tA, tB, M, N, K):
     """x = hi + lo + r with hi = bf16(fl32(x)), lo = bf16(fl32(x) - hi) and
     BF16 unit roundoff 2^-8: |fl32(x) - hi| <= 2^-8 |x|, so
