@@ -62,8 +62,10 @@ static int grid_for(int64_t n, int block) {
 // LDS, so that reads run along q and writes along l, both coalesced.  TQ is
 // the extent of q itself when that is at most 96 (the bond dimensions D^2
 // and chi here: no lanes wasted on a partial tile), else 64, and
-// TL = min(2048 / TQ, 256); the 256 threads cover 256 / TQ rows of the tile
-// per pass when reading and 256 / TL when writing.  The remaining output
+// TL = min(2048 / TQ, 256), except that an output row of at most 48 (with
+// q longer than 96) is one tile wide, TL = l and TQ = min(2048 / TL, 256);
+// the 256 threads cover 256 / TQ rows of the tile per pass when reading
+// and 256 / TL when writing.  The remaining output
 // dimensions enumerate tiles in blockIdx.y (grid-stride, div/mod once per
 // tile).
 constexpr int PERM_TILE = 2048;  // elements of one tile
@@ -177,8 +179,14 @@ void permute(Device& dev, const Tensor& in, const std::vector<int>& perm,
     a.nl = (int)oshape[ld];
     a.sq_out = ostride[qd];
     a.sl_in = ostr[ld];
-    a.bq = a.nq <= 96 ? a.nq : 64;
-    a.bl = std::min(PERM_TILE / a.bq, 256);
+    if (a.nq > 96 && a.nl <= 48) {
+      // a short output row (D^2 = 36): one tile spans it, TQ = 2048 / TL
+      a.bl = a.nl;
+      a.bq = std::min(PERM_TILE / a.nl, 256);
+    } else {
+      a.bq = a.nq <= 96 ? a.nq : 64;
+      a.bl = std::min(PERM_TILE / a.bq, 256);
+    }
     a.tq = (a.nq + a.bq - 1) / a.bq;
     a.tl = (a.nl + a.bl - 1) / a.bl;
     int64_t nrest = 1;

@@ -70,6 +70,9 @@ def test_gemm_split_k():
     ((300, 4, 300, 4), (0, 3, 2, 1), 0.0),  # tiled, 90000 outer tiles
     ((5, 4, 3, 6), (0, 3, 2, 1), -0.5),      # tile of 4 x 256
     ((130, 6, 70), (2, 1, 0), 0.0),          # q longer than one tile
+    ((40, 300), (1, 0), 0.0),                # short output row: one tile
+    ((5, 36, 2600), (0, 2, 1), -0.5),        # the same, D^2 = 36, accumulate
+    ((4, 1000), (1, 0), 0.0),                # row of 4: TQ capped at 256
     ((3, 4), (0, 1), 0.5)])                  # identity: plain copy
 def test_permute(shape, perm, beta):
     _say(f"permute {shape} {perm} beta={beta}")
