@@ -66,6 +66,53 @@ struct PtrArgs {
   double* c[MAXP];
 };
 
+// Epilogue of a tile of 16 x 16 MFMA blocks: out = alpha acc + beta out
+// (one split) or the partial sums (split K).  Register r of block (i, j)
+// holds row 4 (l / 16) + r (FP32 and BF16 layouts, L32) or l / 16 + 4 r
+// (FP64) and column l % 16.  With beta != 0 the C values of a block row are
+// all loaded before any of them is stored: the compiler cannot tell that a
+// store does not alias a later load, and would wait one memory round trip
+// per element.
+template <bool L32, int TM, int TN, typename V, typename PT>
+__device__ __forceinline__ void store_tile(const V (&acc)[TM][TN], int lane,
+                                           int r0, int c0, int M, int N,
+                                           double alpha, double beta,
+                                           double* out, long ldc, PT* pout,
+                                           int splits) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    double cv[TN][4];
+    if (splits == 1 && beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row =
+              r0 + i * 16 + (L32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
+          const int col = c0 + j * 16 + (lane & 15);
+          cv[j][r] = row < M && col < N ? out[(long)row * ldc + col] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row =
+            r0 + i * 16 + (L32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
+        const int col = c0 + j * 16 + (lane & 15);
+        if (row < M && col < N) {
+          if (splits == 1) {
+            double v = alpha * (double)acc[i][j][r];
+            if (beta != 0.0) v += beta * cv[j][r];
+            out[(long)row * ldc + col] = v;
+          } else {
+            pout[(long)row * N + col] = acc[i][j][r];
+          }
+        }
+      }
+  }
+}
+
 template <typename TI, int BM, int BN, int WM, int WN, bool TA, bool TB,
           bool F32, bool KM, int BK>
 __global__ __launch_bounds__(256, 2) void gemm_kernel(
@@ -207,25 +254,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
   // sums kept in the accumulator's type (exact)
   double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
   T* pout = (T*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rr = F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r;
-        const int row = m0 + wm * WTM + i * 16 + rr;
-        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (row < M && col < N) {
-          if (splits == 1) {
-            double v = alpha * (double)acc[i][j][r];
-            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
-            out[(long)row * ldc + col] = v;
-          } else {
-            pout[(long)row * N + col] = acc[i][j][r];
-          }
-        }
-      }
+  store_tile<F32>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha, beta,
+                  out, ldc, pout, splits);
 }
 
 // BF16x3 arithmetic: every FP64 operand x is split into x_hi = bf16(x) and
@@ -365,24 +395,8 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
   double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
   float* pout =
       (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
-        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (row < M && col < N) {
-          if (splits == 1) {
-            double v = alpha * (double)acc[i][j][r];
-            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
-            out[(long)row * ldc + col] = v;
-          } else {
-            pout[(long)row * N + col] = acc[i][j][r];
-          }
-        }
-      }
+  store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
+                   beta, out, ldc, pout, splits);
 }
 
 // FP32 products with direct global-to-LDS loads (`global_load_lds_dwordx4`:
@@ -573,24 +587,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
   }
   double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
   float* pout = (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
-        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (row < M && col < N) {
-          if (splits == 1) {
-            double v = alpha * (double)acc[i][j][r];
-            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
-            out[(long)row * ldc + col] = v;
-          } else {
-            pout[(long)row * N + col] = acc[i][j][r];
-          }
-        }
-      }
+  store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
+                   beta, out, ldc, pout, splits);
 }
 
 // part layout [S][batch][M][N] (FP64, or FP32 for FP32 accumulators);
@@ -813,24 +811,8 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
   double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
   float* pout =
       (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * WTM + i * 16 + 4 * (lane >> 4) + r;
-        const int col = n0 + wn * WTN + j * 16 + (lane & 15);
-        if (row < M && col < N) {
-          if (splits == 1) {
-            double v = alpha * (double)acc[i][j][r];
-            if (beta != 0.0) v += beta * out[(long)row * ldc + col];
-            out[(long)row * ldc + col] = v;
-          } else {
-            pout[(long)row * N + col] = acc[i][j][r];
-          }
-        }
-      }
+  store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
+                   beta, out, ldc, pout, splits);
 }
 
 struct Call {
