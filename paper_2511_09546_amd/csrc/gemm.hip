@@ -943,11 +943,12 @@ void launch_presplit(Device& dev, const Call& c) {
 // ceil(wg / 256) times the time of one workgroup (2 BM BN kchunk flops at
 // half the per-CU peak `flops_cu`), stretched by 1 + 128 / wg when few
 // workgroups per CU are left to hide latency; a split also writes and
-// re-reads S partial sums of `pbytes` bytes each (at 4 TB/s).  The split
-// minimises the sum (the larger split on ties), with at least 64 of K per
-// split, at most 256 splits and 2048 workgroups.  Against measured sweeps
-// of the split: on the 8 x (2592 x 72 x 2592) products splits 3 to 8 lie
-// within 8 % of each other (it picks 6); on the small 8 x (72 x 72 x 2592)
+// re-reads S partial sums of `pbytes` bytes each (at 2 TB/s, about what the
+// separate reduction kernel reaches).  The split minimises the sum (the
+// larger split on ties), with at least 64 of K per split, at most 256
+// splits and 2048 workgroups.  Against measured sweeps of the split: on the
+// 8 x (2592 x 72 x 2592) products 3 splits are the fastest (101 us, 6: 105,
+// 8: 110), and it picks 3; on the small 8 x (72 x 72 x 2592)
 // products, which wait on memory latency slice by slice, 8 splits of 64-row
 // tiles took 27 us and 27 splits of one 96-row tile take 16 us (it picks
 // 27, hence the floor of 64 of K per split).
@@ -966,7 +967,7 @@ int split_k(long tb, int K, int BK, int BM, int BN, long mn_batch,
       const long wg = tb * se;
       double t = (double)((wg + 255) / 256) * 2.0 * BM * BN * kc /
                  (0.5 * flops_cu) * (1.0 + 128.0 / wg);
-      if (se > 1) t += (double)se * mn_batch * 2.0 * pbytes / 4e12;
+      if (se > 1) t += (double)se * mn_batch * 2.0 * pbytes / 2e12;
       if (best_t < 0.0 || t <= best_t) {
         best_t = t;
         best = (int)se;
