@@ -547,6 +547,10 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
     }
   };
   auto mma = [&]() {
+    // raised issue priority while the MFMAs run, so that a wave of another
+    // workgroup in its load and conversion phase fills the gaps instead
+    // of delaying the MFMA chain
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int s4 = 0; s4 < BK / 4; ++s4)
 #pragma unroll
@@ -555,6 +559,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(
               fa[s4][i], fb[s4][j], acc[i][j], 0, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
   };
   // Two stages.  Slice t: wait for its loads (each wave its own, then a
   // barrier), read all its operands into registers, start the loads of
