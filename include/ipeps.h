@@ -66,11 +66,15 @@ typedef enum {
  *               raises tolerances below 1e-7 to 1e-7;
  *   IPEPS_BF16  each operand split into two BF16 terms, three BF16 products
  *               (about 16 significant bits), FP32 accumulation;
- *               ctm_converge raises tolerances below 3e-6 to 3e-6. */
+ *               ctm_converge raises tolerances below 3e-6 to 3e-6;
+ *   IPEPS_BF16X1 one BF16 product per operand pair (operands rounded to
+ *               BF16, 8 significant bits), FP32 accumulation;
+ *               ctm_converge raises tolerances below 1e-3 to 1e-3. */
 typedef enum {
   IPEPS_FP64 = 0,
   IPEPS_FP32 = 1,
-  IPEPS_BF16 = 2
+  IPEPS_BF16 = 2,
+  IPEPS_BF16X1 = 3
 } ipeps_prec;
 
 /* One Hamiltonian term (Eq. (12), Eq. (13)).
@@ -107,6 +111,17 @@ typedef struct {
                           and recomputes the iteration in the backward pass
                           (one iteration resident, about one more forward
                           pass of work; same gradient up to rounding) */
+  double adj_cg_tol;  /* relative residual at which the complement solves of
+                         the truncated-SVD adjoint stop when their products
+                         are FP64 (1e-12); FP32 and BF16 products stop at
+                         their own rounding floor */
+  int ladder;         /* precision ladder (with prec IPEPS_BF16 or
+                         IPEPS_BF16X1): 1 = ctm_converge runs its iterations
+                         in the BF16 arithmetic until the spectrum change
+                         reaches that arithmetic's floor or stops falling,
+                         then in FP32 down to the FP32 floor;
+                         ipeps_energy_grad and precond_apply then run in
+                         FP32.  0 (default) = one arithmetic throughout */
 } ipeps_opts;
 
 /* What ipeps_energy_grad differentiates (Sec. III A, Sec. IV A):

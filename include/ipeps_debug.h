@@ -56,9 +56,22 @@ int ipeps_debug_permute(int rank, const long* shape, const int* perm,
  * residual (relative to s_1), out[3] complement-CG iterations of the
  * backward pass, out[4] complement solves, out[5] device memory held by the
  * context's pool in bytes, out[6] peak of the bytes in use, out[7] the
- * number of unrolled iterations of the last gradient (out has 8 entries). */
+ * number of unrolled iterations of the last gradient, out[8] projector SVDs
+ * and out[9] complement solves that stopped at their iteration limit above
+ * their tolerance, out[10] the arithmetic (ipeps_prec) the context's next
+ * contractions use (out has 11 entries). */
 struct ipeps_ctx;
 int ipeps_debug_stats(struct ipeps_ctx* ctx, double* out);
+
+/* Failure injection for the error-path tests (forced from the host; every
+ * kernel still runs to its normal end):
+ *   kind 0  clear all injected faults;
+ *   kind 1  device-memory budget of the context: allocations that would
+ *           take the bytes in use above `value` fail (ENOMEM from the call);
+ *   kind 2  precond_apply stops before CG iteration `value` as if it had
+ *           met p^T (N + delta) p <= 0 (ECG_BREAKDOWN, x = last iterate).
+ * Returns a status (EINVAL for an unknown kind or a negative value). */
+int ipeps_debug_set_fault(struct ipeps_ctx* ctx, int kind, double value);
 
 #ifdef __cplusplus
 }

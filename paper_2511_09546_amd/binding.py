@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libipeps.so")
 
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ECG_BREAKDOWN, ESTATE, ENOTIMPL = -1, -2, -3, -4, -5, -6
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, BF16X1 = 0, 1, 2, 3
 GRAD_FULL, GRAD_K, GRAD_FP = 0, 1, 2
 
 # every function declared in include/ipeps.h (checked by the CPU tests)
@@ -35,7 +35,7 @@ PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
                    "ipeps_debug_svd_ts", "ipeps_debug_stats",
                    "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time",
-                   "ipeps_debug_permute"]
+                   "ipeps_debug_permute", "ipeps_debug_set_fault"]
 
 
 class IpepsError(RuntimeError):
@@ -53,7 +53,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", c_int), ("svd_cutoff", c_double), ("grad_K", c_int),
                 ("svd_oversample", c_int), ("svd_max_iter", c_int),
                 ("svd_tol", c_double), ("grad_mode", c_int),
-                ("adj_tol", c_double), ("grad_checkpoint", c_int)]
+                ("adj_tol", c_double), ("grad_checkpoint", c_int),
+                ("adj_cg_tol", c_double), ("ladder", c_int)]
 
 
 _lib = None
@@ -113,6 +114,7 @@ def load():
     lib.ipeps_debug_permute.argtypes = [c_int, POINTER(ctypes.c_long),
                                         _IP, c_double, _DP, c_double, _DP]
     lib.ipeps_debug_stats.argtypes = [c_void_p, _DP]
+    lib.ipeps_debug_set_fault.argtypes = [c_void_p, c_int, c_double]
     lib.ipeps_debug_svd_ts.argtypes = [c_int, c_int, c_int, _DP, _DP, _DP,
                                        _DP]
     for name in ("ctm_init", "ctm_set_state", "ctm_converge",
@@ -123,7 +125,8 @@ def load():
                  "precond_apply_dev",
                  "ipeps_debug_sym_eig", "ipeps_debug_svd_ts",
                  "ipeps_debug_stats", "ipeps_debug_gemm_prec",
-                 "ipeps_debug_gemm_time", "ipeps_debug_permute"):
+                 "ipeps_debug_gemm_time", "ipeps_debug_permute",
+                 "ipeps_debug_set_fault"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -181,6 +184,7 @@ class Context:
         if st != OK:
             raise IpepsError(st, "ctm_init")
         self._h = h
+        self.last_status = OK
 
     def close(self):
         if getattr(self, "_h", None):
@@ -215,6 +219,7 @@ class Context:
                                  ctypes.byref(dl))
         if st < 0:
             raise IpepsError(st, "ctm_converge")
+        self.last_status = st
         return n.value, dl.value, st == OK
 
     def energy_grad(self, terms, grad: bool = True):
@@ -225,8 +230,9 @@ class Context:
                                       ctypes.byref(e),
                                       _dp(g) if grad else None)
         del keep
-        if st != OK:
+        if st < 0:
             raise IpepsError(st, "ipeps_energy_grad")
+        self.last_status = st  # NOT_CONVERGED: a solver hit its limit
         return e.value, g
 
     def precond(self, g, delta: float, cg_tol: float, cg_maxiter: int):
@@ -254,8 +260,9 @@ class Context:
         st = load().ipeps_energy_grad_dev(self._h, len(terms), arr,
                                           ctypes.byref(e), c_void_p(d_grad))
         del keep
-        if st != OK:
+        if st < 0:
             raise IpepsError(st, "ipeps_energy_grad_dev")
+        self.last_status = st
         return e.value
 
     def precond_dev(self, d_g: int, d_x: int, delta: float, cg_tol: float,
@@ -308,14 +315,23 @@ class Context:
         return n.value, sec.value, fl.value, by.value
 
     def stats(self) -> dict:
-        out = np.zeros(8)
+        out = np.zeros(11)
         st = load().ipeps_debug_stats(self._h, _dp(out))
         if st != OK:
             raise IpepsError(st, "ipeps_debug_stats")
         return dict(svd_iters=int(out[0]), svd_calls=int(out[1]),
                     svd_worst_residual=float(out[2]), cg_iters=int(out[3]),
                     cg_solves=int(out[4]), pool_bytes=int(out[5]),
-                    peak_live_bytes=int(out[6]), grad_K_used=int(out[7]))
+                    peak_live_bytes=int(out[6]), grad_K_used=int(out[7]),
+                    svd_unconverged=int(out[8]), cg_unconverged=int(out[9]),
+                    work_prec=int(out[10]))
+
+    def set_fault(self, kind: int, value: float = 0.0):
+        """Failure injection (ipeps_debug_set_fault): 0 clear, 1 memory
+        budget in bytes, 2 CG breakdown before iteration `value`."""
+        st = load().ipeps_debug_set_fault(self._h, int(kind), float(value))
+        if st != OK:
+            raise IpepsError(st, "ipeps_debug_set_fault")
 
     def set_env(self, C, T):
         buf = np.concatenate([_f64(C).ravel(), _f64(T).ravel()])

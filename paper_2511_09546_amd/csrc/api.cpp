@@ -61,6 +61,8 @@ void ipeps_default_opts(ipeps_opts* o) {
   o->grad_mode = IPEPS_GRAD_K;
   o->adj_tol = 1e-13;
   o->grad_checkpoint = 0;
+  o->adj_cg_tol = 1e-12;
+  o->ladder = 0;
 }
 
 const char* ipeps_version(void) { return "ipeps-mi355x 0.1"; }
@@ -113,7 +115,11 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
   ipeps_opts o;
   ipeps_default_opts(&o);
   if (opts) o = *opts;
-  if (o.prec != IPEPS_FP64 && o.prec != IPEPS_FP32 && o.prec != IPEPS_BF16)
+  if (o.prec != IPEPS_FP64 && o.prec != IPEPS_FP32 && o.prec != IPEPS_BF16 &&
+      o.prec != IPEPS_BF16X1)
+    return IPEPS_EINVAL;
+  if (!(o.adj_cg_tol > 0.0) || (o.ladder != 0 && o.ladder != 1) ||
+      (o.ladder == 1 && o.prec != IPEPS_BF16 && o.prec != IPEPS_BF16X1))
     return IPEPS_EINVAL;
   if (!(o.svd_cutoff >= 0.0) || o.grad_K < 0 || o.svd_max_iter < 1 ||
       !(o.svd_tol >= 0.0) || o.svd_oversample < 0 ||
@@ -146,6 +152,9 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
     cx.grad_mode = o.grad_mode;
     cx.adj_tol = o.adj_tol;
     cx.grad_ckpt = o.grad_checkpoint;
+    cx.adj_cg_tol = o.adj_cg_tol;
+    cx.ladder = o.ladder;
+    cx.work_prec = o.prec;
     cx.svd.cutoff = o.svd_cutoff;
     cx.svd.tol = o.svd_tol;
     cx.svd.max_iter = o.svd_max_iter;
@@ -191,16 +200,25 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
   int it = 0;
   double dl = INFINITY;
   const double svd_tol = cx.svd.tol;
+  const long svd_bad0 = cx.stats.svd_unconverged;
   // the spectrum change cannot fall below the rounding of the contraction
-  // arithmetic: tolerances under that floor are raised to it
-  const double floor = cx.prec == IPEPS_FP64
-                            ? 0.0
-                            : (cx.prec == IPEPS_FP32 ? kSpectraFloorFp32
-                                                     : kSpectraFloorBf16);
-  if (tol > 0.0) tol = std::max(tol, floor);
+  // arithmetic: tolerances under that floor are raised to it (with the
+  // precision ladder, to the floor of the arithmetic of the last rung)
+  const double tol_in = tol;
+  auto eff_tol = [&]() {
+    return tol_in > 0.0
+               ? std::max(tol_in, prec_floors(cx.work_prec).spectra)
+               : tol_in;
+  };
+  tol = eff_tol();
+  // precision ladder: the BF16 rung ends when the spectrum change reaches
+  // its floor or has not fallen below 0.9 of its smallest value for three
+  // iterations; the iterations then continue in FP32
+  double best = INFINITY;
+  int flat = 0;
   int st = guarded([&]() {
-    PrecScope ps(cx.dev, cx.prec);
     while (it < max_iter) {
+      PrecScope ps(cx.dev, cx.work_prec);
       // when iterating to a tolerance, the projector SVD of an iteration
       // only needs to be as accurate as the environment it produces: its
       // tolerance follows the last spectrum change (never looser than 1e-6,
@@ -213,6 +231,19 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
       cx.env = next;
       ++it;
       dl = corner_spectra_change(cx, cx.env);
+      if (cx.ladder && cx.work_prec != PREC_FP32) {
+        if (dl < 0.9 * best) {
+          best = dl;
+          flat = 0;
+        } else {
+          ++flat;
+        }
+        if (dl < prec_floors(cx.work_prec).spectra || flat >= 3) {
+          cx.work_prec = PREC_FP32;
+          tol = eff_tol();
+          continue;
+        }
+      }
       if (tol > 0.0 && dl < tol) break;
     }
     cx.svd.tol = svd_tol;
@@ -224,7 +255,23 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
   if (n_iter) *n_iter = it;
   if (delta) *delta = dl;
   if (tol > 0.0 && !(dl < tol)) return IPEPS_NOT_CONVERGED;
+  // a projector SVD that stopped at svd_max_iter above its tolerance
+  if (cx.stats.svd_unconverged != svd_bad0) return IPEPS_NOT_CONVERGED;
   return IPEPS_OK;
+}
+
+// Arithmetic of the gradient and the preconditioner: the context's, or FP32
+// behind the precision ladder.
+static int late_prec(const Context& cx) {
+  return cx.ladder ? (int)PREC_FP32 : cx.prec;
+}
+
+// NOT_CONVERGED when a projector SVD or a complement solve of the call
+// stopped at its iteration limit above its tolerance (outputs valid).
+static int solver_warning(const Context& cx, long svd0, long cg0) {
+  return (cx.stats.svd_unconverged != svd0 || cx.stats.cg_unconverged != cg0)
+             ? IPEPS_NOT_CONVERGED
+             : IPEPS_OK;
 }
 
 static int parse_terms(const Context& cx, int n_terms, const ipeps_term* H,
@@ -267,8 +314,9 @@ int ipeps_energy_grad(ipeps_ctx* c, int n_terms, const ipeps_term* H,
   if (st != IPEPS_OK) return st;
   if (!cx.converged_once) return IPEPS_ESTATE;
   double e = 0.0;
+  const long svd0 = cx.stats.svd_unconverged, cg0 = cx.stats.cg_unconverged;
   st = guarded([&]() {
-    PrecScope ps(cx.dev, cx.prec);
+    PrecScope ps(cx.dev, late_prec(cx));
     if (grad) {
       e = energy_grad(cx, terms, grad);
     } else {
@@ -278,7 +326,7 @@ int ipeps_energy_grad(ipeps_ctx* c, int n_terms, const ipeps_term* H,
   });
   if (st != IPEPS_OK) return st;
   *e_per_site = e;
-  return IPEPS_OK;
+  return solver_warning(cx, svd0, cg0);
 }
 
 int precond_apply(ipeps_ctx* c, const double* g, double delta, double cg_tol,
@@ -291,7 +339,7 @@ int precond_apply(ipeps_ctx* c, const double* g, double delta, double cg_tol,
   if (!cx.converged_once) return IPEPS_ESTATE;
   int res = 0;
   int st = guarded([&]() {
-    PrecScope ps(cx.dev, cx.prec);
+    PrecScope ps(cx.dev, late_prec(cx));
     res = precondition(cx, g, delta, cg_tol, cg_maxiter, x, n_iter,
                        rel_resid);
     return IPEPS_OK;
@@ -320,14 +368,15 @@ int ipeps_energy_grad_dev(ipeps_ctx* c, int n_terms, const ipeps_term* H,
   if (st != IPEPS_OK) return st;
   if (!cx.converged_once) return IPEPS_ESTATE;
   double e = 0.0;
+  const long svd0 = cx.stats.svd_unconverged, cg0 = cx.stats.cg_unconverged;
   st = guarded([&]() {
-    PrecScope ps(cx.dev, cx.prec);
+    PrecScope ps(cx.dev, late_prec(cx));
     e = energy_grad(cx, terms, d_grad, true);
     return IPEPS_OK;
   });
   if (st != IPEPS_OK) return st;
   *e_per_site = e;
-  return IPEPS_OK;
+  return solver_warning(cx, svd0, cg0);
 }
 
 int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
@@ -340,7 +389,7 @@ int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
   if (!cx.converged_once) return IPEPS_ESTATE;
   int res = 0;
   int st = guarded([&]() {
-    PrecScope ps(cx.dev, cx.prec);
+    PrecScope ps(cx.dev, late_prec(cx));
     res = precondition(cx, d_g, delta, cg_tol, cg_maxiter, d_x, n_iter,
                        rel_resid, true);
     return IPEPS_OK;
@@ -383,6 +432,7 @@ int ipeps_set_env(ipeps_ctx* c, const double* in) {
     cx.env = e;
     cx.have_warm = false;
     cx.converged_once = true;
+    cx.work_prec = cx.prec;  // a new environment climbs the ladder again
     (void)corner_spectra_change(cx, cx.env);
     cx.dev.sync();
     return IPEPS_OK;
@@ -424,7 +474,29 @@ int ipeps_debug_stats(ipeps_ctx* c, double* out) {
   out[5] = (double)c->cx.dev.pool.reserved();
   out[6] = (double)c->cx.dev.pool.peak_live();
   out[7] = (double)c->cx.grad_K_used;
+  out[8] = (double)st.svd_unconverged;
+  out[9] = (double)st.cg_unconverged;
+  out[10] = (double)c->cx.work_prec;
   return IPEPS_OK;
+}
+
+int ipeps_debug_set_fault(ipeps_ctx* c, int kind, double value) {
+  if (!c || !(value >= 0.0)) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  switch (kind) {
+    case 0:
+      cx.dev.pool.set_limit(SIZE_MAX);
+      cx.fault_cg_breakdown_at = -1;
+      return IPEPS_OK;
+    case 1:
+      cx.dev.pool.set_limit(value >= 1.8e19 ? SIZE_MAX : (size_t)value);
+      return IPEPS_OK;
+    case 2:
+      cx.fault_cg_breakdown_at = value > 2e9 ? -1 : (int)value;
+      return IPEPS_OK;
+    default:
+      return IPEPS_EINVAL;
+  }
 }
 
 void ctm_free(ipeps_ctx* c) {

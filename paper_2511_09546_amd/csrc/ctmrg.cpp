@@ -267,7 +267,7 @@ void corner_spectra(Context& cx, const Env& e, Tensor& S) {
     pad3(dev, e.C.ptr, W.ptr, nb, chi, chi, chi, b);
   }
   Tensor U, J;
-  svd_ts(dev, W, nb, chi, b, U, S, J, cx.prec == PREC_FP64 ? 1e-15 : 1e-12);
+  svd_ts(dev, W, nb, chi, b, U, S, J, dev.cprec == PREC_FP64 ? 1e-15 : 1e-12);
 }
 
 double corner_spectra_change(Context& cx, const Env& e) {

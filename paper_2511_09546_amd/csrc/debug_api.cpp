@@ -48,7 +48,7 @@ int ipeps_debug_gemm_prec(int prec, int tA, int tB, int M, int N, int K,
                           double alpha, const double* A, const double* B,
                           double beta, double* C) {
   if (!A || !B || !C || M < 1 || N < 1 || K < 1 ||
-      (prec != IPEPS_FP64 && prec != IPEPS_FP32 && prec != IPEPS_BF16))
+      (prec < IPEPS_FP64 || prec > IPEPS_BF16X1))
     return IPEPS_EINVAL;
   return run([&](Device& dev) {
     Tensor a = dev.empty({(int64_t)M * K}), b = dev.empty({(int64_t)K * N}),
@@ -66,7 +66,7 @@ int ipeps_debug_gemm_prec(int prec, int tA, int tB, int M, int N, int K,
 int ipeps_debug_gemm_time(int prec, int tA, int tB, int M, int N, int K,
                           int batch, int reps, double* us_per_call) {
   if (!us_per_call || M < 1 || N < 1 || K < 1 || batch < 1 || reps < 1 ||
-      (prec != IPEPS_FP64 && prec != IPEPS_FP32 && prec != IPEPS_BF16))
+      (prec < IPEPS_FP64 || prec > IPEPS_BF16X1))
     return IPEPS_EINVAL;
   return run([&](Device& dev) {
     const int64_t sA = (int64_t)M * K, sB = (int64_t)K * N,

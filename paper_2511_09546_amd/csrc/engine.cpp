@@ -46,6 +46,9 @@ void trim_idle() {
 
 void* Pool::alloc(size_t bytes, size_t* got) {
   bytes = round_bytes(std::max<size_t>(bytes, 8));
+  if (bytes > limit_ || live_ > limit_ - bytes)
+    throw OomError("context memory budget of " + std::to_string(limit_) +
+                   " bytes exceeded");
   auto it = free_.lower_bound(bytes);
   if (it != free_.end() && it->first <= bytes + bytes / 8) {
     void* p = it->second;

@@ -53,11 +53,15 @@ class Pool {
   void release(void* p, size_t block_bytes);
   size_t reserved() const { return reserved_; }
   size_t peak_live() const { return peak_live_; }
+  // bytes in use at once beyond which alloc fails with OomError (a budget
+  // the caller sets; no limit by default)
+  void set_limit(size_t bytes) { limit_ = bytes; }
 
  private:
   std::multimap<size_t, void*> free_;
   std::vector<std::pair<void*, size_t>> all_;
   size_t reserved_ = 0, live_ = 0, peak_live_ = 0;
+  size_t limit_ = SIZE_MAX;
 };
 
 struct Buffer {
@@ -102,7 +106,23 @@ enum ProfFamily {
 
 // Arithmetic of the GEMMs issued on a device (the contraction precision;
 // the values match ipeps_prec of the C ABI).
-enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2, PREC_BF16X1 = 3 };
+
+// Rounding floors of a contraction arithmetic: the smallest corner-spectrum
+// change CTMRG can resolve with it, and the relative residuals at which the
+// projector SVD and the complement solves of its adjoint level off (FP64:
+// none; the configured tolerances apply).
+struct PrecFloors {
+  double spectra, svd_res, cg_res;
+};
+inline PrecFloors prec_floors(int p) {
+  switch (p) {
+    case PREC_FP32: return {1e-7, 1e-5, 1e-5};
+    case PREC_BF16: return {3e-6, 1e-3, 1e-3};
+    case PREC_BF16X1: return {1e-3, 3e-2, 3e-2};
+    default: return {0.0, 0.0, 0.0};
+  }
+}
 
 struct Profiler {
   bool on = false;

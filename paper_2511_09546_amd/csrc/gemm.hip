@@ -272,7 +272,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <typename TI, int BM, int BN, int WM, int WN, bool TA, bool TB>
+template <typename TI, int BM, int BN, int WM, int WN, bool TA, bool TB,
+          int NP>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
     int M, int N, int K, double alpha, const void* __restrict__ Av,
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
   auto split = [](auto v, __bf16& h, __bf16& l) {
     const float f = (float)v;
     h = (__bf16)f;
-    l = (__bf16)(f - (float)h);
+    if constexpr (NP == 3) l = (__bf16)(f - (float)h);
   };
   auto store = [&]() {
 #pragma unroll
@@ -369,21 +370,25 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
     for (int i = 0; i < TM; ++i) {
       const int r = wm * WTM + i * 16 + (lane & 15);
       ah[i] = *(const bf16x8*)&Ah[r][kq];
-      al[i] = *(const bf16x8*)&Al[r][kq];
+      if constexpr (NP == 3) al[i] = *(const bf16x8*)&Al[r][kq];
     }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int c = wn * WTN + j * 16 + (lane & 15);
       const bf16x8 bh = *(const bf16x8*)&Bh[c][kq];
-      const bf16x8 bl = *(const bf16x8*)&Bl[c][kq];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
+      for (int i = 0; i < TM; ++i)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh,
                                                             acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl,
-                                                            acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh,
-                                                            acc[i][j], 0, 0, 0);
+      if constexpr (NP == 3) {
+        const bf16x8 bl = *(const bf16x8*)&Bl[c][kq];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              al[i], bh, acc[i][j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -670,7 +675,7 @@ __global__ __launch_bounds__(256) void split_bf16_kernel(SplitArgs a) {
                      ((long)(r >> 4) * (a.Kp >> 5) + (k >> 5)) * 512 +
                      (r & 15) * 32 + (k & 31);
       a.hi[o] = h;
-      a.lo[o] = (__bf16)(f - (float)h);
+      if (a.lo) a.lo[o] = (__bf16)(f - (float)h);
     }
   }
 }
@@ -678,7 +683,7 @@ __global__ __launch_bounds__(256) void split_bf16_kernel(SplitArgs a) {
 // C[b] = alpha A B + beta C from split planes A (Mp x Kp), B (Np x Kp)
 // (block layout above); tiles BM x BN, K slices of 32, LDS in the layout
 // of gemm_bf16x3_kernel; split K and XCD numbering as there.
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int NP>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
     int M, int N, int Kp, double alpha, const __bf16* __restrict__ Ah,
     const __bf16* __restrict__ Al, long sA, const __bf16* __restrict__ Bh,
@@ -736,7 +741,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
         const long o = (row >> 4) * rbs + ((kb) >> 5) * 512 +              \
                        (row & 15) * 32 + 8 * q;                            \
         rah[i] = *(const u32x4*)(Ah + o);                                  \
-        ral[i] = *(const u32x4*)(Al + o);                                  \
+        if constexpr (NP == 3) ral[i] = *(const u32x4*)(Al + o);           \
       }                                                                    \
     }                                                                      \
     _Pragma("unroll") for (int i = 0; i < BC; ++i) {                       \
@@ -745,7 +750,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
         const long o = (row >> 4) * rbs + ((kb) >> 5) * 512 +              \
                        (row & 15) * 32 + 8 * q;                            \
         rbh[i] = *(const u32x4*)(Bh + o);                                  \
-        rbl[i] = *(const u32x4*)(Bl + o);                                  \
+        if constexpr (NP == 3) rbl[i] = *(const u32x4*)(Bl + o);           \
       }                                                                    \
     }                                                                      \
   }
@@ -755,14 +760,14 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
       const int c = tid + i * 256, row = ps_row(c), q = c & 3;                \
       if (c < BM * 4) {                                                    \
         *(u32x4*)&Ahs[0][row][8 * q] = rah[i];                             \
-        *(u32x4*)&Als[0][row][8 * q] = ral[i];                             \
+        if constexpr (NP == 3) *(u32x4*)&Als[0][row][8 * q] = ral[i];      \
       }                                                                    \
     }                                                                      \
     _Pragma("unroll") for (int i = 0; i < BC; ++i) {                       \
       const int c = tid + i * 256, row = ps_row(c), q = c & 3;                \
       if (c < BN * 4) {                                                    \
         *(u32x4*)&Bhs[0][row][8 * q] = rbh[i];                             \
-        *(u32x4*)&Bls[0][row][8 * q] = rbl[i];                             \
+        if constexpr (NP == 3) *(u32x4*)&Bls[0][row][8 * q] = rbl[i];      \
       }                                                                    \
     }                                                                      \
   }
@@ -788,21 +793,25 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
     for (int i = 0; i < TM; ++i) {
       const int r = wm * WTM + i * 16 + (lane & 15);
       ah[i] = *(const bf16x8*)&Ahs[buf][r][kq];
-      al[i] = *(const bf16x8*)&Als[buf][r][kq];
+      if constexpr (NP == 3) al[i] = *(const bf16x8*)&Als[buf][r][kq];
     }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int c = wn * WTN + j * 16 + (lane & 15);
       const bf16x8 bh = *(const bf16x8*)&Bhs[buf][c][kq];
-      const bf16x8 bl = *(const bf16x8*)&Bls[buf][c][kq];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
+      for (int i = 0; i < TM; ++i)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh,
                                                             acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl,
-                                                            acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh,
-                                                            acc[i][j], 0, 0, 0);
+      if constexpr (NP == 3) {
+        const bf16x8 bl = *(const bf16x8*)&Bls[buf][c][kq];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              ah[i], bl, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              al[i], bh, acc[i][j], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -842,19 +851,21 @@ bool presplit_pays(const Call& c) {
   return c.M >= 4 * BM && c.N >= 4 * BN && c.K >= 128 && c.batch <= MAXP;
 }
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int NP>
 void launch_presplit(Device& dev, const Call& c) {
   auto up = [](long x, long m) { return (x + m - 1) / m * m; };
   const int Mp = (int)up(c.M, BM), Np = (int)up(c.N, BN);
   const int Kp = (int)up(c.K, 32);
   const long sA = (long)Mp * Kp, sB = (long)Np * Kp;
-  // hi and lo planes of A and B (bf16) in one buffer
-  const long nbf = 2L * c.batch * (sA + sB);
+  // hi (and, for three products, lo) planes of A and B (bf16) in one
+  // buffer
+  const long np = NP == 3 ? 2 : 1;
+  const long nbf = np * c.batch * (sA + sB);
   Tensor planes = dev.empty({(nbf + 3) / 4});
   __bf16* Ah = (__bf16*)planes.ptr;
-  __bf16* Al = Ah + c.batch * sA;
-  __bf16* Bh = Al + c.batch * sA;
-  __bf16* Bl = Bh + c.batch * sB;
+  __bf16* Al = NP == 3 ? Ah + c.batch * sA : nullptr;
+  __bf16* Bh = Ah + np * c.batch * sA;
+  __bf16* Bl = NP == 3 ? Bh + c.batch * sB : nullptr;
   const long tm = Mp / BM, tn = Np / BN, tiles = tm * tn;
   int S = 1;
   if (tiles * c.batch < 512 && c.K >= 512) {
@@ -923,7 +934,7 @@ void launch_presplit(Device& dev, const Call& c) {
                        dev.stream, b);
   PtrArgs pa{};
   if (c.ptrs) pa = *c.ptrs;
-  hipLaunchKernelGGL((gemm_bf16x3_ps_kernel<BM, BN, WM, WN>),
+  hipLaunchKernelGGL((gemm_bf16x3_ps_kernel<BM, BN, WM, WN, NP>),
                      dim3((unsigned)tiles, (unsigned)(c.batch * S)),
                      dim3(256), 0, dev.stream, c.M, c.N, Kp, c.alpha, Ah, Al,
                      sA, Bh, Bl, sB, c.beta, c.C, c.ldc, c.sC, (int)tn, S,
@@ -983,10 +994,10 @@ int split_k(long tb, int K, int BK, int BM, int BN, long mn_batch,
   return best;
 }
 
-// per-CU matrix-core peaks (flop/s): FP64, FP32, and BF16x3 (three BF16
-// products per product)
-constexpr double CU_PEAK[3] = {78.6e12 / 256, 157.3e12 / 256,
-                               2.5e15 / 3 / 256};
+// per-CU matrix-core peaks (flop/s): FP64, FP32, BF16x3 (three BF16
+// products per product) and single BF16 products
+constexpr double CU_PEAK[4] = {78.6e12 / 256, 157.3e12 / 256,
+                               2.5e15 / 3 / 256, 2.5e15 / 256};
 
 // Products with at most 4 x 4 outputs per batch entry and a long K (overlaps
 // and norms of whole tensors, K up to 4 D^8): a matrix-core tile would be
@@ -1156,17 +1167,18 @@ bool lds_ok(const Call& c) {
   return true;
 }
 
-// P: 0 = FP64, 1 = FP32, 2 = BF16x3 arithmetic
+// P: 0 = FP64, 1 = FP32, 2 = BF16x3, 3 = single BF16 arithmetic
 template <int BM, int BN, int WM, int WN, int P, bool LDSK = false>
 void launch_cfg(Device& dev, const Call& c) {
-  if constexpr (P == 2) {
+  constexpr int NP = P == 3 ? 1 : 3;  // BF16 products per product
+  if constexpr (P >= 2) {
     if (presplit_pays<BM, BN>(c)) {
-      launch_presplit<BM, BN, WM, WN>(dev, c);
+      launch_presplit<BM, BN, WM, WN, NP>(dev, c);
       return;
     }
   }
   constexpr bool F32 = P == 1;
-  constexpr int BK = P == 2 ? 32 : 16;
+  constexpr int BK = P >= 2 ? 32 : 16;
   const long tm = (c.M + BM - 1) / BM, tn = (c.N + BN - 1) / BN;
   const long tiles = tm * tn;
   int kchunk;
@@ -1224,15 +1236,15 @@ void launch_cfg(Device& dev, const Call& c) {
   }
   auto pick = [&](auto ti) {
     using TI = decltype(ti);
-    if constexpr (P == 2) {
+    if constexpr (P >= 2) {
       if (!c.tA && !c.tB)
-        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, false, false>);
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, false, false, NP>);
       if (c.tA && !c.tB)
-        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, true, false>);
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, true, false, NP>);
       if (!c.tA && c.tB)
-        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, false, true>);
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, false, true, NP>);
       if (c.tA && c.tB)
-        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, true, true>);
+        go(gemm_bf16x3_kernel<TI, BM, BN, WM, WN, true, true, NP>);
     } else {
       if (!c.tA && !c.tB)
         go(gemm_kernel<TI, BM, BN, WM, WN, false, false, F32, false, BK>);
@@ -1307,7 +1319,7 @@ void dispatch_prec(Device& dev, const Call& c) {
     else if (c.N <= 96)
       direct ? launch_cfg<128, 96, 4, 1, P, P == 1>(dev, c)
              : launch_cfg<128, 96, 4, 1, P>(dev, c);
-    else if constexpr (P == 2)  // BF16x3: 128 x 128 would spill registers
+    else if constexpr (P >= 2)  // BF16x3: 128 x 128 would spill registers
       launch_cfg<128, 96, 4, 1, P>(dev, c);
     else if constexpr (P == 1) {
       // FP32: 128 x 144 tiles (4 waves of 32 x 144; D^4 = 1296 and its
@@ -1352,8 +1364,10 @@ void dispatch(Device& dev, const Call& c) {
     dispatch_prec<1>(dev, c);
   else if (dev.cprec == PREC_FP64)
     dispatch_prec<0>(dev, c);
-  else
+  else if (dev.cprec == PREC_BF16)
     dispatch_prec<2>(dev, c);
+  else
+    dispatch_prec<3>(dev, c);
 }
 
 void check_sizes(int64_t M, int64_t N, int64_t K, int64_t batch) {

@@ -40,6 +40,9 @@ struct SvdStats {
   double worst_residual = 0.0;
   long cg_iters = 0;    // complement solves of the backward pass
   long cg_solves = 0;
+  // calls that ended at their iteration limit above the tolerance in effect
+  long svd_unconverged = 0;   // projector SVDs (svd_max_iter)
+  long cg_unconverged = 0;    // complement solves of the backward pass
 };
 
 // tol2: Jacobi criterion of the second pass (1e-15 gives the full FP64
@@ -91,12 +94,6 @@ struct VEnv {
   std::vector<Var> C, T;
 };
 
-// Smallest corner-spectrum change that CTMRG with FP32 contractions can
-// resolve (their rounding moves the normalised spectra by about this much).
-constexpr double kSpectraFloorFp32 = 1e-7;
-// The same for the BF16x3 products (about 16 significant bits; the
-// spectrum change levels off near 1e-6).
-constexpr double kSpectraFloorBf16 = 3e-6;
 
 struct Context {
   Device dev;
@@ -111,6 +108,14 @@ struct Context {
   double adj_tol = 1e-13;
   int grad_ckpt = 0;     // recompute the unrolled iterations in the backward
   int grad_K_used = 0;   // K of the last gradient (fixed-point mode)
+  double adj_cg_tol = 1e-12;  // complement solves, FP64 products
+  int ladder = 0;        // BF16 -> FP32 precision ladder
+  // arithmetic of the contractions of the next call: prec, or FP32 once the
+  // ladder has stepped up
+  int work_prec = 0;
+  // test hooks: precondition() stops as at a breakdown before this CG
+  // iteration (-1: never)
+  int fault_cg_breakdown_at = -1;
   SvdParams svd;
   SvdStats stats;
 

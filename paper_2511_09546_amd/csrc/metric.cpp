@@ -105,6 +105,11 @@ int precondition(Context& cx, const double* g_host, double delta,
     int it = 0;
     if (gnorm > 0.0) {
       while (it < cg_maxiter && std::sqrt(rr) > cg_tol * gnorm) {
+        if (it == cx.fault_cg_breakdown_at) {
+          // test hook: handled like a detected breakdown at this iteration
+          breakdown = true;
+          break;
+        }
         apply_ring(cx, sm, p.ptr, Ap.ptr, W1);
         // Ap = Ap / Z + delta p
         scale_add_dev(dev, m, sc.ptr + 4, p.ptr, delta, Ap.ptr);

@@ -427,8 +427,9 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     // floor of the products).  Tested before the first iteration of a warm
     // start and after every second iteration.
     const bool lowp = cp != PREC_FP64;
-    const double tol2 = cp == PREC_FP64 ? 1e-24 : (cp == PREC_FP32 ? 1e-10
-                                                                   : 1e-6);
+    const double rtol = cp == PREC_FP64 ? cxp->adj_cg_tol
+                                        : prec_floors(cp).cg_res;
+    const double tol2 = rtol * rtol;
     double prev_worst = INFINITY;
     // <r, r> alternates between the rr and rr_new slices of sc (the fused
     // direction update writes the new value next to the old one)
@@ -453,6 +454,7 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     const int max_it = 600;
     int it = 0;
     const bool done0 = warm && converged(false);
+    bool done = done0;
     for (; !done0 && it < max_it; ++it) {
       apply(Pp, AP);
       // x += alpha p, r -= alpha A p with alpha = <r, p> / <p, A p> (equal
@@ -469,9 +471,11 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       if (m > 0) deflate(R.ptr, Pp.ptr);
       if ((it + 1) % 2 == 0 && converged(true)) {
         ++it;
+        done = true;
         break;
       }
     }
+    if (!done) ++st->cg_unconverged;
     st->cg_iters += it;
     st->cg_solves += nc;
     cxp->cg_warm = X;

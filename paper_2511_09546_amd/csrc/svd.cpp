@@ -145,13 +145,12 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
   int it = 0;
   double worst = 0.0;
   // with FP32 products the residual levels off at a few 1e-6 s_1 (BF16x3:
-  // a few 1e-4): the tolerance is raised to 1e-5 (1e-3) and the iteration
-  // also ends when an iteration no longer halves the residual
+  // a few 1e-4, single BF16 products about 1e-2): the tolerance is raised
+  // to that arithmetic's floor and the iteration also ends when an
+  // iteration no longer halves the residual
   const bool lowp = dev.cprec != PREC_FP64;
-  const double floor = dev.cprec == PREC_FP64   ? 0.0
-                       : dev.cprec == PREC_FP32 ? 1e-5
-                                                : 1e-3;
-  const double tol = std::max(prm.tol, floor);
+  const double tol = std::max(prm.tol, prec_floors(dev.cprec).svd_res);
+  bool stalled = false;
   double prev = INFINITY;
   for (;;) {
     ++it;
@@ -175,7 +174,10 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
     dev.download(res, hres.data());
     worst = *std::max_element(hres.begin(), hres.end());
     if (worst <= tol || it >= prm.max_iter) break;
-    if (lowp && it >= 3 && worst > 0.5 * prev) break;
+    if (lowp && it >= 3 && worst > 0.5 * prev) {
+      stalled = true;
+      break;
+    }
     prev = worst;
     // next block: an orthonormal basis of span(Z) (Cholesky QR of the
     // column-normalised Z, whose columns are nearly orthogonal since
@@ -194,6 +196,10 @@ void projector_svd(Device& dev, const CutBatch& cb, Tensor& X, bool warm,
     stats->iters += it;
     stats->calls += 1;
     stats->worst_residual = std::max(stats->worst_residual, worst);
+    // ended by the iteration limit above the tolerance in effect (not at
+    // the rounding floor of a low-precision arithmetic): the projectors are
+    // less accurate than asked, which the entry points report as a warning
+    if (!direct && !stalled && worst > tol) ++stats->svd_unconverged;
   }
 }
 

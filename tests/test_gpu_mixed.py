@@ -164,6 +164,39 @@ def test_bf16x3_gemm_error_bound(tA, tB, M, N, K):
     assert np.max(err) > 0.0
 
 
+@pytest.mark.parametrize("tA,tB,M,N,K", [(0, 0, 200, 130, 300),
+                                         (1, 0, 129, 72, 2592),
+                                         (0, 0, 640, 1296, 1296),
+                                         (1, 1, 530, 400, 1000),
+                                         (0, 1, 517, 389, 131),
+                                         (1, 0, 72, 72, 2592)])
+def test_bf16x1_gemm_error_bound(tA, tB, M, N, K):
+    """Single BF16 products: a -> bf16(fl32(a)) with
+    |a - bf16(fl32(a))| <= eps |a|, eps = 2^-24 + 2^-8 (1 + 2^-24), so one
+    product is off by at most (2 eps + eps^2) |a||b|, and K of them
+    accumulate in FP32: bound (2 eps + eps^2 + gamma_K) (|A||B|)."""
+    _say(f"bf16x1 gemm {tA}{tB} {M}x{N}x{K}")
+    rng = np.random.default_rng(M * N + K + 1)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    Aop = A.T.copy() if tA else A
+    Bop = B.T.copy() if tB else B
+    C = binding.debug_gemm_prec(binding.BF16X1, Aop, Bop, np.zeros((M, N)),
+                                tA=bool(tA), tB=bool(tB))
+    ref = A @ B
+    u = 2.0 ** -24
+    eps = u + 2.0 ** -8 * (1 + u)
+    g = K * u / (1 - K * u)
+    bound = (2 * eps + eps * eps + g) * (np.abs(A) @ np.abs(B))
+    err = np.abs(C - ref)
+    _say(f"  max err/bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
+    # coarser than the three-product split: not silently BF16x3
+    C3 = binding.debug_gemm_prec(binding.BF16, Aop, Bop, np.zeros((M, N)),
+                                 tA=bool(tA), tB=bool(tB))
+    assert np.max(err) > 10 * np.max(np.abs(C3 - ref))
+
+
 def test_profile_network_family_is_a_subset():
     """Family 5 (GEMMs of the network contractions) counts a proper subset of
     the FP32 GEMM launches: the projector-SVD and complement-solve products
