@@ -111,42 +111,6 @@ def test_device_pointer_twins():
         assert abs(e3 - e2) < 1e-13 * abs(e2)   # scale invariance
 
 
-def test_adjoint_vs_finite_differences_kitaev():
-    """The unrolled adjoint is the exact derivative of
-    f(A) = e(A, F^K(A, env*)): central differences of f, evaluated through
-    the library itself (environment reset to env*, K iterations, energy),
-    along seeded unit directions over all four tensors of the 2x2 Kitaev
-    cell (D=5, chi=50).  h = 1e-4 leaves a truncation error ~h^2 times the
-    third derivative and a rounding error ~1e-16 |e| / h (plus the 1e-13
-    projector-SVD tolerance over h); measured differences are ~1e-11 |g|,
-    the bound is 1e-8 |g|."""
-    name = "kitaev2x2"
-    _say("adjoint vs FD kitaev2x2")
-    w = inputs.WORKLOADS[name]
-    A = inputs.workload_state(name)
-    terms = inputs.workload_terms(name)
-    K, h = w["grad_K"], 1e-4
-    with binding.Context(A, w["chi"]) as ctx:
-        ctx.converge(w["tol"], w["n_iter"])
-        C, T = ctx.get_env()
-        e0, g = ctx.energy_grad(terms, grad=True)
-        gn = np.linalg.norm(g)
-        for seed in (1000, 1001, 1002, 1003):
-            v = np.random.default_rng(seed).standard_normal(A.shape)
-            v /= np.linalg.norm(v)
-            f = []
-            for sgn in (1.0, -1.0):
-                ctx.set_state(A + sgn * h * v)
-                ctx.set_env(C, T)
-                ctx.converge(0.0, K)
-                f.append(ctx.energy_grad(terms, grad=False)[0])
-            fd = (f[0] - f[1]) / (2 * h)
-            ad = float(np.sum(g * v))
-            _say(f"  seed {seed}: adjoint {ad:.12e} fd {fd:.12e} "
-                 f"diff/|g| {abs(fd - ad) / gn:.2e}")
-            assert abs(fd - ad) < 1e-8 * gn
-
-
 @pytest.mark.parametrize("ckpt", [0, 1])
 def test_grad_mode_full(ckpt):
     """IPEPS_GRAD_FULL: derivative through the trace-boundary start and N
