@@ -52,7 +52,9 @@ typedef enum {
                                last iterate (written in this case) */
   IPEPS_ESTATE = -5,        /* call out of order (e.g. energy before any
                                ctm_converge) */
-  IPEPS_ENOTIMPL = -6       /* option not implemented */
+  IPEPS_ENOTIMPL = -6,      /* option not implemented */
+  IPEPS_ESCRATCH = -7       /* the state is too large for the fixed scratch
+                               area of precond_apply_dev_noalloc */
 } ipeps_status;
 
 /* Arithmetic of the dense contractions (every product of the CTMRG and
@@ -206,6 +208,29 @@ int ipeps_energy_grad_dev(ipeps_ctx* ctx, int n_terms, const ipeps_term* terms,
 int precond_apply_dev(ipeps_ctx* ctx, const double* d_g, double delta,
                       double cg_tol, int cg_maxiter, double* d_x, int* n_iter,
                       double* rel_resid);
+
+/* Allocation-free precond_apply_dev, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * semantics and results as precond_apply_dev (d_g, d_x device pointers in
+ * the layout of A); the metric is applied one physical index at a time.
+ * Every temporary of the call lives in one fixed scratch array of
+ * IPEPS_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load until
+ * the process ends; the call makes no hipMalloc, hipFree or other
+ * allocating call.  All calls on one GPU share that array: calls that
+ * overlap in time on one GPU (from any context or thread) race and must be
+ * serialised by the caller.  A state whose working set
+ * (precond_noalloc_bytes) exceeds the array is refused with
+ * IPEPS_ESCRATCH before any work.  Errors: EINVAL, ESTATE, ESCRATCH, EHIP,
+ * ECG_BREAKDOWN (x written). */
+#define IPEPS_NOALLOC_SCRATCH_BYTES ((size_t)192 << 20)
+int precond_apply_dev_noalloc(ipeps_ctx* ctx, const double* d_g,
+                              double delta, double cg_tol, int cg_maxiter,
+                              double* d_x, int* n_iter, double* rel_resid);
+
+/* Scratch bytes precond_apply_dev_noalloc needs for a state of these sizes
+ * (an upper estimate; host only).  Returns 0 for invalid sizes. */
+size_t precond_noalloc_bytes(int Lx, int Ly, int d, int D, int chi);
 
 /* Sum-normalised singular values of every corner, out[4][Lx*Ly][chi] (host),
  * zero padded. Errors: EINVAL, EHIP. */

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(HERE, "libipeps.so")
 
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EHIP, ECG_BREAKDOWN, ESTATE, ENOTIMPL = -1, -2, -3, -4, -5, -6
+ESCRATCH = -7
+# size of the fixed scratch array of precond_apply_dev_noalloc (per GPU)
+NOALLOC_SCRATCH_BYTES = 192 << 20
 FP64, FP32, BF16, BF16X1 = 0, 1, 2, 3
 GRAD_FULL, GRAD_K, GRAD_FP = 0, 1, 2
 
@@ -29,6 +32,7 @@ API_FUNCTIONS = [
     "ipeps_strerror", "ipeps_version", "ipeps_profile_enable",
     "ipeps_profile_read", "ctm_set_state_dev", "ipeps_energy_grad_dev",
     "precond_apply_dev", "ipeps_footprint_bytes",
+    "precond_apply_dev_noalloc", "precond_noalloc_bytes",
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
 PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
@@ -100,6 +104,12 @@ def load():
                                           _DP, c_void_p]
     lib.precond_apply_dev.argtypes = [c_void_p, c_void_p, c_double,
                                       c_double, c_int, c_void_p, _IP, _DP]
+    lib.precond_apply_dev_noalloc.argtypes = [c_void_p, c_void_p, c_double,
+                                              c_double, c_int, c_void_p, _IP,
+                                              _DP]
+    lib.precond_apply_dev_noalloc.restype = c_int
+    lib.precond_noalloc_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int]
+    lib.precond_noalloc_bytes.restype = c_size_t
     lib.ipeps_profile_enable.argtypes = [c_void_p, c_int]
     lib.ipeps_profile_read.argtypes = [c_void_p, c_int,
                                        POINTER(ctypes.c_long), _DP, _DP, _DP]
@@ -148,6 +158,11 @@ def default_opts() -> Opts:
     o = Opts()
     load().ipeps_default_opts(ctypes.byref(o))
     return o
+
+
+def noalloc_bytes(Lx, Ly, d, D, chi) -> int:
+    """Scratch bytes of precond_apply_dev_noalloc (precond_noalloc_bytes)."""
+    return int(load().precond_noalloc_bytes(Lx, Ly, d, D, chi))
 
 
 def footprint_bytes(Lx, Ly, d, D, chi, opts=None) -> int:
@@ -275,6 +290,18 @@ class Context:
                                       ctypes.byref(n), ctypes.byref(rr))
         if st < 0 and st != ECG_BREAKDOWN:
             raise IpepsError(st, "precond_apply_dev")
+        return n.value, rr.value, st == ECG_BREAKDOWN
+
+    def precond_dev_noalloc(self, d_g: int, d_x: int, delta: float,
+                            cg_tol: float, cg_maxiter: int):
+        """precond_apply_dev_noalloc: (n_iter, rel_resid, breakdown)."""
+        n = c_int(0)
+        rr = c_double(0.0)
+        st = load().precond_apply_dev_noalloc(
+            self._h, c_void_p(d_g), delta, cg_tol, cg_maxiter, c_void_p(d_x),
+            ctypes.byref(n), ctypes.byref(rr))
+        if st < 0 and st != ECG_BREAKDOWN:
+            raise IpepsError(st, "precond_apply_dev_noalloc")
         return n.value, rr.value, st == ECG_BREAKDOWN
 
     def spectra(self) -> np.ndarray:

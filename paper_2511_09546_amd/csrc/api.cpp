@@ -9,10 +9,6 @@
 #include "../../include/ipeps_debug.h"
 #include "ipeps_impl.hpp"
 
-struct ipeps_ctx {
-  ipeps::Context cx;
-};
-
 using namespace ipeps;
 
 namespace {
@@ -77,6 +73,9 @@ const char* ipeps_strerror(int s) {
     case IPEPS_ECG_BREAKDOWN: return "CG breakdown (p^T P p <= 0)";
     case IPEPS_ESTATE: return "call out of order";
     case IPEPS_ENOTIMPL: return "not implemented";
+    case IPEPS_ESCRATCH:
+      return "state too large for the fixed scratch area of "
+             "precond_apply_dev_noalloc";
     default: return "unknown status";
   }
 }
@@ -140,6 +139,7 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
       IPEPS_HIP(hipStreamCreate(&cx.dev.stream));
       cx.dev.own_stream = true;
     }
+    IPEPS_HIP(hipGetDevice(&cx.device));
     cx.lat.Lx = Lx;
     cx.lat.Ly = Ly;
     cx.d = d;

@@ -44,8 +44,40 @@ void trim_idle() {
 }
 }  // namespace
 
+void Pool::begin_arena(void* base, size_t bytes) {
+  arena_ = (char*)base;
+  arena_size_ = bytes;
+  arena_top_ = 0;
+  arena_peak_ = 0;
+  arena_lo_ = arena_;
+  arena_hi_ = arena_ + bytes;
+  arena_free_.clear();
+}
+
+void Pool::end_arena() {
+  arena_ = nullptr;
+  arena_free_.clear();
+}
+
 void* Pool::alloc(size_t bytes, size_t* got) {
   bytes = round_bytes(std::max<size_t>(bytes, 8));
+  if (arena_) {
+    auto it = arena_free_.lower_bound(bytes);
+    if (it != arena_free_.end() && it->first <= bytes + bytes / 8) {
+      void* p = it->second;
+      *got = it->first;
+      arena_free_.erase(it);
+      return p;
+    }
+    if (bytes > arena_size_ - arena_top_)
+      throw OomError("scratch area of " + std::to_string(arena_size_) +
+                     " bytes exhausted");
+    void* p = arena_ + arena_top_;
+    arena_top_ += bytes;
+    arena_peak_ = std::max(arena_peak_, arena_top_);
+    *got = bytes;
+    return p;
+  }
   if (bytes > limit_ || live_ > limit_ - bytes)
     throw OomError("context memory budget of " + std::to_string(limit_) +
                    " bytes exceeded");
@@ -93,6 +125,13 @@ void* Pool::alloc(size_t bytes, size_t* got) {
 }
 
 void Pool::release(void* p, size_t block_bytes) {
+  const char* c = (const char*)p;
+  if (arena_lo_ && c >= arena_lo_ && c < arena_hi_) {
+    // a block of the scratch region: back to the arena while it is active,
+    // dropped otherwise (never to HIP or the cached blocks)
+    if (arena_) arena_free_.emplace(block_bytes, p);
+    return;
+  }
   live_ -= block_bytes;
   free_.emplace(block_bytes, p);
 }

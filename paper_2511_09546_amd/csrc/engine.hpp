@@ -56,12 +56,26 @@ class Pool {
   // bytes in use at once beyond which alloc fails with OomError (a budget
   // the caller sets; no limit by default)
   void set_limit(size_t bytes) { limit_ = bytes; }
+  // Arena mode: between begin_arena and end_arena every block is carved
+  // from the fixed region [base, base + bytes) (a bump pointer; blocks
+  // released meanwhile are handed out again, best fit within 1/8), and
+  // nothing is taken from HIP, the idle list or this pool's cached blocks;
+  // a request that does not fit throws OomError.  Blocks of the region that
+  // are released after end_arena are dropped.
+  void begin_arena(void* base, size_t bytes);
+  void end_arena();
+  size_t arena_peak() const { return arena_peak_; }
 
  private:
   std::multimap<size_t, void*> free_;
   std::vector<std::pair<void*, size_t>> all_;
   size_t reserved_ = 0, live_ = 0, peak_live_ = 0;
   size_t limit_ = SIZE_MAX;
+  char* arena_ = nullptr;            // active region (null: none)
+  size_t arena_size_ = 0, arena_top_ = 0, arena_peak_ = 0;
+  const char* arena_lo_ = nullptr;   // last region, for late releases
+  const char* arena_hi_ = nullptr;
+  std::multimap<size_t, void*> arena_free_;
 };
 
 struct Buffer {

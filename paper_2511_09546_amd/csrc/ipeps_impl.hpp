@@ -133,6 +133,8 @@ struct Context {
   bool have_cg_warm = false;
   Tensor spec_cur, spec_old;  // [4*nsite][chi]
 
+  int device = 0;        // HIP device of the context (current at ctm_init)
+
   int nsite() const { return lat.n(); }
   int ncut() const { return 4 * lat.n(); }
   Tensor Cv(const Env& e, int c, int s) const;
@@ -179,10 +181,14 @@ double energy_ad(Tape& tp, Context& cx, const VEnv& e,
 double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms);
 
 // metric.cpp
-// g and x are host pointers, or device pointers when on_device
+// g and x are host pointers, or device pointers when on_device; lean applies
+// the metric one physical index at a time (smallest working set)
 int precondition(Context& cx, const double* g, double delta, double cg_tol,
                  int cg_maxiter, double* x, int* n_iter, double* rel_resid,
-                 bool on_device = false);
+                 bool on_device = false, bool lean = false);
+// Device bytes precondition(..., lean = true) works in at most (an upper
+// estimate of its temporaries, split-K partial sums included).
+size_t precondition_lean_bytes(int nsite, int d, int D, int chi);
 
 // adjoint.cpp
 // grad is a host pointer, or a device pointer when on_device
@@ -190,3 +196,9 @@ double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
                    double* grad, bool on_device = false);
 
 }  // namespace ipeps
+
+// The opaque context of the C ABI.
+struct ipeps_ctx {
+  ipeps::Context cx;
+};
+inline ipeps::Context& ipeps_context(ipeps_ctx* c) { return c->cx; }

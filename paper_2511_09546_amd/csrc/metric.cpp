@@ -27,39 +27,75 @@ struct SiteMetric {
 SiteMetric build_metric(Context& cx, const Env& e, int s) {
   Device& dev = cx.dev;
   const int D = cx.D, chi = cx.chi;
-  Tensor Tp1 = einsum(dev, "ij,jek->iek", cx.Cv(e, 0, s), cx.Tv(e, 0, s));
-  Tensor Tp = einsum(dev, "iek,km->iem", Tp1, cx.Cv(e, 1, s));
-  Tensor Bt1 = einsum(dev, "np,pzq->nzq", cx.Cv(e, 2, s), cx.Tv(e, 2, s));
-  Tensor Bt = einsum(dev, "nzq,qw->nzw", Bt1, cx.Cv(e, 3, s));
-  Tensor LT = einsum(dev, "wgi,iem->wgem", cx.Tv(e, 3, s), Tp);
-  Tensor RB = einsum(dev, "mbn,nzw->mbzw", cx.Tv(e, 1, s), Bt);
   SiteMetric sm;
-  // LT[w, l, l', u, u', m] -> [l, u, l', u', w, m]
-  Tensor LT6 = LT.view({chi, D, D, D, D, chi});
-  sm.LTq = permuted(dev, LT6, {1, 3, 2, 4, 0, 5});
-  // RB[m, r, r', d, d', w] -> [w, m, r, d, r', d']
-  Tensor RB6 = RB.view({chi, D, D, D, D, chi});
-  sm.RBq = permuted(dev, RB6, {5, 0, 1, 3, 2, 4});
+  // each half ring is permuted and its unpermuted form released before the
+  // other is built: at most three chi^2 D^4 buffers are live at once
+  {
+    Tensor Tp1 = einsum(dev, "ij,jek->iek", cx.Cv(e, 0, s), cx.Tv(e, 0, s));
+    Tensor Tp = einsum(dev, "iek,km->iem", Tp1, cx.Cv(e, 1, s));
+    Tensor LT = einsum(dev, "wgi,iem->wgem", cx.Tv(e, 3, s), Tp);
+    // LT[w, l, l', u, u', m] -> [l, u, l', u', w, m]
+    Tensor LT6 = LT.view({chi, D, D, D, D, chi});
+    sm.LTq = permuted(dev, LT6, {1, 3, 2, 4, 0, 5});
+  }
+  {
+    Tensor Bt1 = einsum(dev, "np,pzq->nzq", cx.Cv(e, 2, s), cx.Tv(e, 2, s));
+    Tensor Bt = einsum(dev, "nzq,qw->nzw", Bt1, cx.Cv(e, 3, s));
+    Tensor RB = einsum(dev, "mbn,nzw->mbzw", cx.Tv(e, 1, s), Bt);
+    // RB[m, r, r', d, d', w] -> [w, m, r, d, r', d']
+    Tensor RB6 = RB.view({chi, D, D, D, D, chi});
+    sm.RBq = permuted(dev, RB6, {5, 0, 1, 3, 2, 4});
+  }
   sm.Zinv = dev.empty({1});
   return sm;
 }
 
-// y = E x (unnormalised), x and y [d][D^4]
+// y = E x (unnormalised), x and y [d][D^4]; `lean` runs the physical
+// index t one at a time through a W1 of one chi^2 D^4 block (the
+// allocation-free entry point), else all of them in one batched product
 void apply_ring(Context& cx, const SiteMetric& sm, const double* x,
-                double* y, Tensor& W1) {
+                double* y, Tensor& W1, bool lean = false) {
   Device& dev = cx.dev;
-  const int64_t D2 = cx.D2, chi = cx.chi, d = cx.d;
+  const int64_t D2 = cx.D2, chi = cx.chi;
   const int64_t Mq = D2 * chi * chi;  // (l' u' w m)
-  if (W1.numel() != d * Mq * D2) W1 = dev.empty({d, Mq, D2});
-  // W1[t][(l' u' w m)][(r d)] = sum_{(l u)} LTq[(l u)][(l' u' w m)] x[t][(l u)][(r d)]
-  gemm(dev, true, false, Mq, D2, D2, 1.0, sm.LTq.ptr, Mq, 0, x, D2, D2 * D2,
-       0.0, W1.ptr, D2, Mq * D2, d);
-  // y[t][(l' u')][(r' d')] = sum_{(w m r d)} W1[t][(l' u')][(w m r d)] RBq
-  gemm(dev, false, false, D2, D2, chi * chi * D2, 1.0, W1.ptr,
-       chi * chi * D2, Mq * D2, sm.RBq.ptr, D2, 0, 0.0, y, D2, D2 * D2, d);
+  const int64_t nb = lean ? 1 : cx.d;
+  if (W1.numel() != nb * Mq * D2) W1 = dev.empty({nb, Mq, D2});
+  for (int64_t t0 = 0; t0 < cx.d; t0 += nb) {
+    const double* xt = x + t0 * D2 * D2;
+    double* yt = y + t0 * D2 * D2;
+    // W1[t][(l' u' w m)][(r d)] =
+    //   sum_{(l u)} LTq[(l u)][(l' u' w m)] x[t][(l u)][(r d)]
+    gemm(dev, true, false, Mq, D2, D2, 1.0, sm.LTq.ptr, Mq, 0, xt, D2,
+         D2 * D2, 0.0, W1.ptr, D2, Mq * D2, nb);
+    // y[t][(l' u')][(r' d')] = sum_{(w m r d)} W1[t][(l' u')][(w m r d)] RBq
+    gemm(dev, false, false, D2, D2, chi * chi * D2, 1.0, W1.ptr,
+         chi * chi * D2, Mq * D2, sm.RBq.ptr, D2, 0, 0.0, yt, D2, D2 * D2,
+         nb);
+  }
 }
 
 }  // namespace
+
+size_t precondition_lean_bytes(int nsite, int d, int D, int chi) {
+  // blocks as the pool rounds them (256 bytes; 64 KiB above 1 MiB)
+  auto blk = [](double words) {
+    double b = 8.0 * words;
+    b = std::ceil(b / 256.0) * 256.0;
+    if (b > 1048576.0) b = std::ceil(b / 65536.0) * 65536.0;
+    return b;
+  };
+  const double D2 = (double)D * D, c = chi;
+  const double q = c * c * D2 * D2;     // a half ring, or W1 of one index
+  const double m = d * D2 * D2;         // one site tensor
+  // LTq, RBq and one more half-ring block (the unpermuted ring, then W1);
+  // two chi^2 D^2 products per half ring; g, x, r, p, Ap; the CG scalars,
+  // the reduction partials of dot and 256 split-K partial sums of the
+  // D^2 x D^2 product with K = chi^2 D^2; 1 MiB of slack
+  const double bytes = 3.0 * blk(q) + 2.0 * blk(c * c * D2) +
+                       2.0 * blk(nsite * m) + 3.0 * blk(m) + blk(8) +
+                       4.0 * blk(4096) + blk(256.0 * D2 * D2) + 1048576.0;
+  return (size_t)bytes;
+}
 
 // CG kernels live in kernels.hip
 void cg_update_xr(Device& dev, int64_t n, const double* rr, const double* pAp,
@@ -72,7 +108,7 @@ void scale_add_dev(Device& dev, int64_t n, const double* s, const double* x,
 
 int precondition(Context& cx, const double* g_host, double delta,
                  double cg_tol, int cg_maxiter, double* x_host, int* n_iter,
-                 double* rel_resid, bool on_device) {
+                 double* rel_resid, bool on_device, bool lean) {
   Device& dev = cx.dev;
   const int ns = cx.nsite();
   const int64_t m = (int64_t)cx.d * cx.D2 * cx.D2;  // per-site length
@@ -91,7 +127,7 @@ int precondition(Context& cx, const double* g_host, double delta,
   for (int s = 0; s < ns; ++s) {
     SiteMetric sm = build_metric(cx, cx.env, s);
     // Z = <A, E A>
-    apply_ring(cx, sm, cx.A.ptr + s * m, Ap.ptr, W1);
+    apply_ring(cx, sm, cx.A.ptr + s * m, Ap.ptr, W1, lean);
     dot(dev, cx.A.ptr + s * m, Ap.ptr, m, sc.ptr + 4);
     const double* gs = g.ptr + s * m;
     double* xs = x.ptr + s * m;
@@ -110,7 +146,7 @@ int precondition(Context& cx, const double* g_host, double delta,
           breakdown = true;
           break;
         }
-        apply_ring(cx, sm, p.ptr, Ap.ptr, W1);
+        apply_ring(cx, sm, p.ptr, Ap.ptr, W1, lean);
         // Ap = Ap / Z + delta p
         scale_add_dev(dev, m, sc.ptr + 4, p.ptr, delta, Ap.ptr);
         dot(dev, p.ptr, Ap.ptr, m, sc.ptr + 1);

@@ -69,3 +69,22 @@ def test_argument_checks_before_any_device_call(lib):
     assert lib.ctm_converge(None, 1e-10, 10, None, None) == -1
     assert lib.precond_apply(None, None, 1.0, 0.0, 1, None, None, None) == -1
     lib.ctm_free(None)
+
+
+def test_noalloc_scratch_size_and_estimate(lib):
+    """The scratch size the binding states is the header's, and the host-only
+    working-set estimate admits the D=6, chi=72 state and refuses chi=100."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "ipeps.h")).read()
+    m = re.search(r"#define IPEPS_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)",
+                  hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == \
+        binding.NOALLOC_SCRATCH_BYTES
+    cap = binding.NOALLOC_SCRATCH_BYTES
+    need = binding.noalloc_bytes(1, 1, 2, 6, 72)
+    # three chi^2 D^4 half-ring blocks dominate
+    assert 3 * 8 * 72 ** 2 * 6 ** 4 < need <= cap
+    assert binding.noalloc_bytes(1, 1, 2, 6, 100) > cap
+    assert binding.noalloc_bytes(0, 1, 2, 6, 72) == 0
+    assert lib.precond_apply_dev_noalloc(None, None, 1e-4, 0.0, 1, None,
+                                         None, None) == -1
