@@ -15,29 +15,37 @@ scalars cross PCIe inside the timed region.
 
 The headline runs the dense contractions in FP32 on the matrix cores
 (projector SVD, normalisation, traces and CG scalars stay FP64); the same
-steps are then timed with BF16x3 contractions (three BF16 products of a
-two-term split) and with every product in FP64 ("plain FP64"), and the
-energies of the cold steps are compared with the FP64 one.
+steps are then timed with BF16x3 contractions, with every product in FP64
+("plain FP64"), and shorter runs take single-pass BF16 contractions and the
+BF16 -> FP32 precision ladder.  Every arithmetic reports the error of its
+cold step against the FP64 oracle's stored values, its per-phase times and
+its milliseconds per CTMRG iteration (the converge phases of different
+arithmetics run different iteration counts: their floors differ).
 
-Prints one JSON line.  The roofline object reports the library's
-matrix-core GEMM in the headline arithmetic (the dominant kernel):
-algorithmic flops (2 M N K per launch) over the device time of its
-launches, both recorded live with HIP events on the library's stream
-during as many steps as the timed ones, run right after them (the events
-cost about 6 % of a step, so the timed steps run without); its traffic is
-the HBM bytes per launch from the
-counter record under profiles/ (null when the kernel source has changed
-since the counters were taken).  The cpu_baseline object times the CPU oracle on a
-bounded sample of the same workload (one CTMRG iteration and one K=1
-gradient step) and scales it to one step.
+Further legs: `serving` replays the seeded request stream (Poisson arrivals
+at 20/s, D 3..6, chi 2D^2..3D^2; a prefix of --serve-requests requests) and
+reports p50/p99 latency, throughput, the device overlap of requests and how
+many of a sample gave bitwise the results of the same request run alone;
+`lbfgs` times iterations of the preconditioned L-BFGS on the same state.
+
+The roofline object reports the library's matrix-core GEMM in the headline
+arithmetic (the dominant kernel): algorithmic flops (2 M N K per launch)
+over the device time of its launches, both recorded live with HIP events on
+the library's stream during as many steps as the timed ones, run right after
+them (the events cost about 6 % of a step, so the timed steps run without);
+its traffic is the HBM bytes per launch from the counter record under
+profiles/ (null when the kernel source has changed since the counters were
+taken).  The cpu_baseline object times the CPU oracle on the host on a
+bounded sample of the same workload (one CTMRG iteration, the energy network
+with its backward, one unrolled iteration with its backward, one CG solve)
+and composes one step from those phases; the full oracle step measured on
+the GPU host, when its record is under profiles/, is reported beside it.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--prec fp32]
                     [--no-fp64] [--no-cpu-baseline] [--checkpoint]
+                    [--serve-requests 128] [--no-lbfgs]
 
-Besides the contract fields the line reports the median and p10/p90 of the
-timed steps with the mean time of each phase (step_ms), and for every
-arithmetic the error of its cold step against the FP64 CPU oracle's stored
-values for the same workload (error_vs_oracle: |de|, |dg|/|g|, |dx|/|x|).
+Prints one JSON line.
 """
 import argparse
 import json
@@ -50,15 +58,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("energy+grad+precond steps/s at D=6,χ=72 vs plain FP64; "
           "MFMA util; p50/p99 lat")
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0,
+               "bf16x1": 2500.0}
 
 
 def cpu_baseline(name, n_conv):
-    """Oracle on the host: one CTMRG iteration from the trace boundary and
-    one K=1 gradient step from that environment, scaled to a step of
-    n_conv iterations + K gradient steps (+ the negligible CG)."""
+    """The oracle on the host, phase by phase: one CTMRG iteration (from the
+    trace boundary), the energy network and its backward (K = 0 gradient),
+    one unrolled iteration with its backward (K = 1 minus K = 0) and one
+    20-iteration CG solve; composed into one step of n_conv iterations and
+    K unrolled iterations."""
+    import numpy as np
     import torch
-    from oracle import ctmrg, gradient
+    from oracle import ctmrg, gradient, metric
     from paper_2511_09546_amd import inputs
     w = inputs.WORKLOADS[name]
     A = inputs.workload_state(name)
@@ -67,16 +79,33 @@ def cpu_baseline(name, n_conv):
     t0 = time.perf_counter()
     env, _, _ = ctmrg.converge(A, w["chi"], 0.0, 1)
     t1 = time.perf_counter()
-    gradient.grad_K(A, terms, env, w["chi"], 1)
+    gradient.grad_K(A, terms, env, w["chi"], 0)
     t2 = time.perf_counter()
-    t_fwd, t_g1 = t1 - t0, t2 - t1
-    t_step = n_conv * t_fwd + w["grad_K"] * t_g1
-    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": (f"{name}: 1 CTMRG iteration ({t_fwd:.1f} s) + 1 "
-                       f"K=1 gradient step ({t_g1:.1f} s) on the host, "
-                       f"scaled to {n_conv} iterations + K={w['grad_K']} "
-                       f"gradient steps = {t_step:.0f} s/step")}
+    _, g = gradient.grad_K(A, terms, env, w["chi"], 1)
+    t3 = time.perf_counter()
+    metric.precondition(env, A, g.numpy(), w["delta"], 0.0, w["cg_maxiter"])
+    t4 = time.perf_counter()
+    t_it, t_g0, t_g1, t_cg = t1 - t0, t2 - t1, t3 - t2, t4 - t3
+    t_adj = max(t_g1 - t_g0, 0.0)
+    K = w["grad_K"]
+    t_step = n_conv * t_it + t_g0 + K * t_adj + t_cg
+    out = {"value": 1.0 / t_step, "unit": "steps/s", "cores": threads,
+           "kind": "oracle",
+           "host_cpu_count": os.cpu_count(), "torch_threads": threads,
+           "sample": (f"{name} on the host: 1 CTMRG iteration {t_it:.1f} s, "
+                      f"energy network + backward {t_g0:.1f} s, 1 unrolled "
+                      f"iteration + backward {t_g1:.1f} - {t_g0:.1f} s, "
+                      f"CG {t_cg:.2f} s; one step = {n_conv} iterations + "
+                      f"energy + K={K} unrolled iterations + CG = "
+                      f"{t_step:.0f} s"),
+           "sample_seconds": t4 - t0}
+    rec = os.path.join(ROOT, "profiles", f"oracle_step_{name}_host.json")
+    if os.path.exists(rec):
+        r = json.load(open(rec))
+        out["full_step_measured"] = {
+            k: r[k] for k in ("seconds", "n_iter", "cpu_count",
+                              "torch_threads", "command") if k in r}
+    return out
 
 
 def measured_traffic(prec):
@@ -95,7 +124,10 @@ def measured_traffic(prec):
     return r["traffic_bytes_per_launch"]
 
 
-def run(name, prec, steps, warmup, ckpt=0):
+PRECS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x1": 3}
+
+
+def run(name, prec, steps, warmup, ckpt=0, ladder=0, profile=True):
     """Warm-up and timed steps in one arithmetic; returns the measurements."""
     import torch
     from paper_2511_09546_amd import binding, inputs
@@ -103,12 +135,13 @@ def run(name, prec, steps, warmup, ckpt=0):
     A = inputs.workload_state(name)
     terms = inputs.workload_terms(name)
     o = binding.default_opts()
-    o.prec = {"fp64": binding.FP64, "fp32": binding.FP32,
-              "bf16": binding.BF16}[prec]
+    o.prec = PRECS[prec]
     o.grad_checkpoint = ckpt
+    o.ladder = ladder
     ctx = binding.Context(A, w["chi"], opts=o)
     fam = {"fp64": binding.PROF_GEMM, "fp32": binding.PROF_GEMM32,
-           "bf16": binding.PROF_GEMM16}[prec]
+           "bf16": binding.PROF_GEMM16,
+           "bf16x1": binding.PROF_GEMM16}[prec]
 
     # site tensor, gradient and direction stay resident in HBM: the step
     # uses the device-pointer entry points (torch provides the buffers)
@@ -149,46 +182,56 @@ def run(name, prec, steps, warmup, ckpt=0):
         if i == 0:
             cold = (info["e"],) + kept
         infos.append(info)
-        print(f"[{prec}] warmup {i}: {info}", file=sys.stderr, flush=True)
+        print(f"[{prec}{' ladder' if ladder else ''}] warmup {i}: {info}",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     timed = []
     for i in range(steps):
         A, info, _ = step(A)
         timed.append(info)
-        print(f"[{prec}] step {i}: {info}", file=sys.stderr, flush=True)
+        print(f"[{prec}{' ladder' if ladder else ''}] step {i}: {info}",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # the same number of steps again, continuing the trajectory, with HIP
-    # events around every launch of the timed kernel families (the events
-    # cost about 6 % of a step, so the steps above run without them)
-    ctx.profile(True)
-    t1 = time.perf_counter()
-    for i in range(steps):
-        A, info, _ = step(A)
-    torch.cuda.synchronize()
-    elapsed_prof = time.perf_counter() - t1
-    prof = {f: ctx.profile_read(f) for f in
-            (fam, binding.PROF_JACOBI, binding.PROF_PERMUTE,
-             binding.PROF_NET)}
-    ctx.profile(False)
+    prof, elapsed_prof = None, None
+    if profile:
+        # the same number of steps again, continuing the trajectory, with
+        # HIP events around every launch of the timed kernel families (the
+        # events cost about 6 % of a step, so the steps above run without)
+        ctx.profile(True)
+        t1 = time.perf_counter()
+        for i in range(steps):
+            A, info, _ = step(A)
+        torch.cuda.synchronize()
+        elapsed_prof = time.perf_counter() - t1
+        prof = {f: ctx.profile_read(f) for f in
+                (fam, binding.PROF_JACOBI, binding.PROF_PERMUTE,
+                 binding.PROF_NET)}
+        ctx.profile(False)
     stats = ctx.stats()
     ctx.close()
     return dict(elapsed=elapsed, timed=timed, infos=infos, prof=prof,
-                fam=fam, stats=stats, cold=cold, elapsed_prof=elapsed_prof)
+                fam=fam, stats=stats, cold=cold, elapsed_prof=elapsed_prof,
+                steps=steps)
 
 
 def step_summary(r):
-    """Median, p10, p90 of the timed steps and the mean time per phase."""
+    """Median, p10, p90 of the timed steps, the mean time per phase and the
+    milliseconds per CTMRG iteration of the converge phase."""
     import numpy as np
     ms = np.array([t["ms"] for t in r["timed"]])
     ph = np.array([t["phase_ms"] for t in r["timed"]]).mean(axis=0)
+    its = np.array([t["iters"] for t in r["timed"]], dtype=float)
+    conv = np.array([t["phase_ms"][0] for t in r["timed"]])
     return {"p10_ms": float(np.percentile(ms, 10)),
             "p50_ms": float(np.percentile(ms, 50)),
             "p90_ms": float(np.percentile(ms, 90)),
             "phase_ms": {"ctm_converge": float(ph[0]),
                          "energy_grad": float(ph[1]),
-                         "precond_apply": float(ph[2])}}
+                         "precond_apply": float(ph[2])},
+            "ctm_iters_mean": float(its.mean()),
+            "ms_per_ctm_iteration": float(conv.sum() / max(its.sum(), 1))}
 
 
 def oracle_error(name, cold):
@@ -207,7 +250,66 @@ def oracle_error(name, cold):
             "e_rel": abs(e - gold["e"]) / abs(gold["e"]),
             "g_rel": float(np.linalg.norm(g - g_or) / np.linalg.norm(g_or)),
             "x_rel": float(np.linalg.norm(x - x_or) / np.linalg.norm(x_or)),
+            "g_max_rel": float(np.abs(g - g_or).max() / np.abs(g_or).max()),
+            "x_max_rel": float(np.abs(x - x_or).max() / np.abs(x_or).max()),
             "reference": f"tests/golden/{name}.json (oracle, FP64)"}
+
+
+def arith_record(r, name, base=None):
+    """Throughput, per-phase times and error of one arithmetic's run."""
+    v = r["steps"] / r["elapsed"]
+    out = {"value": v, "ms_per_step": 1e3 * r["elapsed"] / r["steps"],
+           "step_ms": step_summary(r),
+           "error_vs_oracle": oracle_error(name, r["cold"]),
+           "ctm_iters_per_step": [t["iters"] for t in r["timed"]]}
+    if base is not None:
+        sb, sr = step_summary(base), out["step_ms"]
+        out["speedup_vs_fp64"] = v / (base["steps"] / base["elapsed"])
+        # equal work: the K-step gradient and the 20-iteration CG do the
+        # same iterations in every arithmetic; CTMRG per iteration
+        out["speedup_vs_fp64_equal_work"] = {
+            "energy_grad": sb["phase_ms"]["energy_grad"] /
+            sr["phase_ms"]["energy_grad"],
+            "precond_apply": sb["phase_ms"]["precond_apply"] /
+            sr["phase_ms"]["precond_apply"],
+            "per_ctm_iteration": sb["ms_per_ctm_iteration"] /
+            sr["ms_per_ctm_iteration"]}
+    if r["prof"] is not None:
+        n, t, fl, _ = r["prof"][r["fam"]]
+        out["gemm_tflops"] = fl / t / 1e12 if t > 0 else 0.0
+    return out
+
+
+def lbfgs_leg(name, prec, iters):
+    """Iterations of the preconditioned L-BFGS (ipeps_lbfgs_step) on the
+    workload's state: seconds and evaluations per iteration."""
+    from paper_2511_09546_amd import binding, inputs
+    w = inputs.WORKLOADS[name]
+    A = inputs.workload_state(name)
+    terms = inputs.workload_terms(name)
+    o = binding.default_opts()
+    o.prec = PRECS[prec]
+    p = binding.lbfgs_default_params()
+    rec = []
+    with binding.Context(A, w["chi"], opts=o) as ctx:
+        t0 = time.perf_counter()
+        with binding.Lbfgs(ctx, terms, p) as opt:
+            t1 = time.perf_counter()
+            e0 = opt.e0
+            for _ in range(iters):
+                t = time.perf_counter()
+                info = opt.step()
+                info["seconds"] = time.perf_counter() - t
+                rec.append(info)
+                print(f"[lbfgs] {info}", file=sys.stderr, flush=True)
+    secs = sum(r["seconds"] for r in rec)
+    return {"workload": f"{name}, {prec} contractions, local-metric "
+                        "preconditioned, m=200, Hager-Zhang, delta = |dE|",
+            "first_evaluation_s": t1 - t0, "e0": e0,
+            "energies": [r["e"] for r in rec],
+            "evals_per_iteration": [r["n_evals"] for r in rec],
+            "seconds_per_iteration": secs / max(len(rec), 1),
+            "iterations": len(rec)}
 
 
 def main():
@@ -219,11 +321,15 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16",
                                                        "fp64"])
     ap.add_argument("--no-fp64", action="store_true",
-                    help="skip the plain FP64 and the other mixed runs")
+                    help="skip the plain FP64 and the other arithmetics")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--checkpoint", action="store_true",
                     help="checkpointed gradient (recompute each unrolled "
                          "iteration in the backward pass)")
+    ap.add_argument("--serve-requests", type=int, default=128,
+                    help="prefix of the seeded request stream to replay "
+                         "(0: no serving leg)")
+    ap.add_argument("--no-lbfgs", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
@@ -242,11 +348,17 @@ def main():
 
     ck = 1 if args.checkpoint else 0
     head = run(name, args.prec, args.steps, args.warmup, ck)
-    base = other = None
+    base = None
+    others = {}
     if args.prec != "fp64" and not args.no_fp64:
+        base = run(name, "fp64", args.steps, args.warmup, ck, profile=False)
         oprec = "bf16" if args.prec == "fp32" else "fp32"
-        other = (oprec, run(name, oprec, args.steps, args.warmup, ck))
-        base = run(name, "fp64", args.steps, args.warmup, ck)
+        others[oprec] = run(name, oprec, args.steps, args.warmup, ck)
+        short = max(3, args.steps // 4)
+        others["bf16x1"] = run(name, "bf16x1", short, args.warmup, ck,
+                               profile=False)
+        others["bf16_ladder"] = run(name, "bf16", short, args.warmup, ck,
+                                    ladder=1, profile=False)
 
     timed, elapsed = head["timed"], head["elapsed"]
     n_g, t_g, fl_g, by_g = head["prof"][head["fam"]]
@@ -311,31 +423,23 @@ def main():
         "svd_stats": head["stats"],
     }
     if base is not None:
-        v64 = args.steps / base["elapsed"]
-        e_b = base["infos"][0]["e"] if base["infos"] else None
-
-        def ediff(r):
-            e = r["infos"][0]["e"] if r["infos"] else None
-            return abs(e - e_b) if e is not None and e_b is not None else None
-
-        out["plain_fp64"] = {
-            "value": v64, "ms_per_step": 1e3 * base["elapsed"] / args.steps,
-            "speedup": value / v64,
-            "step_ms": step_summary(base),
-            "error_vs_oracle": oracle_error(name, base["cold"]),
-            "ctm_iters_per_step": [t["iters"] for t in base["timed"]],
-            "cold_step_energy_abs_diff": ediff(head)}
-        oprec, o = other
-        vo = args.steps / o["elapsed"]
-        n_o, t_o, fl_o, _ = o["prof"][o["fam"]]
-        out[f"{oprec}_contractions"] = {
-            "value": vo, "ms_per_step": 1e3 * o["elapsed"] / args.steps,
-            "speedup_vs_fp64": vo / v64,
-            "step_ms": step_summary(o),
-            "error_vs_oracle": oracle_error(name, o["cold"]),
-            "ctm_iters_per_step": [t["iters"] for t in o["timed"]],
-            "cold_step_energy_abs_diff_vs_fp64": ediff(o),
-            "gemm_tflops": fl_o / t_o / 1e12 if t_o > 0 else 0.0}
+        rb = arith_record(base, name)
+        rb["cold_step_energy_abs_diff"] = (
+            abs(head["infos"][0]["e"] - base["infos"][0]["e"])
+            if head["infos"] and base["infos"] else None)
+        hb = arith_record(head, name, base)
+        rb["speedup"] = hb["speedup_vs_fp64"]
+        rb["speedup_equal_work"] = hb["speedup_vs_fp64_equal_work"]
+        out["plain_fp64"] = rb
+        for k, r in others.items():
+            out[f"{k}_contractions"] = arith_record(r, name, base)
+    if args.serve_requests > 0:
+        from paper_2511_09546_amd import serve
+        out["serving"] = serve.replay(args.serve_requests, 20.0, 5,
+                                      binding.FP32, 8, 230.0, check_solo=16)
+        out["serving"]["prefix_of"] = 256
+    if not args.no_lbfgs:
+        out["lbfgs"] = lbfgs_leg(name, args.prec, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, n_conv)
     print(json.dumps(out), flush=True)

@@ -44,6 +44,8 @@ typedef enum {
   IPEPS_OK = 0,
   IPEPS_NOT_CONVERGED = 1,  /* warning: Delta >= tol after max_iter; the
                                environment of the last iteration is kept */
+  IPEPS_STATIONARY = 2,     /* warning (ipeps_lbfgs_step): no descent
+                               direction left; nothing was changed */
   IPEPS_EINVAL = -1,        /* bad argument (null pointer, sizes, non-finite
                                values, chi < D^2, delta <= 0, ...) */
   IPEPS_ENOMEM = -2,        /* device allocation failed */
@@ -246,6 +248,13 @@ int ipeps_corner_spectra(ipeps_ctx* ctx, double* out);
 int ipeps_get_env(ipeps_ctx* ctx, double* out);
 int ipeps_set_env(ipeps_ctx* ctx, const double* in);
 
+/* Device-pointer twins of ipeps_get_env / ipeps_set_env: the same layout
+ * and size, in device memory the caller keeps (e.g. environments kept
+ * resident as warm starts by a request loop); non-finite values are not
+ * detected.  Return after the copy is complete.  Errors: EINVAL, EHIP. */
+int ipeps_get_env_dev(ipeps_ctx* ctx, double* d_out);
+int ipeps_set_env_dev(ipeps_ctx* ctx, const double* d_in);
+
 /* Size in doubles of the environment buffer of ipeps_get_env. */
 size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
 
@@ -276,6 +285,110 @@ size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
 int ipeps_profile_enable(ipeps_ctx* ctx, int on);
 int ipeps_profile_read(ipeps_ctx* ctx, int family, long* launches,
                        double* seconds, double* flop, double* bytes);
+
+/* ------------------------------------------------------------------------
+ * Belief-propagation preconditioner (Sec. III A after Eq. (11); App. A):
+ * the local metric with environment bond dimension 1, the environment of a
+ * site being the product of four D x D messages that belief propagation on
+ * the double-layer network provides (a mean-field environment).
+ *
+ * bp_converge: parallel message updates from the trace message (or from the
+ * context's previous messages: a warm start) until the largest change of a
+ * normalised message (unit Frobenius norm, positive trace) is below tol or
+ * max_iter updates.  Returns OK, NOT_CONVERGED (warning, messages kept), or
+ * an error.  The messages belong to the site tensors at the call; a new
+ * state (ctm_set_state*) needs a new bp_converge. */
+int bp_converge(ipeps_ctx* ctx, double tol, int max_iter, int* n_iter,
+                double* change);
+
+/* Messages of the last bp_converge, host out[Ly*Lx][4][D*D]: the message
+ * arriving at the left, up, right and down leg of each site, as row-major
+ * D x D matrices on the leg's (ket, bra) pair.  Errors: EINVAL, ESTATE. */
+int ipeps_bp_messages(ipeps_ctx* ctx, double* out);
+
+/* x = (N_BP + delta I)^-1 g per site, N_BP x = (E x) / Z with
+ * E = m_l (x) m_u (x) m_r (x) m_d and Z = <A, E A>, applied in closed form
+ * in the eigenbasis of the (symmetrised) messages.  g, x: layout of A, host
+ * (precond_apply_bp) or device pointers (precond_apply_bp_dev).  Errors:
+ * EINVAL, ESTATE (no bp_converge for the current state), EHIP. */
+int precond_apply_bp(ipeps_ctx* ctx, const double* g, double delta,
+                     double* x);
+int precond_apply_bp_dev(ipeps_ctx* ctx, const double* d_g, double delta,
+                         double* d_x);
+
+/* ------------------------------------------------------------------------
+ * Preconditioned L-BFGS on the state of a context (Sec. II, Eqs. (1)-(4):
+ * the preconditioned gradient P^-1 g enters the quasi-Newton update; the
+ * regularised local metric P = N_local + delta I of Sec. III B with an
+ * adaptive delta; L-BFGS with history m = 200 and the Hager-Zhang line
+ * search of Sec. IV A).  The two-loop recursion starts from H_0 = P^-1
+ * (one precond_apply solve at the current point per iteration) or, with
+ * precondition = 0, from H_0 = gamma I (gamma = s^T y / y^T y of the newest
+ * pair).  Every line-search evaluation writes x + a d into the context,
+ * converges its environment from the previous one (ctm_tol, ctm_max_iter)
+ * and takes the energy and the gradient in the context's gradient mode and
+ * arithmetic.  A step is accepted at the first evaluation meeting the Wolfe
+ * or the approximate Wolfe condition of Hager and Zhang (parameters hz_*);
+ * after max_evals evaluations the step with the lowest energy is taken.
+ * A pair (s, y) enters the history when s^T y > 1e-12 |s| |y|.  The first
+ * trial step is 1 (psi0 max|x| / max|g| for the first iteration without
+ * the preconditioner).  delta_mode: 0 fixed delta0, 1 |E_{k+1} - E_k|,
+ * 2 |g_{k+1}|^2, clamped to [delta_min, delta_max]. */
+typedef struct {
+  int m;               /* history pairs (200) */
+  int precondition;    /* 1 (default): H_0 = P^-1 with the local metric;
+                          2: with the belief-propagation metric
+                          (bp_converge to ctm_tol within ctm_max_iter
+                          updates at every point, precond_apply_bp);
+                          0: H_0 = gamma I */
+  int delta_mode;      /* 0 fixed, 1 energy change (default), 2 |g|^2 */
+  double delta0;       /* delta of the first iteration (1e-2) */
+  double delta_min, delta_max;  /* clamp of the adaptive delta (1e-12, 1) */
+  double ctm_tol;      /* CTMRG tolerance of every evaluation (1e-10) */
+  int ctm_max_iter;    /* (200) */
+  double cg_tol;       /* preconditioner CG: relative residual (0) */
+  int cg_maxiter;      /* and iteration count (20) */
+  int max_evals;       /* line-search evaluations per iteration (20) */
+  double psi0;         /* first trial step without preconditioner (0.01) */
+  double hz_delta, hz_sigma, hz_eps, hz_theta, hz_gamma, hz_rho;
+                       /* 0.1, 0.9, 1e-6, 0.5, 0.66, 5 */
+} ipeps_lbfgs_params;
+
+typedef struct {
+  double e;            /* energy per site at the new point */
+  double alpha;        /* accepted step along the direction */
+  int n_evals;         /* energy+gradient evaluations of the iteration */
+  int ls_ok;           /* 1: the step met the line-search conditions */
+  double gnorm;        /* |g| at the new point */
+  double delta;        /* delta for the next iteration */
+  int ctm_iters;       /* CTMRG iterations of the iteration's evaluations */
+} ipeps_lbfgs_info;
+
+typedef struct ipeps_lbfgs ipeps_lbfgs;
+
+void ipeps_lbfgs_default_params(ipeps_lbfgs_params* p);
+
+/* Create an optimiser for the context's current state and Hamiltonian
+ * (terms copied) and evaluate there (e0: energy per site, may be NULL).
+ * The optimiser keeps device buffers in the context (2 m + 7 state-sized
+ * vectors) and must be freed before the context.  params NULL = defaults.
+ * Errors: EINVAL, ENOMEM, EHIP; warning NOT_CONVERGED. */
+int ipeps_lbfgs_create(ipeps_ctx* ctx, int n_terms, const ipeps_term* terms,
+                       const ipeps_lbfgs_params* params, ipeps_lbfgs** opt,
+                       double* e0);
+
+/* One iteration: direction, line search, history update; the context
+ * holds the new state and its environment afterwards (read A with
+ * ipeps_get_state).  info may be NULL.  Returns OK; NOT_CONVERGED when the
+ * line search ended without meeting its conditions or an evaluation
+ * returned a warning (the step is still taken); STATIONARY when no descent
+ * direction exists (nothing changed); or an error. */
+int ipeps_lbfgs_step(ipeps_lbfgs* opt, ipeps_lbfgs_info* info);
+
+void ipeps_lbfgs_free(ipeps_lbfgs* opt);
+
+/* Copy the context's site tensors to the host, layout of A. */
+int ipeps_get_state(ipeps_ctx* ctx, double* A);
 
 /* Release the context and all its device memory (NULL is a no-op). */
 void ctm_free(ipeps_ctx* ctx);

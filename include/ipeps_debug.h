@@ -59,7 +59,8 @@ int ipeps_debug_permute(int rank, const long* shape, const int* perm,
  * number of unrolled iterations of the last gradient, out[8] projector SVDs
  * and out[9] complement solves that stopped at their iteration limit above
  * their tolerance, out[10] the arithmetic (ipeps_prec) the context's next
- * contractions use (out has 11 entries). */
+ * contractions use, out[11] the largest true relative residual of a
+ * complement solve (recorded with test hook 4; out has 12 entries). */
 struct ipeps_ctx;
 int ipeps_debug_stats(struct ipeps_ctx* ctx, double* out);
 
@@ -69,7 +70,11 @@ int ipeps_debug_stats(struct ipeps_ctx* ctx, double* out);
  *   kind 1  device-memory budget of the context: allocations that would
  *           take the bytes in use above `value` fail (ENOMEM from the call);
  *   kind 2  precond_apply stops before CG iteration `value` as if it had
- *           met p^T (N + delta) p <= 0 (ECG_BREAKDOWN, x = last iterate).
+ *           met p^T (N + delta) p <= 0 (ECG_BREAKDOWN, x = last iterate);
+ *   kind 3  deflation vectors per half of the complement solves of the
+ *           projector backward: at most `value` (32; 0 = no deflation);
+ *   kind 4  value != 0: after every complement solve, recompute its true
+ *           residual (ipeps_debug_stats out[11]).
  * Returns a status (EINVAL for an unknown kind or a negative value). */
 int ipeps_debug_set_fault(struct ipeps_ctx* ctx, int kind, double value);
 

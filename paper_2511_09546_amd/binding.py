@@ -29,10 +29,14 @@ API_FUNCTIONS = [
     "ipeps_default_opts", "ctm_init", "ctm_set_state", "ctm_converge",
     "ipeps_energy_grad", "precond_apply", "ipeps_corner_spectra",
     "ipeps_get_env", "ipeps_set_env", "ipeps_env_size", "ctm_free",
+    "ipeps_get_env_dev", "ipeps_set_env_dev", "bp_converge",
+    "ipeps_bp_messages", "precond_apply_bp", "precond_apply_bp_dev",
     "ipeps_strerror", "ipeps_version", "ipeps_profile_enable",
     "ipeps_profile_read", "ctm_set_state_dev", "ipeps_energy_grad_dev",
     "precond_apply_dev", "ipeps_footprint_bytes",
     "precond_apply_dev_noalloc", "precond_noalloc_bytes",
+    "ipeps_lbfgs_default_params", "ipeps_lbfgs_create", "ipeps_lbfgs_step",
+    "ipeps_lbfgs_free", "ipeps_get_state",
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
 PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
@@ -89,6 +93,19 @@ def load():
     lib.ipeps_corner_spectra.argtypes = [c_void_p, _DP]
     lib.ipeps_get_env.argtypes = [c_void_p, _DP]
     lib.ipeps_set_env.argtypes = [c_void_p, _DP]
+    lib.ipeps_get_env_dev.argtypes = [c_void_p, c_void_p]
+    lib.ipeps_get_env_dev.restype = c_int
+    lib.bp_converge.argtypes = [c_void_p, c_double, c_int, _IP, _DP]
+    lib.bp_converge.restype = c_int
+    lib.ipeps_bp_messages.argtypes = [c_void_p, _DP]
+    lib.ipeps_bp_messages.restype = c_int
+    lib.precond_apply_bp.argtypes = [c_void_p, _DP, c_double, _DP]
+    lib.precond_apply_bp.restype = c_int
+    lib.precond_apply_bp_dev.argtypes = [c_void_p, c_void_p, c_double,
+                                         c_void_p]
+    lib.precond_apply_bp_dev.restype = c_int
+    lib.ipeps_set_env_dev.argtypes = [c_void_p, c_void_p]
+    lib.ipeps_set_env_dev.restype = c_int
     lib.ipeps_env_size.argtypes = [c_int, c_int, c_int, c_int]
     lib.ipeps_env_size.restype = c_size_t
     lib.ipeps_footprint_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int,
@@ -342,7 +359,7 @@ class Context:
         return n.value, sec.value, fl.value, by.value
 
     def stats(self) -> dict:
-        out = np.zeros(11)
+        out = np.zeros(12)
         st = load().ipeps_debug_stats(self._h, _dp(out))
         if st != OK:
             raise IpepsError(st, "ipeps_debug_stats")
@@ -351,7 +368,7 @@ class Context:
                     cg_solves=int(out[4]), pool_bytes=int(out[5]),
                     peak_live_bytes=int(out[6]), grad_K_used=int(out[7]),
                     svd_unconverged=int(out[8]), cg_unconverged=int(out[9]),
-                    work_prec=int(out[10]))
+                    work_prec=int(out[10]), cg_true_residual=float(out[11]))
 
     def set_fault(self, kind: int, value: float = 0.0):
         """Failure injection (ipeps_debug_set_fault): 0 clear, 1 memory
@@ -367,6 +384,51 @@ class Context:
         st = load().ipeps_set_env(self._h, _dp(buf))
         if st != OK:
             raise IpepsError(st, "ipeps_set_env")
+
+    # ---- belief-propagation (chi = 1) preconditioner
+    def bp_converge(self, tol: float = 1e-12, max_iter: int = 500):
+        """Returns (updates, last change, converged)."""
+        n = c_int(0)
+        ch = c_double(0.0)
+        st = load().bp_converge(self._h, tol, max_iter, ctypes.byref(n),
+                                ctypes.byref(ch))
+        if st < 0:
+            raise IpepsError(st, "bp_converge")
+        return n.value, ch.value, st == OK
+
+    def bp_messages(self) -> np.ndarray:
+        """[Lx*Ly][4][D][D]: messages into the left, up, right, down legs."""
+        out = np.zeros((self.Lx * self.Ly, 4, self.D, self.D))
+        st = load().ipeps_bp_messages(self._h, _dp(out))
+        if st != OK:
+            raise IpepsError(st, "ipeps_bp_messages")
+        return out
+
+    def precond_bp(self, g, delta: float) -> np.ndarray:
+        g = _f64(g)
+        x = np.zeros(self.shape)
+        st = load().precond_apply_bp(self._h, _dp(g), delta, _dp(x))
+        if st != OK:
+            raise IpepsError(st, "precond_apply_bp")
+        return x
+
+    def precond_bp_dev(self, d_g: int, d_x: int, delta: float):
+        st = load().precond_apply_bp_dev(self._h, c_void_p(d_g), delta,
+                                         c_void_p(d_x))
+        if st != OK:
+            raise IpepsError(st, "precond_apply_bp_dev")
+
+    def get_env_dev(self, d_out: int):
+        """Environment into a device buffer of env_size() doubles."""
+        st = load().ipeps_get_env_dev(self._h, c_void_p(d_out))
+        if st != OK:
+            raise IpepsError(st, "ipeps_get_env_dev")
+
+    def set_env_dev(self, d_in: int):
+        """Environment from a device buffer of env_size() doubles."""
+        st = load().ipeps_set_env_dev(self._h, c_void_p(d_in))
+        if st != OK:
+            raise IpepsError(st, "ipeps_set_env_dev")
 
 
 # ------------------------------------------------------------- test hooks
@@ -441,3 +503,104 @@ def debug_svd_ts(W):
     if st != OK:
         raise IpepsError(st, "ipeps_debug_svd_ts")
     return U, s, J
+
+
+# ------------------------------------------------------------ optimiser
+class LbfgsParams(ctypes.Structure):
+    _fields_ = [("m", c_int), ("precondition", c_int), ("delta_mode", c_int),
+                ("delta0", c_double), ("delta_min", c_double),
+                ("delta_max", c_double), ("ctm_tol", c_double),
+                ("ctm_max_iter", c_int), ("cg_tol", c_double),
+                ("cg_maxiter", c_int), ("max_evals", c_int),
+                ("psi0", c_double), ("hz_delta", c_double),
+                ("hz_sigma", c_double), ("hz_eps", c_double),
+                ("hz_theta", c_double), ("hz_gamma", c_double),
+                ("hz_rho", c_double)]
+
+
+class LbfgsInfo(ctypes.Structure):
+    _fields_ = [("e", c_double), ("alpha", c_double), ("n_evals", c_int),
+                ("ls_ok", c_int), ("gnorm", c_double), ("delta", c_double),
+                ("ctm_iters", c_int)]
+
+
+STATIONARY = 2
+
+
+def _load_lbfgs(lib):
+    if getattr(lib, "_lbfgs_ready", False):
+        return lib
+    lib.ipeps_lbfgs_default_params.argtypes = [POINTER(LbfgsParams)]
+    lib.ipeps_lbfgs_default_params.restype = None
+    lib.ipeps_lbfgs_create.argtypes = [c_void_p, c_int, POINTER(Term),
+                                       POINTER(LbfgsParams),
+                                       POINTER(c_void_p), _DP]
+    lib.ipeps_lbfgs_create.restype = c_int
+    lib.ipeps_lbfgs_step.argtypes = [c_void_p, POINTER(LbfgsInfo)]
+    lib.ipeps_lbfgs_step.restype = c_int
+    lib.ipeps_lbfgs_free.argtypes = [c_void_p]
+    lib.ipeps_lbfgs_free.restype = None
+    lib.ipeps_get_state.argtypes = [c_void_p, _DP]
+    lib.ipeps_get_state.restype = c_int
+    lib._lbfgs_ready = True
+    return lib
+
+
+def lbfgs_default_params() -> LbfgsParams:
+    p = LbfgsParams()
+    _load_lbfgs(load()).ipeps_lbfgs_default_params(ctypes.byref(p))
+    return p
+
+
+def get_state(ctx: "Context") -> np.ndarray:
+    A = np.zeros(ctx.shape)
+    st = _load_lbfgs(load()).ipeps_get_state(ctx._h, _dp(A))
+    if st != OK:
+        raise IpepsError(st, "ipeps_get_state")
+    return A
+
+
+class Lbfgs:
+    """Preconditioned L-BFGS on a context's state (ipeps_lbfgs_*)."""
+
+    def __init__(self, ctx: "Context", terms, params: LbfgsParams = None):
+        lib = _load_lbfgs(load())
+        self._arr, self._keep = make_terms(terms)
+        self.ctx = ctx
+        h = c_void_p()
+        e0 = c_double(0.0)
+        st = lib.ipeps_lbfgs_create(ctx._h, len(terms), self._arr,
+                                    ctypes.byref(params) if params else None,
+                                    ctypes.byref(h), ctypes.byref(e0))
+        if st < 0:
+            raise IpepsError(st, "ipeps_lbfgs_create")
+        self._h = h
+        self.e0 = e0.value
+        self.last_status = st
+
+    def step(self) -> dict:
+        info = LbfgsInfo()
+        st = load().ipeps_lbfgs_step(self._h, ctypes.byref(info))
+        if st < 0:
+            raise IpepsError(st, "ipeps_lbfgs_step")
+        self.last_status = st
+        return dict(e=info.e, alpha=info.alpha, n_evals=info.n_evals,
+                    ls_ok=bool(info.ls_ok), gnorm=info.gnorm,
+                    delta=info.delta, ctm_iters=info.ctm_iters, status=st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ipeps_lbfgs_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

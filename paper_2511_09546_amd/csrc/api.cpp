@@ -15,21 +15,7 @@ namespace {
 
 template <class F>
 int guarded(F&& f) {
-  try {
-    return f();
-  } catch (const ArgError&) {
-    return IPEPS_EINVAL;
-  } catch (const NotImplError&) {
-    return IPEPS_ENOTIMPL;
-  } catch (const OomError&) {
-    return IPEPS_ENOMEM;
-  } catch (const std::bad_alloc&) {
-    return IPEPS_ENOMEM;
-  } catch (const HipError&) {
-    return IPEPS_EHIP;
-  } catch (...) {
-    return IPEPS_EHIP;
-  }
+  return guarded_call(std::forward<F>(f));
 }
 
 bool all_finite(const double* p, size_t n) {
@@ -67,6 +53,7 @@ const char* ipeps_strerror(int s) {
   switch (s) {
     case IPEPS_OK: return "ok";
     case IPEPS_NOT_CONVERGED: return "not converged (warning)";
+    case IPEPS_STATIONARY: return "stationary point: no descent direction";
     case IPEPS_EINVAL: return "invalid argument";
     case IPEPS_ENOMEM: return "device out of memory";
     case IPEPS_EHIP: return "HIP runtime error";
@@ -197,73 +184,16 @@ int ctm_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
                  double* delta) {
   if (!c || max_iter < 0 || std::isnan(tol)) return IPEPS_EINVAL;
   Context& cx = c->cx;
-  int it = 0;
+  int it = 0, warn = 0;
   double dl = INFINITY;
-  const double svd_tol = cx.svd.tol;
-  const long svd_bad0 = cx.stats.svd_unconverged;
-  // the spectrum change cannot fall below the rounding of the contraction
-  // arithmetic: tolerances under that floor are raised to it (with the
-  // precision ladder, to the floor of the arithmetic of the last rung)
-  const double tol_in = tol;
-  auto eff_tol = [&]() {
-    return tol_in > 0.0
-               ? std::max(tol_in, prec_floors(cx.work_prec).spectra)
-               : tol_in;
-  };
-  tol = eff_tol();
-  // precision ladder: the BF16 rung ends when the spectrum change reaches
-  // its floor or has not fallen below 0.9 of its smallest value for three
-  // iterations; the iterations then continue in FP32
-  double best = INFINITY;
-  int flat = 0;
   int st = guarded([&]() {
-    while (it < max_iter) {
-      PrecScope ps(cx.dev, cx.work_prec);
-      // when iterating to a tolerance, the projector SVD of an iteration
-      // only needs to be as accurate as the environment it produces: its
-      // tolerance follows the last spectrum change (never looser than 1e-6,
-      // never tighter than the configured one), so the final iterations and
-      // the fixed point are computed at full accuracy
-      if (tol > 0.0)
-        cx.svd.tol = std::max(svd_tol, std::min(1e-6, 1e-2 * dl));
-      Env next;
-      ctm_step(cx, cx.env, next);
-      cx.env = next;
-      ++it;
-      dl = corner_spectra_change(cx, cx.env);
-      if (cx.ladder && cx.work_prec != PREC_FP32) {
-        if (dl < 0.9 * best) {
-          best = dl;
-          flat = 0;
-        } else {
-          ++flat;
-        }
-        if (dl < prec_floors(cx.work_prec).spectra || flat >= 3) {
-          cx.work_prec = PREC_FP32;
-          tol = eff_tol();
-          continue;
-        }
-      }
-      if (tol > 0.0 && dl < tol) break;
-    }
-    cx.svd.tol = svd_tol;
-    cx.converged_once = true;
+    warn = converge_env(cx, tol, max_iter, &it, &dl);
     return IPEPS_OK;
   });
-  cx.svd.tol = svd_tol;
   if (st != IPEPS_OK) return st;
   if (n_iter) *n_iter = it;
   if (delta) *delta = dl;
-  if (tol > 0.0 && !(dl < tol)) return IPEPS_NOT_CONVERGED;
-  // a projector SVD that stopped at svd_max_iter above its tolerance
-  if (cx.stats.svd_unconverged != svd_bad0) return IPEPS_NOT_CONVERGED;
-  return IPEPS_OK;
-}
-
-// Arithmetic of the gradient and the preconditioner: the context's, or FP32
-// behind the precision ladder.
-static int late_prec(const Context& cx) {
-  return cx.ladder ? (int)PREC_FP32 : cx.prec;
+  return warn ? IPEPS_NOT_CONVERGED : IPEPS_OK;
 }
 
 // NOT_CONVERGED when a projector SVD or a complement solve of the call
@@ -274,7 +204,9 @@ static int solver_warning(const Context& cx, long svd0, long cg0) {
              : IPEPS_OK;
 }
 
-static int parse_terms(const Context& cx, int n_terms, const ipeps_term* H,
+}  // extern "C"
+
+int ipeps::parse_terms(const Context& cx, int n_terms, const ipeps_term* H,
                        std::vector<TermSpec>& out) {
   if (n_terms < 0 || (n_terms > 0 && !H)) return IPEPS_EINVAL;
   for (int i = 0; i < n_terms; ++i) {
@@ -304,6 +236,8 @@ static int parse_terms(const Context& cx, int n_terms, const ipeps_term* H,
   }
   return IPEPS_OK;
 }
+
+extern "C" {
 
 int ipeps_energy_grad(ipeps_ctx* c, int n_terms, const ipeps_term* H,
                       double* e_per_site, double* grad) {
@@ -398,6 +332,66 @@ int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
   return res;
 }
 
+int bp_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
+                double* change) {
+  if (!c || max_iter < 1 || !(tol >= 0.0)) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  int warn = 0, it = 0;
+  double ch = 0.0;
+  int st = guarded([&]() {
+    warn = ipeps::bp_converge(cx, tol, max_iter, &it, &ch);
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  if (n_iter) *n_iter = it;
+  if (change) *change = ch;
+  return warn ? IPEPS_NOT_CONVERGED : IPEPS_OK;
+}
+
+int ipeps_bp_messages(ipeps_ctx* c, double* out) {
+  if (!c || !out) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!cx.bp_valid) return IPEPS_ESTATE;
+  return guarded([&]() {
+    cx.dev.download(cx.bp_msg, out);
+    return IPEPS_OK;
+  });
+}
+
+int precond_apply_bp(ipeps_ctx* c, const double* g, double delta,
+                     double* x) {
+  if (!c || !g || !x || !(delta > 0.0) || !std::isfinite(delta))
+    return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!all_finite(g, state_size(cx))) return IPEPS_EINVAL;
+  if (!cx.bp_valid) return IPEPS_ESTATE;
+  return guarded([&]() {
+    precondition_bp(cx, g, delta, x, false);
+    return IPEPS_OK;
+  });
+}
+
+int precond_apply_bp_dev(ipeps_ctx* c, const double* d_g, double delta,
+                         double* d_x) {
+  if (!c || !d_g || !d_x || !(delta > 0.0) || !std::isfinite(delta))
+    return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!cx.bp_valid) return IPEPS_ESTATE;
+  return guarded([&]() {
+    precondition_bp(cx, d_g, delta, d_x, true);
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_get_state(ipeps_ctx* c, double* A) {
+  if (!c || !A) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    cx.dev.download(cx.A, A);
+    return IPEPS_OK;
+  });
+}
+
 int ipeps_corner_spectra(ipeps_ctx* c, double* out) {
   if (!c || !out) return IPEPS_EINVAL;
   Context& cx = c->cx;
@@ -433,6 +427,37 @@ int ipeps_set_env(ipeps_ctx* c, const double* in) {
     cx.have_warm = false;
     cx.converged_once = true;
     cx.work_prec = cx.prec;  // a new environment climbs the ladder again
+    (void)corner_spectra_change(cx, cx.env);
+    cx.dev.sync();
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_get_env_dev(ipeps_ctx* c, double* d_out) {
+  if (!c || !d_out) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    const int64_t nc = cx.env.C.numel();
+    axpby(cx.dev, nc, 1.0, cx.env.C.ptr, 0.0, d_out);
+    axpby(cx.dev, cx.env.T.numel(), 1.0, cx.env.T.ptr, 0.0, d_out + nc);
+    cx.dev.sync();
+    return IPEPS_OK;
+  });
+}
+
+int ipeps_set_env_dev(ipeps_ctx* c, const double* d_in) {
+  if (!c || !d_in) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  return guarded([&]() {
+    Env e;
+    e.C = cx.dev.empty({4, cx.nsite(), cx.chi, cx.chi});
+    e.T = cx.dev.empty({4, cx.nsite(), cx.chi, cx.D2, cx.chi});
+    axpby(cx.dev, e.C.numel(), 1.0, d_in, 0.0, e.C.ptr);
+    axpby(cx.dev, e.T.numel(), 1.0, d_in + e.C.numel(), 0.0, e.T.ptr);
+    cx.env = e;
+    cx.have_warm = false;
+    cx.converged_once = true;
+    cx.work_prec = cx.prec;
     (void)corner_spectra_change(cx, cx.env);
     cx.dev.sync();
     return IPEPS_OK;
@@ -477,6 +502,7 @@ int ipeps_debug_stats(ipeps_ctx* c, double* out) {
   out[8] = (double)st.svd_unconverged;
   out[9] = (double)st.cg_unconverged;
   out[10] = (double)c->cx.work_prec;
+  out[11] = st.cg_true_residual;
   return IPEPS_OK;
 }
 
@@ -487,12 +513,20 @@ int ipeps_debug_set_fault(ipeps_ctx* c, int kind, double value) {
     case 0:
       cx.dev.pool.set_limit(SIZE_MAX);
       cx.fault_cg_breakdown_at = -1;
+      cx.defl_max = 32;
+      cx.check_true_residual = false;
       return IPEPS_OK;
     case 1:
       cx.dev.pool.set_limit(value >= 1.8e19 ? SIZE_MAX : (size_t)value);
       return IPEPS_OK;
     case 2:
       cx.fault_cg_breakdown_at = value > 2e9 ? -1 : (int)value;
+      return IPEPS_OK;
+    case 3:
+      cx.defl_max = value > 128 ? 128 : (int)value;
+      return IPEPS_OK;
+    case 4:
+      cx.check_true_residual = value != 0.0;
       return IPEPS_OK;
     default:
       return IPEPS_EINVAL;

@@ -42,6 +42,7 @@ static std::vector<int> rot_perm(int c) {
 // stored in the four clockwise rotations a_c.
 void build_double_layer(Context& cx) {
   const int ns = cx.nsite(), D2 = cx.D2, D = cx.D;
+  cx.bp_valid = false;  // the belief-propagation messages belong to old A
   const int64_t a4 = (int64_t)D2 * D2 * D2 * D2;
   if (cx.a_rot.numel() != ns * 4 * a4)
     cx.a_rot = cx.dev.empty({ns, 4, D2, D2, D2, D2});
@@ -268,6 +269,68 @@ void corner_spectra(Context& cx, const Env& e, Tensor& S) {
   }
   Tensor U, J;
   svd_ts(dev, W, nb, chi, b, U, S, J, dev.cprec == PREC_FP64 ? 1e-15 : 1e-12);
+}
+
+int converge_env(Context& cx, double tol, int max_iter, int* n_iter,
+                 double* delta) {
+  int it = 0;
+  double dl = INFINITY;
+  const double svd_tol = cx.svd.tol;
+  const long svd_bad0 = cx.stats.svd_unconverged;
+  // the spectrum change cannot fall below the rounding of the contraction
+  // arithmetic: tolerances under that floor are raised to it (with the
+  // precision ladder, to the floor of the arithmetic of the last rung)
+  const double tol_in = tol;
+  auto eff_tol = [&]() {
+    return tol_in > 0.0
+               ? std::max(tol_in, prec_floors(cx.work_prec).spectra)
+               : tol_in;
+  };
+  tol = eff_tol();
+  // precision ladder: the BF16 rung ends when the spectrum change reaches
+  // its floor or has not fallen below 0.9 of its smallest value for three
+  // iterations; the iterations then continue in FP32
+  double best = INFINITY;
+  int flat = 0;
+  struct RestoreTol {
+    Context& c;
+    double t;
+    ~RestoreTol() { c.svd.tol = t; }
+  } restore{cx, svd_tol};
+  while (it < max_iter) {
+    PrecScope ps(cx.dev, cx.work_prec);
+    // when iterating to a tolerance, the projector SVD of an iteration only
+    // needs to be as accurate as the environment it produces: its tolerance
+    // follows the last spectrum change (never looser than 1e-6, never
+    // tighter than the configured one), so the final iterations and the
+    // fixed point are computed at full accuracy
+    if (tol > 0.0) cx.svd.tol = std::max(svd_tol, std::min(1e-6, 1e-2 * dl));
+    Env next;
+    ctm_step(cx, cx.env, next);
+    cx.env = next;
+    ++it;
+    dl = corner_spectra_change(cx, cx.env);
+    if (cx.ladder && cx.work_prec != PREC_FP32) {
+      if (dl < 0.9 * best) {
+        best = dl;
+        flat = 0;
+      } else {
+        ++flat;
+      }
+      if (dl < prec_floors(cx.work_prec).spectra || flat >= 3) {
+        cx.work_prec = PREC_FP32;
+        tol = eff_tol();
+        continue;
+      }
+    }
+    if (tol > 0.0 && dl < tol) break;
+  }
+  cx.converged_once = true;
+  if (n_iter) *n_iter = it;
+  if (delta) *delta = dl;
+  if (tol > 0.0 && !(dl < tol)) return 1;
+  // a projector SVD that stopped at svd_max_iter above its tolerance
+  return cx.stats.svd_unconverged != svd_bad0 ? 1 : 0;
 }
 
 double corner_spectra_change(Context& cx, const Env& e) {

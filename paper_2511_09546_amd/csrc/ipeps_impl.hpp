@@ -2,12 +2,36 @@
 #pragma once
 
 #include <array>
+#include <new>
+#include <utility>
 #include <vector>
 
+#include "../../include/ipeps.h"
 #include "ad.hpp"
 #include "engine.hpp"
 
 namespace ipeps {
+
+// Runs f (returning a status) and maps the engine's exceptions to status
+// codes: the C ABI never throws.
+template <class F>
+int guarded_call(F&& f) {
+  try {
+    return f();
+  } catch (const ArgError&) {
+    return IPEPS_EINVAL;
+  } catch (const NotImplError&) {
+    return IPEPS_ENOTIMPL;
+  } catch (const OomError&) {
+    return IPEPS_ENOMEM;
+  } catch (const std::bad_alloc&) {
+    return IPEPS_ENOMEM;
+  } catch (const HipError&) {
+    return IPEPS_EHIP;
+  } catch (...) {
+    return IPEPS_EHIP;
+  }
+}
 
 // ---------------------------------------------------------------- SVD
 struct CutBatch {
@@ -43,6 +67,9 @@ struct SvdStats {
   // calls that ended at their iteration limit above the tolerance in effect
   long svd_unconverged = 0;   // projector SVDs (svd_max_iter)
   long cg_unconverged = 0;    // complement solves of the backward pass
+  // largest |rhs - A x| / |rhs| of a complement solve, recomputed after the
+  // solve (only with Context::check_true_residual)
+  double cg_true_residual = 0.0;
 };
 
 // tol2: Jacobi criterion of the second pass (1e-15 gives the full FP64
@@ -116,6 +143,14 @@ struct Context {
   // test hooks: precondition() stops as at a breakdown before this CG
   // iteration (-1: never)
   int fault_cg_breakdown_at = -1;
+  // complement solves of the projector backward: at most this many
+  // deflation vectors per half (32); diagnostics of their true residual
+  int defl_max = 32;
+  bool check_true_residual = false;
+  // belief-propagation messages [nsite][4 legs l, u, r, d][D^2] and whether
+  // they were converged for the current site tensors
+  Tensor bp_msg;
+  bool bp_valid = false;
   SvdParams svd;
   SvdStats stats;
 
@@ -159,6 +194,17 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
                  const std::vector<Var>& arot);
 // Plain forward iteration (nothing recorded).
 void ctm_step(Context& cx, const Env& in, Env& out);
+// CTMRG iterations on the context's environment until the corner-spectrum
+// change is below tol (raised to the floor of the arithmetic; tol <= 0: a
+// fixed count) or max_iter; runs the precision ladder.  Returns 1 when tol
+// was not reached or a projector SVD stopped above its tolerance, else 0.
+int converge_env(Context& cx, double tol, int max_iter, int* n_iter,
+                 double* delta);
+// Arithmetic of the gradient and the preconditioner: the context's, or FP32
+// behind the precision ladder.
+inline int late_prec(const Context& cx) {
+  return cx.ladder ? (int)PREC_FP32 : cx.prec;
+}
 double corner_spectra_change(Context& cx, const Env& e);
 void corner_spectra(Context& cx, const Env& e, Tensor& out);
 
@@ -179,6 +225,9 @@ double energy_ad(Tape& tp, Context& cx, const VEnv& e,
                  const std::vector<Var>& As, const std::vector<Var>& arot,
                  const std::vector<TermSpec>& terms);
 double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms);
+// Checks and copies the Hamiltonian terms of the C ABI (status code).
+int parse_terms(const Context& cx, int n_terms, const ipeps_term* H,
+                std::vector<TermSpec>& out);
 
 // metric.cpp
 // g and x are host pointers, or device pointers when on_device; lean applies
@@ -186,6 +235,14 @@ double energy(Context& cx, const Env& e, const std::vector<TermSpec>& terms);
 int precondition(Context& cx, const double* g, double delta, double cg_tol,
                  int cg_maxiter, double* x, int* n_iter, double* rel_resid,
                  bool on_device = false, bool lean = false);
+// bp.hip: belief-propagation (chi = 1) environment; returns 1 when tol was
+// not reached within max_iter updates
+int bp_converge(Context& cx, double tol, int max_iter, int* n_iter,
+                double* change);
+// x = (N_BP + delta I)^-1 g per site in closed form (g, x host pointers, or
+// device pointers when on_device)
+int precondition_bp(Context& cx, const double* g, double delta, double* x,
+                    bool on_device);
 // Device bytes precondition(..., lean = true) works in at most (an upper
 // estimate of its temporaries, split-K partial sums included).
 size_t precondition_lean_bytes(int nsite, int d, int D, int chi);

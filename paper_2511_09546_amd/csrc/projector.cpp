@@ -221,7 +221,7 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     // complement of W.  The Galerkin quantities are exact for any W, so the
     // solution does not depend on how well the triplets beyond chi have
     // converged; only the iteration count does.
-    int m = std::min(b - chi, 32);
+    int m = std::min(b - chi, cxp->defl_max);
     if (m % 2) --m;
     if (m < 2) m = 0;
     const int m2 = 2 * m, m4 = 4 * m;
@@ -476,6 +476,18 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       }
     }
     if (!done) ++st->cg_unconverged;
+    if (cxp->check_true_residual) {
+      // diagnostics: |rhs - A_j x_j| / |rhs_j| from a fresh application
+      apply(X, AP);
+      axpby(dev, tot, 1.0, rhs.ptr, -1.0, AP.ptr);
+      coldot(dev, AP.ptr, AP.ptr, 2 * n, chi, rp, nc, s2);
+      dev.download(sc, h.data());
+      for (int j = 0; j < nc * chi; ++j)
+        if (h[4 * nc * chi + j] > 0.0)
+          st->cg_true_residual = std::max(
+              st->cg_true_residual,
+              std::sqrt(h[j] / h[4 * nc * chi + j]));
+    }
     st->cg_iters += it;
     st->cg_solves += nc;
     cxp->cg_warm = X;

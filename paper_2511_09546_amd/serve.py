@@ -2,33 +2,45 @@
 
 Each request is one step of the method on its own state (CTMRG environment,
 energy and K-step gradient, preconditioned direction; Sec. III) and runs in
-its own library context on its own HIP stream, so up to `workers` requests
-execute concurrently and small ones fill the GPU while large ones run.
-Admission follows the device-memory footprint that ipeps_footprint_bytes
-predicts for each request: a request starts only when its footprint fits
-the budget next to those already running (first come first served, later
-requests may start ahead of a waiting large one when they fit).  Contexts
-are freed when their request ends.
+its own library context on one of `workers` HIP streams (torch streams of
+the default priority, handed to ctm_init), so up to `workers` requests
+execute concurrently: requests that arrive while others run are admitted as
+soon as a stream and enough memory are free, and their kernels overlap on
+the device.  Admission follows the device-memory footprint that
+ipeps_footprint_bytes predicts for each request: a request starts only when
+its footprint fits the budget next to those already running and the cached
+environments (first come first served; later requests may start ahead of a
+waiting large one when they fit).  Contexts are freed when their request
+ends.
 
 Checkpointing: a request whose gradient with every unrolled iteration
 resident would take more than its share of the budget (budget / workers)
 runs with the checkpointed gradient (ipeps_opts.grad_checkpoint: one
 iteration resident, recomputed in the backward pass), unless the request
-fixes grad_checkpoint itself; the large requests then no longer run alone.
+fixes grad_checkpoint itself.
 
 Warm starts: a request that carries a `state_key` seen before (same cell,
-D and chi) starts CTMRG from the environment that the earlier request left
-(kept on the host), instead of the trace boundary.  The environment depends
-only on the state, not on the Hamiltonian, so e.g. a sweep of couplings on
-one state converges in a few iterations after the first request.
+D and chi) starts CTMRG from the environment that the earlier request left.
+Those environments stay resident in device memory (ipeps_get_env_dev /
+ipeps_set_env_dev into device buffers), count against the budget, and the
+least recently used ones are dropped when a waiting request needs the room.
+The environment depends only on the state, not on the Hamiltonian, so a
+sweep of couplings on one state converges in a few iterations after the
+first request.
+
+Every request records HIP events on its stream at the start and the end of
+its device work (`Result.window`, milliseconds after the server started), so
+the overlap of requests on the device can be measured.
 
     python -m paper_2511_09546_amd.serve [--requests 256] [--rate 20]
         [--workers 8] [--prec fp32] [--budget-gb 230] [--seed 5]
+        [--check-solo 16]
 
 replays a seeded stream of requests (exponential inter-arrival times, D in
 3..6, chi in 2D^2..3D^2, J1-J2 with J2 in [0, 0.6], random states) in real
 time and prints one JSON line: latency percentiles (finish - arrival),
-throughput and the admission statistics.
+throughput, the admission statistics, the device overlap, and how many of a
+sample of requests gave bitwise the results of the same request run alone.
 """
 from __future__ import annotations
 
@@ -76,6 +88,7 @@ class Result:
     arrival: float
     start: float
     finish: float
+    window: tuple = (0.0, 0.0)    # device work, ms after the server start
 
     @property
     def latency(self) -> float:
@@ -99,6 +112,17 @@ def request_footprint(req: Request, ckpt: int) -> float:
     return float(binding.footprint_bytes(Lx, Ly, d, D, req.chi, o))
 
 
+def max_overlap(windows) -> int:
+    """Largest number of device-work windows [a, b] open at one time."""
+    ev = sorted([(a, 1) for a, _ in windows] + [(b, -1) for _, b in windows],
+                key=lambda t: (t[0], t[1]))
+    cur = best = 0
+    for _, s in ev:
+        cur += s
+        best = max(best, cur)
+    return best
+
+
 class Server:
     """Footprint-admitted concurrent execution of Requests."""
 
@@ -110,11 +134,16 @@ class Server:
         self.running = 0
         self.queue = collections.deque()
         self.cv = threading.Condition()
-        self.envs = {}                 # state_key -> (shape key, C, T)
+        # state_key -> (shape key, device buffer), least recently used first
+        self.envs = collections.OrderedDict()
+        self.env_bytes = 0.0
         self.pool = cf.ThreadPoolExecutor(max_workers=workers)
         self.closed = False
         self.peak_used = 0.0
         self.max_running = 0
+        self._streams = None           # created on the first device step
+        self._free_streams = list(range(workers))
+        self._ref = None
         self.sched = threading.Thread(target=self._schedule, daemon=True)
         self.sched.start()
 
@@ -140,6 +169,15 @@ class Server:
             self.cv.notify_all()
         return fut
 
+    def _evict_for(self, fp: float) -> bool:
+        """Drop least recently used environments until fp fits (cv held)."""
+        while self.envs and self.used + fp > self.budget:
+            _, (_, buf) = self.envs.popitem(last=False)
+            nbytes = float(buf.numel() * 8)
+            self.env_bytes -= nbytes
+            self.used -= nbytes
+        return self.used + fp <= self.budget
+
     def _schedule(self):
         while True:
             with self.cv:
@@ -152,6 +190,11 @@ class Server:
                             if self.used + fp <= self.budget:
                                 pick = i
                                 break
+                        if pick is None and self.queue and self.running == 0:
+                            # nothing runs: room can only come from the
+                            # environment cache
+                            if self._evict_for(self.queue[0][1]):
+                                pick = 0
                     if pick is not None:
                         break
                     self.cv.wait()
@@ -161,12 +204,13 @@ class Server:
                 self.running += 1
                 self.peak_used = max(self.peak_used, self.used)
                 self.max_running = max(self.max_running, self.running)
-            self.pool.submit(self._run, req, fp, fut)
+                sidx = self._free_streams.pop()
+            self.pool.submit(self._run, req, fp, fut, sidx)
 
-    def _run(self, req: Request, fp: float, fut: cf.Future):
+    def _run(self, req: Request, fp: float, fut: cf.Future, sidx: int = 0):
         start = time.perf_counter()
         try:
-            res = self._step(req, start)
+            res = self._step(req, start, sidx)
             fut.set_result(res)
         except BaseException as ex:  # delivered to the caller
             fut.set_exception(ex)
@@ -174,9 +218,25 @@ class Server:
             with self.cv:
                 self.used -= fp
                 self.running -= 1
+                self._free_streams.append(sidx)
                 self.cv.notify_all()
 
-    def _step(self, req: Request, start: float) -> Result:
+    def _device(self):
+        """The worker streams (default priority) and the reference event,
+        created once."""
+        import torch
+        with self.cv:
+            if self._streams is None:
+                self._streams = [torch.cuda.Stream()
+                                 for _ in range(self.workers)]
+                self._ref = torch.cuda.Event(enable_timing=True)
+                self._ref.record()
+                torch.cuda.synchronize()
+        return torch
+
+    def _step(self, req: Request, start: float, sidx: int = 0) -> Result:
+        torch = self._device()
+        stream = self._streams[sidx]
         Lx, Ly, d, D = _shape(req.A)
         o = binding.default_opts()
         o.prec = req.prec
@@ -184,24 +244,49 @@ class Server:
         o.grad_checkpoint = self.checkpoint(req)
         key = (Lx, Ly, d, D, req.chi)
         warm = False
-        with binding.Context(req.A, req.chi, opts=o) as ctx:
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        with binding.Context(req.A, req.chi, opts=o,
+                             stream=stream.cuda_stream) as ctx:
             if req.state_key is not None:
                 with self.cv:
                     cached = self.envs.get(req.state_key)
+                    if cached is not None:
+                        self.envs.move_to_end(req.state_key)
                 if cached is not None and cached[0] == key:
-                    ctx.set_env(cached[1], cached[2])
+                    ctx.set_env_dev(cached[1].data_ptr())
                     warm = True
             it, dl, ok = ctx.converge(req.tol, req.max_iter)
             if req.state_key is not None:
-                C, T = ctx.get_env()
-                with self.cv:
-                    self.envs[req.state_key] = (key, C, T)
+                self._keep_env(req.state_key, key, ctx, torch, stream)
             e, g = ctx.energy_grad(req.terms, grad=True)
             x, cg_it, res, brk = ctx.precond(g, req.delta, req.cg_tol,
                                              req.cg_maxiter)
+            t1.record(stream)
+        t1.synchronize()
+        window = (self._ref.elapsed_time(t0), self._ref.elapsed_time(t1))
         return Result(e=e, g=g, x=x, ctm_iters=it, delta=dl, cg_iters=cg_it,
                       warm=warm, arrival=req.arrival, start=start,
-                      finish=time.perf_counter())
+                      finish=time.perf_counter(), window=window)
+
+    def _keep_env(self, skey, key, ctx, torch, stream):
+        """Copy the context's environment into a resident device buffer of
+        the cache (counted against the budget)."""
+        n = ctx.env_size()
+        with self.cv:
+            old = self.envs.pop(skey, None)
+            if old is not None:
+                self.env_bytes -= old[1].numel() * 8
+                self.used -= old[1].numel() * 8
+        with torch.cuda.stream(stream):
+            buf = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.get_env_dev(buf.data_ptr())
+        with self.cv:
+            self.envs[skey] = (key, buf)
+            self.env_bytes += n * 8
+            self.used += n * 8
+            self.peak_used = max(self.peak_used, self.used)
 
     def close(self):
         with self.cv:
@@ -230,18 +315,25 @@ def request_stream(n: int, rate: float, seed: int, prec: int):
     return out
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=256)
-    ap.add_argument("--rate", type=float, default=20.0)
-    ap.add_argument("--workers", type=int, default=8)
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--budget-gb", type=float, default=230.0)
-    ap.add_argument("--seed", type=int, default=5)
-    args = ap.parse_args(argv)
-    prec = binding.FP32 if args.prec == "fp32" else binding.FP64
-    stream = request_stream(args.requests, args.rate, args.seed, prec)
-    srv = Server(args.budget_gb * 1e9, args.workers)
+def solo(req: Request, ckpt: int):
+    """(e, g, x, ctm iterations) of a request run alone on its own context."""
+    o = binding.default_opts()
+    o.prec = req.prec
+    o.grad_K = req.grad_K
+    o.grad_checkpoint = ckpt
+    with binding.Context(req.A, req.chi, opts=o) as ctx:
+        it, dl, ok = ctx.converge(req.tol, req.max_iter)
+        e, g = ctx.energy_grad(req.terms, grad=True)
+        x, cg, res, brk = ctx.precond(g, req.delta, req.cg_tol,
+                                      req.cg_maxiter)
+    return e, g, x, it
+
+
+def replay(n: int, rate: float, seed: int, prec: int, workers: int,
+           budget_gb: float, check_solo: int = 0, log=sys.stderr) -> dict:
+    """Replays the seeded stream in real time; returns the record."""
+    stream = request_stream(n, rate, seed, prec)
+    srv = Server(budget_gb * 1e9, workers)
     n_ckpt = sum(srv.checkpoint(r) for _, r in stream)
     t0 = time.perf_counter()
     futs = []
@@ -254,31 +346,62 @@ def main(argv=None):
     results, errors = [], 0
     for i, (req, f) in enumerate(futs):
         try:
-            results.append(f.result())
+            results.append((req, f.result()))
         except Exception as ex:  # counted, reported
             errors += 1
-            print(f"request {i}: {ex}", file=sys.stderr, flush=True)
+            print(f"request {i}: {ex}", file=log, flush=True)
         if (i + 1) % 32 == 0:
-            print(f"{i + 1} requests done", file=sys.stderr, flush=True)
+            print(f"{i + 1} requests done", file=log, flush=True)
     makespan = time.perf_counter() - t0
     srv.close()
-    lat = np.array([r.latency for r in results])
-    svc = np.array([r.finish - r.start for r in results])
+    lat = np.array([r.latency for _, r in results])
+    svc = np.array([r.finish - r.start for _, r in results])
+    wins = [r.window for _, r in results]
+    busy = sum(b - a for a, b in wins)
     out = {
-        "workload": (f"{args.requests} requests, Poisson arrivals at "
-                     f"{args.rate}/s, D 3..6, chi 2D^2..3D^2, J1-J2 random "
-                     f"states, {args.prec} contractions, cold starts"),
-        "requests": args.requests, "errors": errors,
+        "workload": (f"{n} requests, Poisson arrivals at {rate}/s (seed "
+                     f"{seed}), D 3..6, chi 2D^2..3D^2, J1-J2 random "
+                     "states, cold starts"),
+        "requests": n, "errors": errors,
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
         "mean_service_s": float(svc.mean()),
         "throughput_req_per_s": len(results) / makespan,
-        "makespan_s": makespan, "workers": args.workers,
-        "budget_gb": args.budget_gb,
+        "makespan_s": makespan, "workers": workers,
+        "budget_gb": budget_gb,
         "peak_admitted_gb": srv.peak_used / 1e9,
         "max_concurrent": srv.max_running,
+        "max_concurrent_on_device": max_overlap(wins),
+        "device_busy_sum_over_makespan": busy / 1e3 / makespan,
         "checkpointed_requests": n_ckpt,
     }
+    if check_solo > 0 and results:
+        idx = np.linspace(0, len(results) - 1, min(check_solo, len(results)))
+        same = 0
+        for i in sorted(set(int(round(v)) for v in idx)):
+            req, r = results[i]
+            e, g, x, it = solo(req, srv.checkpoint(req))
+            same += int(e == r.e and np.array_equal(g, r.g) and
+                        np.array_equal(x, r.x) and it == r.ctm_iters)
+        out["solo_checked"] = len(set(int(round(v)) for v in idx))
+        out["solo_bitwise_equal"] = same
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--budget-gb", type=float, default=230.0)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--check-solo", type=int, default=16)
+    args = ap.parse_args(argv)
+    prec = binding.FP32 if args.prec == "fp32" else binding.FP64
+    out = replay(args.requests, args.rate, args.seed, prec, args.workers,
+                 args.budget_gb, args.check_solo)
+    out["prec"] = args.prec
     print(json.dumps(out), flush=True)
 
 

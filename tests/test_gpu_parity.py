@@ -93,8 +93,11 @@ def test_converged_energy_and_spectra(name):
     x_or, it2, res2, _ = metric.precondition(env, A, g, w["delta"],
                                              w["cg_tol"], w["cg_maxiter"])
     x_or = x_or.numpy()
+    ex = np.linalg.norm(x - x_or) / np.linalg.norm(x_or)
+    ex_max = np.abs(x - x_or).max() / np.abs(x_or).max()
+    _say(f"  x rel {ex:.2e}, max elementwise / max|x| {ex_max:.2e}")
     assert cg_it == it2
-    assert np.linalg.norm(x - x_or) < 1e-8 * np.linalg.norm(x_or)
+    assert ex < 1e-10 and ex_max < 1e-10
 
 
 def test_errors_and_state():

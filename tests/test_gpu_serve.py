@@ -40,6 +40,9 @@ def test_concurrent_equals_solo(prec, ckpt):
     res = [f.result(timeout=120) for f in futs]
     srv.close()
     assert srv.max_running >= 2
+    # the device-work windows (HIP events on the request streams) of at
+    # least two requests overlap in time
+    assert serve.max_overlap([r.window for r in res]) >= 2
     for r, out in zip(reqs, res):
         e, g, x, it = _solo(r)
         assert out.ctm_iters == it

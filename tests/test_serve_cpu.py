@@ -40,7 +40,7 @@ def test_admission_respects_budget_and_workers(monkeypatch):
     live = {"used": 0.0, "peak": 0.0, "n": 0, "nmax": 0}
     lock = threading.Lock()
 
-    def fake_step(self, req, start):
+    def fake_step(self, req, start, sidx=0):
         fp = self.footprint(req)
         with lock:
             live["used"] += fp
@@ -105,3 +105,11 @@ def test_large_requests_are_checkpointed():
         assert srv.checkpoint(large) == 0
     finally:
         srv.close()
+
+
+def test_max_overlap_of_windows():
+    assert serve.max_overlap([]) == 0
+    assert serve.max_overlap([(0, 1), (2, 3)]) == 1
+    assert serve.max_overlap([(0, 2), (1, 3), (1.5, 1.8)]) == 3
+    # touching windows do not overlap
+    assert serve.max_overlap([(0, 1), (1, 2)]) == 1
