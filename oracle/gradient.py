@@ -13,11 +13,9 @@ enter exactly:
              + diag(Sbar) ] V^T,   F_ij = 1/(s_j^2 - s_i^2)  (i != j),
 
 with the cotangents of the discarded triplets equal to zero, F_ij = 0 when
-both i and j are discarded, the exact 1/x when one of them is kept and the
-other discarded, and the Lorentzian form x/(x^2 + eta^2), eta =
-1e-12 * s_1^2, when both are kept (it differs from 1/x only for
-near-degenerate kept pairs, whose mixing the truncated projectors do not
-see).
+both i and j are discarded, and the Lorentzian form x/(x^2 + eta^2),
+eta = 1e-12 * s_1^2, in place of 1/x (it differs from 1/x only for
+near-degenerate pairs).
 
 Gradient modes (A is real and enters both ket and bra; the gradient is with
 respect to every real entry of every unit-cell tensor):
@@ -64,15 +62,10 @@ class _TruncatedSVD(torch.autograd.Function):
         s2 = S * S
         x = s2[None, :] - s2[:, None]            # x_ij = s_j^2 - s_i^2
         eta = 1e-12 * s2[0]
-        kept = torch.arange(n) < k
-        both = (kept[:, None] & kept[None, :]).to(F64)
-        one = (kept[:, None] ^ kept[None, :]).to(F64)
-        # Lorentzian form between two kept values; exact 1/x between a kept
-        # and a discarded value (a pair split by the truncation); 0 between
-        # two discarded values
-        safe = torch.where(one > 0, x, torch.ones_like(x))
-        F = both * (x / (x * x + eta * eta)) + one / safe
+        F = x / (x * x + eta * eta)
         F.fill_diagonal_(0.0)
+        kept = torch.arange(n) < k
+        F = F * (kept[:, None] | kept[None, :]).to(F64)
         Au = U.transpose(0, 1) @ Ub
         Bv = V.transpose(0, 1) @ Vb
         G = (F * (Au - Au.transpose(0, 1))) * S[None, :] \

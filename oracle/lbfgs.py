@@ -218,10 +218,15 @@ def minimize(fg, x0, n_iter, precond=None, m=200, delta_mode="energy",
             fa, ga = fg(x + a * d)
             ga = np.asarray(ga, dtype=np.float64).ravel()
             cache[a] = (fa, ga)
-            return fa, float(ga @ d)
+            dfa = float(ga @ d)
+            if not (np.isfinite(fa) and np.isfinite(dfa)):
+                return np.inf, np.inf    # unusable point: move back
+            return fa, dfa
 
         a, fa, dfa, nev, ok = hager_zhang(phi, c, f, dphi0, abs(f),
                                          max_evals, hz)
+        if not np.isfinite(fa):
+            a = 0.0                      # no usable point: stay at x
         if a in cache:
             fa, ga = cache[a]
         if not ok or order_last(cache) != a:

@@ -1654,8 +1654,11 @@ void inv_sqrt_clip(Device& dev, double* x, int64_t n, double thr) {
 // H = [(W Phi)^T r; (H W Phi)^T r] ([batch][4m][chi]):
 //   mode 0: c = h1 / (s_j - lambda)                (x0 = W Phi c)
 //   mode 1: c = (s_j h1 - h2) / (s_j - lambda)      (p -= W Phi c)
-// Zero for masked columns (j >= keep) and where s_j - lambda <= 1e-12 s_1
-// (that direction is left out of the deflation space of column j).
+//   mode 2: c = y (s_j + lambda) h1 / (y^2 + eta^2), y = s_j^2 - lambda^2,
+//           eta = 1e-12 s_1^2                        (broadened x0)
+// Zero for masked columns (j >= keep) and, in modes 0 and 1, where
+// s_j - lambda <= 1e-12 s_1 (that direction is left out of the deflation
+// space of column j).
 __global__ void defl_coef_kernel(int mode, const double* S, const int* keep,
                                  const double* lam, int chi, int m2, int sS,
                                  const double* H, double* out) {
@@ -1666,12 +1669,21 @@ __global__ void defl_coef_kernel(int mode, const double* S, const int* keep,
   out += (long)bt * m2 * chi;
   const int k = keep[bt];
   const double guard = 1e-12 * s[0];
+  const double eta = 1e-12 * s[0] * s[0];
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m2 * chi;
        e += gridDim.x * blockDim.x) {
     const int i = e / chi, j = e % chi;
     const double sj = s[j], dd = sj - l[i];
     double v = 0.0;
-    if (j < k && dd > guard) {
+    if (mode == 2) {
+      // broadened Galerkin coefficient y (s_j + lambda) / (y^2 + eta^2),
+      // y = s_j^2 - lambda^2: 1 / (s_j - lambda) away from s_j, bounded
+      // through it
+      if (j < k) {
+        const double y = (sj - l[i]) * (sj + l[i]);
+        v = y / (y * y + eta * eta) * (sj + l[i]) * H[e];
+      }
+    } else if (j < k && dd > guard) {
       const double h1 = H[e];
       v = mode == 0 ? h1 / dd : (sj * h1 - H[m2 * chi + e]) / dd;
     }

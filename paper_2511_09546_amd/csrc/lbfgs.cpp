@@ -359,9 +359,18 @@ struct Lbfgs {
       axpby(dev, n, 1.0, x.ptr, 0.0, xt.ptr);
       axpby(dev, n, a, d.ptr, 1.0, xt.ptr);
       const int it0 = ctm_iters;
-      const double fa = evaluate(xt.ptr, gt.ptr, &ctm_iters);
+      const long cg0 = cx->stats.cg_unconverged;
+      double fa = evaluate(xt.ptr, gt.ptr, &ctm_iters);
       last_eval = a;
-      const double dfa = dotd(gt.ptr, d.ptr);
+      double dfa = dotd(gt.ptr, d.ptr);
+      // a point whose gradient could not be computed (a complement solve
+      // of the SVD adjoint stopped at its limit, or non-finite values) is
+      // treated as infinitely high: the line search moves back from it
+      if (cx->stats.cg_unconverged != cg0 || !std::isfinite(fa) ||
+          !std::isfinite(dfa)) {
+        fa = INFINITY;
+        dfa = INFINITY;
+      }
       if (trace)
         std::fprintf(stderr, "  eval a %.17g f %.17g df %.9e ctm %d\n", a,
                      fa, dfa, ctm_iters - it0);
@@ -371,6 +380,9 @@ struct Lbfgs {
     double a = 0.0, fa = 0.0, dfa = 0.0;
     int nev = 0;
     const bool ok = hz.run(c0, &a, &fa, &dfa, &nev);
+    // no usable point at all: stay at x (evaluated again below, so that
+    // the context holds x's environment)
+    if (!std::isfinite(fa)) a = 0.0;
     if (!ok || last_eval != a) {
       // make the accepted point the evaluated one (context state, gt)
       axpby(dev, n, 1.0, x.ptr, 0.0, xt.ptr);

@@ -403,19 +403,41 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
             cxp->cg_warm.ptr, AP.ptr, 2 * n);
     }
     if (m > 0) {
-      // x0 = x_g + W Phi c with c = (W^T A_j W)^-1 W^T r in the eigenbasis,
-      // r0 = r - A_j W Phi c = r - s_j W Phi c + (H W Phi) c
+      // x += W Phi c and r -= A_j W Phi c = s_j W Phi c - (H W Phi) c for the
+      // coefficients c in Cf
+      Tensor Dx = dev.empty({nc, 2, n, chi});
+      auto galerkin_add = [&]() {
+        gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr, m4, sXi, Cf.ptr,
+             chi, sC, 0.0, Dx.ptr, chi, s2, nc);
+        axpby(dev, tot, 1.0, Dx.ptr, 1.0, X.ptr);
+        col_axpby(dev, nc * 2 * n, chi, -1.0, S.ptr, Dx.ptr, 1.0, R.ptr,
+                  2 * n, b);
+        gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr + m2, m4, sXi,
+             Cf.ptr, chi, sC, 1.0, R.ptr, chi, s2, nc);
+      };
+      if (warm) {
+        // the warm start keeps no component in span(W): c = -(W Phi)^T x_g
+        gemm(dev, true, false, m2, chi, 2 * n, -1.0, Xi.ptr, m4, sXi, X.ptr,
+             chi, s2, 0.0, Cf.ptr, chi, sC, nc);
+        galerkin_add();
+      }
+      // span(W) holds the discarded triplets next to the truncation, the
+      // only ones that can come close to a kept one: there the solution is
+      // the Galerkin one with the Lorentzian-broadened inverse,
+      // c = rho / (s_j - lambda) (W Phi)^T r, rho = y^2 / (y^2 + eta^2),
+      // y = s_j^2 - lambda^2, eta = 1e-12 s_1^2 (the broadening of the
+      // kept block), i.e. x_j = y / (y^2 + eta^2) (s_j + lambda) in place
+      // of 1 / (s_j - lambda)
       gemm(dev, true, false, m4, chi, 2 * n, 1.0, Xi.ptr, m4, sXi, R.ptr,
            chi, s2, 0.0, Hd.ptr, chi, sH, nc);
-      defl_coef(dev, 0, S.ptr, kp, lamK.ptr, chi, m2, b, Hd.ptr, Cf.ptr, nc);
-      Tensor Dx = warm ? dev.empty({nc, 2, n, chi}) : X;
-      gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr, m4, sXi, Cf.ptr,
-           chi, sC, 0.0, Dx.ptr, chi, s2, nc);
-      if (warm) axpby(dev, tot, 1.0, Dx.ptr, 1.0, X.ptr);
-      col_axpby(dev, nc * 2 * n, chi, -1.0, S.ptr, Dx.ptr, 1.0, R.ptr, 2 * n,
-                b);
-      gemm(dev, false, false, 2 * n, chi, m2, 1.0, Xi.ptr + m2, m4, sXi,
-           Cf.ptr, chi, sC, 1.0, R.ptr, chi, s2, nc);
+      defl_coef(dev, 2, S.ptr, kp, lamK.ptr, chi, m2, b, Hd.ptr, Cf.ptr, nc);
+      galerkin_add();
+      // the part of r in span(W) that the broadening leaves is not to be
+      // solved: CG runs on the complement of W only
+      gemm(dev, true, false, m2, chi, 2 * n, 1.0, Xi.ptr, m4, sXi, R.ptr,
+           chi, s2, 0.0, Cf.ptr, chi, sC, nc);
+      gemm(dev, false, false, 2 * n, chi, m2, -1.0, Xi.ptr, m4, sXi, Cf.ptr,
+           chi, sC, 1.0, R.ptr, chi, s2, nc);
     }
     axpby(dev, tot, 1.0, R.ptr, 0.0, Pp.ptr);
     if (m > 0) deflate(R.ptr, Pp.ptr);

@@ -25,12 +25,14 @@ import numpy as np
 from . import binding, inputs
 
 
-def run(D, chi, iters, seed, J2, prec, precondition, delta_mode, K=20):
+def run(D, chi, iters, seed, J2, prec, precondition, delta_mode, K=20,
+        svd_cutoff=1e-8):
     A0 = inputs.random_state(seed, 1, 1, 2, D)
     terms = inputs.terms_j1j2(1, 1, 1.0, J2)
     o = binding.default_opts()
     o.prec = prec
     o.grad_K = K
+    o.svd_cutoff = svd_cutoff
     p = binding.lbfgs_default_params()
     p.precondition = int(precondition)
     p.delta_mode = delta_mode
@@ -65,10 +67,16 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--delta-mode", type=int, default=1)
     ap.add_argument("--gaps", default="1e-3,1e-4,1e-5")
+    # near a converged low-entanglement state the smallest kept singular
+    # values of the cut matrices fall towards 1e-12 s_1, where the adjoint
+    # of the truncated SVD (its complement solves) becomes ill-conditioned:
+    # the optimiser keeps the values above 1e-8 s_1
+    ap.add_argument("--svd-cutoff", type=float, default=1e-8)
     a = ap.parse_args()
     binding.load()
     prec = {"fp64": binding.FP64, "fp32": binding.FP32}[a.prec]
-    runs = [run(a.D, a.chi, a.iters, a.seed, a.J2, prec, P, a.delta_mode)
+    runs = [run(a.D, a.chi, a.iters, a.seed, a.J2, prec, P, a.delta_mode,
+                svd_cutoff=a.svd_cutoff)
             for P in (True, False)]
     e_best = min(min(r["energies"]) for r in runs)
     gaps = [float(g) for g in a.gaps.split(",")]
@@ -78,7 +86,8 @@ def main():
                           if e - e_best <= g), None) for g in gaps}
         r["evals_total"] = 1 + sum(r["evals"])
     print(json.dumps(dict(D=a.D, chi=a.chi, seed=a.seed, J2=a.J2,
-                          prec=a.prec, e_best=e_best, runs=runs)),
+                          prec=a.prec, svd_cutoff=a.svd_cutoff,
+                          e_best=e_best, runs=runs)),
           flush=True)
 
 
