@@ -20,6 +20,15 @@ metric       local metric N_local (Eq. (11)), the regularised preconditioner
              N + delta I (Sec. III B), the CG / direct solves of
              P g' = g (Sec. III C) used to form the preconditioned gradient
              (Eq. (4)).
+step         the whole preconditioned step of one evaluation, composed.
+lbfgs        L-BFGS with the Hager-Zhang line search and the preconditioner
+             as initial inverse Hessian; adaptive delta (Secs. II, III B,
+             IV A).
+bp           belief-propagation (chi = 1) environment and its metric
+             (Sec. III A).
+full_metric  the full tangent-space metric (Eq. (10)) applied matrix-free as
+             the mixed ket/bra second derivative of the per-site log-norm,
+             and the GMRES solve of one cycle (Sec. III C).
 
 Parity status: every function is pinned by the CPU tests in tests/ (closed
 forms, brute-force finite lattices, decoupled chains, invariances, finite
