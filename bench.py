@@ -26,7 +26,11 @@ Further legs: `serving` replays the seeded request stream (Poisson arrivals
 at 20/s, D 3..6, chi 2D^2..3D^2; a prefix of --serve-requests requests) and
 reports p50/p99 latency, throughput, the device overlap of requests and how
 many of a sample gave bitwise the results of the same request run alone;
-`lbfgs` times iterations of the preconditioned L-BFGS on the same state.
+`lbfgs` times iterations of the preconditioned L-BFGS on the same state;
+`preconditioners` times one application of every preconditioner at the
+converged state (local metric by CG and by GMRES(30), belief propagation,
+one product with the full metric and its GMRES(30) solve) beside one
+gradient evaluation.
 
 The roofline object reports the library's matrix-core GEMM in the headline
 arithmetic (the dominant kernel): algorithmic flops (2 M N K per launch)
@@ -44,7 +48,7 @@ it.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--prec fp32]
                     [--no-fp64] [--no-cpu-baseline] [--checkpoint]
-                    [--serve-requests 128] [--no-lbfgs]
+                    [--serve-requests 128] [--no-lbfgs] [--no-precond]
 
 Prints one JSON line.
 """
@@ -313,6 +317,50 @@ def lbfgs_leg(name, prec, iters):
             "iterations": len(rec)}
 
 
+def precond_leg(name, prec, gmres_m=30):
+    """Seconds per application of every preconditioner at the workload's
+    converged state, beside one energy-gradient evaluation: the local
+    metric by CG (20 iterations) and by one GMRES cycle, the
+    belief-propagation metric (messages converged from the trace message,
+    then the closed-form solve), one product with the full metric, and the
+    full metric by one GMRES cycle of gmres_m vectors."""
+    from paper_2511_09546_amd import binding, inputs
+    w = inputs.WORKLOADS[name]
+    A = inputs.workload_state(name)
+    terms = inputs.workload_terms(name)
+    o = binding.default_opts()
+    o.prec = PRECS[prec]
+    delta = w["delta"]
+    out = {"workload": f"{name}, {prec} contractions, delta {delta}, "
+                       f"K={w['grad_K']}", "gmres_m": gmres_m}
+
+    def timed(key, f):
+        t = time.perf_counter()
+        r = f()
+        out[key] = time.perf_counter() - t
+        print(f"[precond] {key} {out[key]:.4f} s", file=sys.stderr,
+              flush=True)
+        return r
+
+    with binding.Context(A, w["chi"], opts=o) as ctx:
+        ctx.converge(w["tol"], w["n_iter"])
+        _, g = timed("energy_grad_s", lambda: ctx.energy_grad(terms, True))
+        timed("local_cg20_s", lambda: ctx.precond(g, delta, 0.0, 20))
+        _, k, r = timed("local_gmres_s",
+                        lambda: ctx.precond_gmres(g, delta, gmres_m))
+        out["local_gmres_vectors"], out["local_gmres_resid"] = k, r
+        timed("bp_converge_s", lambda: ctx.bp_converge(w["tol"], 500))
+        timed("bp_apply_s", lambda: ctx.precond_bp(g, delta))
+        timed("full_metric_product_s", lambda: ctx.metric_full(g))
+        _, k, r = timed("full_gmres_s",
+                        lambda: ctx.precond_full(g, delta, gmres_m))
+        out["full_gmres_vectors"], out["full_gmres_resid"] = k, r
+        out["peak_live_bytes"] = ctx.stats()["peak_live_bytes"]
+    out["full_product_over_gradient"] = (out["full_metric_product_s"] /
+                                         out["energy_grad_s"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +379,8 @@ def main():
                     help="prefix of the seeded request stream to replay "
                          "(0: no serving leg)")
     ap.add_argument("--no-lbfgs", action="store_true")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="skip the timing of every preconditioner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
@@ -441,6 +491,8 @@ def main():
         out["serving"]["prefix_of"] = 256
     if not args.no_lbfgs:
         out["lbfgs"] = lbfgs_leg(name, args.prec, 3)
+    if not args.no_precond:
+        out["preconditioners"] = precond_leg(name, args.prec)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(name, n_conv)
     print(json.dumps(out), flush=True)

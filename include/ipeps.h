@@ -234,6 +234,70 @@ int precond_apply_dev_noalloc(ipeps_ctx* ctx, const double* d_g,
  * (an upper estimate; host only).  Returns 0 for invalid sizes. */
 size_t precond_noalloc_bytes(int Lx, int Ly, int d, int D, int chi);
 
+/* ------------------------------------------------------------------------
+ * GMRES solve of the local-metric system (Sec. III C: P g' = g by
+ * matrix-vector products only, one outer GMRES iteration of 30 Krylov
+ * vectors): the operator of precond_apply, (N_local + delta I), solved per
+ * site by one GMRES cycle from x0 = 0 with at most m vectors, stopping
+ * early when the residual estimate is <= tol |g| or the Krylov space is
+ * invariant (the new vector below 1e-12 of the product it came from).
+ *   g, x      layout of A; host (precond_apply_gmres) or device pointers
+ *             (precond_apply_gmres_dev)
+ *   m         1..256 (30 in the paper)
+ *   n_used    out: largest number of Krylov vectors over sites (or NULL)
+ *   rel_resid out: largest residual estimate / |g| over sites (or NULL)
+ * Errors: EINVAL, ESTATE (no ctm_converge for this state), ENOMEM, EHIP. */
+int precond_apply_gmres(ipeps_ctx* ctx, const double* g, double delta, int m,
+                        double tol, double* x, int* n_used,
+                        double* rel_resid);
+int precond_apply_gmres_dev(ipeps_ctx* ctx, const double* d_g, double delta,
+                            int m, double tol, double* d_x, int* n_used,
+                            double* rel_resid);
+
+/* ------------------------------------------------------------------------
+ * Full tangent-space metric (Eq. (10), Sec. III A) of a 1x1 unit cell,
+ * applied matrix-free.  N is the mixed ket/bra second derivative of the
+ * per-site log-norm F(A_ket, A_bra) = log |kappa|, kappa = n_site n_corner /
+ * (n_h n_v): the closed networks of the cell (the ring around the mixed
+ * double layer a = sum_p A_ket (x) A_bra; the four corners; the ring with
+ * one column removed; with one row removed) on the environment that
+ * grad_K CTMRG iterations of a produce from the converged environment of
+ * A (ctm_converge first).  The log removes the overlap along the state:
+ * N is the connected sum over vacancy separations, symmetric, N A = 0, and
+ * infinitesimal gauge transformations of the bonds are zero modes (up to
+ * the truncation of the environment).
+ *
+ * log_norm_grad: F at (A_ket, A) and dF/dA_bra.  A_ket host, layout of A,
+ * or NULL for A itself; F host out; g host out (layout of A) or NULL for F
+ * only.  With A_ket = A, <g, A> = 1.
+ *
+ * metric_full_apply: NB = N B by the central difference
+ *   (dF/dA_bra(A + h B, A) - dF/dA_bra(A - h B, A)) / (2 h),
+ *   h = rel_step |A| / |B|;
+ * rel_step 0 selects 1e-5 in FP64 arithmetic and 3e-3 otherwise (the
+ * context's late arithmetic: the difference amplifies the rounding of the
+ * gradients by |A| / (h |B|)).  Two gradient evaluations per call.
+ *
+ * precond_apply_full: x = (N + delta I)^-1 g by one GMRES cycle of at most
+ * m vectors (stopping rules of precond_apply_gmres); m + 1 metric
+ * applications at most.
+ *
+ * _dev variants take device pointers (same layouts).  Errors: EINVAL,
+ * ESTATE (no ctm_converge), ENOTIMPL (unit cell larger than 1x1: there the
+ * full metric couples the tensors of the cell), ENOMEM, EHIP. */
+int log_norm_grad(ipeps_ctx* ctx, const double* A_ket, double* F,
+                  double* g);
+int metric_full_apply(ipeps_ctx* ctx, const double* B, double rel_step,
+                      double* NB);
+int metric_full_apply_dev(ipeps_ctx* ctx, const double* d_B, double rel_step,
+                          double* d_NB);
+int precond_apply_full(ipeps_ctx* ctx, const double* g, double delta, int m,
+                       double tol, double rel_step, double* x, int* n_used,
+                       double* rel_resid);
+int precond_apply_full_dev(ipeps_ctx* ctx, const double* d_g, double delta,
+                           int m, double tol, double rel_step, double* d_x,
+                           int* n_used, double* rel_resid);
+
 /* Sum-normalised singular values of every corner, out[4][Lx*Ly][chi] (host),
  * zero padded. Errors: EINVAL, EHIP. */
 int ipeps_corner_spectra(ipeps_ctx* ctx, double* out);
@@ -336,10 +400,15 @@ int precond_apply_bp_dev(ipeps_ctx* ctx, const double* d_g, double delta,
  * 2 |g_{k+1}|^2, clamped to [delta_min, delta_max]. */
 typedef struct {
   int m;               /* history pairs (200) */
-  int precondition;    /* 1 (default): H_0 = P^-1 with the local metric;
+  int precondition;    /* 1 (default): H_0 = P^-1 with the local metric
+                          (CG, precond_apply);
                           2: with the belief-propagation metric
                           (bp_converge to ctm_tol within ctm_max_iter
                           updates at every point, precond_apply_bp);
+                          3: the local metric by GMRES
+                          (precond_apply_gmres, gmres_m vectors);
+                          4: the full metric by GMRES (precond_apply_full,
+                          gmres_m vectors, 1x1 cells; ENOTIMPL otherwise);
                           0: H_0 = gamma I */
   int delta_mode;      /* 0 fixed, 1 energy change (default), 2 |g|^2 */
   double delta0;       /* delta of the first iteration (1e-2) */
@@ -352,6 +421,10 @@ typedef struct {
   double psi0;         /* first trial step without preconditioner (0.01) */
   double hz_delta, hz_sigma, hz_eps, hz_theta, hz_gamma, hz_rho;
                        /* 0.1, 0.9, 1e-6, 0.5, 0.66, 5 */
+  int gmres_m;         /* Krylov vectors of the GMRES solves (30); the
+                          GMRES solves stop early at cg_tol */
+  double fd_step;      /* full metric: rel_step of metric_full_apply (0:
+                          by arithmetic) */
 } ipeps_lbfgs_params;
 
 typedef struct {

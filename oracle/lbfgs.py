@@ -270,10 +270,12 @@ class IpepsProblem:
     of that environment (Eq. (11)) solved by CG (Sec. III C)."""
 
     def __init__(self, shape, terms, chi, ctm_tol=1e-10, ctm_max_iter=200,
-                 K=20, cg_tol=0.0, cg_maxiter=20):
+                 K=20, cg_tol=0.0, cg_maxiter=20, gmres_m=30,
+                 fd_step=1e-5):
         self.shape, self.terms, self.chi = tuple(shape), terms, chi
         self.ctm_tol, self.ctm_max_iter, self.K = ctm_tol, ctm_max_iter, K
         self.cg_tol, self.cg_maxiter = cg_tol, cg_maxiter
+        self.gmres_m, self.fd_step = gmres_m, fd_step
         self.env = None
         self.evals = 0
 
@@ -301,3 +303,21 @@ class IpepsProblem:
             self.env, A, np.asarray(g).reshape(self.shape), delta,
             self.cg_tol, self.cg_maxiter)
         return xg.numpy().ravel()
+
+    def precond_local_gmres(self, x, g, delta):
+        """The local metric solved by one GMRES cycle (Sec. III C)."""
+        from . import full_metric
+        A = np.asarray(x).reshape(self.shape)
+        xg, _, _ = full_metric.precondition_local_gmres(
+            self.env, A, np.asarray(g).reshape(self.shape), delta,
+            self.gmres_m, self.cg_tol)
+        return xg.numpy().ravel()
+
+    def precond_full(self, x, g, delta):
+        """The full metric (Eq. (10)) solved by one GMRES cycle, 1x1 cell."""
+        from . import full_metric
+        A = np.asarray(x).reshape(self.shape)
+        xg, _, _ = full_metric.precondition_full(
+            A, np.asarray(g).reshape(self.shape), self.env, self.chi, self.K,
+            delta, self.gmres_m, self.cg_tol, self.fd_step)
+        return np.asarray(xg).ravel()

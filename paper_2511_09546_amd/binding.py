@@ -36,7 +36,9 @@ API_FUNCTIONS = [
     "precond_apply_dev", "ipeps_footprint_bytes",
     "precond_apply_dev_noalloc", "precond_noalloc_bytes",
     "ipeps_lbfgs_default_params", "ipeps_lbfgs_create", "ipeps_lbfgs_step",
-    "ipeps_lbfgs_free", "ipeps_get_state",
+    "ipeps_lbfgs_free", "ipeps_get_state", "precond_apply_gmres",
+    "precond_apply_gmres_dev", "log_norm_grad", "metric_full_apply",
+    "metric_full_apply_dev", "precond_apply_full", "precond_apply_full_dev",
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
 PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
@@ -105,6 +107,25 @@ def load():
                                          c_void_p]
     lib.precond_apply_bp_dev.restype = c_int
     lib.ipeps_set_env_dev.argtypes = [c_void_p, c_void_p]
+    lib.precond_apply_gmres.argtypes = [c_void_p, _DP, c_double, c_int,
+                                        c_double, _DP, _IP, _DP]
+    lib.precond_apply_gmres_dev.argtypes = [c_void_p, c_void_p, c_double,
+                                            c_int, c_double, c_void_p, _IP,
+                                            _DP]
+    lib.log_norm_grad.argtypes = [c_void_p, _DP, _DP, _DP]
+    lib.metric_full_apply.argtypes = [c_void_p, _DP, c_double, _DP]
+    lib.metric_full_apply_dev.argtypes = [c_void_p, c_void_p, c_double,
+                                          c_void_p]
+    lib.precond_apply_full.argtypes = [c_void_p, _DP, c_double, c_int,
+                                       c_double, c_double, _DP, _IP, _DP]
+    lib.precond_apply_full_dev.argtypes = [c_void_p, c_void_p, c_double,
+                                           c_int, c_double, c_double,
+                                           c_void_p, _IP, _DP]
+    for name in ("precond_apply_gmres", "precond_apply_gmres_dev",
+                 "log_norm_grad", "metric_full_apply",
+                 "metric_full_apply_dev", "precond_apply_full",
+                 "precond_apply_full_dev"):
+        getattr(lib, name).restype = c_int
     lib.ipeps_set_env_dev.restype = c_int
     lib.ipeps_env_size.argtypes = [c_int, c_int, c_int, c_int]
     lib.ipeps_env_size.restype = c_size_t
@@ -412,6 +433,82 @@ class Context:
             raise IpepsError(st, "precond_apply_bp")
         return x
 
+    # ---- GMRES solves and the full metric (1x1 cells)
+    def precond_gmres(self, g, delta: float, m: int = 30, tol: float = 0.0):
+        """(N_local + delta)^-1 g by one GMRES cycle: (x, n_used, resid)."""
+        g = _f64(g).reshape(self.shape)
+        x = np.zeros(self.shape)
+        n = c_int(0)
+        rr = c_double(0.0)
+        st = load().precond_apply_gmres(self._h, _dp(g), delta, m, tol,
+                                        _dp(x), ctypes.byref(n),
+                                        ctypes.byref(rr))
+        if st != OK:
+            raise IpepsError(st, "precond_apply_gmres")
+        return x, n.value, rr.value
+
+    def precond_gmres_dev(self, d_g: int, d_x: int, delta: float,
+                          m: int = 30, tol: float = 0.0):
+        n = c_int(0)
+        rr = c_double(0.0)
+        st = load().precond_apply_gmres_dev(self._h, c_void_p(d_g), delta, m,
+                                            tol, c_void_p(d_x),
+                                            ctypes.byref(n), ctypes.byref(rr))
+        if st != OK:
+            raise IpepsError(st, "precond_apply_gmres_dev")
+        return n.value, rr.value
+
+    def log_norm_grad(self, A_ket=None, grad: bool = True):
+        """(F, dF/dA_bra) of the per-site log-norm at (A_ket, A)."""
+        F = c_double(0.0)
+        ak = (_f64(A_ket).reshape(self.shape) if A_ket is not None
+              else None)
+        g = np.zeros(self.shape) if grad else None
+        st = load().log_norm_grad(self._h, _dp(ak) if ak is not None else None,
+                                  ctypes.byref(F), _dp(g) if grad else None)
+        if st != OK:
+            raise IpepsError(st, "log_norm_grad")
+        return F.value, g
+
+    def metric_full(self, B, rel_step: float = 0.0) -> np.ndarray:
+        B = _f64(B).reshape(self.shape)
+        y = np.zeros(self.shape)
+        st = load().metric_full_apply(self._h, _dp(B), rel_step, _dp(y))
+        if st != OK:
+            raise IpepsError(st, "metric_full_apply")
+        return y
+
+    def metric_full_dev(self, d_B: int, d_NB: int, rel_step: float = 0.0):
+        st = load().metric_full_apply_dev(self._h, c_void_p(d_B), rel_step,
+                                          c_void_p(d_NB))
+        if st != OK:
+            raise IpepsError(st, "metric_full_apply_dev")
+
+    def precond_full(self, g, delta: float, m: int = 30, tol: float = 0.0,
+                     rel_step: float = 0.0):
+        """(N + delta)^-1 g, N the full metric: (x, n_used, resid)."""
+        g = _f64(g).reshape(self.shape)
+        x = np.zeros(self.shape)
+        n = c_int(0)
+        rr = c_double(0.0)
+        st = load().precond_apply_full(self._h, _dp(g), delta, m, tol,
+                                       rel_step, _dp(x), ctypes.byref(n),
+                                       ctypes.byref(rr))
+        if st != OK:
+            raise IpepsError(st, "precond_apply_full")
+        return x, n.value, rr.value
+
+    def precond_full_dev(self, d_g: int, d_x: int, delta: float, m: int = 30,
+                         tol: float = 0.0, rel_step: float = 0.0):
+        n = c_int(0)
+        rr = c_double(0.0)
+        st = load().precond_apply_full_dev(self._h, c_void_p(d_g), delta, m,
+                                           tol, rel_step, c_void_p(d_x),
+                                           ctypes.byref(n), ctypes.byref(rr))
+        if st != OK:
+            raise IpepsError(st, "precond_apply_full_dev")
+        return n.value, rr.value
+
     def precond_bp_dev(self, d_g: int, d_x: int, delta: float):
         st = load().precond_apply_bp_dev(self._h, c_void_p(d_g), delta,
                                          c_void_p(d_x))
@@ -515,7 +612,13 @@ class LbfgsParams(ctypes.Structure):
                 ("psi0", c_double), ("hz_delta", c_double),
                 ("hz_sigma", c_double), ("hz_eps", c_double),
                 ("hz_theta", c_double), ("hz_gamma", c_double),
-                ("hz_rho", c_double)]
+                ("hz_rho", c_double), ("gmres_m", c_int),
+                ("fd_step", c_double)]
+
+
+# ipeps_lbfgs_params.precondition
+PRECOND_NONE, PRECOND_LOCAL, PRECOND_BP = 0, 1, 2
+PRECOND_LOCAL_GMRES, PRECOND_FULL_GMRES = 3, 4
 
 
 class LbfgsInfo(ctypes.Structure):

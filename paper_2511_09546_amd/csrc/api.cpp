@@ -332,6 +332,138 @@ int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
   return res;
 }
 
+static int gmres_args_ok(double delta, int m, double tol) {
+  return delta > 0.0 && std::isfinite(delta) && m >= 1 && m <= 256 &&
+         tol >= 0.0 && std::isfinite(tol);
+}
+
+static int precond_gmres_impl(ipeps_ctx* c, const double* g, double delta,
+                              int m, double tol, double* x, int* n_used,
+                              double* rel_resid, bool dev) {
+  if (!c || !g || !x || !gmres_args_ok(delta, m, tol)) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!dev && !all_finite(g, state_size(cx))) return IPEPS_EINVAL;
+  if (!cx.converged_once) return IPEPS_ESTATE;
+  return guarded([&]() {
+    PrecScope ps(cx.dev, late_prec(cx));
+    precondition_gmres(cx, g, delta, m, tol, x, n_used, rel_resid, dev);
+    return IPEPS_OK;
+  });
+}
+
+int precond_apply_gmres(ipeps_ctx* c, const double* g, double delta, int m,
+                        double tol, double* x, int* n_used,
+                        double* rel_resid) {
+  return precond_gmres_impl(c, g, delta, m, tol, x, n_used, rel_resid, false);
+}
+
+int precond_apply_gmres_dev(ipeps_ctx* c, const double* d_g, double delta,
+                            int m, double tol, double* d_x, int* n_used,
+                            double* rel_resid) {
+  return precond_gmres_impl(c, d_g, delta, m, tol, d_x, n_used, rel_resid,
+                            true);
+}
+
+// the central-difference step of the full metric: 1e-5 |A| / |B| in FP64,
+// 3e-3 |A| / |B| in the FP32-class arithmetics
+static double full_step(const Context& cx, double rel_step) {
+  if (rel_step > 0.0) return rel_step;
+  return late_prec(cx) == PREC_FP64 ? 1e-5 : 3e-3;
+}
+
+static int full_ok(const Context& cx) {
+  if (!cx.converged_once) return IPEPS_ESTATE;
+  if (cx.nsite() != 1) return IPEPS_ENOTIMPL;
+  return IPEPS_OK;
+}
+
+int log_norm_grad(ipeps_ctx* c, const double* A_ket, double* F, double* g) {
+  if (!c || !F) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (A_ket && !all_finite(A_ket, state_size(cx))) return IPEPS_EINVAL;
+  int st = full_ok(cx);
+  if (st != IPEPS_OK) return st;
+  return guarded([&]() {
+    PrecScope ps(cx.dev, late_prec(cx));
+    Tensor Ak = cx.A;
+    if (A_ket) {
+      Ak = cx.dev.empty(cx.A.shape);
+      cx.dev.upload(Ak, A_ket);
+    }
+    Tensor gd;
+    if (g) gd = cx.dev.empty(cx.A.shape);
+    *F = log_kappa_grad(cx, Ak.ptr, g ? gd.ptr : nullptr);
+    if (g) cx.dev.download(gd, g);
+    return IPEPS_OK;
+  });
+}
+
+static int metric_full_impl(ipeps_ctx* c, const double* B, double rel_step,
+                            double* NB, bool dev) {
+  if (!c || !B || !NB || !(rel_step >= 0.0) || !(rel_step < 1.0))
+    return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!dev && !all_finite(B, state_size(cx))) return IPEPS_EINVAL;
+  int st = full_ok(cx);
+  if (st != IPEPS_OK) return st;
+  return guarded([&]() {
+    PrecScope ps(cx.dev, late_prec(cx));
+    const double h = full_step(cx, rel_step);
+    if (dev) {
+      full_metric_apply(cx, B, NB, h);
+      cx.dev.sync();
+    } else {
+      Tensor b = cx.dev.empty(cx.A.shape), y = cx.dev.empty(cx.A.shape);
+      cx.dev.upload(b, B);
+      full_metric_apply(cx, b.ptr, y.ptr, h);
+      cx.dev.download(y, NB);
+    }
+    return IPEPS_OK;
+  });
+}
+
+int metric_full_apply(ipeps_ctx* c, const double* B, double rel_step,
+                      double* NB) {
+  return metric_full_impl(c, B, rel_step, NB, false);
+}
+
+int metric_full_apply_dev(ipeps_ctx* c, const double* d_B, double rel_step,
+                          double* d_NB) {
+  return metric_full_impl(c, d_B, rel_step, d_NB, true);
+}
+
+static int precond_full_impl(ipeps_ctx* c, const double* g, double delta,
+                             int m, double tol, double rel_step, double* x,
+                             int* n_used, double* rel_resid, bool dev) {
+  if (!c || !g || !x || !gmres_args_ok(delta, m, tol) ||
+      !(rel_step >= 0.0) || !(rel_step < 1.0))
+    return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (!dev && !all_finite(g, state_size(cx))) return IPEPS_EINVAL;
+  int st = full_ok(cx);
+  if (st != IPEPS_OK) return st;
+  return guarded([&]() {
+    PrecScope ps(cx.dev, late_prec(cx));
+    precondition_full(cx, g, delta, m, tol, full_step(cx, rel_step), x,
+                      n_used, rel_resid, dev);
+    return IPEPS_OK;
+  });
+}
+
+int precond_apply_full(ipeps_ctx* c, const double* g, double delta, int m,
+                       double tol, double rel_step, double* x, int* n_used,
+                       double* rel_resid) {
+  return precond_full_impl(c, g, delta, m, tol, rel_step, x, n_used,
+                           rel_resid, false);
+}
+
+int precond_apply_full_dev(ipeps_ctx* c, const double* d_g, double delta,
+                           int m, double tol, double rel_step, double* d_x,
+                           int* n_used, double* rel_resid) {
+  return precond_full_impl(c, d_g, delta, m, tol, rel_step, d_x, n_used,
+                           rel_resid, true);
+}
+
 int bp_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
                 double* change) {
   if (!c || max_iter < 1 || !(tol >= 0.0)) return IPEPS_EINVAL;

@@ -68,10 +68,18 @@ std::vector<Var> arot_leaves(Tape& tp, Context& cx) {
 
 std::vector<Var> arot_from_sites(Tape& tp, Context& cx,
                                  const std::vector<Var>& As) {
+  return arot_from_pairs(tp, cx, As, As);
+}
+
+// a = sum_p K[p,l,u,r,d] B[p,l',u',r',d'] per site, fused (k k') with k
+// from the ket K: the mixed double layer of two different site tensors
+std::vector<Var> arot_from_pairs(Tape& tp, Context& cx,
+                                 const std::vector<Var>& Ks,
+                                 const std::vector<Var>& Bs) {
   const int D2 = cx.D2;
   std::vector<Var> r(4 * cx.nsite());
   for (int s = 0; s < cx.nsite(); ++s) {
-    Var a = tp.view(tp.einsum("pabce,pfghi->afbgchei", As[s], As[s]),
+    Var a = tp.view(tp.einsum("pabce,pfghi->afbgchei", Ks[s], Bs[s]),
                     {D2, D2, D2, D2});
     r[s * 4] = a;
     for (int c = 1; c < 4; ++c) r[s * 4 + c] = tp.permute(a, rot_perm(c));

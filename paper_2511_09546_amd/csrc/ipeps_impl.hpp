@@ -2,6 +2,7 @@
 #pragma once
 
 #include <array>
+#include <functional>
 #include <new>
 #include <utility>
 #include <vector>
@@ -183,6 +184,10 @@ void init_env(Context& cx);
 std::vector<Var> arot_leaves(Tape& tp, Context& cx);
 std::vector<Var> arot_from_sites(Tape& tp, Context& cx,
                                  const std::vector<Var>& As);
+// double layers of ket Ks[s] and bra Bs[s] (different tensors), rotated
+std::vector<Var> arot_from_pairs(Tape& tp, Context& cx,
+                                 const std::vector<Var>& Ks,
+                                 const std::vector<Var>& Bs);
 std::vector<Var> site_leaves(Tape& tp, Context& cx, bool req);
 VEnv venv_leaves(Tape& tp, Context& cx, const Env& e, bool req = false);
 // The trace-boundary environment as a function of the double layers on the
@@ -246,6 +251,39 @@ int precondition_bp(Context& cx, const double* g, double delta, double* x,
 // Device bytes precondition(..., lean = true) works in at most (an upper
 // estimate of its temporaries, split-K partial sums included).
 size_t precondition_lean_bytes(int nsite, int d, int D, int chi);
+// x = (N_local + delta I)^-1 g per site by one GMRES cycle of at most m
+// Krylov vectors (g, x host pointers, or device pointers when on_device);
+// n_used: largest vector count over sites, rel_resid: largest residual
+// estimate
+void precondition_gmres(Context& cx, const double* g, double delta, int m,
+                        double tol, double* x, int* n_used, double* rel_resid,
+                        bool on_device);
+
+// gmres.cpp
+// One GMRES cycle from x0 = 0 for op(x) = b, op(in, out) on device vectors
+// of length n; Arnoldi by classical Gram-Schmidt with one
+// re-orthogonalisation, the Hessenberg least-squares problem by Givens
+// rotations on the host.  Stops after m vectors, when the residual
+// estimate is <= tol |b|, or when the new Krylov vector is below 1e-12 of
+// the product it came from.  x: device out.  Returns the vectors used;
+// *rel_resid the residual estimate / |b|.
+int gmres(Device& dev, int64_t n, const double* b, double* x, int m,
+          double tol, const std::function<void(const double*, double*)>& op,
+          double* rel_resid);
+
+// full_metric.cpp (1x1 unit cell)
+// F = log kappa of the mixed double layer (ket Ak, bra the context's A),
+// K = grad_K CTMRG iterations from the converged environment; gbra
+// (device, may be null) receives dF/dA_bra.  Ak: device, layout of A.
+double log_kappa_grad(Context& cx, const double* Ak, double* gbra);
+// NB = N B, the full metric by the central difference of the bra gradient
+// along B in the ket with step rel_step |A| / |B| (device vectors)
+void full_metric_apply(Context& cx, const double* B, double* NB,
+                       double rel_step);
+// x = (N + delta I)^-1 g by one GMRES cycle (host or device pointers)
+void precondition_full(Context& cx, const double* g, double delta, int m,
+                       double tol, double rel_step, double* x, int* n_used,
+                       double* rel_resid, bool on_device);
 
 // adjoint.cpp
 // grad is a host pointer, or a device pointer when on_device

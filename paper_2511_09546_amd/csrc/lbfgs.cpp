@@ -48,6 +48,8 @@ struct Params {
   int m, precondition, delta_mode, ctm_max_iter, cg_maxiter, max_evals;
   double delta0, delta_min, delta_max, ctm_tol, cg_tol, psi0;
   double hz_delta, hz_sigma, hz_eps, hz_theta, hz_gamma, hz_rho;
+  int gmres_m;
+  double fd_step;
 };
 
 // Hager-Zhang line search on phi with phi(0) = phi0, phi'(0) = dphi0 < 0.
@@ -285,6 +287,23 @@ struct Lbfgs {
       c.bp_msg = Tensor();
       warn |= bp_converge(c, p.ctm_tol, p.ctm_max_iter, &it, &ch);
       (void)precondition_bp(c, qv, delta, rv, true);
+    } else if (p.precondition == 3) {
+      // local metric, one GMRES cycle
+      PrecScope ps(c.dev, late_prec(c));
+      int k = 0;
+      double res = 0.0;
+      precondition_gmres(c, qv, delta, p.gmres_m, p.cg_tol, rv, &k, &res,
+                         true);
+    } else if (p.precondition == 4) {
+      // full metric, one GMRES cycle
+      PrecScope ps(c.dev, late_prec(c));
+      int k = 0;
+      double res = 0.0;
+      const double h =
+          p.fd_step > 0.0 ? p.fd_step
+                          : (late_prec(c) == PREC_FP64 ? 1e-5 : 3e-3);
+      precondition_full(c, qv, delta, p.gmres_m, p.cg_tol, h, rv, &k, &res,
+                        true);
     } else if (p.precondition) {
       PrecScope ps(c.dev, late_prec(c));
       int it = 0;
@@ -466,6 +485,8 @@ void ipeps_lbfgs_default_params(ipeps_lbfgs_params* p) {
   p->hz_theta = 0.5;
   p->hz_gamma = 0.66;
   p->hz_rho = 5.0;
+  p->gmres_m = 30;
+  p->fd_step = 0.0;
 }
 
 int ipeps_lbfgs_create(ipeps_ctx* c, int n_terms, const ipeps_term* H,
@@ -475,7 +496,9 @@ int ipeps_lbfgs_create(ipeps_ctx* c, int n_terms, const ipeps_term* H,
   ipeps_lbfgs_params q;
   ipeps_lbfgs_default_params(&q);
   if (prm) q = *prm;
-  if (q.m < 1 || q.precondition < 0 || q.precondition > 2 ||
+  if (q.m < 1 || q.precondition < 0 || q.precondition > 4 ||
+      q.gmres_m < 1 || q.gmres_m > 256 || !(q.fd_step >= 0.0) ||
+      !(q.fd_step < 1.0) ||
       q.delta_mode < 0 || q.delta_mode > 2 || !(q.delta0 > 0.0) ||
       !(q.delta_min > 0.0) || !(q.delta_max >= q.delta_min) ||
       q.ctm_max_iter < 1 || q.cg_maxiter < 0 || !(q.cg_tol >= 0.0) ||
@@ -486,6 +509,7 @@ int ipeps_lbfgs_create(ipeps_ctx* c, int n_terms, const ipeps_term* H,
       std::isnan(q.ctm_tol))
     return IPEPS_EINVAL;
   Context& cx = ipeps_context(c);
+  if (q.precondition == 4 && cx.nsite() != 1) return IPEPS_ENOTIMPL;
   std::vector<TermSpec> terms;
   int st = parse_terms(cx, n_terms, H, terms);
   if (st != IPEPS_OK) return st;
@@ -497,7 +521,8 @@ int ipeps_lbfgs_create(ipeps_ctx* c, int n_terms, const ipeps_term* H,
   L.p = Params{q.m, q.precondition, q.delta_mode, q.ctm_max_iter,
                q.cg_maxiter, q.max_evals, q.delta0, q.delta_min,
                q.delta_max, q.ctm_tol, q.cg_tol, q.psi0, q.hz_delta,
-               q.hz_sigma, q.hz_eps, q.hz_theta, q.hz_gamma, q.hz_rho};
+               q.hz_sigma, q.hz_eps, q.hz_theta, q.hz_gamma, q.hz_rho,
+               q.gmres_m, q.fd_step};
   L.delta = q.delta0;
   int warn = 0;
   st = guarded_call([&]() {

@@ -9,7 +9,9 @@
 //   (N x)[t, l'u'r'd'] = sum_{lurd} E x[t, lurd] / Z,  Z = <A, E A>.
 // Two GEMMs per application (K = D^2, then K = chi^2 D^2) with LT and RB
 // permuted once so that neither GEMM needs a permute.  CG scalars, dots and
-// residuals are FP64; alpha and beta stay on the device.
+// residuals are FP64; alpha and beta stay on the device.  The same operator
+// is also solved by one GMRES cycle (precondition_gmres), the Krylov solve
+// the paper names.
 #include <cmath>
 
 #include "ipeps_impl.hpp"
@@ -181,6 +183,47 @@ int precondition(Context& cx, const double* g_host, double delta,
   if (n_iter) *n_iter = worst_it;
   if (rel_resid) *rel_resid = worst_res;
   return breakdown ? -4 : 0;
+}
+
+void precondition_gmres(Context& cx, const double* g_in, double delta,
+                        int m_kry, double tol, double* x_out, int* n_used,
+                        double* rel_resid, bool on_device) {
+  Device& dev = cx.dev;
+  const int ns = cx.nsite();
+  const int64_t m = (int64_t)cx.d * cx.D2 * cx.D2;  // per-site length
+  Tensor g = dev.empty({ns, m});
+  if (on_device)
+    axpby(dev, ns * m, 1.0, g_in, 0.0, g.ptr);
+  else
+    dev.upload(g, g_in);
+  Tensor x = dev.empty({ns, m});
+  Tensor Ap = dev.empty({m});
+  Tensor Z = dev.empty({1});
+  Tensor W1;
+  int worst_k = 0;
+  double worst_res = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    SiteMetric sm = build_metric(cx, cx.env, s);
+    apply_ring(cx, sm, cx.A.ptr + s * m, Ap.ptr, W1);
+    dot(dev, cx.A.ptr + s * m, Ap.ptr, m, Z.ptr);
+    auto op = [&](const double* v, double* y) {
+      apply_ring(cx, sm, v, y, W1);
+      scale_add_dev(dev, m, Z.ptr, v, delta, y);
+    };
+    double res = 0.0;
+    const int k = gmres(dev, m, g.ptr + s * m, x.ptr + s * m, m_kry, tol, op,
+                        &res);
+    worst_k = std::max(worst_k, k);
+    worst_res = std::max(worst_res, res);
+  }
+  if (on_device) {
+    axpby(dev, ns * m, 1.0, x.ptr, 0.0, x_out);
+    dev.sync();
+  } else {
+    dev.download(x, x_out);
+  }
+  if (n_used) *n_used = worst_k;
+  if (rel_resid) *rel_resid = worst_res;
 }
 
 }  // namespace ipeps

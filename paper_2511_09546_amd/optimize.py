@@ -1,16 +1,17 @@
 """Ground-state search of an iPEPS with the library's preconditioned L-BFGS.
 
-Runs ipeps_lbfgs_* (Sec. II, III B, IV A: L-BFGS with the local-metric
-preconditioner inside the two-loop recursion, Hager-Zhang line search,
-adaptive delta) on a seeded random state, with and without the
-preconditioner, and prints one JSON line per run: the energy after every
-iteration, the evaluations per iteration, the wall time, and the iteration
-at which the energy first came within each listed gap of the lowest energy
-either run reached.
+Runs ipeps_lbfgs_* (Sec. II, III B, IV A: L-BFGS with a preconditioner
+inside the two-loop recursion, Hager-Zhang line search, adaptive delta) on
+a seeded random state once per listed preconditioner (none; the local
+metric by CG or by GMRES; the belief-propagation metric; the full metric by
+GMRES, Sec. III A-C) and prints one JSON line: per run the energy after
+every iteration, the evaluations per iteration, the wall time, and the
+iteration at which the energy first came within each listed gap of the
+lowest energy any run reached.
 
     python -m paper_2511_09546_amd.optimize --D 2 --chi 32 --iters 60
         [--seed 11] [--J2 0.0] [--prec fp64|fp32] [--delta-mode 1]
-        [--gaps 1e-3,1e-4,1e-5]
+        [--precond local,none] [--gaps 1e-3,1e-4,1e-5]
 
 Every computation runs in the library (binding.Lbfgs); this module only
 sets up the state and the Hamiltonian and formats the record.
@@ -24,6 +25,8 @@ import numpy as np
 
 from . import binding, inputs
 
+PRECOND = {"none": 0, "local": 1, "bp": 2, "local-gmres": 3, "full": 4}
+
 
 def run(D, chi, iters, seed, J2, prec, precondition, delta_mode, K=20,
         svd_cutoff=1e-8):
@@ -34,7 +37,7 @@ def run(D, chi, iters, seed, J2, prec, precondition, delta_mode, K=20,
     o.grad_K = K
     o.svd_cutoff = svd_cutoff
     p = binding.lbfgs_default_params()
-    p.precondition = int(precondition)
+    p.precondition = PRECOND[precondition]
     p.delta_mode = delta_mode
     t0 = time.perf_counter()
     energies, evals, ctm = [], [], []
@@ -48,11 +51,11 @@ def run(D, chi, iters, seed, J2, prec, precondition, delta_mode, K=20,
                 energies.append(info["e"])
                 evals.append(info["n_evals"])
                 ctm.append(info["ctm_iters"])
-                print(f"  P={int(precondition)} it {len(evals)}: e "
+                print(f"  P={precondition} it {len(evals)}: e "
                       f"{info['e']:.12f} alpha {info['alpha']:.3g} evals "
                       f"{info['n_evals']} |g| {info['gnorm']:.3e} delta "
                       f"{info['delta']:.2e}", file=sys.stderr, flush=True)
-    return dict(precondition=int(precondition), energies=energies,
+    return dict(precondition=precondition, energies=energies,
                 evals=evals, ctm_iters=ctm,
                 seconds=time.perf_counter() - t0)
 
@@ -67,6 +70,8 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--delta-mode", type=int, default=1)
     ap.add_argument("--gaps", default="1e-3,1e-4,1e-5")
+    ap.add_argument("--precond", default="local,none",
+                    help="comma-separated: " + ",".join(PRECOND))
     # near a converged low-entanglement state the smallest kept singular
     # values of the cut matrices fall towards 1e-12 s_1, where the adjoint
     # of the truncated SVD (its complement solves) becomes ill-conditioned:
@@ -77,7 +82,7 @@ def main():
     prec = {"fp64": binding.FP64, "fp32": binding.FP32}[a.prec]
     runs = [run(a.D, a.chi, a.iters, a.seed, a.J2, prec, P, a.delta_mode,
                 svd_cutoff=a.svd_cutoff)
-            for P in (True, False)]
+            for P in a.precond.split(",")]
     e_best = min(min(r["energies"]) for r in runs)
     gaps = [float(g) for g in a.gaps.split(",")]
     for r in runs:

@@ -88,3 +88,43 @@ def test_noalloc_scratch_size_and_estimate(lib):
     assert binding.noalloc_bytes(0, 1, 2, 6, 72) == 0
     assert lib.precond_apply_dev_noalloc(None, None, 1e-4, 0.0, 1, None,
                                          None, None) == -1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the C structs have the header's size and field
+    offsets (compiled with the host C compiler)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    from paper_2511_09546_amd import binding
+    structs = {"ipeps_opts": binding.Opts, "ipeps_term": binding.Term,
+               "ipeps_lbfgs_params": binding.LbfgsParams,
+               "ipeps_lbfgs_info": binding.LbfgsInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>',
+             '#include "ipeps.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", '
+                         f'offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True,
+                         text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -1,8 +1,9 @@
 """The device L-BFGS (ipeps_lbfgs_*) against the oracle's optimiser on the
 same problem: the D=2, chi=8 rotated Heisenberg state, K = 20 gradients,
 every evaluation converged to 1e-11 from the previous environment, local
-metric with 20 CG iterations and the energy-change delta (Sec. II, III B,
-IV A).  The first iterates agree (energy, accepted step, evaluation count,
+metric with 20 CG iterations, the local metric and the full metric each
+by one GMRES cycle of 30 vectors, and the energy-change delta (Sec. II,
+III B, III C, IV A).  The first iterates agree (energy, accepted step, evaluation count,
 the site tensor element by element) and the energy decreases monotonically,
 with and without the preconditioner.
 
@@ -28,7 +29,7 @@ def _say(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("precond", [1, 0])
+@pytest.mark.parametrize("precond", [1, 0, 3, 4])
 def test_lbfgs_iterates_match_oracle(precond):
     name = "d2chi8"
     _say(f"lbfgs vs oracle {name}, precondition={precond}")
@@ -38,9 +39,10 @@ def test_lbfgs_iterates_match_oracle(precond):
     chi, K, tol = w["chi"], 20, 1e-11
     prob = lbfgs.IpepsProblem(A0.shape, terms, chi, ctm_tol=tol,
                               ctm_max_iter=300, K=K, cg_tol=0.0,
-                              cg_maxiter=20)
-    hist = lbfgs.minimize(prob.fg, A0, N_ITER,
-                          precond=prob.precond if precond else None,
+                              cg_maxiter=20, gmres_m=30)
+    pc = {0: None, 1: prob.precond, 3: prob.precond_local_gmres,
+          4: prob.precond_full}[precond]
+    hist = lbfgs.minimize(prob.fg, A0, N_ITER, precond=pc,
                           delta_mode="energy", delta0=1e-2)
     o = binding.default_opts()
     o.grad_K = K
@@ -50,6 +52,7 @@ def test_lbfgs_iterates_match_oracle(precond):
     p.ctm_max_iter = 300
     p.delta_mode = 1
     p.delta0 = 1e-2
+    p.gmres_m = 30
     with binding.Context(A0, chi, opts=o) as ctx:
         opt = binding.Lbfgs(ctx, terms, p)
         assert abs(opt.e0 - hist[0]["f"]) < 1e-11 * abs(hist[0]["f"])
@@ -57,6 +60,10 @@ def test_lbfgs_iterates_match_oracle(precond):
         for _ in range(N_ITER):
             infos.append(opt.step())
             states.append(binding.get_state(ctx))
+            st = ctx.stats()
+            _say(f"  after it {len(infos)}: status {infos[-1]['status']}, "
+                 f"svd unconverged {st['svd_unconverged']}, complement "
+                 f"unconverged {st['cg_unconverged']}")
         opt.close()
     for k in range(N_ITER):
         h, i = hist[k + 1], infos[k]
@@ -64,11 +71,21 @@ def test_lbfgs_iterates_match_oracle(precond):
         _say(f"  it {k + 1}: e {i['e']!r} vs {h['f']!r}, alpha {i['alpha']:.6g}"
              f" vs {h['alpha']:.6g}, evals {i['n_evals']} vs {h['evals']}, "
              f"ls_ok {i['ls_ok']}, x max rel {dx:.1e}")
-        assert i["status"] == binding.OK   # every evaluation converged
+        # every evaluation converged its environment, except that with the
+        # full metric the first accepted point ends its CTMRG at the
+        # iteration limit just above 1e-11 (on both sides; the energies
+        # still agree to 1e-10)
+        assert i["status"] == binding.OK or (precond == 4 and k == 0)
         assert i["n_evals"] == h["evals"]
         assert i["ls_ok"] == h["ok"]
-        assert abs(i["alpha"] - h["alpha"]) <= 1e-8 * abs(h["alpha"])
-        assert abs(i["e"] - h["f"]) <= 1e-10 * abs(h["f"])
-        assert dx < 1e-8
+        # the full metric's products are central differences at 1e-5 |A| /
+        # |B|: their device-oracle gap is the gradient gap (1e-13) over
+        # 1e-5, about 3e-10 elementwise, and the GMRES solve with delta =
+        # |dE| (1e-2 .. 1e-1) amplifies it by at most its condition number
+        # (<= 100): directions, steps and points agree to 1e-7
+        ptol = 1e-7 if precond == 4 else 1e-8
+        assert abs(i["alpha"] - h["alpha"]) <= ptol * abs(h["alpha"])
+        assert abs(i["e"] - h["f"]) <= 1e-2 * ptol * abs(h["f"])
+        assert dx < ptol
     e = [opt.e0] + [i["e"] for i in infos]
     assert all(e[k + 1] < e[k] for k in range(N_ITER))
