@@ -26,6 +26,8 @@ lbfgs        L-BFGS with the Hager-Zhang line search and the preconditioner
              IV A).
 bp           belief-propagation (chi = 1) environment and its metric
              (Sec. III A).
+c4v          the C4v-symmetric real ansatz, QR-based CTMRG with one corner
+             and one edge, and its K-step gradient (Sec. IV A).
 full_metric  the full tangent-space metric (Eq. (10)) applied matrix-free as
              the mixed ket/bra second derivative of the per-site log-norm,
              and the GMRES solve of one cycle (Sec. III C).
