@@ -235,6 +235,54 @@ int precond_apply_dev_noalloc(ipeps_ctx* ctx, const double* d_g,
 size_t precond_noalloc_bytes(int Lx, int Ly, int d, int D, int chi);
 
 /* ------------------------------------------------------------------------
+ * C4v-symmetric real ansatz with a QR-based CTMRG (Sec. IV A: a one-site
+ * C4v-symmetric real iPEPS, the symmetry fixing the gauge, its environment
+ * from a QR-CTMRG, the gradient by reverse mode through the last K
+ * iterations).  1x1 unit cells, D >= 2, chi <= 128.
+ *
+ * The state is used through its projection A_s, the average of A over the
+ * eight elements of the square's symmetry group acting on the virtual legs
+ * [l, u, r, d]; c4v_converge and c4v_set_env replace the context's A by
+ * A_s.  The environment is one corner C [chi][chi] and one edge T
+ * [chi][D^2][chi] (both symmetric in their chi legs) standing for all four
+ * corners and edges, plus the warm-start block V [chi D^2][b] of the
+ * subspace iteration, b = c4v_block_size(chi) = chi + max(8, ceil(chi/4))
+ * made even, at most 128.  One iteration: enlarged corner M = T C T a;
+ * while the bond c has c D^2 <= chi it grows untruncated; otherwise one
+ * step of block subspace iteration, Q0 = qr(M V) (Cholesky QR in two
+ * passes, diag R > 0), Rayleigh-Ritz W of Q0^T M Q0 (the chi eigenvalues of
+ * largest |lambda| first, each group in descending signed order),
+ * V' = Q0 W with each column's entry of largest |v_r| (1 + r/(2n)) made
+ * positive, Q = the first chi columns of V'; C' = Q^T M Q, T' = Q^T (T a) Q,
+ * symmetrised and normalised.  The four-corner environment with every
+ * corner C and every edge T is written too, so ipeps_energy_grad,
+ * precond_apply and the other metric entry points work on it.
+ *
+ * c4v_converge: from the trace boundary (first call) or the previous C4v
+ * environment, until the corner-spectrum change is below tol (raised to
+ * the arithmetic's floor) or max_iter iterations.  Returns OK,
+ * NOT_CONVERGED (warning), or an error.
+ * c4v_energy_grad(_dev): energy per site and the gradient of
+ * A -> e(A_s, F^K(C*, T*, V*)) with the converged (C*, T*, V*) held fixed
+ * (K = grad_K), which lies in the symmetric subspace; grad NULL for the
+ * energy alone (the energy of the last K iterations' environment).
+ * c4v_get_env / c4v_set_env: C, T, V host buffers of the sizes above (V
+ * may be NULL; on set, NULL means no warm-start block); *bond receives the
+ * bond dimension reached (0: none yet).  Setting takes the bond as chi.
+ * Errors: EINVAL, ESTATE (no C4v environment), ENOTIMPL (cell larger than
+ * 1x1, D < 2 or chi > 128), ENOMEM, EHIP. */
+int c4v_block_size(int chi);
+int c4v_converge(ipeps_ctx* ctx, double tol, int max_iter, int* n_iter,
+                 double* delta);
+int c4v_energy_grad(ipeps_ctx* ctx, int n_terms, const ipeps_term* terms,
+                    double* e_per_site, double* grad);
+int c4v_energy_grad_dev(ipeps_ctx* ctx, int n_terms, const ipeps_term* terms,
+                        double* e_per_site, double* d_grad);
+int c4v_get_env(ipeps_ctx* ctx, double* C, double* T, double* V, int* bond);
+int c4v_set_env(ipeps_ctx* ctx, const double* C, const double* T,
+                const double* V);
+
+/* ------------------------------------------------------------------------
  * GMRES solve of the local-metric system (Sec. III C: P g' = g by
  * matrix-vector products only, one outer GMRES iteration of 30 Krylov
  * vectors): the operator of precond_apply, (N_local + delta I), solved per

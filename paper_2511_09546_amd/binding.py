@@ -39,6 +39,8 @@ API_FUNCTIONS = [
     "ipeps_lbfgs_free", "ipeps_get_state", "precond_apply_gmres",
     "precond_apply_gmres_dev", "log_norm_grad", "metric_full_apply",
     "metric_full_apply_dev", "precond_apply_full", "precond_apply_full_dev",
+    "c4v_block_size", "c4v_converge", "c4v_energy_grad",
+    "c4v_energy_grad_dev", "c4v_get_env", "c4v_set_env",
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
 PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
@@ -121,6 +123,17 @@ def load():
     lib.precond_apply_full_dev.argtypes = [c_void_p, c_void_p, c_double,
                                            c_int, c_double, c_double,
                                            c_void_p, _IP, _DP]
+    lib.c4v_block_size.argtypes = [c_int]
+    lib.c4v_converge.argtypes = [c_void_p, c_double, c_int, _IP, _DP]
+    lib.c4v_energy_grad.argtypes = [c_void_p, c_int, POINTER(Term), _DP,
+                                    _DP]
+    lib.c4v_energy_grad_dev.argtypes = [c_void_p, c_int, POINTER(Term), _DP,
+                                        c_void_p]
+    lib.c4v_get_env.argtypes = [c_void_p, _DP, _DP, _DP, _IP]
+    lib.c4v_set_env.argtypes = [c_void_p, _DP, _DP, _DP]
+    for name in ("c4v_block_size", "c4v_converge", "c4v_energy_grad",
+                 "c4v_energy_grad_dev", "c4v_get_env", "c4v_set_env"):
+        getattr(lib, name).restype = c_int
     for name in ("precond_apply_gmres", "precond_apply_gmres_dev",
                  "log_norm_grad", "metric_full_apply",
                  "metric_full_apply_dev", "precond_apply_full",
@@ -182,6 +195,11 @@ def load():
 
 def strerror(status: int) -> str:
     return load().ipeps_strerror(status).decode()
+
+
+def c4v_block_size(chi: int) -> int:
+    """Columns of the C4v subspace-iteration block for this chi."""
+    return load().c4v_block_size(chi)
 
 
 def _dp(a: np.ndarray):
@@ -432,6 +450,64 @@ class Context:
         if st != OK:
             raise IpepsError(st, "precond_apply_bp")
         return x
+
+    # ---- C4v ansatz and QR-CTMRG (1x1 cells)
+    def c4v_converge(self, tol: float, max_iter: int):
+        """QR-CTMRG of the projected state: (n_iter, delta, converged)."""
+        n = c_int(0)
+        dl = c_double(0.0)
+        st = load().c4v_converge(self._h, tol, max_iter, ctypes.byref(n),
+                                 ctypes.byref(dl))
+        if st < 0:
+            raise IpepsError(st, "c4v_converge")
+        return n.value, dl.value, st == OK
+
+    def c4v_energy_grad(self, terms, grad: bool = True):
+        arr, keep = make_terms(terms)
+        e = c_double(0.0)
+        g = np.zeros(self.shape) if grad else None
+        st = load().c4v_energy_grad(self._h, len(terms), arr,
+                                    ctypes.byref(e),
+                                    _dp(g) if grad else None)
+        del keep
+        if st != OK:
+            raise IpepsError(st, "c4v_energy_grad")
+        return e.value, g
+
+    def c4v_energy_grad_dev(self, terms, d_grad: int) -> float:
+        arr, keep = make_terms(terms)
+        e = c_double(0.0)
+        st = load().c4v_energy_grad_dev(self._h, len(terms), arr,
+                                        ctypes.byref(e), c_void_p(d_grad))
+        del keep
+        if st != OK:
+            raise IpepsError(st, "c4v_energy_grad_dev")
+        return e.value
+
+    def c4v_get_env(self):
+        """(C [chi][chi], T [chi][D^2][chi], V [chi D^2][b], bond)."""
+        chi, D2 = self.chi, self.D * self.D
+        b = c4v_block_size(chi)
+        C = np.zeros((chi, chi))
+        T = np.zeros((chi, D2, chi))
+        V = np.zeros((chi * D2, b))
+        bond = c_int(0)
+        st = load().c4v_get_env(self._h, _dp(C), _dp(T), _dp(V),
+                                ctypes.byref(bond))
+        if st != OK:
+            raise IpepsError(st, "c4v_get_env")
+        return C, T, V, bond.value
+
+    def c4v_set_env(self, C, T, V=None):
+        chi, D2 = self.chi, self.D * self.D
+        C = _f64(C).reshape(chi, chi)
+        T = _f64(T).reshape(chi, D2, chi)
+        if V is not None:
+            V = _f64(V).reshape(chi * D2, c4v_block_size(chi))
+        st = load().c4v_set_env(self._h, _dp(C), _dp(T),
+                                _dp(V) if V is not None else None)
+        if st != OK:
+            raise IpepsError(st, "c4v_set_env")
 
     # ---- GMRES solves and the full metric (1x1 cells)
     def precond_gmres(self, g, delta: float, m: int = 30, tol: float = 0.0):

@@ -56,6 +56,20 @@ class Tape {
   // view): out[l][j][k] = x[l][j][k] for l < a, j < b, k < c
   Var pad3(const Var& x, int a, int b, int c, std::vector<int64_t> shape);
 
+  // Q of the thin QR Y = Q R (n x b, diag R > 0) by Cholesky QR in two
+  // passes (FP64); a column whose R diagonal is below 1e-6 of the column
+  // scale |Y|_F / sqrt(b) is dropped (a zero column of Q)
+  Var qr_q(const Var& Y);
+  // eigenvectors (columns) of a symmetric b x b matrix (b even, <= 128):
+  // the k of largest |lambda| first, then the others, each group in
+  // descending signed order; the derivative uses x / (x^2 + eta^2),
+  // eta = 1e-12 max|lambda|, for 1 / (lambda_j - lambda_i)
+  Var eig_kept(const Var& B, int k);
+  // y = X diag(s) for an n x b X and a constant device vector s
+  Var colscale(const Var& X, const Tensor& s);
+  // y = (x + P x) / 2 for a permutation P that is its own inverse
+  Var sym_pair(const Var& x, const std::vector<int>& perm);
+
   void push(std::function<void()> f) {
     if (rec) ops_.push_back(std::move(f));
   }

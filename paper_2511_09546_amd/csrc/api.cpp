@@ -332,6 +332,101 @@ int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
   return res;
 }
 
+int c4v_block_size(int chi) {
+  return chi >= 1 && chi <= 128 ? c4v_block(chi) : -1;
+}
+
+static int c4v_ok(const Context& cx) {
+  if (cx.nsite() != 1 || cx.D < 2 || cx.chi > 128) return IPEPS_ENOTIMPL;
+  return IPEPS_OK;
+}
+
+int c4v_converge(ipeps_ctx* c, double tol, int max_iter, int* n_iter,
+                 double* delta) {
+  if (!c || max_iter < 0 || std::isnan(tol)) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  int st = c4v_ok(cx);
+  if (st != IPEPS_OK) return st;
+  int it = 0, warn = 0;
+  double dl = INFINITY;
+  st = guarded([&]() {
+    warn = ipeps::c4v_converge(cx, tol, max_iter, &it, &dl);
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  if (n_iter) *n_iter = it;
+  if (delta) *delta = dl;
+  return warn ? IPEPS_NOT_CONVERGED : IPEPS_OK;
+}
+
+static int c4v_eg_impl(ipeps_ctx* c, int n_terms, const ipeps_term* H,
+                       double* e_per_site, double* grad, bool dev) {
+  if (!c || !e_per_site) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  int st = c4v_ok(cx);
+  if (st != IPEPS_OK) return st;
+  std::vector<TermSpec> terms;
+  st = parse_terms(cx, n_terms, H, terms);
+  if (st != IPEPS_OK) return st;
+  if (cx.c4v_c == 0) return IPEPS_ESTATE;
+  double e = 0.0;
+  st = guarded([&]() {
+    PrecScope ps(cx.dev, late_prec(cx));
+    e = ipeps::c4v_energy_grad(cx, terms, grad, dev);
+    return IPEPS_OK;
+  });
+  if (st != IPEPS_OK) return st;
+  *e_per_site = e;
+  return IPEPS_OK;
+}
+
+int c4v_energy_grad(ipeps_ctx* c, int n_terms, const ipeps_term* H,
+                    double* e_per_site, double* grad) {
+  return c4v_eg_impl(c, n_terms, H, e_per_site, grad, false);
+}
+
+int c4v_energy_grad_dev(ipeps_ctx* c, int n_terms, const ipeps_term* H,
+                        double* e_per_site, double* d_grad) {
+  if (!d_grad) return IPEPS_EINVAL;
+  return c4v_eg_impl(c, n_terms, H, e_per_site, d_grad, true);
+}
+
+int c4v_get_env(ipeps_ctx* c, double* C, double* T, double* V, int* bond) {
+  if (!c || !C || !T) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  int st = c4v_ok(cx);
+  if (st != IPEPS_OK) return st;
+  if (cx.c4v_c == 0) return IPEPS_ESTATE;
+  return guarded([&]() {
+    cx.dev.download(cx.c4v_C, C);
+    cx.dev.download(cx.c4v_T, T);
+    if (V) {
+      if (cx.c4v_V.ptr)
+        cx.dev.download(cx.c4v_V, V);
+      else
+        std::fill(V, V + (size_t)cx.chi * cx.D2 * c4v_block(cx.chi), 0.0);
+    }
+    if (bond) *bond = cx.c4v_c;
+    return IPEPS_OK;
+  });
+}
+
+int c4v_set_env(ipeps_ctx* c, const double* C, const double* T,
+                const double* V) {
+  if (!c || !C || !T) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  int st = c4v_ok(cx);
+  if (st != IPEPS_OK) return st;
+  const size_t nc = (size_t)cx.chi * cx.chi, nt = nc * cx.D2;
+  if (!all_finite(C, nc) || !all_finite(T, nt) ||
+      (V && !all_finite(V, (size_t)cx.chi * cx.D2 * c4v_block(cx.chi))))
+    return IPEPS_EINVAL;
+  return guarded([&]() {
+    ipeps::c4v_set_env(cx, C, T, V, false);
+    return IPEPS_OK;
+  });
+}
+
 static int gmres_args_ok(double delta, int m, double tol) {
   return delta > 0.0 && std::isfinite(delta) && m >= 1 && m <= 256 &&
          tol >= 0.0 && std::isfinite(tol);

@@ -43,6 +43,7 @@ static std::vector<int> rot_perm(int c) {
 void build_double_layer(Context& cx) {
   const int ns = cx.nsite(), D2 = cx.D2, D = cx.D;
   cx.bp_valid = false;  // the belief-propagation messages belong to old A
+  cx.c4v_sym = false;   // A is no longer known to be projected
   const int64_t a4 = (int64_t)D2 * D2 * D2 * D2;
   if (cx.a_rot.numel() != ns * 4 * a4)
     cx.a_rot = cx.dev.empty({ns, 4, D2, D2, D2, D2});

@@ -341,6 +341,20 @@ void null_threshold(Device& dev, double* S, int b, double rel, int batch,
 // (dependent) directions give zero rows and columns.
 void chol_orth_factor(Device& dev, const double* G, double* R, int b,
                       int batch);
+// out[i][j] = M[max(i,j)][min(i,j)] (lower triangle mirrored), b x b
+void copyltu(Device& dev, const double* M, double* out, int b);
+// out = F o X, F_ij = x / (x^2 + eta^2), x = lam_j - lam_i, F_ii = 0,
+// eta = rel max|lam| (the broadened eigenvector derivative), b x b
+void eig_fmul(Device& dev, const double* lam, const double* X, double* out,
+              int b, double rel);
+// Eigenpairs in descending signed order (lam, columns of W, b x b)
+// reordered: the k of largest |lambda| first (ties: the larger signed
+// value), then the others, each group in descending signed order
+void eig_order_kept(Device& dev, const double* lam, const double* W,
+                    double* lam_out, double* W_out, int b, int k);
+// s[j] = sign of the entry of column j of X (n x b) maximising
+// |x_rj| (1 + r / (2n)) (first on ties), +1 for a zero column
+void col_sign(Device& dev, const double* X, int64_t n, int b, double* s);
 }  // namespace ipeps
 
 namespace ipeps {

@@ -171,6 +171,14 @@ struct Context {
 
   int device = 0;        // HIP device of the context (current at ctm_init)
 
+  // C4v QR-CTMRG state (1x1 cell): corner [chi][chi], edge [chi][D2][chi],
+  // warm-start block [chi D2][c4v_b]; c4v_c the bond dimension reached (0:
+  // no C4v environment yet)
+  Tensor c4v_C, c4v_T, c4v_V;
+  int c4v_c = 0;
+  int c4v_b = 0;
+  bool c4v_sym = false;  // A holds its own symmetric projection
+
   int nsite() const { return lat.n(); }
   int ncut() const { return 4 * lat.n(); }
   Tensor Cv(const Env& e, int c, int s) const;
@@ -284,6 +292,30 @@ void full_metric_apply(Context& cx, const double* B, double* NB,
 void precondition_full(Context& cx, const double* g, double delta, int m,
                        double tol, double rel_step, double* x, int* n_used,
                        double* rel_resid, bool on_device);
+
+// c4v.cpp (1x1 cell)
+// block size of the subspace iteration: chi + max(8, ceil(chi/4)), even,
+// at most 128
+int c4v_block(int chi);
+// out = the average of in [d][D]^4 over the square's symmetry group acting
+// on the virtual legs (in and out device, distinct)
+void c4v_symmetrize(Device& dev, const double* in, double* out, int d, int D);
+// A <- A_s and the double layer rebuilt
+void c4v_project_state(Context& cx);
+// QR-CTMRG of the projected state until the corner-spectrum change is
+// below tol (raised to the arithmetic's floor) or max_iter iterations;
+// writes the replicated four-corner environment; returns 1 when tol was
+// not reached
+int c4v_converge(Context& cx, double tol, int max_iter, int* n_iter,
+                 double* delta);
+// (C, T, V) given (host or device; V null: no warm-start block), bond chi;
+// the state is projected first
+void c4v_set_env(Context& cx, const double* C, const double* T,
+                 const double* V, bool on_device);
+// energy per site and (grad non-null) the projected K-step gradient, the
+// converged (C, T, V) held fixed
+double c4v_energy_grad(Context& cx, const std::vector<TermSpec>& terms,
+                       double* grad, bool on_device);
 
 // adjoint.cpp
 // grad is a host pointer, or a device pointer when on_device

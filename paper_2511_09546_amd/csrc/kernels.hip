@@ -1749,3 +1749,120 @@ void copy2d(Device& dev, const double* src, int64_t lds, double* dst,
 }
 
 }  // namespace ipeps
+
+namespace ipeps {
+
+// ------------------------------------------------ C4v QR-CTMRG helpers
+// out[i][j] = M[max(i,j)][min(i,j)] (the lower triangle mirrored), b x b
+__global__ void copyltu_kernel(const double* M, double* out, int b) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < b * b;
+       e += gridDim.x * blockDim.x) {
+    const int i = e / b, j = e % b;
+    out[e] = i >= j ? M[i * b + j] : M[j * b + i];
+  }
+}
+
+void copyltu(Device& dev, const double* M, double* out, int b) {
+  hipLaunchKernelGGL(copyltu_kernel, dim3(grid_for((int64_t)b * b, 256)),
+                     dim3(256), 0, dev.stream, M, out, b);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// out[i][j] = F_ij X[i][j], F_ij = x / (x^2 + eta^2), x = lam_j - lam_i,
+// F_ii = 0; eta = rel * max|lam|
+__global__ void eig_fmul_kernel(const double* lam, const double* X,
+                                double* out, int b, double rel) {
+  double mx = 0.0;
+  for (int i = 0; i < b; ++i) mx = fmax(mx, fabs(lam[i]));
+  const double eta = rel * mx;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < b * b;
+       e += gridDim.x * blockDim.x) {
+    const int i = e / b, j = e % b;
+    const double x = lam[j] - lam[i];
+    out[e] = i == j ? 0.0 : X[e] * x / (x * x + eta * eta);
+  }
+}
+
+void eig_fmul(Device& dev, const double* lam, const double* X, double* out,
+              int b, double rel) {
+  hipLaunchKernelGGL(eig_fmul_kernel, dim3(grid_for((int64_t)b * b, 256)),
+                     dim3(256), 0, dev.stream, lam, X, out, b, rel);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Reorders eigenpairs given in descending signed order: the k of largest
+// |lambda| (ties: the larger signed value, i.e. the lower index) first,
+// then the others, each group keeping its descending signed order.  One
+// workgroup; b <= 128.
+__global__ void eig_order_kept_kernel(const double* lam, const double* W,
+                                      double* lam_out, double* W_out, int b,
+                                      int k) {
+  __shared__ int src[128];
+  if (threadIdx.x == 0) {
+    int nk = 0, nd = k;
+    for (int i = 0; i < b; ++i) {
+      // rank of i by (|lambda| descending, index ascending)
+      int r = 0;
+      const double ai = fabs(lam[i]);
+      for (int j = 0; j < b; ++j) {
+        const double aj = fabs(lam[j]);
+        r += (aj > ai || (aj == ai && j < i)) ? 1 : 0;
+      }
+      if (r < k)
+        src[nk++] = i;
+      else
+        src[nd++] = i;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < b * b; e += blockDim.x) {
+    const int r = e / b, c = e % b;
+    W_out[e] = W[r * b + src[c]];
+  }
+  for (int c = threadIdx.x; c < b; c += blockDim.x) lam_out[c] = lam[src[c]];
+}
+
+void eig_order_kept(Device& dev, const double* lam, const double* W,
+                    double* lam_out, double* W_out, int b, int k) {
+  if (b < 1 || b > 128 || k < 0 || k > b)
+    throw ArgError("eig_order_kept: needs 0 <= k <= b <= 128");
+  hipLaunchKernelGGL(eig_order_kept_kernel, dim3(1), dim3(256), 0,
+                     dev.stream, lam, W, lam_out, W_out, b, k);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// s[j] = sign of the entry of column j of X (n x b, row major) maximising
+// |x_rj| (1 + r / (2n)) (first on ties), +1 for a zero column.  One wave
+// per column.
+__global__ void col_sign_kernel(const double* X, int64_t n, int b,
+                                double* s) {
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= b) return;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = lane; i < n; i += 64) {
+    const double a = fabs(X[i * b + j]) * (1.0 + (double)i / (2.0 * (double)n));
+    if (a > best) {
+      best = a;
+      bi = i;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ob = __shfl_down(best, o, 64);
+    const int64_t oi = __shfl_down(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if (lane == 0) s[j] = X[bi * b + j] < 0.0 ? -1.0 : 1.0;
+}
+
+void col_sign(Device& dev, const double* X, int64_t n, int b, double* s) {
+  hipLaunchKernelGGL(col_sign_kernel, dim3((b + 3) / 4), dim3(256), 0,
+                     dev.stream, X, n, b, s);
+  IPEPS_HIP(hipGetLastError());
+}
+
+}  // namespace ipeps
