@@ -51,6 +51,22 @@ int ipeps_debug_permute(int rank, const long* shape, const int* perm,
                         double alpha, const double* in, double beta,
                         double* out);
 
+/* out = alpha einsum(spec, A, B) + beta out by the library's contraction
+ * planner, on host data: spec like "mgek,gebf->mfkb" (single-letter
+ * labels; every label of an operand is either shared with the other one or
+ * kept in the output); `count` independent items of the same shapes, item i
+ * at A + i |A|, B + i |B|, out + i |out| (contracted in one batched launch,
+ * as the network's contractions are); products in the arithmetic `prec`
+ * (ipeps_prec).  mode 0: the planner's choice, which may write a permuted
+ * output straight from the GEMM epilogue; mode 1: never (GEMM in its own
+ * order, then a permute pass).  *scattered receives the number of launches
+ * that wrote a scattered output.  Returns a status. */
+int ipeps_debug_einsum(const char* spec, int prec, int mode, int count,
+                       int rankA, const long* shapeA, const double* A,
+                       int rankB, const long* shapeB, const double* B,
+                       double alpha, double beta, double* out,
+                       int* scattered);
+
 /* Iteration counters of a context since its creation: out[0] subspace
  * iterations, out[1] projector-SVD calls, out[2] largest final subspace
  * residual (relative to s_1), out[3] complement-CG iterations of the

@@ -58,8 +58,20 @@ class Energy(torch.autograd.Function):
 
 def energy(A: torch.Tensor, lib_ctx: binding.Context, terms,
            tol: float = 1e-10, max_iter: int = 200) -> torch.Tensor:
-    """Energy per site (0-d tensor) whose backward gives de/dA."""
-    return Energy.apply(A, lib_ctx, terms, tol, max_iter)
+    """Energy per site (0-d tensor) whose backward gives de/dA.
+
+    When no gradient can be asked for (A does not require one, or autograd
+    is off) only the energy is evaluated: the reverse pass through the
+    unrolled iterations, several times the cost of the energy itself, is
+    skipped."""
+    if torch.is_grad_enabled() and A.requires_grad:
+        return Energy.apply(A, lib_ctx, terms, tol, max_iter)
+    A = _check(A, "A", lib_ctx.shape)
+    torch.cuda.current_stream(A.device).synchronize()
+    lib_ctx.set_state_dev(A.data_ptr())
+    lib_ctx.last_converge = lib_ctx.converge(tol, max_iter)
+    e, _ = lib_ctx.energy_grad(terms, grad=False)
+    return torch.tensor(e, dtype=torch.float64, device=A.device)
 
 
 def precondition(lib_ctx: binding.Context, g: torch.Tensor,

@@ -47,7 +47,8 @@ PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
                    "ipeps_debug_svd_ts", "ipeps_debug_stats",
                    "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time",
-                   "ipeps_debug_permute", "ipeps_debug_set_fault"]
+                   "ipeps_debug_permute", "ipeps_debug_set_fault",
+                   "ipeps_debug_einsum"]
 
 
 class IpepsError(RuntimeError):
@@ -174,6 +175,10 @@ def load():
     lib.ipeps_debug_sym_eig.argtypes = [c_int, c_int, _DP, _DP, _DP]
     lib.ipeps_debug_permute.argtypes = [c_int, POINTER(ctypes.c_long),
                                         _IP, c_double, _DP, c_double, _DP]
+    lib.ipeps_debug_einsum.argtypes = [
+        ctypes.c_char_p, c_int, c_int, c_int, c_int, POINTER(ctypes.c_long),
+        _DP, c_int, POINTER(ctypes.c_long), _DP, c_double, c_double, _DP,
+        _IP]
     lib.ipeps_debug_stats.argtypes = [c_void_p, _DP]
     lib.ipeps_debug_set_fault.argtypes = [c_void_p, c_int, c_double]
     lib.ipeps_debug_svd_ts.argtypes = [c_int, c_int, c_int, _DP, _DP, _DP,
@@ -187,7 +192,7 @@ def load():
                  "ipeps_debug_sym_eig", "ipeps_debug_svd_ts",
                  "ipeps_debug_stats", "ipeps_debug_gemm_prec",
                  "ipeps_debug_gemm_time", "ipeps_debug_permute",
-                 "ipeps_debug_set_fault"):
+                 "ipeps_debug_set_fault", "ipeps_debug_einsum"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -663,6 +668,25 @@ def debug_permute(X, perm, alpha=1.0, beta=0.0, out=None):
     if st != OK:
         raise IpepsError(st, "ipeps_debug_permute")
     return out
+
+
+def debug_einsum(spec, A, B, out, prec=0, mode=0, alpha=1.0, beta=0.0):
+    """alpha einsum(spec, A[i], B[i]) + beta out[i] for the items i of the
+    leading axis of A, B, out, by the library's contraction planner (one
+    batched launch).  Returns (result, number of launches whose GEMM wrote
+    the permuted output from its epilogue)."""
+    A, B = _f64(A), _f64(B)
+    out = _f64(out).copy()
+    n = A.shape[0]
+    sa = (ctypes.c_long * (A.ndim - 1))(*A.shape[1:])
+    sb = (ctypes.c_long * (B.ndim - 1))(*B.shape[1:])
+    sc = c_int(0)
+    st = load().ipeps_debug_einsum(spec.encode(), prec, mode, n, A.ndim - 1,
+                                   sa, _dp(A), B.ndim - 1, sb, _dp(B), alpha,
+                                   beta, _dp(out), ctypes.byref(sc))
+    if st != OK:
+        raise IpepsError(st, "ipeps_debug_einsum")
+    return out, sc.value
 
 
 def debug_svd_ts(W):

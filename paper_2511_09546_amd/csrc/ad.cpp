@@ -31,6 +31,31 @@ static void parse3(const std::string& spec, std::string& a, std::string& b,
   o = spec.substr(ar + 2);
 }
 
+// The two backward contractions of out = einsum(la, lb -> lo) read the
+// incoming gradient with its labels grouped as [shared by la and lb | only
+// in la | only in lb] (in lo's order within each group): the first reads it
+// as [batch, free, contracted], the second as [batch, contracted, free].
+// When lo interleaves the groups and both operands need their gradient, the
+// gradient is permuted into that grouping once, instead of once by each
+// contraction.  Returns lo when it is grouped already.
+static std::string grad_grouping(const std::string& la, const std::string& lb,
+                                 const std::string& lo) {
+  std::string bt, ga, gb;
+  for (char ch : lo) {
+    const bool ia = la.find(ch) != std::string::npos;
+    const bool ib = lb.find(ch) != std::string::npos;
+    (ia && ib ? bt : (ia ? ga : gb)) += ch;
+  }
+  return bt + ga + gb;
+}
+
+static std::vector<int> label_perm(const std::string& from,
+                                   const std::string& to) {
+  std::vector<int> p;
+  for (char ch : to) p.push_back((int)from.find(ch));
+  return p;
+}
+
 Var Tape::einsum(const std::string& spec, const Var& a, const Var& b) {
   auto out = std::make_shared<Node>();
   out->v = ipeps::einsum(dev, spec, a->v, b->v);
@@ -41,15 +66,22 @@ Var Tape::einsum(const std::string& spec, const Var& a, const Var& b) {
     push([this, a, b, out, la, lb, lo]() {
       if (!has_grad(out)) return;
       double beta;
+      std::string lg = lo;
+      Tensor g = out->g;
+      if (a->req && b->req) {
+        const std::string grp = grad_grouping(la, lb, lo);
+        if (grp != lo) {
+          g = permuted(dev, out->g, label_perm(lo, grp));
+          lg = grp;
+        }
+      }
       if (a->req) {
         Tensor& ga = grad_target(dev, a.get(), beta);
-        einsum_into(dev, lo + "," + lb + "->" + la, out->g, b->v, ga, 1.0,
-                    beta);
+        einsum_into(dev, lg + "," + lb + "->" + la, g, b->v, ga, 1.0, beta);
       }
       if (b->req) {
         Tensor& gb = grad_target(dev, b.get(), beta);
-        einsum_into(dev, la + "," + lo + "->" + lb, a->v, out->g, gb, 1.0,
-                    beta);
+        einsum_into(dev, la + "," + lg + "->" + lb, a->v, g, gb, 1.0, beta);
       }
     });
   }
@@ -113,25 +145,36 @@ std::vector<Var> Tape::einsum_n(const std::string& spec,
     std::string la, lb, lo;
     parse3(spec, la, lb, lo);
     push([this, a, b, out, la, lb, lo]() {
+      // gradients grouped once when both sides need them (grad_grouping)
+      const std::string grp = grad_grouping(la, lb, lo);
+      bool both = grp != lo;
+      for (size_t i = 0; i < out.size() && both; ++i)
+        both = !has_grad(out[i]) || (a[i]->req && b[i]->req);
+      const std::string lg = both ? grp : lo;
+      std::vector<Tensor> g(out.size());
+      for (size_t i = 0; i < out.size(); ++i)
+        if (has_grad(out[i]))
+          g[i] = both ? permuted(dev, out[i]->g, label_perm(lo, grp))
+                      : out[i]->g;
       std::vector<Tensor> f, s;
       std::vector<Node*> k;
       for (size_t i = 0; i < out.size(); ++i)
         if (has_grad(out[i]) && a[i]->req) {
-          f.push_back(out[i]->g);
+          f.push_back(g[i]);
           s.push_back(b[i]->v);
           k.push_back(a[i].get());
         }
-      accumulate_n(dev, lo + "," + lb + "->" + la, f, s, k);
+      accumulate_n(dev, lg + "," + lb + "->" + la, f, s, k);
       f.clear();
       s.clear();
       k.clear();
       for (size_t i = 0; i < out.size(); ++i)
         if (has_grad(out[i]) && b[i]->req) {
           f.push_back(a[i]->v);
-          s.push_back(out[i]->g);
+          s.push_back(g[i]);
           k.push_back(b[i].get());
         }
-      accumulate_n(dev, la + "," + lo + "->" + lb, f, s, k);
+      accumulate_n(dev, la + "," + lg + "->" + lb, f, s, k);
     });
   }
   return out;

@@ -123,6 +123,55 @@ int ipeps_debug_permute(int rank, const long* shape, const int* perm,
   });
 }
 
+int ipeps_debug_einsum(const char* spec, int prec, int mode, int count,
+                       int rankA, const long* shapeA, const double* A,
+                       int rankB, const long* shapeB, const double* B,
+                       double alpha, double beta, double* out,
+                       int* scattered) {
+  if (!spec || !A || !B || !out || !scattered || count < 1 || count > 64 ||
+      rankA < 1 || rankA > 12 || rankB < 1 || rankB > 12 || mode < 0 ||
+      mode > 1 || (prec < IPEPS_FP64 || prec > IPEPS_BF16X1))
+    return IPEPS_EINVAL;
+  const std::string sp(spec);
+  const size_t c = sp.find(','), ar = sp.find("->");
+  if (c == std::string::npos || ar == std::string::npos || ar < c ||
+      (int)c != rankA || (int)(ar - c - 1) != rankB)
+    return IPEPS_EINVAL;
+  const std::string la = sp.substr(0, c), lb = sp.substr(c + 1, ar - c - 1),
+                    lo = sp.substr(ar + 2);
+  std::vector<int64_t> sa(shapeA, shapeA + rankA), sb(shapeB, shapeB + rankB),
+      so;
+  for (char ch : lo) {
+    const size_t i = la.find(ch), j = lb.find(ch);
+    if (i == std::string::npos && j == std::string::npos) return IPEPS_EINVAL;
+    so.push_back(i != std::string::npos ? sa[i] : sb[j]);
+  }
+  int64_t na = 1, nb = 1, no = 1;
+  for (auto x : sa) na *= x;
+  for (auto x : sb) nb *= x;
+  for (auto x : so) no *= x;
+  if (na < 1 || nb < 1 || no < 1 || count * std::max(na, std::max(nb, no)) >=
+                                         (1LL << 31))
+    return IPEPS_EINVAL;
+  return run([&](Device& dev) {
+    std::vector<Tensor> ta, tb, to;
+    for (int i = 0; i < count; ++i) {
+      Tensor a = dev.empty(sa), b = dev.empty(sb), o = dev.empty(so);
+      dev.upload(a, A + i * na);
+      dev.upload(b, B + i * nb);
+      dev.upload(o, out + i * no);
+      ta.push_back(a);
+      tb.push_back(b);
+      to.push_back(o);
+    }
+    dev.allow_scatter = mode == 0;
+    PrecScope ps(dev, prec);
+    einsum_into_n(dev, sp, ta, tb, to, alpha, beta);
+    for (int i = 0; i < count; ++i) dev.download(to[i], out + i * no);
+    *scattered = (int)dev.scatter_count;
+  });
+}
+
 int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
                         double* lam) {
   if (!G || !V || !lam || b < 2 || b > 128 || b % 2 || batch < 1)

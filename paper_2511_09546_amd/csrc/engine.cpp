@@ -296,8 +296,43 @@ struct Plan {
   std::string first, second, out;  // label orders actually used
   bool tA = false, tB = false;
   bool perm_first = false, perm_second = false, perm_out = false;
+  bool scatter = false;    // the GEMM writes the output layout directly
   int64_t cost = std::numeric_limits<int64_t>::max();
 };
+
+// Mixed-radix digits (least significant first) of an index that enumerates
+// the labels `ls` row-major, each digit's stride that of its label in the
+// row-major tensor with labels `o` and shape `shape`; adjacent digits that
+// are contiguous in the output are merged.  False when more than
+// CMAP_DIGITS digits remain.
+bool cmap_digits(const std::string& ls, const std::string& o,
+                 const std::vector<int64_t>& shape, int& n, int* ext,
+                 int64_t* str) {
+  std::vector<int64_t> e, st;
+  for (int i = (int)ls.size() - 1; i >= 0; --i) {
+    const size_t pos = o.find(ls[i]);
+    int64_t stride = 1;
+    for (size_t j = pos + 1; j < o.size(); ++j) stride *= shape[j];
+    const int64_t ex = shape[pos];
+    if (!e.empty() && st.back() * e.back() == stride) {
+      e.back() *= ex;
+    } else {
+      e.push_back(ex);
+      st.push_back(stride);
+    }
+  }
+  if (e.empty()) {  // no label: a single index 0
+    e.push_back(1);
+    st.push_back(0);
+  }
+  if ((int)e.size() > CMAP_DIGITS) return false;
+  n = (int)e.size();
+  for (int i = 0; i < n; ++i) {
+    ext[i] = (int)e[i];
+    str[i] = st[i];
+  }
+  return true;
+}
 
 }  // namespace
 
@@ -364,6 +399,13 @@ void einsum_into_n(Device& dev, const std::string& spec,
   const std::string free_b_own = own_order(s.b, free_b_o);
 
   int64_t nA = A.numel(), nB = B.numel(), nO = out.numel();
+  // a scattered output needs the batch labels next to each other in the
+  // output (one batch stride)
+  bool batch_adjacent = true;
+  if (!batch.empty()) {
+    const size_t p0 = s.o.find(batch[0]);
+    batch_adjacent = s.o.compare(p0, batch.size(), batch) == 0;
+  }
   Plan best;
   for (int swap = 0; swap < 2; ++swap) {
     const std::string& L1 = swap ? s.b : s.a;
@@ -406,13 +448,33 @@ void einsum_into_n(Device& dev, const std::string& spec,
           }
           p.out = batch + f1 + f2;
           p.perm_out = (p.out != s.o);
-          p.cost = (p.perm_first ? n1 : 0) + (p.perm_second ? n2 : 0) +
-                   (p.perm_out ? 2 * nO : 0);
+          const int64_t pin = (p.perm_first ? n1 : 0) +
+                              (p.perm_second ? n2 : 0);
+          p.cost = pin + (p.perm_out ? 2 * nO : 0);
           // prefer no transposes on ties (slightly faster loads)
-          if (p.cost < best.cost ||
-              (p.cost == best.cost && (int)p.tA + (int)p.tB <
-                                          (int)best.tA + (int)best.tB))
-            best = p;
+          auto take = [&](const Plan& q) {
+            if (q.cost < best.cost ||
+                (q.cost == best.cost &&
+                 ((int)q.scatter > (int)best.scatter ||
+                  ((int)q.scatter == (int)best.scatter &&
+                   (int)q.tA + (int)q.tB < (int)best.tA + (int)best.tB))))
+              best = q;
+          };
+          take(p);
+          if (p.perm_out && batch_adjacent && dev.allow_scatter) {
+            // the same GEMM writing the output layout from its epilogue: no
+            // permute pass.  Its stores run along the fastest column digit,
+            // coalesced when that is the output's innermost label (runs of
+            // that label's extent); otherwise they are strided
+            Plan q = p;
+            q.perm_out = false;
+            q.scatter = true;
+            const char inner = s.o.back();
+            const bool coal = !f2.empty() && f2.back() == inner;
+            const int64_t ein = dim_of(inner, s.a, A, s.b, B);
+            q.cost = pin + (coal ? (ein >= 8 ? 0 : nO / 2) : 4 * nO);
+            take(q);
+          }
         }
       }
     }
@@ -450,6 +512,37 @@ void einsum_into_n(Device& dev, const std::string& spec,
 
   std::vector<Tensor> dst(outs);
   double beta_g = beta;
+  CMap cm;
+  int64_t sC_out = M * N;
+  if (best.scatter) {
+    const std::vector<int64_t>& osh = out.shape;
+    if (!cmap_digits(lf1, s.o, osh, cm.nr, cm.re, cm.rs) ||
+        !cmap_digits(lf2, s.o, osh, cm.nc, cm.ce, cm.cs)) {
+      // too many digits: write the GEMM's own order and permute
+      best.scatter = false;
+      best.perm_out = true;
+    } else if (!batch.empty()) {
+      const size_t pl = s.o.find(batch.back());
+      sC_out = 1;
+      for (size_t j = pl + 1; j < s.o.size(); ++j) sC_out *= osh[j];
+    }
+    if (best.scatter) {
+      // every address the epilogue forms lies inside the output: the digit
+      // extents multiply to M and N, and the largest offset of a batch item
+      // plus the largest batch offset is below the element count
+      int64_t pr = 1, pc = 1, top = (nbatch - 1) * sC_out;
+      for (int i = 0; i < cm.nr; ++i) {
+        pr *= cm.re[i];
+        top += (cm.re[i] - 1) * cm.rs[i];
+      }
+      for (int i = 0; i < cm.nc; ++i) {
+        pc *= cm.ce[i];
+        top += (cm.ce[i] - 1) * cm.cs[i];
+      }
+      if (pr != M || pc != N || top >= out.numel() || top < 0)
+        throw std::logic_error("einsum: scattered layout out of range");
+    }
+  }
   if (best.perm_out) {
     std::vector<int64_t> sh;
     for (char ch : best.out) sh.push_back(dim_of(ch, s.a, A, s.b, B));
@@ -459,10 +552,13 @@ void einsum_into_n(Device& dev, const std::string& spec,
   const int64_t lda = best.tA ? M : K;
   const int64_t ldb = best.tB ? K : N;
   const double alpha_g = best.perm_out ? 1.0 : alpha;
+  const CMap* cmp = best.scatter ? &cm : nullptr;
+  if (best.scatter) ++dev.scatter_count;
   if (ni == 1 || nbatch > 1) {
     for (size_t i = 0; i < ni; ++i)
       gemm(dev, best.tA, best.tB, M, N, K, alpha_g, op1[i].ptr, lda, M * K,
-           op2[i].ptr, ldb, K * N, beta_g, dst[i].ptr, N, M * N, nbatch);
+           op2[i].ptr, ldb, K * N, beta_g, dst[i].ptr, N, sC_out, nbatch,
+           cmp);
   } else {
     // the items are independent products of one shape: one pointer batch
     std::vector<const double*> pa(ni), pb(ni);
@@ -473,7 +569,7 @@ void einsum_into_n(Device& dev, const std::string& spec,
       pc[i] = dst[i].ptr;
     }
     gemm_ptrs(dev, best.tA, best.tB, M, N, K, alpha_g, pa, lda, pb, ldb,
-              beta_g, pc, N);
+              beta_g, pc, N, cmp);
   }
   if (best.perm_out)
     for (size_t i = 0; i < ni; ++i) {

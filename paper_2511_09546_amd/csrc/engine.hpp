@@ -167,6 +167,11 @@ struct Device {
   Pool pool;
   Profiler prof;
   int cprec = PREC_FP64;  // arithmetic of the GEMMs issued now
+  // contractions may write a permuted output from the GEMM epilogue
+  // (false: GEMM in its own order, then a permute pass); the count of the
+  // contractions that did
+  bool allow_scatter = true;
+  long scatter_count = 0;
 
   Tensor empty(std::vector<int64_t> shape);
   Tensor zeros(std::vector<int64_t> shape);
@@ -198,20 +203,37 @@ struct PrecScope {
 };
 
 // ---------------------------------------------------------------- kernels
+// Scattered layout of a GEMM result: element (row, col) of C[b] lives at
+// C[b] + roff(row) + coff(col), where roff splits row into nr mixed-radix
+// digits (extents re[], least significant first) and sums digit * rs[],
+// and coff does the same for col with ce[], cs[].  nr == 0 is the plain
+// row-major layout with leading dimension ldc.  A permutation of the
+// output labels of a contraction is such a layout, so the GEMM epilogue
+// writes the permuted tensor directly.
+constexpr int CMAP_DIGITS = 4;
+struct CMap {
+  int nr = 0, nc = 0;
+  int re[CMAP_DIGITS] = {0, 0, 0, 0}, ce[CMAP_DIGITS] = {0, 0, 0, 0};
+  int64_t rs[CMAP_DIGITS] = {0, 0, 0, 0}, cs[CMAP_DIGITS] = {0, 0, 0, 0};
+};
+
 // C[b] = alpha op(A[b]) op(B[b]) + beta C[b], row major; op(A) is M x K
 // (A[m*lda+k], or A[k*lda+m] when tA), op(B) is K x N (B[k*ldb+n], or
-// B[n*ldb+k] when tB), batch strides sA, sB, sC in elements.
+// B[n*ldb+k] when tB), batch strides sA, sB, sC in elements.  With cm, C[b]
+// is in the scattered layout cm describes (ldc unused).
 void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
           double alpha, const double* A, int64_t lda, int64_t sA,
           const double* B, int64_t ldb, int64_t sB, double beta, double* C,
-          int64_t ldc, int64_t sC, int64_t batch = 1);
+          int64_t ldc, int64_t sC, int64_t batch = 1,
+          const CMap* cm = nullptr);
 
 // Batched GEMM over arbitrary operand addresses (one launch): C[i] = alpha
 // op(A[i]) op(B[i]) + beta C[i], same shapes and leading dimensions.
 void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                int64_t K, double alpha, const std::vector<const double*>& A,
                int64_t lda, const std::vector<const double*>& B, int64_t ldb,
-               double beta, const std::vector<double*>& C, int64_t ldc);
+               double beta, const std::vector<double*>& C, int64_t ldc,
+               const CMap* cm = nullptr);
 
 // gemm_ptrs with the A operands stored in FP32 (the products in the FP32
 // or BF16x3 arithmetic of the device; FP64 is refused).

@@ -66,6 +66,30 @@ struct PtrArgs {
   double* c[MAXP];
 };
 
+// offset of index x in a mixed-radix layout of n digits (CMap)
+__device__ __forceinline__ long cmap_off(int n, const int* e, const int64_t* s,
+                                         int x) {
+  long o = 0;
+#pragma unroll
+  for (int i = 0; i < CMAP_DIGITS; ++i) {
+    if (i >= n) break;
+    if (i == n - 1) {
+      o += (long)x * s[i];
+      break;
+    }
+    const int q = x / e[i];
+    o += (long)(x - q * e[i]) * s[i];
+    x = q;
+  }
+  return o;
+}
+__device__ __forceinline__ long cmap_row(const CMap& cm, int row, long ldc) {
+  return cm.nr == 0 ? (long)row * ldc : cmap_off(cm.nr, cm.re, cm.rs, row);
+}
+__device__ __forceinline__ long cmap_col(const CMap& cm, int col) {
+  return cm.nr == 0 ? (long)col : cmap_off(cm.nc, cm.ce, cm.cs, col);
+}
+
 // Epilogue of a tile of 16 x 16 MFMA blocks: out = alpha acc + beta out
 // (one split) or the partial sums (split K).  Register r of block (i, j)
 // holds row 4 (l / 16) + r (FP32 and BF16 layouts, L32) or l / 16 + 4 r
@@ -78,9 +102,24 @@ __device__ __forceinline__ void store_tile(const V (&acc)[TM][TN], int lane,
                                            int r0, int c0, int M, int N,
                                            double alpha, double beta,
                                            double* out, long ldc, PT* pout,
-                                           int splits) {
+                                           int splits, const CMap& cm) {
+  // offsets of this lane's TN columns in C (the layout cm describes)
+  long coff[TN];
+  if (splits == 1) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+      coff[j] = cmap_col(cm, c0 + j * 16 + (lane & 15));
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
+    long roff[4];
+    if (splits == 1) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        roff[r] = cmap_row(
+            cm, r0 + i * 16 + (L32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r),
+            ldc);
+    }
     double cv[TN][4];
     if (splits == 1 && beta != 0.0) {
 #pragma unroll
@@ -90,7 +129,7 @@ __device__ __forceinline__ void store_tile(const V (&acc)[TM][TN], int lane,
           const int row =
               r0 + i * 16 + (L32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
           const int col = c0 + j * 16 + (lane & 15);
-          cv[j][r] = row < M && col < N ? out[(long)row * ldc + col] : 0.0;
+          cv[j][r] = row < M && col < N ? out[roff[r] + coff[j]] : 0.0;
         }
     }
 #pragma unroll
@@ -104,7 +143,7 @@ __device__ __forceinline__ void store_tile(const V (&acc)[TM][TN], int lane,
           if (splits == 1) {
             double v = alpha * (double)acc[i][j][r];
             if (beta != 0.0) v += beta * cv[j][r];
-            out[(long)row * ldc + col] = v;
+            out[roff[r] + coff[j]] = v;
           } else {
             pout[(long)row * N + col] = acc[i][j][r];
           }
@@ -120,7 +159,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
     int splits, int kchunk, void* __restrict__ part, int use_ptrs,
-    PtrArgs ptrs) {
+    PtrArgs ptrs, CMap cm) {
   static_assert(WM * WN == 4, "4 waves");
   using T = typename std::conditional<F32, float, double>::type;
   using V4 = typename std::conditional<F32, f32x4, f64x4>::type;
@@ -255,7 +294,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
   double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
   T* pout = (T*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<F32>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha, beta,
-                  out, ldc, pout, splits);
+                  out, ldc, pout, splits, cm);
 }
 
 // BF16x3 arithmetic: every FP64 operand x is split into x_hi = bf16(x) and
@@ -279,7 +318,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
     long lda, long sA, const double* __restrict__ B, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
     int splits, int kchunk, void* __restrict__ part, int use_ptrs,
-    PtrArgs ptrs) {
+    PtrArgs ptrs, CMap cm) {
   static_assert(WM * WN == 4, "4 waves");
   constexpr int BK = 32, KP = BK + 8;  // 80-byte rows, 16-byte aligned reads
   constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -401,7 +440,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
   float* pout =
       (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
-                   beta, out, ldc, pout, splits);
+                   beta, out, ldc, pout, splits, cm);
 }
 
 // FP32 products with direct global-to-LDS loads (`global_load_lds_dwordx4`:
@@ -428,7 +467,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
     long lda, long sA, const double* __restrict__ B0, long ldb, long sB,
     double beta, double* __restrict__ C, long ldc, long sC, int tiles_n,
     int splits, int kchunk, void* __restrict__ part, int use_ptrs,
-    PtrArgs ptrs) {
+    PtrArgs ptrs, CMap cm) {
   static_assert(WM * WN == 4, "4 waves");
   constexpr int BM = 128, BK = 16, NS = 2;
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
@@ -598,7 +637,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
   double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
   float* pout = (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
-                   beta, out, ldc, pout, splits);
+                   beta, out, ldc, pout, splits, cm);
 }
 
 // part layout [S][batch][M][N] (FP64, or FP32 for FP32 accumulators);
@@ -608,7 +647,7 @@ __global__ void splitk_sum_kernel(const PT* __restrict__ part, int S,
                                   int batch, long M, long N, double alpha,
                                   double beta, double* __restrict__ C,
                                   long ldc, long sC, int use_ptrs,
-                                  PtrArgs ptrs) {
+                                  PtrArgs ptrs, CMap cm) {
   const long mn = M * N, tot = mn * batch;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
        e += (long)gridDim.x * blockDim.x) {
@@ -618,7 +657,8 @@ __global__ void splitk_sum_kernel(const PT* __restrict__ part, int S,
     for (int s = 0; s < S; ++s)
       v += (double)part[((long)s * batch + b) * mn + i];
     const long r = i / N, c = i % N;
-    double* cp = (use_ptrs ? ptrs.c[b] : C + b * sC) + r * ldc + c;
+    double* cp = (use_ptrs ? ptrs.c[b] : C + b * sC) +
+                 cmap_row(cm, (int)r, ldc) + cmap_col(cm, (int)c);
     double o = alpha * v;
     if (beta != 0.0) o += beta * *cp;
     *cp = o;
@@ -689,7 +729,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
     const __bf16* __restrict__ Al, long sA, const __bf16* __restrict__ Bh,
     const __bf16* __restrict__ Bl, long sB, double beta,
     double* __restrict__ C, long ldc, long sC, int tiles_n, int splits,
-    int kchunk, void* __restrict__ part, int use_ptrs, PtrArgs ptrs) {
+    int kchunk, void* __restrict__ part, int use_ptrs, PtrArgs ptrs, CMap cm) {
   static_assert(WM * WN == 4, "4 waves");
   constexpr int BK = 32, KP = BK + 8;
   constexpr int WTM = BM / WM, WTN = BN / WN;
@@ -826,7 +866,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
   float* pout =
       (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
-                   beta, out, ldc, pout, splits);
+                   beta, out, ldc, pout, splits, cm);
 }
 
 struct Call {
@@ -841,6 +881,7 @@ struct Call {
   long ldc, sC;
   const PtrArgs* ptrs;  // null: strided batch
   bool a32 = false;     // A stored in FP32
+  CMap cm{};            // layout of C (nr == 0: row major, ldc)
 };
 
 // BF16x3 product through split planes (see split_bf16_kernel): chosen when
@@ -938,7 +979,7 @@ void launch_presplit(Device& dev, const Call& c) {
                      dim3((unsigned)tiles, (unsigned)(c.batch * S)),
                      dim3(256), 0, dev.stream, c.M, c.N, Kp, c.alpha, Ah, Al,
                      sA, Bh, Bl, sB, c.beta, c.C, c.ldc, c.sC, (int)tn, S,
-                     kchunk, part.ptr, c.ptrs ? 1 : 0, pa);
+                     kchunk, part.ptr, c.ptrs ? 1 : 0, pa, c.cm);
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
   if (S > 1) {
@@ -948,7 +989,7 @@ void launch_presplit(Device& dev, const Call& c) {
     hipLaunchKernelGGL(splitk_sum_kernel<float>, dim3(g), dim3(256), 0,
                        dev.stream, (const float*)part.ptr, S, c.batch,
                        (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
-                       c.sC, c.ptrs ? 1 : 0, pa);
+                       c.sC, c.ptrs ? 1 : 0, pa, c.cm);
     IPEPS_HIP(hipGetLastError());
   }
 }
@@ -1065,7 +1106,7 @@ __global__ __launch_bounds__(SMALL_T) void gemm_small_kernel(
 __global__ __launch_bounds__(SMALL_T) void small_sum_kernel(
     const double* __restrict__ part, int S, int M, int N, double alpha,
     double beta, double* __restrict__ C, long ldc, long sC, int use_ptrs,
-    PtrArgs ptrs) {
+    PtrArgs ptrs, CMap cm) {
   const int bz = blockIdx.x, batch = gridDim.x, mn = M * N;
   __shared__ double red[SMALL_T];
   double* Cb = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
@@ -1080,7 +1121,7 @@ __global__ __launch_bounds__(SMALL_T) void small_sum_kernel(
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      double* cp = Cb + (long)(o / N) * ldc + o % N;
+      double* cp = Cb + cmap_row(cm, o / N, ldc) + cmap_col(cm, o % N);
       double r = alpha * red[0];
       if (beta != 0.0) r += beta * *cp;
       *cp = r;
@@ -1133,7 +1174,7 @@ void launch_small(Device& dev, const Call& c) {
   IPEPS_HIP(hipGetLastError());
   hipLaunchKernelGGL(small_sum_kernel, dim3(c.batch), dim3(SMALL_T), 0,
                      dev.stream, part.ptr, S, c.M, c.N, c.alpha, c.beta, c.C,
-                     c.ldc, c.sC, up, pa);
+                     c.ldc, c.sC, up, pa, c.cm);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -1206,7 +1247,8 @@ void launch_cfg(Device& dev, const Call& c) {
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), 0, dev.stream, c.M, c.N, c.K,
                        c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.beta,
-                       c.C, c.ldc, c.sC, (int)tn, S, kchunk, part.ptr, up, pa);
+                       c.C, c.ldc, c.sC, (int)tn, S, kchunk, part.ptr, up, pa,
+                       c.cm);
   };
   if constexpr (LDSK) {
     static_assert(P == 1 && BM == 128, "LDS kernel: FP32, 128 rows");
@@ -1215,7 +1257,7 @@ void launch_cfg(Device& dev, const Call& c) {
       hipLaunchKernelGGL(kern, grid, dim3(256), lb, dev.stream, c.M, c.N,
                          c.K, c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB,
                          c.beta, c.C, c.ldc, c.sC, (int)tn, S, kchunk,
-                         part.ptr, up, pa);
+                         part.ptr, up, pa, c.cm);
     };
     auto pickl = [&](auto ti) {
       using TI = decltype(ti);
@@ -1275,12 +1317,12 @@ void launch_cfg(Device& dev, const Call& c) {
       hipLaunchKernelGGL(splitk_sum_kernel<double>, dim3(g), dim3(256), 0,
                          dev.stream, (const double*)part.ptr, S, c.batch,
                          (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
-                         c.sC, up, pa);
+                         c.sC, up, pa, c.cm);
     else
       hipLaunchKernelGGL(splitk_sum_kernel<float>, dim3(g), dim3(256), 0,
                          dev.stream, (const float*)part.ptr, S, c.batch,
                          (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
-                         c.sC, up, pa);
+                         c.sC, up, pa, c.cm);
     IPEPS_HIP(hipGetLastError());
   }
 }
@@ -1381,9 +1423,10 @@ void check_sizes(int64_t M, int64_t N, int64_t K, int64_t batch) {
 void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
           double alpha, const double* A, int64_t lda, int64_t sA,
           const double* B, int64_t ldb, int64_t sB, double beta, double* C,
-          int64_t ldc, int64_t sC, int64_t batch) {
+          int64_t ldc, int64_t sC, int64_t batch, const CMap* cm) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K == 0) {
+    if (cm && cm->nr) throw ArgError("gemm: scattered C with K = 0");
     for (int64_t b = 0; b < batch; ++b)
       for (int64_t m = 0; m < M; ++m)
         axpby(dev, N, 0.0, C + b * sC + m * ldc, beta, C + b * sC + m * ldc);
@@ -1392,6 +1435,7 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
   check_sizes(M, N, K, batch);
   Call c{tA, tB, (int)M, (int)N, (int)K, (int)batch, alpha, beta, A, lda, sA,
          B, ldb, sB, C, ldc, sC, nullptr};
+  if (cm) c.cm = *cm;
   dispatch(dev, c);
 }
 
@@ -1401,7 +1445,7 @@ void gemm_ptrs_impl(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                     int64_t K, double alpha, const std::vector<const TA*>& A,
                     int64_t lda, const std::vector<const double*>& B,
                     int64_t ldb, double beta, const std::vector<double*>& C,
-                    int64_t ldc) {
+                    int64_t ldc, const CMap* cm = nullptr) {
   const int64_t batch = (int64_t)A.size();
   if (M <= 0 || N <= 0 || batch <= 0 || K <= 0) return;
   if ((int64_t)B.size() != batch || (int64_t)C.size() != batch)
@@ -1418,6 +1462,7 @@ void gemm_ptrs_impl(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
     }
     Call c{tA, tB, (int)M, (int)N, (int)K, nb, alpha, beta, pa.a[0], lda, 0,
            pa.b[0], ldb, 0, pa.c[0], ldc, 0, &pa, sizeof(TA) == 4};
+    if (cm) c.cm = *cm;
     dispatch(dev, c);
   }
 }
@@ -1426,8 +1471,10 @@ void gemm_ptrs_impl(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
 void gemm_ptrs(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                int64_t K, double alpha, const std::vector<const double*>& A,
                int64_t lda, const std::vector<const double*>& B, int64_t ldb,
-               double beta, const std::vector<double*>& C, int64_t ldc) {
-  gemm_ptrs_impl(dev, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+               double beta, const std::vector<double*>& C, int64_t ldc,
+               const CMap* cm) {
+  gemm_ptrs_impl(dev, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                 cm);
 }
 
 void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,

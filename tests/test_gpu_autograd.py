@@ -33,7 +33,13 @@ def test_energy_backward_is_library_gradient():
         g = A.grad.detach()
         x = autograd.precondition(ctx, g, w["delta"], w["cg_tol"],
                                   w["cg_maxiter"])
-    _say(f"  e {e.item()!r} vs {e_ref!r}")
+    with binding.Context(A0, w["chi"]) as ctx:
+        # no gradient asked for: the energy alone, from the same network
+        with torch.no_grad():
+            e_only = autograd.energy(A.detach(), ctx, terms, w["tol"],
+                                     w["n_iter"])
+    _say(f"  e {e.item()!r} vs {e_ref!r}, energy only {e_only.item()!r}")
+    assert e_only.item() == e_ref
     assert e.item() == e_ref
     assert np.array_equal(g.cpu().numpy(), g_ref)
     assert np.array_equal(x.cpu().numpy(), x_ref)
