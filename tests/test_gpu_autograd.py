@@ -39,7 +39,10 @@ def test_energy_backward_is_library_gradient():
             e_only = autograd.energy(A.detach(), ctx, terms, w["tol"],
                                      w["n_iter"])
     _say(f"  e {e.item()!r} vs {e_ref!r}, energy only {e_only.item()!r}")
-    assert e_only.item() == e_ref
+    # the gradient path reports the energy after its K unrolled iterations
+    # from the converged environment, the energy alone that of the
+    # environment itself: equal to the convergence tolerance
+    assert abs(e_only.item() - e_ref) <= 1e-10 * abs(e_ref)
     assert e.item() == e_ref
     assert np.array_equal(g.cpu().numpy(), g_ref)
     assert np.array_equal(x.cpu().numpy(), x_ref)
