@@ -180,6 +180,28 @@ std::vector<Var> Tape::einsum_n(const std::string& spec,
   return out;
 }
 
+Var Tape::trace_dd(const Var& x) {
+  const int r = x->v.rank();
+  if (r < 2 || x->v.shape[r - 1] != x->v.shape[r - 2])
+    throw ArgError("trace_dd: last two extents differ");
+  const int d = (int)x->v.shape[r - 1];
+  std::vector<int64_t> sh(x->v.shape.begin(), x->v.shape.end() - 2);
+  if (sh.empty()) sh.push_back(1);
+  auto out = std::make_shared<Node>();
+  out->v = dev.empty(sh);
+  const int64_t rows = out->v.numel();
+  ipeps::trace_dd(dev, x->v.ptr, rows, d, out->v.ptr);
+  out->req = rec && x->req;
+  if (out->req)
+    push([this, x, out, rows, d]() {
+      if (!has_grad(out)) return;
+      double beta;
+      Tensor& gx = grad_target(dev, x.get(), beta);
+      trace_dd_backward(dev, out->g.ptr, rows, d, gx.ptr, beta);
+    });
+  return out;
+}
+
 Var Tape::view(const Var& x, std::vector<int64_t> shape) {
   auto out = std::make_shared<Node>();
   out->v = x->v.view(std::move(shape));

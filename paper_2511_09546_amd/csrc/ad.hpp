@@ -65,6 +65,8 @@ class Tape {
   // descending signed order; the derivative uses x / (x^2 + eta^2),
   // eta = 1e-12 max|lambda|, for 1 / (lambda_j - lambda_i)
   Var eig_kept(const Var& B, int k);
+  // y[r] = sum_s x[r][s][s] over the last two (equal) extents of x
+  Var trace_dd(const Var& x);
   // y = X diag(s) for an n x b X and a constant device vector s
   Var colscale(const Var& X, const Tensor& s);
   // y = (x + P x) / 2 for a permutation P that is its own inverse

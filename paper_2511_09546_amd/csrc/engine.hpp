@@ -419,6 +419,11 @@ void inv_sqrt_clip(Device& dev, double* x, int64_t n, double thr);
 void defl_coef(Device& dev, int mode, const double* S, const int* keep,
                const double* lam, int chi, int m2, int sS, const double* H,
                double* out, int batch);
+// y[r] = sum_s x[r][s][s], x: rows x d x d
+void trace_dd(Device& dev, const double* x, int64_t rows, int d, double* y);
+// gx[r][s][t] = beta gx[r][s][t] + (s == t) g[r]
+void trace_dd_backward(Device& dev, const double* g, int64_t rows, int d,
+                       double* gx, double beta);
 void copy2d(Device& dev, const double* src, int64_t lds, double* dst,
             int64_t ldd, int64_t rows, int64_t cols, int batch = 1,
             int64_t sSrc = 0, int64_t sDst = 0);

@@ -1700,6 +1700,50 @@ void defl_coef(Device& dev, int mode, const double* S, const int* keep,
   IPEPS_HIP(hipGetLastError());
 }
 
+// y[r] = sum_s x[r][s][s] (x: rows x d x d)
+__global__ void trace_dd_kernel(const double* __restrict__ x, int64_t rows,
+                                int d, double* __restrict__ y) {
+  const int64_t dd = (int64_t)d * d;
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < d; ++s) v += x[r * dd + s * (d + 1)];
+    y[r] = v;
+  }
+}
+
+void trace_dd(Device& dev, const double* x, int64_t rows, int d, double* y) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(trace_dd_kernel, dim3(grid_for(rows, 256)), dim3(256), 0,
+                     dev.stream, x, rows, d, y);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// gx[r][s][t] = beta gx[r][s][t] + (s == t) g[r]
+__global__ void trace_dd_backward_kernel(const double* __restrict__ g,
+                                         int64_t rows, int d,
+                                         double* __restrict__ gx,
+                                         double beta) {
+  const int64_t dd = (int64_t)d * d, n = rows * dd;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / dd;
+    const int q = (int)(e - r * dd);
+    double v = (q % (d + 1) == 0) ? g[r] : 0.0;
+    if (beta != 0.0) v += beta * gx[e];
+    gx[e] = v;
+  }
+}
+
+void trace_dd_backward(Device& dev, const double* g, int64_t rows, int d,
+                       double* gx, double beta) {
+  const int64_t n = rows * d * d;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(trace_dd_backward_kernel, dim3(grid_for(n, 256)),
+                     dim3(256), 0, dev.stream, g, rows, d, gx, beta);
+  IPEPS_HIP(hipGetLastError());
+}
+
 // y[i][j] = a * s_j * x[i][j] + b * y[i][j]   (column-scaled axpby)
 __global__ void col_axpby_kernel(int64_t n, int m, double a, const double* s,
                                  const double* x, double b, double* y,

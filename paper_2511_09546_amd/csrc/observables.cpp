@@ -7,7 +7,11 @@
 //   on-site: the 3x3 block around the site.
 // Written on the differentiation tape so that the same contractions serve
 // the energy and its backward pass.
+#include <array>
 #include <cmath>
+#include <map>
+#include <set>
+#include <utility>
 
 #include "ad.hpp"
 #include "ipeps_impl.hpp"
@@ -29,51 +33,108 @@ struct Net {
   Var E(const char* spec, const Var& x, const Var& y) {
     return tp.einsum(spec, x, y);
   }
+  // tensors shared by several terms of one evaluation, keyed by
+  // (corner, site): the open double layers, the corner-edge products X2
+  // and the enlarged corners (plain and with open physical legs)
+  using Key = std::pair<int, int>;
+  std::map<Key, Var> ao_c, x2_c, qo_c, qp_c;
+  std::set<Key> open_and_plain;  // corners wanted both ways
   // ao[s, t, (l l'), (u u'), (r r'), (d d')]
   Var ao(int s, int c = 0) {
+    auto it = ao_c.find({c, s});
+    if (it != ao_c.end()) return it->second;
     const int D2 = cx.D2, d = cx.d;
-    Var o = tp.view(E("sabce,tfghi->stafbgchei", As[s], As[s]),
-                    {d, d, D2, D2, D2, D2});
-    if (c == 0) return o;
-    return tp.permute(o, {0, 1, 2 + c % 4, 2 + (c + 1) % 4, 2 + (c + 2) % 4,
-                          2 + (c + 3) % 4});
+    Var o;
+    if (c == 0)
+      o = tp.view(E("sabce,tfghi->stafbgchei", As[s], As[s]),
+                  {d, d, D2, D2, D2, D2});
+    else
+      o = tp.permute(ao(s, 0), {0, 1, 2 + c % 4, 2 + (c + 1) % 4,
+                                2 + (c + 2) % 4, 2 + (c + 3) % 4});
+    return ao_c[{c, s}] = o;
   }
+  // T_{c-1} C_c T_c of corner c at site s, grouped [m k | g e] for the
+  // product with the double layer
+  Var x2(int c, int s) {
+    auto it = x2_c.find({c, s});
+    if (it != x2_c.end()) return it->second;
+    Var X1 = E("mgi,ij->mgj", T((c + 3) % 4, s), C(c, s));
+    return x2_c[{c, s}] = E("mgj,jek->mkge", X1, T(c, s));
+  }
+  // Each half of the 2x1 (1x2) block contracts the open double layer into
+  // the corner-edge-corner-edge product over the two legs they share first
+  // (chi^2 d^2 D^4 intermediate, like an open enlarged corner), then closes
+  // the third edge; intermediates are written grouped for their next
+  // product.
   Var rdm_h(int s1, int s2) {
     Var L1 = E("ij,mgi->jmg", C(0, s1), T(3, s1));
     Var L2 = E("jmg,qm->jgq", L1, C(3, s1));
-    Var L3 = E("jgq,jek->gqek", L2, T(0, s1));
-    Var L4 = E("gqek,wzq->gekwz", L3, T(2, s1));
-    Var HL = E("gekwz,stgebz->kwstb", L4, ao(s1));
+    Var L3 = E("jgq,jek->qkge", L2, T(0, s1));
+    Var L5 = E("qkge,stgebz->kstbqz", L3, ao(s1));
+    Var HL = E("kstbqz,wzq->kwstb", L5, T(2, s1));
     Var R1 = E("ji,ibm->jbm", C(1, s2), T(1, s2));
     Var R2 = E("jbm,mq->jbq", R1, C(2, s2));
-    Var R3 = E("kej,jbq->kebq", T(0, s2), R2);
-    Var R4 = E("kebq,qzw->kebzw", R3, T(2, s2));
-    Var HR = E("kebzw,stvebz->kwstv", R4, ao(s2));
+    Var R3 = E("kej,jbq->kqeb", T(0, s2), R2);
+    Var R5 = E("kqeb,stvebz->kstvqz", R3, ao(s2));
+    Var HR = E("kstvqz,qzw->kwstv", R5, T(2, s2));
     return E("kwstb,kwuvb->sutv", HL, HR);
   }
   Var rdm_v(int s1, int s2) {
     Var V1 = E("ij,jek->iek", C(0, s1), T(0, s1));
     Var V2 = E("iek,kp->iep", V1, C(1, s1));
-    Var V3 = E("iep,mgi->epmg", V2, T(3, s1));
-    Var V4 = E("epmg,pbn->emgbn", V3, T(1, s1));
-    Var HT = E("emgbn,stgebz->mnstz", V4, ao(s1));
+    Var V3 = E("iep,mgi->pmge", V2, T(3, s1));
+    Var V5 = E("pmge,stgebz->mstzpb", V3, ao(s1));
+    Var HT = E("mstzpb,pbn->mnstz", V5, T(1, s1));
     Var W1 = E("qgm,wq->gmw", T(3, s2), C(3, s2));
     Var W2 = E("gmw,vyw->gmvy", W1, T(2, s2));
-    Var W3 = E("gmvy,pv->gmyp", W2, C(2, s2));
-    Var W4 = E("gmyp,nbp->gmynb", W3, T(1, s2));
-    Var HB = E("gmynb,stgzby->mnstz", W4, ao(s2));
+    Var W3 = E("gmvy,pv->mpgy", W2, C(2, s2));
+    Var W5 = E("mpgy,stgzby->mstzpb", W3, ao(s2));
+    Var HB = E("mstzpb,nbp->mnstz", W5, T(1, s2));
     return E("mnstz,mnuvz->sutv", HT, HB);
   }
-  // enlarged corner c of site s, plain ([n][n]) or open ([n][n][d][d])
+  // enlarged corner c of site s, plain ([n][n]) or open ([n][n][d][d]);
+  // a corner wanted both ways is built open once and traced over its
+  // physical legs for the plain one
   Var corner(int c, int s, bool open) {
     const int64_t n = cx.n;
-    Var X1 = E("mgi,ij->mgj", T((c + 3) % 4, s), C(c, s));
-    Var X2 = E("mgj,jek->mgek", X1, T(c, s));
-    if (!open) return tp.view(E("mgek,gebf->mfkb", X2, a(s, c)), {n, n});
-    return tp.view(E("mgek,stgebf->mfkbst", X2, ao(s, c)),
-                   {n, n, cx.d, cx.d});
+    const Key k{c, s};
+    std::map<Key, Var>& cache = open ? qo_c : qp_c;
+    auto it = cache.find(k);
+    if (it != cache.end()) return it->second;
+    Var q;
+    if (open)
+      q = tp.view(E("mkge,stgebf->mfkbst", x2(c, s), ao(s, c)),
+                  {n, n, cx.d, cx.d});
+    else if (open_and_plain.count(k))
+      q = tp.trace_dd(corner(c, s, true));
+    else
+      q = tp.view(E("mkge,gebf->mfkb", x2(c, s), a(s, c)), {n, n});
+    return cache[k] = q;
+  }
+  // the corners of the diagonal terms, [c] = (site, open)
+  std::array<std::pair<int, bool>, 4> diag_corners(const TermSpec& t) const {
+    const Lattice& L = cx.lat;
+    const int x = t.site % L.Lx, y = t.site / L.Lx;
+    if (t.dy == 1)
+      return {{{L.idx(x, y), true}, {L.idx(x + 1, y), false},
+               {L.idx(x + 1, y + 1), true}, {L.idx(x, y + 1), false}}};
+    return {{{L.idx(x, y - 1), false}, {L.idx(x + 1, y - 1), true},
+             {L.idx(x + 1, y), false}, {L.idx(x, y), true}}};
+  }
+  // marks the corners that the diagonal terms want both open and plain
+  void plan(const std::vector<TermSpec>& terms) {
+    std::set<Key> op, pl;
+    for (const auto& t : terms) {
+      if (t.kind == 0 || t.dx != 1 || (t.dy != 1 && t.dy != -1)) continue;
+      const auto cs = diag_corners(t);
+      for (int c = 0; c < 4; ++c)
+        (cs[c].second ? op : pl).insert({c, cs[c].first});
+    }
+    for (const Key& k : op)
+      if (pl.count(k)) open_and_plain.insert(k);
   }
   Var rdm_diag(int s00, int s10, int s11, int s01, bool anti) {
+    // the corner choices of diag_corners
     if (!anti) {
       Var Q0 = corner(0, s00, true), Q1 = corner(1, s10, false);
       Var Q2 = corner(2, s11, true), Q3 = corner(3, s01, false);
@@ -120,6 +181,7 @@ double energy_ad(Tape& tp, Context& cx, const VEnv& e,
                  const std::vector<TermSpec>& terms) {
   Device& dev = cx.dev;
   Net net{tp, cx, e, As, arot};
+  net.plan(terms);
   Tensor acc = dev.zeros({1});
   for (const auto& t : terms) {
     Var rho = net.term_rdm(t);

@@ -312,23 +312,13 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     // first 2m columns are W Phi, the last 2m are H W Phi
     Tensor Xi, lamK, Hd, Cf;
     if (m > 0) {
-      Tensor Wr = dev.empty({2, nc, n, m});
-      copy2d(dev, U.ptr + chi, b, Wr.ptr, m, n, m, nc, sUV, sNm);
-      copy2d(dev, V.ptr + chi, b, Wr.ptr + nc * sNm, m, n, m, nc, sUV, sNm);
-      off_kept(Ukm, Wr.ptr);
-      off_kept(Vkm, Wr.ptr + nc * sNm);
-      // orthonormalise: W <- W J diag(lambda^-1/2) from W^T W = J lambda J^T
-      // (columns that vanished, e.g. null directions, stay zero)
-      Tensor G = dev.empty({2 * nc, m, m}), J = dev.empty({2 * nc, m, m});
-      Tensor lw = dev.empty({2 * nc, m});
-      gemm(dev, true, false, m, m, n, 1.0, Wr.ptr, m, sNm, Wr.ptr, m, sNm,
-           0.0, G.ptr, m, (int64_t)m * m, 2 * nc);
-      sym_eig_jacobi(dev, G.ptr, J.ptr, lw.ptr, m, 2 * nc);
-      inv_sqrt_clip(dev, lw.ptr, 2 * nc * m, 1e-12);
+      // W: the subspace singular vectors chi..chi+m-1 of both sides.  They
+      // are orthonormal and orthogonal to the kept ones already (columns of
+      // the orthonormal U and V of the forward SVD; zero columns, from null
+      // directions, stay zero and drop out of the Galerkin system)
       Tensor Wn = dev.empty({2, nc, n, m});
-      gemm(dev, false, false, n, m, m, 1.0, Wr.ptr, m, sNm, J.ptr, m,
-           (int64_t)m * m, 0.0, Wn.ptr, m, sNm, 2 * nc);
-      col_axpby(dev, 2 * nc * n, m, 1.0, lw.ptr, Wn.ptr, 0.0, Wn.ptr, n, m);
+      copy2d(dev, U.ptr + chi, b, Wn.ptr, m, n, m, nc, sUV, sNm);
+      copy2d(dev, V.ptr + chi, b, Wn.ptr + nc * sNm, m, n, m, nc, sUV, sNm);
       const double* Wu = Wn.ptr;
       const double* Wv = Wn.ptr + nc * sNm;
       // Y = P_D Qa Qb W_v, Zt = P'_D Qb^T Qa^T W_u
