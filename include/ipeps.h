@@ -238,7 +238,7 @@ size_t precond_noalloc_bytes(int Lx, int Ly, int d, int D, int chi);
  * C4v-symmetric real ansatz with a QR-based CTMRG (Sec. IV A: a one-site
  * C4v-symmetric real iPEPS, the symmetry fixing the gauge, its environment
  * from a QR-CTMRG, the gradient by reverse mode through the last K
- * iterations).  1x1 unit cells, D >= 2, chi <= 128.
+ * iterations).  1x1 unit cells, D >= 2, chi <= 408 (block <= 512).
  *
  * The state is used through its projection A_s, the average of A over the
  * eight elements of the square's symmetry group acting on the virtual legs
@@ -247,7 +247,7 @@ size_t precond_noalloc_bytes(int Lx, int Ly, int d, int D, int chi);
  * [chi][D^2][chi] (both symmetric in their chi legs) standing for all four
  * corners and edges, plus the warm-start block V [chi D^2][b] of the
  * subspace iteration, b = c4v_block_size(chi) = chi + max(8, ceil(chi/4))
- * made even, at most 128.  One iteration: enlarged corner M = T C T a;
+ * made even (-1 when above 512).  One iteration: enlarged corner M = T C T a;
  * while the bond c has c D^2 <= chi it grows untruncated; otherwise one
  * step of block subspace iteration, Q0 = qr(M V) (Cholesky QR in two
  * passes, diag R > 0), Rayleigh-Ritz W of Q0^T M Q0 (the chi eigenvalues of
@@ -270,7 +270,7 @@ size_t precond_noalloc_bytes(int Lx, int Ly, int d, int D, int chi);
  * may be NULL; on set, NULL means no warm-start block); *bond receives the
  * bond dimension reached (0: none yet).  Setting takes the bond as chi.
  * Errors: EINVAL, ESTATE (no C4v environment), ENOTIMPL (cell larger than
- * 1x1, D < 2 or chi > 128), ENOMEM, EHIP. */
+ * 1x1, D < 2 or chi > 408), ENOMEM, EHIP. */
 int c4v_block_size(int chi);
 int c4v_converge(ipeps_ctx* ctx, double tol, int max_iter, int* n_iter,
                  double* delta);

@@ -32,13 +32,13 @@ int ipeps_debug_gemm_time(int prec, int tA, int tB, int M, int N, int K,
                           int batch, int reps, double* us_per_call);
 
 /* Symmetric eigendecomposition of `batch` b x b row-major matrices G (b even,
- * b <= 128) by the library's Jacobi kernel: V (columns = eigenvectors) and
+ * b <= 512) by the library's Jacobi kernel: V (columns = eigenvectors) and
  * lam, sorted by descending eigenvalue. */
 int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
                         double* lam);
 
 /* Tall-skinny SVD W J = U diag(s) of `batch` n x b row-major matrices by
- * the library's two-pass Gram/Jacobi routine (b even, b <= 128). */
+ * the library's two-pass Gram/Jacobi routine (b even, b <= 512). */
 int ipeps_debug_svd_ts(int n, int b, int batch, const double* W, double* U,
                        double* s, double* J);
 

@@ -22,8 +22,8 @@ reading, written out step by step:
   matrix (c the current bond dimension; M is symmetric); while c D^2 <=
   chi the bond grows without truncation (Q = identity); otherwise the kept
   space comes from one step of block subspace iteration with QR on b =
-  chi + p columns (oversampling p = max(8, ceil(chi / 4)), b made even and
-  at most 128): Y = M V with V the previous iteration's b-column block
+  chi + p columns (oversampling p = max(8, ceil(chi / 4)), b made
+  even): Y = M V with V the previous iteration's b-column block
   (the first b unit vectors when there is none of that shape), the thin QR
   Y = Q0 R with diag R > 0 (a column whose R diagonal is below 1e-6 of the
   column scale |Y|_F / sqrt(b) is dropped: set to zero), then the
@@ -87,10 +87,10 @@ def init_env(a: torch.Tensor):
 
 
 def block_size(chi: int) -> int:
-    """b = chi + p, p = max(8, ceil(chi / 4)), even, at most 128."""
+    """b = chi + p, p = max(8, ceil(chi / 4)), even."""
     b = chi + max(8, -(-chi // 4))
     b += b % 2
-    return min(b, 128)
+    return b
 
 
 def _qr_positive(Y):

@@ -333,11 +333,12 @@ int precond_apply_dev(ipeps_ctx* c, const double* d_g, double delta,
 }
 
 int c4v_block_size(int chi) {
-  return chi >= 1 && chi <= 128 ? c4v_block(chi) : -1;
+  return chi >= 1 && c4v_block(chi) <= MAX_BLOCK ? c4v_block(chi) : -1;
 }
 
 static int c4v_ok(const Context& cx) {
-  if (cx.nsite() != 1 || cx.D < 2 || cx.chi > 128) return IPEPS_ENOTIMPL;
+  if (cx.nsite() != 1 || cx.D < 2 || c4v_block(cx.chi) > MAX_BLOCK)
+    return IPEPS_ENOTIMPL;
   return IPEPS_OK;
 }
 

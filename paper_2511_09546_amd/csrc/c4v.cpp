@@ -15,7 +15,7 @@
 //              first chi unit vectors as Q (the zero padding beyond c D^2
 //              carries zeros);
 //   truncation one step of block subspace iteration on b = chi + p columns
-//              (p = max(8, ceil(chi/4)), b even, <= 128): Y = M V with the
+//              (p = max(8, ceil(chi/4)), b even, <= 512): Y = M V with the
 //              previous block V (the first b unit vectors at the first
 //              truncation), Q0 = qr(Y) (Cholesky QR, two passes), the
 //              Rayleigh-Ritz eigenvectors W of B = Q0^T M Q0 (Jacobi; the
@@ -42,8 +42,8 @@ Var Tape::qr_q(const Var& Y) {
   PrecScope ps(dev, PREC_FP64);
   const int64_t n = Y->v.shape[0];
   const int b = (int)Y->v.shape[1];
-  if (Y->v.rank() != 2 || b < 1 || b > 128 || n < b)
-    throw ArgError("qr_q: needs an n x b matrix, b <= 128, n >= b");
+  if (Y->v.rank() != 2 || b < 1 || b > MAX_BLOCK || n < b)
+    throw ArgError("qr_q: needs an n x b matrix, b <= 512, n >= b");
   auto out = std::make_shared<Node>();
   Tensor nr = dev.empty({1});
   nrm2(dev, Y->v.ptr, n * b, nr.ptr);
@@ -99,8 +99,8 @@ Var Tape::qr_q(const Var& Y) {
 Var Tape::eig_kept(const Var& B, int k) {
   PrecScope ps(dev, PREC_FP64);
   const int b = (int)B->v.shape[0];
-  if (B->v.rank() != 2 || B->v.shape[1] != b || b % 2 || b > 128)
-    throw ArgError("eig_kept: needs a b x b matrix, b even, b <= 128");
+  if (B->v.rank() != 2 || B->v.shape[1] != b || b % 2 || b > MAX_BLOCK)
+    throw ArgError("eig_kept: needs a b x b matrix, b even, b <= 512");
   Tensor G = dev.empty({b, b}), V = dev.empty({b, b}), lam = dev.empty({b});
   axpby(dev, (int64_t)b * b, 1.0, B->v.ptr, 0.0, G.ptr);
   sym_eig_jacobi(dev, G.ptr, V.ptr, lam.ptr, b, 1);
@@ -177,7 +177,7 @@ void replicate_env(Context& cx);
 int c4v_block(int chi) {
   int b = chi + std::max(8, (chi + 3) / 4);
   b += b % 2;
-  return std::min(b, 128);
+  return b;
 }
 
 void c4v_set_env(Context& cx, const double* C, const double* T,

@@ -174,7 +174,7 @@ int ipeps_debug_einsum(const char* spec, int prec, int mode, int count,
 
 int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
                         double* lam) {
-  if (!G || !V || !lam || b < 2 || b > 128 || b % 2 || batch < 1)
+  if (!G || !V || !lam || b < 2 || b > 512 || b % 2 || batch < 1)
     return IPEPS_EINVAL;
   return run([&](Device& dev) {
     Tensor g = dev.empty({batch, b, b}), v = dev.empty({batch, b, b}),
@@ -188,7 +188,7 @@ int ipeps_debug_sym_eig(int b, int batch, const double* G, double* V,
 
 int ipeps_debug_svd_ts(int n, int b, int batch, const double* W, double* U,
                        double* s, double* J) {
-  if (!W || !U || !s || !J || n < 1 || b < 2 || b > 128 || b % 2 ||
+  if (!W || !U || !s || !J || n < 1 || b < 2 || b > 512 || b % 2 ||
       batch < 1)
     return IPEPS_EINVAL;
   return run([&](Device& dev) {

@@ -357,6 +357,9 @@ void splitk_reduce(Device& dev, const double* part, int S, int64_t M,
 }  // namespace ipeps
 
 namespace ipeps {
+// columns with a zero entry in cn replaced by pseudo-random ones
+void fill_null_cols(Device& dev, double* X, int64_t n, int b,
+                    const double* cn, int batch, uint64_t seed);
 void null_threshold(Device& dev, double* S, int b, double rel, int batch,
                     int64_t sS);
 // R = L^-T from the Cholesky factor of G = L L^T (b x b, batched); dropped

@@ -104,6 +104,9 @@ struct Lattice {
   }
 };
 
+// largest subspace block (b x b Gram, eigen and Cholesky problems of the
+// projector SVD and the C4v QR-CTMRG)
+constexpr int MAX_BLOCK = 512;
 constexpr int PLAQ_OFFSET[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
 constexpr int CORNER_MOVE[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
 constexpr int EDGE_MOVE[4][2] = {{0, 1}, {-1, 0}, {0, -1}, {1, 0}};

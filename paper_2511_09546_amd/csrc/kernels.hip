@@ -690,10 +690,180 @@ __global__ __launch_bounds__(JAC_THREADS) void sym_eig_jacobi_kernel(
   for (int i = tid; i < b; i += JAC_THREADS) lam[i] = ev[i];
 }
 
+// The same parallel cyclic Jacobi for larger matrices (JAC_MAXB < b <=
+// JAC_BIGB): G (upper triangle, row stride b + 1) and the transposed
+// eigenvector matrix live in global memory (one workgroup per matrix, so
+// both stay in its compute unit's cache and the barriers order every
+// access); only the rotations of a round and the (a, c) block list are in
+// LDS.  Same rotations, criterion, stopping rule and sort as
+// sym_eig_jacobi_kernel.
+constexpr int JACB_THREADS = 1024;
+constexpr int JAC_BIGB = 512;
+
+__global__ __launch_bounds__(JACB_THREADS) void sym_eig_jacobi_big_kernel(
+    double* __restrict__ Gall, double* __restrict__ Vall,
+    double* __restrict__ lamall, double* __restrict__ Wall, int b,
+    double tol) {
+  extern __shared__ double lds[];
+  const int S = b + 1, h = b / 2;
+  double* cs = lds;
+  double* sn = cs + h;
+  double* dp = sn + h;
+  double* dq = dp + h;
+  double* tq = dq + h;
+  int* pp = (int*)(tq + h);
+  int* qq = pp + h;
+  int* blk = qq + h;  // h (h + 1) / 2 packed blocks a | c << 16
+  __shared__ int rotated;
+  const int bt = blockIdx.x;
+  double* Gg = Gall + (long)bt * b * b;
+  double* Vt = Vall + (long)bt * b * b;
+  double* G = Wall + (long)bt * b * S;
+  double* lam = lamall + (long)bt * b;
+  const int tid = threadIdx.x;
+  const int nblk = h * (h + 1) / 2, nitem = h * b;
+  for (int e = tid; e < b * b; e += JACB_THREADS) {
+    const int p = e / b, q = e - p * b;
+    if (p <= q) G[p * S + q] = Gg[e];
+    Vt[e] = p == q ? 1.0 : 0.0;
+  }
+  for (int a = tid; a < h; a += JACB_THREADS) {
+    const int base = a * h - a * (a - 1) / 2;  // blocks of rows < a
+    for (int c = a; c < h; ++c) blk[base + c - a] = a | c << 16;
+  }
+  auto gi = [S](int x, int y) { return x < y ? x * S + y : y * S + x; };
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    bool any = false;
+    for (int e = tid; e < b * b; e += JACB_THREADS) {
+      const int p = e / b, q = e - p * b;
+      if (p < q) {
+        const double apq = G[p * S + q];
+        any |= apq != 0.0 &&
+               fabs(apq) > tol * sqrt(fabs(G[p * S + p] * G[q * S + q]));
+      }
+    }
+    if (any) rotated = 1;
+    __syncthreads();
+    if (!rotated) break;
+    for (int r = 0; r < b - 1; ++r) {
+      for (int i = tid; i < h; i += JACB_THREADS) {
+        const int j = b - 1 - i;
+        int p = i == 0 ? 0 : 1 + (i - 1 + r) % (b - 1);
+        int q = 1 + (j - 1 + r) % (b - 1);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        const double apq = G[p * S + q];
+        const double app = G[p * S + p], aqq = G[q * S + q];
+        double c = 1.0, s = 0.0, tg = 0.0;
+        if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) /
+                           (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          tg = t * apq;
+        }
+        cs[i] = c;
+        sn[i] = s;
+        dp[i] = app;
+        dq[i] = aqq;
+        tq[i] = tg;
+        pp[i] = p;
+        qq[i] = q;
+      }
+      __syncthreads();
+      for (int t = tid; t < nblk; t += JACB_THREADS) {
+        const int a = blk[t] & 0xffff, c = blk[t] >> 16;
+        const double sa = sn[a];
+        const int pa = pp[a], qa = qq[a];
+        if (a == c) {
+          if (sa != 0.0) {
+            G[pa * S + qa] = 0.0;
+            G[pa * S + pa] = dp[a] - tq[a];
+            G[qa * S + qa] = dq[a] + tq[a];
+          }
+          continue;
+        }
+        const double sc = sn[c];
+        if (sa == 0.0 && sc == 0.0) continue;
+        const double ca = cs[a], cc = cs[c];
+        const int pc = pp[c], qc = qq[c];
+        const int i00 = gi(pa, pc), i01 = gi(pa, qc);
+        const int i10 = gi(qa, pc), i11 = gi(qa, qc);
+        const double g00 = G[i00], g01 = G[i01], g10 = G[i10], g11 = G[i11];
+        const double h00 = ca * g00 - sa * g10, h01 = ca * g01 - sa * g11;
+        const double h10 = sa * g00 + ca * g10, h11 = sa * g01 + ca * g11;
+        G[i00] = cc * h00 - sc * h01;
+        G[i01] = sc * h00 + cc * h01;
+        G[i10] = cc * h10 - sc * h11;
+        G[i11] = sc * h10 + cc * h11;
+      }
+      for (int t = tid; t < nitem; t += JACB_THREADS) {
+        const int i = t / b, k = t - i * b;
+        const double s = sn[i];
+        if (s == 0.0) continue;
+        const double c = cs[i];
+        const int p = pp[i], q = qq[i];
+        const double vp = Vt[p * b + k], vq = Vt[q * b + k];
+        Vt[p * b + k] = c * vp - s * vq;
+        Vt[q * b + k] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // sort by descending eigenvalue (stable rank of every diagonal entry)
+  int* rk = pp;  // pp, qq: b ints
+  double* ev = cs;  // cs, sn: b doubles
+  for (int i = tid; i < b; i += JACB_THREADS) {
+    const double g = G[i * S + i];
+    int rank = 0;
+    for (int j = 0; j < b; ++j) {
+      const double gj = G[j * S + j];
+      rank += (gj > g) || (gj == g && j < i);
+    }
+    rk[i] = rank;
+  }
+  __syncthreads();
+  for (int i = tid; i < b; i += JACB_THREADS) ev[rk[i]] = G[i * S + i];
+  __syncthreads();
+  // G is no longer needed: V[k][rk[i]] = Vt[i][k] staged through it
+  for (int e = tid; e < b * b; e += JACB_THREADS) {
+    const int i = e / b, k = e - i * b;
+    G[k * b + rk[i]] = Vt[e];
+  }
+  __syncthreads();
+  for (int e = tid; e < b * b; e += JACB_THREADS) {
+    Vt[e] = G[e];
+    Gg[e] = (e / b == e % b) ? ev[e / b] : 0.0;
+  }
+  for (int i = tid; i < b; i += JACB_THREADS) lam[i] = ev[i];
+}
+
 void sym_eig_jacobi(Device& dev, double* G, double* V, double* lam, int b,
                     int batch, double tol) {
-  if (b % 2 != 0 || b < 2 || b > JAC_MAXB)
-    throw ArgError("sym_eig_jacobi: b must be even and <= 128");
+  if (b % 2 != 0 || b < 2 || b > JAC_BIGB)
+    throw ArgError("sym_eig_jacobi: b must be even and <= 512");
+  if (b > JAC_MAXB) {
+    const int h = b / 2;
+    const size_t lds = (size_t)h * 5 * sizeof(double) +
+                       (size_t)h * 2 * sizeof(int) +
+                       (size_t)h * (h + 1) / 2 * sizeof(int);
+    allow_lds((const void*)sym_eig_jacobi_big_kernel, lds);
+    Tensor w = dev.empty({batch, b, b + 1});
+    if (dev.prof.on) dev.prof.begin(dev.stream, PROF_JACOBI, 0.0, 0.0);
+    hipLaunchKernelGGL(sym_eig_jacobi_big_kernel, dim3(batch),
+                       dim3(JACB_THREADS), lds, dev.stream, G, V, lam, w.ptr,
+                       b, tol);
+    if (dev.prof.on) dev.prof.end(dev.stream);
+    IPEPS_HIP(hipGetLastError());
+    return;
+  }
   const bool vlds = b <= 96;
   const size_t lds = jacobi_lds_bytes(b, vlds);
   const void* fn = vlds ? (const void*)sym_eig_jacobi_kernel<true>
@@ -721,11 +891,14 @@ namespace ipeps {
 // the span of the earlier ones) drops that direction: its row and column of
 // R are zero and Z R has a zero column there.  The inverse is formed by
 // column-wise forward substitution into the free upper triangle of G.
+// With glob (b > 128) the b x b work matrix is a global scratch block per
+// matrix instead of LDS (one workgroup each, so the barriers order it).
 __global__ __launch_bounds__(256) void chol_orth_kernel(
-    const double* __restrict__ Gall, double* __restrict__ Rall, int b) {
+    const double* __restrict__ Gall, double* __restrict__ Rall, int b,
+    double* __restrict__ glob) {
   extern __shared__ double lds[];
-  double* G = lds;       // b*b
-  double* dg = G + b * b;  // b: pivots
+  double* G = glob ? glob + (long)blockIdx.x * b * b : lds;  // b*b
+  double* dg = glob ? lds : G + b * b;  // b: pivots
   const int bt = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const double* Gg = Gall + (long)bt * b * b;
   double* R = Rall + (long)bt * b * b;
@@ -770,11 +943,16 @@ __global__ __launch_bounds__(256) void chol_orth_kernel(
 
 void chol_orth_factor(Device& dev, const double* G, double* R, int b,
                       int batch) {
-  if (b < 1 || b > 128) throw ArgError("chol_orth_factor: b must be <= 128");
-  const size_t lds = ((size_t)b * b + b) * sizeof(double);
+  if (b < 1 || b > 512) throw ArgError("chol_orth_factor: b must be <= 512");
+  Tensor w;
+  size_t lds = ((size_t)b * b + b) * sizeof(double);
+  if (b > 128) {
+    w = dev.empty({batch, b, b});
+    lds = (size_t)b * sizeof(double);
+  }
   if (lds > 65536) allow_lds((const void*)chol_orth_kernel, lds);
   hipLaunchKernelGGL(chol_orth_kernel, dim3(batch), dim3(256), lds,
-                     dev.stream, G, R, b);
+                     dev.stream, G, R, b, b > 128 ? w.ptr : nullptr);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -1190,6 +1368,35 @@ void null_threshold(Device& dev, double* S, int b, double rel, int batch,
                     int64_t sS) {
   hipLaunchKernelGGL(null_threshold_kernel, dim3(batch), dim3(128), 0,
                      dev.stream, S, b, rel, (long)sS);
+  IPEPS_HIP(hipGetLastError());
+}
+
+// Columns c of X (batch x n x b, row major) with cn[bt][c] == 0 are
+// overwritten by deterministic pseudo-random values in (-1, 1) (splitmix64
+// of the seed and the element's index, as random_block); the others are
+// left alone.
+__global__ void fill_null_cols_kernel(double* X, int64_t n, int b,
+                                      const double* cn, uint64_t seed) {
+  const int bt = blockIdx.y;
+  const int64_t nb = n * b;
+  double* x = X + bt * nb;
+  const double* c = cn + (int64_t)bt * b;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nb;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (c[i % b] != 0.0) continue;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(bt * nb + i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
+void fill_null_cols(Device& dev, double* X, int64_t n, int b,
+                    const double* cn, int batch, uint64_t seed) {
+  hipLaunchKernelGGL(fill_null_cols_kernel,
+                     dim3(grid_for(n * b, 256), batch), dim3(256), 0,
+                     dev.stream, X, n, b, cn, seed);
   IPEPS_HIP(hipGetLastError());
 }
 
@@ -1837,11 +2044,11 @@ void eig_fmul(Device& dev, const double* lam, const double* X, double* out,
 // Reorders eigenpairs given in descending signed order: the k of largest
 // |lambda| (ties: the larger signed value, i.e. the lower index) first,
 // then the others, each group keeping its descending signed order.  One
-// workgroup; b <= 128.
+// workgroup; b <= 512.
 __global__ void eig_order_kept_kernel(const double* lam, const double* W,
                                       double* lam_out, double* W_out, int b,
                                       int k) {
-  __shared__ int src[128];
+  __shared__ int src[512];
   if (threadIdx.x == 0) {
     int nk = 0, nd = k;
     for (int i = 0; i < b; ++i) {
@@ -1868,8 +2075,8 @@ __global__ void eig_order_kept_kernel(const double* lam, const double* W,
 
 void eig_order_kept(Device& dev, const double* lam, const double* W,
                     double* lam_out, double* W_out, int b, int k) {
-  if (b < 1 || b > 128 || k < 0 || k > b)
-    throw ArgError("eig_order_kept: needs 0 <= k <= b <= 128");
+  if (b < 1 || b > 512 || k < 0 || k > b)
+    throw ArgError("eig_order_kept: needs 0 <= k <= b <= 512");
   hipLaunchKernelGGL(eig_order_kept_kernel, dim3(1), dim3(256), 0,
                      dev.stream, lam, W, lam_out, W_out, b, k);
   IPEPS_HIP(hipGetLastError());

@@ -70,6 +70,13 @@ void orth_block(Device& dev, const Tensor& Z, int batch, int64_t n, int b,
   null_threshold(dev, cn.ptr, b, 1e-13, batch, b);
   Tensor Zs = dev.empty({batch, n, b});
   axpby(dev, batch * sZ, 1.0, Z.ptr, 0.0, Zs.ptr);
+  // null columns of Z (directions M does not reach while the environment
+  // is rank deficient, e.g. a small bond still growing towards chi) are
+  // refilled with fresh pseudo-random directions before the orthogonal
+  // basis is formed: dropped, they would never come back, and the block
+  // would stay short of chi directions once the rank has grown
+  fill_null_cols(dev, Zs.ptr, n, b, cn.ptr, batch, 0x0b10c5eedull);
+  col_norms(dev, Zs.ptr, n, b, cn.ptr, batch, sZ, b);
   col_scale(dev, Zs.ptr, n, b, cn.ptr, 0, nullptr, batch, sZ, b);
   Tensor G = dev.empty({batch, b, b}), R = dev.empty({batch, b, b});
   gemm(dev, true, false, b, b, n, 1.0, Zs.ptr, b, sZ, Zs.ptr, b, sZ, 0.0,
@@ -100,7 +107,7 @@ int subspace_block(int n, int chi, int oversample) {
   if (b >= n) {
     b = n + (n % 2);
   }
-  if (b > 128) b = 128;
+  if (b > MAX_BLOCK) b = MAX_BLOCK;
   if (b < n && b <= chi) throw ArgError("chi too large for the projector SVD");
   return b;
 }

@@ -16,7 +16,8 @@ def _say(msg):
     print(msg, flush=True)
 
 
-CASES = [(2, 16, 0.3, 11), (3, 18, 0.3, 11), (2, 32, 0.0, 4)]
+CASES = [(2, 16, 0.3, 11), (3, 18, 0.3, 11), (2, 32, 0.0, 4),
+         (3, 160, 0.3, 11)]  # the last: block 200, beyond 128
 
 
 @pytest.mark.parametrize("D,chi,J2,seed", CASES)
@@ -38,15 +39,19 @@ def test_converge_matches_oracle(D, chi, J2, seed):
         As = binding.get_state(ctx)
     _say(f"  iters {it} vs {it_or}, e {e!r} vs {e_or!r} (general {e_gen!r})")
     assert ok
-    assert abs(it - it_or) <= 1
+    # at chi = 160 the change of the spectrum approaches 1e-12 at the
+    # rounding level of the b = 200 QR and eigen steps: the two sides can
+    # stop a few iterations apart (energy and spectrum bounds unchanged)
+    assert abs(it - it_or) <= (1 if chi <= 32 else 3)
     assert abs(e - e_or) < 1e-11 * abs(e_or)
     assert abs(e_gen - e_or) < 1e-11 * abs(e_or)
     assert np.abs(s - s_or).max() < 1e-10
     assert np.abs(As[0, 0] - c4v.symmetrize(A[0, 0]).numpy()).max() < 1e-15
 
 
-@pytest.mark.parametrize("K", [5, 20])
-@pytest.mark.parametrize("D,chi,J2,seed", CASES[:2])
+@pytest.mark.parametrize("D,chi,J2,seed,K", [c + (K,) for c in CASES[:2]
+                                               for K in (5, 20)] +
+                         [CASES[3] + (3,)])
 def test_grad_same_env(D, chi, J2, seed, K):
     _say(f"c4v grad D={D} chi={chi} K={K}")
     A = inputs.random_state(seed, 1, 1, 2, D)
@@ -90,5 +95,8 @@ def test_errors():
         assert ei.value.status == binding.ENOTIMPL
     assert binding.c4v_block_size(72) == 90
     assert binding.c4v_block_size(16) == 24
-    assert binding.c4v_block_size(129) == -1
-    assert binding.c4v_block_size(72) == c4v.block_size(72)
+    assert binding.c4v_block_size(129) == 162
+    assert binding.c4v_block_size(409) == 512
+    assert binding.c4v_block_size(410) == -1
+    for chi in (72, 129, 200, 409):
+        assert binding.c4v_block_size(chi) == c4v.block_size(chi)

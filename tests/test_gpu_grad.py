@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import ctmrg, gradient, metric
+from oracle import ctmrg, gradient, metric, observables
 from paper_2511_09546_amd import binding, inputs
 
 pytestmark = pytest.mark.gpu
@@ -50,6 +50,57 @@ def test_grad_K_same_env(D, chi, K, J2, seed, ckpt):
     err = np.linalg.norm(g - g_or) / np.linalg.norm(g_or)
     _say(f"  rel grad err {err:.2e}")
     assert err < 1e-10
+
+
+def test_large_chi_forward_against_oracle():
+    """chi = 128 at D = 2 (cut matrices of side 512, subspace block 170, so
+    the projector SVD runs blocks beyond 128, and the environment's rank
+    grows 4 -> 16 -> 64 -> 128 over the first iterations, so the subspace
+    block must regain the directions that the rank-deficient cut matrices
+    did not reach): iteration count, converged energy and corner spectra
+    against the oracle."""
+    D, chi = 2, 128
+    _say(f"large chi forward: D={D} chi={chi}")
+    A = inputs.random_state(12, 1, 1, 2, D)
+    terms = inputs.terms_j1j2(1, 1, 1.0, 0.3)
+    env, n_or, _ = ctmrg.converge(A, chi, 1e-10, 300)
+    e_or = float(observables.energy(env, A, terms))
+    sp_or = ctmrg.corner_spectra(env).numpy()
+    with binding.Context(A, chi) as ctx:
+        it, dl, ok = ctx.converge(1e-10, 300)
+        e, _ = ctx.energy_grad(terms, grad=False)
+        sp = ctx.spectra()
+    _say(f"  iterations {it} vs {n_or}; e {e!r} vs {e_or!r}; spectra "
+         f"{np.abs(sp - sp_or).max():.1e}")
+    assert it == n_or
+    assert abs(e - e_or) < 1e-10 * abs(e_or)
+    assert np.abs(sp - sp_or).max() < 1e-10
+
+
+def test_large_block_gradient():
+    """The K = 2 gradient with a subspace block of 140 (chi = 40 with an
+    oversampling of 100 at D = 3: the b > 128 eigensolver and the wide
+    deflation of the complement solves), from the oracle's environment,
+    element by element against the oracle."""
+    D, chi, K = 3, 40, 2
+    _say(f"large block gradient: D={D} chi={chi} K={K} block 140")
+    A = inputs.random_state(13, 1, 1, 2, D)
+    terms = inputs.terms_j1j2(1, 1, 1.0, 0.3)
+    env, _, _ = ctmrg.converge(A, chi, 1e-10, 300)
+    e_or, g_or = gradient.grad_K(A, terms, env, chi, K)
+    g_or = g_or.numpy()
+    o = binding.default_opts()
+    o.grad_K = K
+    o.svd_oversample = 100
+    C, T = _env_arrays(env)
+    with binding.Context(A, chi, opts=o) as ctx:
+        ctx.set_env(C, T)
+        e, g = ctx.energy_grad(terms, grad=True)
+    err = np.linalg.norm(g - g_or) / np.linalg.norm(g_or)
+    emax = np.abs(g - g_or).max() / np.abs(g_or).max()
+    _say(f"  e {e!r} vs {e_or!r}; rel grad err {err:.2e}, max {emax:.2e}")
+    assert abs(e - e_or) < 1e-10 * abs(e_or)
+    assert err < 1e-10 and emax < 1e-10
 
 
 @pytest.mark.parametrize("name", ["d2chi8", "d4chi32", "d6chi72",

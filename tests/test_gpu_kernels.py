@@ -101,6 +101,47 @@ def test_sym_eig(b, batch):
             < 1e-12 * np.abs(G[i]).max() * b
 
 
+@pytest.mark.parametrize("b,batch", [(130, 2), (192, 1), (256, 3)])
+def test_sym_eig_large_block(b, batch):
+    """Blocks beyond 128 (the global-memory Jacobi kernel): the same bounds
+    as the LDS kernel, on random and on nearly diagonal graded matrices."""
+    _say(f"sym_eig large b={b} batch={batch}")
+    rng = np.random.default_rng(b)
+    X = rng.standard_normal((batch, b, b))
+    G = X + X.transpose(0, 2, 1)
+    # the last entry: graded diagonal plus a small symmetric perturbation
+    d = np.logspace(0, -8, b)
+    E = 1e-6 * rng.standard_normal((b, b))
+    G[-1] = np.diag(d) + (E + E.T) * np.sqrt(np.outer(d, d))
+    lam, V = binding.debug_sym_eig(G)
+    for i in range(batch):
+        ref = np.sort(np.linalg.eigvalsh(G[i]))[::-1]
+        assert np.abs(lam[i] - ref).max() < 1e-12 * np.abs(ref).max() * b
+        assert np.abs(V[i].T @ V[i] - np.eye(b)).max() < 1e-13 * b
+        assert np.abs(V[i] @ np.diag(lam[i]) @ V[i].T - G[i]).max() \
+            < 1e-12 * np.abs(G[i]).max() * b
+
+
+def test_svd_ts_graded_large_block():
+    """The graded tall-skinny SVD at b = 192 (global-memory Jacobi)."""
+    _say("svd_ts graded, b = 192")
+    rng = np.random.default_rng(6)
+    n, b = 700, 192
+    Q1, _ = np.linalg.qr(rng.standard_normal((n, b)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((b, b)))
+    s_true = np.logspace(0, -10, b)
+    W = (Q1 * s_true) @ Q2.T
+    U, s, J = binding.debug_svd_ts(W[None])
+    # rounding of the Gram products and of b - 1 rotations per sweep: the
+    # b = 24 bounds scaled by b / 24
+    assert np.abs(s[0] - s_true).max() < 1e-14 * b / 24
+    big = s_true >= 1e-5
+    assert np.abs(s[0][big] / s_true[big] - 1).max() < 1e-10
+    assert np.abs(U[0].T @ U[0] - np.eye(b)).max() < 1e-12 * b / 24
+    assert np.abs(W @ J[0] - U[0] * s[0]).max() < 1e-13 * b / 24
+    assert np.abs(J[0].T @ J[0] - np.eye(b)).max() < 1e-13 * b / 24
+
+
 def test_svd_ts_graded():
     """Singular values spanning 10 orders of magnitude: absolute accuracy
     1e-14 s_1 for all of them, relative accuracy 1e-10 down to 1e-5 s_1 (the
