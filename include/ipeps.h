@@ -374,7 +374,7 @@ size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
  * which keeps every intermediate of the K = opts->grad_K unrolled CTMRG
  * iterations, or of one with opts->grad_checkpoint, next to the energy
  * network's tape): an upper estimate for admission decisions, 8 bytes times
- * n_sites * chi^2 D^4 * (64 K + 512) (K = 1 with checkpointing) plus the
+ * n_sites * chi^2 D^4 * (46 K + 220) (K = 1 with checkpointing) plus the
  * double-layer tensors
  * (n_sites * 4 (d^2 + 1) D^8) and the environment.  opts NULL = defaults.
  * Returns 0 for invalid sizes.  Host-only; no device call. */

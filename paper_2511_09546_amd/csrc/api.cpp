@@ -85,10 +85,11 @@ size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
   // checkpointing (the stored input environments are small)
   const double K = o.grad_checkpoint ? 1.0 : (o.grad_K > 0 ? o.grad_K : 0);
   const double dbl = ns * 4.0 * ((double)d * d + 1.0) * D4 * D4;
-  // 64 enlarged-corner sizes per resident unrolled iteration; 512 for the
-  // energy network's tape (its next-nearest-neighbour reduced density
-  // matrices dominate: about 470 measured at D = 6, chi = 72) and the rest
-  const double words = ns * q * (64.0 * K + 512.0) + dbl +
+  // 46 enlarged-corner sizes per resident unrolled iteration and 220 for
+  // the energy network's tape and the rest (peaks measured per site: 957
+  // and 163 at K = 20 without and with checkpointing, D = 6, chi = 72;
+  // 1045 and 234 for the 2x2 Kitaev cell, D = 5, chi = 50)
+  const double words = ns * q * (46.0 * K + 220.0) + dbl +
                        (double)ipeps_env_size(Lx, Ly, D, chi);
   return (size_t)(8.0 * words);
 }

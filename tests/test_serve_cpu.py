@@ -22,7 +22,7 @@ def test_footprint_formula():
     q = 72 * 72 * 6 ** 4
     dbl = 4 * (4 + 1) * 6 ** 8
     env = 4 * 72 * 72 + 4 * 72 * 36 * 72
-    assert f == int(8.0 * (q * (64 * 20 + 512) + dbl + env))
+    assert f == int(8.0 * (q * (46 * 20 + 220) + dbl + env))
     # grows with every size and with K; zero for invalid sizes
     assert binding.footprint_bytes(1, 1, 2, 6, 108, o) > f
     assert binding.footprint_bytes(2, 2, 2, 6, 72, o) > 3.9 * f
@@ -33,7 +33,7 @@ def test_footprint_formula():
     o.grad_K = 20
     o.grad_checkpoint = 1
     assert binding.footprint_bytes(1, 1, 2, 6, 72, o) == int(
-        8.0 * (q * (64 * 1 + 512) + dbl + env))
+        8.0 * (q * (46 * 1 + 220) + dbl + env))
 
 
 def test_admission_respects_budget_and_workers(monkeypatch):
