@@ -67,7 +67,12 @@ def test_complement_solve_iteration_limit_is_reported():
     solves of the SVD adjoint stop at their iteration limit: the gradient is
     still returned, with the warning."""
     _say("failure: complement CG below its floor")
-    w, A, terms = _state()
+    # D = 4, chi = 32: the complement of the kept vectors (dimension 480)
+    # is much larger than the deflation space (16 vectors), so CG has to
+    # iterate (at D = 2, chi = 8 the deflation space covers it all)
+    w = inputs.WORKLOADS["d4chi32"]
+    A = inputs.workload_state("d4chi32")
+    terms = inputs.workload_terms("d4chi32")
     o = binding.default_opts()
     o.adj_cg_tol = 1e-17
     o.grad_K = 1
