@@ -32,14 +32,17 @@ converged state (local metric by CG and by GMRES(30), belief propagation,
 one product with the full metric and its GMRES(30) solve) beside one
 gradient evaluation.
 
-The roofline object reports the library's matrix-core GEMM in the headline
-arithmetic (the dominant kernel): algorithmic flops (2 M N K per launch)
-over the device time of its launches, both recorded live with HIP events on
-the library's stream during as many steps as the timed ones, run right after
-them (the events cost about 6 % of a step, so the timed steps run without);
-its traffic is the HBM bytes per launch from the counter record under
-profiles/ (null when the kernel source has changed since the counters were
-taken).  The cpu_baseline object times the CPU oracle on the host on a
+The roofline object reports the dominant kernel, the FP32 matrix-core GEMM
+with 128 x 144 tiles that carries the chi^2 D^8 products of the network
+contractions (enlarged corners, renormalised edges, open corners of the
+energy network, and their reverse passes): algorithmic flops (2 M N K per
+launch) over the device time of its launches, both recorded live with HIP
+events on the library's stream during as many steps as the timed ones, run
+right after them (the events cost about 6 % of a step, so the timed steps
+run without); its traffic is the HBM bytes per launch from the counter
+record under profiles/ (null when the kernel source has changed since the
+counters were taken).  Beside it: every GEMM launch of the network
+contractions, and every GEMM launch of the step.  The cpu_baseline object times the CPU oracle on the host on a
 bounded sample of the same workload (one CTMRG iteration, the energy network
 with its backward, one unrolled iteration with its backward, one CG solve)
 and composes one step from those phases; the wall time of the whole cold
@@ -114,11 +117,12 @@ def cpu_baseline(name, n_conv):
 
 
 def measured_traffic(prec):
-    """HBM bytes per launch of the FP32 GEMM from the committed counter
-    record (two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled
-    by a plain copy), or None when the GEMM source changed since then."""
+    """HBM bytes per launch of the 128 x 144-tile FP32 GEMM from the
+    committed counter record (two rocprofv3 --pmc passes, FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy), or None when the GEMM source
+    changed since then."""
     import hashlib
-    rec = os.path.join(ROOT, "profiles", "gemm_fp32_d6chi72_traffic.json")
+    rec = os.path.join(ROOT, "profiles", "gemm_fp32_wide_d6chi72_traffic.json")
     src = os.path.join(ROOT, "paper_2511_09546_amd", "csrc", "gemm.hip")
     if prec != "fp32" or not os.path.exists(rec):
         return None
@@ -212,7 +216,7 @@ def run(name, prec, steps, warmup, ckpt=0, ladder=0, profile=True):
         elapsed_prof = time.perf_counter() - t1
         prof = {f: ctx.profile_read(f) for f in
                 (fam, binding.PROF_JACOBI, binding.PROF_PERMUTE,
-                 binding.PROF_NET)}
+                 binding.PROF_NET, binding.PROF_WIDE)}
         ctx.profile(False)
     stats = ctx.stats()
     ctx.close()
@@ -413,11 +417,13 @@ def main():
 
     timed, elapsed = head["timed"], head["elapsed"]
     n_g, t_g, fl_g, by_g = head["prof"][head["fam"]]
+    n_w, t_w, fl_w, by_w = head["prof"][binding.PROF_WIDE]
     _, t_jac, _, _ = head["prof"][binding.PROF_JACOBI]
     _, t_perm, _, _ = head["prof"][binding.PROF_PERMUTE]
     ms = sorted(t["ms"] for t in timed)
     p = lambda q: ms[min(len(ms) - 1, int(round(q * (len(ms) - 1))))]  # noqa
     achieved = fl_g / t_g / 1e12 if t_g > 0 else 0.0
+    ach_w = fl_w / t_w / 1e12 if t_w > 0 else 0.0
     n_net, t_net, fl_net, _ = head["prof"][binding.PROF_NET]
     ach_net = fl_net / t_net / 1e12 if t_net > 0 else 0.0
     peak = PEAK_TFLOPS[args.prec]
@@ -451,25 +457,39 @@ def main():
         "ctm_iters_per_step": [t["iters"] for t in timed],
         "cold_step_ms": head["infos"][0]["ms"] if head["infos"] else None,
         "energy_per_site": timed[-1]["e"],
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak,
+        # the dominant kernel: the 128 x 144-tile FP32 GEMM of the chi^2 D^8
+        # network products (enlarged corners, renormalised edges, open
+        # corners and their reverse passes), timed live with HIP events on
+        # the library's stream; 2 M N K algorithmic flops per launch
+        "roofline": {"bound": "mfma", "achieved": ach_w if n_w else achieved,
+                     "peak": peak, "unit": "TFLOP/s",
+                     "frac": (ach_w if n_w else achieved) / peak,
                      "traffic": measured_traffic(args.prec),
-                     "kernel": f"{args.prec} matrix-core GEMM (gemm_kernel "
-                               "and gemm_f32_lds_kernel, all tile shapes)",
-                     "launches": n_g,
-                     "avg_launch_us": 1e6 * t_g / max(n_g, 1),
-                     "algorithmic_bytes_per_launch": by_g / max(n_g, 1),
-                     "gemm_share_of_step": t_g / head["elapsed_prof"],
+                     "kernel": ("gemm_f32_lds_kernel, 128 x 144 tiles (FP32 "
+                                "products of the chi^2 D^8 network "
+                                "contractions)") if n_w else
+                               f"{args.prec} matrix-core GEMM",
+                     "launches": n_w,
+                     "avg_launch_us": 1e6 * t_w / max(n_w, 1),
+                     "algorithmic_flop_per_launch": fl_w / max(n_w, 1),
+                     "algorithmic_bytes_per_launch": by_w / max(n_w, 1),
+                     "share_of_step": t_w / head["elapsed_prof"],
                      "measured_over": f"{args.steps} profiled steps after "
                                       "the timed ones",
-                     # the same GEMM restricted to the launches of the
-                     # tensor-network contractions (CTMRG moves, energy
-                     # network, their reverse passes): no SVD or
-                     # complement-solve products
+                     # every GEMM launch of the tensor-network contractions
+                     # (all tile shapes; no SVD or complement-solve products)
                      "network_contractions": {
                          "achieved": ach_net, "frac": ach_net / peak,
                          "launches": n_net,
-                         "share_of_gemm_time": t_net / max(t_g, 1e-30)}},
+                         "share_of_gemm_time": t_net / max(t_g, 1e-30)},
+                     # every matrix-core GEMM launch in the headline
+                     # arithmetic, all shapes
+                     "all_gemms": {
+                         "achieved": achieved, "frac": achieved / peak,
+                         "launches": n_g,
+                         "avg_launch_us": 1e6 * t_g / max(n_g, 1),
+                         "algorithmic_bytes_per_launch": by_g / max(n_g, 1),
+                         "share_of_step": t_g / head["elapsed_prof"]}},
         "kernel_time_s": {"gemm": t_g, "jacobi": t_jac, "permute": t_perm},
         "svd_stats": head["stats"],
     }

@@ -389,7 +389,9 @@ size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
  * launches of the tensor-network contractions (double layer, CTMRG moves,
  * energy network and their reverse passes; any arithmetic, a subset of
  * 0, 3 and 4: the products of the projector SVD and of the complement
- * solves are not in it).
+ * solves are not in it), 6 = the FP32 GEMM with 128 x 144 tiles (the
+ * chi^2 D^8-class products of those contractions: enlarged corners,
+ * renormalised edges, open corners; a subset of 3).
  * ipeps_profile_read returns, for one family,
  * the number of launches, their summed device time in seconds and their
  * algorithmic FLOP and byte counts (2 M N K flop; the operand and result

@@ -44,6 +44,7 @@ API_FUNCTIONS = [
 ]
 PROF_GEMM, PROF_JACOBI, PROF_PERMUTE, PROF_GEMM32, PROF_GEMM16 = 0, 1, 2, 3, 4
 PROF_NET = 5  # GEMMs of the network contractions (subset of 0, 3, 4)
+PROF_WIDE = 6  # the 128 x 144-tile FP32 GEMM (chi^2 D^8 products; subset of 3)
 DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
                    "ipeps_debug_svd_ts", "ipeps_debug_stats",
                    "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time",

@@ -125,14 +125,14 @@ static void accumulate_n(Device& dev, const std::string& spec,
 
 std::vector<Var> Tape::einsum_n(const std::string& spec,
                                 const std::vector<Var>& a,
-                                const std::vector<Var>& b) {
+                                const std::vector<Var>& b, bool f32) {
   const size_t ni = a.size();
   std::vector<Tensor> av(ni), bv(ni);
   for (size_t i = 0; i < ni; ++i) {
     av[i] = a[i]->v;
     bv[i] = b[i]->v;
   }
-  std::vector<Tensor> ov = ipeps::einsum_n(dev, spec, av, bv);
+  std::vector<Tensor> ov = ipeps::einsum_n(dev, spec, av, bv, f32);
   std::vector<Var> out(ni);
   bool any = false;
   for (size_t i = 0; i < ni; ++i) {

@@ -40,9 +40,10 @@ class Tape {
 
   Var einsum(const std::string& spec, const Var& a, const Var& b);
   // the same contraction for items of one shape, batched in one GEMM launch
-  // forwards and backwards
+  // forwards and backwards; f32: the outputs kept in FP32 storage when the
+  // products are FP32 or BF16 (for intermediates that only products read)
   std::vector<Var> einsum_n(const std::string& spec, const std::vector<Var>& a,
-                            const std::vector<Var>& b);
+                            const std::vector<Var>& b, bool f32 = false);
   Var view(const Var& x, std::vector<int64_t> shape);
   // i-th sub-tensor along the leading dimension (shares memory)
   Var slice0(const Var& x, int64_t i);

@@ -198,9 +198,11 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
         ac[c * ns + s] = a(s, c);
       }
     // X2 is written in the grouping the big contraction reads ([m k | g e]),
-    // and Q in its cut-matrix layout, both from the GEMM epilogues
+    // and Q in its cut-matrix layout, both from the GEMM epilogues; X2 (and
+    // Y1 below) only ever enter products, which round them to FP32 in the
+    // FP32 and BF16 arithmetics: they are stored in FP32 there
     std::vector<Var> X1 = tp.einsum_n("mgi,ij->mgj", Tl, Cc);
-    std::vector<Var> X2 = tp.einsum_n("mgj,jek->mkge", X1, Tc);
+    std::vector<Var> X2 = tp.einsum_n("mgj,jek->mkge", X1, Tc, true);
     std::vector<Var> Qe = tp.einsum_n("mkge,gebf->mfkb", X2, ac);
     for (int i = 0; i < 4 * ns; ++i) Q[i] = tp.view(Qe[i], {n, n});
   }
@@ -244,7 +246,7 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
   std::vector<Var> Y = tp.einsum_n("rx,rq->xq", PtL, Qc);
   std::vector<Var> Cn = tp.einsum_n("xq,qy->xy", Y, PR);
   // intermediates written in the grouping of their consumers
-  std::vector<Var> Y1 = tp.einsum_n("jgx,jek->xkge", Pt3, Tc);
+  std::vector<Var> Y1 = tp.einsum_n("jgx,jek->xkge", Pt3, Tc, true);
   std::vector<Var> Y2 = tp.einsum_n("xkge,gebf->xfkb", Y1, ac);
   std::vector<Var> Tn = tp.einsum_n("xfkb,kby->xfy", Y2, P3);
   std::vector<Var> raw(Cn);

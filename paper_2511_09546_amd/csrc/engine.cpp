@@ -152,7 +152,7 @@ Tensor Tensor::view(std::vector<int64_t> s) const {
 Tensor Tensor::slice0(int64_t i) const {
   Tensor t = *this;
   t.shape.erase(t.shape.begin());
-  t.ptr = ptr + i * t.numel();
+  t.ptr = f32 ? (double*)((float*)ptr + i * t.numel()) : ptr + i * t.numel();
   return t;
 }
 
@@ -168,8 +168,9 @@ hipEvent_t Profiler::get() {
   return e;
 }
 
-void Profiler::begin(hipStream_t s, int fam, double flop, double bytes) {
-  Rec r{fam, get(), get(), flop, bytes, net};
+void Profiler::begin(hipStream_t s, int fam, double flop, double bytes,
+                     bool wide) {
+  Rec r{fam, get(), get(), flop, bytes, net, wide};
   IPEPS_HIP(hipEventRecord(r.a, s));
   recs.push_back(r);
 }
@@ -183,7 +184,9 @@ void Profiler::read(int fam, long* n, double* sec, double* flop,
   for (auto& r : recs) {
     const bool gemm =
         r.fam == PROF_GEMM || r.fam == PROF_GEMM32 || r.fam == PROF_GEMM16;
-    if (fam == PROF_NET ? !(r.net && gemm) : r.fam != fam) continue;
+    if (fam == PROF_NET ? !(r.net && gemm)
+                        : (fam == PROF_WIDE ? !r.wide : r.fam != fam))
+      continue;
     IPEPS_HIP(hipEventSynchronize(r.b));
     float ms = 0.f;
     IPEPS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
@@ -231,6 +234,15 @@ Tensor Device::empty(std::vector<int64_t> shape) {
   b->pool = &pool;
   t.buf = b;
   t.ptr = (double*)b->p;
+  return t;
+}
+
+Tensor Device::empty_f32(std::vector<int64_t> shape) {
+  int64_t n = 1;
+  for (auto s : shape) n *= s;
+  Tensor t = empty({(n + 1) / 2});
+  t.shape = std::move(shape);
+  t.f32 = true;
   return t;
 }
 
@@ -352,6 +364,40 @@ void einsum_into_n(Device& dev, const std::string& spec,
   if (ni == 0) return;
   if (Bs.size() != ni || outs.size() != ni)
     throw ArgError("einsum: operand counts differ in " + spec);
+  for (size_t i = 1; i < ni; ++i)
+    if (As[i].f32 != As[0].f32 || Bs[i].f32 != Bs[0].f32 ||
+        outs[i].f32 != outs[0].f32)
+      throw ArgError("einsum: batched items differ in storage in " + spec);
+  // FP32-stored tensors take part directly only as operands of FP32 or
+  // BF16 products: with FP64 products they are widened first, and an FP32
+  // output is computed in FP64 and rounded
+  if (dev.cprec == PREC_FP64 && (As[0].f32 || Bs[0].f32 || outs[0].f32)) {
+    auto widen = [&](const std::vector<Tensor>& v) {
+      std::vector<Tensor> r(v.size());
+      for (size_t i = 0; i < v.size(); ++i) {
+        if (!v[i].f32) {
+          r[i] = v[i];
+          continue;
+        }
+        r[i] = dev.empty(v[i].shape);
+        to_f64(dev, (const float*)v[i].ptr, r[i].ptr, v[i].numel());
+      }
+      return r;
+    };
+    std::vector<Tensor> ow = outs;
+    if (outs[0].f32) {
+      if (beta != 0.0) {
+        ow = widen(outs);
+      } else {
+        for (auto& o : ow) o = dev.empty(o.shape);
+      }
+    }
+    einsum_into_n(dev, spec, widen(As), widen(Bs), ow, alpha, beta);
+    if (outs[0].f32)
+      for (size_t i = 0; i < ni; ++i)
+        to_f32(dev, ow[i].ptr, (float*)outs[i].ptr, outs[i].numel());
+    return;
+  }
   NetScope net(dev.prof);
   for (size_t i = 1; i < ni; ++i)
     if (As[i].shape != As[0].shape || Bs[i].shape != Bs[0].shape ||
@@ -399,6 +445,8 @@ void einsum_into_n(Device& dev, const std::string& spec,
   const std::string free_b_own = own_order(s.b, free_b_o);
 
   int64_t nA = A.numel(), nB = B.numel(), nO = out.numel();
+  int64_t nbatch_all = 1;
+  for (char ch : batch) nbatch_all *= dim_of(ch, s.a, A, s.b, B);
   // a scattered output needs the batch labels next to each other in the
   // output (one batch stride)
   bool batch_adjacent = true;
@@ -411,6 +459,7 @@ void einsum_into_n(Device& dev, const std::string& spec,
     const std::string& L1 = swap ? s.b : s.a;
     const std::string& L2 = swap ? s.a : s.b;
     const int64_t n1 = swap ? nB : nA, n2 = swap ? nA : nB;
+    const bool f1s = swap ? B.f32 : A.f32, f2s = swap ? A.f32 : B.f32;
     const std::string& f1o = swap ? free_b_o : free_a_o;
     const std::string& f2o = swap ? free_a_o : free_b_o;
     const std::string& f1own = swap ? free_b_own : free_a_own;
@@ -448,8 +497,13 @@ void einsum_into_n(Device& dev, const std::string& spec,
           }
           p.out = batch + f1 + f2;
           p.perm_out = (p.out != s.o);
+          // an FP32-stored operand is read as it is by the products only
+          // as the first one, unpermuted; elsewhere it is widened first
           const int64_t pin = (p.perm_first ? n1 : 0) +
-                              (p.perm_second ? n2 : 0);
+                              (p.perm_second ? n2 : 0) +
+                              (f1s && p.perm_first ? n1 : 0) +
+                              (f2s ? n2 : 0) +
+                              (f1s && nbatch_all > 1 ? n1 : 0);
           p.cost = pin + (p.perm_out ? 2 * nO : 0);
           // prefer no transposes on ties (slightly faster loads)
           auto take = [&](const Plan& q) {
@@ -483,9 +537,20 @@ void einsum_into_n(Device& dev, const std::string& spec,
   const std::string& L1 = best.swap ? s.b : s.a;
   const std::string& L2 = best.swap ? s.a : s.b;
   std::vector<Tensor> op1(ni), op2(ni);
+  auto widened = [&](const Tensor& t) {
+    if (!t.f32) return t;
+    Tensor w = dev.empty(t.shape);
+    to_f64(dev, (const float*)t.ptr, w.ptr, t.numel());
+    return w;
+  };
+  // the first operand stays FP32 when the products can read it so (one
+  // pointer batch, no permutation)
+  const bool a32 = (best.swap ? B.f32 : A.f32) && !best.perm_first &&
+                   nbatch_all == 1;
   for (size_t i = 0; i < ni; ++i) {
-    const Tensor& T1 = best.swap ? Bs[i] : As[i];
-    const Tensor& T2 = best.swap ? As[i] : Bs[i];
+    const Tensor T1 = a32 ? (best.swap ? Bs[i] : As[i])
+                          : widened(best.swap ? Bs[i] : As[i]);
+    const Tensor T2 = widened(best.swap ? As[i] : Bs[i]);
     op1[i] = best.perm_first ? permuted(dev, T1, perm_of(L1, best.first))
                              : T1;
     op2[i] = best.perm_second ? permuted(dev, T2, perm_of(L2, best.second))
@@ -552,9 +617,23 @@ void einsum_into_n(Device& dev, const std::string& spec,
   const int64_t lda = best.tA ? M : K;
   const int64_t ldb = best.tB ? K : N;
   const double alpha_g = best.perm_out ? 1.0 : alpha;
-  const CMap* cmp = best.scatter ? &cm : nullptr;
+  // an FP32 output written straight from the epilogue (after a permute
+  // pass it is rounded below)
+  cm.c32 = (out.f32 && !best.perm_out) ? 1 : 0;
+  const CMap* cmp = (best.scatter || cm.c32) ? &cm : nullptr;
   if (best.scatter) ++dev.scatter_count;
-  if (ni == 1 || nbatch > 1) {
+  if (a32) {
+    std::vector<const float*> pa(ni);
+    std::vector<const double*> pb(ni);
+    std::vector<double*> pc(ni);
+    for (size_t i = 0; i < ni; ++i) {
+      pa[i] = (const float*)op1[i].ptr;
+      pb[i] = op2[i].ptr;
+      pc[i] = dst[i].ptr;
+    }
+    gemm_ptrs_a32(dev, best.tA, best.tB, M, N, K, alpha_g, pa, lda, pb, ldb,
+                  beta_g, pc, N, cmp);
+  } else if (ni == 1 || nbatch > 1) {
     for (size_t i = 0; i < ni; ++i)
       gemm(dev, best.tA, best.tB, M, N, K, alpha_g, op1[i].ptr, lda, M * K,
            op2[i].ptr, ldb, K * N, beta_g, dst[i].ptr, N, sC_out, nbatch,
@@ -573,8 +652,16 @@ void einsum_into_n(Device& dev, const std::string& spec,
   }
   if (best.perm_out)
     for (size_t i = 0; i < ni; ++i) {
-      Tensor o = outs[i];
+      if (!out.f32) {
+        Tensor o = outs[i];
+        permute(dev, dst[i], perm_of(best.out, s.o), o, alpha, beta);
+        continue;
+      }
+      Tensor o = dev.empty(outs[i].shape);
+      if (beta != 0.0)
+        to_f64(dev, (const float*)outs[i].ptr, o.ptr, o.numel());
       permute(dev, dst[i], perm_of(best.out, s.o), o, alpha, beta);
+      to_f32(dev, o.ptr, (float*)outs[i].ptr, o.numel());
     }
 }
 
@@ -585,13 +672,14 @@ void einsum_into(Device& dev, const std::string& spec, const Tensor& A,
 
 std::vector<Tensor> einsum_n(Device& dev, const std::string& spec,
                              const std::vector<Tensor>& A,
-                             const std::vector<Tensor>& B) {
+                             const std::vector<Tensor>& B, bool f32) {
   if (A.empty()) return {};
   Spec s = parse(spec);
   std::vector<int64_t> sh;
   for (char ch : s.o) sh.push_back(dim_of(ch, s.a, A[0], s.b, B[0]));
   std::vector<Tensor> out(A.size());
-  for (auto& o : out) o = dev.empty(sh);
+  const bool o32 = f32 && dev.cprec != PREC_FP64;
+  for (auto& o : out) o = o32 ? dev.empty_f32(sh) : dev.empty(sh);
   einsum_into_n(dev, spec, A, B, out, 1.0, 0.0);
   return out;
 }

@@ -87,12 +87,15 @@ struct Buffer {
   }
 };
 
-// Dense row-major FP64 tensor in device memory (shared ownership of the
-// buffer; views share it).
+// Dense row-major tensor in device memory (shared ownership of the buffer;
+// views share it).  FP64, or FP32 when f32 is set: then ptr holds numel()
+// floats.  FP32 storage is used for contraction intermediates whose every
+// reader rounds them to FP32 anyway (operands of FP32 and BF16x3 products).
 struct Tensor {
   std::shared_ptr<Buffer> buf;
   double* ptr = nullptr;
   std::vector<int64_t> shape;
+  bool f32 = false;
 
   int64_t numel() const {
     int64_t n = 1;
@@ -115,7 +118,9 @@ enum ProfFamily {
   PROF_GEMM16 = 4,   // BF16x3 matrix-core GEMM
   PROF_NET = 5,      // GEMMs of the network contractions (einsum), any
                      // arithmetic: a subset of the three GEMM families
-  PROF_N = 6
+  PROF_WIDE = 6,     // the 128 x 144-tile FP32 GEMM (the chi^2 D^8-class
+                     // network products): a subset of PROF_GEMM32
+  PROF_N = 7
 };
 
 // Arithmetic of the GEMMs issued on a device (the contraction precision;
@@ -144,13 +149,15 @@ struct Profiler {
     int fam;
     hipEvent_t a, b;
     double flop, bytes;
-    bool net;  // issued by a network contraction
+    bool net;   // issued by a network contraction
+    bool wide;  // the 128 x 144-tile FP32 GEMM
   };
   bool net = false;  // launches now belong to a network contraction
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   hipEvent_t get();
-  void begin(hipStream_t s, int fam, double flop, double bytes);
+  void begin(hipStream_t s, int fam, double flop, double bytes,
+             bool wide = false);
   void end(hipStream_t s);
   // launches, seconds, flop, bytes of one family (synchronises)
   void read(int fam, long* n, double* sec, double* flop, double* bytes);
@@ -174,6 +181,7 @@ struct Device {
   long scatter_count = 0;
 
   Tensor empty(std::vector<int64_t> shape);
+  Tensor empty_f32(std::vector<int64_t> shape);  // FP32 storage
   Tensor zeros(std::vector<int64_t> shape);
   Tensor scalar_buffer(int n);            // n doubles
   void upload(Tensor& t, const double* host);
@@ -213,6 +221,7 @@ struct PrecScope {
 constexpr int CMAP_DIGITS = 4;
 struct CMap {
   int nr = 0, nc = 0;
+  int c32 = 0;  // C stored in FP32 (offsets and strides count floats)
   int re[CMAP_DIGITS] = {0, 0, 0, 0}, ce[CMAP_DIGITS] = {0, 0, 0, 0};
   int64_t rs[CMAP_DIGITS] = {0, 0, 0, 0}, cs[CMAP_DIGITS] = {0, 0, 0, 0};
 };
@@ -241,9 +250,12 @@ void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                    int64_t K, double alpha,
                    const std::vector<const float*>& A, int64_t lda,
                    const std::vector<const double*>& B, int64_t ldb,
-                   double beta, const std::vector<double*>& C, int64_t ldc);
+                   double beta, const std::vector<double*>& C, int64_t ldc,
+                   const CMap* cm = nullptr);
 // y[i] = (float) x[i]
 void to_f32(Device& dev, const double* x, float* y, int64_t n);
+// y[i] = (double) x[i]
+void to_f64(Device& dev, const float* x, double* y, int64_t n);
 // Up to NB_MAX vectors of any lengths, normalised in one pass (see
 // normalize_batch): a[i] the input (forward) or y (backward), b[i] ybar
 // (backward), out[i] y (forward) or xbar (backward, accumulated), nrm[i]
@@ -323,9 +335,11 @@ void einsum_into_n(Device& dev, const std::string& spec,
                    const std::vector<Tensor>& A, const std::vector<Tensor>& B,
                    const std::vector<Tensor>& out, double alpha = 1.0,
                    double beta = 0.0);
+// f32: the outputs stored in FP32 (only where the device's product
+// arithmetic is not FP64; otherwise FP64).
 std::vector<Tensor> einsum_n(Device& dev, const std::string& spec,
                              const std::vector<Tensor>& A,
-                             const std::vector<Tensor>& B);
+                             const std::vector<Tensor>& B, bool f32 = false);
 
 }  // namespace ipeps
 

@@ -89,6 +89,22 @@ __device__ __forceinline__ long cmap_row(const CMap& cm, int row, long ldc) {
 __device__ __forceinline__ long cmap_col(const CMap& cm, int col) {
   return cm.nr == 0 ? (long)col : cmap_off(cm.nc, cm.ce, cm.cs, col);
 }
+// C[bz] of a strided batch (element strides count floats for FP32 C)
+__device__ __forceinline__ double* cbase(double* C, long bz, long sC,
+                                         int c32) {
+  return c32 ? (double*)((float*)C + bz * sC) : C + bz * sC;
+}
+// element idx of C, FP64 or FP32 storage
+__device__ __forceinline__ double cload(const double* C, long idx, int c32) {
+  return c32 ? (double)((const float*)C)[idx] : C[idx];
+}
+__device__ __forceinline__ void cstore(double* C, long idx, double v,
+                                       int c32) {
+  if (c32)
+    ((float*)C)[idx] = (float)v;
+  else
+    C[idx] = v;
+}
 
 // Epilogue of a tile of 16 x 16 MFMA blocks: out = alpha acc + beta out
 // (one split) or the partial sums (split K).  Register r of block (i, j)
@@ -129,7 +145,8 @@ __device__ __forceinline__ void store_tile(const V (&acc)[TM][TN], int lane,
           const int row =
               r0 + i * 16 + (L32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
           const int col = c0 + j * 16 + (lane & 15);
-          cv[j][r] = row < M && col < N ? out[roff[r] + coff[j]] : 0.0;
+          cv[j][r] =
+              row < M && col < N ? cload(out, roff[r] + coff[j], cm.c32) : 0.0;
         }
     }
 #pragma unroll
@@ -143,7 +160,7 @@ __device__ __forceinline__ void store_tile(const V (&acc)[TM][TN], int lane,
           if (splits == 1) {
             double v = alpha * (double)acc[i][j][r];
             if (beta != 0.0) v += beta * cv[j][r];
-            out[roff[r] + coff[j]] = v;
+            cstore(out, roff[r] + coff[j], v, cm.c32);
           } else {
             pout[(long)row * N + col] = acc[i][j][r];
           }
@@ -291,7 +308,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(
 
   // epilogue: direct (splits == 1) or partial tile (split K), the partial
   // sums kept in the accumulator's type (exact)
-  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  double* out = use_ptrs ? ptrs.c[bz] : cbase(C, bz, sC, cm.c32);
   T* pout = (T*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<F32>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha, beta,
                   out, ldc, pout, splits, cm);
@@ -436,7 +453,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(
   }
 
   // split K: FP32 partial sums (exact copies of the accumulators)
-  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  double* out = use_ptrs ? ptrs.c[bz] : cbase(C, bz, sC, cm.c32);
   float* pout =
       (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
@@ -634,7 +651,7 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
     if (t + 2 < T) issue(As0, Bs0, kbeg + (t + 2) * BK);
     mma();
   }
-  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  double* out = use_ptrs ? ptrs.c[bz] : cbase(C, bz, sC, cm.c32);
   float* pout = (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
                    beta, out, ldc, pout, splits, cm);
@@ -657,11 +674,11 @@ __global__ void splitk_sum_kernel(const PT* __restrict__ part, int S,
     for (int s = 0; s < S; ++s)
       v += (double)part[((long)s * batch + b) * mn + i];
     const long r = i / N, c = i % N;
-    double* cp = (use_ptrs ? ptrs.c[b] : C + b * sC) +
-                 cmap_row(cm, (int)r, ldc) + cmap_col(cm, (int)c);
+    double* base = use_ptrs ? ptrs.c[b] : cbase(C, b, sC, cm.c32);
+    const long off = cmap_row(cm, (int)r, ldc) + cmap_col(cm, (int)c);
     double o = alpha * v;
-    if (beta != 0.0) o += beta * *cp;
-    *cp = o;
+    if (beta != 0.0) o += beta * cload(base, off, cm.c32);
+    cstore(base, off, o, cm.c32);
   }
 }
 
@@ -862,7 +879,7 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_ps_kernel(
 #undef PS_STORE
 
   // split K: FP32 partial sums (exact copies of the accumulators)
-  double* out = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  double* out = use_ptrs ? ptrs.c[bz] : cbase(C, bz, sC, cm.c32);
   float* pout =
       (float*)part + ((long)sp * (gridDim.y / splits) + bz) * (long)M * N;
   store_tile<true>(acc, lane, m0 + wm * WTM, n0 + wn * WTN, M, N, alpha,
@@ -1109,7 +1126,7 @@ __global__ __launch_bounds__(SMALL_T) void small_sum_kernel(
     PtrArgs ptrs, CMap cm) {
   const int bz = blockIdx.x, batch = gridDim.x, mn = M * N;
   __shared__ double red[SMALL_T];
-  double* Cb = use_ptrs ? ptrs.c[bz] : C + (long)bz * sC;
+  double* Cb = use_ptrs ? ptrs.c[bz] : cbase(C, bz, sC, cm.c32);
   for (int o = 0; o < mn; ++o) {
     double v = 0.0;
     for (int sp = threadIdx.x; sp < S; sp += SMALL_T)
@@ -1121,10 +1138,10 @@ __global__ __launch_bounds__(SMALL_T) void small_sum_kernel(
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      double* cp = Cb + cmap_row(cm, o / N, ldc) + cmap_col(cm, o % N);
+      const long off = cmap_row(cm, o / N, ldc) + cmap_col(cm, o % N);
       double r = alpha * red[0];
-      if (beta != 0.0) r += beta * *cp;
-      *cp = r;
+      if (beta != 0.0) r += beta * cload(Cb, off, cm.c32);
+      cstore(Cb, off, r, cm.c32);
     }
     __syncthreads();
   }
@@ -1243,7 +1260,8 @@ void launch_cfg(Device& dev, const Call& c) {
                    2.0 * c.M * c.N * c.K * c.batch,
                    c.batch * ((c.a32 ? 4.0 : 8.0) * c.M * c.K +
                               8.0 * ((double)c.K * c.N +
-                                     (c.beta != 0.0 ? 2.0 : 1.0) * c.M * c.N)));
+                                     (c.beta != 0.0 ? 2.0 : 1.0) * c.M * c.N)),
+                   P == 1 && BN == 144);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, grid, dim3(256), 0, dev.stream, c.M, c.N, c.K,
                        c.alpha, c.A, c.lda, c.sA, c.B, c.ldb, c.sB, c.beta,
@@ -1426,7 +1444,8 @@ void gemm(Device& dev, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
           int64_t ldc, int64_t sC, int64_t batch, const CMap* cm) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   if (K == 0) {
-    if (cm && cm->nr) throw ArgError("gemm: scattered C with K = 0");
+    if (cm && (cm->nr || cm->c32))
+      throw ArgError("gemm: scattered or FP32 C with K = 0");
     for (int64_t b = 0; b < batch; ++b)
       for (int64_t m = 0; m < M; ++m)
         axpby(dev, N, 0.0, C + b * sC + m * ldc, beta, C + b * sC + m * ldc);
@@ -1481,10 +1500,12 @@ void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                    int64_t K, double alpha,
                    const std::vector<const float*>& A, int64_t lda,
                    const std::vector<const double*>& B, int64_t ldb,
-                   double beta, const std::vector<double*>& C, int64_t ldc) {
+                   double beta, const std::vector<double*>& C, int64_t ldc,
+                   const CMap* cm) {
   if (dev.cprec == PREC_FP64)
     throw ArgError("gemm_ptrs_a32: FP32 operands need FP32 or BF16x3 products");
-  gemm_ptrs_impl(dev, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  gemm_ptrs_impl(dev, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                 cm);
 }
 
 }  // namespace ipeps

@@ -284,6 +284,19 @@ void to_f32(Device& dev, const double* x, float* y, int64_t n) {
   IPEPS_HIP(hipGetLastError());
 }
 
+__global__ void to_f64_kernel(const float* x, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+
+void to_f64(Device& dev, const float* x, double* y, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(to_f64_kernel, dim3(grid_for(n, 256)), dim3(256), 0,
+                     dev.stream, x, y, n);
+  IPEPS_HIP(hipGetLastError());
+}
+
 // dst (cols x rows) = src^T (rows x cols), row major, 32 x 32 tiles staged
 // through LDS (row stride 33) so that reads and writes are both coalesced.
 template <typename T>

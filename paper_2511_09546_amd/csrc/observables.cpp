@@ -33,6 +33,11 @@ struct Net {
   Var E(const char* spec, const Var& x, const Var& y) {
     return tp.einsum(spec, x, y);
   }
+  // the same for an intermediate that only products read: FP32 storage
+  // with FP32 or BF16 products (which round it to FP32 anyway)
+  Var E32(const char* spec, const Var& x, const Var& y) {
+    return tp.einsum_n(spec, {x}, {y}, true)[0];
+  }
   // tensors shared by several terms of one evaluation, keyed by
   // (corner, site): the open double layers, the corner-edge products X2
   // and the enlarged corners (plain and with open physical legs)
@@ -59,7 +64,7 @@ struct Net {
     auto it = x2_c.find({c, s});
     if (it != x2_c.end()) return it->second;
     Var X1 = E("mgi,ij->mgj", T((c + 3) % 4, s), C(c, s));
-    return x2_c[{c, s}] = E("mgj,jek->mkge", X1, T(c, s));
+    return x2_c[{c, s}] = E32("mgj,jek->mkge", X1, T(c, s));
   }
   // Each half of the 2x1 (1x2) block contracts the open double layer into
   // the corner-edge-corner-edge product over the two legs they share first
@@ -69,26 +74,26 @@ struct Net {
   Var rdm_h(int s1, int s2) {
     Var L1 = E("ij,mgi->jmg", C(0, s1), T(3, s1));
     Var L2 = E("jmg,qm->jgq", L1, C(3, s1));
-    Var L3 = E("jgq,jek->qkge", L2, T(0, s1));
-    Var L5 = E("qkge,stgebz->kstbqz", L3, ao(s1));
+    Var L3 = E32("jgq,jek->qkge", L2, T(0, s1));
+    Var L5 = E32("qkge,stgebz->kstbqz", L3, ao(s1));
     Var HL = E("kstbqz,wzq->kwstb", L5, T(2, s1));
     Var R1 = E("ji,ibm->jbm", C(1, s2), T(1, s2));
     Var R2 = E("jbm,mq->jbq", R1, C(2, s2));
-    Var R3 = E("kej,jbq->kqeb", T(0, s2), R2);
-    Var R5 = E("kqeb,stvebz->kstvqz", R3, ao(s2));
+    Var R3 = E32("kej,jbq->kqeb", T(0, s2), R2);
+    Var R5 = E32("kqeb,stvebz->kstvqz", R3, ao(s2));
     Var HR = E("kstvqz,qzw->kwstv", R5, T(2, s2));
     return E("kwstb,kwuvb->sutv", HL, HR);
   }
   Var rdm_v(int s1, int s2) {
     Var V1 = E("ij,jek->iek", C(0, s1), T(0, s1));
     Var V2 = E("iek,kp->iep", V1, C(1, s1));
-    Var V3 = E("iep,mgi->pmge", V2, T(3, s1));
-    Var V5 = E("pmge,stgebz->mstzpb", V3, ao(s1));
+    Var V3 = E32("iep,mgi->pmge", V2, T(3, s1));
+    Var V5 = E32("pmge,stgebz->mstzpb", V3, ao(s1));
     Var HT = E("mstzpb,pbn->mnstz", V5, T(1, s1));
     Var W1 = E("qgm,wq->gmw", T(3, s2), C(3, s2));
     Var W2 = E("gmw,vyw->gmvy", W1, T(2, s2));
-    Var W3 = E("gmvy,pv->mpgy", W2, C(2, s2));
-    Var W5 = E("mpgy,stgzby->mstzpb", W3, ao(s2));
+    Var W3 = E32("gmvy,pv->mpgy", W2, C(2, s2));
+    Var W5 = E32("mpgy,stgzby->mstzpb", W3, ao(s2));
     Var HB = E("mstzpb,nbp->mnstz", W5, T(1, s2));
     return E("mnstz,mnuvz->sutv", HT, HB);
   }
