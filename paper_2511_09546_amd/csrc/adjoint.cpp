@@ -58,7 +58,8 @@ double run(Context& cx, const std::vector<TermSpec>& terms, int K, bool full,
   VEnv env0 = full ? init_env_ad(tp, cx, arot)
                    : venv_leaves(tp, cx, cx.env, env_req);
   VEnv env = env0;
-  for (int k = 0; k < K; ++k) env = ctm_step_ad(tp, cx, env, arot);
+  const std::vector<Var> arotf = arot_fb(tp, arot);
+  for (int k = 0; k < K; ++k) env = ctm_step_ad(tp, cx, env, arot, &arotf);
   const double e = energy_ad(tp, cx, env, As, arot, terms);
   tp.backward();
   if (env_req) {

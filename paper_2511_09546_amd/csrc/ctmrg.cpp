@@ -176,14 +176,27 @@ void init_env(Context& cx) {
   cx.have_warm = false;
 }
 
+std::vector<Var> arot_fb(Tape& tp, const std::vector<Var>& arot) {
+  std::vector<Var> r(arot.size());
+  for (size_t i = 0; i < arot.size(); ++i)
+    r[i] = tp.permute(arot[i], {0, 1, 3, 2});
+  return r;
+}
+
 VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
-                 const std::vector<Var>& arot) {
+                 const std::vector<Var>& arot,
+                 const std::vector<Var>* arotf) {
   const int ns = cx.nsite(), chi = cx.chi, D2 = cx.D2, nc = cx.ncut();
   const int64_t n = cx.n;
   const Lattice& L = cx.lat;
   auto C = [&](int c, int s) { return in.C[c * ns + s]; };
   auto T = [&](int c, int s) { return in.T[c * ns + s]; };
-  auto a = [&](int s, int c) { return arot[s * 4 + c]; };
+  std::vector<Var> af_own;
+  if (!arotf) af_own = arot_fb(tp, arot);
+  const std::vector<Var>& afv = arotf ? *arotf : af_own;
+  // a[g e f b]: columns (f, b) of the products with the double layer, b the
+  // innermost output leg
+  auto af = [&](int s, int c) { return afv[s * 4 + c]; };
 
   // enlarged corners Q_c(s)[(m f), (k b)], all corners of all sites in one
   // batched contraction per step
@@ -195,7 +208,7 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
         Tl[c * ns + s] = T((c + 3) % 4, s);
         Cc[c * ns + s] = C(c, s);
         Tc[c * ns + s] = T(c, s);
-        ac[c * ns + s] = a(s, c);
+        ac[c * ns + s] = af(s, c);
       }
     // X2 is written in the grouping the big contraction reads ([m k | g e]),
     // and Q in its cut-matrix layout, both from the GEMM epilogues; X2 (and
@@ -203,7 +216,7 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
     // FP32 and BF16 arithmetics: they are stored in FP32 there
     std::vector<Var> X1 = tp.einsum_n("mgi,ij->mgj", Tl, Cc);
     std::vector<Var> X2 = tp.einsum_n("mgj,jek->mkge", X1, Tc, true);
-    std::vector<Var> Qe = tp.einsum_n("mkge,gebf->mfkb", X2, ac);
+    std::vector<Var> Qe = tp.einsum_n("mkge,gefb->mfkb", X2, ac);
     for (int i = 0; i < 4 * ns; ++i) Q[i] = tp.view(Qe[i], {n, n});
   }
   // projectors of every cut: cut index c*ns + p (plaquette p, cut c between
@@ -240,14 +253,14 @@ VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
                                -PLAQ_OFFSET[(c + 1) % 4][1]);
       Pt3[i] = tp.view(PtT[c * ns + pccw], {chi, D2, chi});
       Tc[i] = T(c, s);
-      ac[i] = a(s, c);
+      ac[i] = af(s, c);
       P3[i] = tp.view(P[cutR], {chi, D2, chi});
     }
   std::vector<Var> Y = tp.einsum_n("rx,rq->xq", PtL, Qc);
   std::vector<Var> Cn = tp.einsum_n("xq,qy->xy", Y, PR);
   // intermediates written in the grouping of their consumers
   std::vector<Var> Y1 = tp.einsum_n("jgx,jek->xkge", Pt3, Tc, true);
-  std::vector<Var> Y2 = tp.einsum_n("xkge,gebf->xfkb", Y1, ac);
+  std::vector<Var> Y2 = tp.einsum_n("xkge,gefb->xfkb", Y1, ac);
   std::vector<Var> Tn = tp.einsum_n("xfkb,kby->xfy", Y2, P3);
   std::vector<Var> raw(Cn);
   raw.insert(raw.end(), Tn.begin(), Tn.end());

@@ -99,7 +99,9 @@ double log_kappa_grad(Context& cx, const double* Ak, double* gbra) {
   Var bra = tp.leaf(cx.A.view({cx.d, D, D, D, D}), true);
   std::vector<Var> arot = arot_from_pairs(tp, cx, {ket}, {bra});
   VEnv env = venv_leaves(tp, cx, cx.env, false);
-  for (int k = 0; k < cx.grad_K; ++k) env = ctm_step_ad(tp, cx, env, arot);
+  const std::vector<Var> arotf = arot_fb(tp, arot);
+  for (int k = 0; k < cx.grad_K; ++k)
+    env = ctm_step_ad(tp, cx, env, arot, &arotf);
   Nets n = kappa_networks(tp, env, tp.view(arot[0], {D2, D2, D2, D2}));
   // the four values in one download
   Tensor vals = dev.empty({4});

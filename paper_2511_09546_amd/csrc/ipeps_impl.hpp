@@ -205,9 +205,14 @@ VEnv venv_leaves(Tape& tp, Context& cx, const Env& e, bool req = false);
 // tape (the start of the full-N gradient).
 VEnv init_env_ad(Tape& tp, Context& cx, const std::vector<Var>& arot);
 Env env_pack(Context& cx, const VEnv& v);
-// One simultaneous CTMRG iteration on the tape.
+// The double layers with their last two legs exchanged, a[g e f b]: the
+// layout in which the corner and edge products read them.
+std::vector<Var> arot_fb(Tape& tp, const std::vector<Var>& arot);
+// One simultaneous CTMRG iteration on the tape (arotf: arot_fb(arot), made
+// here when not given).
 VEnv ctm_step_ad(Tape& tp, Context& cx, const VEnv& in,
-                 const std::vector<Var>& arot);
+                 const std::vector<Var>& arot,
+                 const std::vector<Var>* arotf = nullptr);
 // Plain forward iteration (nothing recorded).
 void ctm_step(Context& cx, const Env& in, Env& out);
 // CTMRG iterations on the context's environment until the corner-spectrum
