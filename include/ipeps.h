@@ -381,6 +381,17 @@ size_t ipeps_env_size(int Lx, int Ly, int D, int chi);
 size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
                              const ipeps_opts* opts);
 
+/* Device memory that destroyed contexts left cached for later contexts of
+ * the process (ctm_free keeps a context's blocks in a process-wide list,
+ * from which later contexts allocate first) is returned to HIP, largest
+ * blocks first, until at most keep_bytes remain cached; *remaining (may be
+ * NULL) receives the bytes still cached.  For long-lived processes that
+ * share the device with others, e.g. the worker processes of a request
+ * loop: without it the cache holds the largest working set any context of
+ * the process has had.  Thread-safe (the list is locked; its blocks are
+ * idle).  Errors: EHIP. */
+int ipeps_release_cache(size_t keep_bytes, size_t* remaining);
+
 /* Kernel timing of the context's own launches, for roofline reports: with
  * on = 1 the context records HIP events on its stream around every launch
  * of the timed kernel families (clearing earlier records); on = 0 stops.

@@ -80,6 +80,19 @@ int ipeps_debug_einsum(const char* spec, int prec, int mode, int count,
 struct ipeps_ctx;
 int ipeps_debug_stats(struct ipeps_ctx* ctx, double* out);
 
+/* Memory check of a context created while IPEPS_MEMCHECK was set in the
+ * environment (1: guard bands of 16 KiB around every device tensor, released
+ * blocks held back from reuse until the next check; 2: also every new
+ * tensor filled with NaN).  Synchronises the context's stream, verifies the
+ * bands of every live and held block, writes one line per damaged band to
+ * stderr (tensor size and address, side, distance of the nearest changed
+ * byte) and sets *damaged to their number, or to -1 when the context was
+ * created without the check; the held blocks are reusable afterwards.
+ * ctm_free runs the same verification.  For finding kernels that write
+ * outside their tensors, or read memory no kernel wrote: never enabled in
+ * production runs. */
+int ipeps_debug_memcheck(struct ipeps_ctx* ctx, long* damaged);
+
 /* Failure injection for the error-path tests (forced from the host; every
  * kernel still runs to its normal end):
  *   kind 0  clear all injected faults;

@@ -33,7 +33,7 @@ API_FUNCTIONS = [
     "ipeps_bp_messages", "precond_apply_bp", "precond_apply_bp_dev",
     "ipeps_strerror", "ipeps_version", "ipeps_profile_enable",
     "ipeps_profile_read", "ctm_set_state_dev", "ipeps_energy_grad_dev",
-    "precond_apply_dev", "ipeps_footprint_bytes",
+    "precond_apply_dev", "ipeps_footprint_bytes", "ipeps_release_cache",
     "precond_apply_dev_noalloc", "precond_noalloc_bytes",
     "ipeps_lbfgs_default_params", "ipeps_lbfgs_create", "ipeps_lbfgs_step",
     "ipeps_lbfgs_free", "ipeps_get_state", "precond_apply_gmres",
@@ -49,7 +49,7 @@ DEBUG_FUNCTIONS = ["ipeps_debug_gemm", "ipeps_debug_sym_eig",
                    "ipeps_debug_svd_ts", "ipeps_debug_stats",
                    "ipeps_debug_gemm_prec", "ipeps_debug_gemm_time",
                    "ipeps_debug_permute", "ipeps_debug_set_fault",
-                   "ipeps_debug_einsum"]
+                   "ipeps_debug_einsum", "ipeps_debug_memcheck"]
 
 
 class IpepsError(RuntimeError):
@@ -147,6 +147,8 @@ def load():
     lib.ipeps_footprint_bytes.argtypes = [c_int, c_int, c_int, c_int, c_int,
                                           c_void_p]
     lib.ipeps_footprint_bytes.restype = c_size_t
+    lib.ipeps_release_cache.argtypes = [c_size_t, POINTER(c_size_t)]
+    lib.ipeps_release_cache.restype = c_int
     lib.ctm_free.argtypes = [c_void_p]
     lib.ctm_free.restype = None
     lib.ipeps_strerror.argtypes = [c_int]
@@ -182,6 +184,7 @@ def load():
         _IP]
     lib.ipeps_debug_stats.argtypes = [c_void_p, _DP]
     lib.ipeps_debug_set_fault.argtypes = [c_void_p, c_int, c_double]
+    lib.ipeps_debug_memcheck.argtypes = [c_void_p, POINTER(ctypes.c_long)]
     lib.ipeps_debug_svd_ts.argtypes = [c_int, c_int, c_int, _DP, _DP, _DP,
                                        _DP]
     for name in ("ctm_init", "ctm_set_state", "ctm_converge",
@@ -193,7 +196,8 @@ def load():
                  "ipeps_debug_sym_eig", "ipeps_debug_svd_ts",
                  "ipeps_debug_stats", "ipeps_debug_gemm_prec",
                  "ipeps_debug_gemm_time", "ipeps_debug_permute",
-                 "ipeps_debug_set_fault", "ipeps_debug_einsum"):
+                 "ipeps_debug_set_fault", "ipeps_debug_einsum",
+                 "ipeps_debug_memcheck"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -231,6 +235,17 @@ def footprint_bytes(Lx, Ly, d, D, chi, opts=None) -> int:
     """Peak device bytes of one context (ipeps_footprint_bytes)."""
     return int(load().ipeps_footprint_bytes(
         Lx, Ly, d, D, chi, ctypes.byref(opts) if opts is not None else None))
+
+
+def release_cache(keep_bytes: int = 0) -> int:
+    """Returns the device memory of destroyed contexts cached in this
+    process to HIP down to keep_bytes (ipeps_release_cache); returns the
+    bytes still cached."""
+    left = c_size_t(0)
+    st = load().ipeps_release_cache(int(keep_bytes), ctypes.byref(left))
+    if st != OK:
+        raise IpepsError(st, "ipeps_release_cache")
+    return int(left.value)
 
 
 def make_terms(terms):
@@ -402,6 +417,15 @@ class Context:
         if st != OK:
             raise IpepsError(st, "ipeps_profile_read")
         return n.value, sec.value, fl.value, by.value
+
+    def memcheck(self) -> int:
+        """Damaged guard bands of a context created with IPEPS_MEMCHECK set
+        (ipeps_debug_memcheck; -1 without the check)."""
+        n = ctypes.c_long(0)
+        st = load().ipeps_debug_memcheck(self._h, ctypes.byref(n))
+        if st != OK:
+            raise IpepsError(st, "ipeps_debug_memcheck")
+        return n.value
 
     def stats(self) -> dict:
         out = np.zeros(12)

@@ -2,6 +2,7 @@
 // host <-> device copies.  Every entry point catches all exceptions.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -73,6 +74,14 @@ size_t ipeps_env_size(int Lx, int Ly, int D, int chi) {
   return 4 * n * chi * chi + 4 * n * chi * (size_t)D * D * chi;
 }
 
+int ipeps_release_cache(size_t keep_bytes, size_t* remaining) {
+  return guarded([&]() {
+    const size_t left = trim_idle_to(keep_bytes);
+    if (remaining) *remaining = left;
+    return IPEPS_OK;
+  });
+}
+
 size_t ipeps_footprint_bytes(int Lx, int Ly, int d, int D, int chi,
                              const ipeps_opts* opts) {
   if (Lx < 1 || Ly < 1 || d < 1 || D < 1 || chi < 1) return 0;
@@ -119,6 +128,7 @@ int ctm_init(ipeps_ctx** out, int Lx, int Ly, int d, int D, int chi,
   if (!all_finite(A, nA)) return IPEPS_EINVAL;
   ipeps_ctx* c = nullptr;
   int st = guarded([&]() {
+    prime_attributes();
     c = new ipeps_ctx();
     Context& cx = c->cx;
     if (hip_stream) {
@@ -735,6 +745,20 @@ int ipeps_debug_stats(ipeps_ctx* c, double* out) {
   return IPEPS_OK;
 }
 
+int ipeps_debug_memcheck(ipeps_ctx* c, long* damaged) {
+  if (!c || !damaged) return IPEPS_EINVAL;
+  Context& cx = c->cx;
+  if (cx.dev.memcheck <= 0) {
+    *damaged = -1;
+    return IPEPS_OK;
+  }
+  return guarded([&]() {
+    *damaged = cx.dev.memcheck_pending + cx.dev.memcheck_verify();
+    cx.dev.memcheck_pending = 0;
+    return IPEPS_OK;
+  });
+}
+
 int ipeps_debug_set_fault(ipeps_ctx* c, int kind, double value) {
   if (!c || !(value >= 0.0)) return IPEPS_EINVAL;
   Context& cx = c->cx;
@@ -767,6 +791,14 @@ void ctm_free(ipeps_ctx* c) {
   hipStream_t s = c->cx.dev.stream;
   bool own = c->cx.dev.own_stream;
   if (s) (void)hipStreamSynchronize(s);
+  if (c->cx.dev.memcheck > 0) {
+    try {
+      const long bad =
+          c->cx.dev.memcheck_pending + c->cx.dev.memcheck_verify();
+      if (bad) std::fprintf(stderr, "memcheck: %ld damaged guards\n", bad);
+    } catch (...) {
+    }
+  }
   delete c;
   if (own && s) (void)hipStreamDestroy(s);
 }

@@ -11,6 +11,7 @@ namespace {
 template <class F>
 int run(F&& f) {
   try {
+    prime_attributes();
     Device dev;
     dev.stream = nullptr;
     f(dev);

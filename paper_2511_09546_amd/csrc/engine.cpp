@@ -1,5 +1,7 @@
 // Device memory pool, tensor views, and the pairwise contraction planner.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <mutex>
@@ -43,6 +45,20 @@ void trim_idle() {
   g_idle.clear();
 }
 }  // namespace
+
+size_t trim_idle_to(size_t keep_bytes) {
+  std::lock_guard<std::mutex> lock(g_idle_mu);
+  size_t total = 0;
+  for (const auto& kv : g_idle) total += kv.first;
+  // the largest blocks first
+  while (total > keep_bytes && !g_idle.empty()) {
+    auto it = std::prev(g_idle.end());
+    IPEPS_HIP(hipFree(it->second));
+    total -= it->first;
+    g_idle.erase(it);
+  }
+  return total;
+}
 
 void Pool::begin_arena(void* base, size_t bytes) {
   arena_ = (char*)base;
@@ -133,7 +149,18 @@ void Pool::release(void* p, size_t block_bytes) {
     return;
   }
   live_ -= block_bytes;
-  free_.emplace(block_bytes, p);
+  if (hold_) {
+    held_.emplace_back(p, block_bytes);
+    held_bytes_ += block_bytes;
+  } else
+    free_.emplace(block_bytes, p);
+}
+
+std::vector<std::pair<void*, size_t>> Pool::take_held() {
+  std::vector<std::pair<void*, size_t>> r;
+  r.swap(held_);
+  held_bytes_ = 0;
+  return r;
 }
 
 Pool::~Pool() {
@@ -223,18 +250,79 @@ Profiler::~Profiler() {
 }
 
 // ----------------------------------------------------------------- Device
+int memcheck_mode() {
+  const char* v = std::getenv("IPEPS_MEMCHECK");
+  return v ? std::atoi(v) : 0;
+}
+
 Tensor Device::empty(std::vector<int64_t> shape) {
   Tensor t;
   t.shape = std::move(shape);
   const size_t bytes = (size_t)std::max<int64_t>(t.numel(), 1) * 8;
   auto b = std::make_shared<Buffer>();
   size_t got = 0;
+  if (memcheck > 0 && !pool.in_arena()) {
+    // guard bands on both sides (pattern 0xa5), the tensor in between
+    const size_t G = MEMCHECK_GUARD;
+    pool.hold_released(true);
+    if (pool.held_bytes() >= MEMCHECK_HOLD)
+      memcheck_pending += memcheck_verify();
+    b->p = pool.alloc(bytes + 2 * G, &got);
+    b->bytes = got;
+    b->pool = &pool;
+    char* raw = (char*)b->p;
+    IPEPS_HIP(hipMemsetAsync(raw, 0xa5, G, stream));
+    IPEPS_HIP(hipMemsetAsync(raw + G + bytes, 0xa5, got - G - bytes, stream));
+    if (memcheck >= 2) IPEPS_HIP(hipMemsetAsync(raw + G, 0xff, bytes, stream));
+    guarded[raw] = {bytes, got};
+    t.buf = b;
+    t.ptr = (double*)(raw + G);
+    return t;
+  }
   b->p = pool.alloc(bytes, &got);
   b->bytes = got;
   b->pool = &pool;
   t.buf = b;
   t.ptr = (double*)b->p;
   return t;
+}
+
+long Device::memcheck_verify() {
+  if (memcheck <= 0) return 0;
+  IPEPS_HIP(hipStreamSynchronize(stream));
+  const size_t G = MEMCHECK_GUARD;
+  long bad = 0;
+  std::vector<unsigned char> h;
+  for (const auto& kv : guarded) {
+    const char* raw = (const char*)kv.first;
+    const size_t user = kv.second.first, block = kv.second.second;
+    for (int tail = 0; tail < 2; ++tail) {
+      const size_t n = tail ? block - G - user : G;
+      h.resize(n);
+      IPEPS_HIP(hipMemcpy(h.data(), tail ? raw + G + user : raw, n,
+                          hipMemcpyDeviceToHost));
+      size_t first = n, last = 0, cnt = 0;
+      for (size_t i = 0; i < n; ++i)
+        if (h[i] != 0xa5) {
+          if (first == n) first = i;
+          last = i;
+          ++cnt;
+        }
+      if (!cnt) continue;
+      ++bad;
+      std::fprintf(stderr,
+                   "memcheck: tensor of %zu bytes at %p: %zu bytes changed "
+                   "%s it, the nearest %zu bytes away\n",
+                   user, (const void*)(raw + G), cnt,
+                   tail ? "after" : "before", tail ? first : G - 1 - last);
+    }
+  }
+  // the held blocks are verified: reusable again
+  for (const auto& hb : pool.take_held()) {
+    guarded.erase(hb.first);
+    pool.reissue(hb.first, hb.second);
+  }
+  return bad;
 }
 
 Tensor Device::empty_f32(std::vector<int64_t> shape) {
@@ -266,6 +354,17 @@ void Device::download(const Tensor& t, double* host) {
 }
 
 void Device::sync() { IPEPS_HIP(hipStreamSynchronize(stream)); }
+
+void prime_gemm_attributes();    // gemm.hip
+void prime_kernel_attributes();  // kernels.hip
+
+void prime_attributes() {
+  static std::once_flag once;
+  std::call_once(once, []() {
+    prime_gemm_attributes();
+    prime_kernel_attributes();
+  });
+}
 
 // ---------------------------------------------------------------- einsum
 namespace {

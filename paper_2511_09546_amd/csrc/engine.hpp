@@ -65,6 +65,14 @@ class Pool {
   void begin_arena(void* base, size_t bytes);
   void end_arena();
   size_t arena_peak() const { return arena_peak_; }
+  bool in_arena() const { return arena_ != nullptr; }
+  // Memory check mode (Device::memcheck): released blocks are held back
+  // instead of handed out again until take_held() passes them to the
+  // checker, which returns them with reissue()
+  void hold_released(bool on) { hold_ = on; }
+  size_t held_bytes() const { return held_bytes_; }
+  std::vector<std::pair<void*, size_t>> take_held();
+  void reissue(void* p, size_t block_bytes) { free_.emplace(block_bytes, p); }
 
  private:
   std::multimap<size_t, void*> free_;
@@ -76,7 +84,14 @@ class Pool {
   const char* arena_lo_ = nullptr;   // last region, for late releases
   const char* arena_hi_ = nullptr;
   std::multimap<size_t, void*> arena_free_;
+  bool hold_ = false;
+  size_t held_bytes_ = 0;
+  std::vector<std::pair<void*, size_t>> held_;
 };
+
+// Returns blocks of the idle list (those of destroyed contexts) to HIP,
+// largest first, until at most keep_bytes remain; returns the bytes left.
+size_t trim_idle_to(size_t keep_bytes);
 
 struct Buffer {
   void* p = nullptr;
@@ -168,11 +183,35 @@ struct Profiler {
 };
 
 // Execution context: one stream and one pool.
+// Memory check mode of the devices created while IPEPS_MEMCHECK is set in
+// the environment (0 or unset: off): 1 = every block carries guard bands
+// of MEMCHECK_GUARD bytes on both sides of the tensor, filled with a byte
+// pattern when the tensor is created, and released blocks are held back
+// from reuse until the next memcheck(), which verifies the bands of every
+// live and held block after the stream has drained (a kernel writing past
+// either end of its tensor changes them); 2 = also every new tensor is
+// filled with NaN, so that results that read memory no kernel wrote differ
+// from those of an unchecked run.
+int memcheck_mode();
+constexpr size_t MEMCHECK_GUARD = 16384;
+constexpr size_t MEMCHECK_HOLD = (size_t)8 << 30;
+
 struct Device {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   Pool pool;
   Profiler prof;
+  int memcheck = memcheck_mode();
+  // check mode: raw block -> (tensor bytes, block bytes) of every block
+  // handed out since its last verification
+  std::map<void*, std::pair<size_t, size_t>> guarded;
+  // verifies the guard bands (check mode; synchronises the stream),
+  // reports each damaged band on stderr, returns their number and lets
+  // the held blocks be reused.  It also runs by itself when the held
+  // blocks reach MEMCHECK_HOLD bytes; damage found then is counted in
+  // memcheck_pending.
+  long memcheck_verify();
+  long memcheck_pending = 0;
   int cprec = PREC_FP64;  // arithmetic of the GEMMs issued now
   // contractions may write a permuted output from the GEMM epilogue
   // (false: GEMM in its own order, then a permute pass); the count of the
@@ -252,6 +291,10 @@ void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
                    const std::vector<const double*>& B, int64_t ldb,
                    double beta, const std::vector<double*>& C, int64_t ldc,
                    const CMap* cm = nullptr);
+// Raises, once per process, the dynamic LDS limit of every kernel that
+// needs more than the default, before any context launches work (safe to
+// call from several threads; the first call does the work).
+void prime_attributes();
 // y[i] = (float) x[i]
 void to_f32(Device& dev, const double* x, float* y, int64_t n);
 // y[i] = (double) x[i]

@@ -1195,17 +1195,43 @@ void launch_small(Device& dev, const Call& c) {
   IPEPS_HIP(hipGetLastError());
 }
 
-// Raises a kernel's dynamic LDS limit to `bytes` once (contexts on several
-// host threads may get here together).
+// Raises a kernel's dynamic LDS limit to `bytes` once.  Every limit the
+// direct-load kernels need is raised by prime_gemm_attributes before the
+// first context exists, so that no attribute changes while other host
+// threads launch kernels (contexts of a serving loop); this is the fallback
+// for anything not primed.
+std::mutex g_lds_mu;
+std::map<const void*, size_t> g_lds_done;
 void allow_dyn_lds(const void* fn, size_t bytes) {
-  static std::mutex mu;
-  static std::map<const void*, size_t> done;
-  std::lock_guard<std::mutex> lock(mu);
-  size_t& have = done[fn];
+  std::lock_guard<std::mutex> lock(g_lds_mu);
+  size_t& have = g_lds_done[fn];
   if (bytes <= have) return;
   IPEPS_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)bytes));
   have = bytes;
+}
+
+template <typename TI, int BN, int WM, int WN>
+void prime_lds_kernels() {
+  constexpr size_t lb = lds_stage_bytes<TI>(BN);
+  allow_dyn_lds((const void*)gemm_f32_lds_kernel<TI, BN, WM, WN, false, false>,
+                lb);
+  allow_dyn_lds((const void*)gemm_f32_lds_kernel<TI, BN, WM, WN, true, false>,
+                lb);
+  allow_dyn_lds((const void*)gemm_f32_lds_kernel<TI, BN, WM, WN, false, true>,
+                lb);
+  allow_dyn_lds((const void*)gemm_f32_lds_kernel<TI, BN, WM, WN, true, true>,
+                lb);
+}
+
+template <typename TI>
+void prime_lds_all() {
+  prime_lds_kernels<TI, 48, 4, 1>();
+  prime_lds_kernels<TI, 64, 4, 1>();
+  prime_lds_kernels<TI, 80, 4, 1>();
+  prime_lds_kernels<TI, 96, 4, 1>();
+  prime_lds_kernels<TI, 128, 2, 2>();
+  prime_lds_kernels<TI, 144, 4, 1>();
 }
 
 // direct-load conditions: 16-byte aligned operands whose contiguous extent
@@ -1506,6 +1532,13 @@ void gemm_ptrs_a32(Device& dev, bool tA, bool tB, int64_t M, int64_t N,
     throw ArgError("gemm_ptrs_a32: FP32 operands need FP32 or BF16x3 products");
   gemm_ptrs_impl(dev, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
                  cm);
+}
+
+// the LDS limits of every direct-load GEMM instantiation the dispatcher
+// can pick (see allow_dyn_lds)
+void prime_gemm_attributes() {
+  prime_lds_all<double>();
+  prime_lds_all<float>();
 }
 
 }  // namespace ipeps

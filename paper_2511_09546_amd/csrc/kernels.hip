@@ -477,7 +477,10 @@ void col_scale(Device& dev, double* X, int64_t n, int b, const double* s,
 }
 
 // Raises a kernel's dynamic LDS limit to at least `bytes` (once per kernel
-// and size; contexts on several host threads may get here together).
+// and size; the largest sizes are raised by prime_kernel_attributes before
+// the first context exists, so that no attribute changes while other host
+// threads launch kernels; contexts on several host threads may get here
+// together).
 static void allow_lds(const void* fn, size_t bytes) {
   static std::mutex mu;
   static std::map<const void*, size_t> done;
@@ -2127,6 +2130,22 @@ void col_sign(Device& dev, const double* X, int64_t n, int b, double* s) {
   hipLaunchKernelGGL(col_sign_kernel, dim3((b + 3) / 4), dim3(256), 0,
                      dev.stream, X, n, b, s);
   IPEPS_HIP(hipGetLastError());
+}
+
+// the largest dynamic LDS each kernel here can ask for (see allow_lds)
+void prime_kernel_attributes() {
+  allow_lds((const void*)sym_eig_jacobi_kernel<true>,
+            jacobi_lds_bytes(96, true));
+  allow_lds((const void*)sym_eig_jacobi_kernel<false>,
+            jacobi_lds_bytes(JAC_MAXB, false));
+  {
+    const size_t h = JAC_BIGB / 2;
+    allow_lds((const void*)sym_eig_jacobi_big_kernel,
+              h * 5 * sizeof(double) + h * 2 * sizeof(int) +
+                  h * (h + 1) / 2 * sizeof(int));
+  }
+  allow_lds((const void*)chol_orth_kernel,
+            ((size_t)128 * 128 + 128) * sizeof(double));
 }
 
 }  // namespace ipeps

@@ -2,16 +2,20 @@
 
 Each request is one step of the method on its own state (CTMRG environment,
 energy and K-step gradient, preconditioned direction; Sec. III) and runs in
-its own library context on one of `workers` HIP streams (torch streams of
-the default priority, handed to ctm_init), so up to `workers` requests
-execute concurrently: requests that arrive while others run are admitted as
-soon as a stream and enough memory are free, and their kernels overlap on
-the device.  Admission follows the device-memory footprint that
-ipeps_footprint_bytes predicts for each request: a request starts only when
-its footprint fits the budget next to those already running and the cached
-environments (first come first served; later requests may start ahead of a
-waiting large one when they fit).  Contexts are freed when their request
-ends.
+its own library context in one of `workers` worker processes (started once,
+with the spawn method; each context on a stream of its own), so up to
+`workers` requests execute concurrently and their kernels overlap on the
+device, from separate processes: every process issues its launches from one
+host thread.  Requests that arrive while others run are admitted as soon as
+a worker and enough memory are free.  Admission follows the device-memory
+footprint that ipeps_footprint_bytes predicts for each request: a request
+starts only when its footprint fits the budget next to those already
+running and the cached environments (first come first served; later
+requests may start ahead of a waiting large one when they fit).  Contexts
+are freed when their request ends, and each worker then returns the memory
+its finished contexts left cached beyond a small reserve to HIP
+(ipeps_release_cache), so that the budget stays the only large holder.  A
+worker that dies fails its request only; it is started again for the next.
 
 Checkpointing: a request whose gradient with every unrolled iteration
 resident would take more than its share of the budget (budget / workers)
@@ -21,16 +25,21 @@ fixes grad_checkpoint itself.
 
 Warm starts: a request that carries a `state_key` seen before (same cell,
 D and chi) starts CTMRG from the environment that the earlier request left.
-Those environments stay resident in device memory (ipeps_get_env_dev /
-ipeps_set_env_dev into device buffers), count against the budget, and the
-least recently used ones are dropped when a waiting request needs the room.
-The environment depends only on the state, not on the Hamiltonian, so a
-sweep of couplings on one state converges in a few iterations after the
-first request.
+Those environments stay resident in device memory, in the worker process
+that computed them (ipeps_get_env_dev / ipeps_set_env_dev into device
+buffers of their own, hipMalloc); a request with a known key goes to that worker when it is free
+(elsewhere it starts cold and its environment replaces the old one).  They
+count against the budget, and the least recently used ones are dropped when
+a waiting request needs the room.  The environment depends only on the
+state, not on the Hamiltonian, so a sweep of couplings on one state
+converges in a few iterations after the first request.
 
-Every request records HIP events on its stream at the start and the end of
-its device work (`Result.window`, milliseconds after the server started), so
-the overlap of requests on the device can be measured.
+Every request records the host clock (CLOCK_MONOTONIC, common to all
+processes) right before its context is created and right after its last
+call returned (every library call waits for its stream), as
+`Result.window` in milliseconds after the server started: the interval
+holds all of the request's device work, so overlapping windows are
+requests whose work shared the device.
 
     python -m paper_2511_09546_amd.serve [--requests 256] [--rate 20]
         [--workers 8] [--prec fp32] [--budget-gb 230] [--seed 5]
@@ -39,15 +48,18 @@ the overlap of requests on the device can be measured.
 replays a seeded stream of requests (exponential inter-arrival times, D in
 3..6, chi in 2D^2..3D^2, J1-J2 with J2 in [0, 0.6], random states) in real
 time and prints one JSON line: latency percentiles (finish - arrival),
-throughput, the admission statistics, the device overlap, and how many of a
-sample of requests gave bitwise the results of the same request run alone.
+throughput, the admission statistics, the overlap of the request windows,
+and how many of a sample of requests gave bitwise the results of the same
+request run alone.
 """
 from __future__ import annotations
 
 import argparse
 import collections
 import concurrent.futures as cf
+import ctypes
 import json
+import multiprocessing
 import sys
 import threading
 import time
@@ -88,7 +100,7 @@ class Result:
     arrival: float
     start: float
     finish: float
-    window: tuple = (0.0, 0.0)    # device work, ms after the server start
+    window: tuple = (0.0, 0.0)    # device work within, ms after the start
 
     @property
     def latency(self) -> float:
@@ -123,6 +135,103 @@ def max_overlap(windows) -> int:
     return best
 
 
+# Device memory that a worker keeps cached after each request (of what its
+# finished contexts left, ipeps_release_cache): its next context allocates
+# from it first.
+WORKER_CACHE_BYTES = 2 << 30
+
+
+class _DeviceBuffer:
+    """Device memory of a worker's resident environment (hipMalloc /
+    hipFree of the HIP runtime the library uses; no caching allocator, so
+    a dropped environment goes straight back to HIP)."""
+    _hip = None
+
+    def __init__(self, nbytes: int):
+        if _DeviceBuffer._hip is None:
+            # the runtime libipeps.so is linked against (same soname)
+            try:
+                _DeviceBuffer._hip = ctypes.CDLL("libamdhip64.so.7")
+            except OSError:
+                _DeviceBuffer._hip = ctypes.CDLL("libamdhip64.so")
+            _DeviceBuffer._hip.hipMalloc.argtypes = [
+                ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+            _DeviceBuffer._hip.hipFree.argtypes = [ctypes.c_void_p]
+        p = ctypes.c_void_p()
+        st = _DeviceBuffer._hip.hipMalloc(ctypes.byref(p), nbytes)
+        if st != 0 or not p.value:
+            raise MemoryError(f"hipMalloc of {nbytes} bytes: status {st}")
+        self.ptr, self.nbytes = p.value, nbytes
+
+    def data_ptr(self) -> int:
+        return self.ptr
+
+    def free(self) -> None:
+        if self.ptr:
+            _DeviceBuffer._hip.hipFree(self.ptr)
+            self.ptr = 0
+
+
+def _worker_run(msg: dict, envs: dict) -> dict:
+    """One request inside a worker process (envs: the worker's resident
+    environments, state_key -> (shape key, device buffer))."""
+    o = binding.default_opts()
+    o.prec = msg["prec"]
+    o.grad_K = msg["grad_K"]
+    o.grad_checkpoint = msg["ckpt"]
+    skey, shape = msg["state_key"], msg["shape"]
+    warm, nbytes = False, 0
+    t0 = time.perf_counter()
+    with binding.Context(msg["A"], msg["chi"], opts=o) as ctx:
+        held = envs.get(skey) if skey is not None else None
+        if held is not None and held[0] == shape:
+            ctx.set_env_dev(held[1].data_ptr())
+            warm = True
+        it, dl, ok = ctx.converge(msg["tol"], msg["max_iter"])
+        if skey is not None:
+            old = envs.pop(skey, None)
+            if old is not None:
+                old[1].free()
+            buf = _DeviceBuffer(ctx.env_size() * 8)
+            envs[skey] = (shape, buf)
+            ctx.get_env_dev(buf.data_ptr())
+            nbytes = buf.nbytes
+        e, g = ctx.energy_grad(msg["terms"], grad=True)
+        x, cg_it, res, brk = ctx.precond(g, msg["delta"], msg["cg_tol"],
+                                         msg["cg_maxiter"])
+    t1 = time.perf_counter()
+    return dict(e=e, g=g, x=x, it=it, delta=dl, cg=cg_it, warm=warm, t0=t0,
+                t1=t1, env_bytes=nbytes)
+
+
+def _worker_main(conn) -> None:
+    """Worker process: requests in, ("ok", result) or ("err", message) out,
+    until None or the end of the pipe."""
+    binding.load()
+    envs: dict = {}
+    while True:
+        try:
+            msg = conn.recv()
+        except EOFError:
+            return
+        if msg is None:
+            return
+        for k in msg["drop"]:
+            held = envs.pop(k, None)
+            if held is not None:
+                held[1].free()
+        try:
+            out = ("ok", _worker_run(msg, envs))
+        except Exception as ex:  # delivered to the caller
+            out = ("err", f"{type(ex).__name__}: {ex}")
+        try:
+            binding.release_cache(WORKER_CACHE_BYTES)
+        except Exception as ex:
+            if out[0] == "ok":
+                out = ("err", f"{type(ex).__name__}: {ex}")
+        conn.send(out)
+
+
 class Server:
     """Footprint-admitted concurrent execution of Requests."""
 
@@ -134,16 +243,17 @@ class Server:
         self.running = 0
         self.queue = collections.deque()
         self.cv = threading.Condition()
-        # state_key -> (shape key, device buffer), least recently used first
+        # state_key -> (shape key, worker, bytes), least recently used first
         self.envs = collections.OrderedDict()
         self.env_bytes = 0.0
         self.pool = cf.ThreadPoolExecutor(max_workers=workers)
         self.closed = False
         self.peak_used = 0.0
         self.max_running = 0
-        self._streams = None           # created on the first device step
-        self._free_streams = list(range(workers))
-        self._ref = None
+        self._procs = [None] * workers   # (process, pipe end), on first use
+        self._drops = [[] for _ in range(workers)]  # keys to drop, per worker
+        self._free_slots = list(range(workers))
+        self._t0 = time.perf_counter()
         self.sched = threading.Thread(target=self._schedule, daemon=True)
         self.sched.start()
 
@@ -169,14 +279,56 @@ class Server:
             self.cv.notify_all()
         return fut
 
+    def start(self) -> None:
+        """Starts every worker process now (otherwise each on its first
+        request), so that their start-up is not part of request times."""
+        for i in range(self.workers):
+            self._worker(i)
+
+    def _worker(self, sidx: int):
+        """(process, pipe end) of worker sidx, started if needed (only the
+        thread that holds slot sidx calls this, or start() before any)."""
+        if self._procs[sidx] is None:
+            mp = multiprocessing.get_context("spawn")
+            here, there = mp.Pipe()
+            proc = mp.Process(target=_worker_main, args=(there,), daemon=True)
+            proc.start()
+            there.close()
+            self._procs[sidx] = (proc, here)
+        return self._procs[sidx]
+
+    def _lost_worker(self, sidx: int) -> int:
+        """Forgets worker sidx after it died and the environments it held;
+        returns its exit code."""
+        proc, conn = self._procs[sidx]
+        self._procs[sidx] = None
+        conn.close()
+        proc.join(timeout=10)
+        with self.cv:
+            for k in [k for k, v in self.envs.items() if v[1] == sidx]:
+                nbytes = self.envs.pop(k)[2]
+                self.env_bytes -= nbytes
+                self.used -= nbytes
+            self._drops[sidx] = []
+        return proc.exitcode
+
     def _evict_for(self, fp: float) -> bool:
         """Drop least recently used environments until fp fits (cv held)."""
         while self.envs and self.used + fp > self.budget:
-            _, (_, buf) = self.envs.popitem(last=False)
-            nbytes = float(buf.numel() * 8)
+            key, (_, sidx, nbytes) = self.envs.popitem(last=False)
+            self._drops[sidx].append(key)
             self.env_bytes -= nbytes
             self.used -= nbytes
         return self.used + fp <= self.budget
+
+    def _pick_slot(self, req: Request) -> int:
+        """A free worker, the one holding the request's environment when it
+        is free (cv held)."""
+        held = self.envs.get(req.state_key) if req.state_key else None
+        if held is not None and held[1] in self._free_slots:
+            self._free_slots.remove(held[1])
+            return held[1]
+        return self._free_slots.pop()
 
     def _schedule(self):
         while True:
@@ -204,7 +356,7 @@ class Server:
                 self.running += 1
                 self.peak_used = max(self.peak_used, self.used)
                 self.max_running = max(self.max_running, self.running)
-                sidx = self._free_streams.pop()
+                sidx = self._pick_slot(req)
             self.pool.submit(self._run, req, fp, fut, sidx)
 
     def _run(self, req: Request, fp: float, fut: cf.Future, sidx: int = 0):
@@ -218,75 +370,50 @@ class Server:
             with self.cv:
                 self.used -= fp
                 self.running -= 1
-                self._free_streams.append(sidx)
+                self._free_slots.append(sidx)
                 self.cv.notify_all()
 
-    def _device(self):
-        """The worker streams (default priority) and the reference event,
-        created once."""
-        import torch
-        with self.cv:
-            if self._streams is None:
-                self._streams = [torch.cuda.Stream()
-                                 for _ in range(self.workers)]
-                self._ref = torch.cuda.Event(enable_timing=True)
-                self._ref.record()
-                torch.cuda.synchronize()
-        return torch
-
     def _step(self, req: Request, start: float, sidx: int = 0) -> Result:
-        torch = self._device()
-        stream = self._streams[sidx]
+        proc, conn = self._worker(sidx)
         Lx, Ly, d, D = _shape(req.A)
-        o = binding.default_opts()
-        o.prec = req.prec
-        o.grad_K = req.grad_K
-        o.grad_checkpoint = self.checkpoint(req)
-        key = (Lx, Ly, d, D, req.chi)
-        warm = False
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        with binding.Context(req.A, req.chi, opts=o,
-                             stream=stream.cuda_stream) as ctx:
-            if req.state_key is not None:
-                with self.cv:
-                    cached = self.envs.get(req.state_key)
-                    if cached is not None:
-                        self.envs.move_to_end(req.state_key)
-                if cached is not None and cached[0] == key:
-                    ctx.set_env_dev(cached[1].data_ptr())
-                    warm = True
-            it, dl, ok = ctx.converge(req.tol, req.max_iter)
-            if req.state_key is not None:
-                self._keep_env(req.state_key, key, ctx, torch, stream)
-            e, g = ctx.energy_grad(req.terms, grad=True)
-            x, cg_it, res, brk = ctx.precond(g, req.delta, req.cg_tol,
-                                             req.cg_maxiter)
-            t1.record(stream)
-        t1.synchronize()
-        window = (self._ref.elapsed_time(t0), self._ref.elapsed_time(t1))
-        return Result(e=e, g=g, x=x, ctm_iters=it, delta=dl, cg_iters=cg_it,
-                      warm=warm, arrival=req.arrival, start=start,
-                      finish=time.perf_counter(), window=window)
-
-    def _keep_env(self, skey, key, ctx, torch, stream):
-        """Copy the context's environment into a resident device buffer of
-        the cache (counted against the budget)."""
-        n = ctx.env_size()
+        shape = (Lx, Ly, d, D, req.chi)
         with self.cv:
-            old = self.envs.pop(skey, None)
-            if old is not None:
-                self.env_bytes -= old[1].numel() * 8
-                self.used -= old[1].numel() * 8
-        with torch.cuda.stream(stream):
-            buf = torch.empty(n, dtype=torch.float64, device="cuda")
-        ctx.get_env_dev(buf.data_ptr())
-        with self.cv:
-            self.envs[skey] = (key, buf)
-            self.env_bytes += n * 8
-            self.used += n * 8
-            self.peak_used = max(self.peak_used, self.used)
+            drop, self._drops[sidx] = self._drops[sidx], []
+            if req.state_key in self.envs:
+                self.envs.move_to_end(req.state_key)
+        msg = dict(A=np.asarray(req.A), chi=req.chi, terms=req.terms,
+                   tol=req.tol, max_iter=req.max_iter, delta=req.delta,
+                   cg_tol=req.cg_tol, cg_maxiter=req.cg_maxiter,
+                   prec=req.prec, grad_K=req.grad_K,
+                   ckpt=self.checkpoint(req), state_key=req.state_key,
+                   shape=shape, drop=drop)
+        try:
+            conn.send(msg)
+            status, out = conn.recv()
+        except (EOFError, OSError) as ex:
+            code = self._lost_worker(sidx)
+            raise RuntimeError(f"worker {sidx} ended (exit code {code}) "
+                               "during the request") from ex
+        if status != "ok":
+            raise RuntimeError(out)
+        if req.state_key is not None:
+            with self.cv:
+                old = self.envs.pop(req.state_key, None)
+                if old is not None:
+                    self.env_bytes -= old[2]
+                    self.used -= old[2]
+                    if old[1] != sidx:
+                        self._drops[old[1]].append(req.state_key)
+                self.envs[req.state_key] = (shape, sidx, out["env_bytes"])
+                self.env_bytes += out["env_bytes"]
+                self.used += out["env_bytes"]
+                self.peak_used = max(self.peak_used, self.used)
+        ms = lambda t: (t - self._t0) * 1e3  # noqa: E731
+        return Result(e=out["e"], g=out["g"], x=out["x"], ctm_iters=out["it"],
+                      delta=out["delta"], cg_iters=out["cg"],
+                      warm=out["warm"], arrival=req.arrival, start=start,
+                      finish=time.perf_counter(),
+                      window=(ms(out["t0"]), ms(out["t1"])))
 
     def close(self):
         with self.cv:
@@ -294,6 +421,20 @@ class Server:
             self.cv.notify_all()
         self.sched.join()
         self.pool.shutdown(wait=True)
+        for i, w in enumerate(self._procs):
+            if w is None:
+                continue
+            proc, conn = w
+            try:
+                conn.send(None)
+            except OSError:
+                pass
+            proc.join(timeout=30)
+            if proc.is_alive():
+                proc.terminate()
+                proc.join(timeout=10)
+            conn.close()
+            self._procs[i] = None
 
 
 def request_stream(n: int, rate: float, seed: int, prec: int):
@@ -333,7 +474,13 @@ def replay(n: int, rate: float, seed: int, prec: int, workers: int,
            budget_gb: float, check_solo: int = 0, log=sys.stderr) -> dict:
     """Replays the seeded stream in real time; returns the record."""
     stream = request_stream(n, rate, seed, prec)
+    # device memory this process keeps cached (contexts it has freed,
+    # torch's allocator) goes back to HIP: the workers need it
+    binding.release_cache(0)
+    if "torch" in sys.modules:
+        sys.modules["torch"].cuda.empty_cache()
     srv = Server(budget_gb * 1e9, workers)
+    srv.start()
     n_ckpt = sum(srv.checkpoint(r) for _, r in stream)
     t0 = time.perf_counter()
     futs = []
@@ -371,7 +518,7 @@ def replay(n: int, rate: float, seed: int, prec: int, workers: int,
         "budget_gb": budget_gb,
         "peak_admitted_gb": srv.peak_used / 1e9,
         "max_concurrent": srv.max_running,
-        "max_concurrent_on_device": max_overlap(wins),
+        "max_concurrent_windows": max_overlap(wins),
         "device_busy_sum_over_makespan": busy / 1e3 / makespan,
         "checkpointed_requests": n_ckpt,
     }

@@ -1,7 +1,7 @@
-"""The request loop on the GPU: requests that run concurrently (own
-contexts, own streams) give exactly the results of the same requests run
-alone, and a warm start from a cached environment reaches the same fixed
-point in fewer iterations."""
+"""The request loop on the GPU: requests that run concurrently (worker
+processes, own contexts and streams) give exactly the results of the same
+requests run alone, and a warm start from a cached environment reaches the
+same fixed point in fewer iterations."""
 import numpy as np
 import pytest
 
@@ -40,8 +40,8 @@ def test_concurrent_equals_solo(prec, ckpt):
     res = [f.result(timeout=120) for f in futs]
     srv.close()
     assert srv.max_running >= 2
-    # the device-work windows (HIP events on the request streams) of at
-    # least two requests overlap in time
+    # the windows that hold the device work of the requests (host clock
+    # around their calls) overlap for at least two of them
     assert serve.max_overlap([r.window for r in res]) >= 2
     for r, out in zip(reqs, res):
         e, g, x, it = _solo(r)

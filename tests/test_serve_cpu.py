@@ -113,3 +113,62 @@ def test_max_overlap_of_windows():
     assert serve.max_overlap([(0, 2), (1, 3), (1.5, 1.8)]) == 3
     # touching windows do not overlap
     assert serve.max_overlap([(0, 1), (1, 2)]) == 1
+
+
+def test_worker_errors_reach_the_caller():
+    """A request that fails inside its worker process (here: no GPU, so
+    ctm_init fails; on a GPU machine: arguments the library rejects) fails its
+    future with the library's message; the worker keeps serving."""
+    srv = serve.Server(1e12, workers=1)
+    bad = _req(3, 18)
+    bad.chi = 0  # rejected by ctm_init before any device call
+    try:
+        for _ in range(2):
+            with pytest.raises(RuntimeError, match="ctm_init"):
+                srv.submit(bad).result(timeout=120)
+        assert srv._procs[0] is not None and srv._procs[0][0].is_alive()
+    finally:
+        srv.close()
+    assert srv._procs == [None]
+
+
+def test_dead_worker_fails_only_its_request():
+    """A worker that is gone when its request is sent fails that request
+    with the exit code; the slot starts a new worker for the next one."""
+    srv = serve.Server(1e12, workers=1)
+    bad = _req(3, 18)
+    bad.chi = 0
+    try:
+        srv.start()
+        proc = srv._procs[0][0]
+        proc.terminate()
+        proc.join(timeout=30)
+        with pytest.raises(RuntimeError, match="worker 0 ended"):
+            srv.submit(bad).result(timeout=120)
+        with pytest.raises(RuntimeError, match="ctm_init"):
+            srv.submit(bad).result(timeout=120)
+        assert srv._procs[0][0] is not proc and srv._procs[0][0].is_alive()
+    finally:
+        srv.close()
+
+
+def test_environment_routing_and_eviction():
+    """Scheduler bookkeeping of the resident environments: a request with a
+    known key goes to the worker that holds it when that worker is free,
+    eviction tells the holding worker to drop the key and returns the
+    bytes to the budget."""
+    srv = serve.Server(1e9, workers=3)
+    try:
+        with srv.cv:
+            srv.envs["k"] = ((1, 1, 2, 3, 18), 0, 4e8)
+            srv.env_bytes = srv.used = 4e8
+            r = _req(3, 18, key="k")
+            assert srv._pick_slot(r) == 0 and 0 not in srv._free_slots
+            # the holder is busy now: another worker, cold
+            assert srv._pick_slot(r) in (1, 2)
+            srv._free_slots = [0, 1, 2]
+            assert srv._evict_for(8e8)
+            assert srv._drops[0] == ["k"] and not srv.envs
+            assert srv.used == 0.0 and srv.env_bytes == 0.0
+    finally:
+        srv.close()
