@@ -24,7 +24,7 @@ arithmetics run different iteration counts: their floors differ).
 
 Further legs: `serving` replays the seeded request stream (Poisson arrivals
 at 20/s, D 3..6, chi 2D^2..3D^2; a prefix of --serve-requests requests) and
-reports p50/p99 latency, throughput, the device overlap of requests and how
+reports p50/p99 latency, throughput, the overlap of the request windows and how
 many of a sample gave bitwise the results of the same request run alone;
 `lbfgs` times iterations of the preconditioned L-BFGS on the same state;
 `preconditioners` times one application of every preconditioner at the

@@ -64,7 +64,9 @@ typedef enum {
  * inside the projector SVD and its adjoint).  Projector SVD (Gram matrices,
  * Jacobi, subspace rotations), SVD-adjoint algebra, normalisation,
  * convergence measure, energy traces and CG inner products are FP64 in every
- * mode.  Operands stay FP64 in memory in every mode.
+ * mode.  Inputs, outputs and the environment are FP64 in every mode; in the
+ * FP32 and BF16 modes the intermediates that only products read are kept
+ * in FP32.
  *   IPEPS_FP64  FP64 matrix cores;
  *   IPEPS_FP32  operands rounded to FP32, FP32 accumulation; ctm_converge
  *               raises tolerances below 1e-7 to 1e-7;

@@ -100,8 +100,18 @@ def test_bf16x3_step_against_golden(name):
     _step_against_golden(name, binding.BF16, BF16_REL)
 
 
-def _step_against_golden(name, prec, rel):
-    _say(f"prec {prec} step vs golden {name}")
+@pytest.mark.parametrize("name,prec", [("d2chi8", binding.BF16X1),
+                                       ("d4chi32", binding.BF16X1),
+                                       ("d4chi32", binding.BF16)])
+def test_ladder_steps_up_to_fp32(name, prec):
+    """BF16 -> FP32 ladder (ipeps_opts.ladder): the converge phase ends in
+    FP32 (the arithmetic the context reports for its next calls), and the
+    step then meets the FP32 bounds against the FP64 oracle."""
+    _step_against_golden(name, prec, 1e-4, ladder=1)
+
+
+def _step_against_golden(name, prec, rel, ladder=0):
+    _say(f"prec {prec} ladder {ladder} step vs golden {name}")
     gold = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
     w = inputs.WORKLOADS[name]
     A = inputs.workload_state(name)
@@ -110,8 +120,11 @@ def _step_against_golden(name, prec, rel):
     x_or = np.array(gold["x"]).reshape(A.shape)
     o = binding.default_opts()
     o.prec = prec
+    o.ladder = ladder
     with binding.Context(A, w["chi"], opts=o) as ctx:
         it, dl, ok = ctx.converge(w["tol"], w["n_iter"])
+        if ladder:
+            assert ctx.stats()["work_prec"] == binding.FP32
         e, g = ctx.energy_grad(terms, grad=True)
         x, cg_it, res, brk = ctx.precond(g, w["delta"], w["cg_tol"],
                                          w["cg_maxiter"])
