@@ -244,6 +244,7 @@ double energy_grad(Context& cx, const std::vector<TermSpec>& terms,
     ~DropCg() {
       c.have_cg_warm = false;
       c.cg_warm = Tensor();
+      c.defl_phi = Tensor();
     }
   } drop_cg{cx};
   if (cx.grad_mode == 0) {

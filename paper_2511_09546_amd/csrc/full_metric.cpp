@@ -88,6 +88,7 @@ double log_kappa_grad(Context& cx, const double* Ak, double* gbra) {
       c.have_warm = h;
       c.have_cg_warm = false;
       c.cg_warm = Tensor();
+      c.defl_phi = Tensor();
     }
   } restore{cx, cx.Xwarm, cx.have_warm};
   cx.have_cg_warm = false;

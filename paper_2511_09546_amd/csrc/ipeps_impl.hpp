@@ -170,6 +170,9 @@ struct Context {
   // ([ncut][2][n][chi]), the start of the next one within one gradient
   Tensor cg_warm;
   bool have_cg_warm = false;
+  // eigenbasis of the deflation Galerkin matrix of that solve (used, like
+  // cg_warm, only within one gradient)
+  Tensor defl_phi;
   Tensor spec_cur, spec_old;  // [4*nsite][chi]
 
   int device = 0;        // HIP device of the context (current at ctm_init)

@@ -346,9 +346,29 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
       Tensor K = dev.empty({nc, m2, m2}), Phi = dev.empty({nc, m2, m2});
       lamK = dev.empty({nc, m2});
       defl_build_k(dev, Bk.ptr, Bk.ptr + nc * m * m, m, K.ptr, nc);
-      sym_eig_jacobi(dev, K.ptr, Phi.ptr, lamK.ptr, m2, nc);
-      Xi = dev.empty({nc, 2 * n, m4});
       const int64_t sPhi = (int64_t)m2 * m2;
+      if (cxp->have_cg_warm && cxp->defl_phi.numel() == nc * sPhi) {
+        // within one gradient the solves of consecutive unrolled
+        // iterations see nearly the same K: in the eigenbasis Phi0 of the
+        // previous solve's K, Phi0^T K Phi0 is nearly diagonal, and the
+        // Jacobi solve finishes it in a sweep or two instead of the eight
+        // or nine that the zero diagonal blocks of K itself take; Phi =
+        // Phi0 Phi' is an eigenbasis of K to the same accuracy
+        const double* P0 = cxp->defl_phi.ptr;
+        Tensor KP = dev.empty({nc, m2, m2}), Kr = dev.empty({nc, m2, m2});
+        Tensor Pr = dev.empty({nc, m2, m2});
+        gemm(dev, false, false, m2, m2, m2, 1.0, K.ptr, m2, sPhi, P0, m2,
+             sPhi, 0.0, KP.ptr, m2, sPhi, nc);
+        gemm(dev, true, false, m2, m2, m2, 1.0, P0, m2, sPhi, KP.ptr, m2,
+             sPhi, 0.0, Kr.ptr, m2, sPhi, nc);
+        sym_eig_jacobi(dev, Kr.ptr, Pr.ptr, lamK.ptr, m2, nc);
+        gemm(dev, false, false, m2, m2, m2, 1.0, P0, m2, sPhi, Pr.ptr, m2,
+             sPhi, 0.0, Phi.ptr, m2, sPhi, nc);
+      } else {
+        sym_eig_jacobi(dev, K.ptr, Phi.ptr, lamK.ptr, m2, nc);
+      }
+      cxp->defl_phi = Phi;
+      Xi = dev.empty({nc, 2 * n, m4});
       const double* Phu = Phi.ptr;
       const double* Phv = Phi.ptr + (int64_t)m * m2;
       gemm(dev, false, false, n, m2, m, 1.0, Wu, m, sNm, Phu, m2, sPhi, 0.0,
