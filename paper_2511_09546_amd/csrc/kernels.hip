@@ -517,11 +517,11 @@ static void allow_lds(const void* fn, size_t bytes) {
 // output buffer in global memory.  Every thread's blocks and (pair, k)
 // items are fixed for the whole solve and are computed once, into
 // registers.
-constexpr int JAC_THREADS = 512;
+constexpr int JAC_THREADS = 1024;
 constexpr int JAC_MAXB = 128;
 // most blocks and (pair, k) items of one thread at b = JAC_MAXB
-constexpr int JAC_GBLK = (64 * 65 / 2 + JAC_THREADS - 1) / JAC_THREADS;  // 5
-constexpr int JAC_VITEM = (64 * 128 + JAC_THREADS - 1) / JAC_THREADS;    // 16
+constexpr int JAC_GBLK = (64 * 65 / 2 + JAC_THREADS - 1) / JAC_THREADS;  // 3
+constexpr int JAC_VITEM = (64 * 128 + JAC_THREADS - 1) / JAC_THREADS;    // 8
 
 size_t jacobi_lds_bytes(int b, bool vlds) {
   const size_t h = b / 2;
