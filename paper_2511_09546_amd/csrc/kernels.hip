@@ -913,28 +913,33 @@ __global__ __launch_bounds__(256) void chol_orth_kernel(
     const double* __restrict__ Gall, double* __restrict__ Rall, int b,
     double* __restrict__ glob) {
   extern __shared__ double lds[];
-  double* G = glob ? glob + (long)blockIdx.x * b * b : lds;  // b*b
-  double* dg = glob ? lds : G + b * b;  // b: pivots
+  // row stride b + 1 in LDS: a column (fixed k, consecutive rows), which
+  // the trailing update and the triangular inverse read across the lanes,
+  // then spreads over the banks instead of hitting one bank (stride b = 96
+  // doubles is a multiple of the bank count)
+  const int S = glob ? b : b + 1;
+  double* G = glob ? glob + (long)blockIdx.x * b * b : lds;  // b*S
+  double* dg = glob ? lds : G + b * S;  // b: pivots
   const int bt = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
   const double* Gg = Gall + (long)bt * b * b;
   double* R = Rall + (long)bt * b * b;
-  for (int i = tid; i < b * b; i += nt) G[i] = Gg[i];
+  for (int e = tid; e < b * b; e += nt) G[(e / b) * S + e % b] = Gg[e];
   __syncthreads();
   for (int k = 0; k < b; ++k) {
     if (tid == 0) {
-      const double d = G[k * b + k];
+      const double d = G[k * S + k];
       dg[k] = d > 1e-12 ? sqrt(d) : 0.0;
     }
     __syncthreads();
     const double p = dg[k];
     for (int i = k + 1 + tid; i < b; i += nt)
-      G[i * b + k] = p > 0.0 ? G[i * b + k] / p : 0.0;
+      G[i * S + k] = p > 0.0 ? G[i * S + k] / p : 0.0;
     __syncthreads();
     // trailing lower triangle: G[i][j] -= L[i][k] L[j][k], k < j <= i
     const int m = b - k - 1;
     for (int e = tid; e < m * m; e += nt) {
       const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j <= i) G[i * b + j] -= G[i * b + k] * G[j * b + k];
+      if (j <= i) G[i * S + j] -= G[i * S + k] * G[j * S + k];
     }
     __syncthreads();
   }
@@ -944,16 +949,16 @@ __global__ __launch_bounds__(256) void chol_orth_kernel(
   for (int j = tid; j < b; j += nt) {
     for (int i = j; i < b; ++i) {
       double acc = (i == j) ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) acc -= G[i * b + k] * G[j * b + k];
+      for (int k = j; k < i; ++k) acc -= G[i * S + k] * G[j * S + k];
       const double y = dg[i] > 0.0 ? acc / dg[i] : 0.0;
-      G[j * b + i] = y;
+      G[j * S + i] = y;
     }
   }
   __syncthreads();
   // R = L^-T: R[j][i] = Y[i][j] for i >= j, else 0
   for (int e = tid; e < b * b; e += nt) {
     const int j = e / b, i = e % b;
-    R[e] = i >= j ? G[j * b + i] : 0.0;
+    R[e] = i >= j ? G[j * S + i] : 0.0;
   }
 }
 
@@ -961,7 +966,7 @@ void chol_orth_factor(Device& dev, const double* G, double* R, int b,
                       int batch) {
   if (b < 1 || b > 512) throw ArgError("chol_orth_factor: b must be <= 512");
   Tensor w;
-  size_t lds = ((size_t)b * b + b) * sizeof(double);
+  size_t lds = ((size_t)b * (b + 1) + b) * sizeof(double);
   if (b > 128) {
     w = dev.empty({batch, b, b});
     lds = (size_t)b * sizeof(double);
@@ -2145,7 +2150,7 @@ void prime_kernel_attributes() {
                   h * (h + 1) / 2 * sizeof(int));
   }
   allow_lds((const void*)chol_orth_kernel,
-            ((size_t)128 * 128 + 128) * sizeof(double));
+            ((size_t)128 * 129 + 128) * sizeof(double));
 }
 
 }  // namespace ipeps
