@@ -658,25 +658,52 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_lds_kernel(
 }
 
 // part layout [S][batch][M][N] (FP64, or FP32 for FP32 accumulators);
-// C[b] = alpha sum_s part[s][b] + beta C[b], summed in FP64 in the order of s
-template <typename PT>
-__global__ void splitk_sum_kernel(const PT* __restrict__ part, int S,
-                                  int batch, long M, long N, double alpha,
-                                  double beta, double* __restrict__ C,
-                                  long ldc, long sC, int use_ptrs,
-                                  PtrArgs ptrs, CMap cm) {
-  const long mn = M * N, tot = mn * batch;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
-       e += (long)gridDim.x * blockDim.x) {
-    const long b = e / mn, i = e % mn;
-    double v = 0.0;
-#pragma unroll 8
-    for (int s = 0; s < S; ++s)
-      v += (double)part[((long)s * batch + b) * mn + i];
-    const long r = i / N, c = i % N;
-    double* base = use_ptrs ? ptrs.c[b] : cbase(C, b, sC, cm.c32);
-    const long off = cmap_row(cm, (int)r, ldc) + cmap_col(cm, (int)c);
-    double o = alpha * v;
+// C[b] = alpha sum_s part[s][b] + beta C[b], summed in FP64 in the order of
+// s.  Grid (element groups, batch entry): each thread sums V consecutive
+// elements of one row (V = 4 when N is a multiple of 4, then every split's
+// four partial sums are one 16-byte load, or two), so the batch entry, row
+// and column are found once per thread, not per element.
+template <typename PT, int V>
+__global__ __launch_bounds__(256) void splitk_sum_kernel(
+    const PT* __restrict__ part, int S, int M, int N, double alpha,
+    double beta, double* __restrict__ C, long ldc, long sC, int use_ptrs,
+    PtrArgs ptrs, CMap cm) {
+  const int b = blockIdx.y;
+  const long mn = (long)M * N;
+  const long i0 = ((long)blockIdx.x * blockDim.x + threadIdx.x) * V;
+  if (i0 >= mn) return;
+  const long sstride = (long)gridDim.y * mn;
+  const PT* p = part + (long)b * mn + i0;
+  double v[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) v[q] = 0.0;
+#pragma unroll 4
+  for (int s = 0; s < S; ++s) {
+    const PT* ps = p + (long)s * sstride;
+    if constexpr (V == 4 && sizeof(PT) == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(ps);
+      v[0] += (double)t.x;
+      v[1] += (double)t.y;
+      v[2] += (double)t.z;
+      v[3] += (double)t.w;
+    } else if constexpr (V == 4) {
+      const double2 t0 = *reinterpret_cast<const double2*>(ps);
+      const double2 t1 = *reinterpret_cast<const double2*>(ps + 2);
+      v[0] += t0.x;
+      v[1] += t0.y;
+      v[2] += t1.x;
+      v[3] += t1.y;
+    } else {
+      v[0] += (double)ps[0];
+    }
+  }
+  const int r = (int)(i0 / N), c0 = (int)(i0 - (long)r * N);
+  double* base = use_ptrs ? ptrs.c[b] : cbase(C, b, sC, cm.c32);
+  const long roff = cmap_row(cm, r, ldc);
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const long off = roff + cmap_col(cm, c0 + q);
+    double o = alpha * v[q];
     if (beta != 0.0) o += beta * cload(base, off, cm.c32);
     cstore(base, off, o, cm.c32);
   }
@@ -901,6 +928,29 @@ struct Call {
   CMap cm{};            // layout of C (nr == 0: row major, ldc)
 };
 
+// The split-K reduction of a product (partial sums in part, S splits).
+template <typename PT>
+void launch_splitk_sum(Device& dev, const void* part, int S, const Call& c) {
+  PtrArgs pa{};
+  if (c.ptrs) pa = *c.ptrs;
+  const long mn = (long)c.M * c.N;
+  const bool v4 = c.N % 4 == 0;
+  const long groups = v4 ? mn / 4 : mn;
+  const long gx = (groups + 255) / 256;
+  if (gx >= (1L << 31) || c.batch > 65535)
+    throw ArgError("gemm: reduction grid too large");
+  const dim3 grid((unsigned)gx, (unsigned)c.batch);
+  if (v4)
+    hipLaunchKernelGGL((splitk_sum_kernel<PT, 4>), grid, dim3(256), 0,
+                       dev.stream, (const PT*)part, S, c.M, c.N, c.alpha,
+                       c.beta, c.C, c.ldc, c.sC, c.ptrs ? 1 : 0, pa, c.cm);
+  else
+    hipLaunchKernelGGL((splitk_sum_kernel<PT, 1>), grid, dim3(256), 0,
+                       dev.stream, (const PT*)part, S, c.M, c.N, c.alpha,
+                       c.beta, c.C, c.ldc, c.sC, c.ptrs ? 1 : 0, pa, c.cm);
+  IPEPS_HIP(hipGetLastError());
+}
+
 // BF16x3 product through split planes (see split_bf16_kernel): chosen when
 // both operands are read by at least four tiles and the batch fits one
 // pointer set
@@ -999,16 +1049,7 @@ void launch_presplit(Device& dev, const Call& c) {
                      kchunk, part.ptr, c.ptrs ? 1 : 0, pa, c.cm);
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
-  if (S > 1) {
-    const long tot = (long)c.batch * c.M * c.N;
-    const int g = (int)std::max<long>(1, std::min<long>((tot + 255) / 256,
-                                                        8192));
-    hipLaunchKernelGGL(splitk_sum_kernel<float>, dim3(g), dim3(256), 0,
-                       dev.stream, (const float*)part.ptr, S, c.batch,
-                       (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
-                       c.sC, c.ptrs ? 1 : 0, pa, c.cm);
-    IPEPS_HIP(hipGetLastError());
-  }
+  if (S > 1) launch_splitk_sum<float>(dev, part.ptr, S, c);
 }
 
 // Split of K for a grid of tb tiles (BM x BN each; mn_batch outputs in
@@ -1354,20 +1395,10 @@ void launch_cfg(Device& dev, const Call& c) {
   if (dev.prof.on) dev.prof.end(dev.stream);
   IPEPS_HIP(hipGetLastError());
   if (S > 1) {
-    const long tot = (long)c.batch * c.M * c.N;
-    const int g = (int)std::max<long>(1, std::min<long>((tot + 255) / 256,
-                                                        8192));
     if constexpr (P == 0)
-      hipLaunchKernelGGL(splitk_sum_kernel<double>, dim3(g), dim3(256), 0,
-                         dev.stream, (const double*)part.ptr, S, c.batch,
-                         (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
-                         c.sC, up, pa, c.cm);
+      launch_splitk_sum<double>(dev, part.ptr, S, c);
     else
-      hipLaunchKernelGGL(splitk_sum_kernel<float>, dim3(g), dim3(256), 0,
-                         dev.stream, (const float*)part.ptr, S, c.batch,
-                         (long)c.M, (long)c.N, c.alpha, c.beta, c.C, c.ldc,
-                         c.sC, up, pa, c.cm);
-    IPEPS_HIP(hipGetLastError());
+      launch_splitk_sum<float>(dev, part.ptr, S, c);
   }
 }
 
