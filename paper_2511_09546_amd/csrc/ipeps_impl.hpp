@@ -170,9 +170,12 @@ struct Context {
   // ([ncut][2][n][chi]), the start of the next one within one gradient
   Tensor cg_warm;
   bool have_cg_warm = false;
-  // eigenbasis of the deflation Galerkin matrix of that solve (used, like
-  // cg_warm, only within one gradient)
+  // eigenbasis of the deflation Galerkin matrix of that solve, and the
+  // squared right-hand-side norms of the gradient's first solve over K^2
+  // (the residual scale of the later solves); used, like cg_warm, only
+  // within one gradient
   Tensor defl_phi;
+  std::vector<double> cg_ref;
   Tensor spec_cur, spec_old;  // [4*nsite][chi]
 
   int device = 0;        // HIP device of the context (current at ctm_init)

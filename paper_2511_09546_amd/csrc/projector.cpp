@@ -468,17 +468,40 @@ std::pair<std::vector<Var>, std::vector<Var>> projector_op(
     double* rrb[2] = {rr, rrn};
     int cur = 0;
     Tensor part = dev.empty({nc, colcg_parts(), chi});
+    // Residual scale.  The first solve of a gradient belongs to the
+    // unrolled iteration next to the energy, whose cotangent is the
+    // largest; the cotangents reaching earlier iterations shrink by the
+    // contraction factor of the CTMRG map per iteration, and so do the
+    // right-hand sides of their solves.  Each later solve of the same
+    // gradient stops at tol times the larger of its own right-hand side and
+    // 1/K of the first one's (per cut and column): the error it leaves in
+    // the gradient is then at most tol |rhs_first| / K, and the K solves
+    // together at most about what the first one leaves, while the solves
+    // of the iterations far from the energy end after few iterations or
+    // none.
+    const size_t ncol = (size_t)nc * chi;
+    const bool use_ref = cxp->have_cg_warm && cxp->cg_ref.size() == ncol;
+    bool set_ref = !cxp->have_cg_warm;
     auto converged = [&](bool stagnation) {
       dev.download(sc, h.data());
       bool done = true;
       double worst = 0.0;
       const double* hr = h.data() + (rrb[cur] - sc.ptr);  // rr
       const double* h0 = h.data() + 4 * nc * chi;  // rr0
-      for (int j = 0; j < nc * chi; ++j)
-        if (h0[j] > 0.0) {
-          worst = std::max(worst, hr[j] / h0[j]);
-          if (hr[j] > tol2 * h0[j]) done = false;
+      if (set_ref) {
+        const double kk = (double)std::max(1, cxp->grad_K);
+        const double k2 = kk * kk;
+        cxp->cg_ref.assign(h0, h0 + ncol);
+        for (double& v : cxp->cg_ref) v /= k2;
+        set_ref = false;
+      }
+      for (size_t j = 0; j < ncol; ++j) {
+        const double den = use_ref ? std::max(h0[j], cxp->cg_ref[j]) : h0[j];
+        if (den > 0.0) {
+          worst = std::max(worst, hr[j] / den);
+          if (hr[j] > tol2 * den) done = false;
         }
+      }
       if (stagnation && lowp && worst > 0.5 * prev_worst) done = true;
       prev_worst = worst;
       return done;
