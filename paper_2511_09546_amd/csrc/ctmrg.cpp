@@ -294,8 +294,35 @@ void corner_spectra(Context& cx, const Env& e, Tensor& S) {
     W = dev.zeros({nb, chi, b});
     pad3(dev, e.C.ptr, W.ptr, nb, chi, chi, chi, b);
   }
+  // Warm start: the singular values of W J are those of W for any
+  // orthogonal J, and with J the right singular vectors of the previous
+  // call's corners (which change little from one CTMRG iteration to the
+  // next) the Gram matrices of the two Jacobi passes are nearly diagonal
+  // already.  The rotation is the product of the calls' Jacobi rotations;
+  // every 64 calls the solve starts cold, so that its rounding stays at
+  // the level of a few products.
+  const int64_t sW = (int64_t)chi * b, sJ = (int64_t)b * b;
+  const bool warm = cx.spec_J.numel() == nb * sJ && cx.spec_J_age < 64;
+  Tensor Wr = W;
+  if (warm) {
+    PrecScope f64(dev, PREC_FP64);
+    Wr = dev.empty({nb, chi, b});
+    gemm(dev, false, false, chi, b, b, 1.0, W.ptr, b, sW, cx.spec_J.ptr, b,
+         sJ, 0.0, Wr.ptr, b, sW, nb);
+  }
   Tensor U, J;
-  svd_ts(dev, W, nb, chi, b, U, S, J, dev.cprec == PREC_FP64 ? 1e-15 : 1e-12);
+  svd_ts(dev, Wr, nb, chi, b, U, S, J, dev.cprec == PREC_FP64 ? 1e-15 : 1e-12);
+  if (warm) {
+    PrecScope f64(dev, PREC_FP64);
+    Tensor Jn = dev.empty({nb, b, b});
+    gemm(dev, false, false, b, b, b, 1.0, cx.spec_J.ptr, b, sJ, J.ptr, b, sJ,
+         0.0, Jn.ptr, b, sJ, nb);
+    cx.spec_J = Jn;
+    ++cx.spec_J_age;
+  } else {
+    cx.spec_J = J;
+    cx.spec_J_age = 0;
+  }
 }
 
 int converge_env(Context& cx, double tol, int max_iter, int* n_iter,

@@ -177,6 +177,10 @@ struct Context {
   Tensor defl_phi;
   std::vector<double> cg_ref;
   Tensor spec_cur, spec_old;  // [4*nsite][chi]
+  // right singular vectors of the corners at the last spectrum (the warm
+  // start of the next one) and the calls since the last cold start
+  Tensor spec_J;
+  int spec_J_age = 0;
 
   int device = 0;        // HIP device of the context (current at ctm_init)
 
