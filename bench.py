@@ -26,6 +26,9 @@ Further legs: `serving` replays the seeded request stream (Poisson arrivals
 at 20/s, D 3..6, chi 2D^2..3D^2; a prefix of --serve-requests requests) and
 reports p50/p99 latency, throughput, the overlap of the request windows and how
 many of a sample gave bitwise the results of the same request run alone;
+`serving_sweep` replays a coupling sweep (8 states x 6 values of J2, one
+state_key per state) and reports the same with the warm-start counts and
+the CTMRG iterations of cold and warm requests;
 `lbfgs` times iterations of the preconditioned L-BFGS on the same state;
 `preconditioners` times one application of every preconditioner at the
 converged state (local metric by CG and by GMRES(30), belief propagation,
@@ -47,7 +50,8 @@ bounded sample of the same workload (one CTMRG iteration, the energy network
 with its backward, one unrolled iteration with its backward, one CG solve)
 and composes one step from those phases; the wall time of the whole cold
 oracle step that wrote the stored values (tests/golden) is reported beside
-it.
+it, and so are one-core oracle times of the two small workloads (the whole
+cold step of D=2, chi=8; a composed cold step of D=4, chi=32).
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--prec fp32]
                     [--no-fp64] [--no-cpu-baseline] [--checkpoint]
@@ -113,7 +117,61 @@ def cpu_baseline(name, n_conv):
         # where they were written (not this host)
         g = json.load(open(gold))
         out["stored_cold_step_seconds"] = g.get("total_seconds")
+    out["one_core_small"] = cpu_small_one_core()
     return out
+
+
+def cpu_small_one_core():
+    """The oracle on one host thread at the two small workloads: the whole
+    cold step of d2chi8 (D=2, chi=8: its stored settings), and for d4chi32
+    (D=4, chi=32) one CTMRG iteration, the energy network with its backward
+    and one unrolled iteration with its backward, composed like the main
+    sample into a cold step of its stored iteration count (seconds)."""
+    import torch
+    from oracle import ctmrg, gradient, metric, step
+    from paper_2511_09546_amd import inputs
+    keep = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        w = inputs.WORKLOADS["d2chi8"]
+        A = inputs.workload_state("d2chi8")
+        terms = inputs.workload_terms("d2chi8")
+        t0 = time.perf_counter()
+        step.run_step(A, terms, w["chi"], w["tol"], w["n_iter"], w["grad_K"],
+                      w["delta"], w["cg_tol"], w["cg_maxiter"])
+        t_small = time.perf_counter() - t0
+        w = inputs.WORKLOADS["d4chi32"]
+        A = inputs.workload_state("d4chi32")
+        terms = inputs.workload_terms("d4chi32")
+        t0 = time.perf_counter()
+        env, _, _ = ctmrg.converge(A, w["chi"], 0.0, 1)
+        t1 = time.perf_counter()
+        gradient.grad_K(A, terms, env, w["chi"], 0)
+        t2 = time.perf_counter()
+        _, g = gradient.grad_K(A, terms, env, w["chi"], 1)
+        t3 = time.perf_counter()
+        metric.precondition(env, A, g.numpy(), w["delta"], 0.0,
+                            w["cg_maxiter"])
+        t4 = time.perf_counter()
+        gold = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                           "d4chi32.json")))
+        n_conv = int(gold["n_iter"])
+        t_adj = max((t3 - t2) - (t2 - t1), 0.0)
+        t_mid = (n_conv * (t1 - t0) + (t2 - t1) + w["grad_K"] * t_adj +
+                 (t4 - t3))
+    finally:
+        torch.set_num_threads(keep)
+    return {"cores": 1,
+            "d2chi8_cold_step_s": t_small,
+            "d4chi32_cold_step_s": t_mid,
+            "d4chi32_sample": (f"1 CTMRG iteration {t1 - t0:.2f} s, energy "
+                               f"network + backward {t2 - t1:.2f} s, 1 "
+                               f"unrolled iteration + backward "
+                               f"{t3 - t2:.2f} - {t2 - t1:.2f} s, CG "
+                               f"{t4 - t3:.3f} s; {n_conv} iterations + "
+                               f"energy + K={w['grad_K']} unrolled "
+                               f"iterations + CG"),
+            "sample_seconds": t_small + (t4 - t0)}
 
 
 def measured_traffic(prec):
@@ -509,6 +567,10 @@ def main():
         out["serving"] = serve.replay(args.serve_requests, 20.0, 5,
                                       binding.FP32, 8, 230.0, check_solo=16)
         out["serving"]["prefix_of"] = 256
+        # the warm-start variant: 8 states x 6 couplings, one state_key
+        # per state
+        out["serving_sweep"] = serve.replay(0, 20.0, 7, binding.FP32, 8,
+                                            230.0, sweep=(8, 6))
     if not args.no_lbfgs:
         out["lbfgs"] = lbfgs_leg(name, args.prec, 3)
     if not args.no_precond:

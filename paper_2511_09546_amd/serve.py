@@ -24,7 +24,9 @@ iteration resident, recomputed in the backward pass), unless the request
 fixes grad_checkpoint itself.
 
 Warm starts: a request that carries a `state_key` seen before (same cell,
-D and chi) starts CTMRG from the environment that the earlier request left.
+D and chi) starts CTMRG from the environment that the earlier request left;
+while a request of that key runs, later ones of the key wait for it
+(others go ahead), so that they can start from its environment.
 Those environments stay resident in device memory, in the worker process
 that computed them (ipeps_get_env_dev / ipeps_set_env_dev into device
 buffers of their own, hipMalloc); a request with a known key goes to that worker when it is free
@@ -43,7 +45,7 @@ requests whose work shared the device.
 
     python -m paper_2511_09546_amd.serve [--requests 256] [--rate 20]
         [--workers 8] [--prec fp32] [--budget-gb 230] [--seed 5]
-        [--check-solo 16]
+        [--check-solo 16] [--sweep STATES COUPLINGS]
 
 replays a seeded stream of requests (exponential inter-arrival times, D in
 3..6, chi in 2D^2..3D^2, J1-J2 with J2 in [0, 0.6], random states) in real
@@ -253,6 +255,7 @@ class Server:
         self._procs = [None] * workers   # (process, pipe end), on first use
         self._drops = [[] for _ in range(workers)]  # keys to drop, per worker
         self._free_slots = list(range(workers))
+        self._running_keys = set()     # state_keys of running requests
         self._t0 = time.perf_counter()
         self.sched = threading.Thread(target=self._schedule, daemon=True)
         self.sched.start()
@@ -339,6 +342,10 @@ class Server:
                     pick = None
                     if self.running < self.workers:
                         for i, (req, fp, fut) in enumerate(self.queue):
+                            # a request whose state is being computed waits
+                            # for it, to start from its environment
+                            if req.state_key in self._running_keys:
+                                continue
                             if self.used + fp <= self.budget:
                                 pick = i
                                 break
@@ -352,6 +359,8 @@ class Server:
                     self.cv.wait()
                 req, fp, fut = self.queue[pick]
                 del self.queue[pick]
+                if req.state_key is not None:
+                    self._running_keys.add(req.state_key)
                 self.used += fp
                 self.running += 1
                 self.peak_used = max(self.peak_used, self.used)
@@ -371,6 +380,7 @@ class Server:
                 self.used -= fp
                 self.running -= 1
                 self._free_slots.append(sidx)
+                self._running_keys.discard(req.state_key)
                 self.cv.notify_all()
 
     def _step(self, req: Request, start: float, sidx: int = 0) -> Result:
@@ -470,10 +480,45 @@ def solo(req: Request, ckpt: int):
     return e, g, x, it
 
 
+def sweep_stream(n_states: int, n_couplings: int, rate: float, seed: int,
+                 prec: int):
+    """(offset seconds, Request) of a coupling sweep: n_states random states
+    (D uniform in 3..6, chi uniform in 2D^2..3D^2, state seed 6000 + s),
+    each at n_couplings values of J2 evenly spaced in [0, 0.6], all requests
+    of one state with one state_key (so that every one after the first can
+    start from the environment the previous one left); the couplings go
+    round robin over the states, with exponential inter-arrivals of mean
+    1/rate."""
+    from . import inputs
+    rng = np.random.default_rng(seed)
+    states = []
+    for st in range(n_states):
+        D = int(rng.integers(3, 7))
+        chi = int(rng.integers(2 * D * D, 3 * D * D + 1))
+        states.append((D, chi, inputs.random_state(6000 + st, 1, 1, 2, D)))
+    t = 0.0
+    out = []
+    for c in range(n_couplings):
+        J2 = 0.6 * c / max(n_couplings - 1, 1)
+        for st, (D, chi, A) in enumerate(states):
+            t += rng.exponential(1.0 / rate)
+            out.append((t, Request(A=A, chi=chi,
+                                   terms=inputs.terms_j1j2(1, 1, 1.0, J2),
+                                   prec=prec, state_key=f"sweep{seed}-{st}")))
+    return out
+
+
 def replay(n: int, rate: float, seed: int, prec: int, workers: int,
-           budget_gb: float, check_solo: int = 0, log=sys.stderr) -> dict:
-    """Replays the seeded stream in real time; returns the record."""
-    stream = request_stream(n, rate, seed, prec)
+           budget_gb: float, check_solo: int = 0, log=sys.stderr,
+           sweep=None) -> dict:
+    """Replays the seeded stream in real time (or, with sweep = (states,
+    couplings), the coupling sweep of sweep_stream; n is then ignored);
+    returns the record."""
+    if sweep is not None:
+        stream = sweep_stream(sweep[0], sweep[1], rate, seed, prec)
+        n = len(stream)
+    else:
+        stream = request_stream(n, rate, seed, prec)
     # device memory this process keeps cached (contexts it has freed,
     # torch's allocator) goes back to HIP: the workers need it
     binding.release_cache(0)
@@ -505,10 +550,17 @@ def replay(n: int, rate: float, seed: int, prec: int, workers: int,
     svc = np.array([r.finish - r.start for _, r in results])
     wins = [r.window for _, r in results]
     busy = sum(b - a for a, b in wins)
+    if sweep is not None:
+        wl = (f"coupling sweep: {sweep[0]} random states x {sweep[1]} values "
+              f"of J2 in [0, 0.6] = {n} requests, Poisson arrivals at "
+              f"{rate}/s (seed {seed}), D 3..6, chi 2D^2..3D^2, one "
+              "state_key per state (warm starts from resident "
+              "environments)")
+    else:
+        wl = (f"{n} requests, Poisson arrivals at {rate}/s (seed {seed}), "
+              "D 3..6, chi 2D^2..3D^2, J1-J2 random states, cold starts")
     out = {
-        "workload": (f"{n} requests, Poisson arrivals at {rate}/s (seed "
-                     f"{seed}), D 3..6, chi 2D^2..3D^2, J1-J2 random "
-                     "states, cold starts"),
+        "workload": wl,
         "requests": n, "errors": errors,
         "p50_latency_s": float(np.percentile(lat, 50)),
         "p99_latency_s": float(np.percentile(lat, 99)),
@@ -522,6 +574,22 @@ def replay(n: int, rate: float, seed: int, prec: int, workers: int,
         "device_busy_sum_over_makespan": busy / 1e3 / makespan,
         "checkpointed_requests": n_ckpt,
     }
+    if sweep is not None:
+        warm = [r for _, r in results if r.warm]
+        cold = [r for _, r in results if not r.warm]
+        out["warm_requests"] = len(warm)
+        out["mean_ctm_iters_cold"] = (float(np.mean([r.ctm_iters
+                                                     for r in cold]))
+                                      if cold else None)
+        out["mean_ctm_iters_warm"] = (float(np.mean([r.ctm_iters
+                                                     for r in warm]))
+                                      if warm else None)
+        out["mean_service_s_cold"] = (float(np.mean([r.finish - r.start
+                                                     for r in cold]))
+                                      if cold else None)
+        out["mean_service_s_warm"] = (float(np.mean([r.finish - r.start
+                                                     for r in warm]))
+                                      if warm else None)
     if check_solo > 0 and results:
         idx = np.linspace(0, len(results) - 1, min(check_solo, len(results)))
         same = 0
@@ -544,10 +612,14 @@ def main(argv=None):
     ap.add_argument("--budget-gb", type=float, default=230.0)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--check-solo", type=int, default=16)
+    ap.add_argument("--sweep", type=int, nargs=2, metavar=("STATES",
+                                                           "COUPLINGS"),
+                    help="replay a coupling sweep instead (warm starts)")
     args = ap.parse_args(argv)
     prec = binding.FP32 if args.prec == "fp32" else binding.FP64
     out = replay(args.requests, args.rate, args.seed, prec, args.workers,
-                 args.budget_gb, args.check_solo)
+                 args.budget_gb, 0 if args.sweep else args.check_solo,
+                 sweep=tuple(args.sweep) if args.sweep else None)
     out["prec"] = args.prec
     print(json.dumps(out), flush=True)
 

@@ -172,3 +172,56 @@ def test_environment_routing_and_eviction():
             assert srv.used == 0.0 and srv.env_bytes == 0.0
     finally:
         srv.close()
+
+
+def test_sweep_stream_shares_keys_per_state():
+    """The coupling sweep: every state at every coupling, one state_key per
+    state, couplings round robin over the states, seeded."""
+    a = serve.sweep_stream(3, 4, 20.0, 7, binding.FP32)
+    b = serve.sweep_stream(3, 4, 20.0, 7, binding.FP32)
+    assert len(a) == 12 and [t for t, _ in a] == [t for t, _ in b]
+    keys = [r.state_key for _, r in a]
+    assert keys[:3] == keys[3:6] == keys[9:12] and len(set(keys)) == 3
+    for i, (_, r) in enumerate(a):
+        same = a[i % 3][1]
+        assert np.array_equal(r.A, same.A) and r.chi == same.chi
+        D = r.A.shape[3]
+        assert 3 <= D <= 6 and 2 * D * D <= r.chi <= 3 * D * D
+    # the couplings rise from 0 to 0.6 across the rounds (the J2 term's
+    # coefficient of the diagonal terms)
+    j2 = [([t[4] for t in r.terms if t[2] == 1 and abs(t[3]) == 1] or
+           [0.0])[0] for _, r in a[::3]]
+    assert j2[0] == 0.0 and abs(j2[-1] - 0.6) < 1e-12
+    assert all(x < y for x, y in zip(j2, j2[1:]))
+
+
+def test_requests_of_a_running_state_wait_for_it(monkeypatch):
+    """Requests that share a state_key never run at the same time (each
+    can start from the environment of the one before); requests of other
+    states go ahead of them."""
+    lock = threading.Lock()
+    running, seen, order = {}, [], []
+
+    def fake_step(self, req, start, sidx=0):
+        with lock:
+            running[req.state_key] = running.get(req.state_key, 0) + 1
+            seen.append(running[req.state_key])
+            order.append(req.state_key)
+        time.sleep(0.05)
+        with lock:
+            running[req.state_key] -= 1
+        return serve.Result(e=0.0, g=np.zeros(1), x=np.zeros(1), ctm_iters=0,
+                            delta=0.0, cg_iters=0, warm=False,
+                            arrival=req.arrival, start=start,
+                            finish=time.perf_counter())
+
+    monkeypatch.setattr(serve.Server, "_step", fake_step)
+    srv = serve.Server(1e15, workers=4)
+    reqs = [_req(3, 18, key="a") for _ in range(3)] + [_req(3, 18, key="b")]
+    futs = [srv.submit(r) for r in reqs]
+    for f in futs:
+        f.result(timeout=30)
+    srv.close()
+    assert max(seen) == 1
+    # "b" arrived last but did not wait behind the queued "a" requests
+    assert order.index("b") < 3
