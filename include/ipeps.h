@@ -169,7 +169,13 @@ int ctm_set_state(ipeps_ctx* ctx, const double* A);
  * corners of every unit-cell plaquette with SVD-truncated half-system
  * projectors) until Delta < tol or max_iter iterations.  Delta is the largest
  * 2-norm change of the sum-normalised singular values of any corner.
- * tol <= 0 runs exactly max_iter iterations.
+ * tol <= 0 runs exactly max_iter iterations.  In the reduced-precision
+ * modes (see ipeps_prec) the iteration also stops, NOT_CONVERGED, once Delta
+ * is within 100 times the mode's floor and has not fallen below 0.9 of its
+ * smallest value for 8 iterations (a state whose kept spectrum reaches the
+ * rounding of the products).  After ipeps_set_env / ipeps_set_env_dev the
+ * environment is taken as near its fixed point: the first iteration runs
+ * with FP64 products and an SVD as accurate as the tolerance asks.
  *   n_iter, delta  out (may be NULL)
  * Returns OK, NOT_CONVERGED (warning), or an error. */
 int ctm_converge(ipeps_ctx* ctx, double tol, int max_iter, int* n_iter,

@@ -665,6 +665,7 @@ int ipeps_set_env(ipeps_ctx* c, const double* in) {
     cx.env = e;
     cx.have_warm = false;
     cx.converged_once = true;
+    cx.env_injected = true;
     cx.work_prec = cx.prec;  // a new environment climbs the ladder again
     (void)corner_spectra_change(cx, cx.env);
     cx.dev.sync();
@@ -696,6 +697,7 @@ int ipeps_set_env_dev(ipeps_ctx* c, const double* d_in) {
     cx.env = e;
     cx.have_warm = false;
     cx.converged_once = true;
+    cx.env_injected = true;
     cx.work_prec = cx.prec;
     (void)corner_spectra_change(cx, cx.env);
     cx.dev.sync();

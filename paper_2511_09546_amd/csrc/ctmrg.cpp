@@ -44,6 +44,7 @@ void build_double_layer(Context& cx) {
   const int ns = cx.nsite(), D2 = cx.D2, D = cx.D;
   cx.bp_valid = false;  // the belief-propagation messages belong to old A
   cx.c4v_sym = false;   // A is no longer known to be projected
+  cx.env_injected = false;  // an environment set before was for old A
   const int64_t a4 = (int64_t)D2 * D2 * D2 * D2;
   if (cx.a_rot.numel() != ns * 4 * a4)
     cx.a_rot = cx.dev.empty({ns, 4, D2, D2, D2, D2});
@@ -330,6 +331,8 @@ int converge_env(Context& cx, double tol, int max_iter, int* n_iter,
   int it = 0;
   double dl = INFINITY;
   const double svd_tol = cx.svd.tol;
+  const bool injected = cx.env_injected;
+  cx.env_injected = false;
   const long svd_bad0 = cx.stats.svd_unconverged;
   // the spectrum change cannot fall below the rounding of the contraction
   // arithmetic: tolerances under that floor are raised to it (with the
@@ -346,19 +349,36 @@ int converge_env(Context& cx, double tol, int max_iter, int* n_iter,
   // iterations; the iterations then continue in FP32
   double best = INFINITY;
   int flat = 0;
+  // reduced-precision arithmetic: a state whose corner spectra hold values
+  // near the rounding of the products (a small singular value kept at the
+  // cut) leaves the change hovering above the floor, where more iterations
+  // only redraw the rounding; once the change is within 100 times the floor
+  // and has not set a new low (below 0.9 of the smallest) for 8 iterations
+  // the iteration stops, reported as not converged
+  double low = INFINITY;
+  int stall = 0;
   struct RestoreTol {
     Context& c;
     double t;
     ~RestoreTol() { c.svd.tol = t; }
   } restore{cx, svd_tol};
   while (it < max_iter) {
-    PrecScope ps(cx.dev, cx.work_prec);
+    // the first projectors of an environment set from outside have no
+    // subspace of an earlier iteration to start from: computed with FP32
+    // products the subspace iteration levels off near its rounding floor
+    // and the truncation moves the environment by ~1e-4 in the spectra,
+    // which the next iterations then have to undo; that first iteration
+    // runs in FP64
+    PrecScope ps(cx.dev, it == 0 && injected ? (int)PREC_FP64 : cx.work_prec);
     // when iterating to a tolerance, the projector SVD of an iteration only
     // needs to be as accurate as the environment it produces: its tolerance
     // follows the last spectrum change (never looser than 1e-6, never
     // tighter than the configured one), so the final iterations and the
-    // fixed point are computed at full accuracy
-    if (tol > 0.0) cx.svd.tol = std::max(svd_tol, std::min(1e-6, 1e-2 * dl));
+    // fixed point are computed at full accuracy; an environment set from
+    // outside for these site tensors is taken to change by about the
+    // tolerance, so its first projectors are as accurate as the last ones
+    const double ref = it == 0 && injected ? tol : dl;
+    if (tol > 0.0) cx.svd.tol = std::max(svd_tol, std::min(1e-6, 1e-2 * ref));
     Env next;
     ctm_step(cx, cx.env, next);
     cx.env = next;
@@ -374,10 +394,21 @@ int converge_env(Context& cx, double tol, int max_iter, int* n_iter,
       if (dl < prec_floors(cx.work_prec).spectra || flat >= 3) {
         cx.work_prec = PREC_FP32;
         tol = eff_tol();
+        low = INFINITY;
+        stall = 0;
         continue;
       }
     }
     if (tol > 0.0 && dl < tol) break;
+    const double floor = prec_floors(cx.work_prec).spectra;
+    if (tol > 0.0 && floor > 0.0) {
+      if (dl < 0.9 * low) {
+        low = dl;
+        stall = 0;
+      } else if (dl < 100.0 * floor && ++stall >= 8) {
+        break;
+      }
+    }
   }
   cx.converged_once = true;
   if (n_iter) *n_iter = it;

@@ -164,6 +164,9 @@ struct Context {
   Env env;
   bool have_env = false;
   bool converged_once = false;
+  // the environment was set from outside (ipeps_set_env*) for the current
+  // site tensors and is taken to be near its fixed point
+  bool env_injected = false;
   Tensor Xwarm;         // [ncut][n][b] right singular blocks (warm start)
   bool have_warm = false;
   // solution of the last complement solve of the projector backward

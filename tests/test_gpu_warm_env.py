@@ -1,0 +1,68 @@
+"""An environment converged for a state, set back into a context of the same
+state (ipeps_set_env / ipeps_set_env_dev), is taken as near its fixed point:
+converging again from it costs one iteration in FP64 and a few in FP32/BF16
+(the first iteration after the injection runs in FP64 with the tolerance's
+SVD accuracy), and ends at the same energy as the cold convergence."""
+import numpy as np
+import pytest
+
+from paper_2511_09546_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# energies per site in units of J1 (random states sit near e = 0, so the
+# bounds are absolute: the rounding of the arithmetic, FP64 ~1e-15, FP32
+# ~1e-8, BF16 products ~1e-7)
+@pytest.mark.parametrize("prec,max_warm,atol", [
+    (binding.FP64, 1, 1e-12),
+    (binding.FP32, 4, 1e-7),
+    (binding.BF16, 4, 2e-6),
+])
+@pytest.mark.parametrize("D,chi", [(4, 40), (5, 60)])
+def test_warm_env_converges_at_once(prec, max_warm, atol, D, chi):
+    _say(f"warm env prec={prec} D={D} chi={chi}")
+    A = inputs.random_state(6001, 1, 1, 2, D)
+    terms = inputs.terms_j1j2(1, 1, 1.0, 0.3)
+    o = binding.default_opts()
+    o.prec = prec
+    with binding.Context(A, chi, opts=o) as c1:
+        it1, _, ok1 = c1.converge(1e-10, 200)
+        e1, _ = c1.energy_grad(terms, grad=False)
+        env = c1.get_env()
+    assert ok1
+    with binding.Context(A, chi, opts=o) as c2:
+        c2.set_env(*env)
+        it2, _, ok2 = c2.converge(1e-10, 200)
+        e2, _ = c2.energy_grad(terms, grad=False)
+    _say(f"  cold {it1} iterations, warm {it2}; e {e1!r} {e2!r}")
+    assert ok2
+    assert it2 <= max_warm < it1
+    assert abs(e2 - e1) < atol
+
+
+def test_new_state_clears_the_injection():
+    """After ctm_set_state the injected environment belongs to the old site
+    tensors: the next convergence takes the ordinary iteration path and
+    reaches the cold result of the new state."""
+    _say("warm env then new state")
+    A = inputs.random_state(6002, 1, 1, 2, 3)
+    B = inputs.random_state(6003, 1, 1, 2, 3)
+    terms = inputs.terms_j1j2(1, 1, 1.0, 0.3)
+    with binding.Context(A, 20) as c1:
+        c1.converge(1e-10, 200)
+        env = c1.get_env()
+    with binding.Context(B, 20) as c0:
+        c0.converge(1e-10, 200)
+        e_ref, _ = c0.energy_grad(terms, grad=False)
+    with binding.Context(A, 20) as c2:
+        c2.set_env(*env)
+        c2.set_state(B)
+        it, _, ok = c2.converge(1e-10, 200)
+        e, _ = c2.energy_grad(terms, grad=False)
+    assert ok and it > 1
+    assert abs(e - e_ref) < 1e-12
