@@ -66,3 +66,31 @@ def test_new_state_clears_the_injection():
         e, _ = c2.energy_grad(terms, grad=False)
     assert ok and it > 1
     assert abs(e - e_ref) < 1e-12
+
+
+def test_fp32_stall_at_the_rounding_floor():
+    """A state whose smallest kept corner singular value (about 3e-6 of the
+    sum at D = 4, chi = 45) sits at the rounding of FP32 products: the FP32
+    spectrum change hovers between 1e-7 and 1e-6, and the iteration stops
+    on the stall rule (not converged) instead of running to the limit, cold
+    and from its own environment; in FP64 the same state converges."""
+    _say("fp32 stall, D=4 chi=45")
+    A = inputs.random_state(6007, 1, 1, 2, 4)
+    o = binding.default_opts()
+    o.prec = binding.FP32
+    with binding.Context(A, 45, opts=o) as c1:
+        it1, dl1, ok1 = c1.converge(1e-10, 200)
+        env = c1.get_env()
+    with binding.Context(A, 45, opts=o) as c2:
+        c2.set_env(*env)
+        it2, dl2, ok2 = c2.converge(1e-10, 200)
+    _say(f"  FP32 cold {it1} iterations (delta {dl1:.1e}, ok {ok1}), warm "
+         f"{it2} ({dl2:.1e}, ok {ok2})")
+    assert it1 < 200 and it2 < 100
+    # the status says whether the floor was reached
+    assert ok1 == (dl1 < 1e-7)
+    assert not ok2 and 1e-7 <= dl2 < 1e-5
+    with binding.Context(A, 45) as c3:
+        it3, dl3, ok3 = c3.converge(1e-10, 200)
+    _say(f"  FP64 {it3} iterations (delta {dl3:.1e})")
+    assert ok3 and dl3 < 1e-10
