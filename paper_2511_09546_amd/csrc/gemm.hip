@@ -1447,7 +1447,15 @@ void dispatch_prec(Device& dev, const Call& c) {
       const double c128 = tile_cost(c, 128, 128, 16);
       const double c144 = tile_cost(c, 128, 144, 16);
       const bool direct = c.K >= 256 && lds_ok(c);
-      if (direct && c144 < c128)
+      // inner size below 256 and a large output (the n x n cut-matrix
+      // gradients accumulated from n x 2 chi factors, outer products of
+      // chi-wide blocks): the time goes into writing (and with beta,
+      // reading) C, and 64 x 64 tiles keep more workgroups storing at once
+      // than 128 x 128 ones (3 ms less per FP32 step at D = 6, chi = 72;
+      // the same products in the same order)
+      if (c.K < 256 && c.M >= 1024 && c.N >= 1024)
+        launch_cfg<64, 64, 2, 2, P>(dev, c);
+      else if (direct && c144 < c128)
         launch_cfg<128, 144, 4, 1, P, true>(dev, c);
       else if (direct)
         launch_cfg<128, 128, 2, 2, P, true>(dev, c);
