@@ -400,12 +400,12 @@ int converge_env(Context& cx, double tol, int max_iter, int* n_iter,
       }
     }
     if (tol > 0.0 && dl < tol) break;
-    const double floor = prec_floors(cx.work_prec).spectra;
-    if (tol > 0.0 && floor > 0.0) {
+    const double rounding = prec_floors(cx.work_prec).spectra;
+    if (tol > 0.0 && rounding > 0.0) {
       if (dl < 0.9 * low) {
         low = dl;
         stall = 0;
-      } else if (dl < 100.0 * floor && ++stall >= 8) {
+      } else if (dl < 100.0 * rounding && ++stall >= 8) {
         break;
       }
     }
