@@ -445,7 +445,7 @@ def main():
                     help="skip the timing of every preconditioner")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is "
               "not supported (independent states would shard across GPUs "
               "with no exchange; one state is not split)", file=sys.stderr)
         sys.exit(2)
