@@ -117,7 +117,7 @@ def test_max_overlap_of_windows():
 
 def test_worker_errors_reach_the_caller():
     """A request that fails inside its worker process (here: no GPU, so
-    ctm_init fails; on a GPU machine: arguments the library rejects) fails its
+    ctm_init fails; with a GPU: arguments the library rejects) fails its
     future with the library's message; the worker keeps serving."""
     srv = serve.Server(1e12, workers=1)
     bad = _req(3, 18)
