@@ -61,9 +61,34 @@ def test_warm_start_sweep():
         res.append(srv.submit(req).result(timeout=120))
     srv.close()
     assert not res[0].warm and res[1].warm and res[2].warm
-    assert res[1].ctm_iters < res[0].ctm_iters
+    # a converged FP64 environment converges again in one iteration
+    assert res[1].ctm_iters == 1 and res[2].ctm_iters == 1 < res[0].ctm_iters
     for J2, r in zip((0.0, 0.25, 0.5), res):
         req = serve.Request(A=A, chi=12, terms=inputs.terms_j1j2(1, 1, 1.0, J2),
                             prec=binding.FP64, grad_K=6)
         e, g, x, it = _solo(req)
         assert abs(r.e - e) < 1e-9 * abs(e)
+
+
+def test_sweep_requests_wait_for_their_state_fp32():
+    """Two states, three couplings each, all submitted at once to two
+    workers: a request whose state is still running waits for it and then
+    starts from the environment it left (FP32 contractions: a few CTMRG
+    iterations instead of a cold convergence)."""
+    print("serve sweep, FP32, concurrent submission", flush=True)
+    states = [(inputs.random_state(6001, 1, 1, 2, 4), 40),
+              (inputs.random_state(6001, 1, 1, 2, 5), 60)]
+    srv = serve.Server(100e9, workers=2)
+    futs = []
+    for J2 in (0.0, 0.3, 0.6):
+        for i, (A, chi) in enumerate(states):
+            futs.append(srv.submit(serve.Request(
+                A=A, chi=chi, terms=inputs.terms_j1j2(1, 1, 1.0, J2),
+                prec=binding.FP32, grad_K=6, state_key=f"sweep-{i}")))
+    res = [f.result(timeout=300) for f in futs]
+    srv.close()
+    cold = [r.ctm_iters for r in res if not r.warm]
+    warm = [r.ctm_iters for r in res if r.warm]
+    print(f"  cold {cold}, warm {warm}", flush=True)
+    assert len(cold) == 2 and len(warm) == 4
+    assert max(warm) <= 6 < min(cold)
